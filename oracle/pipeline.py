@@ -1,0 +1,169 @@
+"""The forward hot path, end to end, in float64 (Sections 2-3).
+
+Test infrastructure (see the package docstring).
+
+  weights   W[g, j, i] = m_age[g, i] * P[g, j, i]   (Eqs. cspsum, agedep_mdf)
+  sed       L[g, l] = sum_{j,i} W[g, j, i] L_SSP[j, i, l]   (Eqs. cspdeftheta,
+            full_mdf), optionally times F_att (Eq. attenuation)
+  band_sums num/den of Eq. restmag on the redshifted grid
+  mags      apparent AB magnitudes (Section 2.2.1)
+
+The contraction is a plain matrix product (a library primitive); galaxies are
+processed in blocks only to bound memory.  Nothing is windowed or skipped.
+
+quantize_bf16_rne is the reference for the BF16 storage of the SSP block: each
+(met, age) row is divided by its power-of-two scale s_k (the smallest power of
+two not below the row maximum) and rounded to bfloat16 with
+round-to-nearest-even.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import cosmology, dust, mdf, photometry, sfh
+
+
+@dataclass
+class OracleInputs:
+    lgz: np.ndarray          # [n_met]
+    lg_age: np.ndarray       # [n_age]
+    wave: np.ndarray         # [n_wave] rest-frame Angstrom
+    lum: np.ndarray          # [n_met, n_age, n_wave] float64
+    filt_wave: np.ndarray    # [n_band, n_pts]
+    filt_trans: np.ndarray   # [n_band, n_pts]
+    t_table: np.ndarray      # [n_t] Gyr
+    sfr: np.ndarray          # [n_gal, n_t] M_sun/yr
+    z: np.ndarray
+    lgmet: np.ndarray
+    sigma_z: np.ndarray
+    av: np.ndarray
+    delta: np.ndarray
+    bump: np.ndarray
+    lgmet_slope: float = 0.1
+    lg_age_pivot: float = 9.0
+    om0: float = 0.3
+    h: float = 0.7
+    w0: float = -1.0
+    k0_reading: str = "salim"
+    sfh_params: np.ndarray | None = None
+
+    @property
+    def n_gal(self):
+        return int(self.z.shape[0])
+
+    def subset(self, idx):
+        idx = np.asarray(idx)
+        kw = dict(self.__dict__)
+        for name in ("sfr", "z", "lgmet", "sigma_z", "av", "delta", "bump"):
+            kw[name] = getattr(self, name)[idx]
+        if self.sfh_params is not None:
+            kw["sfh_params"] = self.sfh_params[:, idx]
+        return OracleInputs(**kw)
+
+
+def prepare_inputs(ssp, filters, pop, sfr=None, om0=0.3, h=0.7, w0=-1.0,
+                   k0_reading="salim") -> OracleInputs:
+    """Collect generator outputs; tabulate the SFR from the parametric history
+    when no table is given (the oracle's own step, see oracle.sfh)."""
+    if sfr is None:
+        sfr = sfh.sfr_from_params(pop.t_table, pop.sfh_params)
+    return OracleInputs(
+        lgz=np.asarray(ssp.lgz, np.float64), lg_age=np.asarray(ssp.lg_age, np.float64),
+        wave=np.asarray(ssp.wave, np.float64), lum=np.asarray(ssp.lum, np.float64),
+        filt_wave=np.asarray(filters.wave, np.float64),
+        filt_trans=np.asarray(filters.trans, np.float64),
+        t_table=np.asarray(pop.t_table, np.float64), sfr=np.asarray(sfr, np.float64),
+        z=np.asarray(pop.z, np.float64), lgmet=np.asarray(pop.lgmet, np.float64),
+        sigma_z=np.asarray(pop.sigma_z, np.float64), av=np.asarray(pop.av, np.float64),
+        delta=np.asarray(pop.delta, np.float64), bump=np.asarray(pop.bump, np.float64),
+        lgmet_slope=float(pop.lgmet_slope), lg_age_pivot=float(pop.lg_age_pivot),
+        om0=om0, h=h, w0=w0, k0_reading=k0_reading,
+        sfh_params=np.asarray(pop.sfh_params, np.float64))
+
+
+def observation_times(inp: OracleInputs):
+    return cosmology.age_at_z(inp.z, inp.om0, inp.h, inp.w0)
+
+
+def weights(inp: OracleInputs, return_parts: bool = False):
+    """W[g, j, i] in M_sun: age-bin masses times metallicity weights."""
+    t_obs = observation_times(inp)
+    m_age = sfh.age_bin_masses(t_obs, inp.t_table, inp.sfr, inp.lg_age)       # [g, i]
+    p_met = mdf.mdf_weights(inp.lgmet, inp.sigma_z, inp.lgz, inp.lg_age,
+                            inp.lgmet_slope, inp.lg_age_pivot)                  # [g, j, i]
+    w = m_age[:, None, :] * p_met
+    if return_parts:
+        return w, m_age, p_met, t_obs
+    return w
+
+
+def sed(inp: OracleInputs, apply_dust: bool = False, block: int = 256):
+    """Rest-frame composite SED [n_gal, n_wave] in L_sun/Hz."""
+    n_met, n_age, n_wave = inp.lum.shape
+    table = inp.lum.reshape(n_met * n_age, n_wave)
+    out = np.empty((inp.n_gal, n_wave))
+    for s in range(0, inp.n_gal, block):
+        sub = inp.subset(np.arange(s, min(s + block, inp.n_gal)))
+        w = weights(sub).reshape(sub.n_gal, n_met * n_age)
+        spec = w @ table
+        if apply_dust:
+            spec = spec * dust.attenuation(inp.wave, sub.av, sub.delta, sub.bump, inp.k0_reading)
+        out[s:s + sub.n_gal] = spec
+    return out
+
+
+def band_sums(inp: OracleInputs, block: int = 256):
+    """(num, den) [n_gal, n_band] of Eq. restmag for the dust-attenuated SED."""
+    n_band = inp.filt_wave.shape[0]
+    num = np.empty((inp.n_gal, n_band))
+    den = np.empty((inp.n_gal, n_band))
+    for s in range(0, inp.n_gal, block):
+        idx = np.arange(s, min(s + block, inp.n_gal))
+        spec = sed(inp.subset(idx), apply_dust=True, block=block)
+        for r, g in enumerate(idx):
+            num[g], den[g] = photometry.band_integrals(inp.wave, spec[r], inp.z[g],
+                                                       inp.filt_wave, inp.filt_trans)
+    return num, den
+
+
+def mags(inp: OracleInputs, block: int = 256, return_sums: bool = False):
+    """Apparent AB magnitudes [n_gal, n_band]."""
+    num, den = band_sums(inp, block)
+    dmod = cosmology.distance_modulus(inp.z, inp.om0, inp.h, inp.w0)
+    m = photometry.apparent_mag(num, den, dmod, inp.z)
+    if return_sums:
+        return m, num, den
+    return m
+
+
+def bf16_row_scales(lum_rows_f32):
+    """Smallest power of two >= each row maximum, as float32 [rows]."""
+    x = np.asarray(lum_rows_f32, dtype=np.float32)
+    row_max = x.max(axis=1).astype(np.float64)
+    mant, expo = np.frexp(row_max)           # row_max = mant * 2**expo, mant in [0.5, 1)
+    expo = np.where(mant == 0.5, expo - 1, expo)
+    return np.ldexp(np.float32(1.0), expo).astype(np.float32)
+
+
+def quantize_bf16_rne(lum_rows_f32):
+    """(bf16 bits [rows, cols] uint16, scale [rows] float32).
+
+    q = bf16_rne(x / s_row); the division by a power of two is exact except
+    where it produces a subnormal, which float32 division rounds the same way
+    on any IEEE implementation.
+    """
+    x = np.asarray(lum_rows_f32, dtype=np.float32)
+    s = bf16_row_scales(x)
+    y = (x / s[:, None]).astype(np.float32)
+    bits = y.view(np.uint32).astype(np.uint64)
+    bias = 0x7FFF + ((bits >> 16) & 1)
+    q = ((bits + bias) >> 16).astype(np.uint16)
+    return q, s
+
+
+def bf16_to_f32(bits):
+    b = np.asarray(bits, dtype=np.uint16).astype(np.uint32) << 16
+    return b.view(np.float32)

@@ -1,0 +1,407 @@
+"""Pins for the oracle's hot-path steps: age-bin masses (Section 3.1),
+metallicity weights (Section 3.2), contraction (Section 2.1), filter
+integrals and magnitudes (Section 2.2.1), BF16 quantisation, and the
+hand-written adjoint.  Each test checks the oracle against something other
+than its own formulas: closed forms, invariants, quadrature of the
+definitions, brute force on tiny grids, a library routine or finite
+differences.  CPU only."""
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import synth
+import oracle
+from oracle import constants, cosmology, dust, kernels, mdf, photometry, sfh
+from synth.filters import FilterSet, make_tophat_filters
+from synth.ssp import SspTable
+
+
+def _pop(n, seed=11, z_range=(0.1, 1.0), n_t=100):
+    return synth.make_population(n, n_t=n_t, z_range=z_range, seed=seed)
+
+
+def _step_sfr(t_table, sfr_row):
+    """The SFR implied by linear interpolation of the cumulative trapezoid:
+    constant inside each time step at the mean of its two end values, zero
+    outside the grid."""
+    t_table = np.asarray(t_table)
+    mean = 0.5 * (sfr_row[:-1] + sfr_row[1:])
+
+    def f(t):
+        if t <= t_table[0] or t >= t_table[-1]:
+            return 0.0
+        n = int(np.searchsorted(t_table, t, side="right") - 1)
+        return float(mean[n])
+    return f
+
+
+# ---------------------------------------------------------------- a0-a2
+def test_cumulative_mass_exact_for_linear_sfr():
+    t = np.linspace(0.01, 13.8, 57)
+    c0, c1 = 3.0, 0.7
+    sfr = (c0 + c1 * t)[None, :]
+    m = sfh.cumulative_mass(t, sfr)[0]
+    exact = 1e9 * (c0 * (t - t[0]) + 0.5 * c1 * (t**2 - t[0] ** 2))
+    np.testing.assert_allclose(m, exact, rtol=1e-13, atol=1e-3)
+
+
+def test_age_bin_masses_telescope_to_total(small_ssp):
+    pop = _pop(40, seed=3)
+    sfr = sfh.sfr_from_params(pop.t_table, pop.sfh_params)
+    t_obs = cosmology.age_at_z(pop.z)
+    m_age = sfh.age_bin_masses(t_obs, pop.t_table, sfr, small_ssp.lg_age)
+    # Independent route: integrate the step SFR from t_table[0] to t_obs
+    # with adaptive quadrature.
+    for g in range(pop.n_gal):
+        f = _step_sfr(pop.t_table, sfr[g])
+        pts = pop.t_table[pop.t_table < t_obs[g]]
+        val, _ = integrate.quad(f, pop.t_table[0], t_obs[g], points=pts[1:], limit=400,
+                                epsabs=0, epsrel=1e-12)
+        assert m_age[g].sum() == pytest.approx(1e9 * val, rel=1e-10)
+        assert np.all(m_age[g] >= 0)
+
+
+def test_age_bin_masses_constant_sfr_exact(small_ssp):
+    t = np.linspace(0.01, 13.8, 100)
+    c = 2.5
+    sfr = np.full((1, t.size), c)
+    edges = sfh.age_bin_edges_yr(small_ssp.lg_age) / 1e9
+    for t_obs in (1.3, 5.75, 12.9):
+        m_age = sfh.age_bin_masses(np.array([t_obs]), t, sfr, small_ssp.lg_age)[0]
+        lo = np.maximum(t_obs - edges[1:], t[0])
+        hi = np.maximum(t_obs - edges[:-1], t[0])
+        np.testing.assert_allclose(m_age, 1e9 * c * (hi - lo), rtol=1e-12, atol=1e-3)
+
+
+def test_age_bin_masses_brute_force_quadrature():
+    # Tiny grid: 3 SSP ages, 7 time nodes; each bin mass is the integral of
+    # the step SFR over the formation times that land in the bin.
+    rng = np.random.default_rng(5)
+    t = np.sort(rng.uniform(0.05, 13.0, 7))
+    t[0] = 0.01
+    sfr = rng.uniform(0.1, 5.0, (1, 7))
+    lg_age = np.array([8.0, 9.0, 9.7])
+    t_obs = 11.0
+    edges = [0.0, 10 ** 8.5, 10 ** 9.35, np.inf]
+    got = sfh.age_bin_masses(np.array([t_obs]), t, sfr, lg_age)[0]
+    for i in range(3):
+        t_hi = t_obs - edges[i] / 1e9
+        t_lo = max(t_obs - edges[i + 1] / 1e9, t[0])
+        f = _step_sfr(t, sfr[0])
+        val, _ = integrate.quad(f, t_lo, min(t_hi, t[-1]), points=t[1:-1], epsabs=0, epsrel=1e-13)
+        assert got[i] == pytest.approx(1e9 * val, rel=1e-11)
+
+
+def test_age_bin_masses_converge_to_analytic_sfh():
+    # SFR(t) = A (t/tau)^alpha e^{-t/tau} with q = 0: tabulating it ever more
+    # finely converges to the exact bin integrals at second order.
+    params = np.array([[10.0], [2.0], [1.5], [0.0], [5.0]])
+    lg_age = np.linspace(5.5, 10.15, 94)
+    edges = sfh.age_bin_edges_yr(lg_age) / 1e9
+    t_obs = 9.0
+    exact = np.empty(94)
+    f = lambda t: 10.0 * (t / 2.0) ** 1.5 * np.exp(-t / 2.0)
+    for i in range(94):
+        lo = max(t_obs - edges[i + 1], 0.01)
+        hi = max(t_obs - edges[i], 0.01)
+        exact[i] = 1e9 * integrate.quad(f, lo, hi, epsabs=0, epsrel=1e-13)[0] if hi > lo else 0.0
+    errs = []
+    for n_t in (200, 400, 800):
+        t = np.linspace(0.01, 13.8, n_t)
+        m = sfh.age_bin_masses(np.array([t_obs]), t, sfh.sfr_from_params(t, params), lg_age)[0]
+        errs.append(np.abs(m.sum() - exact.sum()) / exact.sum())
+    assert errs[0] < 1e-3
+    assert errs[1] < errs[0] / 3.0 and errs[2] < errs[1] / 3.0
+
+
+def test_sfr_from_params_special_cases():
+    t = np.linspace(0.01, 13.8, 50)
+    p = np.array([[3.0], [2.0], [1.0], [0.0], [6.0]])
+    np.testing.assert_allclose(sfh.sfr_from_params(t, p)[0], 3.0 * (t / 2.0) * np.exp(-t / 2.0), rtol=1e-15)
+    # Full quenching long before t: SFR -> 0; quench time far in the future: unchanged.
+    p_q = np.array([[3.0], [2.0], [1.0], [1.0], [-100.0]])
+    assert np.all(sfh.sfr_from_params(t, p_q) == 0.0)
+    p_f = np.array([[3.0], [2.0], [1.0], [1.0], [1e3]])
+    np.testing.assert_allclose(sfh.sfr_from_params(t, p_f), sfh.sfr_from_params(t, p), rtol=1e-15)
+    # Half-way through the quench transition the SFR is (1 - q/2) of the base.
+    p_h = np.array([[3.0], [2.0], [1.0], [0.6], [t[10]]])
+    assert sfh.sfr_from_params(t, p_h)[0, 10] == pytest.approx(0.7 * sfh.sfr_from_params(t, p)[0, 10])
+
+
+# ---------------------------------------------------------------- a3
+def test_mdf_weights_sum_to_one_and_nonnegative(small_ssp):
+    pop = _pop(64, seed=7)
+    p = mdf.mdf_weights(pop.lgmet, pop.sigma_z, small_ssp.lgz, small_ssp.lg_age, 0.1, 9.0)
+    assert p.shape == (64, 12, 94)
+    assert np.all(p >= 0)
+    np.testing.assert_allclose(p.sum(axis=1), 1.0, atol=1e-14)
+
+
+def test_mdf_interior_bins_equal_kernel_quadrature(small_ssp):
+    lgz = small_ssp.lgz
+    edges = mdf.met_bin_edges(lgz)
+    lgmet, sig = -2.4, 0.37
+    p = mdf.mdf_weights([lgmet], [sig], lgz, small_ssp.lg_age, 0.1, 9.0)[0]
+    for i in (0, 40, 93):
+        mu = lgmet + 0.1 * (small_ssp.lg_age[i] - 9.0)
+        for j in range(1, 11):
+            pdf = lambda x: kernels.triweight_pdf((x - mu) / sig) / sig
+            val, _ = integrate.quad(pdf, edges[j], edges[j + 1], epsabs=1e-15, epsrel=1e-13,
+                                    points=[mu - 3 * sig, mu + 3 * sig])
+            assert p[j, i] == pytest.approx(val, abs=1e-13)
+
+
+def test_mdf_narrow_limit_is_one_hot(small_ssp):
+    lgz = small_ssp.lgz
+    lgmet = -2.07
+    p = mdf.mdf_weights([lgmet], [1e-7], lgz, small_ssp.lg_age, 0.0, 9.0)[0]
+    j_star = int(np.argmin(np.abs(lgz - lgmet)))
+    assert np.allclose(p[j_star], 1.0) and np.allclose(np.delete(p, j_star, axis=0), 0.0)
+
+
+def test_mdf_zero_slope_is_separable(small_ssp):
+    p = mdf.mdf_weights([-2.2], [0.3], small_ssp.lgz, small_ssp.lg_age, 0.0, 9.0)[0]
+    assert np.allclose(p, p[:, :1], atol=0)
+    p2 = mdf.mdf_weights([-2.2], [0.3], small_ssp.lgz, small_ssp.lg_age, 0.1, 9.0)[0]
+    # The age dependence moves the mean metallicity up with age: mean log Z
+    # of the weights tracks mu_i.
+    mean_lgz = (p2 * small_ssp.lgz[:, None]).sum(axis=0)
+    assert mean_lgz[-1] > mean_lgz[0]
+
+
+# ---------------------------------------------------------------- a5-a7
+def _flat_ssp(n_wave=700, lo=900.0, hi=25000.0, level=2.0e-15):
+    lgz = np.linspace(-4.5, -1.3, 12)
+    lg_age = np.linspace(5.5, 10.15, 94)
+    wave = np.geomspace(lo, hi, n_wave)
+    lum = np.full((12, 94, n_wave), level)
+    return SspTable(lgz=lgz, lg_age=lg_age, wave=wave, lum=lum)
+
+
+def test_constant_sfh_flat_fnu_analytic_magnitudes(filters6):
+    # Constant SFR c, flat L_nu = L0 per M_sun, A_V = 0: through any band
+    # m = -2.5 log10(1e9 c (t_obs - t0) L0 / AB0) + D_mod(z) - 2.5 log10(1+z).
+    pop = _pop(12, seed=21, z_range=(0.1, 1.0))
+    pop.av[:] = 0.0
+    ssp = _flat_ssp()
+    c = 4.2
+    sfr = np.full((pop.n_gal, pop.n_t), c)
+    inp = oracle.prepare_inputs(ssp, filters6, pop, sfr=sfr)
+    m = oracle.mags(inp)
+    t_obs = cosmology.age_at_z(pop.z)
+    mass = 1e9 * c * (t_obs - pop.t_table[0])
+    expect = (-2.5 * np.log10(mass * 2.0e-15 / constants.AB0_LSUN_PER_HZ)
+              + cosmology.distance_modulus(pop.z) - 2.5 * np.log10(1 + pop.z))
+    np.testing.assert_allclose(m, np.repeat(expect[:, None], 6, axis=1), atol=1e-10)
+
+
+def test_power_law_through_tophat_redshifted():
+    # L_nu = lambda^beta (rest) observed through a top-hat [a, b] in the
+    # observer frame: num/den = (1+z)^-beta (b^beta - a^beta) / (beta ln(b/a)).
+    # The trapezoid on the log grid is accurate to O(dlnlambda^2).
+    beta = 1.7
+    wave = np.geomspace(900.0, 25000.0, 20000)
+    sed_row = wave**beta
+    filt = make_tophat_filters([(4000.0, 5500.0), (7000.0, 9000.0)], n_pts=4001)
+    for z in (0.0, 0.4, 1.3):
+        num, den = photometry.band_integrals(wave, sed_row, z, filt.wave, filt.trans)
+        for b, (lo, hi) in enumerate([(4000.0, 5500.0), (7000.0, 9000.0)]):
+            exact = (1 + z) ** -beta * (hi**beta - lo**beta) / (beta * np.log(hi / lo))
+            assert num[b] / den[b] == pytest.approx(exact, rel=2e-4)
+
+
+def test_unit_vector_table_and_linearity(small_ssp, filters6):
+    pop = _pop(5, seed=9)
+    k_met, k_age = 5, 60
+    lum = np.zeros_like(small_ssp.lum, dtype=np.float64)
+    lum[k_met, k_age] = small_ssp.lum[k_met, k_age]
+    ssp1 = SspTable(small_ssp.lgz, small_ssp.lg_age, small_ssp.wave, lum)
+    inp = oracle.prepare_inputs(ssp1, filters6, pop)
+    w = oracle.weights(inp)
+    spec = oracle.sed(inp)
+    np.testing.assert_allclose(spec, w[:, k_met, k_age, None] * lum[k_met, k_age][None, :], rtol=1e-14)
+    base = oracle.prepare_inputs(small_ssp, filters6, pop)
+    m0 = oracle.mags(base)
+    scaled = oracle.prepare_inputs(small_ssp, filters6, pop,
+                                   sfr=3.7 * sfh.sfr_from_params(pop.t_table, pop.sfh_params))
+    np.testing.assert_allclose(oracle.mags(scaled), m0 - 2.5 * np.log10(3.7), atol=1e-11)
+
+
+def test_brute_force_tiny_grid():
+    # 2 metallicities x 3 ages x 5 wavelengths, pure-Python loops over the
+    # definitions: bin masses by quadrature of the SFR, metallicity weights by
+    # quadrature of the kernel, explicit trapezoid loops for the band sums.
+    rng = np.random.default_rng(17)
+    lgz = np.array([-3.0, -2.0])
+    lg_age = np.array([7.5, 8.8, 9.6])
+    wave = np.array([3000.0, 3600.0, 4100.0, 4900.0, 5800.0])
+    lum = rng.uniform(0.5, 2.0, (2, 3, 5)) * 1e-15
+    t_table = np.linspace(0.01, 13.8, 9)
+    sfr = rng.uniform(0.5, 4.0, (1, 9))
+    fw = np.linspace(3500.0, 9000.0, 11)[None, :]
+    ft = rng.uniform(0.2, 1.0, (1, 11))
+    z, lgmet, sig, av, delta, bump = 0.35, -2.6, 0.4, 0.8, -0.3, 1.1
+    slope, pivot = 0.1, 9.0
+    pop = synth.Population(t_table=t_table, sfh_params=np.zeros((5, 1)), z=np.array([z]),
+                           lgmet=np.array([lgmet]), sigma_z=np.array([sig]), av=np.array([av]),
+                           delta=np.array([delta]), bump=np.array([bump]), targets=np.zeros((1, 1)),
+                           lgmet_slope=slope, lg_age_pivot=pivot)
+    inp = oracle.prepare_inputs(SspTable(lgz, lg_age, wave, lum), FilterSet(fw, ft), pop, sfr=sfr)
+    inp.sfh_params = None
+    m_oracle = oracle.mags(inp)[0, 0]
+
+    t_obs = cosmology.age_at_z(z)
+    age_edges = [0.0, 10 ** ((7.5 + 8.8) / 2), 10 ** ((8.8 + 9.6) / 2), np.inf]
+    met_edges = [-np.inf, -2.5, np.inf]
+    sfr_f = _step_sfr(t_table, sfr[0])
+    spec = [0.0] * 5
+    for i in range(3):
+        lo = max(t_obs - age_edges[i + 1] / 1e9, t_table[0])
+        hi = t_obs - age_edges[i] / 1e9
+        m_i = 1e9 * integrate.quad(sfr_f, lo, hi, points=list(t_table[1:-1]), epsabs=0,
+                                   epsrel=1e-13)[0] if hi > lo else 0.0
+        mu = lgmet + slope * (lg_age[i] - pivot)
+        for j in range(2):
+            a = max(met_edges[j], mu - 3 * sig)
+            b = min(met_edges[j + 1], mu + 3 * sig)
+            p_ji = integrate.quad(lambda x: 35 / 96 * (1 - ((x - mu) / sig / 3) ** 2) ** 3 / sig,
+                                  a, b, epsabs=1e-15)[0] if b > a else 0.0
+            for l in range(5):
+                spec[l] += m_i * p_ji * lum[j, i, l]
+    num = den = 0.0
+    for l in range(4):
+        vals = []
+        for ll in (l, l + 1):
+            lo_ = (1 + z) * wave[ll]
+            tr = float(np.interp(lo_, fw[0], ft[0], left=0.0, right=0.0))
+            lam_um = wave[ll] / 1e4
+            k0 = (5.472 + 0.671 / lam_um - 9.218e-3 / lam_um**2 + 2.620e-3 / lam_um**3
+                  if lam_um < 0.15 else
+                  2.659 * (-2.156 + 1.509 / lam_um - 0.198 / lam_um**2 + 0.011 / lam_um**3) + 4.05)
+            dr = bump * (wave[ll] * 350) ** 2 / ((wave[ll] ** 2 - 2175.0**2) ** 2 + (wave[ll] * 350) ** 2)
+            att = 10 ** (-0.4 * av / 4.05 * (k0 * (wave[ll] / 5500.0) ** delta + dr))
+            vals.append((tr * att * spec[ll] / lo_, tr / lo_, lo_))
+        dx = vals[1][2] - vals[0][2]
+        num += 0.5 * dx * (vals[0][0] + vals[1][0])
+        den += 0.5 * dx * (vals[0][1] + vals[1][1])
+    dmod = 5 * np.log10(cosmology.luminosity_distance_mpc(z)[0]) + 25
+    m_brute = -2.5 * np.log10(num / (1.13492e-13 * den)) + dmod - 2.5 * np.log10(1 + z)
+    assert m_oracle == pytest.approx(m_brute, abs=1e-10)
+
+
+def test_uncovered_band_gives_nan(small_ssp):
+    pop = _pop(2, seed=4)
+    far = FilterSet(np.linspace(1e6, 2e6, 50)[None, :], np.ones((1, 50)))
+    inp = oracle.prepare_inputs(small_ssp, far, pop)
+    assert np.all(np.isnan(oracle.mags(inp)))
+
+
+def test_delta_gradient_sign_matches_paper(small_ssp, filters6):
+    # Section 3.4: a larger delta gives optical colours that are less
+    # reddened, so d(blue - red)/d(delta) < 0 around delta = -0.25, A_V = 1.
+    pop = _pop(8, seed=31, z_range=(0.1, 0.3))
+    pop.av[:] = 1.0
+    h = 1e-3
+    cols = []
+    for d in (-0.25 - h, -0.25 + h):
+        pop.delta[:] = d
+        m = oracle.mags(oracle.prepare_inputs(small_ssp, filters6, pop))
+        cols.append(m[:, 1] - m[:, 4])
+    assert np.all((cols[1] - cols[0]) / (2 * h) < 0)
+
+
+# ---------------------------------------------------------------- a8
+def test_bf16_quantiser_matches_library_rne(small_ssp):
+    torch = pytest.importorskip("torch")
+    rows = small_ssp.lum.reshape(-1, small_ssp.lum.shape[-1])
+    q, s = oracle.quantize_bf16_rne(rows)
+    # Scales: powers of two with row max / s in (0.5, 1].
+    ratio = rows.max(axis=1) / s
+    assert np.all((ratio > 0.5) & (ratio <= 1.0))
+    assert np.all(np.frexp(s)[0] == 0.5)
+    ref = torch.from_numpy((rows / s[:, None]).astype(np.float32)).to(torch.bfloat16)
+    np.testing.assert_array_equal(q, ref.view(torch.int16).numpy().view(np.uint16))
+    # bfloat16 keeps 8 significand bits, so round-to-nearest-even is within
+    # 2^-8 relative of the float32 input.
+    back = oracle.bf16_to_f32(q).astype(np.float64) * s[:, None]
+    rel = np.abs(back - rows) / rows
+    assert rel.max() <= 2.0**-8
+    assert rel.max() > 2.0**-9            # and that bound is attained
+
+
+def test_bf16_ties_round_to_even():
+    # Row maximum 1.0 gives scale 1; in [0.5, 1) the bf16 spacing is 2^-8.
+    x = np.array([[1.0, 0.5 + 2**-9, 0.5 + 3 * 2**-9, 0.5 + 2**-9 + 2**-13, 0.75]], dtype=np.float32)
+    q, s = oracle.quantize_bf16_rne(x)
+    assert s[0] == 1.0
+    assert list(q[0]) == [0x3F80, 0x3F00, 0x3F02, 0x3F01, 0x3F40]
+
+
+# ---------------------------------------------------------------- a9
+def _loss_and_grad(inp, targets):
+    m = oracle.mags(inp)
+    return np.sum((m - targets) ** 2), oracle.mags_vjp(inp, 2 * (m - targets))
+
+
+def test_adjoint_matches_central_differences(small_ssp, filters6):
+    pop = _pop(6, seed=41, z_range=(0.1, 1.0))
+    inp = oracle.prepare_inputs(small_ssp, filters6, pop)
+    targets = pop.targets
+    _, g = _loss_and_grad(inp, targets)
+
+    def loss_at(mod):
+        p2 = oracle.prepare_inputs(small_ssp, filters6, pop)
+        mod(p2)
+        if p2.sfh_params is not None:
+            p2.sfr = sfh.sfr_from_params(p2.t_table, p2.sfh_params)
+        return np.sum((oracle.mags(p2) - targets) ** 2)
+
+    fields = {"lgmet": "lgmet_bar", "sigma_z": "sigma_bar", "av": "av_bar",
+              "delta": "delta_bar", "bump": "bump_bar"}
+    for g_idx in range(pop.n_gal):
+        for fld, key in fields.items():
+            h = 1e-4
+            def plus(p, s=+1):
+                arr = getattr(p, fld).copy(); arr[g_idx] += s * h; setattr(p, fld, arr)
+            fd = (loss_at(lambda p: plus(p, +1)) - loss_at(lambda p: plus(p, -1))) / (2 * h)
+            assert g[key][g_idx] == pytest.approx(fd, rel=1e-5, abs=1e-6), (fld, g_idx)
+        for k in range(5):
+            h = 1e-4 * max(1.0, abs(inp.sfh_params[k, g_idx]))
+            def pp(p, s):
+                arr = p.sfh_params.copy(); arr[k, g_idx] += s * h; p.sfh_params = arr
+            fd = (loss_at(lambda p: pp(p, +1)) - loss_at(lambda p: pp(p, -1))) / (2 * h)
+            assert g["sfh_params_bar"][k, g_idx] == pytest.approx(fd, rel=1e-5, abs=1e-6), (k, g_idx)
+
+
+def test_adjoint_sfr_table_matches_central_differences(small_ssp, filters6):
+    pop = _pop(2, seed=43, z_range=(0.2, 0.9))
+    inp = oracle.prepare_inputs(small_ssp, filters6, pop)
+    inp.sfh_params = None
+    m = oracle.mags(inp)
+    g = oracle.mags_vjp(inp, 2 * (m - pop.targets))["sfr_bar"]
+    rng = np.random.default_rng(0)
+    for gi in range(2):
+        for n in rng.choice(pop.n_t, 12, replace=False):
+            h = 1e-4 * max(1.0, inp.sfr[gi, n])
+            vals = []
+            for s in (+1, -1):
+                p2 = oracle.prepare_inputs(small_ssp, filters6, pop, sfr=inp.sfr.copy())
+                p2.sfr[gi, n] += s * h
+                vals.append(np.sum((oracle.mags(p2) - pop.targets) ** 2))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert g[gi, n] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+
+
+def test_adjoint_closed_forms(small_ssp, filters6):
+    pop = _pop(4, seed=45)
+    pop.av[1] = 0.0
+    inp = oracle.prepare_inputs(small_ssp, filters6, pop)
+    for b in range(6):
+        bar = np.zeros((4, 6)); bar[:, b] = 1.0
+        g = oracle.mags_vjp(inp, bar)
+        # SFR is proportional to A, so dm/dln A = -2.5/ln 10 for every band.
+        np.testing.assert_allclose(g["sfh_params_bar"][0] * inp.sfh_params[0], -2.5 / np.log(10), rtol=1e-10)
+        # With A_V = 0 the curve shape parameters have no effect.
+        assert g["delta_bar"][1] == 0.0 and g["bump_bar"][1] == 0.0
+        assert np.all(g["av_bar"] > 0)

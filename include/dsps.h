@@ -1,0 +1,253 @@
+/*
+ * dsps.h -- C ABI of libdsps, the MI355X (gfx950) hot path of differentiable
+ * stellar population synthesis (Hearin et al., arXiv 2112.06830).
+ *
+ * For every galaxy of a population the library turns a tabulated star-
+ * formation history, an age-dependent metallicity distribution and dust
+ * parameters into apparent AB magnitudes through a set of filters:
+ *
+ *   age-bin masses from the cumulative SFH     (Section 3.1, Eqs. cspsum, mstartot)
+ *   x triweight metallicity weights            (Section 3.2.2, Eq. agedep_mdf;
+ *                                               Appendix B, Eqs. triweight, terf)
+ *   contracted against the SSP block           (Section 2.1, Eqs. cspdeftheta, full_mdf)
+ *   x dust attenuation                         (Section 3.4, Eqs. attenuation-uvbump)
+ *   -> redshifted filter integrals, AB mags    (Section 2.2.1, Eq. restmag)
+ *
+ * and it returns the reverse-mode gradient of the magnitudes (Section 2.1:
+ * with the SSP block fixed, every gradient flows through the weights).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: DSPS_OK (0) or a negative dsps_status.  No exception ever
+ *    crosses the ABI.  dsps_last_error() gives a thread-local message for the
+ *    last failing call.
+ *  - Unless stated otherwise, array pointers are DEVICE pointers to
+ *    contiguous row-major memory owned by the caller (for example torch
+ *    tensors).  The library never frees caller memory, never allocates during
+ *    a compute call, and never synchronises the host in a compute call: work
+ *    is enqueued on the caller's hipStream_t.  Argument and shape checks run
+ *    on the host before any launch; a failed check enqueues nothing.
+ *  - Scratch memory comes from a caller-provided workspace whose size
+ *    dsps_workspace_size() reports; a smaller workspace is DSPS_ERR_WORKSPACE.
+ *  - Outputs are fully overwritten.  Inputs are const.  n_gal == 0 is a no-op
+ *    that returns DSPS_OK.  NaN and Inf inputs are not checked; they
+ *    propagate.  A band whose transmission misses the SED grid entirely
+ *    yields NaN; a zero numerator yields +Inf.
+ *  - Device faults surface as DSPS_ERR_DEVICE at the next call that checks
+ *    for launch errors, or at the caller's synchronisation.
+ *  - Compute calls on different streams may run concurrently if each has its
+ *    own workspace.  Handles are immutable after creation.
+ *  - All compute calls must be made with the device current on which the
+ *    handles were created.
+ */
+#ifndef DSPS_H
+#define DSPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DSPS_ABI_VERSION 1
+
+typedef enum {
+  DSPS_OK = 0,
+  DSPS_ERR_ARG = -1,          /* NULL pointer, bad enum or bad scalar        */
+  DSPS_ERR_SHAPE = -2,        /* sizes inconsistent or outside the limits    */
+  DSPS_ERR_DEVICE = -3,       /* HIP runtime error                           */
+  DSPS_ERR_WORKSPACE = -4,    /* workspace too small or misaligned           */
+  DSPS_ERR_UNSUPPORTED = -5,  /* valid request this build does not implement */
+  DSPS_ERR_ALLOC = -6         /* device allocation failed in a create call   */
+} dsps_status;
+
+typedef enum { DSPS_FP32 = 0, DSPS_BF16 = 1 } dsps_precision;
+
+/* Branch order of the k0 attenuation curve (Section 3.4, Eq. kzero).
+ * DSPS_K0_SALIM: Leitherer et al. 2002 below 0.15 micron, Calzetti et al. 2000
+ * at and above it (the order of the cited Salim et al. parameterisation).
+ * DSPS_K0_PRINTED: the order printed in Eq. kzero (Calzetti below). */
+typedef enum { DSPS_K0_SALIM = 0, DSPS_K0_PRINTED = 1 } dsps_k0_reading;
+
+typedef enum {
+  DSPS_OP_WEIGHTS = 0, DSPS_OP_SED = 1, DSPS_OP_MAGS = 2, DSPS_OP_MAGS_VJP = 3
+} dsps_op;
+
+/* Limits of this build. */
+#define DSPS_MAX_MET 16       /* metallicities in the SSP block             */
+#define DSPS_MAX_AGE 96       /* ages in the SSP block                      */
+#define DSPS_MAX_BAND 8       /* filters per filter set                     */
+#define DSPS_MAX_NT 2048      /* points of the tabulated SFH                */
+#define DSPS_MAX_FILTER_FLOATS 8192  /* n_band * n_pts of a filter set          */
+
+/* ---------------------------------------------------------------------------
+ * Resident SSP block (Section 2.1: the SSP spectra are loaded once as a
+ * contiguous block and then held fixed).
+ *
+ * dsps_ssp_create copies the block to the current device and prepares it:
+ * a wavelength-major, zero-padded float32 copy and, if requested, a bfloat16
+ * copy with one power-of-two float32 scale per (metallicity, age) row (the
+ * same rows dsps_quantize_bf16 produces), plus per-wavelength attenuation
+ * constants for the chosen k0 reading.
+ *   n_met, n_age, n_wave   grid sizes; 1 <= n_met <= 16, 1 <= n_age <= 96,
+ *                          2 <= n_wave
+ *   lgz    HOST [n_met]    log10 Z, strictly ascending
+ *   lg_age HOST [n_age]    log10 of the SSP age in years, strictly ascending
+ *   wave   HOST [n_wave]   rest-frame wavelength in Angstrom, strictly ascending
+ *   lum    HOST [n_met*n_age*n_wave] float32, L_sun/Hz per M_sun formed, row
+ *                          (met, age) major, finite and >= 0
+ *   precisions             bit mask of (1 << DSPS_FP32) | (1 << DSPS_BF16)
+ *   k0_reading             dsps_k0_reading
+ *   out                    receives the handle; unchanged on failure
+ * Allocates device memory (the only allocating call besides
+ * dsps_filters_create); synchronous.  Free with dsps_ssp_destroy.
+ * ------------------------------------------------------------------------ */
+typedef struct dsps_ssp_s dsps_ssp;
+int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz,
+                    const double *lg_age, const double *wave, const float *lum,
+                    int precisions, int k0_reading, dsps_ssp **out);
+void dsps_ssp_destroy(dsps_ssp *ssp);
+
+/* ---------------------------------------------------------------------------
+ * Resident filter set (Section 2.2.1, T_Q in Eq. restmag).
+ *   n_band  1..8 filters;  n_pts >= 2 points per filter, n_band * n_pts <= 8192
+ *   wave  HOST [n_band*n_pts] observed-frame Angstrom; each row uniformly
+ *         spaced and ascending (relative deviation <= 1e-9), else
+ *         DSPS_ERR_UNSUPPORTED
+ *   trans HOST [n_band*n_pts] transmission probability, finite and >= 0
+ * The transmission at an observed wavelength is the linear interpolation of
+ * the table, and zero outside it.  Allocates; synchronous.
+ * ------------------------------------------------------------------------ */
+typedef struct dsps_filters_s dsps_filters;
+int dsps_filters_create(int n_band, int n_pts, const double *wave, const double *trans,
+                        dsps_filters **out);
+void dsps_filters_destroy(dsps_filters *filters);
+
+/* Flat wCDM cosmology (Section 2.2.1, distance modulus after Eq. restmag).
+ * om0 in (0, 1]; h > 0; w0 < 0 (w0 = -1 is LCDM; the age t(z) then uses
+ * its closed form, otherwise quadrature). */
+typedef struct { double om0, w0, h; } dsps_cosmo;
+
+/* ---------------------------------------------------------------------------
+ * A population (structure of arrays, all DEVICE pointers).
+ *   n_gal       >= 0 galaxies;  n_t  2..2048 points of the SFH table
+ *   t_table     [n_t] cosmic time in Gyr, strictly ascending, shared by all
+ *               galaxies; no star forms before t_table[0] and the SFR is
+ *               taken as zero after t_table[n_t-1]
+ *   sfr         [n_gal*n_t] SFR in M_sun/yr, or NULL when sfh_params is set
+ *   sfh_params  [5*n_gal] rows (A, tau, alpha, q, t_q) of the parametric
+ *               history SFR(t) = A (t/tau)^alpha exp(-t/tau)
+ *               (1 - q Phi((t - t_q)/0.5 Gyr)), or NULL when sfr is set.
+ *               Exactly one of sfr and sfh_params is non-NULL.
+ *   z           [n_gal] observed redshift, >= 0
+ *   lgmet       [n_gal] MDF centre log10 Z at the pivot age
+ *   sigma_z     [n_gal] MDF width in dex, > 0
+ *   av, delta, bump [n_gal] attenuation A_V, power-law slope, Drude amplitude
+ *   lgmet_slope, lg_age_pivot  mu(tau) = lgmet + slope (log10 tau - pivot)
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int n_gal, n_t;
+  const double *t_table;
+  const double *sfr;
+  const double *sfh_params;
+  const float *z, *lgmet, *sigma_z, *av, *delta, *bump;
+  double lgmet_slope, lg_age_pivot;
+} dsps_pop;
+
+/* Workspace bytes a call of kind `op` needs for this population shape and
+ * precision (filters may be NULL for DSPS_OP_WEIGHTS and DSPS_OP_SED).  The
+ * workspace pointer must be 256-byte aligned. */
+int dsps_workspace_size(int op, const dsps_ssp *ssp, const dsps_filters *filters,
+                        int n_gal, int n_t, int precision, size_t *bytes);
+
+/* ---------------------------------------------------------------------------
+ * a0. Parametric SFH table (the stand-in for Diffstar, Section 3.1, Eq.
+ * diffstar): sfr[g*n_t + n] = SFR(t_table[n]) for params [5*n_gal] as in
+ * dsps_pop.  All DEVICE pointers; float64.
+ * ------------------------------------------------------------------------ */
+int dsps_sfh_table(const double *t_table, int n_t, const double *sfh_params, int n_gal,
+                   double *sfr, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * a1-a4. SSP weights (Eqs. cspsum, mstartot, agedep_mdf).
+ *   w      [n_gal*n_met*n_age] float32, M_sun formed per (metallicity, age)
+ *          bin, row (g, met, age) major: the age-bin mass times the
+ *          metallicity weight.  Age-bin masses are differences of the float64
+ *          cumulative trapezoid of the SFR; bins are bounded by geometric
+ *          midpoints of adjacent SSP ages (0 and +inf outermost), metallicity
+ *          bins by midpoints of adjacent log10 Z (-inf and +inf outermost).
+ *   mstar  [n_gal] float64 total mass formed up to t(z), or NULL
+ * ------------------------------------------------------------------------ */
+int dsps_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
+                 float *w, double *mstar, void *workspace, size_t workspace_bytes,
+                 hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * a5 (+a6). Composite rest-frame SED (Eqs. cspdeftheta, full_mdf), optionally
+ * attenuated (Eq. attenuation).
+ *   apply_dust  0 or 1;  precision  dsps_precision
+ *   sed   [n_gal*n_wave] float32, L_sun/Hz, rest frame
+ * ------------------------------------------------------------------------ */
+int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
+             int apply_dust, int precision, float *sed, void *workspace,
+             size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * a1-a7. Fused magnitudes: the SED is contracted, attenuated and integrated
+ * through every filter without ever being written to memory.
+ *   mags   [n_gal*n_band] float32 apparent AB magnitudes
+ *          m = -2.5 log10(num / (AB0 den)) + D_mod(z) - 2.5 log10(1+z)
+ *   bands  [n_gal*2*n_band] float32 (num_b then den_b per galaxy): the two
+ *          trapezoid sums of Eq. restmag over the redshifted grid with the
+ *          common factor (1+z) removed, or NULL.  dsps_mags_vjp accepts them
+ *          to skip the forward recomputation of the sums.
+ * ------------------------------------------------------------------------ */
+int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
+              const dsps_pop *pop, int precision, float *mags, float *bands,
+              void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * a9. Vector-Jacobian product of dsps_mags (reverse mode).
+ *   mags_bar        [n_gal*n_band] float32 cotangent of the magnitudes
+ *   bands           [n_gal*2*n_band] from dsps_mags with the same inputs and
+ *                   precision, or NULL (then recomputed)
+ *   sfr_bar         [n_gal*n_t] float64 gradient w.r.t. the SFR table, or NULL
+ *   sfh_params_bar  [5*n_gal] float64 gradient w.r.t. (A, tau, alpha, q, t_q);
+ *                   requires pop->sfh_params, else NULL
+ *   lgmet_bar, sigma_bar, av_bar, delta_bar, bump_bar
+ *                   [n_gal] float32 each, or NULL
+ * The SED is recomputed tile by tile, never stored.  Redshift gets no
+ * gradient.
+ * ------------------------------------------------------------------------ */
+int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
+                  const dsps_pop *pop, int precision, const float *mags_bar,
+                  const float *bands, double *sfr_bar, double *sfh_params_bar,
+                  float *lgmet_bar, float *sigma_bar, float *av_bar, float *delta_bar,
+                  float *bump_bar, void *workspace, size_t workspace_bytes,
+                  hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * a8. BF16 quantisation with power-of-two row scales.
+ *   x      [rows*cols] float32, finite
+ *   q      [rows*cols] bfloat16 bits: round-to-nearest-even of x / scale[row]
+ *   scale  [rows] float32, the smallest power of two >= max(x[row]) (1 for an
+ *          all-zero row)
+ * ------------------------------------------------------------------------ */
+int dsps_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float *scale,
+                       hipStream_t stream);
+
+/* Introspection. */
+int dsps_abi_version(void);
+const char *dsps_last_error(void);
+/* Grid sizes of a handle: n_met, n_age, n_wave, precisions, k0_reading. */
+int dsps_ssp_info(const dsps_ssp *ssp, int *n_met, int *n_age, int *n_wave,
+                  int *precisions, int *k0_reading);
+int dsps_filters_info(const dsps_filters *filters, int *n_band, int *n_pts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSPS_H */

@@ -1,0 +1,19 @@
+"""MI355X-native hot path of differentiable stellar population synthesis.
+
+The compute lives in libdsps.so (HIP for gfx950, C ABI in include/dsps.h);
+this package only marshals arguments.  Importing it loads the library and
+raises if it has not been built.
+"""
+
+from . import _native
+from ._native import DspsError, load as load_library
+
+load_library()
+
+from .api import (Cosmology, DevicePopulation, FilterBank, SspBlock, Workspace,  # noqa: E402
+                  mags, quantize_bf16, sed, sfh_table, weights, workspace_size)
+
+__all__ = [
+    "Cosmology", "DevicePopulation", "FilterBank", "SspBlock", "Workspace", "DspsError",
+    "mags", "quantize_bf16", "sed", "sfh_table", "weights", "workspace_size", "load_library",
+]

@@ -1,0 +1,274 @@
+"""Thin Python binding over the libdsps C ABI.
+
+Argument marshalling only: torch provides device memory and the current
+stream, every step of the computation runs in the HIP library.  Function
+names follow the C entry points (dsps_weights -> weights, ...).
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+_PREC = {"fp32": N.FP32, "bf16": N.BF16, N.FP32: N.FP32, N.BF16: N.BF16}
+_K0 = {"salim": N.K0_SALIM, "printed": N.K0_PRINTED}
+
+
+def _lib():
+    return N.load()
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(x, dtype, device):
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=device)
+
+
+def _workspace(nbytes: int, device) -> tuple[torch.Tensor | None, int]:
+    if nbytes == 0:
+        return None, 0
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, off
+
+
+class SspBlock:
+    """Resident SSP block (dsps_ssp_create)."""
+
+    def __init__(self, lgz, lg_age, wave, lum, precisions=("fp32", "bf16"), k0_reading="salim"):
+        lgz = np.ascontiguousarray(lgz, dtype=np.float64)
+        lg_age = np.ascontiguousarray(lg_age, dtype=np.float64)
+        wave = np.ascontiguousarray(wave, dtype=np.float64)
+        lum = np.ascontiguousarray(lum, dtype=np.float32)
+        n_met, n_age, n_wave = lgz.size, lg_age.size, wave.size
+        if lum.size != n_met * n_age * n_wave:
+            raise ValueError("lum has the wrong size")
+        mask = 0
+        for p in precisions:
+            mask |= 1 << _PREC[p]
+        torch.cuda.init()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        rc = _lib().dsps_ssp_create(n_met, n_age, n_wave, lgz.ctypes.data, lg_age.ctypes.data,
+                                    wave.ctypes.data, lum.ctypes.data, mask, _K0[k0_reading],
+                                    ctypes.byref(h))
+        N.check(rc, "dsps_ssp_create")
+        self.handle = h
+        self.n_met, self.n_age, self.n_wave = n_met, n_age, n_wave
+        self.wave = wave
+
+    @classmethod
+    def from_synth(cls, ssp, **kw):
+        return cls(ssp.lgz, ssp.lg_age, ssp.wave, ssp.lum, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib().dsps_ssp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FilterBank:
+    """Resident filter set (dsps_filters_create)."""
+
+    def __init__(self, wave, trans):
+        wave = np.ascontiguousarray(wave, dtype=np.float64)
+        trans = np.ascontiguousarray(trans, dtype=np.float64)
+        n_band, n_pts = wave.shape
+        h = ctypes.c_void_p()
+        rc = _lib().dsps_filters_create(n_band, n_pts, wave.ctypes.data, trans.ctypes.data,
+                                        ctypes.byref(h))
+        N.check(rc, "dsps_filters_create")
+        self.handle = h
+        self.n_band, self.n_pts = n_band, n_pts
+
+    @classmethod
+    def from_synth(cls, f):
+        return cls(f.wave, f.trans)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib().dsps_filters_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Cosmology:
+    om0: float = 0.3
+    h: float = 0.7
+    w0: float = -1.0
+
+    def c(self):
+        return N.Cosmo(self.om0, self.w0, self.h)
+
+
+@dataclass
+class DevicePopulation:
+    """Device-resident population (structure of arrays)."""
+
+    t_table: torch.Tensor
+    sfr: torch.Tensor | None
+    sfh_params: torch.Tensor | None
+    z: torch.Tensor
+    lgmet: torch.Tensor
+    sigma_z: torch.Tensor
+    av: torch.Tensor
+    delta: torch.Tensor
+    bump: torch.Tensor
+    lgmet_slope: float = 0.1
+    lg_age_pivot: float = 9.0
+
+    @property
+    def n_gal(self):
+        return int(self.z.shape[0])
+
+    @property
+    def n_t(self):
+        return int(self.t_table.shape[0])
+
+    @property
+    def device(self):
+        return self.z.device
+
+    def c(self):
+        return N.Pop(self.n_gal, self.n_t, _ptr(self.t_table), _ptr(self.sfr), _ptr(self.sfh_params),
+                     _ptr(self.z), _ptr(self.lgmet), _ptr(self.sigma_z), _ptr(self.av),
+                     _ptr(self.delta), _ptr(self.bump), self.lgmet_slope, self.lg_age_pivot)
+
+    @classmethod
+    def from_synth(cls, pop, device="cuda", sfr=None, use_params=False):
+        """Upload a synth.Population.  With use_params the library evaluates
+        the parametric history itself; otherwise `sfr` (host or device table)
+        is used."""
+        d = torch.device(device)
+        f32 = lambda a: _dev(a, torch.float32, d)
+        if use_params:
+            sfr_t, par = None, _dev(pop.sfh_params, torch.float64, d)
+        else:
+            if sfr is None:
+                raise ValueError("give an SFR table or use_params=True")
+            sfr_t, par = _dev(sfr, torch.float64, d), None
+        return cls(t_table=_dev(pop.t_table, torch.float64, d), sfr=sfr_t, sfh_params=par,
+                   z=f32(pop.z), lgmet=f32(pop.lgmet), sigma_z=f32(pop.sigma_z), av=f32(pop.av),
+                   delta=f32(pop.delta), bump=f32(pop.bump), lgmet_slope=float(pop.lgmet_slope),
+                   lg_age_pivot=float(pop.lg_age_pivot))
+
+    def with_sfr(self, sfr):
+        return DevicePopulation(self.t_table, sfr, None, self.z, self.lgmet, self.sigma_z, self.av,
+                                self.delta, self.bump, self.lgmet_slope, self.lg_age_pivot)
+
+
+def workspace_size(op: int, ssp: SspBlock, filters: FilterBank | None, n_gal: int, n_t: int,
+                   precision="fp32") -> int:
+    out = ctypes.c_size_t()
+    rc = _lib().dsps_workspace_size(op, ssp.handle, filters.handle if filters else None, n_gal, n_t,
+                                    _PREC[precision], ctypes.byref(out))
+    N.check(rc, "dsps_workspace_size")
+    return int(out.value)
+
+
+def sfh_table(t_table: torch.Tensor, sfh_params: torch.Tensor, stream=None) -> torch.Tensor:
+    """dsps_sfh_table: float64 [n_gal, n_t] from params [5, n_gal]."""
+    t_table = t_table.contiguous()
+    sfh_params = sfh_params.contiguous()
+    n_t, n_gal = t_table.shape[0], sfh_params.shape[1]
+    out = torch.empty((n_gal, n_t), dtype=torch.float64, device=t_table.device)
+    rc = _lib().dsps_sfh_table(_ptr(t_table), n_t, _ptr(sfh_params), n_gal, _ptr(out), _stream(stream))
+    N.check(rc, "dsps_sfh_table")
+    return out
+
+
+def weights(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, with_mstar=False, stream=None):
+    """dsps_weights: W [n_gal, n_met, n_age] float32 (and M_star float64)."""
+    w = torch.empty((pop.n_gal, ssp.n_met, ssp.n_age), dtype=torch.float32, device=pop.device)
+    ms = torch.empty(pop.n_gal, dtype=torch.float64, device=pop.device) if with_mstar else None
+    c, p = cosmo.c(), pop.c()
+    rc = _lib().dsps_weights(ssp.handle, ctypes.byref(c), ctypes.byref(p), _ptr(w), _ptr(ms), None, 0,
+                             _stream(stream))
+    N.check(rc, "dsps_weights")
+    return (w, ms) if with_mstar else w
+
+
+def sed(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, apply_dust=True, precision="fp32",
+        stream=None):
+    """dsps_sed: rest-frame SED [n_gal, n_wave] float32."""
+    out = torch.empty((pop.n_gal, ssp.n_wave), dtype=torch.float32, device=pop.device)
+    nbytes = workspace_size(N.OP_SED, ssp, None, pop.n_gal, pop.n_t, precision)
+    buf, off = _workspace(nbytes, pop.device)
+    c, p = cosmo.c(), pop.c()
+    ws = ctypes.c_void_p(buf.data_ptr() + off) if buf is not None else None
+    rc = _lib().dsps_sed(ssp.handle, ctypes.byref(c), ctypes.byref(p), int(bool(apply_dust)),
+                         _PREC[precision], _ptr(out), ws, nbytes, _stream(stream))
+    N.check(rc, "dsps_sed")
+    return out
+
+
+class Workspace:
+    """Reusable workspace for repeated calls of one shape."""
+
+    def __init__(self, nbytes: int, device):
+        self.nbytes = nbytes
+        self.buf, self.off = _workspace(nbytes, device)
+
+    def ptr(self):
+        return None if self.buf is None else ctypes.c_void_p(self.buf.data_ptr() + self.off)
+
+
+def mags(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopulation,
+         precision="fp32", with_bands=False, workspace: Workspace | None = None, out=None,
+         bands_out=None, stream=None):
+    """dsps_mags: apparent AB magnitudes [n_gal, n_band] float32 (and the
+    band sums [n_gal, 2, n_band])."""
+    nb = filters.n_band
+    m = out if out is not None else torch.empty((pop.n_gal, nb), dtype=torch.float32, device=pop.device)
+    bands = None
+    if with_bands:
+        bands = bands_out if bands_out is not None else torch.empty(
+            (pop.n_gal, 2, nb), dtype=torch.float32, device=pop.device)
+    if workspace is None:
+        workspace = Workspace(workspace_size(N.OP_MAGS, ssp, filters, pop.n_gal, pop.n_t, precision),
+                              pop.device)
+    c, p = cosmo.c(), pop.c()
+    rc = _lib().dsps_mags(ssp.handle, filters.handle, ctypes.byref(c), ctypes.byref(p),
+                          _PREC[precision], _ptr(m), _ptr(bands), workspace.ptr(), workspace.nbytes,
+                          _stream(stream))
+    N.check(rc, "dsps_mags")
+    return (m, bands) if with_bands else m
+
+
+def quantize_bf16(x: torch.Tensor, stream=None):
+    """dsps_quantize_bf16: (bf16 bits as int16 [rows, cols], scale float32 [rows])."""
+    x = x.to(torch.float32).contiguous()
+    rows, cols = x.shape
+    q = torch.empty((rows, cols), dtype=torch.int16, device=x.device)
+    s = torch.empty(rows, dtype=torch.float32, device=x.device)
+    rc = _lib().dsps_quantize_bf16(_ptr(x), rows, cols, _ptr(q), _ptr(s), _stream(stream))
+    N.check(rc, "dsps_quantize_bf16")
+    return q, s

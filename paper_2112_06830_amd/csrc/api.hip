@@ -1,0 +1,612 @@
+// Host side of libdsps: argument checks, resident handles, workspace layout
+// and the launch sequence of every C-ABI entry point.
+#include "dsps_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+namespace dsps {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  if (e == hipSuccess) return DSPS_OK;
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return DSPS_ERR_DEVICE;
+}
+
+#define DSPS_CHECK(cond, code, ...) \
+  do {                              \
+    if (!(cond)) {                  \
+      set_error(__VA_ARGS__);       \
+      return (code);                \
+    }                               \
+  } while (0)
+
+#define DSPS_TRY(expr)           \
+  do {                           \
+    const int rc_ = (expr);      \
+    if (rc_ != DSPS_OK) return rc_; \
+  } while (0)
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_16.
+static GaussLegendre build_gl16() {
+  GaussLegendre gl{};
+  const int n = GL_N;
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    gl.x[i] = x;
+    gl.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return gl;
+}
+
+const GaussLegendre &gauss_legendre16() {
+  static const GaussLegendre gl = build_gl16();
+  return gl;
+}
+
+CosmoArgs make_cosmo(const dsps_cosmo &c) {
+  CosmoArgs a{};
+  a.om0 = c.om0;
+  a.ol = 1.0 - c.om0;
+  a.w0 = c.w0;
+  a.hubble_time_gyr = GYR_PER_MPC_S_KM / (100.0 * c.h);
+  a.hubble_dist_mpc = LIGHT_KM_S / (100.0 * c.h);
+  a.lcdm = c.w0 == -1.0 ? 1 : 0;
+  return a;
+}
+
+static int check_cosmo(const dsps_cosmo *c) {
+  DSPS_CHECK(c, DSPS_ERR_ARG, "cosmo is NULL");
+  DSPS_CHECK(c->om0 > 0.0 && c->om0 <= 1.0, DSPS_ERR_ARG, "om0 must be in (0, 1], got %g", c->om0);
+  DSPS_CHECK(c->h > 0.0 && std::isfinite(c->h), DSPS_ERR_ARG, "h must be positive, got %g", c->h);
+  DSPS_CHECK(c->w0 < 0.0 && std::isfinite(c->w0), DSPS_ERR_ARG, "w0 must be negative, got %g", c->w0);
+  return DSPS_OK;
+}
+
+static int check_device(int device) {
+  int cur = -1;
+  DSPS_TRY(hip_fail(hipGetDevice(&cur), "hipGetDevice"));
+  DSPS_CHECK(cur == device, DSPS_ERR_ARG, "handle lives on device %d but device %d is current",
+             device, cur);
+  return DSPS_OK;
+}
+
+// ---------------------------------------------------------------- attenuation
+// k0(lambda) of the Salim-type curve: Calzetti et al. (2000) starburst curve
+// (R_V = 4.05; UV-optical branch below 0.63 micron) and Leitherer et al.
+// (2002) far-UV curve, joined at 0.15 micron in the order chosen.
+static double calzetti00(double um) {
+  if (um < 0.63)
+    return 2.659 * (-2.156 + 1.509 / um - 0.198 / (um * um) + 0.011 / (um * um * um)) + DUST_RV;
+  return 2.659 * (-1.857 + 1.040 / um) + DUST_RV;
+}
+static double leitherer02(double um) {
+  return 5.472 + 0.671 / um - 9.218e-3 / (um * um) + 2.620e-3 / (um * um * um);
+}
+static double k0_curve(double angstrom, int reading) {
+  const double um = angstrom * 1e-4;
+  const bool below = angstrom < DUST_SWITCH_ANGSTROM;
+  if (reading == DSPS_K0_SALIM) return below ? leitherer02(um) : calzetti00(um);
+  return below ? calzetti00(um) : leitherer02(um);
+}
+static double drude_shape(double l) {
+  const double lw = l * BUMP_WIDTH;
+  const double d = l * l - BUMP_CENTRE * BUMP_CENTRE;
+  return lw * lw / (d * d + lw * lw);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace dsps
+
+using namespace dsps;
+
+struct dsps_ssp_s : SspHandle {};
+struct dsps_filters_s : FiltersHandle {};
+
+extern "C" {
+
+int dsps_abi_version(void) { return DSPS_ABI_VERSION; }
+
+const char *dsps_last_error(void) { return g_err; }
+
+// ------------------------------------------------------------------ SSP block
+int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const double *lg_age,
+                    const double *wave, const float *lum, int precisions, int k0_reading,
+                    dsps_ssp **out) {
+  DSPS_CHECK(out && lgz && lg_age && wave && lum, DSPS_ERR_ARG, "NULL argument to dsps_ssp_create");
+  DSPS_CHECK(n_met >= 1 && n_met <= DSPS_MAX_MET, DSPS_ERR_SHAPE, "n_met %d outside [1, %d]", n_met, DSPS_MAX_MET);
+  DSPS_CHECK(n_age >= 1 && n_age <= DSPS_MAX_AGE, DSPS_ERR_SHAPE, "n_age %d outside [1, %d]", n_age, DSPS_MAX_AGE);
+  DSPS_CHECK(n_wave >= 2, DSPS_ERR_SHAPE, "n_wave %d < 2", n_wave);
+  DSPS_CHECK(precisions >= 1 && precisions <= 3, DSPS_ERR_ARG, "precisions mask %d invalid", precisions);
+  DSPS_CHECK(k0_reading == DSPS_K0_SALIM || k0_reading == DSPS_K0_PRINTED, DSPS_ERR_ARG,
+             "k0_reading %d invalid", k0_reading);
+  for (int j = 1; j < n_met; ++j) DSPS_CHECK(lgz[j] > lgz[j - 1], DSPS_ERR_ARG, "lgz not ascending");
+  for (int i = 1; i < n_age; ++i) DSPS_CHECK(lg_age[i] > lg_age[i - 1], DSPS_ERR_ARG, "lg_age not ascending");
+  for (int l = 0; l < n_wave; ++l) {
+    DSPS_CHECK(wave[l] > 0.0 && std::isfinite(wave[l]), DSPS_ERR_ARG, "wave[%d] not positive", l);
+    if (l) DSPS_CHECK(wave[l] > wave[l - 1], DSPS_ERR_ARG, "wave not ascending");
+  }
+  const size_t n_lum = (size_t)n_met * n_age * n_wave;
+  for (size_t i = 0; i < n_lum; ++i)
+    DSPS_CHECK(lum[i] >= 0.0f && std::isfinite(lum[i]), DSPS_ERR_ARG, "lum[%zu] negative or not finite", i);
+
+  SspView v{};
+  v.n_met = n_met;
+  v.n_age = n_age;
+  v.n_wave = n_wave;
+  v.n_wave_pad = (n_wave + TILE_L - 1) / TILE_L * TILE_L;
+  v.k_pad = n_met * AGE_PAD;
+  const int nwp = v.n_wave_pad, kp = v.k_pad;
+  const bool want32 = precisions & (1 << DSPS_FP32), want16 = precisions & (1 << DSPS_BF16);
+
+  // host-side derived tables
+  std::vector<double> age_edges(n_age + 1), met_edges(n_met + 1);
+  age_edges[0] = 0.0;
+  for (int i = 1; i < n_age; ++i) age_edges[i] = std::pow(10.0, 0.5 * (lg_age[i - 1] + lg_age[i])) / YEARS_PER_GYR;
+  age_edges[n_age] = std::numeric_limits<double>::infinity();
+  met_edges[0] = -std::numeric_limits<double>::infinity();
+  for (int j = 1; j < n_met; ++j) met_edges[j] = 0.5 * (lgz[j - 1] + lgz[j]);
+  met_edges[n_met] = std::numeric_limits<double>::infinity();
+  std::vector<float4> lconst(nwp);
+  std::vector<float> qw(nwp, 0.0f);
+  for (int l = 0; l < nwp; ++l) {
+    const double lam = wave[std::min(l, n_wave - 1)];
+    lconst[l] = make_float4((float)lam, (float)std::log2(lam / DUST_LAMBDA_V),
+                            (float)k0_curve(lam, k0_reading), (float)drude_shape(lam));
+    if (l < n_wave) {
+      const double lo = wave[std::max(l - 1, 0)], hi = wave[std::min(l + 1, n_wave - 1)];
+      qw[l] = (float)(0.5 * (hi - lo) / lam);
+    }
+  }
+
+  // one device allocation for the resident block
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
+  const size_t o_wave = take(sizeof(double) * n_wave);
+  const size_t o_age = take(sizeof(double) * (n_age + 1));
+  const size_t o_met = take(sizeof(double) * (n_met + 1));
+  const size_t o_lg = take(sizeof(double) * n_age);
+  const size_t o_st32 = want32 ? take(sizeof(float) * (size_t)nwp * kp) : 0;
+  const size_t o_st16 = want16 ? take(sizeof(uint16_t) * (size_t)nwp * kp) : 0;
+  const size_t o_ks = take(sizeof(float) * kp);
+  const size_t o_lc = take(sizeof(float4) * nwp);
+  const size_t o_q = take(sizeof(float) * nwp);
+  void *base = nullptr;
+  if (hipMalloc(&base, off) != hipSuccess) {
+    set_error("hipMalloc of %zu bytes for the SSP block failed", off);
+    return DSPS_ERR_ALLOC;
+  }
+  char *b = (char *)base;
+  float *d_rows = nullptr;
+  uint16_t *d_q = nullptr;
+  float *d_scale = nullptr;
+  int rc = DSPS_OK;
+  auto cleanup = [&]() {
+    if (d_rows) (void)hipFree(d_rows);
+    if (d_q) (void)hipFree(d_q);
+    if (d_scale) (void)hipFree(d_scale);
+  };
+  do {
+    rc = hip_fail(hipMemcpy(b + o_wave, wave, sizeof(double) * n_wave, hipMemcpyHostToDevice), "upload wave");
+    if (rc) break;
+    rc = hip_fail(hipMemcpy(b + o_age, age_edges.data(), sizeof(double) * (n_age + 1), hipMemcpyHostToDevice), "upload ages");
+    if (rc) break;
+    rc = hip_fail(hipMemcpy(b + o_met, met_edges.data(), sizeof(double) * (n_met + 1), hipMemcpyHostToDevice), "upload mets");
+    if (rc) break;
+    rc = hip_fail(hipMemcpy(b + o_lg, lg_age, sizeof(double) * n_age, hipMemcpyHostToDevice), "upload lg_age");
+    if (rc) break;
+    rc = hip_fail(hipMemcpy(b + o_lc, lconst.data(), sizeof(float4) * nwp, hipMemcpyHostToDevice), "upload lconst");
+    if (rc) break;
+    rc = hip_fail(hipMemcpy(b + o_q, qw.data(), sizeof(float) * nwp, hipMemcpyHostToDevice), "upload qweight");
+    if (rc) break;
+    const int rows = n_met * n_age;
+    if (hipMalloc((void **)&d_rows, sizeof(float) * n_lum) != hipSuccess) { rc = DSPS_ERR_ALLOC; set_error("hipMalloc staging"); break; }
+    rc = hip_fail(hipMemcpy(d_rows, lum, sizeof(float) * n_lum, hipMemcpyHostToDevice), "upload lum");
+    if (rc) break;
+    std::vector<float> kscale(kp, 1.0f);
+    if (want16) {
+      if (hipMalloc((void **)&d_q, sizeof(uint16_t) * n_lum) != hipSuccess ||
+          hipMalloc((void **)&d_scale, sizeof(float) * rows) != hipSuccess) {
+        rc = DSPS_ERR_ALLOC; set_error("hipMalloc staging"); break;
+      }
+      rc = launch_quantize_bf16(d_rows, rows, n_wave, d_q, d_scale, nullptr);
+      if (rc) break;
+      std::vector<float> scale(rows);
+      rc = hip_fail(hipMemcpy(scale.data(), d_scale, sizeof(float) * rows, hipMemcpyDeviceToHost), "download scales");
+      if (rc) break;
+      for (int j = 0; j < n_met; ++j)
+        for (int i = 0; i < n_age; ++i) kscale[j * AGE_PAD + i] = scale[j * n_age + i];
+    }
+    rc = hip_fail(hipMemcpy(b + o_ks, kscale.data(), sizeof(float) * kp, hipMemcpyHostToDevice), "upload kscale");
+    if (rc) break;
+    rc = launch_pack_table(d_rows, d_q, n_met, n_age, n_wave, nwp, kp,
+                           want32 ? (float *)(b + o_st32) : nullptr,
+                           want16 ? (uint16_t *)(b + o_st16) : nullptr, nullptr);
+    if (rc) break;
+    rc = hip_fail(hipDeviceSynchronize(), "SSP block preparation");
+  } while (false);
+  cleanup();
+  if (rc != DSPS_OK) {
+    (void)hipFree(base);
+    return rc;
+  }
+  v.wave = (const double *)(b + o_wave);
+  v.age_edges = (const double *)(b + o_age);
+  v.met_edges = (const double *)(b + o_met);
+  v.lg_age = (const double *)(b + o_lg);
+  v.st32 = want32 ? (const float *)(b + o_st32) : nullptr;
+  v.st16 = want16 ? (const uint16_t *)(b + o_st16) : nullptr;
+  v.kscale = (const float *)(b + o_ks);
+  v.lconst = (const float4 *)(b + o_lc);
+  v.qweight = (const float *)(b + o_q);
+  dsps_ssp *h = new dsps_ssp();
+  (void)hipGetDevice(&h->device);
+  h->precisions = precisions;
+  h->k0_reading = k0_reading;
+  h->v = v;
+  h->alloc = base;
+  *out = h;
+  return DSPS_OK;
+}
+
+void dsps_ssp_destroy(dsps_ssp *ssp) {
+  if (!ssp) return;
+  if (ssp->alloc) (void)hipFree(ssp->alloc);
+  delete ssp;
+}
+
+int dsps_ssp_info(const dsps_ssp *ssp, int *n_met, int *n_age, int *n_wave, int *precisions,
+                  int *k0_reading) {
+  DSPS_CHECK(ssp, DSPS_ERR_ARG, "ssp is NULL");
+  if (n_met) *n_met = ssp->v.n_met;
+  if (n_age) *n_age = ssp->v.n_age;
+  if (n_wave) *n_wave = ssp->v.n_wave;
+  if (precisions) *precisions = ssp->precisions;
+  if (k0_reading) *k0_reading = ssp->k0_reading;
+  return DSPS_OK;
+}
+
+// ------------------------------------------------------------------ filters
+int dsps_filters_create(int n_band, int n_pts, const double *wave, const double *trans,
+                        dsps_filters **out) {
+  DSPS_CHECK(out && wave && trans, DSPS_ERR_ARG, "NULL argument to dsps_filters_create");
+  DSPS_CHECK(n_band >= 1 && n_band <= DSPS_MAX_BAND, DSPS_ERR_SHAPE, "n_band %d outside [1, %d]", n_band, DSPS_MAX_BAND);
+  DSPS_CHECK(n_pts >= 2 && (long long)n_band * n_pts <= DSPS_MAX_FILTER_FLOATS, DSPS_ERR_SHAPE,
+             "n_pts %d invalid (n_band * n_pts must be <= %d)", n_pts, DSPS_MAX_FILTER_FLOATS);
+  std::vector<float> tr((size_t)n_band * n_pts);
+  std::vector<float2> grid(n_band);
+  double lo = std::numeric_limits<double>::infinity(), hi = -lo;
+  for (int b = 0; b < n_band; ++b) {
+    const double *w = wave + (size_t)b * n_pts;
+    const double w0 = w[0], w1 = w[n_pts - 1];
+    DSPS_CHECK(w1 > w0 && w0 > 0.0 && std::isfinite(w1), DSPS_ERR_ARG, "filter %d wavelengths invalid", b);
+    const double dw = (w1 - w0) / (n_pts - 1);
+    for (int i = 0; i < n_pts; ++i) {
+      DSPS_CHECK(std::fabs(w[i] - (w0 + i * dw)) <= 1e-9 * w1, DSPS_ERR_UNSUPPORTED,
+                 "filter %d is not uniformly gridded", b);
+      const double t = trans[(size_t)b * n_pts + i];
+      DSPS_CHECK(t >= 0.0 && std::isfinite(t), DSPS_ERR_ARG, "filter %d transmission invalid", b);
+      tr[(size_t)b * n_pts + i] = (float)t;
+    }
+    grid[b] = make_float2((float)w0, (float)(1.0 / dw));
+    lo = std::min(lo, w0);
+    hi = std::max(hi, w1);
+  }
+  size_t off = 0;
+  const size_t o_tr = off; off += align256(sizeof(float) * tr.size());
+  const size_t o_gr = off; off += align256(sizeof(float2) * n_band);
+  void *base = nullptr;
+  if (hipMalloc(&base, off) != hipSuccess) { set_error("hipMalloc filters"); return DSPS_ERR_ALLOC; }
+  char *b = (char *)base;
+  int rc = hip_fail(hipMemcpy(b + o_tr, tr.data(), sizeof(float) * tr.size(), hipMemcpyHostToDevice), "upload filters");
+  if (!rc) rc = hip_fail(hipMemcpy(b + o_gr, grid.data(), sizeof(float2) * n_band, hipMemcpyHostToDevice), "upload grids");
+  if (rc) { (void)hipFree(base); return rc; }
+  dsps_filters *h = new dsps_filters();
+  (void)hipGetDevice(&h->device);
+  h->v.n_band = n_band;
+  h->v.n_pts = n_pts;
+  h->v.trans = (const float *)(b + o_tr);
+  h->v.grid = (const float2 *)(b + o_gr);
+  h->obs_lo = lo;
+  h->obs_hi = hi;
+  h->alloc = base;
+  *out = h;
+  return DSPS_OK;
+}
+
+void dsps_filters_destroy(dsps_filters *f) {
+  if (!f) return;
+  if (f->alloc) (void)hipFree(f->alloc);
+  delete f;
+}
+
+int dsps_filters_info(const dsps_filters *f, int *n_band, int *n_pts) {
+  DSPS_CHECK(f, DSPS_ERR_ARG, "filters is NULL");
+  if (n_band) *n_band = f->v.n_band;
+  if (n_pts) *n_pts = f->v.n_pts;
+  return DSPS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ workspace
+namespace dsps {
+
+constexpr int BATCH = 32768;   // galaxies per weights + GEMM round trip
+
+struct Layout {
+  size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
+  int batch = 0, n_groups = 0;
+};
+
+static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int precision) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
+  L.batch = std::min(n_gal, BATCH);
+  L.n_groups = (v.n_wave_pad / TILE_L + CHUNKS_PER_GROUP - 1) / CHUNKS_PER_GROUP;
+  const size_t elem = precision == DSPS_BF16 ? 2 : 4;
+  if (op == DSPS_OP_WEIGHTS) { L.total = 0; return L; }
+  if (op == DSPS_OP_SED) {
+    L.meta = take(sizeof(GalaxyMeta) * (size_t)n_gal);
+    L.w = take(elem * (size_t)L.batch * v.k_pad);
+    L.total = off;
+    return L;
+  }
+  L.hist = take(sizeof(int) * ZBINS);
+  L.perm = take(sizeof(int) * (size_t)n_gal);
+  L.meta = take(sizeof(GalaxyMeta) * (size_t)n_gal);
+  L.range = take(sizeof(GalaxyRange) * (size_t)n_gal);
+  L.offset = take(sizeof(double) * (size_t)n_gal);
+  L.w = take(elem * (size_t)L.batch * v.k_pad);
+  L.partial = take(sizeof(float) * (size_t)L.batch * L.n_groups * 2 * n_band);
+  L.total = off;
+  return L;
+}
+
+static int check_pop(const dsps_pop *p, bool need_dust) {
+  DSPS_CHECK(p, DSPS_ERR_ARG, "pop is NULL");
+  DSPS_CHECK(p->n_gal >= 0, DSPS_ERR_SHAPE, "n_gal %d negative", p->n_gal);
+  DSPS_CHECK(p->n_t >= 2 && p->n_t <= DSPS_MAX_NT, DSPS_ERR_SHAPE, "n_t %d outside [2, %d]", p->n_t, DSPS_MAX_NT);
+  if (p->n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(p->t_table, DSPS_ERR_ARG, "t_table is NULL");
+  DSPS_CHECK((p->sfr != nullptr) != (p->sfh_params != nullptr), DSPS_ERR_ARG,
+             "exactly one of sfr and sfh_params must be set");
+  DSPS_CHECK(p->z && p->lgmet && p->sigma_z, DSPS_ERR_ARG, "z, lgmet and sigma_z are required");
+  if (need_dust) DSPS_CHECK(p->av && p->delta && p->bump, DSPS_ERR_ARG, "av, delta and bump are required");
+  DSPS_CHECK(std::isfinite(p->lgmet_slope) && std::isfinite(p->lg_age_pivot), DSPS_ERR_ARG,
+             "lgmet_slope and lg_age_pivot must be finite");
+  return DSPS_OK;
+}
+
+static int check_precision(const dsps_ssp *s, int precision) {
+  DSPS_CHECK(precision == DSPS_FP32 || precision == DSPS_BF16, DSPS_ERR_ARG, "precision %d invalid", precision);
+  DSPS_CHECK(s->precisions & (1 << precision), DSPS_ERR_UNSUPPORTED,
+             "SSP handle was created without precision %d", precision);
+  return DSPS_OK;
+}
+
+static int check_workspace(void *ws, size_t have, size_t need) {
+  if (need == 0) return DSPS_OK;
+  DSPS_CHECK(ws, DSPS_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", need);
+  DSPS_CHECK(((uintptr_t)ws & 255u) == 0, DSPS_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  DSPS_CHECK(have >= need, DSPS_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", have, need);
+  return DSPS_OK;
+}
+
+static WeightsLaunch base_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *p) {
+  WeightsLaunch a{};
+  a.t_table = p->t_table;
+  a.sfr = p->sfr;
+  a.sfh_params = p->sfh_params;
+  a.z = p->z; a.lgmet = p->lgmet; a.sigma_z = p->sigma_z;
+  a.av = p->av; a.delta = p->delta; a.bump = p->bump;
+  a.n_gal = p->n_gal;
+  a.n_t = p->n_t;
+  a.slope = p->lgmet_slope;
+  a.pivot = p->lg_age_pivot;
+  a.cosmo = make_cosmo(*cosmo);
+  a.gl = gauss_legendre16();
+  a.ssp = ssp->v;
+  return a;
+}
+
+}  // namespace dsps
+
+extern "C" {
+
+int dsps_workspace_size(int op, const dsps_ssp *ssp, const dsps_filters *filters, int n_gal,
+                        int n_t, int precision, size_t *bytes) {
+  DSPS_CHECK(ssp && bytes, DSPS_ERR_ARG, "NULL argument to dsps_workspace_size");
+  DSPS_CHECK(op >= DSPS_OP_WEIGHTS && op <= DSPS_OP_MAGS_VJP, DSPS_ERR_ARG, "op %d invalid", op);
+  DSPS_CHECK(n_gal >= 0, DSPS_ERR_SHAPE, "n_gal negative");
+  (void)n_t;
+  int n_band = 0;
+  if (op == DSPS_OP_MAGS || op == DSPS_OP_MAGS_VJP) {
+    DSPS_CHECK(filters, DSPS_ERR_ARG, "filters required for this op");
+    n_band = filters->v.n_band;
+  }
+  if (op == DSPS_OP_MAGS_VJP) {
+    set_error("dsps_mags_vjp is not available in this build");
+    return DSPS_ERR_UNSUPPORTED;
+  }
+  *bytes = make_layout(op, ssp->v, n_band, n_gal, precision).total;
+  return DSPS_OK;
+}
+
+int dsps_sfh_table(const double *t_table, int n_t, const double *sfh_params, int n_gal,
+                   double *sfr, hipStream_t stream) {
+  DSPS_CHECK(n_gal >= 0 && n_t >= 1, DSPS_ERR_SHAPE, "bad sizes n_gal=%d n_t=%d", n_gal, n_t);
+  if (n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(t_table && sfh_params && sfr, DSPS_ERR_ARG, "NULL argument to dsps_sfh_table");
+  return launch_sfh_table(t_table, n_t, sfh_params, n_gal, sfr, stream);
+}
+
+int dsps_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float *scale,
+                       hipStream_t stream) {
+  DSPS_CHECK(rows >= 0 && cols >= 0, DSPS_ERR_SHAPE, "negative sizes");
+  if (rows == 0 || cols == 0) return DSPS_OK;
+  DSPS_CHECK(x && q && scale, DSPS_ERR_ARG, "NULL argument to dsps_quantize_bf16");
+  return launch_quantize_bf16(x, rows, cols, q, scale, stream);
+}
+
+int dsps_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, float *w,
+                 double *mstar, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  DSPS_CHECK(ssp, DSPS_ERR_ARG, "ssp is NULL");
+  DSPS_TRY(check_cosmo(cosmo));
+  DSPS_TRY(check_pop(pop, false));
+  if (pop->n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(w, DSPS_ERR_ARG, "w is NULL");
+  DSPS_TRY(check_device(ssp->device));
+  (void)workspace; (void)workspace_bytes;
+  WeightsLaunch a = base_weights(ssp, cosmo, pop);
+  a.perm = nullptr;
+  a.s_begin = 0;
+  a.s_count = pop->n_gal;
+  a.w_user = w;
+  a.mstar = mstar;
+  return launch_weights(a, stream);
+}
+
+int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, int apply_dust,
+             int precision, float *sed, void *workspace, size_t workspace_bytes,
+             hipStream_t stream) {
+  DSPS_CHECK(ssp, DSPS_ERR_ARG, "ssp is NULL");
+  DSPS_TRY(check_cosmo(cosmo));
+  DSPS_TRY(check_pop(pop, apply_dust != 0));
+  DSPS_CHECK(apply_dust == 0 || apply_dust == 1, DSPS_ERR_ARG, "apply_dust must be 0 or 1");
+  DSPS_TRY(check_precision(ssp, precision));
+  if (pop->n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(sed, DSPS_ERR_ARG, "sed is NULL");
+  DSPS_TRY(check_device(ssp->device));
+  const Layout L = make_layout(DSPS_OP_SED, ssp->v, 0, pop->n_gal, precision);
+  DSPS_TRY(check_workspace(workspace, workspace_bytes, L.total));
+  char *ws = (char *)workspace;
+  GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
+  for (int g0 = 0; g0 < pop->n_gal; g0 += L.batch) {
+    const int cnt = std::min(L.batch, pop->n_gal - g0);
+    WeightsLaunch a = base_weights(ssp, cosmo, pop);
+    a.perm = nullptr;
+    a.s_begin = g0;
+    a.s_count = cnt;
+    a.w_pad = ws + L.w;
+    a.w_pad_bf16 = precision == DSPS_BF16;
+    a.meta = apply_dust ? meta : nullptr;
+    DSPS_TRY(launch_weights(a, stream));
+    SedLaunch s{};
+    s.ssp = ssp->v;
+    s.precision = precision;
+    s.apply_dust = apply_dust;
+    s.g_begin = g0;
+    s.g_count = cnt;
+    s.w_pad = ws + L.w;
+    s.meta = meta;
+    s.sed = sed;
+    DSPS_TRY(launch_sed_gemm(s, stream));
+  }
+  return DSPS_OK;
+}
+
+int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
+              const dsps_pop *pop, int precision, float *mags, float *bands, void *workspace,
+              size_t workspace_bytes, hipStream_t stream) {
+  DSPS_CHECK(ssp && filters, DSPS_ERR_ARG, "ssp or filters is NULL");
+  DSPS_TRY(check_cosmo(cosmo));
+  DSPS_TRY(check_pop(pop, true));
+  DSPS_TRY(check_precision(ssp, precision));
+  if (pop->n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(mags, DSPS_ERR_ARG, "mags is NULL");
+  DSPS_TRY(check_device(ssp->device));
+  DSPS_CHECK(filters->device == ssp->device, DSPS_ERR_ARG, "ssp and filters on different devices");
+  const int n_band = filters->v.n_band;
+  const Layout L = make_layout(DSPS_OP_MAGS, ssp->v, n_band, pop->n_gal, precision);
+  DSPS_TRY(check_workspace(workspace, workspace_bytes, L.total));
+  char *ws = (char *)workspace;
+  int *perm = (int *)(ws + L.perm);
+  GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
+  GalaxyRange *range = (GalaxyRange *)(ws + L.range);
+  double *offset = (double *)(ws + L.offset);
+  float *partial = (float *)(ws + L.partial);
+  DSPS_TRY(launch_zsort(pop->z, pop->n_gal, (int *)(ws + L.hist), perm, stream));
+  for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
+    const int cnt = std::min(L.batch, pop->n_gal - s0);
+    WeightsLaunch a = base_weights(ssp, cosmo, pop);
+    a.perm = perm;
+    a.s_begin = s0;
+    a.s_count = cnt;
+    a.w_pad = ws + L.w;
+    a.w_pad_bf16 = precision == DSPS_BF16;
+    a.meta = meta;
+    a.range = range;
+    a.mag_offset = offset;
+    a.obs_lo = filters->obs_lo;
+    a.obs_hi = filters->obs_hi;
+    DSPS_TRY(launch_weights(a, stream));
+    MagsLaunch m{};
+    m.ssp = ssp->v;
+    m.flt = filters->v;
+    m.precision = precision;
+    m.s_begin = s0;
+    m.s_count = cnt;
+    m.w_pad = ws + L.w;
+    m.meta = meta;
+    m.range = range;
+    m.n_groups = L.n_groups;
+    m.partial = partial;
+    DSPS_TRY(launch_mags_gemm(m, stream));
+    FinalizeLaunch f{};
+    f.n_band = n_band;
+    f.n_groups = L.n_groups;
+    f.s_begin = s0;
+    f.s_count = cnt;
+    f.partial = partial;
+    f.mag_offset = offset;
+    f.perm = perm;
+    f.mags = mags;
+    f.bands = bands;
+    DSPS_TRY(launch_mags_finalize(f, stream));
+  }
+  return DSPS_OK;
+}
+
+int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
+                  const dsps_pop *pop, int precision, const float *mags_bar, const float *bands,
+                  double *sfr_bar, double *sfh_params_bar, float *lgmet_bar, float *sigma_bar,
+                  float *av_bar, float *delta_bar, float *bump_bar, void *workspace,
+                  size_t workspace_bytes, hipStream_t stream) {
+  (void)ssp; (void)filters; (void)cosmo; (void)pop; (void)precision; (void)mags_bar; (void)bands;
+  (void)sfr_bar; (void)sfh_params_bar; (void)lgmet_bar; (void)sigma_bar; (void)av_bar;
+  (void)delta_bar; (void)bump_bar; (void)workspace; (void)workspace_bytes; (void)stream;
+  set_error("dsps_mags_vjp is not available in this build");
+  return DSPS_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+// Internal definitions shared by the libdsps translation units.
+//
+// Layout decisions for gfx950 (see the design notes in the repository):
+//  * The SSP block is stored wavelength-major, ST[l][k] with k = met * 96 + age
+//    (ages zero-padded to 96 so that every 16- or 64-wide K block stays inside
+//    one metallicity row).  Both GEMM operands are then K-contiguous rows, which
+//    load as 16-byte vectors and feed MFMA fragments straight from LDS.
+//  * Galaxies are processed in redshift order so that a 128-galaxy tile shares
+//    one rest-frame wavelength window; per-galaxy scalars live in SoA arrays
+//    indexed by sorted position.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/dsps.h"
+
+namespace dsps {
+
+// ----------------------------------------------------------------- limits
+constexpr int AGE_PAD = 96;        // ages per metallicity row in the padded K axis
+constexpr int TILE_G = 128;        // galaxies per GEMM tile (N of the MFMA tile)
+constexpr int TILE_L = 128;        // wavelengths per chunk (M of the MFMA tile)
+constexpr int CHUNKS_PER_GROUP = 4;  // wavelength chunks one workgroup walks
+constexpr int ZBINS = 2048;        // redshift buckets of the ordering sort
+constexpr int GEMM_THREADS = 256;  // 4 wave64s in a 2 x 2 arrangement
+constexpr int WEIGHT_WAVES = 4;    // galaxies per weights workgroup (one per wave)
+
+// ------------------------------------------------------------- constants
+// AB zero point of a source at 10 pc, L_sun/Hz (Section 2.2.1).
+constexpr double AB_ZERO_POINT = 1.13492e-13;
+// Attenuation: A_lambda = A_V / 4.05 * k_lambda, k0 normalised at 5500 A;
+// Drude bump centre 2175 A and width 350 A (Section 3.4).
+constexpr double DUST_RV = 4.05;
+constexpr double DUST_LAMBDA_V = 5500.0;
+constexpr double DUST_SWITCH_ANGSTROM = 1500.0;
+constexpr double BUMP_CENTRE = 2175.0;
+constexpr double BUMP_WIDTH = 350.0;
+// Mpc / (km/s) expressed in Gyr, and c in km/s.
+constexpr double GYR_PER_MPC_S_KM = 977.7922216807891;
+constexpr double LIGHT_KM_S = 299792.458;
+constexpr double YEARS_PER_GYR = 1.0e9;
+constexpr double QUENCH_WIDTH = 0.5;   // Gyr, parametric SFH transition width
+
+// ------------------------------------------------------------- handles
+// Device-side view of the resident SSP block, passed to kernels by value.
+struct SspView {
+  int n_met, n_age, n_wave;
+  int n_wave_pad;                  // multiple of TILE_L
+  int k_pad;                       // n_met * AGE_PAD
+  const double *wave;              // [n_wave] rest Angstrom (float64)
+  const double *age_edges;         // [n_age + 1] Gyr: 0, midpoints, +inf
+  const double *met_edges;         // [n_met + 1] log10 Z: -inf, midpoints, +inf
+  const double *lg_age;            // [n_age]
+  const float *st32;               // [n_wave_pad][k_pad] or null
+  const uint16_t *st16;            // [n_wave_pad][k_pad] bf16 of lum / scale, or null
+  const float *kscale;             // [k_pad] power-of-two row scales (1 on padding)
+  const float4 *lconst;            // [n_wave_pad] (lambda, log2(lambda/5500), k0, drude shape)
+  const float *qweight;            // [n_wave_pad] trapezoid weight in dlambda/lambda
+};
+
+struct SspHandle {
+  int device = -1;
+  int precisions = 0;
+  int k0_reading = 0;
+  SspView v{};
+  void *alloc = nullptr;           // single device allocation backing every array
+};
+
+struct FilterView {
+  int n_band, n_pts;
+  const float *trans;              // [n_band][n_pts]
+  const float2 *grid;              // [n_band] (first wavelength, 1 / spacing)
+};
+
+struct FiltersHandle {
+  int device = -1;
+  FilterView v{};
+  double obs_lo = 0, obs_hi = 0;   // union of the filter supports
+  void *alloc = nullptr;
+};
+
+// Per-galaxy scalars written by the weights kernel, indexed by sorted position.
+struct GalaxyMeta {
+  float zp1;       // 1 + z
+  float dust_a;    // -0.4 log2(10) A_V / 4.05: F = exp2(dust_a * k_lambda)
+  float delta;
+  float bump;
+};
+struct GalaxyRange {
+  int win_lo, win_hi;  // rest-wavelength index window [lo, hi) that any filter sees
+  int met_lo_hi;       // lowest | highest metallicity row with a non-zero weight << 16
+  int age_hi;          // one past the oldest age with a non-zero weight
+};
+
+// ------------------------------------------------------------- device math
+__device__ __forceinline__ double triweight_cdf(double z) {
+  // Integral of 35/96 (1 - z^2/9)^3 from -3: 0 below -3, 1 above +3.
+  if (z <= -3.0) return 0.0;
+  if (z >= 3.0) return 1.0;
+  const double z2 = z * z;
+  double p = -5.0 / 69984.0;
+  p = p * z2 + 7.0 / 2592.0;
+  p = p * z2 - 35.0 / 864.0;
+  p = p * z2 + 35.0 / 96.0;
+  return 0.5 + z * p;
+}
+
+__device__ __forceinline__ double triweight_pdf(double z) {
+  if (z <= -3.0 || z >= 3.0) return 0.0;
+  const double u = 1.0 - z * z * (1.0 / 9.0);
+  return (35.0 / 96.0) * u * u * u;
+}
+
+// Round-to-nearest-even float32 -> bfloat16 bits (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  uint32_t b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return static_cast<uint16_t>(b >> 16);
+}
+
+// Smallest power of two >= m (m > 0 finite), 1 for m == 0.
+__device__ __forceinline__ float pow2_ceil(float m) {
+  if (!(m > 0.0f)) return 1.0f;
+  int e;
+  float mant = frexpf(m, &e);  // m = mant * 2^e, mant in [0.5, 1)
+  if (mant == 0.5f) e -= 1;
+  return ldexpf(1.0f, e);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// ------------------------------------------------------------- host helpers
+void set_error(const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
+// Cosmology parameters passed by value to kernels.
+struct CosmoArgs {
+  double om0, ol, w0, hubble_time_gyr, hubble_dist_mpc;
+  int lcdm;
+};
+CosmoArgs make_cosmo(const dsps_cosmo &c);
+
+// Gauss-Legendre nodes on [-1, 1], 16 points, filled once on the host.
+constexpr int GL_N = 16;
+struct GaussLegendre {
+  double x[GL_N];
+  double w[GL_N];
+};
+const GaussLegendre &gauss_legendre16();
+
+// ------------------------------------------------------------- launchers
+// Defined in k_weights.hip.
+struct WeightsLaunch {
+  // inputs
+  const double *t_table;
+  const double *sfr;         // [n_gal][n_t] or null
+  const double *sfh_params;  // [5][n_gal] or null
+  const float *z, *lgmet, *sigma_z, *av, *delta, *bump;
+  int n_gal, n_t;
+  double slope, pivot;
+  CosmoArgs cosmo;
+  GaussLegendre gl;
+  SspView ssp;
+  // ordering: sorted position s -> galaxy perm[s]; null means identity
+  const int *perm;
+  int s_begin, s_count;      // sorted range processed by this launch
+  // outputs (any may be null)
+  float *w_user;             // [n_gal][n_met][n_age] natural order (by galaxy index)
+  double *mstar;             // [n_gal]
+  void *w_pad;               // [s_count][k_pad] float32 or bf16 (by sorted position - s_begin)
+  int w_pad_bf16;
+  GalaxyMeta *meta;          // [n_gal] by sorted position
+  GalaxyRange *range;        // [n_gal] by sorted position
+  double *mag_offset;        // [n_gal] D_mod(z) - 2.5 log10(1+z), by sorted position
+  double obs_lo, obs_hi;     // filter support union for the window
+};
+int launch_weights(const WeightsLaunch &a, hipStream_t stream);
+
+int launch_sfh_table(const double *t_table, int n_t, const double *params, int n_gal,
+                     double *sfr, hipStream_t stream);
+int launch_zsort(const float *z, int n_gal, int *hist, int *perm, hipStream_t stream);
+int launch_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float *scale,
+                         hipStream_t stream);
+int launch_pack_table(const float *lum_rows, const uint16_t *q_rows, int n_met, int n_age,
+                      int n_wave, int n_wave_pad, int k_pad, float *st32, uint16_t *st16,
+                      hipStream_t stream);
+
+// Defined in k_mags.hip.
+struct MagsLaunch {
+  SspView ssp;
+  FilterView flt;
+  int precision;
+  int s_begin, s_count;          // sorted range of this batch
+  const void *w_pad;             // [s_count][k_pad]
+  const GalaxyMeta *meta;        // full arrays, by sorted position
+  const GalaxyRange *range;
+  int n_groups;                  // wavelength groups covering n_wave_pad
+  float *partial;                // [s_count][n_groups][2 * n_band]
+};
+int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream);
+
+struct FinalizeLaunch {
+  int n_band, n_groups;
+  int s_begin, s_count;
+  const float *partial;
+  const double *mag_offset;
+  const int *perm;
+  float *mags;    // [n_gal][n_band] by galaxy index
+  float *bands;   // [n_gal][2][n_band] or null
+};
+int launch_mags_finalize(const FinalizeLaunch &a, hipStream_t stream);
+
+// Defined in k_sed.hip.
+struct SedLaunch {
+  SspView ssp;
+  int precision, apply_dust;
+  int g_begin, g_count;
+  const void *w_pad;            // [g_count][k_pad]
+  const GalaxyMeta *meta;       // by galaxy index (identity order)
+  float *sed;                   // [n_gal][n_wave]
+};
+int launch_sed_gemm(const SedLaunch &a, hipStream_t stream);
+
+}  // namespace dsps

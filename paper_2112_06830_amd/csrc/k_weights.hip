@@ -1,0 +1,370 @@
+// SSP weights: parametric SFH table, cumulative mass formed, age-bin masses,
+// age-dependent metallicity weights, plus the redshift ordering sort and the
+// preparation kernels of the resident SSP block.
+//
+// One wave64 owns one galaxy in the weights kernel: the SFR row is staged in
+// LDS with coalesced loads, the float64 cumulative trapezoid is a blocked wave
+// scan, lanes then split the age-bin edges and finally the (metallicity, age)
+// weights, which leave as coalesced rows in the GEMM's padded K layout.
+#include "dsps_internal.hpp"
+
+#include <cmath>
+
+namespace dsps {
+
+// SFR(t) = A (t/tau)^alpha exp(-t/tau) (1 - q Phi((t - t_q)/0.5 Gyr)), the
+// parametric stand-in for the Diffstar history (Section 3.1, Eq. diffstar).
+__device__ __forceinline__ double sfr_param(double t, double a, double tau, double alpha,
+                                            double q, double tq) {
+  const double x = t / tau;
+  const double base = a * exp(alpha * log(x) - x);
+  const double v = (t - tq) * (1.0 / QUENCH_WIDTH);
+  const double phi = 0.5 * erfc(-v * 0.70710678118654752440);
+  return base * (1.0 - q * phi);
+}
+
+__global__ void k_sfh_table(const double *__restrict__ t_table, int n_t,
+                            const double *__restrict__ params, int n_gal,
+                            double *__restrict__ sfr) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)n_gal * n_t;
+  if (idx >= total) return;
+  const int g = (int)(idx / n_t);
+  const int n = (int)(idx - (long long)g * n_t);
+  sfr[idx] = sfr_param(t_table[n], params[g], params[n_gal + g], params[2 * n_gal + g],
+                       params[3 * n_gal + g], params[4 * n_gal + g]);
+}
+
+int launch_sfh_table(const double *t_table, int n_t, const double *params, int n_gal,
+                     double *sfr, hipStream_t stream) {
+  const long long total = (long long)n_gal * n_t;
+  if (total == 0) return DSPS_OK;
+  const int threads = 256;
+  const long long blocks = (total + threads - 1) / threads;
+  hipLaunchKernelGGL(k_sfh_table, dim3((unsigned)blocks), dim3(threads), 0, stream, t_table,
+                     n_t, params, n_gal, sfr);
+  return hip_fail(hipGetLastError(), "k_sfh_table launch");
+}
+
+// Cosmic time t(z) in Gyr: closed form for LCDM, else Gauss-Legendre in
+// s = sqrt(a), where t = t_H int_0^{a_z} da / (a E(a)) becomes
+// t_H int_0^{sqrt(a_z)} 2 s^2 / sqrt(Om + OL s^(-6 w)) ds.  Wave-cooperative.
+__device__ double wave_age_at_z(double z, const CosmoArgs &c, const GaussLegendre &gl,
+                                int lane) {
+  if (c.lcdm) {
+    if (c.ol <= 0.0) return (2.0 / 3.0) * c.hubble_time_gyr * pow(1.0 + z, -1.5) / sqrt(c.om0);
+    return (2.0 / (3.0 * sqrt(c.ol))) * c.hubble_time_gyr *
+           asinh(sqrt(c.ol / c.om0) * pow(1.0 + z, -1.5));
+  }
+  const double s_hi = sqrt(1.0 / (1.0 + z));
+  const int panel = lane / GL_N, node = lane % GL_N;  // 4 panels x 16 nodes
+  const double h = s_hi * 0.25;
+  const double s = h * (panel + 0.5) + 0.5 * h * gl.x[node];
+  const double f = 2.0 * s * s / sqrt(c.om0 + c.ol * pow(s, -6.0 * c.w0));
+  const double part = wave_sum(0.5 * h * gl.w[node] * f);
+  return c.hubble_time_gyr * part;
+}
+
+// Distance modulus 5 log10(d_L / 10 pc), d_L = (1+z) (c/H0) int_0^z dz'/E(z').
+__device__ double wave_distance_modulus(double z, const CosmoArgs &c, const GaussLegendre &gl,
+                                        int lane) {
+  const int panel = lane / GL_N, node = lane % GL_N;
+  const double h = z * 0.25;
+  const double x = h * (panel + 0.5) + 0.5 * h * gl.x[node];
+  const double zp1 = 1.0 + x;
+  const double e = sqrt(c.om0 * zp1 * zp1 * zp1 + c.ol * pow(zp1, 3.0 * (1.0 + c.w0)));
+  const double dc = c.hubble_dist_mpc * wave_sum(0.5 * h * gl.w[node] / e);
+  return 5.0 * log10((1.0 + z) * dc) + 25.0;
+}
+
+// Mass formed up to cosmic time t: 0 at or before t_table[0], linear
+// interpolation of the cumulative nodes inside, the last node after.
+__device__ __forceinline__ double mass_formed(double t, const double *tt, const double *mc,
+                                              int n_t) {
+  if (!(t > tt[0])) return 0.0;
+  if (t >= tt[n_t - 1]) return mc[n_t - 1];
+  int lo = 0, hi = n_t - 1;  // tt[lo] <= t < tt[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tt[mid] <= t) lo = mid; else hi = mid;
+  }
+  const double f = (t - tt[lo]) / (tt[hi] - tt[lo]);
+  return mc[lo] + f * (mc[hi] - mc[lo]);
+}
+
+// Orders LDS traffic between the lanes of one wave (no workgroup barrier:
+// waves of a block finish independently).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
+  extern __shared__ double lds[];
+  const int n_t = a.n_t;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  double *tt = lds;                                   // [n_t]
+  double *wbase = lds + n_t + wave * (2 * n_t + 2 * AGE_PAD + 2);
+  double *sfr_s = wbase;                              // [n_t]
+  double *mc = wbase + n_t;                           // [n_t]
+  double *em = wbase + 2 * n_t;                       // [n_age + 1]
+  double *mage = em + AGE_PAD + 1;                    // [n_age]
+
+  for (int n = threadIdx.x; n < n_t; n += blockDim.x) tt[n] = a.t_table[n];
+  __syncthreads();
+
+  const int local = blockIdx.x * WEIGHT_WAVES + wave;
+  if (local >= a.s_count) return;   // whole wave leaves; no block barrier follows
+  const int s = a.s_begin + local;
+  const int g = a.perm ? a.perm[s] : s;
+  const SspView &P = a.ssp;
+  const int n_age = P.n_age, n_met = P.n_met;
+
+  const double z = (double)a.z[g];
+  const double t_obs = wave_age_at_z(z, a.cosmo, a.gl, lane);
+
+  // ---- SFR row -> LDS (coalesced), then segments of the trapezoid.
+  if (a.sfr) {
+    const double *row = a.sfr + (size_t)g * n_t;
+    for (int n = lane; n < n_t; n += 64) sfr_s[n] = row[n];
+  } else {
+    const double pa = a.sfh_params[g], ptau = a.sfh_params[a.n_gal + g];
+    const double palpha = a.sfh_params[2 * a.n_gal + g], pq = a.sfh_params[3 * a.n_gal + g];
+    const double ptq = a.sfh_params[4 * a.n_gal + g];
+    for (int n = lane; n < n_t; n += 64) sfr_s[n] = sfr_param(tt[n], pa, ptau, palpha, pq, ptq);
+  }
+  wave_sync();
+  if (lane == 0) mc[0] = 0.0;
+  for (int m = lane; m < n_t - 1; m += 64)
+    mc[m + 1] = 0.5 * (sfr_s[m] + sfr_s[m + 1]) * (tt[m + 1] - tt[m]) * YEARS_PER_GYR;
+  wave_sync();
+
+  // ---- blocked inclusive scan of mc[1..n_t-1] (lane owns a contiguous block).
+  {
+    const int len = n_t - 1;
+    const int per = (len + 63) / 64;
+    const int b0 = 1 + lane * per;
+    const int b1 = min(1 + (lane + 1) * per, n_t);
+    double run = 0.0;
+    for (int n = b0; n < b1; ++n) run += mc[n];
+    // exclusive prefix of the lane totals
+    double incl = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double up = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += up;
+    }
+    double acc = incl - run;
+    for (int n = b0; n < b1; ++n) { acc += mc[n]; mc[n] = acc; }
+  }
+  wave_sync();
+
+  // ---- mass formed at the age-bin edges, bin masses (float64 differences).
+  for (int e = lane; e <= n_age; e += 64)
+    em[e] = mass_formed(t_obs - P.age_edges[e], tt, mc, n_t);
+  wave_sync();
+  for (int i = lane; i < n_age; i += 64) mage[i] = em[i] - em[i + 1];
+  wave_sync();
+
+  if (a.mstar && lane == 0) a.mstar[g] = em[0];
+
+  // ---- metallicity weights and W = m_age * P, lanes over ages.
+  const double lgmet = (double)a.lgmet[g];
+  const double inv_sig = 1.0 / (double)a.sigma_z[g];
+  int jlo = 1 << 20, jhi = -1, ihi = 0;
+  const int k_pad = P.k_pad;
+  float *wp32 = (a.w_pad && !a.w_pad_bf16) ? (float *)a.w_pad + (size_t)local * k_pad : nullptr;
+  uint16_t *wp16 = (a.w_pad && a.w_pad_bf16) ? (uint16_t *)a.w_pad + (size_t)local * k_pad : nullptr;
+  float *wu = a.w_user ? a.w_user + (size_t)g * n_met * n_age : nullptr;
+  for (int i = lane; i < AGE_PAD; i += 64) {
+    const bool real = i < n_age;
+    const double mu = real ? lgmet + a.slope * (P.lg_age[i] - a.pivot) : 0.0;
+    const double m_i = real ? mage[i] : 0.0;
+    double c_prev = 0.0;  // CDF at the lower edge of metallicity bin 0 (-inf)
+    for (int j = 0; j < n_met; ++j) {
+      double c_next;
+      if (j == n_met - 1) c_next = 1.0;  // upper edge of the last bin is +inf
+      else c_next = triweight_cdf((P.met_edges[j + 1] - mu) * inv_sig);
+      const double wv = real ? m_i * (c_next - c_prev) : 0.0;
+      c_prev = c_next;
+      bool nz;
+      if (wp16) {
+        const uint16_t q = f32_to_bf16_rne((float)(wv * (double)P.kscale[j * AGE_PAD + i]));
+        wp16[j * AGE_PAD + i] = q;
+        nz = (q & 0x7FFFu) != 0;
+      } else {
+        const float wf = (float)wv;
+        if (wp32) wp32[j * AGE_PAD + i] = wf;
+        nz = wf != 0.0f;
+      }
+      if (wu && real) wu[j * n_age + i] = (float)wv;
+      if (nz) { jlo = min(jlo, j); jhi = max(jhi, j); ihi = max(ihi, i + 1); }
+    }
+  }
+  jlo = wave_min(jlo);
+  jhi = wave_max(jhi);
+  ihi = wave_max(ihi);
+
+  const double dmod = a.mag_offset ? wave_distance_modulus(z, a.cosmo, a.gl, lane) : 0.0;
+  if (lane == 0) {
+    if (a.meta) {
+      GalaxyMeta m;
+      m.zp1 = (float)(1.0 + z);
+      // F = 10^(-0.4 A_V/4.05 k) = 2^(dust_a k)
+      m.dust_a = (float)(-0.4 * 3.32192809488736234787 * (double)a.av[g] / DUST_RV);
+      m.delta = a.delta[g];
+      m.bump = a.bump[g];
+      a.meta[s] = m;
+    }
+    if (a.mag_offset) a.mag_offset[s] = dmod - 2.5 * log10(1.0 + z);
+    if (a.range) {
+      // rest wavelengths whose redshifted value can meet a filter, padded by
+      // two grid points on each side (points outside contribute exact zeros)
+      const double lo_rest = a.obs_lo / (1.0 + z), hi_rest = a.obs_hi / (1.0 + z);
+      const double *wv = P.wave;
+      const int nw = P.n_wave;
+      int lo = 0, hi = nw;                       // first index with wave >= lo_rest
+      while (lo < hi) { const int mid = (lo + hi) >> 1; if (wv[mid] < lo_rest) lo = mid + 1; else hi = mid; }
+      int lo2 = lo, hi2 = nw;                    // first index with wave > hi_rest
+      while (lo2 < hi2) { const int mid = (lo2 + hi2) >> 1; if (wv[mid] <= hi_rest) lo2 = mid + 1; else hi2 = mid; }
+      GalaxyRange r;
+      r.win_lo = max(lo - 2, 0);
+      r.win_hi = min(lo2 + 2, nw);
+      if (jhi < 0) { r.met_lo_hi = 0; r.age_hi = 0; }
+      else { r.met_lo_hi = jlo | (jhi << 16); r.age_hi = ihi; }
+      a.range[s] = r;
+    }
+  }
+}
+
+int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
+  if (a.s_count <= 0) return DSPS_OK;
+  const int blocks = (a.s_count + WEIGHT_WAVES - 1) / WEIGHT_WAVES;
+  const size_t lds = sizeof(double) * (a.n_t + WEIGHT_WAVES * (2 * a.n_t + 2 * AGE_PAD + 2));
+  if (lds > 65536) {
+    const int rc = hip_fail(hipFuncSetAttribute((const void *)k_weights,
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                            "k_weights LDS attribute");
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_weights, dim3(blocks), dim3(64 * WEIGHT_WAVES), lds, stream, a);
+  return hip_fail(hipGetLastError(), "k_weights launch");
+}
+
+// ------------------------------------------------------------ redshift sort
+__device__ __forceinline__ int zbin(float z) {
+  if (!(z > 0.0f)) return 0;
+  const float v = log2f(1.0f + z) * 512.0f;
+  return v >= (float)(ZBINS - 1) ? ZBINS - 1 : (int)v;
+}
+
+__global__ void k_fill_int(int *p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_zhist(const float *__restrict__ z, int n, int *hist) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) atomicAdd(&hist[zbin(z[g])], 1);
+}
+
+// Exclusive scan of ZBINS counters by one 1024-thread block, in place.
+__global__ __launch_bounds__(1024) void k_zscan(int *hist) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int a0 = hist[2 * t], a1 = hist[2 * t + 1];
+  part[t] = a0 + a1;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  const int excl = part[t] - (a0 + a1);
+  hist[2 * t] = excl;
+  hist[2 * t + 1] = excl + a0;
+}
+
+__global__ void k_zscatter(const float *__restrict__ z, int n, int *cursor, int *perm) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) perm[atomicAdd(&cursor[zbin(z[g])], 1)] = g;
+}
+
+int launch_zsort(const float *z, int n_gal, int *hist, int *perm, hipStream_t stream) {
+  static_assert(ZBINS == 2048, "k_zscan assumes 2048 bins");
+  if (n_gal <= 0) return DSPS_OK;
+  hipLaunchKernelGGL(k_fill_int, dim3(ZBINS / 256), dim3(256), 0, stream, hist, ZBINS, 0);
+  const int blocks = (n_gal + 255) / 256;
+  hipLaunchKernelGGL(k_zhist, dim3(blocks), dim3(256), 0, stream, z, n_gal, hist);
+  hipLaunchKernelGGL(k_zscan, dim3(1), dim3(1024), 0, stream, hist);
+  hipLaunchKernelGGL(k_zscatter, dim3(blocks), dim3(256), 0, stream, z, n_gal, hist, perm);
+  return hip_fail(hipGetLastError(), "z sort launch");
+}
+
+// ------------------------------------------------------------ BF16 quantiser
+__global__ __launch_bounds__(256) void k_quantize_bf16(const float *__restrict__ x, int cols,
+                                                       uint16_t *__restrict__ q,
+                                                       float *__restrict__ scale) {
+  __shared__ float red[4];
+  const size_t row = blockIdx.x;
+  const float *xr = x + row * cols;
+  float m = 0.0f;
+  for (int c = threadIdx.x; c < cols; c += blockDim.x) m = fmaxf(m, xr[c]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  const float s = pow2_ceil(m);
+  if (threadIdx.x == 0) scale[row] = s;
+  uint16_t *qr = q + row * cols;
+  // x / s is exact for a power-of-two s except where it lands in the
+  // subnormal range, where the correctly rounded division decides.
+  for (int c = threadIdx.x; c < cols; c += blockDim.x) qr[c] = f32_to_bf16_rne(xr[c] / s);
+}
+
+int launch_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float *scale,
+                         hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return DSPS_OK;
+  hipLaunchKernelGGL(k_quantize_bf16, dim3(rows), dim3(256), 0, stream, x, cols, q, scale);
+  return hip_fail(hipGetLastError(), "k_quantize_bf16 launch");
+}
+
+// ------------------------------------------------------------ table packing
+// lum rows (met * n_age + age) x n_wave  ->  ST[l][met * 96 + age], zero padded.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_table(const T *__restrict__ src, int n_age,
+                                                    int n_wave, int n_wave_pad, int k_pad,
+                                                    T *__restrict__ dst) {
+  __shared__ T tile[32][33];
+  const int k0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int k = k0 + r, l = l0 + tx;
+    const int met = k / AGE_PAD, age = k - met * AGE_PAD;
+    T v = T(0);
+    if (age < n_age && l < n_wave) v = src[((size_t)met * n_age + age) * n_wave + l];
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int l = l0 + r, k = k0 + tx;
+    if (l < n_wave_pad && k < k_pad) dst[(size_t)l * k_pad + k] = tile[tx][r];
+  }
+}
+
+int launch_pack_table(const float *lum_rows, const uint16_t *q_rows, int n_met, int n_age,
+                      int n_wave, int n_wave_pad, int k_pad, float *st32, uint16_t *st16,
+                      hipStream_t stream) {
+  (void)n_met;
+  const dim3 grid(k_pad / 32, n_wave_pad / 32);
+  if (st32) hipLaunchKernelGGL(k_pack_table<float>, grid, dim3(256), 0, stream, lum_rows, n_age,
+                               n_wave, n_wave_pad, k_pad, st32);
+  if (st16) hipLaunchKernelGGL(k_pack_table<uint16_t>, grid, dim3(256), 0, stream, q_rows, n_age,
+                               n_wave, n_wave_pad, k_pad, st16);
+  return hip_fail(hipGetLastError(), "k_pack_table launch");
+}
+
+}  // namespace dsps

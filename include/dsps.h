@@ -200,9 +200,8 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
  *   mags   [n_gal*n_band] float32 apparent AB magnitudes
  *          m = -2.5 log10(num / (AB0 den)) + D_mod(z) - 2.5 log10(1+z)
  *   bands  [n_gal*2*n_band] float32 (num_b then den_b per galaxy): the two
- *          trapezoid sums of Eq. restmag over the redshifted grid with the
- *          common factor (1+z) removed, or NULL.  dsps_mags_vjp accepts them
- *          to skip the forward recomputation of the sums.
+ *          trapezoid sums of Eq. restmag over the redshifted grid, or NULL.
+ *          dsps_mags_vjp accepts them to skip the forward recomputation.
  * ------------------------------------------------------------------------ */
 int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
               const dsps_pop *pop, int precision, float *mags, float *bands,

@@ -100,10 +100,10 @@ def test_mags_fp32_small_workload(dev, small):
     ref, num, den = oracle.mags(inp, return_sums=True)
     assert max_abs(m.cpu().numpy(), ref) < FP32_TOL_MAG
     b = bands.cpu().numpy().astype(np.float64)
-    # the device sums drop the common factor (1+z) of the trapezoid in lambda_obs
-    zp1 = (1.0 + pop.z)[:, None]
-    np.testing.assert_allclose(b[:, 0, :] * zp1, num, rtol=2e-5)
-    np.testing.assert_allclose(b[:, 1, :] * zp1, den, rtol=2e-5)
+    # the trapezoid sums over lambda_obs themselves ((1+z) cancels between
+    # d lambda_obs and 1/lambda_obs)
+    np.testing.assert_allclose(b[:, 0, :], num, rtol=2e-5)
+    np.testing.assert_allclose(b[:, 1, :], den, rtol=2e-5)
 
 
 def test_mags_params_path_matches_table_path(dev, small):

@@ -1,0 +1,236 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the fused DSPS magnitude path on one MI355X.
+
+One step = one dsps_mags call over the whole population (redshift ordering,
+age-bin masses and MDF weights, the fused W.SSP contraction with attenuation
+and filter integrals, and the magnitude finalisation), inputs resident in HBM.
+Default workload: 1e5 galaxies, SSP 12 x 94 x 5994 (9e2-2.5e4 A) in float32,
+tabulated SFH on 100 times, z ~ U[0.1, 3], six Gaussian bands.
+
+Prints ONE JSON line.  `roofline` describes the dominant kernel
+(k_mags_gemm), timed with HIP events on its launch stream during the timed
+region.  `cpu_baseline` times the FP64 oracle on a bounded sample of the
+same workload on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "galaxies/sec 6-band mags, fwd & fwd+grad, plain FP32 vs BF16; p50/p99 latency"
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}     # MI355X dense MFMA
+HBM_PEAK_GBS = 8000.0
+GEMM_SOURCES = ("paper_2112_06830_amd/csrc/k_mags.hip", "paper_2112_06830_amd/csrc/gemm_core.hpp",
+                "paper_2112_06830_amd/csrc/dsps_internal.hpp")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gemm_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in GEMM_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(precision: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"k_mags_gemm_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.lstrip().startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != gemm_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def effective_wavelengths(wave, z, obs_lo, obs_hi):
+    """Rest-grid points whose redshifted wavelength lies inside the union of
+    the filter supports (the bands here overlap into one interval)."""
+    lo = np.searchsorted(wave, obs_lo / (1.0 + z), side="left")
+    hi = np.searchsorted(wave, obs_hi / (1.0 + z), side="right")
+    return np.maximum(hi - lo, 0)
+
+
+def algorithmic_flops(P, ssp_h, dpop, ssp, flt, z):
+    """2 * nnz(W_g) * n_lambda_eff(z_g) summed over galaxies: the multiply-adds
+    the contraction must do for the wavelengths any filter sees."""
+    import torch
+    nnz = torch.zeros(dpop.n_gal, dtype=torch.int64, device="cuda")
+    step = 16384
+    for s in range(0, dpop.n_gal, step):
+        e = min(s + step, dpop.n_gal)
+        sub = P.DevicePopulation(dpop.t_table, dpop.sfr[s:e] if dpop.sfr is not None else None,
+                                 dpop.sfh_params[:, s:e].contiguous() if dpop.sfh_params is not None else None,
+                                 dpop.z[s:e], dpop.lgmet[s:e], dpop.sigma_z[s:e], dpop.av[s:e],
+                                 dpop.delta[s:e], dpop.bump[s:e], dpop.lgmet_slope, dpop.lg_age_pivot)
+        w = P.weights(ssp_h, P.Cosmology(), sub)
+        nnz[s:e] = (w.view(e - s, -1) != 0).sum(dim=1)
+    nnz = nnz.cpu().numpy().astype(np.float64)
+    neff = effective_wavelengths(ssp.wave, z, flt.wave[:, 0].min(), flt.wave[:, -1].max())
+    return float(np.sum(2.0 * nnz * neff)), float(nnz.mean()), float(neff.mean())
+
+
+def cpu_baseline(ssp, flt, pop, sfr, min_seconds=10.0, block=512, max_gal=24576):
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    done = 0
+    t0 = time.perf_counter()
+    while done < min(max_gal, pop.n_gal):
+        idx = np.arange(done, min(done + block, pop.n_gal))
+        inp = oracle.prepare_inputs(ssp, flt, pop.subset(idx), sfr=sfr[idx])
+        oracle.mags(inp)
+        done += idx.size
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "galaxies/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {done} galaxies of the same population (FP64 numpy oracle, "
+                      f"{dt:.1f} s, BLAS threads={threads}, host cpus={os.cpu_count()})"}
+
+
+def run_workload(P, name, n_gal, n_t, precision, steps, warmup, seed, want_roofline=True):
+    import torch
+    import synth
+    ssp = synth.make_ssp(n_wave=5994, wave_lo=9.0e2, wave_hi=2.5e4)
+    flt = synth.make_filters()
+    pop = synth.make_population(n_gal, n_t=n_t, z_range=(0.1, 3.0), seed=seed)
+    log(f"{name}: uploading {n_gal} galaxies, n_t={n_t}, precision={precision}")
+    ssp_h = P.SspBlock.from_synth(ssp, precisions=(precision,))
+    flt_h = P.FilterBank.from_synth(flt)
+    dpar = P.DevicePopulation.from_synth(pop, use_params=True)
+    sfr = P.sfh_table(dpar.t_table, dpar.sfh_params)          # a0 on the GPU, untimed
+    dpop = dpar.with_sfr(sfr)
+    ws = P.Workspace(P.workspace_size(2, ssp_h, flt_h, n_gal, n_t, precision), dpop.device)
+    out = torch.empty((n_gal, 6), dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        P.mags(ssp_h, flt_h, P.Cosmology(), dpop, precision=precision, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    P.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.mags(ssp_h, flt_h, P.Cosmology(), dpop, precision=precision, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gemm_ms, gemm_n = P.profile_read("mags_gemm")
+    w_ms, w_n = P.profile_read("weights")
+    P.profile_enable(False)
+    ms_step = (t1 - t0) * 1e3 / steps
+    res = {"ms_per_step": ms_step, "galaxies_per_s": n_gal / (ms_step * 1e-3),
+           "gemm_ms_per_launch": gemm_ms / max(gemm_n, 1), "gemm_launches_per_step": gemm_n / steps,
+           "weights_ms_per_step": w_ms / steps, "gemm_ms_per_step": gemm_ms / steps,
+           "finite": bool(torch.isfinite(out).all().item())}
+    if want_roofline:
+        flops, nnz_mean, neff_mean = algorithmic_flops(P, ssp_h, dpop, ssp, flt, pop.z)
+        achieved = flops / (gemm_ms / steps * 1e-3) / 1e12
+        res.update(alg_flops_per_step=flops, nnz_mean=nnz_mean, n_lambda_eff_mean=neff_mean,
+                   achieved_tflops=achieved)
+    return res, (ssp, flt, pop, sfr)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the BF16 1e6 leg")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(galaxies shard with no exchange; see the design notes). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    import paper_2112_06830_amd as P
+
+    main_res, (ssp, flt, pop, sfr_dev) = run_workload(
+        P, "fwd_fp32_1e5", 100_000, 100, "fp32", args.steps, args.warmup, seed=3)
+    log(f"fp32 1e5: {main_res['ms_per_step']:.3f} ms/step, gemm {main_res['gemm_ms_per_step']:.3f} ms/step")
+
+    extra = {"fp32_fwd_1e5": {k: main_res[k] for k in ("ms_per_step", "galaxies_per_s",
+                                                         "gemm_ms_per_step", "weights_ms_per_step",
+                                                         "nnz_mean", "n_lambda_eff_mean")}}
+    if not args.no_extra:
+        bf, _ = run_workload(P, "fwd_bf16_1e6", 1_000_000, 1000, "bf16", max(3, args.steps // 4),
+                             1, seed=4, want_roofline=True)
+        extra["bf16_fwd_1e6"] = {
+            "ms_per_step": bf["ms_per_step"], "galaxies_per_s": bf["galaxies_per_s"],
+            "gemm_ms_per_step": bf["gemm_ms_per_step"], "weights_ms_per_step": bf["weights_ms_per_step"],
+            "mfma_frac_bf16": bf["achieved_tflops"] / PEAK_TFLOPS["bf16"],
+            "sfh_read_hbm_frac": (1_000_000 * 1000 * 8 / (bf["weights_ms_per_step"] * 1e-3)) / 1e9 / HBM_PEAK_GBS}
+        log(f"bf16 1e6: {bf['ms_per_step']:.3f} ms/step")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: FP64 oracle on a bounded sample")
+        cpu = cpu_baseline(ssp, flt, pop, sfr_dev.cpu().numpy())
+
+    traffic = read_traffic("fp32", "fp32_1e5")
+    achieved = main_res["achieved_tflops"]
+    line = {
+        "metric": METRIC,
+        "value": main_res["galaxies_per_s"],
+        "unit": "galaxies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fwd_fp32_1e5: 1e5 galaxies, SSP 12x94x5994 float32 (9e2-2.5e4 A), "
+                               "tabulated SFH n_t=100, z~U[0.1,3], 6 Gaussian bands, forward magnitudes",
+                   "n_gal": 100_000, "n_t": 100, "n_wave": 5994, "n_met": 12, "n_age": 94,
+                   "n_band": 6, "precision": "fp32"},
+        "roofline": {"bound": "mfma", "kernel": "k_mags_gemm<fp32>", "achieved": achieved,
+                     "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS["fp32"],
+                     "traffic": traffic,
+                     "avg_launch_ms": main_res["gemm_ms_per_launch"],
+                     "launches_per_step": main_res["gemm_launches_per_step"],
+                     "alg_flops_per_step": main_res["alg_flops_per_step"]},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -237,6 +237,28 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
 int dsps_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float *scale,
                        hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Instrumentation.  While enabled, every kernel launch of the compute calls
+ * is bracketed by HIP events recorded on the caller's stream (process-wide,
+ * thread-safe).  dsps_profile_enable(1) clears earlier records;
+ * dsps_profile_read waits for the recorded events of one kernel and returns
+ * their summed duration in milliseconds and the number of launches.  Not
+ * usable under stream capture.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+  DSPS_KERNEL_WEIGHTS = 0,      /* age masses, MDF weights, W rows          */
+  DSPS_KERNEL_MAGS_GEMM = 1,    /* fused contraction + attenuation + filters */
+  DSPS_KERNEL_MAGS_FINALIZE = 2,
+  DSPS_KERNEL_ZSORT = 3,
+  DSPS_KERNEL_SED_GEMM = 4,
+  DSPS_KERNEL_VJP_GEMM = 5,     /* adjoint: recomputed SED tile + dust terms */
+  DSPS_KERNEL_VJP_WBAR = 6,     /* adjoint: transposed contraction          */
+  DSPS_KERNEL_VJP_WEIGHTS = 7,  /* adjoint: weights -> SFH, MDF parameters  */
+  DSPS_KERNEL_COUNT = 8
+} dsps_kernel_id;
+int dsps_profile_enable(int on);
+int dsps_profile_read(int kernel_id, double *total_ms, int *launches);
+
 /* Introspection. */
 int dsps_abi_version(void);
 const char *dsps_last_error(void);

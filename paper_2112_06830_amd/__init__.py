@@ -11,9 +11,11 @@ from ._native import DspsError, load as load_library
 load_library()
 
 from .api import (Cosmology, DevicePopulation, FilterBank, SspBlock, Workspace,  # noqa: E402
-                  mags, quantize_bf16, sed, sfh_table, weights, workspace_size)
+                  mags, profile_enable, profile_read, quantize_bf16, sed, sfh_table, weights,
+                  workspace_size)
 
 __all__ = [
     "Cosmology", "DevicePopulation", "FilterBank", "SspBlock", "Workspace", "DspsError",
     "mags", "quantize_bf16", "sed", "sfh_table", "weights", "workspace_size", "load_library",
+    "profile_enable", "profile_read",
 ]

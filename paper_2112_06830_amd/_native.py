@@ -23,8 +23,11 @@ EXPORTS = (
     "dsps_abi_version", "dsps_last_error", "dsps_ssp_create", "dsps_ssp_destroy",
     "dsps_ssp_info", "dsps_filters_create", "dsps_filters_destroy", "dsps_filters_info",
     "dsps_workspace_size", "dsps_sfh_table", "dsps_weights", "dsps_sed", "dsps_mags",
-    "dsps_mags_vjp", "dsps_quantize_bf16",
+    "dsps_mags_vjp", "dsps_quantize_bf16", "dsps_profile_enable", "dsps_profile_read",
 )
+
+KERNEL_IDS = {"weights": 0, "mags_gemm": 1, "mags_finalize": 2, "zsort": 3, "sed_gemm": 4,
+              "vjp_gemm": 5, "vjp_wbar": 6, "vjp_weights": 7}
 
 
 class DspsError(RuntimeError):
@@ -71,6 +74,8 @@ def _declare(lib):
         "dsps_mags_vjp": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P,
                               P, P, P, P, P, P, P, P, S, P]),
         "dsps_quantize_bf16": (I, [P, I, I, P, P, P]),
+        "dsps_profile_enable": (I, [I]),
+        "dsps_profile_read": (I, [I, ctypes.POINTER(ctypes.c_double), IP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -272,3 +272,17 @@ def quantize_bf16(x: torch.Tensor, stream=None):
     rc = _lib().dsps_quantize_bf16(_ptr(x), rows, cols, _ptr(q), _ptr(s), _stream(stream))
     N.check(rc, "dsps_quantize_bf16")
     return q, s
+
+
+def profile_enable(on: bool = True):
+    """Start (clearing earlier records) or stop kernel-level event timing."""
+    N.check(_lib().dsps_profile_enable(int(bool(on))), "dsps_profile_enable")
+
+
+def profile_read(kernel: str):
+    """(total milliseconds, launches) recorded for one kernel since enabling."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int()
+    N.check(_lib().dsps_profile_read(N.KERNEL_IDS[kernel], ctypes.byref(ms), ctypes.byref(n)),
+            "dsps_profile_read")
+    return float(ms.value), int(n.value)

@@ -153,6 +153,21 @@ __device__ __forceinline__ T wave_max(T v) {
 void set_error(const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 
+// Brackets one kernel launch with HIP events on `stream` while
+// instrumentation is enabled (dsps_profile_enable); a no-op otherwise.
+class ProfScope {
+ public:
+  ProfScope(int kernel_id, hipStream_t stream);
+  ~ProfScope();
+  ProfScope(const ProfScope &) = delete;
+  ProfScope &operator=(const ProfScope &) = delete;
+
+ private:
+  int kid_;
+  hipStream_t stream_;
+  hipEvent_t start_ = nullptr, stop_ = nullptr;
+};
+
 // Cosmology parameters passed by value to kernels.
 struct CosmoArgs {
   double om0, ol, w0, hubble_time_gyr, hubble_dist_mpc;

@@ -210,6 +210,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
 int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
   const dim3 grid(a.n_groups, (a.s_count + TILE_G - 1) / TILE_G);
+  ProfScope prof(DSPS_KERNEL_MAGS_GEMM, stream);
   if (a.precision == DSPS_BF16)
     hipLaunchKernelGGL(k_mags_gemm<DSPS_BF16>, grid, dim3(GEMM_THREADS), 0, stream, a);
   else
@@ -246,6 +247,7 @@ __global__ void k_mags_finalize(FinalizeLaunch a) {
 
 int launch_mags_finalize(const FinalizeLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
+  ProfScope prof(DSPS_KERNEL_MAGS_FINALIZE, stream);
   hipLaunchKernelGGL(k_mags_finalize, dim3((a.s_count + 255) / 256), dim3(256), 0, stream, a);
   return hip_fail(hipGetLastError(), "k_mags_finalize launch");
 }

@@ -69,6 +69,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
 int launch_sed_gemm(const SedLaunch &a, hipStream_t stream) {
   if (a.g_count <= 0) return DSPS_OK;
   const dim3 grid(a.ssp.n_wave_pad / TILE_L, (a.g_count + TILE_G - 1) / TILE_G);
+  ProfScope prof(DSPS_KERNEL_SED_GEMM, stream);
   if (a.precision == DSPS_BF16)
     hipLaunchKernelGGL(k_sed_gemm<DSPS_BF16>, grid, dim3(GEMM_THREADS), 0, stream, a);
   else

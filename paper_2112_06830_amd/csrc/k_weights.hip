@@ -249,6 +249,7 @@ int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
                             "k_weights LDS attribute");
     if (rc) return rc;
   }
+  ProfScope prof(DSPS_KERNEL_WEIGHTS, stream);
   hipLaunchKernelGGL(k_weights, dim3(blocks), dim3(64 * WEIGHT_WAVES), lds, stream, a);
   return hip_fail(hipGetLastError(), "k_weights launch");
 }
@@ -296,6 +297,7 @@ __global__ void k_zscatter(const float *__restrict__ z, int n, int *cursor, int 
 int launch_zsort(const float *z, int n_gal, int *hist, int *perm, hipStream_t stream) {
   static_assert(ZBINS == 2048, "k_zscan assumes 2048 bins");
   if (n_gal <= 0) return DSPS_OK;
+  ProfScope prof(DSPS_KERNEL_ZSORT, stream);
   hipLaunchKernelGGL(k_fill_int, dim3(ZBINS / 256), dim3(256), 0, stream, hist, ZBINS, 0);
   const int blocks = (n_gal + 255) / 256;
   hipLaunchKernelGGL(k_zhist, dim3(blocks), dim3(256), 0, stream, z, n_gal, hist);

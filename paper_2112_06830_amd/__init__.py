@@ -11,11 +11,12 @@ from ._native import DspsError, load as load_library
 load_library()
 
 from .api import (Cosmology, DevicePopulation, FilterBank, SspBlock, Workspace,  # noqa: E402
-                  mags, profile_enable, profile_read, quantize_bf16, sed, sfh_table, weights,
-                  workspace_size)
+                  mags, mags_vjp, profile_enable, profile_read, quantize_bf16, sed, sfh_table,
+                  weights, workspace_size)
+from .autograd import DspsMags, dsps_mags  # noqa: E402
 
 __all__ = [
     "Cosmology", "DevicePopulation", "FilterBank", "SspBlock", "Workspace", "DspsError",
     "mags", "quantize_bf16", "sed", "sfh_table", "weights", "workspace_size", "load_library",
-    "profile_enable", "profile_read",
+    "profile_enable", "profile_read", "mags_vjp", "DspsMags", "dsps_mags",
 ]

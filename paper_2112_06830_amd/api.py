@@ -286,3 +286,33 @@ def profile_read(kernel: str):
     N.check(_lib().dsps_profile_read(N.KERNEL_IDS[kernel], ctypes.byref(ms), ctypes.byref(n)),
             "dsps_profile_read")
     return float(ms.value), int(n.value)
+
+
+def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopulation,
+             mags_bar: torch.Tensor, bands: torch.Tensor | None = None,
+             want=("sfr", "sfh_params", "lgmet", "sigma_z", "av", "delta", "bump"),
+             workspace: Workspace | None = None, stream=None) -> dict:
+    """dsps_mags_vjp: cotangents of the population inputs for a magnitude
+    cotangent mags_bar [n_gal, n_band] (float32 path)."""
+    n, d = pop.n_gal, pop.device
+    mags_bar = mags_bar.to(device=d, dtype=torch.float32).contiguous()
+    if bands is not None:
+        bands = bands.to(device=d, dtype=torch.float32).contiguous()
+    out = {}
+    if "sfr" in want:
+        out["sfr"] = torch.empty((n, pop.n_t), dtype=torch.float64, device=d)
+    if "sfh_params" in want and pop.sfh_params is not None:
+        out["sfh_params"] = torch.empty((5, n), dtype=torch.float64, device=d)
+    for k in ("lgmet", "sigma_z", "av", "delta", "bump"):
+        if k in want:
+            out[k] = torch.empty(n, dtype=torch.float32, device=d)
+    if workspace is None:
+        workspace = Workspace(workspace_size(N.OP_MAGS_VJP, ssp, filters, n, pop.n_t, "fp32"), d)
+    c, p = cosmo.c(), pop.c()
+    rc = _lib().dsps_mags_vjp(ssp.handle, filters.handle, ctypes.byref(c), ctypes.byref(p), N.FP32,
+                              _ptr(mags_bar), _ptr(bands), _ptr(out.get("sfr")),
+                              _ptr(out.get("sfh_params")), _ptr(out.get("lgmet")),
+                              _ptr(out.get("sigma_z")), _ptr(out.get("av")), _ptr(out.get("delta")),
+                              _ptr(out.get("bump")), workspace.ptr(), workspace.nbytes, _stream(stream))
+    N.check(rc, "dsps_mags_vjp")
+    return out

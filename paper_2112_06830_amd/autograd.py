@@ -1,0 +1,64 @@
+"""torch.autograd.Function over the fused magnitudes and their hand-written
+adjoint (dsps_mags / dsps_mags_vjp).  Forward keeps only the per-galaxy band
+sums (2 x n_band floats); backward recomputes the SED tile by tile."""
+
+from __future__ import annotations
+
+import torch
+
+from . import api
+
+
+class DspsMags(torch.autograd.Function):
+    """mags = DspsMags.apply(ssp, filters, cosmo, t_table, sfh_params, sfr, z,
+    lgmet, sigma_z, av, delta, bump, slope, pivot)
+
+    Exactly one of sfh_params [5, n_gal] (float64) and sfr [n_gal, n_t]
+    (float64) is a tensor, the other None.  Gradients flow to sfh_params or
+    sfr, lgmet, sigma_z, av, delta and bump; z and t_table get none.
+    """
+
+    @staticmethod
+    def forward(ctx, ssp, filters, cosmo, t_table, sfh_params, sfr, z, lgmet, sigma_z, av, delta,
+                bump, slope=0.1, pivot=9.0):
+        pop = api.DevicePopulation(t_table.contiguous(),
+                                   None if sfr is None else sfr.detach().contiguous(),
+                                   None if sfh_params is None else sfh_params.detach().contiguous(),
+                                   z.detach().contiguous(), lgmet.detach().contiguous(),
+                                   sigma_z.detach().contiguous(), av.detach().contiguous(),
+                                   delta.detach().contiguous(), bump.detach().contiguous(),
+                                   float(slope), float(pivot))
+        mags, bands = api.mags(ssp, filters, cosmo, pop, precision="fp32", with_bands=True)
+        ctx.ssp, ctx.filters, ctx.cosmo, ctx.pop = ssp, filters, cosmo, pop
+        ctx.save_for_backward(bands)
+        return mags
+
+    @staticmethod
+    def backward(ctx, mags_bar):
+        (bands,) = ctx.saved_tensors
+        pop = ctx.pop
+        want = []
+        if pop.sfh_params is not None and ctx.needs_input_grad[4]:
+            want.append("sfh_params")
+        if pop.sfr is not None and ctx.needs_input_grad[5]:
+            want.append("sfr")
+        names = ["lgmet", "sigma_z", "av", "delta", "bump"]
+        for i, k in enumerate(names):
+            if ctx.needs_input_grad[7 + i]:
+                want.append(k)
+        g = api.mags_vjp(ctx.ssp, ctx.filters, ctx.cosmo, pop, mags_bar, bands=bands, want=tuple(want))
+        return (None, None, None, None, g.get("sfh_params"), g.get("sfr"), None,
+                g.get("lgmet"), g.get("sigma_z"), g.get("av"), g.get("delta"), g.get("bump"),
+                None, None)
+
+
+def dsps_mags(ssp, filters, cosmo, pop: api.DevicePopulation, sfh_params=None, sfr=None,
+              lgmet=None, sigma_z=None, av=None, delta=None, bump=None):
+    """Differentiable magnitudes; tensors not given are taken from `pop`."""
+    return DspsMags.apply(ssp, filters, cosmo, pop.t_table,
+                          sfh_params if sfh_params is not None else pop.sfh_params,
+                          sfr if sfr is not None else pop.sfr, pop.z,
+                          lgmet if lgmet is not None else pop.lgmet,
+                          sigma_z if sigma_z is not None else pop.sigma_z,
+                          av if av is not None else pop.av, delta if delta is not None else pop.delta,
+                          bump if bump is not None else pop.bump, pop.lgmet_slope, pop.lg_age_pivot)

@@ -196,6 +196,8 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   const size_t o_lg = take(sizeof(double) * n_age);
   const size_t o_st32 = want32 ? take(sizeof(float) * (size_t)nwp * kp) : 0;
   const size_t o_st16 = want16 ? take(sizeof(uint16_t) * (size_t)nwp * kp) : 0;
+  const int sk_rows = (kp + TILE_L - 1) / TILE_L * TILE_L;
+  const size_t o_sk = want32 ? take(sizeof(float) * (size_t)sk_rows * nwp) : 0;
   const size_t o_ks = take(sizeof(float) * kp);
   const size_t o_lc = take(sizeof(float4) * nwp);
   const size_t o_q = take(sizeof(float) * nwp);
@@ -251,6 +253,9 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
                            want32 ? (float *)(b + o_st32) : nullptr,
                            want16 ? (uint16_t *)(b + o_st16) : nullptr, nullptr);
     if (rc) break;
+    if (want32) rc = launch_pack_table_kmajor(d_rows, n_age, n_wave, nwp, kp, sk_rows,
+                                              (float *)(b + o_sk), nullptr);
+    if (rc) break;
     rc = hip_fail(hipDeviceSynchronize(), "SSP block preparation");
   } while (false);
   cleanup();
@@ -267,6 +272,8 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   v.kscale = (const float *)(b + o_ks);
   v.lconst = (const float4 *)(b + o_lc);
   v.qweight = (const float *)(b + o_q);
+  v.sk32 = want32 ? (const float *)(b + o_sk) : nullptr;
+  v.sk_rows = sk_rows;
   dsps_ssp *h = new dsps_ssp();
   (void)hipGetDevice(&h->device);
   h->precisions = precisions;
@@ -364,6 +371,7 @@ constexpr int BATCH = 32768;   // galaxies per weights + GEMM round trip
 
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
+  size_t gamma = 0, vpartial = 0, lbar = 0, wbar = 0, fbands = 0;
   int batch = 0, n_groups = 0;
 };
 
@@ -388,6 +396,13 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   L.offset = take(sizeof(double) * (size_t)n_gal);
   L.w = take(elem * (size_t)L.batch * v.k_pad);
   L.partial = take(sizeof(float) * (size_t)L.batch * L.n_groups * 2 * n_band);
+  if (op == DSPS_OP_MAGS_VJP) {
+    L.gamma = take(sizeof(float) * (size_t)n_gal * n_band);
+    L.vpartial = take(sizeof(float) * (size_t)L.batch * L.n_groups * 3);
+    L.lbar = take(sizeof(float) * (size_t)L.batch * v.n_wave_pad);
+    L.wbar = take(sizeof(float) * (size_t)L.batch * v.k_pad);
+    L.fbands = take(sizeof(float) * (size_t)n_gal * 3 * n_band);   // bands + mags if recomputed
+  }
   L.total = off;
   return L;
 }
@@ -453,10 +468,6 @@ int dsps_workspace_size(int op, const dsps_ssp *ssp, const dsps_filters *filters
   if (op == DSPS_OP_MAGS || op == DSPS_OP_MAGS_VJP) {
     DSPS_CHECK(filters, DSPS_ERR_ARG, "filters required for this op");
     n_band = filters->v.n_band;
-  }
-  if (op == DSPS_OP_MAGS_VJP) {
-    set_error("dsps_mags_vjp is not available in this build");
-    return DSPS_ERR_UNSUPPORTED;
   }
   *bytes = make_layout(op, ssp->v, n_band, n_gal, precision).total;
   return DSPS_OK;
@@ -602,11 +613,108 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
                   double *sfr_bar, double *sfh_params_bar, float *lgmet_bar, float *sigma_bar,
                   float *av_bar, float *delta_bar, float *bump_bar, void *workspace,
                   size_t workspace_bytes, hipStream_t stream) {
-  (void)ssp; (void)filters; (void)cosmo; (void)pop; (void)precision; (void)mags_bar; (void)bands;
-  (void)sfr_bar; (void)sfh_params_bar; (void)lgmet_bar; (void)sigma_bar; (void)av_bar;
-  (void)delta_bar; (void)bump_bar; (void)workspace; (void)workspace_bytes; (void)stream;
-  set_error("dsps_mags_vjp is not available in this build");
-  return DSPS_ERR_UNSUPPORTED;
+  DSPS_CHECK(ssp && filters, DSPS_ERR_ARG, "ssp or filters is NULL");
+  DSPS_TRY(check_cosmo(cosmo));
+  DSPS_TRY(check_pop(pop, true));
+  DSPS_TRY(check_precision(ssp, precision));
+  DSPS_CHECK(precision == DSPS_FP32, DSPS_ERR_UNSUPPORTED, "the adjoint runs in float32 only");
+  if (pop->n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(mags_bar, DSPS_ERR_ARG, "mags_bar is NULL");
+  DSPS_CHECK(!sfh_params_bar || pop->sfh_params, DSPS_ERR_ARG,
+             "sfh_params_bar requires the population to carry sfh_params");
+  DSPS_TRY(check_device(ssp->device));
+  DSPS_CHECK(filters->device == ssp->device, DSPS_ERR_ARG, "ssp and filters on different devices");
+  const int n_band = filters->v.n_band;
+  const Layout L = make_layout(DSPS_OP_MAGS_VJP, ssp->v, n_band, pop->n_gal, precision);
+  DSPS_TRY(check_workspace(workspace, workspace_bytes, L.total));
+  char *ws = (char *)workspace;
+  int *perm = (int *)(ws + L.perm);
+  GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
+  GalaxyRange *range = (GalaxyRange *)(ws + L.range);
+  double *offset = (double *)(ws + L.offset);
+  float *fwd_bands = bands ? nullptr : (float *)(ws + L.fbands);
+  float *fwd_mags = (float *)(ws + L.fbands) + (size_t)pop->n_gal * 2 * n_band;
+  const float *use_bands = bands ? bands : fwd_bands;
+  DSPS_TRY(launch_zsort(pop->z, pop->n_gal, (int *)(ws + L.hist), perm, stream));
+  for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
+    const int cnt = std::min(L.batch, pop->n_gal - s0);
+    WeightsLaunch a = base_weights(ssp, cosmo, pop);
+    a.perm = perm;
+    a.s_begin = s0;
+    a.s_count = cnt;
+    a.w_pad = ws + L.w;
+    a.w_pad_bf16 = 0;
+    a.meta = meta;
+    a.range = range;
+    a.mag_offset = offset;
+    a.obs_lo = filters->obs_lo;
+    a.obs_hi = filters->obs_hi;
+    DSPS_TRY(launch_weights(a, stream));
+    if (!bands) {
+      MagsLaunch m{};
+      m.ssp = ssp->v;
+      m.flt = filters->v;
+      m.precision = DSPS_FP32;
+      m.s_begin = s0;
+      m.s_count = cnt;
+      m.w_pad = ws + L.w;
+      m.meta = meta;
+      m.range = range;
+      m.n_groups = L.n_groups;
+      m.partial = (float *)(ws + L.partial);
+      DSPS_TRY(launch_mags_gemm(m, stream));
+      FinalizeLaunch f{};
+      f.n_band = n_band;
+      f.n_groups = L.n_groups;
+      f.s_begin = s0;
+      f.s_count = cnt;
+      f.partial = (const float *)(ws + L.partial);
+      f.mag_offset = offset;
+      f.perm = perm;
+      f.mags = fwd_mags;
+      f.bands = fwd_bands;
+      DSPS_TRY(launch_mags_finalize(f, stream));
+    }
+    VjpLaunch v{};
+    v.ssp = ssp->v;
+    v.flt = filters->v;
+    v.n_band = n_band;
+    v.n_groups = L.n_groups;
+    v.s_begin = s0;
+    v.s_count = cnt;
+    v.perm = perm;
+    v.mags_bar = mags_bar;
+    v.bands = use_bands;
+    v.gamma = (float *)(ws + L.gamma);
+    v.meta = meta;
+    v.range = range;
+    v.w_pad = ws + L.w;
+    v.partial = (float *)(ws + L.vpartial);
+    v.lbar = (float *)(ws + L.lbar);
+    v.wbar = (float *)(ws + L.wbar);
+    v.t_table = pop->t_table;
+    v.sfr = pop->sfr;
+    v.sfh_params = pop->sfh_params;
+    v.z = pop->z;
+    v.lgmet = pop->lgmet;
+    v.sigma_z = pop->sigma_z;
+    v.av = pop->av;
+    v.n_gal = pop->n_gal;
+    v.n_t = pop->n_t;
+    v.slope = pop->lgmet_slope;
+    v.pivot = pop->lg_age_pivot;
+    v.cosmo = make_cosmo(*cosmo);
+    v.gl = gauss_legendre16();
+    v.sfr_bar = sfr_bar;
+    v.sfh_params_bar = sfh_params_bar;
+    v.lgmet_bar = lgmet_bar;
+    v.sigma_bar = sigma_bar;
+    v.av_bar = av_bar;
+    v.delta_bar = delta_bar;
+    v.bump_bar = bump_bar;
+    for (int stage = 0; stage < 4; ++stage) DSPS_TRY(launch_vjp(v, stage, stream));
+  }
+  return DSPS_OK;
 }
 
 }  // extern "C"

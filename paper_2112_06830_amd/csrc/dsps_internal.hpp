@@ -59,6 +59,8 @@ struct SspView {
   const float *kscale;             // [k_pad] power-of-two row scales (1 on padding)
   const float4 *lconst;            // [n_wave_pad] (lambda, log2(lambda/5500), k0, drude shape)
   const float *qweight;            // [n_wave_pad] trapezoid weight in dlambda/lambda
+  const float *sk32;               // [sk_rows][n_wave_pad] K-major float32 copy (adjoint), or null
+  int sk_rows;                     // k_pad rounded up to a multiple of TILE_L
 };
 
 struct SspHandle {
@@ -219,6 +221,8 @@ int launch_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float 
 int launch_pack_table(const float *lum_rows, const uint16_t *q_rows, int n_met, int n_age,
                       int n_wave, int n_wave_pad, int k_pad, float *st32, uint16_t *st16,
                       hipStream_t stream);
+int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n_wave_pad,
+                             int k_pad, int sk_rows, float *sk32, hipStream_t stream);
 
 // Defined in k_mags.hip.
 struct MagsLaunch {
@@ -255,5 +259,35 @@ struct SedLaunch {
   float *sed;                   // [n_gal][n_wave]
 };
 int launch_sed_gemm(const SedLaunch &a, hipStream_t stream);
+
+// Defined in k_vjp.hip.  Stages: 0 gamma, 1 recomputed forward tile with the
+// adjoint epilogue, 2 transposed contraction, 3 per-galaxy pull-back.
+struct VjpLaunch {
+  SspView ssp;
+  FilterView flt;
+  int n_band, n_groups;
+  int s_begin, s_count;
+  const int *perm;
+  const float *mags_bar;      // [n_gal][n_band] by galaxy index
+  const float *bands;         // [n_gal][2][n_band] by galaxy index
+  float *gamma;               // [n_gal][n_band] by sorted position
+  const GalaxyMeta *meta;
+  const GalaxyRange *range;
+  const void *w_pad;          // [s_count][k_pad] float32
+  float *partial;             // [s_count][n_groups][3]
+  float *lbar;                // [s_count][n_wave_pad]
+  float *wbar;                // [s_count][k_pad]
+  // population (for the per-galaxy pull-back)
+  const double *t_table, *sfr, *sfh_params;
+  const float *z, *lgmet, *sigma_z, *av;
+  int n_gal, n_t;
+  double slope, pivot;
+  CosmoArgs cosmo;
+  GaussLegendre gl;
+  // outputs (by galaxy index; any may be null)
+  double *sfr_bar, *sfh_params_bar;
+  float *lgmet_bar, *sigma_bar, *av_bar, *delta_bar, *bump_bar;
+};
+int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream);
 
 }  // namespace dsps

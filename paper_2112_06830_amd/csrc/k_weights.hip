@@ -357,6 +357,26 @@ __global__ __launch_bounds__(256) void k_pack_table(const T *__restrict__ src, i
   }
 }
 
+// lum rows -> SK[k][l] with k = met * 96 + age (rows padded to sk_rows), zero padded.
+__global__ void k_pack_table_kmajor(const float *__restrict__ src, int n_age, int n_wave,
+                                    int n_wave_pad, int k_pad, int sk_rows, float *__restrict__ dst) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)sk_rows * n_wave_pad) return;
+  const int k = (int)(idx / n_wave_pad), l = (int)(idx % n_wave_pad);
+  const int met = k / AGE_PAD, age = k - met * AGE_PAD;
+  float v = 0.0f;
+  if (k < k_pad && age < n_age && l < n_wave) v = src[((size_t)met * n_age + age) * n_wave + l];
+  dst[idx] = v;
+}
+
+int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n_wave_pad,
+                             int k_pad, int sk_rows, float *sk32, hipStream_t stream) {
+  const size_t total = (size_t)sk_rows * n_wave_pad;
+  hipLaunchKernelGGL(k_pack_table_kmajor, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     stream, lum_rows, n_age, n_wave, n_wave_pad, k_pad, sk_rows, sk32);
+  return hip_fail(hipGetLastError(), "k_pack_table_kmajor launch");
+}
+
 int launch_pack_table(const float *lum_rows, const uint16_t *q_rows, int n_met, int n_age,
                       int n_wave, int n_wave_pad, int k_pad, float *st32, uint16_t *st16,
                       hipStream_t stream) {

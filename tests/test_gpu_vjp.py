@@ -1,0 +1,216 @@
+"""GPU parity of the hand-written adjoint (dsps_mags_vjp) and the autograd
+wrapper: against the FP64 oracle adjoint, against central finite differences
+of the FP64 oracle forward (h = 1e-4), and against closed forms."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import filters6, oracle_inputs, ssp_large, ssp_small
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3   # relative, per parameter (workload target)
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def grad_close(got, ref, tol=GRAD_TOL):
+    """Per-parameter metric: relative L2 error and elementwise error with a
+    floor of 1e-2 rms (gradients that nearly cancel are judged against the
+    scale of their parameter, not against zero)."""
+    got = np.asarray(got, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    rms = np.sqrt(np.mean(ref**2))
+    l2 = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+    elem = np.abs(got - ref) <= tol * np.maximum(np.abs(ref), 1e-2 * rms)
+    return l2 <= tol and bool(elem.all()), (l2, float(np.mean(~elem)))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_06830_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def large(dev):
+    ssp = ssp_large()
+    return dev.SspBlock.from_synth(ssp), dev.FilterBank.from_synth(filters6()), ssp
+
+
+@pytest.fixture(scope="module")
+def small(dev):
+    ssp = ssp_small()
+    return dev.SspBlock.from_synth(ssp), dev.FilterBank.from_synth(filters6()), ssp
+
+
+def _loss_cotangent(m, targets):
+    return 2.0 * (m - targets)
+
+
+KEYS = {"lgmet": "lgmet_bar", "sigma_z": "sigma_bar", "av": "av_bar", "delta": "delta_bar",
+        "bump": "bump_bar"}
+
+
+@pytest.mark.parametrize("use_params", [True, False])
+def test_vjp_matches_oracle_adjoint_64_galaxies(dev, large, use_params):
+    """The gradient workload's check set: 64 galaxies, z ~ U[0.1, 3]."""
+    import torch
+    ssp_h, flt_h, ssp = large
+    pop = synth.make_population(64, n_t=100, z_range=(0.1, 3.0), seed=5)
+    inp = oracle_inputs(ssp, pop)
+    _say(f"vjp 64 galaxies use_params={use_params}")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr, use_params=use_params)
+    m, bands = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)
+    m_ref = oracle.mags(inp)
+    bar = _loss_cotangent(m_ref, pop.targets)
+    g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, torch.tensor(bar, dtype=torch.float32),
+                     bands=bands)
+    ref = oracle.mags_vjp(inp, bar)
+    for k, rk in KEYS.items():
+        ok, info = grad_close(g[k].cpu().numpy(), ref[rk])
+        assert ok, (k, info)
+    ok, info = grad_close(g["sfr"].cpu().numpy(), ref["sfr_bar"])
+    assert ok, ("sfr", info)
+    if use_params:
+        for j in range(5):
+            ok, info = grad_close(g["sfh_params"].cpu().numpy()[j], ref["sfh_params_bar"][j])
+            assert ok, (j, info)
+
+
+def test_vjp_matches_central_differences(dev, small):
+    """Gradient of sum (m - target)^2 against central differences of the FP64
+    oracle forward with h = 1e-4 in each parameter's natural units."""
+    import torch
+    ssp_h, flt_h, ssp = small
+    pop = synth.make_population(12, n_t=100, z_range=(0.1, 1.0), seed=41)
+    inp = oracle_inputs(ssp, pop)
+    _say("vjp vs central differences, 12 galaxies")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp).cpu().numpy().astype(np.float64)
+    bar = _loss_cotangent(m, pop.targets)
+    g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, torch.tensor(bar, dtype=torch.float32))
+
+    def loss(p):
+        p.sfr = oracle.sfh.sfr_from_params(p.t_table, p.sfh_params)
+        return np.sum((oracle.mags(p) - pop.targets) ** 2)
+
+    fd = {k: np.zeros(pop.n_gal) for k in KEYS}
+    fd_par = np.zeros((5, pop.n_gal))
+    for gi in range(pop.n_gal):
+        for k in KEYS:
+            vals = []
+            for sgn in (1, -1):
+                p = oracle_inputs(ssp, pop)
+                arr = getattr(p, k).copy()
+                arr[gi] += sgn * 1e-4
+                setattr(p, k, arr)
+                vals.append(loss(p))
+            fd[k][gi] = (vals[0] - vals[1]) / 2e-4
+        for j in range(5):
+            h = 1e-4 * max(1.0, abs(pop.sfh_params[j, gi]))
+            vals = []
+            for sgn in (1, -1):
+                p = oracle_inputs(ssp, pop)
+                p.sfh_params = p.sfh_params.copy()
+                p.sfh_params[j, gi] += sgn * h
+                vals.append(loss(p))
+            fd_par[j, gi] = (vals[0] - vals[1]) / (2 * h)
+    for k in KEYS:
+        ok, info = grad_close(g[k].cpu().numpy(), fd[k])
+        assert ok, (k, info)
+    for j in range(5):
+        ok, info = grad_close(g["sfh_params"].cpu().numpy()[j], fd_par[j])
+        assert ok, (j, info)
+
+
+def test_vjp_closed_forms(dev, small):
+    import torch
+    ssp_h, flt_h, ssp = small
+    pop = synth.make_population(32, n_t=100, z_range=(0.1, 1.0), seed=8)
+    pop.av[:8] = 0.0
+    _say("vjp closed forms")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    for b in (0, 3, 5):
+        bar = np.zeros((32, 6), dtype=np.float32)
+        bar[:, b] = 1.0
+        g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, torch.tensor(bar))
+        # SFR is proportional to A: A dm/dA = -2.5 / ln 10
+        a_grad = g["sfh_params"].cpu().numpy()[0] * pop.sfh_params[0]
+        np.testing.assert_allclose(a_grad, -2.5 / np.log(10.0), rtol=2e-4)
+        # A_V = 0: the curve shape has no effect
+        assert np.all(g["delta"].cpu().numpy()[:8] == 0.0)
+        assert np.all(g["bump"].cpu().numpy()[:8] == 0.0)
+        assert np.all(g["av"].cpu().numpy() > 0.0)
+
+
+def test_vjp_recomputes_band_sums_when_not_given(dev, large):
+    import torch
+    ssp_h, flt_h, ssp = large
+    pop = synth.make_population(200, n_t=100, z_range=(0.1, 3.0), seed=12)
+    _say("vjp bands=None vs bands given")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m, bands = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)
+    bar = torch.tensor(_loss_cotangent(m.cpu().numpy(), pop.targets), dtype=torch.float32)
+    g1 = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bands)
+    g2 = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=None)
+    for k in g1:
+        assert torch.equal(g1[k], g2[k]), k
+
+
+def test_autograd_function_matches_oracle(dev, large):
+    import torch
+    ssp_h, flt_h, ssp = large
+    pop = synth.make_population(48, n_t=100, z_range=(0.1, 3.0), seed=21)
+    inp = oracle_inputs(ssp, pop)
+    _say("autograd.Function backward")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    par = dp.sfh_params.clone().requires_grad_(True)
+    leaves = {k: getattr(dp, k).clone().requires_grad_(True) for k in KEYS}
+    m = dev.dsps_mags(ssp_h, flt_h, dev.Cosmology(), dp, sfh_params=par, **leaves)
+    tgt = torch.tensor(pop.targets, device="cuda", dtype=torch.float32)
+    loss = ((m - tgt) ** 2).sum()
+    loss.backward()
+    ref = oracle.mags_vjp(inp, _loss_cotangent(oracle.mags(inp), pop.targets))
+    for k, rk in KEYS.items():
+        ok, info = grad_close(leaves[k].grad.cpu().numpy(), ref[rk])
+        assert ok, (k, info)
+    for j in range(5):
+        ok, info = grad_close(par.grad.cpu().numpy()[j], ref["sfh_params_bar"][j])
+        assert ok, (j, info)
+
+
+def test_vjp_full_size_sampled(dev, large):
+    """2e5 galaxies (the gradient workload size) in one call; 32 sampled
+    galaxies against the oracle adjoint."""
+    import torch
+    ssp_h, flt_h, ssp = large
+    pop = synth.make_population(200_000, n_t=100, z_range=(0.1, 3.0), seed=5)
+    _say("vjp full size n_gal=200000")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m, bands = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)
+    bar = torch.tensor(pop.targets, device="cuda", dtype=torch.float32)
+    bar = 2.0 * (m - bar)
+    g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bands)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(pop.n_gal, 32, replace=False))
+    sub = pop.subset(idx)
+    inp = oracle_inputs(ssp, sub)
+    ref = oracle.mags_vjp(inp, bar.cpu().numpy()[idx].astype(np.float64))
+    for k, rk in KEYS.items():
+        ok, info = grad_close(g[k].cpu().numpy()[idx], ref[rk])
+        assert ok, (k, info)
+    for j in range(5):
+        ok, info = grad_close(g["sfh_params"].cpu().numpy()[j, idx], ref["sfh_params_bar"][j])
+        assert ok, (j, info)

@@ -59,7 +59,7 @@ struct SspView {
   const float *kscale;             // [k_pad] power-of-two row scales (1 on padding)
   const float4 *lconst;            // [n_wave_pad] (lambda, log2(lambda/5500), k0, drude shape)
   const float *qweight;            // [n_wave_pad] trapezoid weight in dlambda/lambda
-  const float *sk32;               // [sk_rows][n_wave_pad] K-major float32 copy (adjoint), or null
+  const float *sk32;               // [sk_rows][n_wave_pad] K-major, metallicity-differenced (adjoint)
   int sk_rows;                     // k_pad rounded up to a multiple of TILE_L
 };
 

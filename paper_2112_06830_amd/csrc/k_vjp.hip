@@ -390,40 +390,32 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   const double inv_sig = 1.0 / sig;
   const float *wb = a.wbar + (size_t)local * P.k_pad;
   double d_lgmet = 0.0, d_sig = 0.0;
+  // wb holds Y[j] = Wbar[j] - Wbar[j-1] (Y[0] = Wbar[0]) from the
+  // metallicity-differenced table.  Bin j spans edges j and j+1,
+  // P_j = C(u_{j+1}) - C(u_j); the cotangent of the CDF at an interior edge j
+  // is Pbar_{j-1} - Pbar_j = -m_age Y[j], and m_age_bar = sum_j Wbar[j] P_j.
   for (int i = lane; i < n_age; i += 64) {
     const double mu = lgmet + a.slope * (P.lg_age[i] - a.pivot);
-    double mb = 0.0;
-    double c_prev = 0.0, pbar_prev = 0.0;   // CDF at edge j and Pbar of bin j-1
-    for (int j = 0; j <= n_met; ++j) {
-      // edge j sits between bins j-1 and j
-      double c_e, t_e, u_e;
-      if (j == 0) { c_e = 0.0; t_e = 0.0; u_e = 0.0; }
-      else if (j == n_met) { c_e = 1.0; t_e = 0.0; u_e = 0.0; }
-      else {
-        u_e = (P.met_edges[j] - mu) * inv_sig;
-        c_e = triweight_cdf(u_e);
-        t_e = triweight_pdf(u_e);
+    const double m_i = mage[i];
+    double mb = 0.0, wcum = 0.0;
+    double c_lo = 0.0, u_lo = 0.0;    // CDF and u at edge j (the lower edge of bin j)
+    for (int j = 0; j < n_met; ++j) {
+      const double y = (double)wb[j * AGE_PAD + i];
+      wcum += y;                       // Wbar[j]
+      if (j >= 1) {
+        const double ubar = -m_i * y * triweight_pdf(u_lo);
+        d_lgmet -= ubar * inv_sig;
+        d_sig -= ubar * u_lo * inv_sig;
       }
-      double pbar = 0.0;
-      if (j < n_met) {
-        // bin j spans edges j and j+1; its weight needs the upper CDF
-        double c_up;
-        if (j + 1 == n_met) c_up = 1.0;
-        else c_up = triweight_cdf((P.met_edges[j + 1] - mu) * inv_sig);
-        const double p = c_up - (j == 0 ? 0.0 : c_e);
-        const double wbar = (double)wb[j * AGE_PAD + i];
-        mb += wbar * p;
-        pbar = wbar * mage[i];
+      double c_hi = 1.0, u_hi = 0.0;   // upper edge of the last bin is +inf
+      if (j + 1 < n_met) {
+        u_hi = (P.met_edges[j + 1] - mu) * inv_sig;
+        c_hi = triweight_cdf(u_hi);
       }
-      // dC_e: + from bin j-1 (upper edge), - from bin j (lower edge)
-      const double cbar = pbar_prev - pbar;
-      const double ubar = cbar * t_e;
-      d_lgmet -= ubar * inv_sig;
-      d_sig -= ubar * u_e * inv_sig;
-      pbar_prev = pbar;
-      c_prev = c_e;
+      mb += wcum * (c_hi - c_lo);
+      c_lo = c_hi;
+      u_lo = u_hi;
     }
-    (void)c_prev;
     mbar[i] = mb;
   }
   d_lgmet = wave_sum(d_lgmet);

@@ -357,16 +357,25 @@ __global__ __launch_bounds__(256) void k_pack_table(const T *__restrict__ src, i
   }
 }
 
-// lum rows -> SK[k][l] with k = met * 96 + age (rows padded to sk_rows), zero padded.
+// lum rows -> metallicity-differenced K-major table for the adjoint:
+// SK[met * 96 + age][l] = L[met, age, l] - L[met - 1, age, l] (L[-1] = 0),
+// formed in float64 and rounded once.  The transposed contraction against it
+// returns Wbar[0] and the differences Wbar[j] - Wbar[j-1] directly, which are
+// what the metallicity-weight gradients need (adjacent metallicity rows are
+// nearly equal, so differencing Wbar afterwards would cancel in float32).
+// Rows are padded to sk_rows and wavelengths to n_wave_pad with zeros.
 __global__ void k_pack_table_kmajor(const float *__restrict__ src, int n_age, int n_wave,
                                     int n_wave_pad, int k_pad, int sk_rows, float *__restrict__ dst) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)sk_rows * n_wave_pad) return;
   const int k = (int)(idx / n_wave_pad), l = (int)(idx % n_wave_pad);
   const int met = k / AGE_PAD, age = k - met * AGE_PAD;
-  float v = 0.0f;
-  if (k < k_pad && age < n_age && l < n_wave) v = src[((size_t)met * n_age + age) * n_wave + l];
-  dst[idx] = v;
+  double v = 0.0;
+  if (k < k_pad && age < n_age && l < n_wave) {
+    v = (double)src[((size_t)met * n_age + age) * n_wave + l];
+    if (met > 0) v -= (double)src[((size_t)(met - 1) * n_age + age) * n_wave + l];
+  }
+  dst[idx] = (float)v;
 }
 
 int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n_wave_pad,

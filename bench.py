@@ -156,13 +156,95 @@ def run_workload(P, name, n_gal, n_t, precision, steps, warmup, seed, want_roofl
     return res, (ssp, flt, pop, sfr)
 
 
+def run_grad(P, steps, warmup, n_gal=200_000, seed=5):
+    """Forward plus adjoint of sum (m - target)^2 on the gradient workload:
+    2e5 galaxies, parametric SFH (gradients w.r.t. A, tau, alpha, q, t_q,
+    lgmet, sigma_Z, A_V, delta, bump), FP32."""
+    import torch
+    import synth
+    ssp = synth.make_ssp(n_wave=5994, wave_lo=9.0e2, wave_hi=2.5e4)
+    flt = synth.make_filters()
+    pop = synth.make_population(n_gal, n_t=100, z_range=(0.1, 3.0), seed=seed)
+    log(f"grad_fp32_2e5: uploading {n_gal} galaxies")
+    ssp_h = P.SspBlock.from_synth(ssp, precisions=("fp32",))
+    flt_h = P.FilterBank.from_synth(flt)
+    dpop = P.DevicePopulation.from_synth(pop, use_params=True)
+    tgt = torch.tensor(pop.targets, dtype=torch.float32, device="cuda")
+    ws_f = P.Workspace(P.workspace_size(2, ssp_h, flt_h, n_gal, 100, "fp32"), dpop.device)
+    ws_b = P.Workspace(P.workspace_size(3, ssp_h, flt_h, n_gal, 100, "fp32"), dpop.device)
+    m = torch.empty((n_gal, 6), dtype=torch.float32, device="cuda")
+    bands = torch.empty((n_gal, 2, 6), dtype=torch.float32, device="cuda")
+    outs = {"sfh_params": torch.empty((5, n_gal), dtype=torch.float64, device="cuda")}
+    for k in ("lgmet", "sigma_z", "av", "delta", "bump"):
+        outs[k] = torch.empty(n_gal, dtype=torch.float32, device="cuda")
+    bar = torch.empty_like(m)
+
+    def step():
+        P.mags(ssp_h, flt_h, P.Cosmology(), dpop, with_bands=True, workspace=ws_f, out=m, bands_out=bands)
+        torch.sub(m, tgt, out=bar)
+        bar.mul_(2.0)
+        P.mags_vjp(ssp_h, flt_h, P.Cosmology(), dpop, bar, bands=bands, workspace=ws_b, outs=outs)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    P.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = {"ms_per_step": (t1 - t0) * 1e3 / steps}
+    res["galaxies_per_s"] = n_gal / (res["ms_per_step"] * 1e-3)
+    for k in ("mags_gemm", "vjp_gemm", "vjp_wbar", "vjp_weights", "weights"):
+        ms, n = P.profile_read(k)
+        res[f"{k}_ms_per_step"] = ms / steps
+    P.profile_enable(False)
+    res["finite"] = bool(all(torch.isfinite(v).all().item() for v in outs.values()))
+    return res
+
+
+def run_serve(seconds=6.0, rate_hz=200.0):
+    """Serving workload: Poisson arrivals at 200 req/s, N ~ logU[1e3, 1e5]
+    galaxies per request with a per-request redshift range, 30% asking for
+    gradients (FP32), the rest forward on the BF16 table; then the same trace
+    served request by request on the plain FP32 path."""
+    import torch
+    import synth
+    import paper_2112_06830_amd as P
+    import paper_2112_06830_amd.serve as S
+    ssp = synth.make_ssp(n_wave=5994, wave_lo=9.0e2, wave_hi=2.5e4)
+    flt = synth.make_filters()
+    n_req = int(seconds * rate_hz)
+    arrivals, reqs = S.make_trace(n_req, rate_hz=rate_hz, seed=6)
+    eng = S.ServeEngine(ssp, flt, buckets=(16384, 65536, 131072, 262144), hbm_budget_bytes=48 << 30)
+    log("serve: capturing slot graphs")
+    eng.warm(buckets=(65536, 262144))
+    eng.start()
+    wall = S.replay_trace(eng, arrivals, reqs, timeout_s=300)
+    eng.stop()
+    res = S.latency_summary(reqs, wall)
+    res["batches"] = eng.batches_run
+    res["gradient_requests"] = int(sum(r.grad for r in reqs))
+    log(f"serve: p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms, "
+        f"{res['throughput_galaxies_per_s']:.3e} gal/s")
+    _, reqs2 = S.make_trace(n_req, rate_hz=rate_hz, seed=6)
+    base = S.serial_baseline(eng.ssp_h, eng.flt_h, eng.cosmo, eng.t_table, arrivals, reqs2)
+    log(f"serial fp32: p50 {base['p50_ms']:.1f} ms p99 {base['p99_ms']:.1f} ms")
+    res["request_by_request_fp32"] = base
+    torch.cuda.synchronize()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the BF16 1e6 leg")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the BF16 1e6, forward+gradient and serving legs")
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -194,6 +276,10 @@ def main():
             "mfma_frac_bf16": bf["achieved_tflops"] / PEAK_TFLOPS["bf16"],
             "sfh_read_hbm_frac": (1_000_000 * 1000 * 8 / (bf["weights_ms_per_step"] * 1e-3)) / 1e9 / HBM_PEAK_GBS}
         log(f"bf16 1e6: {bf['ms_per_step']:.3f} ms/step")
+        gr = run_grad(P, max(3, args.steps // 4), 1)
+        extra["fp32_fwd_grad_2e5"] = gr
+        log(f"fp32 fwd+grad 2e5: {gr['ms_per_step']:.3f} ms/step")
+        extra["serve_poisson_200hz"] = run_serve(seconds=args.serve_seconds)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -291,14 +291,18 @@ def profile_read(kernel: str):
 def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopulation,
              mags_bar: torch.Tensor, bands: torch.Tensor | None = None,
              want=("sfr", "sfh_params", "lgmet", "sigma_z", "av", "delta", "bump"),
-             workspace: Workspace | None = None, stream=None) -> dict:
+             workspace: Workspace | None = None, outs: dict | None = None, stream=None) -> dict:
     """dsps_mags_vjp: cotangents of the population inputs for a magnitude
-    cotangent mags_bar [n_gal, n_band] (float32 path)."""
+    cotangent mags_bar [n_gal, n_band] (float32 path).  `outs` may supply
+    preallocated output tensors (then `want` is ignored)."""
     n, d = pop.n_gal, pop.device
     mags_bar = mags_bar.to(device=d, dtype=torch.float32).contiguous()
     if bands is not None:
         bands = bands.to(device=d, dtype=torch.float32).contiguous()
     out = {}
+    if outs is not None:
+        out = dict(outs)
+        want = ()
     if "sfr" in want:
         out["sfr"] = torch.empty((n, pop.n_t), dtype=torch.float64, device=d)
     if "sfh_params" in want and pop.sfh_params is not None:

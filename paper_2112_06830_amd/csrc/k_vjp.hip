@@ -30,7 +30,9 @@ __global__ void k_vjp_gamma(VjpLaunch a) {
   const int nb = a.n_band;
   for (int b = 0; b < nb; ++b) {
     const float num = a.bands[(size_t)g * 2 * nb + b];
-    a.gamma[(size_t)s * nb + b] = -2.5f * a.mags_bar[(size_t)g * nb + b] / (LN10_F * num);
+    const float bar = a.mags_bar[(size_t)g * nb + b];
+    // a zero cotangent contributes nothing, also for a band with num = 0
+    a.gamma[(size_t)s * nb + b] = bar == 0.0f ? 0.0f : -2.5f * bar / (LN10_F * num);
   }
 }
 

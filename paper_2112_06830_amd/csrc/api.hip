@@ -278,6 +278,8 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   (void)hipGetDevice(&h->device);
   h->precisions = precisions;
   h->k0_reading = k0_reading;
+  h->lg_age_first = lg_age[0];
+  h->lg_age_last = lg_age[n_age - 1];
   h->v = v;
   h->alloc = base;
   *out = h;
@@ -367,20 +369,26 @@ int dsps_filters_info(const dsps_filters *f, int *n_band, int *n_pts) {
 // ------------------------------------------------------------------ workspace
 namespace dsps {
 
-constexpr int BATCH = 32768;   // galaxies per weights + GEMM round trip
+// Galaxies per weights + GEMM round trip.  The forward keeps whole
+// populations of up to 256k galaxies in one launch (no small tail launch);
+// the adjoint's per-galaxy scratch (Lbar, Wbar) is 28 KB, so it runs in
+// batches of 64k.
+constexpr int BATCH_FWD = 262144;
+constexpr int BATCH_VJP = 65536;
 
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
-  size_t gamma = 0, vpartial = 0, lbar = 0, wbar = 0, fbands = 0;
-  int batch = 0, n_groups = 0;
+  size_t gamma = 0, vpartial = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0;
+  int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
 static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int precision) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
-  L.batch = std::min(n_gal, BATCH);
-  L.n_groups = (v.n_wave_pad / TILE_L + CHUNKS_PER_GROUP - 1) / CHUNKS_PER_GROUP;
+  L.batch = std::min(n_gal, op == DSPS_OP_MAGS_VJP ? BATCH_VJP : BATCH_FWD);
+  L.n_chunks = v.n_wave_pad / TILE_L;
+  L.n_groups = (L.n_chunks + CHUNKS_PER_GROUP - 1) / CHUNKS_PER_GROUP;
   const size_t elem = precision == DSPS_BF16 ? 2 : 4;
   if (op == DSPS_OP_WEIGHTS) { L.total = 0; return L; }
   if (op == DSPS_OP_SED) {
@@ -389,13 +397,14 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
     L.total = off;
     return L;
   }
-  L.hist = take(sizeof(int) * ZBINS);
+  L.hist = take(sizeof(int) * SORT_BINS);
   L.perm = take(sizeof(int) * (size_t)n_gal);
   L.meta = take(sizeof(GalaxyMeta) * (size_t)n_gal);
   L.range = take(sizeof(GalaxyRange) * (size_t)n_gal);
   L.offset = take(sizeof(double) * (size_t)n_gal);
   L.w = take(elem * (size_t)L.batch * v.k_pad);
-  L.partial = take(sizeof(float) * (size_t)L.batch * L.n_groups * 2 * n_band);
+  L.partial = take(sizeof(float) * (size_t)L.batch * L.n_chunks * 2 * n_band);
+  L.tiles = take(sizeof(int2) * (size_t)((L.batch + TILE_G - 1) / TILE_G));
   if (op == DSPS_OP_MAGS_VJP) {
     L.gamma = take(sizeof(float) * (size_t)n_gal * n_band);
     L.vpartial = take(sizeof(float) * (size_t)L.batch * L.n_groups * 3);
@@ -435,6 +444,24 @@ static int check_workspace(void *ws, size_t have, size_t need) {
   DSPS_CHECK(((uintptr_t)ws & 255u) == 0, DSPS_ERR_WORKSPACE, "workspace not 256-byte aligned");
   DSPS_CHECK(have >= need, DSPS_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", have, need);
   return DSPS_OK;
+}
+
+static int sort_population(const dsps_ssp *ssp, const dsps_pop *p, int *hist, int *perm,
+                           hipStream_t stream) {
+  SortLaunch s{};
+  s.z = p->z;
+  s.lgmet = p->lgmet;
+  s.sigma_z = p->sigma_z;
+  s.n_gal = p->n_gal;
+  s.slope = p->lgmet_slope;
+  s.pivot = p->lg_age_pivot;
+  s.lg_age_first = ssp->lg_age_first;
+  s.lg_age_last = ssp->lg_age_last;
+  s.met_edges = ssp->v.met_edges;
+  s.n_met = ssp->v.n_met;
+  s.hist = hist;
+  s.perm = perm;
+  return launch_sort(s, stream);
 }
 
 static WeightsLaunch base_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *p) {
@@ -566,7 +593,7 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
   GalaxyRange *range = (GalaxyRange *)(ws + L.range);
   double *offset = (double *)(ws + L.offset);
   float *partial = (float *)(ws + L.partial);
-  DSPS_TRY(launch_zsort(pop->z, pop->n_gal, (int *)(ws + L.hist), perm, stream));
+  DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), perm, stream));
   for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
     const int cnt = std::min(L.batch, pop->n_gal - s0);
     WeightsLaunch a = base_weights(ssp, cosmo, pop);
@@ -591,11 +618,14 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
     m.meta = meta;
     m.range = range;
     m.n_groups = L.n_groups;
+    m.n_chunks = L.n_chunks;
     m.partial = partial;
+    m.tile_chunks = (int2 *)(ws + L.tiles);
     DSPS_TRY(launch_mags_gemm(m, stream));
     FinalizeLaunch f{};
     f.n_band = n_band;
-    f.n_groups = L.n_groups;
+    f.n_chunks = L.n_chunks;
+    f.tile_chunks = (const int2 *)(ws + L.tiles);
     f.s_begin = s0;
     f.s_count = cnt;
     f.partial = partial;
@@ -635,7 +665,7 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
   float *fwd_bands = bands ? nullptr : (float *)(ws + L.fbands);
   float *fwd_mags = (float *)(ws + L.fbands) + (size_t)pop->n_gal * 2 * n_band;
   const float *use_bands = bands ? bands : fwd_bands;
-  DSPS_TRY(launch_zsort(pop->z, pop->n_gal, (int *)(ws + L.hist), perm, stream));
+  DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), perm, stream));
   for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
     const int cnt = std::min(L.batch, pop->n_gal - s0);
     WeightsLaunch a = base_weights(ssp, cosmo, pop);
@@ -661,11 +691,14 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
       m.meta = meta;
       m.range = range;
       m.n_groups = L.n_groups;
+      m.n_chunks = L.n_chunks;
       m.partial = (float *)(ws + L.partial);
+      m.tile_chunks = (int2 *)(ws + L.tiles);
       DSPS_TRY(launch_mags_gemm(m, stream));
       FinalizeLaunch f{};
       f.n_band = n_band;
-      f.n_groups = L.n_groups;
+      f.n_chunks = L.n_chunks;
+      f.tile_chunks = (const int2 *)(ws + L.tiles);
       f.s_begin = s0;
       f.s_count = cnt;
       f.partial = (const float *)(ws + L.partial);

@@ -24,7 +24,7 @@ constexpr int AGE_PAD = 96;        // ages per metallicity row in the padded K a
 constexpr int TILE_G = 128;        // galaxies per GEMM tile (N of the MFMA tile)
 constexpr int TILE_L = 128;        // wavelengths per chunk (M of the MFMA tile)
 constexpr int CHUNKS_PER_GROUP = 4;  // wavelength chunks one workgroup walks
-constexpr int ZBINS = 2048;        // redshift buckets of the ordering sort
+constexpr int SORT_BINS = 8192;    // keys of the ordering sort (5-bit z bucket, 4+4-bit rows)
 constexpr int GEMM_THREADS = 256;  // 4 wave64s in a 2 x 2 arrangement
 constexpr int WEIGHT_WAVES = 4;    // galaxies per weights workgroup (one per wave)
 
@@ -67,6 +67,7 @@ struct SspHandle {
   int device = -1;
   int precisions = 0;
   int k0_reading = 0;
+  double lg_age_first = 0, lg_age_last = 0;
   SspView v{};
   void *alloc = nullptr;           // single device allocation backing every array
 };
@@ -215,7 +216,17 @@ int launch_weights(const WeightsLaunch &a, hipStream_t stream);
 
 int launch_sfh_table(const double *t_table, int n_t, const double *params, int n_gal,
                      double *sfr, hipStream_t stream);
-int launch_zsort(const float *z, int n_gal, int *hist, int *perm, hipStream_t stream);
+// Counting sort of galaxies by (redshift bucket, metallicity-row range).
+struct SortLaunch {
+  const float *z, *lgmet, *sigma_z;
+  int n_gal;
+  double slope, pivot, lg_age_first, lg_age_last;
+  const double *met_edges;   // [n_met + 1], device
+  int n_met;
+  int *hist;                 // [SORT_BINS] scratch
+  int *perm;                 // [n_gal] sorted position -> galaxy
+};
+int launch_sort(const SortLaunch &a, hipStream_t stream);
 int launch_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float *scale,
                          hipStream_t stream);
 int launch_pack_table(const float *lum_rows, const uint16_t *q_rows, int n_met, int n_age,
@@ -233,15 +244,18 @@ struct MagsLaunch {
   const void *w_pad;             // [s_count][k_pad]
   const GalaxyMeta *meta;        // full arrays, by sorted position
   const GalaxyRange *range;
-  int n_groups;                  // wavelength groups covering n_wave_pad
-  float *partial;                // [s_count][n_groups][2 * n_band]
+  int n_groups;                  // workgroups per tile (upper bound on its chunk groups)
+  int n_chunks;                  // n_wave_pad / TILE_L
+  float *partial;                // [s_count][n_chunks][2 * n_band], chunks of the tile window
+  int2 *tile_chunks;             // [n_tiles] first and one-past-last chunk of each tile
 };
 int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream);
 
 struct FinalizeLaunch {
-  int n_band, n_groups;
+  int n_band, n_chunks;
   int s_begin, s_count;
   const float *partial;
+  const int2 *tile_chunks;
   const double *mag_offset;
   const int *perm;
   float *mags;    // [n_gal][n_band] by galaxy index

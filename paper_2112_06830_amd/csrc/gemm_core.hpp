@@ -17,8 +17,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 template <int PREC> struct GemmCfg;
 template <> struct GemmCfg<DSPS_FP32> {
   using elem = float;
-  static constexpr int KT = 16;        // K per LDS stage (divides AGE_PAD)
-  static constexpr int PITCH = 20;     // elements per LDS row (16-byte aligned, conflict-free)
+  static constexpr int KT = 32;        // K per LDS stage (divides AGE_PAD)
+  static constexpr int PITCH = 36;     // elements per LDS row (16-byte aligned, conflict-free)
 };
 template <> struct GemmCfg<DSPS_BF16> {
   using elem = uint16_t;
@@ -81,32 +81,38 @@ __device__ __forceinline__ void store_stage(const StageRegs<PREC> &r, GemmSmem<P
 __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_FP32> &sm, int wr, int wc, int lane,
                                           f32x16 (&acc)[2][2]) {
   using C = GemmCfg<DSPS_FP32>;
+  constexpr int HALF = C::KT / 2;      // contraction indices owned by one lane half
   const int h = lane >> 5, c = lane & 31;
-  float av[2][8], bv[2][8];
+  // Lane half h supplies contraction index HALF*h + 8u + t at MFMA step
+  // (u, t), for A and B alike; each lane reads 8 contiguous values per
+  // operand block and sub-step.
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) {
-    const float *p = &sm.a[(wr * 64 + mb * 32 + c) * C::PITCH + 8 * h];
-    const float4 x0 = *reinterpret_cast<const float4 *>(p);
-    const float4 x1 = *reinterpret_cast<const float4 *>(p + 4);
-    av[mb][0] = x0.x; av[mb][1] = x0.y; av[mb][2] = x0.z; av[mb][3] = x0.w;
-    av[mb][4] = x1.x; av[mb][5] = x1.y; av[mb][6] = x1.z; av[mb][7] = x1.w;
+  for (int u = 0; u < HALF / 8; ++u) {
+    float av[2][8], bv[2][8];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const float *p = &sm.a[(wr * 64 + mb * 32 + c) * C::PITCH + HALF * h + 8 * u];
+      const float4 x0 = *reinterpret_cast<const float4 *>(p);
+      const float4 x1 = *reinterpret_cast<const float4 *>(p + 4);
+      av[mb][0] = x0.x; av[mb][1] = x0.y; av[mb][2] = x0.z; av[mb][3] = x0.w;
+      av[mb][4] = x1.x; av[mb][5] = x1.y; av[mb][6] = x1.z; av[mb][7] = x1.w;
+    }
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const float *p = &sm.b[(wc * 64 + nb * 32 + c) * C::PITCH + HALF * h + 8 * u];
+      const float4 x0 = *reinterpret_cast<const float4 *>(p);
+      const float4 x1 = *reinterpret_cast<const float4 *>(p + 4);
+      bv[nb][0] = x0.x; bv[nb][1] = x0.y; bv[nb][2] = x0.z; bv[nb][3] = x0.w;
+      bv[nb][4] = x1.x; bv[nb][5] = x1.y; bv[nb][6] = x1.z; bv[nb][7] = x1.w;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][t], bv[nb][t], acc[mb][nb], 0, 0, 0);
   }
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    const float *p = &sm.b[(wc * 64 + nb * 32 + c) * C::PITCH + 8 * h];
-    const float4 x0 = *reinterpret_cast<const float4 *>(p);
-    const float4 x1 = *reinterpret_cast<const float4 *>(p + 4);
-    bv[nb][0] = x0.x; bv[nb][1] = x0.y; bv[nb][2] = x0.z; bv[nb][3] = x0.w;
-    bv[nb][4] = x1.x; bv[nb][5] = x1.y; bv[nb][6] = x1.z; bv[nb][7] = x1.w;
-  }
-  // Lane half h supplies contraction index 8h + t at step t, for A and B alike.
-#pragma unroll
-  for (int t = 0; t < 8; ++t)
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][t], bv[nb][t], acc[mb][nb], 0, 0, 0);
 }
 
 __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_BF16> &sm, int wr, int wc, int lane,

@@ -21,6 +21,56 @@
 
 namespace dsps {
 
+
+// Blocks are dispatched round-robin over the 8 XCDs by linear id.  All
+// wavelength groups of one galaxy tile go to the same XCD (its W tile then
+// stays in that XCD's L2): block b runs on XCD b % 8 and takes tile
+// (b / 8 / G) * 8 + b % 8, group (b / 8) % G.
+__device__ __forceinline__ void xcd_tile_group(int b, int groups, int &tile, int &group) {
+  const int xcd = b & 7, slot = b >> 3;
+  tile = (slot / groups) * 8 + xcd;
+  group = slot % groups;
+}
+
+// Per-galaxy sums of one chunk, reduced over the two lane halves and the two
+// row-waves of each column block, written to the chunk's partial slot.
+__device__ __forceinline__ void write_chunk_partial(float (&num)[2][DSPS_MAX_BAND],
+                                                   float (&den)[2][DSPS_MAX_BAND], int n_band,
+                                                   float *s_red, int wr, int wc, int lane,
+                                                   int nvalid, float *out_base, int stride) {
+  const int h = lane >> 5;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int b = 0; b < DSPS_MAX_BAND; ++b) {
+      num[nb][b] += __shfl_xor(num[nb][b], 32, 64);
+      den[nb][b] += __shfl_xor(den[nb][b], 32, 64);
+    }
+  const int col = h * 32 + (lane & 31);       // lane half h finishes column block nb = h
+  float *red = s_red + (wc * 64 + col) * (2 * DSPS_MAX_BAND);
+  if (wr == 1) {
+#pragma unroll
+    for (int b = 0; b < DSPS_MAX_BAND; ++b) {
+      red[b] = h ? num[1][b] : num[0][b];
+      red[DSPS_MAX_BAND + b] = h ? den[1][b] : den[0][b];
+    }
+  }
+  __syncthreads();
+  if (wr == 0) {
+    const int tcol = wc * 64 + col;
+    if (tcol < nvalid) {
+      float *out = out_base + (size_t)tcol * stride;
+#pragma unroll
+      for (int b = 0; b < DSPS_MAX_BAND; ++b) {
+        if (b < n_band) {
+          out[b] = (h ? num[1][b] : num[0][b]) + red[b];
+          out[n_band + b] = (h ? den[1][b] : den[0][b]) + red[DSPS_MAX_BAND + b];
+        }
+      }
+    }
+  }
+}
+
 template <int PREC>
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
   using C = GemmCfg<PREC>;
@@ -28,12 +78,14 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
   __shared__ GemmSmem<PREC> sm;
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
-  __shared__ float s_filt[DSPS_MAX_FILTER_FLOATS];
-  __shared__ float s_red[2][64][2 * DSPS_MAX_BAND];
-  __shared__ int s_tile[4];   // window lo, window hi, met lo/hi, age hi
+  __shared__ float s_red[2 * 64 * 2 * DSPS_MAX_BAND];
+  __shared__ int s_tile[4];   // window lo, window hi, metallicity-row mask, age hi
+  extern __shared__ float s_filt[];   // [n_band * n_pts]
 
-  const int group = blockIdx.x;
-  const int tile = blockIdx.y;
+  int tile, group;
+  xcd_tile_group(blockIdx.x, a.n_groups, tile, group);
+  const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
+  if (tile >= n_tiles) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1;
@@ -62,22 +114,15 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
   const unsigned met_mask = (unsigned)s_tile[2];
   const int age_hi = s_tile[3];
   const int c_first = win_lo / TILE_L;
-  const int c_last = (win_hi + TILE_L - 1) / TILE_L;      // exclusive
-  const int c_begin = max(group * CHUNKS_PER_GROUP, c_first);
-  const int c_end = min((group + 1) * CHUNKS_PER_GROUP, c_last);
-  const int n_comp = 2 * n_band;
+  const int c_last = max((win_hi + TILE_L - 1) / TILE_L, c_first);   // exclusive
+  if (group == 0 && threadIdx.x == 0) a.tile_chunks[tile] = make_int2(c_first, c_last);
+  // groups are aligned to the tile's own window: all but the last are full
+  const int c_begin = c_first + group * CHUNKS_PER_GROUP;
+  const int c_end = min(c_begin + CHUNKS_PER_GROUP, c_last);
+  if (c_begin >= c_end) return;
 
-  if (c_begin >= c_end) {
-    for (int idx = threadIdx.x; idx < nvalid * n_comp; idx += GEMM_THREADS) {
-      const int gl = idx / n_comp, v = idx % n_comp;
-      a.partial[((size_t)(g0 + gl) * a.n_groups + group) * n_comp + v] = 0.0f;
-    }
-    return;
-  }
-
-  // ---- filters into LDS (the filter-set limit guarantees they fit)
+  // ---- filters into LDS
   for (int i = threadIdx.x; i < n_band * n_pts; i += GEMM_THREADS) s_filt[i] = F.trans[i];
-  const float *ftab = s_filt;
 
   // ---- per-galaxy parameters of this lane's two columns
   float zp1[2], da[2], dl[2], bp[2];
@@ -97,19 +142,15 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
     if (b < n_band) { const float2 gr = F.grid[b]; fw0[b] = gr.x; finv[b] = gr.y; }
     else { fw0[b] = 0.0f; finv[b] = 0.0f; }
   }
-  float num[2][DSPS_MAX_BAND], den[2][DSPS_MAX_BAND];
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-    for (int b = 0; b < DSPS_MAX_BAND; ++b) { num[nb][b] = 0.0f; den[nb][b] = 0.0f; }
 
   // ---- K steps: metallicity rows in met_mask x age blocks below age_hi
   const int n_ab = (age_hi + C::KT - 1) / C::KT;
   const int nk = __builtin_popcount(met_mask) * n_ab;
   const int j_first = met_mask ? __builtin_ctz(met_mask) : 0;
-
   const elem *st = PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16;
   const elem *w = (const elem *)a.w_pad;
+  const int n_comp = 2 * n_band;
+  float *part_tile = a.partial + (size_t)g0 * a.n_chunks * n_comp;
 
   for (int c = c_begin; c < c_end; ++c) {
     const int l0 = c * TILE_L;
@@ -145,6 +186,11 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
     __syncthreads();   // s_lc / s_q / filters visible
 
     // ---- epilogue: attenuation x resampled transmission, lane-local sums
+    float num[2][DSPS_MAX_BAND], den[2][DSPS_MAX_BAND];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int b = 0; b < DSPS_MAX_BAND; ++b) { num[nb][b] = 0.0f; den[nb][b] = 0.0f; }
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
@@ -161,7 +207,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
 #pragma unroll
           for (int b = 0; b < DSPS_MAX_BAND; ++b) {
             if (b < n_band) {
-              const float t = filter_at(ftab + b * n_pts, n_pts, (lobs - fw0[b]) * finv[b]);
+              const float t = filter_at(s_filt + b * n_pts, n_pts, (lobs - fw0[b]) * finv[b]);
               num[nb][b] += t * lq;
               den[nb][b] += t * q;
             }
@@ -169,56 +215,25 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
         }
       }
     }
-  }
-
-  // ---- reduce: lane halves, then the two row-waves of each column block
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-    for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-      num[nb][b] += __shfl_xor(num[nb][b], 32, 64);
-      den[nb][b] += __shfl_xor(den[nb][b], 32, 64);
-    }
-  __syncthreads();
-  const int my_nb = h;                          // lane half h finishes column block nb = h
-  const int col = my_nb * 32 + (lane & 31);     // column within the wave's 64
-  if (wr == 1) {
-#pragma unroll
-    for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-      if (b < n_band) {
-        s_red[wc][col][b] = my_nb ? num[1][b] : num[0][b];
-        s_red[wc][col][n_band + b] = my_nb ? den[1][b] : den[0][b];
-      }
-    }
-  }
-  __syncthreads();
-  if (wr == 0) {
-    const int tcol = wc * 64 + col;
-    if (tcol < nvalid) {
-      float *out = a.partial + ((size_t)(g0 + tcol) * a.n_groups + group) * n_comp;
-#pragma unroll
-      for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-        if (b < n_band) {
-          out[b] = (my_nb ? num[1][b] : num[0][b]) + s_red[wc][col][b];
-          out[n_band + b] = (my_nb ? den[1][b] : den[0][b]) + s_red[wc][col][n_band + b];
-        }
-      }
-    }
+    write_chunk_partial(num, den, n_band, s_red, wr, wc, lane, nvalid,
+                        part_tile + (size_t)c * n_comp, a.n_chunks * n_comp);
   }
 }
 
 int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
-  const dim3 grid(a.n_groups, (a.s_count + TILE_G - 1) / TILE_G);
+  const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
+  const int blocks = (n_tiles + 7) / 8 * 8 * a.n_groups;
+  const size_t lds = sizeof(float) * a.flt.n_band * a.flt.n_pts;
   ProfScope prof(DSPS_KERNEL_MAGS_GEMM, stream);
   if (a.precision == DSPS_BF16)
-    hipLaunchKernelGGL(k_mags_gemm<DSPS_BF16>, grid, dim3(GEMM_THREADS), 0, stream, a);
+    hipLaunchKernelGGL(k_mags_gemm<DSPS_BF16>, dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);
   else
-    hipLaunchKernelGGL(k_mags_gemm<DSPS_FP32>, grid, dim3(GEMM_THREADS), 0, stream, a);
+    hipLaunchKernelGGL(k_mags_gemm<DSPS_FP32>, dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);
   return hip_fail(hipGetLastError(), "k_mags_gemm launch");
 }
 
-// Sum the per-group partial band sums in group order and form magnitudes
+// Sum the per-chunk partial band sums in chunk order and form magnitudes
 // m = -2.5 log10(num / (AB0 den)) + [D_mod(z) - 2.5 log10(1+z)] in float64.
 __global__ void k_mags_finalize(FinalizeLaunch a) {
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
@@ -226,13 +241,14 @@ __global__ void k_mags_finalize(FinalizeLaunch a) {
   const int s = a.s_begin + local;
   const int g = a.perm ? a.perm[s] : s;
   const int nb = a.n_band, nc = 2 * nb;
-  const float *p = a.partial + (size_t)local * a.n_groups * nc;
+  const int2 cr = a.tile_chunks[local / TILE_G];
+  const float *p = a.partial + (size_t)local * a.n_chunks * nc;
   const double offset = a.mag_offset[s];
   for (int b = 0; b < nb; ++b) {
     float num = 0.0f, den = 0.0f;
-    for (int gr = 0; gr < a.n_groups; ++gr) {
-      num += p[gr * nc + b];
-      den += p[gr * nc + nb + b];
+    for (int c = cr.x; c < cr.y; ++c) {
+      num += p[c * nc + b];
+      den += p[c * nc + nb + b];
     }
     double m;
     if (den == 0.0f) m = __builtin_nan("");

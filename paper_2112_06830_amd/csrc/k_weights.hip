@@ -92,6 +92,27 @@ __device__ __forceinline__ double mass_formed(double t, const double *tt, const 
   return mc[lo] + f * (mc[hi] - mc[lo]);
 }
 
+// First index i in [0, n) with x[i] >= v (x[i] > v when strict), or n:
+// a wave-cooperative 64-ary search over an ascending array (each round every
+// lane probes one element, then the range shrinks 64-fold).
+__device__ int wave_lower_bound(const double *x, int n, double v, bool strict, int lane) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int step = (hi - lo + 63) / 64;
+    const int p = lo + lane * step;
+    bool ge = true;                       // probes at or past hi count as true
+    if (p < hi) ge = strict ? (x[p] > v) : (x[p] >= v);
+    const unsigned long long mask = __ballot(ge);
+    const int f = mask ? __ffsll(mask) - 1 : 64;
+    if (f == 0) return lo;                // x[lo] already satisfies the predicate
+    const int new_lo = lo + (f - 1) * step + 1;
+    const int new_hi = min(lo + f * step, hi);
+    lo = new_lo;
+    hi = new_hi;
+  }
+  return lo;
+}
+
 // Orders LDS traffic between the lanes of one wave (no workgroup barrier:
 // waves of a block finish independently).
 __device__ __forceinline__ void wave_sync() {
@@ -208,6 +229,13 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   ihi = wave_max(ihi);
 
   const double dmod = a.mag_offset ? wave_distance_modulus(z, a.cosmo, a.gl, lane) : 0.0;
+  // rest wavelengths whose redshifted value can meet a filter: [lo, hi) with
+  // wave[lo] >= obs_lo/(1+z) and wave[hi-1] <= obs_hi/(1+z)
+  int win_lo = 0, win_hi = 0;
+  if (a.range) {
+    win_lo = wave_lower_bound(P.wave, P.n_wave, a.obs_lo / (1.0 + z), false, lane);
+    win_hi = wave_lower_bound(P.wave, P.n_wave, a.obs_hi / (1.0 + z), true, lane);
+  }
   if (lane == 0) {
     if (a.meta) {
       GalaxyMeta m;
@@ -220,18 +248,11 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
     }
     if (a.mag_offset) a.mag_offset[s] = dmod - 2.5 * log10(1.0 + z);
     if (a.range) {
-      // rest wavelengths whose redshifted value can meet a filter, padded by
-      // two grid points on each side (points outside contribute exact zeros)
-      const double lo_rest = a.obs_lo / (1.0 + z), hi_rest = a.obs_hi / (1.0 + z);
-      const double *wv = P.wave;
-      const int nw = P.n_wave;
-      int lo = 0, hi = nw;                       // first index with wave >= lo_rest
-      while (lo < hi) { const int mid = (lo + hi) >> 1; if (wv[mid] < lo_rest) lo = mid + 1; else hi = mid; }
-      int lo2 = lo, hi2 = nw;                    // first index with wave > hi_rest
-      while (lo2 < hi2) { const int mid = (lo2 + hi2) >> 1; if (wv[mid] <= hi_rest) lo2 = mid + 1; else hi2 = mid; }
+      // padded by two grid points on each side (points outside contribute
+      // exact zeros; the padding covers float32 rounding of (1+z) lambda)
       GalaxyRange r;
-      r.win_lo = max(lo - 2, 0);
-      r.win_hi = min(lo2 + 2, nw);
+      r.win_lo = max(win_lo - 2, 0);
+      r.win_hi = min(win_hi + 2, P.n_wave);
       if (jhi < 0) { r.met_lo_hi = 0; r.age_hi = 0; }
       else { r.met_lo_hi = jlo | (jhi << 16); r.age_hi = ihi; }
       a.range[s] = r;
@@ -254,11 +275,29 @@ int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
   return hip_fail(hipGetLastError(), "k_weights launch");
 }
 
-// ------------------------------------------------------------ redshift sort
-__device__ __forceinline__ int zbin(float z) {
-  if (!(z > 0.0f)) return 0;
-  const float v = log2f(1.0f + z) * 512.0f;
-  return v >= (float)(ZBINS - 1) ? ZBINS - 1 : (int)v;
+// ------------------------------------------------------------ ordering sort
+// Key = (redshift bucket of 1/16 in log2(1+z), lowest and highest metallicity
+// row the galaxy's MDF can reach).  Galaxies of one 128-galaxy tile then share
+// a rest-wavelength window and few non-zero metallicity rows, so the GEMM
+// computes fewer chunks and K blocks.  The order never changes a galaxy's
+// result (the kernels' tiling is exact), only the work.
+__device__ __forceinline__ int sort_key(const SortLaunch &a, int g) {
+  const float z = a.z[g];
+  int zb = 0;
+  if (z > 0.0f) {
+    const float v = log2f(1.0f + z) * 16.0f;
+    zb = v >= 31.0f ? 31 : (int)v;
+  }
+  const double lgmet = (double)a.lgmet[g], three_sig = 3.0 * (double)a.sigma_z[g];
+  const double m0 = lgmet + a.slope * (a.lg_age_first - a.pivot);
+  const double m1 = lgmet + a.slope * (a.lg_age_last - a.pivot);
+  const double lo = fmin(m0, m1) - three_sig, hi = fmax(m0, m1) + three_sig;
+  int jlo = 0, jhi = 0;
+  for (int j = 1; j < a.n_met; ++j) {       // bin j starts at interior edge j
+    jlo += a.met_edges[j] <= lo;
+    jhi += a.met_edges[j] <= hi;
+  }
+  return (zb << 8) | (min(jlo, 15) << 4) | min(jhi, 15);
 }
 
 __global__ void k_fill_int(int *p, int n, int v) {
@@ -266,44 +305,47 @@ __global__ void k_fill_int(int *p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_zhist(const float *__restrict__ z, int n, int *hist) {
+__global__ void k_sort_hist(SortLaunch a) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < n) atomicAdd(&hist[zbin(z[g])], 1);
+  if (g < a.n_gal) atomicAdd(&a.hist[sort_key(a, g)], 1);
 }
 
-// Exclusive scan of ZBINS counters by one 1024-thread block, in place.
-__global__ __launch_bounds__(1024) void k_zscan(int *hist) {
+// Exclusive scan of SORT_BINS counters by one 1024-thread block, in place.
+__global__ __launch_bounds__(1024) void k_sort_scan(int *hist) {
+  constexpr int PER = SORT_BINS / 1024;
   __shared__ int part[1024];
   const int t = threadIdx.x;
-  const int a0 = hist[2 * t], a1 = hist[2 * t + 1];
-  part[t] = a0 + a1;
+  int v[PER], sum = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) { v[i] = hist[PER * t + i]; sum += v[i]; }
+  part[t] = sum;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    const int v = t >= off ? part[t - off] : 0;
+    const int u = t >= off ? part[t - off] : 0;
     __syncthreads();
-    part[t] += v;
+    part[t] += u;
     __syncthreads();
   }
-  const int excl = part[t] - (a0 + a1);
-  hist[2 * t] = excl;
-  hist[2 * t + 1] = excl + a0;
+  int run = part[t] - sum;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) { hist[PER * t + i] = run; run += v[i]; }
 }
 
-__global__ void k_zscatter(const float *__restrict__ z, int n, int *cursor, int *perm) {
+__global__ void k_sort_scatter(SortLaunch a) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < n) perm[atomicAdd(&cursor[zbin(z[g])], 1)] = g;
+  if (g < a.n_gal) a.perm[atomicAdd(&a.hist[sort_key(a, g)], 1)] = g;
 }
 
-int launch_zsort(const float *z, int n_gal, int *hist, int *perm, hipStream_t stream) {
-  static_assert(ZBINS == 2048, "k_zscan assumes 2048 bins");
-  if (n_gal <= 0) return DSPS_OK;
+int launch_sort(const SortLaunch &a, hipStream_t stream) {
+  static_assert(SORT_BINS % 1024 == 0 && SORT_BINS >= (32 << 8), "key range");
+  if (a.n_gal <= 0) return DSPS_OK;
   ProfScope prof(DSPS_KERNEL_ZSORT, stream);
-  hipLaunchKernelGGL(k_fill_int, dim3(ZBINS / 256), dim3(256), 0, stream, hist, ZBINS, 0);
-  const int blocks = (n_gal + 255) / 256;
-  hipLaunchKernelGGL(k_zhist, dim3(blocks), dim3(256), 0, stream, z, n_gal, hist);
-  hipLaunchKernelGGL(k_zscan, dim3(1), dim3(1024), 0, stream, hist);
-  hipLaunchKernelGGL(k_zscatter, dim3(blocks), dim3(256), 0, stream, z, n_gal, hist, perm);
-  return hip_fail(hipGetLastError(), "z sort launch");
+  hipLaunchKernelGGL(k_fill_int, dim3(SORT_BINS / 256), dim3(256), 0, stream, a.hist, SORT_BINS, 0);
+  const int blocks = (a.n_gal + 255) / 256;
+  hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, stream, a.hist);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(blocks), dim3(256), 0, stream, a);
+  return hip_fail(hipGetLastError(), "ordering sort launch");
 }
 
 // ------------------------------------------------------------ BF16 quantiser

@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 METRIC = "galaxies/sec 6-band mags, fwd & fwd+grad, plain FP32 vs BF16; p50/p99 latency"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}     # MI355X dense MFMA
 HBM_PEAK_GBS = 8000.0
+CALIBRATION_BYTES = 512 << 20
 GEMM_SOURCES = ("paper_2112_06830_amd/csrc/k_mags.hip", "paper_2112_06830_amd/csrc/gemm_core.hpp",
                 "paper_2112_06830_amd/csrc/dsps_internal.hpp")
 
@@ -245,7 +246,26 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the BF16 1e6, forward+gradient and serving legs")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="short FP32 run plus a calibration copy, for rocprofv3 --pmc")
     args = ap.parse_args()
+
+    if args.pmc_pass:
+        # A short run for hardware-counter collection: the FP32 workload for a
+        # few steps, then a device copy of known size whose FETCH_SIZE and
+        # WRITE_SIZE calibrate the counters (bytes read = bytes written =
+        # CALIBRATION_BYTES).
+        import torch
+        import paper_2112_06830_amd as P
+        run_workload(P, "fwd_fp32_1e5", 100_000, 100, "fp32", 3, 1, seed=3, want_roofline=False)
+        n = CALIBRATION_BYTES // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"pmc pass done; calibration copy of {CALIBRATION_BYTES} bytes")
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

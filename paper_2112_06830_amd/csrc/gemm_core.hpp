@@ -13,6 +13,9 @@ namespace dsps {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// Native 16-byte vector for staging (HIP's uint4 is a struct wrapper that the
+// optimiser does not always keep in registers).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct GemmCfg;
 template <> struct GemmCfg<DSPS_FP32> {
@@ -41,8 +44,8 @@ struct StageRegs {
   using C = GemmCfg<PREC>;
   static constexpr int VPR = C::KT * (int)sizeof(typename C::elem) / 16;  // vectors per row
   static constexpr int NV = TILE_L * VPR / GEMM_THREADS;                  // vectors per thread
-  uint4 a[NV];
-  uint4 b[NV];
+  u32x4 a[NV];
+  u32x4 b[NV];
 };
 
 template <int PREC>
@@ -55,11 +58,11 @@ __device__ __forceinline__ void load_stage(StageRegs<PREC> &r, const typename Ge
   for (int v = 0; v < S::NV; ++v) {
     const int idx = threadIdx.x + v * GEMM_THREADS;
     const int row = idx / S::VPR, col = idx % S::VPR;
-    r.a[v] = *reinterpret_cast<const uint4 *>(st + (size_t)(l0 + row) * k_pad + kofs + col * EPV);
+    r.a[v] = *reinterpret_cast<const u32x4 *>(st + (size_t)(l0 + row) * k_pad + kofs + col * EPV);
+    u32x4 bv = {0u, 0u, 0u, 0u};
     if (g0 + row < g_count)
-      r.b[v] = *reinterpret_cast<const uint4 *>(w + (size_t)(g0 + row) * k_pad + kofs + col * EPV);
-    else
-      r.b[v] = make_uint4(0u, 0u, 0u, 0u);
+      bv = *reinterpret_cast<const u32x4 *>(w + (size_t)(g0 + row) * k_pad + kofs + col * EPV);
+    r.b[v] = bv;
   }
 }
 
@@ -72,8 +75,8 @@ __device__ __forceinline__ void store_stage(const StageRegs<PREC> &r, GemmSmem<P
   for (int v = 0; v < S::NV; ++v) {
     const int idx = threadIdx.x + v * GEMM_THREADS;
     const int row = idx / S::VPR, col = idx % S::VPR;
-    *reinterpret_cast<uint4 *>(&sm.a[row * C::PITCH + col * EPV]) = r.a[v];
-    *reinterpret_cast<uint4 *>(&sm.b[row * C::PITCH + col * EPV]) = r.b[v];
+    *reinterpret_cast<u32x4 *>(&sm.a[row * C::PITCH + col * EPV]) = r.a[v];
+    *reinterpret_cast<u32x4 *>(&sm.b[row * C::PITCH + col * EPV]) = r.b[v];
   }
 }
 

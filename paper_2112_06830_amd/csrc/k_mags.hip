@@ -46,13 +46,21 @@ __device__ __forceinline__ void write_chunk_partial(float (&num)[2][DSPS_MAX_BAN
       num[nb][b] += __shfl_xor(num[nb][b], 32, 64);
       den[nb][b] += __shfl_xor(den[nb][b], 32, 64);
     }
-  const int col = h * 32 + (lane & 31);       // lane half h finishes column block nb = h
+  // Lane half h finishes column block nb = h.  Every array index below is a
+  // compile-time constant (a runtime-selected index would move the
+  // accumulators to scratch memory).
+  const int col = h * 32 + (lane & 31);
   float *red = s_red + (wc * 64 + col) * (2 * DSPS_MAX_BAND);
   if (wr == 1) {
 #pragma unroll
-    for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-      red[b] = h ? num[1][b] : num[0][b];
-      red[DSPS_MAX_BAND + b] = h ? den[1][b] : den[0][b];
+    for (int nb = 0; nb < 2; ++nb) {
+      if (h == nb) {
+#pragma unroll
+        for (int b = 0; b < DSPS_MAX_BAND; ++b) {
+          red[b] = num[nb][b];
+          red[DSPS_MAX_BAND + b] = den[nb][b];
+        }
+      }
     }
   }
   __syncthreads();
@@ -61,10 +69,15 @@ __device__ __forceinline__ void write_chunk_partial(float (&num)[2][DSPS_MAX_BAN
     if (tcol < nvalid) {
       float *out = out_base + (size_t)tcol * stride;
 #pragma unroll
-      for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-        if (b < n_band) {
-          out[b] = (h ? num[1][b] : num[0][b]) + red[b];
-          out[n_band + b] = (h ? den[1][b] : den[0][b]) + red[DSPS_MAX_BAND + b];
+      for (int nb = 0; nb < 2; ++nb) {
+        if (h == nb) {
+#pragma unroll
+          for (int b = 0; b < DSPS_MAX_BAND; ++b) {
+            if (b < n_band) {
+              out[b] = num[nb][b] + red[b];
+              out[n_band + b] = den[nb][b] + red[DSPS_MAX_BAND + b];
+            }
+          }
         }
       }
     }
@@ -90,8 +103,8 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
   const int wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1;
   const int h = lane >> 5;
-  const SspView &P = a.ssp;
-  const FilterView &F = a.flt;
+  const SspView P = a.ssp;        // by value: a reference into the kernel
+  const FilterView F = a.flt;     // argument would force a private-memory copy
   const int n_band = F.n_band, n_pts = F.n_pts;
   const int g0 = tile * TILE_G;                 // first batch-local galaxy of the tile
   const int nvalid = min(TILE_G, a.s_count - g0);

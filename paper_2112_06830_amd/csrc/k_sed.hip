@@ -13,7 +13,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   const int chunk = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
-  const SspView &P = a.ssp;
+  const SspView P = a.ssp;
   const int l0 = chunk * TILE_L;
   const int g0 = tile * TILE_G;
   const elem *st = PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16;

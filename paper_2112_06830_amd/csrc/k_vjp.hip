@@ -44,13 +44,15 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_gemm(VjpLaunch a) {
   __shared__ float s_q[TILE_L];
   __shared__ float s_filt[DSPS_MAX_FILTER_FLOATS];
   __shared__ float s_red[2][64][3];
+  __shared__ float s_gam[TILE_G * DSPS_MAX_BAND];
+  __shared__ float2 s_grid[DSPS_MAX_BAND];
   __shared__ int s_tile[4];
 
   const int group = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
-  const SspView &P = a.ssp;
-  const FilterView &F = a.flt;
+  const SspView P = a.ssp;
+  const FilterView F = a.flt;
   const int n_band = F.n_band, n_pts = F.n_pts;
   const int g0 = tile * TILE_G;
   const int nvalid = min(TILE_G, a.s_count - g0);
@@ -85,27 +87,26 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_gemm(VjpLaunch a) {
   }
   for (int i = threadIdx.x; i < n_band * n_pts; i += GEMM_THREADS) s_filt[i] = F.trans[i];
 
-  float zp1[2], da[2], dl[2], bp[2], gam[2][DSPS_MAX_BAND];
+  // The band loop of this epilogue produces one scalar per element, so it
+  // stays rolled: per-galaxy gamma and the filter grids are read from LDS
+  // with a runtime band index (an unrolled 8-band loop over 64 elements per
+  // lane exhausts the register file).
+  for (int i = threadIdx.x; i < TILE_G * n_band; i += GEMM_THREADS) {
+    const int col = i / n_band, b = i % n_band;
+    s_gam[col * DSPS_MAX_BAND + b] =
+        col < nvalid ? a.gamma[(size_t)(a.s_begin + g0 + col) * n_band + b] : 0.0f;
+  }
+  if (threadIdx.x < n_band) s_grid[threadIdx.x] = F.grid[threadIdx.x];
+  float zp1[2], da[2], dl[2], bp[2];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const int col = wc * 64 + nb * 32 + (lane & 31);
-    const bool ok = col < nvalid;
-    const int s = a.s_begin + g0 + col;
-    if (ok) {
-      const GalaxyMeta m = a.meta[s];
+    if (col < nvalid) {
+      const GalaxyMeta m = a.meta[a.s_begin + g0 + col];
       zp1[nb] = m.zp1; da[nb] = m.dust_a; dl[nb] = m.delta; bp[nb] = m.bump;
     } else {
       zp1[nb] = 1.0f; da[nb] = 0.0f; dl[nb] = 0.0f; bp[nb] = 0.0f;
     }
-#pragma unroll
-    for (int b = 0; b < DSPS_MAX_BAND; ++b)
-      gam[nb][b] = (ok && b < n_band) ? a.gamma[(size_t)s * n_band + b] : 0.0f;
-  }
-  float fw0[DSPS_MAX_BAND], finv[DSPS_MAX_BAND];
-#pragma unroll
-  for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-    if (b < n_band) { const float2 gr = F.grid[b]; fw0[b] = gr.x; finv[b] = gr.y; }
-    else { fw0[b] = 0.0f; finv[b] = 0.0f; }
   }
   float s_k[2] = {0.0f, 0.0f}, s_pw[2] = {0.0f, 0.0f}, s_d[2] = {0.0f, 0.0f};
 
@@ -148,41 +149,62 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_gemm(VjpLaunch a) {
     }
     __syncthreads();
 
+    // rows outer, galaxies inner: each row's constants are used once and die
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-      const int col = wc * 64 + nb * 32 + (lane & 31);
-      float *lb = a.lbar + (size_t)(g0 + col) * nwp + l0;
+    for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
+      for (int r4 = 0; r4 < 4; ++r4) {
+        float out4[2][4];
 #pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          float out4[4];
+        for (int r1 = 0; r1 < 4; ++r1) {
+          const int r = 4 * r4 + r1;
+          const int row = wr * 64 + mb * 32 + 8 * r4 + 4 * h + r1;
+          const float4 lc = s_lc[row];
+          const float q = s_q[row];
 #pragma unroll
-          for (int r1 = 0; r1 < 4; ++r1) {
-            const int r = 4 * r4 + r1;
-            const int row = wr * 64 + mb * 32 + 8 * r4 + 4 * h + r1;
-            const float4 lc = s_lc[row];
-            const float q = s_q[row];
+          for (int nb = 0; nb < 2; ++nb) {
+            const int col = wc * 64 + nb * 32 + (lane & 31);
             const float powl = exp2f(dl[nb] * lc.y);
             const float kl = lc.z * powl + bp[nb] * lc.w;      // k_lambda
             const float att = exp2f(da[nb] * kl);
             const float lobs = zp1[nb] * lc.x;
+            const float *gcol = s_gam + col * DSPS_MAX_BAND;
             float gsum = 0.0f;
-#pragma unroll
-            for (int b = 0; b < DSPS_MAX_BAND; ++b)
-              if (b < n_band)
-                gsum += gam[nb][b] * filter_at(s_filt + b * n_pts, n_pts, (lobs - fw0[b]) * finv[b]);
+#pragma unroll 1
+            for (int b = 0; b < n_band; ++b) {
+              const float2 gr = s_grid[b];
+              gsum += gcol[b] * filter_at(s_filt + b * n_pts, n_pts, (lobs - gr.x) * gr.y);
+            }
             gsum *= q;
-            const float e = gsum * att * acc[mb][nb][r];       // G L F
-            s_k[nb] += e * kl;
-            s_pw[nb] += e * lc.z * powl * lc.y;
-            s_d[nb] += e * lc.w;
-            out4[r1] = gsum * att;
+            acc[mb][nb][r] *= gsum * att;                      // e = G F L
+            out4[nb][r1] = gsum * att;
           }
-          if (col < nvalid) {
-            const int row0 = wr * 64 + mb * 32 + 8 * r4 + 4 * h;
-            *reinterpret_cast<float4 *>(lb + row0) = make_float4(out4[0], out4[1], out4[2], out4[3]);
-          }
+        }
+        const int row0 = wr * 64 + mb * 32 + 8 * r4 + 4 * h;
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const int col = wc * 64 + nb * 32 + (lane & 31);
+          if (col < nvalid)
+            *reinterpret_cast<float4 *>(a.lbar + (size_t)(g0 + col) * nwp + l0 + row0) =
+                make_float4(out4[nb][0], out4[nb][1], out4[nb][2], out4[nb][3]);
+        }
+      }
+    }
+    // second pass: dust-gradient sums over e = G F L (the per-row factors are
+    // recomputed; holding them from the first pass exhausts the registers)
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const float4 lc = s_lc[row];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const float e = acc[mb][nb][r];
+          const float k0x = lc.z * exp2f(dl[nb] * lc.y);    // k0 (lambda/5500)^delta
+          s_k[nb] += e * (k0x + bp[nb] * lc.w);
+          s_pw[nb] += e * k0x * lc.y;
+          s_d[nb] += e * lc.w;
         }
       }
     }
@@ -222,7 +244,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   const int kblk = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
-  const SspView &P = a.ssp;
+  const SspView P = a.ssp;
   const int g0 = tile * TILE_G;
   const int nvalid = min(TILE_G, a.s_count - g0);
   const int nwp = P.n_wave_pad;
@@ -332,7 +354,7 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   if (local >= a.s_count) return;
   const int s = a.s_begin + local;
   const int g = a.perm[s];
-  const SspView &P = a.ssp;
+  const SspView P = a.ssp;
   const int n_age = P.n_age, n_met = P.n_met;
   const double z = (double)a.z[g];
   const double t_obs = vjp_age_at_z(z, a.cosmo, a.gl, lane);

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   if (local >= a.s_count) return;   // whole wave leaves; no block barrier follows
   const int s = a.s_begin + local;
   const int g = a.perm ? a.perm[s] : s;
-  const SspView &P = a.ssp;
+  const SspView P = a.ssp;
   const int n_age = P.n_age, n_met = P.n_met;
 
   const double z = (double)a.z[g];

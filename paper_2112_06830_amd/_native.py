@@ -83,8 +83,24 @@ def _declare(lib):
         fn.argtypes = args
 
 
+def _hip_runtimes() -> set:
+    """Distinct HIP runtime libraries mapped into this process (Linux)."""
+    try:
+        with open("/proc/self/maps") as f:
+            return {ln.split()[-1] for ln in f if "libamdhip64" in ln and "/" in ln}
+    except OSError:
+        return set()
+
+
 def load(path: str | None = None):
-    """Load libdsps.so (once).  Raises if the library is missing."""
+    """Load libdsps.so (once).  Raises if the library is missing.
+
+    The library must bind to the HIP runtime that PyTorch already uses: the
+    binding hands it PyTorch's device pointers and stream handles, which only
+    that runtime instance understands.  torch is therefore imported first, so
+    that the library's libamdhip64.so.7 dependency resolves to the copy torch
+    has loaded; a second runtime in the process is refused.
+    """
     global _LIB
     if _LIB is not None and path is None:
         return _LIB
@@ -93,7 +109,13 @@ def load(path: str | None = None):
         raise ImportError(
             f"libdsps.so not found at {p}; build it with "
             "`python -m paper_2112_06830_amd.build` (hipcc, gfx950). There is no fallback.")
+    import torch  # noqa: F401  (loads torch's HIP runtime before ours binds)
     lib = ctypes.CDLL(p, mode=ctypes.RTLD_LOCAL)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise ImportError(
+            "two HIP runtimes are loaded in this process (" + ", ".join(sorted(runtimes)) + "); "
+            "libdsps must share torch's. Import torch before any other HIP library.")
     _declare(lib)
     if path is None:
         _LIB = lib

@@ -27,6 +27,15 @@ int hip_fail(hipError_t e, const char *what) {
   return DSPS_ERR_DEVICE;
 }
 
+// hipMalloc that reports the runtime's reason on failure.
+static int hip_alloc(void **p, size_t bytes, const char *what) {
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) return DSPS_OK;
+  *p = nullptr;
+  set_error("hipMalloc of %zu bytes for %s failed: %s", bytes, what, hipGetErrorString(e));
+  return DSPS_ERR_ALLOC;
+}
+
 #define DSPS_CHECK(cond, code, ...) \
   do {                              \
     if (!(cond)) {                  \
@@ -202,10 +211,7 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   const size_t o_lc = take(sizeof(float4) * nwp);
   const size_t o_q = take(sizeof(float) * nwp);
   void *base = nullptr;
-  if (hipMalloc(&base, off) != hipSuccess) {
-    set_error("hipMalloc of %zu bytes for the SSP block failed", off);
-    return DSPS_ERR_ALLOC;
-  }
+  if (int e = hip_alloc(&base, off, "the SSP block")) return e;
   char *b = (char *)base;
   float *d_rows = nullptr;
   uint16_t *d_q = nullptr;
@@ -230,15 +236,15 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
     rc = hip_fail(hipMemcpy(b + o_q, qw.data(), sizeof(float) * nwp, hipMemcpyHostToDevice), "upload qweight");
     if (rc) break;
     const int rows = n_met * n_age;
-    if (hipMalloc((void **)&d_rows, sizeof(float) * n_lum) != hipSuccess) { rc = DSPS_ERR_ALLOC; set_error("hipMalloc staging"); break; }
+    rc = hip_alloc((void **)&d_rows, sizeof(float) * n_lum, "SSP staging");
+    if (rc) break;
     rc = hip_fail(hipMemcpy(d_rows, lum, sizeof(float) * n_lum, hipMemcpyHostToDevice), "upload lum");
     if (rc) break;
     std::vector<float> kscale(kp, 1.0f);
     if (want16) {
-      if (hipMalloc((void **)&d_q, sizeof(uint16_t) * n_lum) != hipSuccess ||
-          hipMalloc((void **)&d_scale, sizeof(float) * rows) != hipSuccess) {
-        rc = DSPS_ERR_ALLOC; set_error("hipMalloc staging"); break;
-      }
+      rc = hip_alloc((void **)&d_q, sizeof(uint16_t) * n_lum, "BF16 staging");
+      if (!rc) rc = hip_alloc((void **)&d_scale, sizeof(float) * rows, "BF16 row scales");
+      if (rc) break;
       rc = launch_quantize_bf16(d_rows, rows, n_wave, d_q, d_scale, nullptr);
       if (rc) break;
       std::vector<float> scale(rows);
@@ -333,7 +339,7 @@ int dsps_filters_create(int n_band, int n_pts, const double *wave, const double 
   const size_t o_tr = off; off += align256(sizeof(float) * tr.size());
   const size_t o_gr = off; off += align256(sizeof(float2) * n_band);
   void *base = nullptr;
-  if (hipMalloc(&base, off) != hipSuccess) { set_error("hipMalloc filters"); return DSPS_ERR_ALLOC; }
+  if (int e = hip_alloc(&base, off, "the filter bank")) return e;
   char *b = (char *)base;
   int rc = hip_fail(hipMemcpy(b + o_tr, tr.data(), sizeof(float) * tr.size(), hipMemcpyHostToDevice), "upload filters");
   if (!rc) rc = hip_fail(hipMemcpy(b + o_gr, grid.data(), sizeof(float2) * n_band, hipMemcpyHostToDevice), "upload grids");

@@ -32,33 +32,42 @@ __device__ __forceinline__ void xcd_tile_group(int b, int groups, int &tile, int
   group = slot % groups;
 }
 
-// Per-galaxy sums of one chunk, reduced over the two lane halves and the two
-// row-waves of each column block, written to the chunk's partial slot.
-__device__ __forceinline__ void write_chunk_partial(float (&num)[2][DSPS_MAX_BAND],
-                                                   float (&den)[2][DSPS_MAX_BAND], int n_band,
-                                                   float *s_red, int wr, int wc, int lane,
-                                                   int nvalid, float *out_base, int stride) {
+// Band slots evaluated together in one epilogue pass.
+constexpr int NSLOT = 3;
+// Rows of the accumulator whose filter lookups are scheduled together.
+constexpr int EPI_ROWS = 2;
+
+// Per-galaxy sums of one chunk for bands base .. base + NSLOT - 1 (those not
+// above b_hi), reduced over the two lane halves and the two row-waves of each
+// column block, written to the chunk's partial slot.  s_red aliases the
+// operand staging area: the leading barrier orders these writes after every
+// wave's last MFMA read and after the previous pass's reads.
+__device__ __forceinline__ void write_band_slots(float (&num)[2][NSLOT], float (&den)[2][NSLOT],
+                                                 int base, int b_hi, int n_band, float *s_red,
+                                                 int wr, int wc, int lane, int nvalid,
+                                                 float *out_base, int stride) {
   const int h = lane >> 5;
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-    for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-      num[nb][b] += __shfl_xor(num[nb][b], 32, 64);
-      den[nb][b] += __shfl_xor(den[nb][b], 32, 64);
+    for (int k = 0; k < NSLOT; ++k) {
+      num[nb][k] += __shfl_xor(num[nb][k], 32, 64);
+      den[nb][k] += __shfl_xor(den[nb][k], 32, 64);
     }
   // Lane half h finishes column block nb = h.  Every array index below is a
   // compile-time constant (a runtime-selected index would move the
   // accumulators to scratch memory).
   const int col = h * 32 + (lane & 31);
-  float *red = s_red + (wc * 64 + col) * (2 * DSPS_MAX_BAND);
+  float *red = s_red + (wc * 64 + col) * (2 * NSLOT);
+  __syncthreads();
   if (wr == 1) {
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
       if (h == nb) {
 #pragma unroll
-        for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-          red[b] = num[nb][b];
-          red[DSPS_MAX_BAND + b] = den[nb][b];
+        for (int k = 0; k < NSLOT; ++k) {
+          red[k] = num[nb][k];
+          red[NSLOT + k] = den[nb][k];
         }
       }
     }
@@ -72,10 +81,10 @@ __device__ __forceinline__ void write_chunk_partial(float (&num)[2][DSPS_MAX_BAN
       for (int nb = 0; nb < 2; ++nb) {
         if (h == nb) {
 #pragma unroll
-          for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-            if (b < n_band) {
-              out[b] = num[nb][b] + red[b];
-              out[n_band + b] = den[nb][b] + red[DSPS_MAX_BAND + b];
+          for (int k = 0; k < NSLOT; ++k) {
+            if (base + k <= b_hi) {
+              out[base + k] = num[nb][k] + red[k];
+              out[n_band + base + k] = den[nb][k] + red[NSLOT + k];
             }
           }
         }
@@ -84,16 +93,36 @@ __device__ __forceinline__ void write_chunk_partial(float (&num)[2][DSPS_MAX_BAN
   }
 }
 
+// Bands whose support meets the observed wavelengths [o_lo, o_hi] (with a
+// relative margin far above float rounding): any band left out has zero
+// transmission for every element of the chunk, so skipping it is exact.
+__device__ __forceinline__ unsigned active_bands(const FilterView &F, float o_lo, float o_hi) {
+  unsigned m = 0;
+  for (int b = 0; b < F.n_band; ++b) {
+    const float2 gr = F.grid[b];
+    const float lo = gr.x, hi = gr.x + (float)(F.n_pts - 1) / gr.y;
+    if (o_hi * 1.0001f >= lo && o_lo * 0.9999f <= hi) m |= 1u << b;
+  }
+  return m;
+}
+
+// The cross-wave reduction buffer of the epilogue reuses the operand staging
+// area, which is idle by then.
 template <int PREC>
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
   using C = GemmCfg<PREC>;
   using elem = typename C::elem;
+  static_assert(sizeof(GemmSmem<PREC>) >= sizeof(float) * 2 * 64 * 2 * DSPS_MAX_BAND, "reduction alias");
   __shared__ GemmSmem<PREC> sm;
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
-  __shared__ float s_red[2 * 64 * 2 * DSPS_MAX_BAND];
-  __shared__ int s_tile[4];   // window lo, window hi, metallicity-row mask, age hi
-  extern __shared__ float s_filt[];   // [n_band * n_pts]
+  // window lo, window hi, metallicity-row mask, age hi, min and max of (1+z)
+  // as float bits (positive floats order like their bit patterns)
+  __shared__ int s_tile[6];
+  // transmission as (T[i], T[i+1] - T[i]) per grid interval: one aligned
+  // 8-byte read and one FMA per interpolation
+  extern __shared__ float2 s_pair[];   // [n_band][n_pts - 1]
+  float *s_red = reinterpret_cast<float *>(&sm);
 
   int tile, group;
   xcd_tile_group(blockIdx.x, a.n_groups, tile, group);
@@ -110,12 +139,18 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
   const int nvalid = min(TILE_G, a.s_count - g0);
 
   // ---- tile union of windows and non-zero weight blocks
-  if (threadIdx.x == 0) { s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0; s_tile[3] = 0; }
+  if (threadIdx.x == 0) {
+    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0; s_tile[3] = 0;
+    s_tile[4] = 0x7f7fffff; s_tile[5] = 0;
+  }
   __syncthreads();
   if (threadIdx.x < nvalid) {
     const GalaxyRange r = a.range[a.s_begin + g0 + threadIdx.x];
+    const int zbits = __float_as_int(a.meta[a.s_begin + g0 + threadIdx.x].zp1);
     atomicMin(&s_tile[0], r.win_lo);
     atomicMax(&s_tile[1], r.win_hi);
+    atomicMin(&s_tile[4], zbits);
+    atomicMax(&s_tile[5], zbits);
     if (r.age_hi > 0) {
       const int jl = r.met_lo_hi & 0xFFFF, jh = r.met_lo_hi >> 16;
       atomicOr(&s_tile[2], (int)(((1u << (jh + 1)) - 1u) & ~((1u << jl) - 1u)));
@@ -126,6 +161,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
   const int win_lo = s_tile[0], win_hi = s_tile[1];
   const unsigned met_mask = (unsigned)s_tile[2];
   const int age_hi = s_tile[3];
+  const float zp1_min = __int_as_float(s_tile[4]), zp1_max = __int_as_float(s_tile[5]);
   const int c_first = win_lo / TILE_L;
   const int c_last = max((win_hi + TILE_L - 1) / TILE_L, c_first);   // exclusive
   if (group == 0 && threadIdx.x == 0) a.tile_chunks[tile] = make_int2(c_first, c_last);
@@ -134,8 +170,13 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
   const int c_end = min(c_begin + CHUNKS_PER_GROUP, c_last);
   if (c_begin >= c_end) return;
 
-  // ---- filters into LDS
-  for (int i = threadIdx.x; i < n_band * n_pts; i += GEMM_THREADS) s_filt[i] = F.trans[i];
+  // ---- filter intervals into LDS
+  const int n_int = n_pts - 1;
+  for (int i = threadIdx.x; i < n_band * n_int; i += GEMM_THREADS) {
+    const int b = i / n_int, k = i - b * n_int;
+    const float t0 = F.trans[b * n_pts + k], t1 = F.trans[b * n_pts + k + 1];
+    s_pair[i] = make_float2(t0, t1 - t0);
+  }
 
   // ---- per-galaxy parameters of this lane's two columns
   float zp1[2], da[2], dl[2], bp[2];
@@ -148,12 +189,6 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
     } else {
       zp1[nb] = 1.0f; da[nb] = 0.0f; dl[nb] = 0.0f; bp[nb] = 0.0f;
     }
-  }
-  float fw0[DSPS_MAX_BAND], finv[DSPS_MAX_BAND];
-#pragma unroll
-  for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-    if (b < n_band) { const float2 gr = F.grid[b]; fw0[b] = gr.x; finv[b] = gr.y; }
-    else { fw0[b] = 0.0f; finv[b] = 0.0f; }
   }
 
   // ---- K steps: metallicity rows in met_mask x age blocks below age_hi
@@ -196,40 +231,84 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
       }
       mma_stage(sm, wr, wc, lane, acc);
     }
-    __syncthreads();   // s_lc / s_q / filters visible
+    __syncthreads();   // s_lc / s_q / filter intervals visible
 
-    // ---- epilogue: attenuation x resampled transmission, lane-local sums
-    float num[2][DSPS_MAX_BAND], den[2][DSPS_MAX_BAND];
+    // ---- epilogue: attenuated SED x resampled transmission, summed over the
+    // bands that can see this chunk
+    // (wavelengths of the chunk are non-decreasing; padding repeats the last)
+    const unsigned bmask = __builtin_amdgcn_readfirstlane(
+        active_bands(F, zp1_min * s_lc[0].x, zp1_max * s_lc[TILE_L - 1].x));
+    const int b_lo = bmask ? __builtin_ctz(bmask) : 0;
+    const int b_hi = bmask ? 31 - __builtin_clz(bmask) : -1;   // inclusive
+    float *part = part_tile + (size_t)c * n_comp;
+    const int stride = a.n_chunks * n_comp;
+    for (int base = b_lo; base <= b_hi; base += NSLOT) {
+      const float2 *tab[NSLOT];
+      float w0[NSLOT], wi[NSLOT];
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+      for (int k = 0; k < NSLOT; ++k) {
+        const int b = min(base + k, n_band - 1);   // slots past b_hi are computed, not stored
+        const float2 gr = F.grid[b];
+        tab[k] = s_pair + b * n_int;
+        w0[k] = gr.x;
+        wi[k] = gr.y;
+      }
+      float num[2][NSLOT], den[2][NSLOT];
 #pragma unroll
-      for (int b = 0; b < DSPS_MAX_BAND; ++b) { num[nb][b] = 0.0f; den[nb][b] = 0.0f; }
+      for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
+        for (int k = 0; k < NSLOT; ++k) { num[nb][k] = 0.0f; den[nb][k] = 0.0f; }
+      const float umax = (float)n_int;
+      // An offset the compiler cannot see through keeps the per-row LDS reads
+      // below inside the pass (hoisted out of it they would pin 64 registers).
+      int zero;
+      asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+      const float4 *lcp = s_lc + zero;
+      const float *qp = s_q + zero;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        const float4 lc = s_lc[row];   // (lambda, log2(lambda/5500), k0, drude shape)
-        const float q = s_q[row];
+      for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          const float powl = exp2f(dl[nb] * lc.y);
-          const float att = exp2f(da[nb] * (lc.z * powl + bp[nb] * lc.w));
-          const float lq = acc[mb][nb][r] * att * q;
-          const float lobs = zp1[nb] * lc.x;
+        for (int r = 0; r < 16; ++r) {
+          const int row = wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+          const float4 lc = lcp[row];
+          const float lam = lc.x;
+          const float q = qp[row];
 #pragma unroll
-          for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-            if (b < n_band) {
-              const float t = filter_at(s_filt + b * n_pts, n_pts, (lobs - fw0[b]) * finv[b]);
-              num[nb][b] += t * lq;
-              den[nb][b] += t * q;
+          for (int nb = 0; nb < 2; ++nb) {
+            const float lobs = zp1[nb] * lam;
+            const float powl = exp2f(dl[nb] * lc.y);
+            const float att = exp2f(da[nb] * (lc.z * powl + bp[nb] * lc.w));
+            const float e = acc[mb][nb][r] * att * q;
+#pragma unroll
+            for (int k = 0; k < NSLOT; ++k) {
+              // linear interpolation on the uniform filter grid, zero outside
+              const float u = (lobs - w0[k]) * wi[k];
+              const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, umax);
+              const int i = min((int)uc, n_int - 1);
+              const float2 pr = tab[k][i];
+              float t = fmaf(uc - (float)i, pr.y, pr.x);
+              t = (u == uc) ? t : 0.0f;
+              num[nb][k] += t * e;
+              den[nb][k] += t * q;
             }
           }
+          // bound the scheduler's look-ahead: batching the lookups of a few
+          // rows hides LDS latency, batching all of them spills registers
+          if ((r & (EPI_ROWS - 1)) == EPI_ROWS - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      write_band_slots(num, den, base, b_hi, n_band, s_red, wr, wc, lane, nvalid, part, stride);
+    }
+    // bands that see none of this chunk contribute exact zeros
+    if (wr == 0) {
+      const int tcol = wc * 64 + h * 32 + (lane & 31);
+      if (tcol < nvalid) {
+        float *out = part + (size_t)tcol * stride;
+        for (int b = 0; b < n_band; ++b) {
+          if (b < b_lo || b > b_hi) { out[b] = 0.0f; out[n_band + b] = 0.0f; }
         }
       }
     }
-    write_chunk_partial(num, den, n_band, s_red, wr, wc, lane, nvalid,
-                        part_tile + (size_t)c * n_comp, a.n_chunks * n_comp);
   }
 }
 
@@ -237,7 +316,7 @@ int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
   const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
   const int blocks = (n_tiles + 7) / 8 * 8 * a.n_groups;
-  const size_t lds = sizeof(float) * a.flt.n_band * a.flt.n_pts;
+  const size_t lds = sizeof(float2) * a.flt.n_band * (a.flt.n_pts - 1);
   ProfScope prof(DSPS_KERNEL_MAGS_GEMM, stream);
   if (a.precision == DSPS_BF16)
     hipLaunchKernelGGL(k_mags_gemm<DSPS_BF16>, dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);

@@ -77,3 +77,17 @@ def test_host_side_argument_checks_fail_before_any_launch(lib):
     # zero-size requests are no-ops
     assert lib.dsps_sfh_table(None, 10, None, 0, None, None) == 0
     assert lib.dsps_quantize_bf16(None, 0, 5, None, None, None) == 0
+
+
+def test_library_binds_to_torch_hip_runtime():
+    """Importing the package first (before torch) must still leave a single
+    HIP runtime in the process: the library shares torch's."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2112_06830_amd as P\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l and '/' in l}\n"
+            "print(len(libs))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

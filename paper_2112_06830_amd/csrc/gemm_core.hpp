@@ -18,10 +18,14 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct GemmCfg;
+// K per LDS stage divides AGE_PAD.  Row pitches keep 16-byte alignment and
+// put the eight rows read by one 8-lane group of a 16-byte LDS read on
+// distinct bank quads.  The FP32 stage is kept short so that the fused kernel
+// fits three workgroups per CU in registers and LDS.
 template <> struct GemmCfg<DSPS_FP32> {
   using elem = float;
-  static constexpr int KT = 32;        // K per LDS stage (divides AGE_PAD)
-  static constexpr int PITCH = 36;     // elements per LDS row (16-byte aligned, conflict-free)
+  static constexpr int KT = 16;
+  static constexpr int PITCH = 20;
 };
 template <> struct GemmCfg<DSPS_BF16> {
   using elem = uint16_t;

@@ -106,10 +106,11 @@ __device__ __forceinline__ unsigned active_bands(const FilterView &F, float o_lo
   return m;
 }
 
-// The cross-wave reduction buffer of the epilogue reuses the operand staging
-// area, which is idle by then.
+// Three workgroups per CU (at most 168 VGPRs).  The cross-wave reduction
+// buffer of the epilogue reuses the operand staging area, which is idle by
+// then.
 template <int PREC>
-__global__ __launch_bounds__(GEMM_THREADS, 2) void k_mags_gemm(MagsLaunch a) {
+__global__ __launch_bounds__(GEMM_THREADS, 3) void k_mags_gemm(MagsLaunch a) {
   using C = GemmCfg<PREC>;
   using elem = typename C::elem;
   static_assert(sizeof(GemmSmem<PREC>) >= sizeof(float) * 2 * 64 * 2 * DSPS_MAX_BAND, "reduction alias");

@@ -2,10 +2,12 @@
 // age-dependent metallicity weights, plus the redshift ordering sort and the
 // preparation kernels of the resident SSP block.
 //
-// One wave64 owns one galaxy in the weights kernel: the SFR row is staged in
-// LDS with coalesced loads, the float64 cumulative trapezoid is a blocked wave
-// scan, lanes then split the age-bin edges and finally the (metallicity, age)
-// weights, which leave as coalesced rows in the GEMM's padded K layout.
+// One wave64 owns one galaxy in the weights kernel.  Lanes first locate the
+// age-bin edges on the time grid (block-shared in LDS), then stream the SFR
+// row in batches of coalesced loads while a float64 wave scan accumulates the
+// trapezoid round by round, picking up the mass at each edge on the fly;
+// finally lanes split the (metallicity, age) weights, which leave as
+// coalesced rows in the GEMM's padded K layout.
 #include "dsps_internal.hpp"
 
 #include <cmath>
@@ -77,144 +79,229 @@ __device__ double wave_distance_modulus(double z, const CosmoArgs &c, const Gaus
   return 5.0 * log10((1.0 + z) * dc) + 25.0;
 }
 
-// Mass formed up to cosmic time t: 0 at or before t_table[0], linear
-// interpolation of the cumulative nodes inside, the last node after.
-__device__ __forceinline__ double mass_formed(double t, const double *tt, const double *mc,
-                                              int n_t) {
-  if (!(t > tt[0])) return 0.0;
-  if (t >= tt[n_t - 1]) return mc[n_t - 1];
-  int lo = 0, hi = n_t - 1;  // tt[lo] <= t < tt[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (tt[mid] <= t) lo = mid; else hi = mid;
+// Lockstep 64-ary searches over an ascending array x: the first index in
+// [lo1, hi1) with x[i] >= v1 (hi1 if none) and the first in [lo2, hi2) with
+// x[i] > v2.  Each round every lane probes one element of each range, both
+// ranges shrink 64-fold, and the two probe loads overlap.
+__device__ void wave_search_pair(const double *x, double v1, double v2, int lane, int &lo1,
+                                 int hi1, int &lo2, int hi2) {
+  while (lo1 < hi1 || lo2 < hi2) {
+    const int st1 = (hi1 - lo1 + 63) / 64, st2 = (hi2 - lo2 + 63) / 64;
+    const int p1 = lo1 + lane * st1, p2 = lo2 + lane * st2;
+    const bool in1 = lo1 < hi1 && p1 < hi1, in2 = lo2 < hi2 && p2 < hi2;
+    const double x1 = in1 ? x[p1] : 0.0;
+    const double x2 = in2 ? x[p2] : 0.0;
+    // probes at or past the range end count as satisfying the predicate
+    const unsigned long long m1 = __ballot(!in1 || x1 >= v1), m2 = __ballot(!in2 || x2 > v2);
+    if (lo1 < hi1) {
+      const int f = m1 ? __ffsll(m1) - 1 : 64;
+      if (f == 0) hi1 = lo1;
+      else { const int nl = lo1 + (f - 1) * st1 + 1; hi1 = min(lo1 + f * st1, hi1); lo1 = nl; }
+    }
+    if (lo2 < hi2) {
+      const int f = m2 ? __ffsll(m2) - 1 : 64;
+      if (f == 0) hi2 = lo2;
+      else { const int nl = lo2 + (f - 1) * st2 + 1; hi2 = min(lo2 + f * st2, hi2); lo2 = nl; }
+    }
   }
-  const double f = (t - tt[lo]) / (tt[hi] - tt[lo]);
-  return mc[lo] + f * (mc[hi] - mc[lo]);
 }
 
-// First index i in [0, n) with x[i] >= v (x[i] > v when strict), or n:
-// a wave-cooperative 64-ary search over an ascending array (each round every
-// lane probes one element, then the range shrinks 64-fold).
-__device__ int wave_lower_bound(const double *x, int n, double v, bool strict, int lane) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int step = (hi - lo + 63) / 64;
-    const int p = lo + lane * step;
-    bool ge = true;                       // probes at or past hi count as true
-    if (p < hi) ge = strict ? (x[p] > v) : (x[p] >= v);
-    const unsigned long long mask = __ballot(ge);
-    const int f = mask ? __ffsll(mask) - 1 : 64;
-    if (f == 0) return lo;                // x[lo] already satisfies the predicate
-    const int new_lo = lo + (f - 1) * step + 1;
-    const int new_hi = min(lo + f * step, hi);
-    lo = new_lo;
-    hi = new_hi;
-  }
-  return lo;
+// Entries of the block-shared coarse wavelength table (every stride-th rest
+// wavelength): the window search brackets in LDS, then finishes in one or two
+// rounds over the global grid.
+constexpr int COARSE_WAVE = 256;
+
+__host__ __device__ inline int coarse_stride(int n_wave) {
+  return (n_wave + COARSE_WAVE - 1) / COARSE_WAVE;
 }
 
-// Orders LDS traffic between the lanes of one wave (no workgroup barrier:
-// waves of a block finish independently).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Time-grid rounds (of 64 nodes each) whose SFR values are loaded together.
+constexpr int SFR_BATCH = 8;
+
+// Block-shared LDS of the weights kernel, in doubles.
+__host__ __device__ inline size_t weights_lds_doubles(int n_t, int n_age, int n_met, int n_wave,
+                                                      int k_pad) {
+  const int n_coarse = (n_wave + coarse_stride(n_wave) - 1) / coarse_stride(n_wave);
+  return (size_t)n_t + (n_age + 1) + n_age + (n_met + 1) + n_coarse + (k_pad + 1) / 2;
 }
 
+// TABULATED: the SFR arrives as a table row per galaxy; otherwise it is
+// evaluated from the parametric history at the time-grid nodes.
+template <bool TABULATED>
 __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
+  const SspView P = a.ssp;
+  const int n_t = a.n_t, n_age = P.n_age, n_met = P.n_met;
+  const int stride = coarse_stride(P.n_wave);
+  const int n_coarse = (P.n_wave + stride - 1) / stride;
+  // block-shared: time grid, SSP grid constants, coarse wavelengths, row scales
   extern __shared__ double lds[];
-  const int n_t = a.n_t;
+  double *tt = lds;                                   // [n_t]
+  double *s_aedge = tt + n_t;                         // [n_age + 1]
+  double *s_lgage = s_aedge + n_age + 1;              // [n_age]
+  double *s_medge = s_lgage + n_age;                  // [n_met + 1]
+  double *s_cw = s_medge + n_met + 1;                 // [n_coarse]
+  float *s_ks = (float *)(s_cw + n_coarse);           // [k_pad]
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  double *tt = lds;                                   // [n_t]
-  double *wbase = lds + n_t + wave * (2 * n_t + 2 * AGE_PAD + 2);
-  double *sfr_s = wbase;                              // [n_t]
-  double *mc = wbase + n_t;                           // [n_t]
-  double *em = wbase + 2 * n_t;                       // [n_age + 1]
-  double *mage = em + AGE_PAD + 1;                    // [n_age]
-
   for (int n = threadIdx.x; n < n_t; n += blockDim.x) tt[n] = a.t_table[n];
+  for (int n = threadIdx.x; n <= n_age; n += blockDim.x) s_aedge[n] = P.age_edges[n];
+  for (int n = threadIdx.x; n < n_age; n += blockDim.x) s_lgage[n] = P.lg_age[n];
+  for (int n = threadIdx.x; n <= n_met; n += blockDim.x) s_medge[n] = P.met_edges[n];
+  for (int n = threadIdx.x; n < n_coarse; n += blockDim.x) s_cw[n] = P.wave[n * stride];
+  if (a.w_pad_bf16)
+    for (int n = threadIdx.x; n < P.k_pad; n += blockDim.x) s_ks[n] = P.kscale[n];
   __syncthreads();
 
   const int local = blockIdx.x * WEIGHT_WAVES + wave;
   if (local >= a.s_count) return;   // whole wave leaves; no block barrier follows
   const int s = a.s_begin + local;
   const int g = a.perm ? a.perm[s] : s;
-  const SspView P = a.ssp;
-  const int n_age = P.n_age, n_met = P.n_met;
 
+  // every per-galaxy load is issued before the first use of any of them
   const double z = (double)a.z[g];
+  const float lgmet_f = a.lgmet[g], sig_f = a.sigma_z[g];
+  const float av_f = a.av[g], delta_f = a.delta[g], bump_f = a.bump[g];
+  const double *row = TABULATED ? a.sfr + (size_t)g * n_t : nullptr;
+  double v[SFR_BATCH], v_next = 0.0;
+  if (TABULATED) {
+#pragma unroll
+    for (int r = 0; r < SFR_BATCH; ++r) {
+      const int n = 64 * r + lane;
+      v[r] = n < n_t ? row[n] : 0.0;
+    }
+    if (64 * SFR_BATCH < n_t) v_next = row[64 * SFR_BATCH];
+  }
+
   const double t_obs = wave_age_at_z(z, a.cosmo, a.gl, lane);
 
-  // ---- SFR row -> LDS (coalesced), then segments of the trapezoid.
-  if (a.sfr) {
-    const double *row = a.sfr + (size_t)g * n_t;
-    for (int n = lane; n < n_t; n += 64) sfr_s[n] = row[n];
-  } else {
-    const double pa = a.sfh_params[g], ptau = a.sfh_params[a.n_gal + g];
-    const double palpha = a.sfh_params[2 * a.n_gal + g], pq = a.sfh_params[3 * a.n_gal + g];
-    const double ptq = a.sfh_params[4 * a.n_gal + g];
-    for (int n = lane; n < n_t; n += 64) sfr_s[n] = sfr_param(tt[n], pa, ptau, palpha, pq, ptq);
-  }
-  wave_sync();
-  if (lane == 0) mc[0] = 0.0;
-  for (int m = lane; m < n_t - 1; m += 64)
-    mc[m + 1] = 0.5 * (sfr_s[m] + sfr_s[m + 1]) * (tt[m + 1] - tt[m]) * YEARS_PER_GYR;
-  wave_sync();
-
-  // ---- blocked inclusive scan of mc[1..n_t-1] (lane owns a contiguous block).
+  // ---- age-bin edges: lane owns edges e = lane and lane + 64.  The mass
+  // formed by cosmic time t is 0 at or before t_table[0], the total after the
+  // last node, and otherwise the cumulative trapezoid at node lo plus the
+  // fraction f of segment lo, where t_table[lo] <= t < t_table[lo + 1].
+  int kind[2], lo[2];            // kind: 0 none formed, 1 inside the grid, 2 all formed
+  double fe[2];
   {
-    const int len = n_t - 1;
-    const int per = (len + 63) / 64;
-    const int b0 = 1 + lane * per;
-    const int b1 = min(1 + (lane + 1) * per, n_t);
-    double run = 0.0;
-    for (int n = b0; n < b1; ++n) run += mc[n];
-    // exclusive prefix of the lane totals
-    double incl = run;
+    double te[2];
+    int hi[2];
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const double up = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += up;
+    for (int q = 0; q < 2; ++q) {
+      const int e = lane + 64 * q;
+      te[q] = e <= n_age ? t_obs - s_aedge[e] : -1.0 / 0.0;
+      kind[q] = !(te[q] > tt[0]) ? 0 : (te[q] >= tt[n_t - 1] ? 2 : 1);
+      lo[q] = 0;
+      hi[q] = n_t - 1;
     }
-    double acc = incl - run;
-    for (int n = b0; n < b1; ++n) { acc += mc[n]; mc[n] = acc; }
+    // bisection of both edges together (tt[lo] <= t < tt[hi] for kind 1)
+    while (hi[0] - lo[0] > 1 || hi[1] - lo[1] > 1) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (hi[q] - lo[q] > 1) {
+          const int mid = (lo[q] + hi[q]) >> 1;
+          if (tt[mid] <= te[q]) lo[q] = mid; else hi[q] = mid;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      fe[q] = kind[q] == 1 ? (te[q] - tt[lo[q]]) / (tt[lo[q] + 1] - tt[lo[q]]) : 0.0;
   }
-  wave_sync();
 
-  // ---- mass formed at the age-bin edges, bin masses (float64 differences).
-  for (int e = lane; e <= n_age; e += 64)
-    em[e] = mass_formed(t_obs - P.age_edges[e], tt, mc, n_t);
-  wave_sync();
-  for (int i = lane; i < n_age; i += 64) mage[i] = em[i] - em[i + 1];
-  wave_sync();
+  // ---- cumulative trapezoid of the SFR row, one round of 64 segments at a
+  // time: segment m joins nodes m and m + 1 and lives on lane m % 64.  The
+  // mass before a round (carry) plus the wave's exclusive scan gives the
+  // cumulative mass at every node of the round; edges whose interval starts
+  // there read it from the owning lane.  Nothing is stored per node.
+  double pa = 0, ptau = 1, palpha = 0, pq = 0, ptq = 0;
+  if (!TABULATED) {
+    pa = a.sfh_params[g]; ptau = a.sfh_params[a.n_gal + g];
+    palpha = a.sfh_params[2 * a.n_gal + g]; pq = a.sfh_params[3 * a.n_gal + g];
+    ptq = a.sfh_params[4 * a.n_gal + g];
+  }
+  const int n_seg = n_t - 1;
+  double carry = 0.0;
+  double em[2] = {0.0, 0.0};
+  for (int base = 0; base < n_seg; base += 64 * SFR_BATCH) {
+    // SFR at nodes base + 64 r + lane (the first batch of a tabulated row was
+    // loaded up front) and at the first node of the next batch
+    const int n_next = base + 64 * SFR_BATCH;
+    if (!TABULATED || base > 0) {
+#pragma unroll
+      for (int r = 0; r < SFR_BATCH; ++r) {
+        const int n = base + 64 * r + lane;
+        v[r] = 0.0;
+        if (n < n_t) v[r] = TABULATED ? row[n] : sfr_param(tt[n], pa, ptau, palpha, pq, ptq);
+      }
+      v_next = 0.0;
+      if (n_next < n_t)
+        v_next = TABULATED ? row[n_next] : sfr_param(tt[n_next], pa, ptau, palpha, pq, ptq);
+    }
+#pragma unroll
+    for (int r = 0; r < SFR_BATCH; ++r) {
+      const int first = base + 64 * r;
+      if (first >= n_seg) break;                       // uniform
+      const int m = first + lane;
+      double s1 = __shfl_down(v[r], 1, 64);            // SFR at node m + 1
+      const double wrap = r + 1 < SFR_BATCH ? __shfl(v[r + 1 < SFR_BATCH ? r + 1 : r], 0, 64) : v_next;
+      if (lane == 63) s1 = wrap;
+      const double seg = m < n_seg ? 0.5 * (v[r] + s1) * (tt[m + 1] - tt[m]) * YEARS_PER_GYR : 0.0;
+      double incl = seg;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const double up = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += up;
+      }
+      double excl = __shfl_up(incl, 1, 64);
+      if (lane == 0) excl = 0.0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int src = lo[q] - first;
+        const double pe = __shfl(excl, src & 63, 64);
+        const double sg = __shfl(seg, src & 63, 64);
+        if (kind[q] == 1 && src >= 0 && src < 64) em[q] = (carry + pe) + fe[q] * sg;
+      }
+      carry += __shfl(incl, 63, 64);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    if (kind[q] == 2) em[q] = carry;
 
+  // ---- bin masses m_i = M(t_obs - edge_i) - M(t_obs - edge_{i+1}) in float64
+  double em_up0 = __shfl_down(em[0], 1, 64);
+  const double em64 = __shfl(em[1], 0, 64);
+  if (lane == 63) em_up0 = em64;
+  const double em_up1 = __shfl_down(em[1], 1, 64);
+  const double mage[2] = {lane < n_age ? em[0] - em_up0 : 0.0,
+                          lane + 64 < n_age ? em[1] - em_up1 : 0.0};
   if (a.mstar && lane == 0) a.mstar[g] = em[0];
 
   // ---- metallicity weights and W = m_age * P, lanes over ages.
-  const double lgmet = (double)a.lgmet[g];
-  const double inv_sig = 1.0 / (double)a.sigma_z[g];
+  const double lgmet = (double)lgmet_f;
+  const double inv_sig = 1.0 / (double)sig_f;
   int jlo = 1 << 20, jhi = -1, ihi = 0;
   const int k_pad = P.k_pad;
   float *wp32 = (a.w_pad && !a.w_pad_bf16) ? (float *)a.w_pad + (size_t)local * k_pad : nullptr;
   uint16_t *wp16 = (a.w_pad && a.w_pad_bf16) ? (uint16_t *)a.w_pad + (size_t)local * k_pad : nullptr;
   float *wu = a.w_user ? a.w_user + (size_t)g * n_met * n_age : nullptr;
-  for (int i = lane; i < AGE_PAD; i += 64) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = lane + 64 * q;
+    if (i >= AGE_PAD) continue;
     const bool real = i < n_age;
-    const double mu = real ? lgmet + a.slope * (P.lg_age[i] - a.pivot) : 0.0;
-    const double m_i = real ? mage[i] : 0.0;
+    const double mu = real ? lgmet + a.slope * (s_lgage[i] - a.pivot) : 0.0;
+    const double m_i = mage[q];
     double c_prev = 0.0;  // CDF at the lower edge of metallicity bin 0 (-inf)
     for (int j = 0; j < n_met; ++j) {
       double c_next;
       if (j == n_met - 1) c_next = 1.0;  // upper edge of the last bin is +inf
-      else c_next = triweight_cdf((P.met_edges[j + 1] - mu) * inv_sig);
+      else c_next = triweight_cdf((s_medge[j + 1] - mu) * inv_sig);
       const double wv = real ? m_i * (c_next - c_prev) : 0.0;
       c_prev = c_next;
       bool nz;
       if (wp16) {
-        const uint16_t q = f32_to_bf16_rne((float)(wv * (double)P.kscale[j * AGE_PAD + i]));
-        wp16[j * AGE_PAD + i] = q;
-        nz = (q & 0x7FFFu) != 0;
+        const uint16_t qv = f32_to_bf16_rne((float)(wv * (double)s_ks[j * AGE_PAD + i]));
+        wp16[j * AGE_PAD + i] = qv;
+        nz = (qv & 0x7FFFu) != 0;
       } else {
         const float wf = (float)wv;
         if (wp32) wp32[j * AGE_PAD + i] = wf;
@@ -233,17 +320,25 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   // wave[lo] >= obs_lo/(1+z) and wave[hi-1] <= obs_hi/(1+z)
   int win_lo = 0, win_hi = 0;
   if (a.range) {
-    win_lo = wave_lower_bound(P.wave, P.n_wave, a.obs_lo / (1.0 + z), false, lane);
-    win_hi = wave_lower_bound(P.wave, P.n_wave, a.obs_hi / (1.0 + z), true, lane);
+    const double v1 = a.obs_lo / (1.0 + z), v2 = a.obs_hi / (1.0 + z);
+    // coarse entries c: wave[c * stride]; the first satisfying one brackets
+    // the answer to ((c - 1) stride, c stride] of the full grid
+    int c1 = 0, c2 = 0;
+    wave_search_pair(s_cw, v1, v2, lane, c1, n_coarse, c2, n_coarse);
+    win_lo = c1 == 0 ? 0 : (c1 - 1) * stride + 1;
+    win_hi = c2 == 0 ? 0 : (c2 - 1) * stride + 1;
+    const int h1 = c1 == 0 ? 0 : min(c1 * stride, P.n_wave);
+    const int h2 = c2 == 0 ? 0 : min(c2 * stride, P.n_wave);
+    wave_search_pair(P.wave, v1, v2, lane, win_lo, h1, win_hi, h2);
   }
   if (lane == 0) {
     if (a.meta) {
       GalaxyMeta m;
       m.zp1 = (float)(1.0 + z);
       // F = 10^(-0.4 A_V/4.05 k) = 2^(dust_a k)
-      m.dust_a = (float)(-0.4 * 3.32192809488736234787 * (double)a.av[g] / DUST_RV);
-      m.delta = a.delta[g];
-      m.bump = a.bump[g];
+      m.dust_a = (float)(-0.4 * 3.32192809488736234787 * (double)av_f / DUST_RV);
+      m.delta = delta_f;
+      m.bump = bump_f;
       a.meta[s] = m;
     }
     if (a.mag_offset) a.mag_offset[s] = dmod - 2.5 * log10(1.0 + z);
@@ -263,15 +358,19 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
 int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
   const int blocks = (a.s_count + WEIGHT_WAVES - 1) / WEIGHT_WAVES;
-  const size_t lds = sizeof(double) * (a.n_t + WEIGHT_WAVES * (2 * a.n_t + 2 * AGE_PAD + 2));
+  const size_t lds = sizeof(double) * weights_lds_doubles(a.n_t, a.ssp.n_age, a.ssp.n_met,
+                                                          a.ssp.n_wave, a.ssp.k_pad);
+  const void *fn = a.sfr ? (const void *)k_weights<true> : (const void *)k_weights<false>;
   if (lds > 65536) {
-    const int rc = hip_fail(hipFuncSetAttribute((const void *)k_weights,
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+    const int rc = hip_fail(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                             "k_weights LDS attribute");
     if (rc) return rc;
   }
   ProfScope prof(DSPS_KERNEL_WEIGHTS, stream);
-  hipLaunchKernelGGL(k_weights, dim3(blocks), dim3(64 * WEIGHT_WAVES), lds, stream, a);
+  if (a.sfr)
+    hipLaunchKernelGGL(k_weights<true>, dim3(blocks), dim3(64 * WEIGHT_WAVES), lds, stream, a);
+  else
+    hipLaunchKernelGGL(k_weights<false>, dim3(blocks), dim3(64 * WEIGHT_WAVES), lds, stream, a);
   return hip_fail(hipGetLastError(), "k_weights launch");
 }
 

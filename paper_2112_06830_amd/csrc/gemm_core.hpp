@@ -143,6 +143,41 @@ __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_BF16> &sm, int wr,
   }
 }
 
+// Bands whose support meets the observed wavelengths [o_lo, o_hi] (with a
+// relative margin far above float rounding): any band left out has zero
+// transmission for every element of the chunk, so skipping it is exact.
+__device__ __forceinline__ unsigned active_bands(const FilterView &F, float o_lo, float o_hi) {
+  unsigned m = 0;
+  for (int b = 0; b < F.n_band; ++b) {
+    const float2 gr = F.grid[b];
+    const float lo = gr.x, hi = gr.x + (float)(F.n_pts - 1) / gr.y;
+    if (o_hi * 1.0001f >= lo && o_lo * 0.9999f <= hi) m |= 1u << b;
+  }
+  return m;
+}
+
+// Filter transmission as (T[i], T[i+1] - T[i]) per grid interval, so that an
+// interpolation is one aligned 8-byte LDS read and one FMA.  Whole workgroup.
+__device__ __forceinline__ void fill_filter_pairs(const FilterView &F, float2 *s_pair) {
+  const int n_int = F.n_pts - 1;
+  for (int i = threadIdx.x; i < F.n_band * n_int; i += blockDim.x) {
+    const int b = i / n_int, k = i - b * n_int;
+    const float t0 = F.trans[b * F.n_pts + k], t1 = F.trans[b * F.n_pts + k + 1];
+    s_pair[i] = make_float2(t0, t1 - t0);
+  }
+}
+
+// Transmission of one band at grid coordinate u = (lambda - first) / spacing:
+// linear interpolation between grid points, zero outside [0, n_int].  Matches
+// filter_at below bit for bit.
+__device__ __forceinline__ float filter_pair_at(const float2 *tab, int n_int, float u) {
+  const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, (float)n_int);
+  const int i = min((int)uc, n_int - 1);
+  const float2 pr = tab[i];
+  const float t = fmaf(uc - (float)i, pr.y, pr.x);
+  return u == uc ? t : 0.0f;
+}
+
 // Linear interpolation of a uniformly gridded filter, zero outside.
 __device__ __forceinline__ float filter_at(const float *tr, int n_pts, float u) {
   if (!(u >= 0.0f) || !(u <= (float)(n_pts - 1))) return 0.0f;

@@ -93,19 +93,6 @@ __device__ __forceinline__ void write_band_slots(float (&num)[2][NSLOT], float (
   }
 }
 
-// Bands whose support meets the observed wavelengths [o_lo, o_hi] (with a
-// relative margin far above float rounding): any band left out has zero
-// transmission for every element of the chunk, so skipping it is exact.
-__device__ __forceinline__ unsigned active_bands(const FilterView &F, float o_lo, float o_hi) {
-  unsigned m = 0;
-  for (int b = 0; b < F.n_band; ++b) {
-    const float2 gr = F.grid[b];
-    const float lo = gr.x, hi = gr.x + (float)(F.n_pts - 1) / gr.y;
-    if (o_hi * 1.0001f >= lo && o_lo * 0.9999f <= hi) m |= 1u << b;
-  }
-  return m;
-}
-
 // Three workgroups per CU (at most 168 VGPRs).  The cross-wave reduction
 // buffer of the epilogue reuses the operand staging area, which is idle by
 // then.
@@ -173,11 +160,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 3) void k_mags_gemm(MagsLaunch a) {
 
   // ---- filter intervals into LDS
   const int n_int = n_pts - 1;
-  for (int i = threadIdx.x; i < n_band * n_int; i += GEMM_THREADS) {
-    const int b = i / n_int, k = i - b * n_int;
-    const float t0 = F.trans[b * n_pts + k], t1 = F.trans[b * n_pts + k + 1];
-    s_pair[i] = make_float2(t0, t1 - t0);
-  }
+  fill_filter_pairs(F, s_pair);
 
   // ---- per-galaxy parameters of this lane's two columns
   float zp1[2], da[2], dl[2], bp[2];
@@ -259,7 +242,6 @@ __global__ __launch_bounds__(GEMM_THREADS, 3) void k_mags_gemm(MagsLaunch a) {
       for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
         for (int k = 0; k < NSLOT; ++k) { num[nb][k] = 0.0f; den[nb][k] = 0.0f; }
-      const float umax = (float)n_int;
       // An offset the compiler cannot see through keeps the per-row LDS reads
       // below inside the pass (hoisted out of it they would pin 64 registers).
       int zero;
@@ -282,13 +264,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 3) void k_mags_gemm(MagsLaunch a) {
             const float e = acc[mb][nb][r] * att * q;
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
-              // linear interpolation on the uniform filter grid, zero outside
-              const float u = (lobs - w0[k]) * wi[k];
-              const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, umax);
-              const int i = min((int)uc, n_int - 1);
-              const float2 pr = tab[k][i];
-              float t = fmaf(uc - (float)i, pr.y, pr.x);
-              t = (u == uc) ? t : 0.0f;
+              const float t = filter_pair_at(tab[k], n_int, (lobs - w0[k]) * wi[k]);
               num[nb][k] += t * e;
               den[nb][k] += t * q;
             }

@@ -42,11 +42,13 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_gemm(VjpLaunch a) {
   __shared__ GemmSmem<DSPS_FP32> sm;
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
-  __shared__ float s_filt[DSPS_MAX_FILTER_FLOATS];
   __shared__ float s_red[2][64][3];
   __shared__ float s_gam[TILE_G * DSPS_MAX_BAND];
   __shared__ float2 s_grid[DSPS_MAX_BAND];
-  __shared__ int s_tile[4];
+  // window lo, window hi, metallicity-row mask, age hi, min and max of (1+z)
+  // as float bits
+  __shared__ int s_tile[6];
+  extern __shared__ float2 s_pair[];   // [n_band][n_pts - 1] filter intervals
 
   const int group = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -57,12 +59,18 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_gemm(VjpLaunch a) {
   const int g0 = tile * TILE_G;
   const int nvalid = min(TILE_G, a.s_count - g0);
 
-  if (threadIdx.x == 0) { s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0; s_tile[3] = 0; }
+  if (threadIdx.x == 0) {
+    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0; s_tile[3] = 0;
+    s_tile[4] = 0x7f7fffff; s_tile[5] = 0;
+  }
   __syncthreads();
   if (threadIdx.x < nvalid) {
     const GalaxyRange r = a.range[a.s_begin + g0 + threadIdx.x];
+    const int zbits = __float_as_int(a.meta[a.s_begin + g0 + threadIdx.x].zp1);
     atomicMin(&s_tile[0], r.win_lo);
     atomicMax(&s_tile[1], r.win_hi);
+    atomicMin(&s_tile[4], zbits);
+    atomicMax(&s_tile[5], zbits);
     if (r.age_hi > 0) {
       const int jl = r.met_lo_hi & 0xFFFF, jh = r.met_lo_hi >> 16;
       atomicOr(&s_tile[2], (int)(((1u << (jh + 1)) - 1u) & ~((1u << jl) - 1u)));
@@ -73,6 +81,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_gemm(VjpLaunch a) {
   const int win_lo = s_tile[0], win_hi = s_tile[1];
   const unsigned met_mask = (unsigned)s_tile[2];
   const int age_hi = s_tile[3];
+  const float zp1_min = __int_as_float(s_tile[4]), zp1_max = __int_as_float(s_tile[5]);
   const int c_first = win_lo / TILE_L;
   const int c_last = (win_hi + TILE_L - 1) / TILE_L;
   const int c_begin = max(group * CHUNKS_PER_GROUP, c_first);
@@ -85,12 +94,12 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_gemm(VjpLaunch a) {
     }
     return;
   }
-  for (int i = threadIdx.x; i < n_band * n_pts; i += GEMM_THREADS) s_filt[i] = F.trans[i];
+  const int n_int = n_pts - 1;
+  fill_filter_pairs(F, s_pair);
 
-  // The band loop of this epilogue produces one scalar per element, so it
-  // stays rolled: per-galaxy gamma and the filter grids are read from LDS
-  // with a runtime band index (an unrolled 8-band loop over 64 elements per
-  // lane exhausts the register file).
+  // Per-galaxy gamma and the filter grids are read from LDS with a runtime
+  // band index (per-band registers for 64 elements per lane would exhaust
+  // the register file).
   for (int i = threadIdx.x; i < TILE_G * n_band; i += GEMM_THREADS) {
     const int col = i / n_band, b = i % n_band;
     s_gam[col * DSPS_MAX_BAND + b] =
@@ -149,38 +158,56 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_gemm(VjpLaunch a) {
     }
     __syncthreads();
 
-    // rows outer, galaxies inner: each row's constants are used once and die
+    // Bands that can see this chunk for some galaxy of the tile (the others
+    // add exact zeros to every sum below).  For each group of four rows (one
+    // 16-byte Lbar store per column) the band loop runs outside the elements,
+    // so the lookups of the group issue together.
+    const unsigned bmask = __builtin_amdgcn_readfirstlane(
+        active_bands(F, zp1_min * s_lc[0].x, zp1_max * s_lc[TILE_L - 1].x));
+    const int b_lo = bmask ? __builtin_ctz(bmask) : 0;
+    const int n_act = bmask ? 32 - __builtin_clz(bmask) - b_lo : 0;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
       for (int r4 = 0; r4 < 4; ++r4) {
+        const int row0 = wr * 64 + mb * 32 + 8 * r4 + 4 * h;
+        float lobs[4][2], gs[4][2];
+#pragma unroll
+        for (int r1 = 0; r1 < 4; ++r1) {
+          const float lam = s_lc[row0 + r1].x;
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) { lobs[r1][nb] = zp1[nb] * lam; gs[r1][nb] = 0.0f; }
+        }
+        // G = sum_b gamma_b T_b in ascending band order
+        for (int k = 0; k < n_act; ++k) {
+          const int b = b_lo + k;
+          const float2 gr = s_grid[b];
+          const float2 *tab = s_pair + b * n_int;
+          float gam[2];
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) gam[nb] = s_gam[(wc * 64 + nb * 32 + (lane & 31)) * DSPS_MAX_BAND + b];
+#pragma unroll
+          for (int r1 = 0; r1 < 4; ++r1)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+              gs[r1][nb] += gam[nb] * filter_pair_at(tab, n_int, (lobs[r1][nb] - gr.x) * gr.y);
+        }
         float out4[2][4];
 #pragma unroll
         for (int r1 = 0; r1 < 4; ++r1) {
           const int r = 4 * r4 + r1;
-          const int row = wr * 64 + mb * 32 + 8 * r4 + 4 * h + r1;
-          const float4 lc = s_lc[row];
-          const float q = s_q[row];
+          const float4 lc = s_lc[row0 + r1];
+          const float q = s_q[row0 + r1];
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb) {
-            const int col = wc * 64 + nb * 32 + (lane & 31);
             const float powl = exp2f(dl[nb] * lc.y);
             const float kl = lc.z * powl + bp[nb] * lc.w;      // k_lambda
             const float att = exp2f(da[nb] * kl);
-            const float lobs = zp1[nb] * lc.x;
-            const float *gcol = s_gam + col * DSPS_MAX_BAND;
-            float gsum = 0.0f;
-#pragma unroll 1
-            for (int b = 0; b < n_band; ++b) {
-              const float2 gr = s_grid[b];
-              gsum += gcol[b] * filter_at(s_filt + b * n_pts, n_pts, (lobs - gr.x) * gr.y);
-            }
-            gsum *= q;
+            const float gsum = gs[r1][nb] * q;
             acc[mb][nb][r] *= gsum * att;                      // e = G F L
             out4[nb][r1] = gsum * att;
           }
         }
-        const int row0 = wr * 64 + mb * 32 + 8 * r4 + 4 * h;
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
           const int col = wc * 64 + nb * 32 + (lane & 31);
@@ -536,7 +563,8 @@ int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
     hipLaunchKernelGGL(k_vjp_gamma, dim3((a.s_count + 255) / 256), dim3(256), 0, stream, a);
   } else if (stage == 1) {
     ProfScope prof(DSPS_KERNEL_VJP_GEMM, stream);
-    hipLaunchKernelGGL(k_vjp_gemm, dim3(a.n_groups, tiles), dim3(GEMM_THREADS), 0, stream, a);
+    const size_t lds = sizeof(float2) * a.flt.n_band * (a.flt.n_pts - 1);
+    hipLaunchKernelGGL(k_vjp_gemm, dim3(a.n_groups, tiles), dim3(GEMM_THREADS), lds, stream, a);
   } else if (stage == 2) {
     ProfScope prof(DSPS_KERNEL_VJP_WBAR, stream);
     hipLaunchKernelGGL(k_vjp_wbar, dim3(a.ssp.sk_rows / TILE_L, tiles), dim3(GEMM_THREADS), 0, stream, a);

@@ -6,22 +6,23 @@ gradient of sum (m - target)^2 w.r.t. every per-galaxy parameter.  The SSP
 block and the filter set stay resident; forward requests run on the BF16 table
 and gradient requests on the FP32 table (both resident).
 
-Scheduling:
+Scheduling (continuous batching):
   * Requests wait in one FIFO queue per kind (forward / gradient).
-  * A batch takes queued requests in order while their galaxies fit the
-    largest slot; it runs in the smallest slot bucket that holds it, padded
-    with inert galaxies (z = 1000: no filter ever sees them, so they skip the
-    contraction).
+  * At most `max_inflight_per_kind` batches of a kind run at once (one by
+    default).  While a batch runs, arrivals accumulate in the queue; when it
+    completes, the next batch takes the queued requests in order while their
+    galaxies fit the largest slot, so load is absorbed by larger batches
+    rather than by a queue of launches on the stream.
+  * A batch runs in the smallest slot bucket that holds it, padded with inert
+    galaxies (z = 1000: no filter ever sees them, so they skip the
+    contraction).  Slot choice, in order: an idle slot of that bucket; a new
+    one if it fits the HBM byte budget; an idle larger slot; a new one after
+    evicting idle slots.
   * Slots (device buffers + pinned staging + a captured hipGraph of the
-    batch's whole launch sequence) are allocated lazily under an HBM byte
-    budget; a batch is admitted only when a slot is free or fits the budget.
-  * Up to `slots_per_bucket` batches per kind are in flight: requests that
-    arrive while others run are packed, copied (copy stream) and enqueued
-    behind them, so their transfers overlap the running kernels.
+    batch's whole launch sequence) are allocated under the budget, ahead of
+    traffic by `warm()` or on first use.  A batch's inputs go over the copy
+    stream; its graph replays on the kind's stream.
 
-Per-galaxy results do not depend on which other galaxies share a batch (the
-kernels' tiling keeps every galaxy's arithmetic identical), so a request's
-answer is the same alone and in the mix.
 """
 
 from __future__ import annotations
@@ -87,14 +88,17 @@ class AdmissionPlanner:
     """Pure scheduling policy (no GPU): FIFO batching into bucketed slots
     under an HBM byte budget."""
 
-    def __init__(self, buckets, bytes_per_galaxy: dict, budget_bytes: int, slots_per_bucket=2):
+    def __init__(self, buckets, bytes_per_galaxy: dict, budget_bytes: int, slots_per_bucket=1,
+                 max_inflight_per_kind=1):
         self.buckets = sorted(int(b) for b in buckets)
         self.bpg = dict(bytes_per_galaxy)
         self.budget = int(budget_bytes)
         self.slots_per_bucket = slots_per_bucket
+        self.max_inflight = max_inflight_per_kind
         self.queues = {KIND_FWD: deque(), KIND_GRAD: deque()}
         self.allocated = {}          # (kind, bucket) -> number of slots allocated
         self.busy = {}               # (kind, bucket) -> number of slots in flight
+        self.inflight = {KIND_FWD: 0, KIND_GRAD: 0}
         self.reserved = 0
         self.evicted = []            # idle slots the engine must free
 
@@ -118,7 +122,7 @@ class AdmissionPlanner:
     def next_batch(self, kind):
         """Requests for the next batch of `kind` and its bucket, or None."""
         q = self.queues[kind]
-        if not q:
+        if not q or self.inflight[kind] >= self.max_inflight:
             return None
         take, total = [], 0
         for r in q:
@@ -127,43 +131,52 @@ class AdmissionPlanner:
             take.append(r)
             total += r.n
         need = self.bucket_for(total)
+        key = (kind, need)
+        nbytes = self.slot_bytes(kind, need)
+        can_add = self.allocated.get(key, 0) < self.slots_per_bucket
         bucket = None
-        # 1. an idle slot of this kind that is large enough (smallest first)
-        for b in self.buckets:
-            if b >= need and self._idle((kind, b)) > 0:
-                bucket = b
-                break
+        if self._idle(key) > 0:                                   # 1. idle exact slot
+            bucket = need
+        elif can_add and self.reserved + nbytes <= self.budget:  # 2. new exact slot
+            self._allocate(key)
+            bucket = need
+        else:
+            for b in self.buckets:                                # 3. idle larger slot
+                if b > need and self._idle((kind, b)) > 0:
+                    bucket = b
+                    break
         if bucket is None:
-            key = (kind, need)
-            nbytes = self.slot_bytes(kind, need)
-            if self.allocated.get(key, 0) >= self.slots_per_bucket:
+            if not can_add:
                 return None
-            # 2. evict idle slots (least useful first: other kind, then larger)
+            # 4. evict idle slots (least useful first: other kind, then larger)
+            victims = sorted((k for k in self.allocated if self._idle(k) > 0),
+                             key=lambda k: (k[0] == kind, -k[1]))
+            for vk in victims:
+                while self._idle(vk) > 0 and self.reserved + nbytes > self.budget:
+                    self.allocated[vk] -= 1
+                    self.reserved -= self.slot_bytes(*vk)
+                    self.evicted.append(vk)
             if self.reserved + nbytes > self.budget:
-                victims = sorted((k for k in self.allocated if self._idle(k) > 0),
-                                 key=lambda k: (k[0] == kind, -k[1]))
-                for vk in victims:
-                    while self._idle(vk) > 0 and self.reserved + nbytes > self.budget:
-                        self.allocated[vk] -= 1
-                        self.reserved -= self.slot_bytes(*vk)
-                        self.evicted.append(vk)
-                if self.reserved + nbytes > self.budget:
-                    return None
-            # 3. allocate
-            self.allocated[key] = self.allocated.get(key, 0) + 1
-            self.reserved += nbytes
+                return None
+            self._allocate(key)
             bucket = need
         key = (kind, bucket)
         self.busy[key] = self.busy.get(key, 0) + 1
+        self.inflight[kind] += 1
         for _ in take:
             q.popleft()
         return take, bucket
+
+    def _allocate(self, key):
+        self.allocated[key] = self.allocated.get(key, 0) + 1
+        self.reserved += self.slot_bytes(*key)
 
     def _idle(self, key):
         return self.allocated.get(key, 0) - self.busy.get(key, 0)
 
     def release(self, kind, bucket):
         self.busy[(kind, bucket)] -= 1
+        self.inflight[kind] -= 1
 
 
 # ---------------------------------------------------------------- GPU slots
@@ -238,8 +251,9 @@ class _Slot:
 class ServeEngine:
     """Continuous-batching server on one GPU (see the module docstring)."""
 
-    def __init__(self, ssp, filters, cosmo=None, n_t=100, buckets=(4096, 16384, 65536, 131072),
-                 hbm_budget_bytes=24 << 30, slots_per_bucket=2, use_graphs=True, device="cuda"):
+    def __init__(self, ssp, filters, cosmo=None, n_t=100,
+                 buckets=(8192, 16384, 32768, 65536, 131072), hbm_budget_bytes=24 << 30,
+                 slots_per_bucket=1, max_inflight_per_kind=1, use_graphs=True, device="cuda"):
         import synth
         self.device = torch.device(device)
         self.n_t = n_t
@@ -258,7 +272,8 @@ class ServeEngine:
                 ws += api.workspace_size(3, self.ssp_h, self.flt_h, ref, n_t, "fp32")
             io = 5 * 8 + 7 * 4 + self.n_band * 4 * (1 if kind == KIND_FWD else 5) + (60 if kind == KIND_GRAD else 0)
             bpg[kind] = int(math.ceil(ws / ref)) + io
-        self.planner = AdmissionPlanner(buckets, bpg, hbm_budget_bytes, slots_per_bucket)
+        self.planner = AdmissionPlanner(buckets, bpg, hbm_budget_bytes, slots_per_bucket,
+                                        max_inflight_per_kind)
         self.free_slots = {}
         self.inflight = []
         self.copy_stream = torch.cuda.Stream(device=self.device)
@@ -304,8 +319,7 @@ class ServeEngine:
                     continue
                 if self.planner.reserved + self.planner.slot_bytes(kind, b) > self.planner.budget:
                     continue
-                self.planner.allocated[key] = self.planner.allocated.get(key, 0) + 1
-                self.planner.reserved += self.planner.slot_bytes(kind, b)
+                self.planner._allocate(key)
                 slot = _Slot(self, kind, b)
                 slot.capture(self.streams[kind])
                 self.free_slots.setdefault(key, []).append(slot)

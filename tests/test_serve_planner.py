@@ -21,7 +21,8 @@ def S():
 
 
 def test_fifo_batches_fit_largest_bucket(S):
-    p = S.AdmissionPlanner([100, 400], {"fwd": 10, "grad": 20}, budget_bytes=10**9)
+    p = S.AdmissionPlanner([100, 400], {"fwd": 10, "grad": 20}, budget_bytes=10**9,
+                           max_inflight_per_kind=2)
     for i, n in enumerate([50, 60, 200, 90, 30]):
         assert p.enqueue(_Req(i, n))
     take, bucket = p.next_batch("fwd")
@@ -31,9 +32,37 @@ def test_fifo_batches_fit_largest_bucket(S):
     assert p.next_batch("fwd") is None
 
 
+def test_one_batch_in_flight_per_kind_absorbs_arrivals(S):
+    # while a batch runs, arrivals queue and leave together as the next batch
+    p = S.AdmissionPlanner([100, 400], {"fwd": 10, "grad": 20}, budget_bytes=10**9)
+    p.enqueue(_Req(0, 50))
+    take, bucket = p.next_batch("fwd")
+    assert [r.rid for r in take] == [0] and bucket == 100
+    for i in range(1, 4):
+        p.enqueue(_Req(i, 60))
+    assert p.next_batch("fwd") is None            # the kind's batch is still running
+    p.enqueue(_Req(9, 10, grad=True))
+    assert [r.rid for r in p.next_batch("grad")[0]] == [9]   # other kind unaffected
+    p.release("fwd", 100)
+    take, bucket = p.next_batch("fwd")
+    assert [r.rid for r in take] == [1, 2, 3] and bucket == 400
+
+
+def test_smallest_fitting_bucket_preferred_over_idle_larger(S):
+    # an idle 400-slot exists, but a new 100-slot fits the budget: take it
+    p = S.AdmissionPlanner([100, 400], {"fwd": 10, "grad": 10}, budget_bytes=10**9)
+    p.enqueue(_Req(0, 350))
+    p.next_batch("fwd")
+    p.release("fwd", 400)
+    p.enqueue(_Req(1, 50))
+    take, b = p.next_batch("fwd")
+    assert b == 100 and p.reserved == 5000 and not p.evicted
+
+
 def test_budget_limits_slots_and_release_reuses(S):
     # one 400-slot of fwd costs 4000 bytes; the budget allows exactly one
-    p = S.AdmissionPlanner([100, 400], {"fwd": 10, "grad": 20}, budget_bytes=4500, slots_per_bucket=2)
+    p = S.AdmissionPlanner([100, 400], {"fwd": 10, "grad": 20}, budget_bytes=4500, slots_per_bucket=2,
+                           max_inflight_per_kind=2)
     for i in range(3):
         p.enqueue(_Req(i, 300))
     first = p.next_batch("fwd")

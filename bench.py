@@ -175,16 +175,19 @@ def run_grad(P, steps, warmup, n_gal=200_000, seed=5):
     ws_b = P.Workspace(P.workspace_size(3, ssp_h, flt_h, n_gal, 100, "fp32"), dpop.device)
     m = torch.empty((n_gal, 6), dtype=torch.float32, device="cuda")
     bands = torch.empty((n_gal, 2, 6), dtype=torch.float32, device="cuda")
+    mom = torch.empty((n_gal, 3, 6), dtype=torch.float32, device="cuda")
     outs = {"sfh_params": torch.empty((5, n_gal), dtype=torch.float64, device="cuda")}
     for k in ("lgmet", "sigma_z", "av", "delta", "bump"):
         outs[k] = torch.empty(n_gal, dtype=torch.float32, device="cuda")
     bar = torch.empty_like(m)
 
     def step():
-        P.mags(ssp_h, flt_h, P.Cosmology(), dpop, with_bands=True, workspace=ws_f, out=m, bands_out=bands)
+        P.mags(ssp_h, flt_h, P.Cosmology(), dpop, with_moments=True, workspace=ws_f, out=m,
+               bands_out=bands, moments_out=mom)
         torch.sub(m, tgt, out=bar)
         bar.mul_(2.0)
-        P.mags_vjp(ssp_h, flt_h, P.Cosmology(), dpop, bar, bands=bands, workspace=ws_b, outs=outs)
+        P.mags_vjp(ssp_h, flt_h, P.Cosmology(), dpop, bar, bands=bands, moments=mom, workspace=ws_b,
+                   outs=outs)
 
     for _ in range(warmup):
         step()
@@ -197,7 +200,7 @@ def run_grad(P, steps, warmup, n_gal=200_000, seed=5):
     t1 = time.perf_counter()
     res = {"ms_per_step": (t1 - t0) * 1e3 / steps}
     res["galaxies_per_s"] = n_gal / (res["ms_per_step"] * 1e-3)
-    for k in ("mags_gemm", "vjp_gemm", "vjp_wbar", "vjp_weights", "weights"):
+    for k in ("mags_gemm", "vjp_lbar", "vjp_wbar", "vjp_weights", "weights"):
         ms, n = P.profile_read(k)
         res[f"{k}_ms_per_step"] = ms / steps
     P.profile_enable(False)

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define DSPS_ABI_VERSION 1
+#define DSPS_ABI_VERSION 2
 
 typedef enum {
   DSPS_OK = 0,
@@ -197,34 +197,40 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
 /* ---------------------------------------------------------------------------
  * a1-a7. Fused magnitudes: the SED is contracted, attenuated and integrated
  * through every filter without ever being written to memory.
- *   mags   [n_gal*n_band] float32 apparent AB magnitudes
- *          m = -2.5 log10(num / (AB0 den)) + D_mod(z) - 2.5 log10(1+z)
- *   bands  [n_gal*2*n_band] float32 (num_b then den_b per galaxy): the two
- *          trapezoid sums of Eq. restmag over the redshifted grid, or NULL.
- *          dsps_mags_vjp accepts them to skip the forward recomputation.
+ *   mags     [n_gal*n_band] float32 apparent AB magnitudes
+ *            m = -2.5 log10(num / (AB0 den)) + D_mod(z) - 2.5 log10(1+z)
+ *   bands    [n_gal*2*n_band] float32 (num_b then den_b per galaxy): the two
+ *            trapezoid sums of Eq. restmag over the redshifted grid, or NULL.
+ *   moments  [n_gal*3*n_band] float32 dust moments of the band sums, or NULL
+ *            (DSPS_FP32 only, else DSPS_ERR_UNSUPPORTED): for each band the
+ *            sums of Eq. restmag's numerand T q F L times k_lambda, times
+ *            k0 (lambda/5500)^delta log2(lambda/5500), and times the bump
+ *            profile D(lambda) (Eqs. attenuation-uvbump), in that order.
+ * dsps_mags_vjp accepts bands and moments to skip the forward pass.
  * ------------------------------------------------------------------------ */
 int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
-              const dsps_pop *pop, int precision, float *mags, float *bands,
+              const dsps_pop *pop, int precision, float *mags, float *bands, float *moments,
               void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * a9. Vector-Jacobian product of dsps_mags (reverse mode).
  *   mags_bar        [n_gal*n_band] float32 cotangent of the magnitudes
- *   bands           [n_gal*2*n_band] from dsps_mags with the same inputs and
- *                   precision, or NULL (then recomputed)
+ *   bands, moments  from dsps_mags with the same inputs in DSPS_FP32, or both
+ *                   NULL (then the forward pass runs first, in the workspace)
  *   sfr_bar         [n_gal*n_t] float64 gradient w.r.t. the SFR table, or NULL
  *   sfh_params_bar  [5*n_gal] float64 gradient w.r.t. (A, tau, alpha, q, t_q);
  *                   requires pop->sfh_params, else NULL
  *   lgmet_bar, sigma_bar, av_bar, delta_bar, bump_bar
  *                   [n_gal] float32 each, or NULL
- * The SED is recomputed tile by tile, never stored.  Redshift gets no
- * gradient.
+ * The dust gradients are the band cotangents applied to the moments; the SED
+ * cotangent F q sum_b gamma_b T_b needs no SED, so the backward pass holds no
+ * forward contraction.  Redshift gets no gradient.
  * ------------------------------------------------------------------------ */
 int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
                   const dsps_pop *pop, int precision, const float *mags_bar,
-                  const float *bands, double *sfr_bar, double *sfh_params_bar,
-                  float *lgmet_bar, float *sigma_bar, float *av_bar, float *delta_bar,
-                  float *bump_bar, void *workspace, size_t workspace_bytes,
+                  const float *bands, const float *moments, double *sfr_bar,
+                  double *sfh_params_bar, float *lgmet_bar, float *sigma_bar, float *av_bar,
+                  float *delta_bar, float *bump_bar, void *workspace, size_t workspace_bytes,
                   hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
@@ -251,7 +257,7 @@ typedef enum {
   DSPS_KERNEL_MAGS_FINALIZE = 2,
   DSPS_KERNEL_ZSORT = 3,
   DSPS_KERNEL_SED_GEMM = 4,
-  DSPS_KERNEL_VJP_GEMM = 5,     /* adjoint: recomputed SED tile + dust terms */
+  DSPS_KERNEL_VJP_LBAR = 5,     /* adjoint: SED cotangent over tile windows  */
   DSPS_KERNEL_VJP_WBAR = 6,     /* adjoint: transposed contraction          */
   DSPS_KERNEL_VJP_WEIGHTS = 7,  /* adjoint: weights -> SFH, MDF parameters  */
   DSPS_KERNEL_COUNT = 8

@@ -27,7 +27,7 @@ EXPORTS = (
 )
 
 KERNEL_IDS = {"weights": 0, "mags_gemm": 1, "mags_finalize": 2, "zsort": 3, "sed_gemm": 4,
-              "vjp_gemm": 5, "vjp_wbar": 6, "vjp_weights": 7}
+              "vjp_lbar": 5, "vjp_wbar": 6, "vjp_weights": 7}
 
 
 class DspsError(RuntimeError):
@@ -70,8 +70,8 @@ def _declare(lib):
         "dsps_sfh_table": (I, [P, I, P, I, P, P]),
         "dsps_weights": (I, [P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), P, P, P, S, P]),
         "dsps_sed": (I, [P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, I, P, P, S, P]),
-        "dsps_mags": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P, S, P]),
-        "dsps_mags_vjp": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P,
+        "dsps_mags": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P, P, S, P]),
+        "dsps_mags_vjp": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P,
                               P, P, P, P, P, P, P, P, S, P]),
         "dsps_quantize_bf16": (I, [P, I, I, P, P, P]),
         "dsps_profile_enable": (I, [I]),

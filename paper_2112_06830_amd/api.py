@@ -242,24 +242,33 @@ class Workspace:
 
 
 def mags(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopulation,
-         precision="fp32", with_bands=False, workspace: Workspace | None = None, out=None,
-         bands_out=None, stream=None):
-    """dsps_mags: apparent AB magnitudes [n_gal, n_band] float32 (and the
-    band sums [n_gal, 2, n_band])."""
+         precision="fp32", with_bands=False, with_moments=False, workspace: Workspace | None = None,
+         out=None, bands_out=None, moments_out=None, stream=None):
+    """dsps_mags: apparent AB magnitudes [n_gal, n_band] float32.
+
+    with_bands also returns the band sums [n_gal, 2, n_band]; with_moments
+    (float32 only) returns (mags, bands, moments) with the dust moments
+    [n_gal, 3, n_band], which is what mags_vjp needs to skip its forward pass.
+    """
     nb = filters.n_band
     m = out if out is not None else torch.empty((pop.n_gal, nb), dtype=torch.float32, device=pop.device)
-    bands = None
-    if with_bands:
+    bands = mom = None
+    if with_bands or with_moments:
         bands = bands_out if bands_out is not None else torch.empty(
             (pop.n_gal, 2, nb), dtype=torch.float32, device=pop.device)
+    if with_moments:
+        mom = moments_out if moments_out is not None else torch.empty(
+            (pop.n_gal, 3, nb), dtype=torch.float32, device=pop.device)
     if workspace is None:
         workspace = Workspace(workspace_size(N.OP_MAGS, ssp, filters, pop.n_gal, pop.n_t, precision),
                               pop.device)
     c, p = cosmo.c(), pop.c()
     rc = _lib().dsps_mags(ssp.handle, filters.handle, ctypes.byref(c), ctypes.byref(p),
-                          _PREC[precision], _ptr(m), _ptr(bands), workspace.ptr(), workspace.nbytes,
-                          _stream(stream))
+                          _PREC[precision], _ptr(m), _ptr(bands), _ptr(mom), workspace.ptr(),
+                          workspace.nbytes, _stream(stream))
     N.check(rc, "dsps_mags")
+    if with_moments:
+        return m, bands, mom
     return (m, bands) if with_bands else m
 
 
@@ -290,15 +299,21 @@ def profile_read(kernel: str):
 
 def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopulation,
              mags_bar: torch.Tensor, bands: torch.Tensor | None = None,
+             moments: torch.Tensor | None = None,
              want=("sfr", "sfh_params", "lgmet", "sigma_z", "av", "delta", "bump"),
              workspace: Workspace | None = None, outs: dict | None = None, stream=None) -> dict:
     """dsps_mags_vjp: cotangents of the population inputs for a magnitude
-    cotangent mags_bar [n_gal, n_band] (float32 path).  `outs` may supply
-    preallocated output tensors (then `want` is ignored)."""
+    cotangent mags_bar [n_gal, n_band] (float32 path).  bands and moments come
+    from mags(..., with_moments=True) on the same inputs, or are both None
+    (the forward pass then runs inside).  `outs` may supply preallocated
+    output tensors (then `want` is ignored)."""
     n, d = pop.n_gal, pop.device
+    if (bands is None) != (moments is None):
+        raise ValueError("bands and moments are given together or not at all")
     mags_bar = mags_bar.to(device=d, dtype=torch.float32).contiguous()
     if bands is not None:
         bands = bands.to(device=d, dtype=torch.float32).contiguous()
+        moments = moments.to(device=d, dtype=torch.float32).contiguous()
     out = {}
     if outs is not None:
         out = dict(outs)
@@ -314,7 +329,7 @@ def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePo
         workspace = Workspace(workspace_size(N.OP_MAGS_VJP, ssp, filters, n, pop.n_t, "fp32"), d)
     c, p = cosmo.c(), pop.c()
     rc = _lib().dsps_mags_vjp(ssp.handle, filters.handle, ctypes.byref(c), ctypes.byref(p), N.FP32,
-                              _ptr(mags_bar), _ptr(bands), _ptr(out.get("sfr")),
+                              _ptr(mags_bar), _ptr(bands), _ptr(moments), _ptr(out.get("sfr")),
                               _ptr(out.get("sfh_params")), _ptr(out.get("lgmet")),
                               _ptr(out.get("sigma_z")), _ptr(out.get("av")), _ptr(out.get("delta")),
                               _ptr(out.get("bump")), workspace.ptr(), workspace.nbytes, _stream(stream))

@@ -1,6 +1,6 @@
 """torch.autograd.Function over the fused magnitudes and their hand-written
 adjoint (dsps_mags / dsps_mags_vjp).  Forward keeps only the per-galaxy band
-sums (2 x n_band floats); backward recomputes the SED tile by tile."""
+sums and dust moments (5 x n_band floats); backward needs no SED."""
 
 from __future__ import annotations
 
@@ -28,14 +28,14 @@ class DspsMags(torch.autograd.Function):
                                    sigma_z.detach().contiguous(), av.detach().contiguous(),
                                    delta.detach().contiguous(), bump.detach().contiguous(),
                                    float(slope), float(pivot))
-        mags, bands = api.mags(ssp, filters, cosmo, pop, precision="fp32", with_bands=True)
+        mags, bands, moments = api.mags(ssp, filters, cosmo, pop, precision="fp32", with_moments=True)
         ctx.ssp, ctx.filters, ctx.cosmo, ctx.pop = ssp, filters, cosmo, pop
-        ctx.save_for_backward(bands)
+        ctx.save_for_backward(bands, moments)
         return mags
 
     @staticmethod
     def backward(ctx, mags_bar):
-        (bands,) = ctx.saved_tensors
+        bands, moments = ctx.saved_tensors
         pop = ctx.pop
         want = []
         if pop.sfh_params is not None and ctx.needs_input_grad[4]:
@@ -46,7 +46,8 @@ class DspsMags(torch.autograd.Function):
         for i, k in enumerate(names):
             if ctx.needs_input_grad[7 + i]:
                 want.append(k)
-        g = api.mags_vjp(ctx.ssp, ctx.filters, ctx.cosmo, pop, mags_bar, bands=bands, want=tuple(want))
+        g = api.mags_vjp(ctx.ssp, ctx.filters, ctx.cosmo, pop, mags_bar, bands=bands, moments=moments,
+                         want=tuple(want))
         return (None, None, None, None, g.get("sfh_params"), g.get("sfr"), None,
                 g.get("lgmet"), g.get("sigma_z"), g.get("av"), g.get("delta"), g.get("bump"),
                 None, None)

@@ -384,7 +384,7 @@ constexpr int BATCH_VJP = 65536;
 
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
-  size_t gamma = 0, vpartial = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0;
+  size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0;
   int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
@@ -409,14 +409,17 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   L.range = take(sizeof(GalaxyRange) * (size_t)n_gal);
   L.offset = take(sizeof(double) * (size_t)n_gal);
   L.w = take(elem * (size_t)L.batch * v.k_pad);
-  L.partial = take(sizeof(float) * (size_t)L.batch * L.n_chunks * 2 * n_band);
+  // float32 forward passes may carry the dust moments
+  const int ncomp = mags_components(precision == DSPS_FP32);
+  L.partial = take(sizeof(float) * (size_t)L.batch * L.n_chunks * ncomp * n_band);
   L.tiles = take(sizeof(int2) * (size_t)((L.batch + TILE_G - 1) / TILE_G));
   if (op == DSPS_OP_MAGS_VJP) {
     L.gamma = take(sizeof(float) * (size_t)n_gal * n_band);
-    L.vpartial = take(sizeof(float) * (size_t)L.batch * L.n_groups * 3);
+    L.dust = take(sizeof(float) * (size_t)L.batch * 3);
     L.lbar = take(sizeof(float) * (size_t)L.batch * v.n_wave_pad);
     L.wbar = take(sizeof(float) * (size_t)L.batch * v.k_pad);
-    L.fbands = take(sizeof(float) * (size_t)n_gal * 3 * n_band);   // bands + mags if recomputed
+    // bands, moments and magnitudes of the forward pass when not supplied
+    L.fbands = take(sizeof(float) * (size_t)n_gal * 6 * n_band);
   }
   L.total = off;
   return L;
@@ -579,13 +582,68 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, 
   return DSPS_OK;
 }
 
+// Forward pass over the sorted batch [s0, s0 + cnt): weights, fused
+// contraction and finalize.  moments requires the float32 table.
+static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
+                      const dsps_pop *pop, int precision, const Layout &L, char *ws, int s0,
+                      int cnt, float *mags, float *bands, float *moments, hipStream_t stream) {
+  int *perm = (int *)(ws + L.perm);
+  GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
+  GalaxyRange *range = (GalaxyRange *)(ws + L.range);
+  double *offset = (double *)(ws + L.offset);
+  float *partial = (float *)(ws + L.partial);
+  WeightsLaunch a = base_weights(ssp, cosmo, pop);
+  a.perm = perm;
+  a.s_begin = s0;
+  a.s_count = cnt;
+  a.w_pad = ws + L.w;
+  a.w_pad_bf16 = precision == DSPS_BF16;
+  a.meta = meta;
+  a.range = range;
+  a.mag_offset = offset;
+  a.obs_lo = filters->obs_lo;
+  a.obs_hi = filters->obs_hi;
+  DSPS_TRY(launch_weights(a, stream));
+  MagsLaunch m{};
+  m.ssp = ssp->v;
+  m.flt = filters->v;
+  m.precision = precision;
+  m.s_begin = s0;
+  m.s_count = cnt;
+  m.w_pad = ws + L.w;
+  m.meta = meta;
+  m.range = range;
+  m.n_groups = L.n_groups;
+  m.n_chunks = L.n_chunks;
+  m.moments = moments != nullptr;
+  m.partial = partial;
+  m.tile_chunks = (int2 *)(ws + L.tiles);
+  DSPS_TRY(launch_mags_gemm(m, stream));
+  FinalizeLaunch f{};
+  f.n_band = filters->v.n_band;
+  f.n_chunks = L.n_chunks;
+  f.tile_chunks = (const int2 *)(ws + L.tiles);
+  f.s_begin = s0;
+  f.s_count = cnt;
+  f.partial = partial;
+  f.mag_offset = offset;
+  f.perm = perm;
+  f.moments = m.moments;
+  f.mags = mags;
+  f.bands = bands;
+  f.mom = moments;
+  return launch_mags_finalize(f, stream);
+}
+
 int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
-              const dsps_pop *pop, int precision, float *mags, float *bands, void *workspace,
-              size_t workspace_bytes, hipStream_t stream) {
+              const dsps_pop *pop, int precision, float *mags, float *bands, float *moments,
+              void *workspace, size_t workspace_bytes, hipStream_t stream) {
   DSPS_CHECK(ssp && filters, DSPS_ERR_ARG, "ssp or filters is NULL");
   DSPS_TRY(check_cosmo(cosmo));
   DSPS_TRY(check_pop(pop, true));
   DSPS_TRY(check_precision(ssp, precision));
+  DSPS_CHECK(!moments || precision == DSPS_FP32, DSPS_ERR_UNSUPPORTED,
+             "dust moments are computed in float32 only");
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(mags, DSPS_ERR_ARG, "mags is NULL");
   DSPS_TRY(check_device(ssp->device));
@@ -594,61 +652,20 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
   const Layout L = make_layout(DSPS_OP_MAGS, ssp->v, n_band, pop->n_gal, precision);
   DSPS_TRY(check_workspace(workspace, workspace_bytes, L.total));
   char *ws = (char *)workspace;
-  int *perm = (int *)(ws + L.perm);
-  GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
-  GalaxyRange *range = (GalaxyRange *)(ws + L.range);
-  double *offset = (double *)(ws + L.offset);
-  float *partial = (float *)(ws + L.partial);
-  DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), perm, stream));
+  DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), (int *)(ws + L.perm), stream));
   for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
     const int cnt = std::min(L.batch, pop->n_gal - s0);
-    WeightsLaunch a = base_weights(ssp, cosmo, pop);
-    a.perm = perm;
-    a.s_begin = s0;
-    a.s_count = cnt;
-    a.w_pad = ws + L.w;
-    a.w_pad_bf16 = precision == DSPS_BF16;
-    a.meta = meta;
-    a.range = range;
-    a.mag_offset = offset;
-    a.obs_lo = filters->obs_lo;
-    a.obs_hi = filters->obs_hi;
-    DSPS_TRY(launch_weights(a, stream));
-    MagsLaunch m{};
-    m.ssp = ssp->v;
-    m.flt = filters->v;
-    m.precision = precision;
-    m.s_begin = s0;
-    m.s_count = cnt;
-    m.w_pad = ws + L.w;
-    m.meta = meta;
-    m.range = range;
-    m.n_groups = L.n_groups;
-    m.n_chunks = L.n_chunks;
-    m.partial = partial;
-    m.tile_chunks = (int2 *)(ws + L.tiles);
-    DSPS_TRY(launch_mags_gemm(m, stream));
-    FinalizeLaunch f{};
-    f.n_band = n_band;
-    f.n_chunks = L.n_chunks;
-    f.tile_chunks = (const int2 *)(ws + L.tiles);
-    f.s_begin = s0;
-    f.s_count = cnt;
-    f.partial = partial;
-    f.mag_offset = offset;
-    f.perm = perm;
-    f.mags = mags;
-    f.bands = bands;
-    DSPS_TRY(launch_mags_finalize(f, stream));
+    DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, precision, L, ws, s0, cnt, mags, bands, moments,
+                        stream));
   }
   return DSPS_OK;
 }
 
 int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
                   const dsps_pop *pop, int precision, const float *mags_bar, const float *bands,
-                  double *sfr_bar, double *sfh_params_bar, float *lgmet_bar, float *sigma_bar,
-                  float *av_bar, float *delta_bar, float *bump_bar, void *workspace,
-                  size_t workspace_bytes, hipStream_t stream) {
+                  const float *moments, double *sfr_bar, double *sfh_params_bar, float *lgmet_bar,
+                  float *sigma_bar, float *av_bar, float *delta_bar, float *bump_bar,
+                  void *workspace, size_t workspace_bytes, hipStream_t stream) {
   DSPS_CHECK(ssp && filters, DSPS_ERR_ARG, "ssp or filters is NULL");
   DSPS_TRY(check_cosmo(cosmo));
   DSPS_TRY(check_pop(pop, true));
@@ -656,6 +673,8 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
   DSPS_CHECK(precision == DSPS_FP32, DSPS_ERR_UNSUPPORTED, "the adjoint runs in float32 only");
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(mags_bar, DSPS_ERR_ARG, "mags_bar is NULL");
+  DSPS_CHECK((bands == nullptr) == (moments == nullptr), DSPS_ERR_ARG,
+             "bands and moments must be given together or both be NULL");
   DSPS_CHECK(!sfh_params_bar || pop->sfh_params, DSPS_ERR_ARG,
              "sfh_params_bar requires the population to carry sfh_params");
   DSPS_TRY(check_device(ssp->device));
@@ -665,54 +684,30 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
   DSPS_TRY(check_workspace(workspace, workspace_bytes, L.total));
   char *ws = (char *)workspace;
   int *perm = (int *)(ws + L.perm);
-  GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
-  GalaxyRange *range = (GalaxyRange *)(ws + L.range);
-  double *offset = (double *)(ws + L.offset);
-  float *fwd_bands = bands ? nullptr : (float *)(ws + L.fbands);
-  float *fwd_mags = (float *)(ws + L.fbands) + (size_t)pop->n_gal * 2 * n_band;
+  float *fwd = (float *)(ws + L.fbands);
+  float *fwd_bands = fwd;
+  float *fwd_mom = fwd + (size_t)pop->n_gal * 2 * n_band;
+  float *fwd_mags = fwd + (size_t)pop->n_gal * 5 * n_band;
   const float *use_bands = bands ? bands : fwd_bands;
+  const float *use_mom = moments ? moments : fwd_mom;
   DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), perm, stream));
   for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
     const int cnt = std::min(L.batch, pop->n_gal - s0);
-    WeightsLaunch a = base_weights(ssp, cosmo, pop);
-    a.perm = perm;
-    a.s_begin = s0;
-    a.s_count = cnt;
-    a.w_pad = ws + L.w;
-    a.w_pad_bf16 = 0;
-    a.meta = meta;
-    a.range = range;
-    a.mag_offset = offset;
-    a.obs_lo = filters->obs_lo;
-    a.obs_hi = filters->obs_hi;
-    DSPS_TRY(launch_weights(a, stream));
-    if (!bands) {
-      MagsLaunch m{};
-      m.ssp = ssp->v;
-      m.flt = filters->v;
-      m.precision = DSPS_FP32;
-      m.s_begin = s0;
-      m.s_count = cnt;
-      m.w_pad = ws + L.w;
-      m.meta = meta;
-      m.range = range;
-      m.n_groups = L.n_groups;
-      m.n_chunks = L.n_chunks;
-      m.partial = (float *)(ws + L.partial);
-      m.tile_chunks = (int2 *)(ws + L.tiles);
-      DSPS_TRY(launch_mags_gemm(m, stream));
-      FinalizeLaunch f{};
-      f.n_band = n_band;
-      f.n_chunks = L.n_chunks;
-      f.tile_chunks = (const int2 *)(ws + L.tiles);
-      f.s_begin = s0;
-      f.s_count = cnt;
-      f.partial = (const float *)(ws + L.partial);
-      f.mag_offset = offset;
-      f.perm = perm;
-      f.mags = fwd_mags;
-      f.bands = fwd_bands;
-      DSPS_TRY(launch_mags_finalize(f, stream));
+    if (bands) {
+      // only the per-galaxy scalars and windows are needed (no weight rows)
+      WeightsLaunch a = base_weights(ssp, cosmo, pop);
+      a.perm = perm;
+      a.s_begin = s0;
+      a.s_count = cnt;
+      a.meta = (GalaxyMeta *)(ws + L.meta);
+      a.range = (GalaxyRange *)(ws + L.range);
+      a.mag_offset = (double *)(ws + L.offset);
+      a.obs_lo = filters->obs_lo;
+      a.obs_hi = filters->obs_hi;
+      DSPS_TRY(launch_weights(a, stream));
+    } else {
+      DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, fwd_mags, fwd_bands,
+                          fwd_mom, stream));
     }
     VjpLaunch v{};
     v.ssp = ssp->v;
@@ -724,11 +719,11 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
     v.perm = perm;
     v.mags_bar = mags_bar;
     v.bands = use_bands;
+    v.moments = use_mom;
     v.gamma = (float *)(ws + L.gamma);
-    v.meta = meta;
-    v.range = range;
-    v.w_pad = ws + L.w;
-    v.partial = (float *)(ws + L.vpartial);
+    v.meta = (const GalaxyMeta *)(ws + L.meta);
+    v.range = (const GalaxyRange *)(ws + L.range);
+    v.dust = (float *)(ws + L.dust);
     v.lbar = (float *)(ws + L.lbar);
     v.wbar = (float *)(ws + L.wbar);
     v.t_table = pop->t_table;

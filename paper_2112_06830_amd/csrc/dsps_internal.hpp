@@ -246,9 +246,14 @@ struct MagsLaunch {
   const GalaxyRange *range;
   int n_groups;                  // workgroups per tile (upper bound on its chunk groups)
   int n_chunks;                  // n_wave_pad / TILE_L
-  float *partial;                // [s_count][n_chunks][2 * n_band], chunks of the tile window
+  int moments;                   // also the three dust moments per band (float32 only)
+  // [s_count][n_chunks][ncomp * n_band], chunks of the tile window; components
+  // num, den and, with moments, the three dust moments
+  float *partial;
   int2 *tile_chunks;             // [n_tiles] first and one-past-last chunk of each tile
 };
+// Components per band of the chunk partials.
+__host__ __device__ inline int mags_components(int moments) { return moments ? 5 : 2; }
 int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream);
 
 struct FinalizeLaunch {
@@ -258,8 +263,10 @@ struct FinalizeLaunch {
   const int2 *tile_chunks;
   const double *mag_offset;
   const int *perm;
+  int moments;    // partials carry the dust moments
   float *mags;    // [n_gal][n_band] by galaxy index
   float *bands;   // [n_gal][2][n_band] or null
+  float *mom;     // [n_gal][3][n_band] or null (requires moments)
 };
 int launch_mags_finalize(const FinalizeLaunch &a, hipStream_t stream);
 
@@ -284,12 +291,12 @@ struct VjpLaunch {
   const int *perm;
   const float *mags_bar;      // [n_gal][n_band] by galaxy index
   const float *bands;         // [n_gal][2][n_band] by galaxy index
+  const float *moments;       // [n_gal][3][n_band] by galaxy index
   float *gamma;               // [n_gal][n_band] by sorted position
   const GalaxyMeta *meta;
   const GalaxyRange *range;
-  const void *w_pad;          // [s_count][k_pad] float32
-  float *partial;             // [s_count][n_groups][3]
-  float *lbar;                // [s_count][n_wave_pad]
+  float *dust;                // [s_count][3] sum_b gamma_b x each moment
+  float *lbar;                // [s_count][n_wave_pad], the tile windows
   float *wbar;                // [s_count][k_pad]
   // population (for the per-galaxy pull-back)
   const double *t_table, *sfr, *sfh_params;

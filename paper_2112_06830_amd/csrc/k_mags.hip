@@ -38,37 +38,36 @@ constexpr int NSLOT = 3;
 constexpr int EPI_ROWS = 2;
 
 // Per-galaxy sums of one chunk for bands base .. base + NSLOT - 1 (those not
-// above b_hi), reduced over the two lane halves and the two row-waves of each
-// column block, written to the chunk's partial slot.  s_red aliases the
-// operand staging area: the leading barrier orders these writes after every
-// wave's last MFMA read and after the previous pass's reads.
-__device__ __forceinline__ void write_band_slots(float (&num)[2][NSLOT], float (&den)[2][NSLOT],
-                                                 int base, int b_hi, int n_band, float *s_red,
-                                                 int wr, int wc, int lane, int nvalid,
-                                                 float *out_base, int stride) {
+// above b_hi), NCOMP components each, reduced over the two lane halves and
+// the two row-waves of each column block and written to the chunk's partial
+// slot (component c of band b at c * n_band + b).  s_red aliases the operand
+// staging area: the leading barrier orders these writes after every wave's
+// last MFMA read and after the previous pass's reads.
+template <int NCOMP>
+__device__ __forceinline__ void write_band_slots(float (&sum)[NCOMP][2][NSLOT], int base, int b_hi,
+                                                 int n_band, float *s_red, int wr, int wc, int lane,
+                                                 int nvalid, float *out_base, int stride) {
   const int h = lane >> 5;
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb)
+  for (int c = 0; c < NCOMP; ++c)
 #pragma unroll
-    for (int k = 0; k < NSLOT; ++k) {
-      num[nb][k] += __shfl_xor(num[nb][k], 32, 64);
-      den[nb][k] += __shfl_xor(den[nb][k], 32, 64);
-    }
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int k = 0; k < NSLOT; ++k) sum[c][nb][k] += __shfl_xor(sum[c][nb][k], 32, 64);
   // Lane half h finishes column block nb = h.  Every array index below is a
   // compile-time constant (a runtime-selected index would move the
   // accumulators to scratch memory).
   const int col = h * 32 + (lane & 31);
-  float *red = s_red + (wc * 64 + col) * (2 * NSLOT);
+  float *red = s_red + (wc * 64 + col) * (NCOMP * NSLOT);
   __syncthreads();
   if (wr == 1) {
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
       if (h == nb) {
 #pragma unroll
-        for (int k = 0; k < NSLOT; ++k) {
-          red[k] = num[nb][k];
-          red[NSLOT + k] = den[nb][k];
-        }
+        for (int c = 0; c < NCOMP; ++c)
+#pragma unroll
+          for (int k = 0; k < NSLOT; ++k) red[c * NSLOT + k] = sum[c][nb][k];
       }
     }
   }
@@ -83,8 +82,9 @@ __device__ __forceinline__ void write_band_slots(float (&num)[2][NSLOT], float (
 #pragma unroll
           for (int k = 0; k < NSLOT; ++k) {
             if (base + k <= b_hi) {
-              out[base + k] = num[nb][k] + red[k];
-              out[n_band + base + k] = den[nb][k] + red[NSLOT + k];
+#pragma unroll
+              for (int c = 0; c < NCOMP; ++c)
+                out[c * n_band + base + k] = sum[c][nb][k] + red[c * NSLOT + k];
             }
           }
         }
@@ -93,14 +93,15 @@ __device__ __forceinline__ void write_band_slots(float (&num)[2][NSLOT], float (
   }
 }
 
-// Three workgroups per CU (at most 168 VGPRs).  The cross-wave reduction
-// buffer of the epilogue reuses the operand staging area, which is idle by
-// then.
-template <int PREC>
-__global__ __launch_bounds__(GEMM_THREADS, 3) void k_mags_gemm(MagsLaunch a) {
+// Three workgroups per CU (at most 168 VGPRs); with the dust moments (MOM),
+// whose extra sums need more registers, two.  The cross-wave reduction buffer
+// of the epilogue reuses the operand staging area, which is idle by then.
+template <int PREC, bool MOM>
+__global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLaunch a) {
   using C = GemmCfg<PREC>;
   using elem = typename C::elem;
-  static_assert(sizeof(GemmSmem<PREC>) >= sizeof(float) * 2 * 64 * 2 * DSPS_MAX_BAND, "reduction alias");
+  constexpr int NCOMP = MOM ? 5 : 2;
+  static_assert(sizeof(GemmSmem<PREC>) >= sizeof(float) * 128 * NCOMP * NSLOT, "reduction alias");
   __shared__ GemmSmem<PREC> sm;
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 3) void k_mags_gemm(MagsLaunch a) {
   const int j_first = met_mask ? __builtin_ctz(met_mask) : 0;
   const elem *st = PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16;
   const elem *w = (const elem *)a.w_pad;
-  const int n_comp = 2 * n_band;
+  const int n_comp = NCOMP * n_band;
   float *part_tile = a.partial + (size_t)g0 * a.n_chunks * n_comp;
 
   for (int c = c_begin; c < c_end; ++c) {
@@ -237,11 +238,15 @@ __global__ __launch_bounds__(GEMM_THREADS, 3) void k_mags_gemm(MagsLaunch a) {
         w0[k] = gr.x;
         wi[k] = gr.y;
       }
-      float num[2][NSLOT], den[2][NSLOT];
+      // components: num, den, then with MOM the moments of k_lambda,
+      // k0 (lambda/5500)^delta log2(lambda/5500) and the bump profile
+      float sum[NCOMP][2][NSLOT];
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
+      for (int c = 0; c < NCOMP; ++c)
 #pragma unroll
-        for (int k = 0; k < NSLOT; ++k) { num[nb][k] = 0.0f; den[nb][k] = 0.0f; }
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+          for (int k = 0; k < NSLOT; ++k) sum[c][nb][k] = 0.0f;
       // An offset the compiler cannot see through keeps the per-row LDS reads
       // below inside the pass (hoisted out of it they would pin 64 registers).
       int zero;
@@ -253,20 +258,30 @@ __global__ __launch_bounds__(GEMM_THREADS, 3) void k_mags_gemm(MagsLaunch a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int row = wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-          const float4 lc = lcp[row];
+          const float4 lc = lcp[row];   // (lambda, log2(lambda/5500), k0, drude shape)
           const float lam = lc.x;
           const float q = qp[row];
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb) {
             const float lobs = zp1[nb] * lam;
-            const float powl = exp2f(dl[nb] * lc.y);
-            const float att = exp2f(da[nb] * (lc.z * powl + bp[nb] * lc.w));
+            // rounding fixed explicitly, so that both instantiations agree bit
+            // for bit whatever the compiler contracts
+            const float k0x = __fmul_rn(lc.z, exp2f(dl[nb] * lc.y));  // k0 (lambda/5500)^delta
+            const float kl = fmaf(bp[nb], lc.w, k0x);                 // k_lambda
+            const float att = exp2f(da[nb] * kl);
             const float e = acc[mb][nb][r] * att * q;
+            float x[3];
+            if (MOM) { x[0] = e * kl; x[1] = e * k0x * lc.y; x[2] = e * lc.w; }
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
               const float t = filter_pair_at(tab[k], n_int, (lobs - w0[k]) * wi[k]);
-              num[nb][k] += t * e;
-              den[nb][k] += t * q;
+              sum[0][nb][k] += t * e;
+              sum[1][nb][k] += t * q;
+              if (MOM) {
+                sum[2 % NCOMP][nb][k] += t * x[0];
+                sum[3 % NCOMP][nb][k] += t * x[1];
+                sum[4 % NCOMP][nb][k] += t * x[2];
+              }
             }
           }
           // bound the scheduler's look-ahead: batching the lookups of a few
@@ -274,7 +289,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 3) void k_mags_gemm(MagsLaunch a) {
           if ((r & (EPI_ROWS - 1)) == EPI_ROWS - 1) __builtin_amdgcn_sched_barrier(0);
         }
       }
-      write_band_slots(num, den, base, b_hi, n_band, s_red, wr, wc, lane, nvalid, part, stride);
+      write_band_slots<NCOMP>(sum, base, b_hi, n_band, s_red, wr, wc, lane, nvalid, part, stride);
     }
     // bands that see none of this chunk contribute exact zeros
     if (wr == 0) {
@@ -282,7 +297,10 @@ __global__ __launch_bounds__(GEMM_THREADS, 3) void k_mags_gemm(MagsLaunch a) {
       if (tcol < nvalid) {
         float *out = part + (size_t)tcol * stride;
         for (int b = 0; b < n_band; ++b) {
-          if (b < b_lo || b > b_hi) { out[b] = 0.0f; out[n_band + b] = 0.0f; }
+          if (b < b_lo || b > b_hi) {
+#pragma unroll
+            for (int c = 0; c < NCOMP; ++c) out[c * n_band + b] = 0.0f;
+          }
         }
       }
     }
@@ -295,10 +313,14 @@ int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
   const int blocks = (n_tiles + 7) / 8 * 8 * a.n_groups;
   const size_t lds = sizeof(float2) * a.flt.n_band * (a.flt.n_pts - 1);
   ProfScope prof(DSPS_KERNEL_MAGS_GEMM, stream);
-  if (a.precision == DSPS_BF16)
-    hipLaunchKernelGGL(k_mags_gemm<DSPS_BF16>, dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);
-  else
-    hipLaunchKernelGGL(k_mags_gemm<DSPS_FP32>, dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);
+  if (a.precision == DSPS_BF16) {
+    if (a.moments) return DSPS_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_mags_gemm<DSPS_BF16, false>), dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);
+  } else if (a.moments) {
+    hipLaunchKernelGGL((k_mags_gemm<DSPS_FP32, true>), dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);
+  } else {
+    hipLaunchKernelGGL((k_mags_gemm<DSPS_FP32, false>), dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);
+  }
   return hip_fail(hipGetLastError(), "k_mags_gemm launch");
 }
 
@@ -309,7 +331,7 @@ __global__ void k_mags_finalize(FinalizeLaunch a) {
   if (local >= a.s_count) return;
   const int s = a.s_begin + local;
   const int g = a.perm ? a.perm[s] : s;
-  const int nb = a.n_band, nc = 2 * nb;
+  const int nb = a.n_band, nc = mags_components(a.moments) * nb;
   const int2 cr = a.tile_chunks[local / TILE_G];
   const float *p = a.partial + (size_t)local * a.n_chunks * nc;
   const double offset = a.mag_offset[s];
@@ -324,8 +346,15 @@ __global__ void k_mags_finalize(FinalizeLaunch a) {
     else m = -2.5 * log10((double)num / (AB_ZERO_POINT * (double)den)) + offset;
     a.mags[(size_t)g * nb + b] = (float)m;
     if (a.bands) {
-      a.bands[(size_t)g * nc + b] = num;
-      a.bands[(size_t)g * nc + nb + b] = den;
+      a.bands[(size_t)g * 2 * nb + b] = num;
+      a.bands[(size_t)g * 2 * nb + nb + b] = den;
+    }
+    if (a.mom) {
+      for (int k = 0; k < 3; ++k) {
+        float v = 0.0f;
+        for (int c = cr.x; c < cr.y; ++c) v += p[c * nc + (2 + k) * nb + b];
+        a.mom[(size_t)g * 3 * nb + k * nb + b] = v;
+      }
     }
   }
 }

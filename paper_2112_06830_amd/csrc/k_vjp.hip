@@ -7,13 +7,15 @@
 //   G(l)      = sum_b gamma_b T_b((1+z) l) q_l                (cotangent of F L)
 //   Lbar(l)   = G(l) F(l)                                     (cotangent of the SED)
 //   Wbar[k]   = sum_l Lbar(l) L_SSP[k, l]                     (transposed contraction)
-//   A_V, delta, bump: sum_l G L dF/dtheta with F = 10^(-0.4 A_V k_lambda / 4.05)
+//   A_V, delta, bump: sum_l G L dF/dtheta with F = 2^(dust_a k_lambda); since
+//   dF/dtheta is F times a per-wavelength factor, this is sum_b gamma_b times
+//   the forward pass's dust moment of band b
 // then Wbar -> (metallicity weights -> lgmet, sigma_Z) and (age-bin masses ->
 // cumulative mass -> SFR table -> parametric SFH) in float64.
 //
-// Kernels: k_vjp_gamma (per galaxy), k_vjp_gemm (the forward tile recomputed
-// on MFMA, never stored; its epilogue writes Lbar and the three dust sums),
-// k_vjp_wbar (Lbar . SSP^T on MFMA), k_vjp_weights (one wave per galaxy).
+// Kernels: k_vjp_gamma (per galaxy: gamma and the dust sums), k_vjp_lbar
+// (Lbar over each tile's wavelength window; no SED needed), k_vjp_wbar
+// (Lbar . SSP^T on MFMA), k_vjp_weights (one wave per galaxy).
 #include "gemm_core.hpp"
 
 namespace dsps {
@@ -28,236 +30,90 @@ __global__ void k_vjp_gamma(VjpLaunch a) {
   const int s = a.s_begin + local;
   const int g = a.perm[s];
   const int nb = a.n_band;
+  const float *mom = a.moments + (size_t)g * 3 * nb;
+  double dust[3] = {0.0, 0.0, 0.0};
   for (int b = 0; b < nb; ++b) {
     const float num = a.bands[(size_t)g * 2 * nb + b];
     const float bar = a.mags_bar[(size_t)g * nb + b];
     // a zero cotangent contributes nothing, also for a band with num = 0
-    a.gamma[(size_t)s * nb + b] = bar == 0.0f ? 0.0f : -2.5f * bar / (LN10_F * num);
+    const float gam = bar == 0.0f ? 0.0f : -2.5f * bar / (LN10_F * num);
+    a.gamma[(size_t)s * nb + b] = gam;
+    if (gam != 0.0f)
+      for (int k = 0; k < 3; ++k) dust[k] += (double)gam * (double)mom[k * nb + b];
   }
+  for (int k = 0; k < 3; ++k) a.dust[(size_t)local * 3 + k] = (float)dust[k];
 }
 
-// Forward tile recomputed; epilogue forms Lbar and the dust-gradient sums.
-__global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_gemm(VjpLaunch a) {
-  using C = GemmCfg<DSPS_FP32>;
-  __shared__ GemmSmem<DSPS_FP32> sm;
-  __shared__ float4 s_lc[TILE_L];
-  __shared__ float s_q[TILE_L];
-  __shared__ float s_red[2][64][3];
+// Lbar(l) = (q_l sum_b gamma_b T_b((1+z) l)) F(l) for every galaxy of a tile
+// and every wavelength of the tile's window (zero where no band sees it),
+// which is the range the transposed contraction reads.  Block (group, tile)
+// covers chunks of the window as the forward kernel groups them; thread
+// (li, gh) holds rest wavelength l0 + li and galaxies gh, gh + 2, ..., so a
+// row of 128 wavelengths leaves as one coalesced store.  The band loop runs
+// over the bands that can see the chunk for some galaxy of the tile, in
+// ascending order, as the forward pass sums them.
+__global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
   __shared__ float s_gam[TILE_G * DSPS_MAX_BAND];
+  __shared__ float4 s_meta[TILE_G];    // (1 + z, dust_a, delta, bump)
   __shared__ float2 s_grid[DSPS_MAX_BAND];
-  // window lo, window hi, metallicity-row mask, age hi, min and max of (1+z)
-  // as float bits
-  __shared__ int s_tile[6];
+  __shared__ int s_tile[4];            // window lo, window hi, min and max of (1+z) bits
   extern __shared__ float2 s_pair[];   // [n_band][n_pts - 1] filter intervals
-
   const int group = blockIdx.x, tile = blockIdx.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
   const SspView P = a.ssp;
   const FilterView F = a.flt;
-  const int n_band = F.n_band, n_pts = F.n_pts;
+  const int n_band = F.n_band, n_int = F.n_pts - 1;
   const int g0 = tile * TILE_G;
   const int nvalid = min(TILE_G, a.s_count - g0);
+  const int nwp = P.n_wave_pad;
 
-  if (threadIdx.x == 0) {
-    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0; s_tile[3] = 0;
-    s_tile[4] = 0x7f7fffff; s_tile[5] = 0;
-  }
+  if (threadIdx.x == 0) { s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0; }
   __syncthreads();
   if (threadIdx.x < nvalid) {
     const GalaxyRange r = a.range[a.s_begin + g0 + threadIdx.x];
-    const int zbits = __float_as_int(a.meta[a.s_begin + g0 + threadIdx.x].zp1);
+    const GalaxyMeta m = a.meta[a.s_begin + g0 + threadIdx.x];
     atomicMin(&s_tile[0], r.win_lo);
     atomicMax(&s_tile[1], r.win_hi);
-    atomicMin(&s_tile[4], zbits);
-    atomicMax(&s_tile[5], zbits);
-    if (r.age_hi > 0) {
-      const int jl = r.met_lo_hi & 0xFFFF, jh = r.met_lo_hi >> 16;
-      atomicOr(&s_tile[2], (int)(((1u << (jh + 1)) - 1u) & ~((1u << jl) - 1u)));
-      atomicMax(&s_tile[3], r.age_hi);
-    }
+    atomicMin(&s_tile[2], __float_as_int(m.zp1));
+    atomicMax(&s_tile[3], __float_as_int(m.zp1));
+    s_meta[threadIdx.x] = make_float4(m.zp1, m.dust_a, m.delta, m.bump);
   }
   __syncthreads();
-  const int win_lo = s_tile[0], win_hi = s_tile[1];
-  const unsigned met_mask = (unsigned)s_tile[2];
-  const int age_hi = s_tile[3];
-  const float zp1_min = __int_as_float(s_tile[4]), zp1_max = __int_as_float(s_tile[5]);
-  const int c_first = win_lo / TILE_L;
-  const int c_last = (win_hi + TILE_L - 1) / TILE_L;
+  const int c_first = s_tile[0] / TILE_L;
+  const int c_last = (s_tile[1] + TILE_L - 1) / TILE_L;
+  const float zp1_min = __int_as_float(s_tile[2]), zp1_max = __int_as_float(s_tile[3]);
   const int c_begin = max(group * CHUNKS_PER_GROUP, c_first);
   const int c_end = min((group + 1) * CHUNKS_PER_GROUP, c_last);
-
-  if (c_begin >= c_end) {
-    for (int idx = threadIdx.x; idx < nvalid * 3; idx += GEMM_THREADS) {
-      const int gl = idx / 3, v = idx % 3;
-      a.partial[((size_t)(g0 + gl) * a.n_groups + group) * 3 + v] = 0.0f;
-    }
-    return;
-  }
-  const int n_int = n_pts - 1;
+  if (c_begin >= c_end) return;
   fill_filter_pairs(F, s_pair);
-
-  // Per-galaxy gamma and the filter grids are read from LDS with a runtime
-  // band index (per-band registers for 64 elements per lane would exhaust
-  // the register file).
-  for (int i = threadIdx.x; i < TILE_G * n_band; i += GEMM_THREADS) {
+  for (int i = threadIdx.x; i < TILE_G * n_band; i += blockDim.x) {
     const int col = i / n_band, b = i % n_band;
     s_gam[col * DSPS_MAX_BAND + b] =
         col < nvalid ? a.gamma[(size_t)(a.s_begin + g0 + col) * n_band + b] : 0.0f;
   }
   if (threadIdx.x < n_band) s_grid[threadIdx.x] = F.grid[threadIdx.x];
-  float zp1[2], da[2], dl[2], bp[2];
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    const int col = wc * 64 + nb * 32 + (lane & 31);
-    if (col < nvalid) {
-      const GalaxyMeta m = a.meta[a.s_begin + g0 + col];
-      zp1[nb] = m.zp1; da[nb] = m.dust_a; dl[nb] = m.delta; bp[nb] = m.bump;
-    } else {
-      zp1[nb] = 1.0f; da[nb] = 0.0f; dl[nb] = 0.0f; bp[nb] = 0.0f;
-    }
-  }
-  float s_k[2] = {0.0f, 0.0f}, s_pw[2] = {0.0f, 0.0f}, s_d[2] = {0.0f, 0.0f};
+  __syncthreads();
 
-  const int n_ab = (age_hi + C::KT - 1) / C::KT;
-  const int nk = __builtin_popcount(met_mask) * n_ab;
-  const int j_first = met_mask ? __builtin_ctz(met_mask) : 0;
-  const float *st = P.st32;
-  const float *w = (const float *)a.w_pad;
-  const int nwp = P.n_wave_pad;
-
+  const int li = threadIdx.x & (TILE_L - 1), gh = threadIdx.x >> 7;
   for (int c = c_begin; c < c_end; ++c) {
-    const int l0 = c * TILE_L;
-    __syncthreads();
-    if (threadIdx.x < TILE_L) {
-      s_lc[threadIdx.x] = P.lconst[l0 + threadIdx.x];
-      s_q[threadIdx.x] = P.qweight[l0 + threadIdx.x];
-    }
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
-    StageRegs<DSPS_FP32> regs;
-    int j_cur = j_first, ab_cur = 0;
-    if (nk > 0) load_stage<DSPS_FP32>(regs, st, P.k_pad, l0, w, g0, a.s_count, j_cur * AGE_PAD);
-    for (int ks = 0; ks < nk; ++ks) {
-      __syncthreads();
-      store_stage<DSPS_FP32>(regs, sm);
-      __syncthreads();
-      if (ks + 1 < nk) {
-        if (++ab_cur == n_ab) {
-          ab_cur = 0;
-          j_cur = __builtin_ctz(met_mask & ~((2u << j_cur) - 1u));
-        }
-        load_stage<DSPS_FP32>(regs, st, P.k_pad, l0, w, g0, a.s_count, j_cur * AGE_PAD + ab_cur * C::KT);
-      }
-      mma_stage(sm, wr, wc, lane, acc);
-    }
-    __syncthreads();
-
-    // Bands that can see this chunk for some galaxy of the tile (the others
-    // add exact zeros to every sum below).  For each group of four rows (one
-    // 16-byte Lbar store per column) the band loop runs outside the elements,
-    // so the lookups of the group issue together.
+    const int l = c * TILE_L + li;
+    const float4 lc = P.lconst[l];     // (lambda, log2(lambda/5500), k0, drude shape)
+    const float q = P.qweight[l];
     const unsigned bmask = __builtin_amdgcn_readfirstlane(
-        active_bands(F, zp1_min * s_lc[0].x, zp1_max * s_lc[TILE_L - 1].x));
+        active_bands(F, zp1_min * P.lconst[c * TILE_L].x, zp1_max * P.lconst[c * TILE_L + TILE_L - 1].x));
     const int b_lo = bmask ? __builtin_ctz(bmask) : 0;
     const int n_act = bmask ? 32 - __builtin_clz(bmask) - b_lo : 0;
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-#pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        const int row0 = wr * 64 + mb * 32 + 8 * r4 + 4 * h;
-        float lobs[4][2], gs[4][2];
-#pragma unroll
-        for (int r1 = 0; r1 < 4; ++r1) {
-          const float lam = s_lc[row0 + r1].x;
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb) { lobs[r1][nb] = zp1[nb] * lam; gs[r1][nb] = 0.0f; }
-        }
-        // G = sum_b gamma_b T_b in ascending band order
-        for (int k = 0; k < n_act; ++k) {
-          const int b = b_lo + k;
-          const float2 gr = s_grid[b];
-          const float2 *tab = s_pair + b * n_int;
-          float gam[2];
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb) gam[nb] = s_gam[(wc * 64 + nb * 32 + (lane & 31)) * DSPS_MAX_BAND + b];
-#pragma unroll
-          for (int r1 = 0; r1 < 4; ++r1)
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
-              gs[r1][nb] += gam[nb] * filter_pair_at(tab, n_int, (lobs[r1][nb] - gr.x) * gr.y);
-        }
-        float out4[2][4];
-#pragma unroll
-        for (int r1 = 0; r1 < 4; ++r1) {
-          const int r = 4 * r4 + r1;
-          const float4 lc = s_lc[row0 + r1];
-          const float q = s_q[row0 + r1];
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb) {
-            const float powl = exp2f(dl[nb] * lc.y);
-            const float kl = lc.z * powl + bp[nb] * lc.w;      // k_lambda
-            const float att = exp2f(da[nb] * kl);
-            const float gsum = gs[r1][nb] * q;
-            acc[mb][nb][r] *= gsum * att;                      // e = G F L
-            out4[nb][r1] = gsum * att;
-          }
-        }
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          const int col = wc * 64 + nb * 32 + (lane & 31);
-          if (col < nvalid)
-            *reinterpret_cast<float4 *>(a.lbar + (size_t)(g0 + col) * nwp + l0 + row0) =
-                make_float4(out4[nb][0], out4[nb][1], out4[nb][2], out4[nb][3]);
-        }
+    for (int col = gh; col < nvalid; col += 2) {
+      const float4 m = s_meta[col];
+      const float lobs = m.x * lc.x;
+      float gs = 0.0f;
+      for (int k = 0; k < n_act; ++k) {
+        const int b = b_lo + k;
+        const float2 gr = s_grid[b];
+        gs += s_gam[col * DSPS_MAX_BAND + b] * filter_pair_at(s_pair + b * n_int, n_int, (lobs - gr.x) * gr.y);
       }
-    }
-    // second pass: dust-gradient sums over e = G F L (the per-row factors are
-    // recomputed; holding them from the first pass exhausts the registers)
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        const float4 lc = s_lc[row];
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          const float e = acc[mb][nb][r];
-          const float k0x = lc.z * exp2f(dl[nb] * lc.y);    // k0 (lambda/5500)^delta
-          s_k[nb] += e * (k0x + bp[nb] * lc.w);
-          s_pw[nb] += e * k0x * lc.y;
-          s_d[nb] += e * lc.w;
-        }
-      }
-    }
-  }
-
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    s_k[nb] += __shfl_xor(s_k[nb], 32, 64);
-    s_pw[nb] += __shfl_xor(s_pw[nb], 32, 64);
-    s_d[nb] += __shfl_xor(s_d[nb], 32, 64);
-  }
-  __syncthreads();
-  const int my_nb = h;
-  const int col = my_nb * 32 + (lane & 31);
-  const float v0 = my_nb ? s_k[1] : s_k[0];
-  const float v1 = my_nb ? s_pw[1] : s_pw[0];
-  const float v2 = my_nb ? s_d[1] : s_d[0];
-  if (wr == 1) { s_red[wc][col][0] = v0; s_red[wc][col][1] = v1; s_red[wc][col][2] = v2; }
-  __syncthreads();
-  if (wr == 0) {
-    const int tcol = wc * 64 + col;
-    if (tcol < nvalid) {
-      float *out = a.partial + ((size_t)(g0 + tcol) * a.n_groups + group) * 3;
-      out[0] = v0 + s_red[wc][col][0];
-      out[1] = v1 + s_red[wc][col][1];
-      out[2] = v2 + s_red[wc][col][2];
+      const float k0x = __fmul_rn(lc.z, exp2f(m.z * lc.y));
+      const float att = exp2f(m.y * fmaf(m.w, lc.w, k0x));
+      a.lbar[(size_t)(g0 + col) * nwp + l] = (gs * q) * att;
     }
   }
 }
@@ -539,13 +395,8 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   if (lane == 0) {
     if (a.lgmet_bar) a.lgmet_bar[g] = (float)d_lgmet;
     if (a.sigma_bar) a.sigma_bar[g] = (float)d_sig;
-    double sk = 0.0, spw = 0.0, sd = 0.0;
-    const float *p = a.partial + (size_t)local * a.n_groups * 3;
-    for (int gr = 0; gr < a.n_groups; ++gr) {
-      sk += p[3 * gr];
-      spw += p[3 * gr + 1];
-      sd += p[3 * gr + 2];
-    }
+    const float *p = a.dust + (size_t)local * 3;
+    const double sk = p[0], spw = p[1], sd = p[2];
     // dF/dA_V = F (-0.4 ln10 / 4.05) k;  dF/d delta = F (-0.4 ln10 A_V / 4.05)
     // k0 (l/5500)^delta ln(l/5500);  dF/d bump = F (-0.4 ln10 A_V / 4.05) D
     const double c1 = -0.4 * LN10_D / DUST_RV;
@@ -562,9 +413,9 @@ int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
   if (stage == 0) {
     hipLaunchKernelGGL(k_vjp_gamma, dim3((a.s_count + 255) / 256), dim3(256), 0, stream, a);
   } else if (stage == 1) {
-    ProfScope prof(DSPS_KERNEL_VJP_GEMM, stream);
+    ProfScope prof(DSPS_KERNEL_VJP_LBAR, stream);
     const size_t lds = sizeof(float2) * a.flt.n_band * (a.flt.n_pts - 1);
-    hipLaunchKernelGGL(k_vjp_gemm, dim3(a.n_groups, tiles), dim3(GEMM_THREADS), lds, stream, a);
+    hipLaunchKernelGGL(k_vjp_lbar, dim3(a.n_groups, tiles), dim3(256), lds, stream, a);
   } else if (stage == 2) {
     ProfScope prof(DSPS_KERNEL_VJP_WBAR, stream);
     hipLaunchKernelGGL(k_vjp_wbar, dim3(a.ssp.sk_rows / TILE_L, tiles), dim3(GEMM_THREADS), 0, stream, a);

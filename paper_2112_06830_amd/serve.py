@@ -203,6 +203,7 @@ class _Slot:
             self.targets = self.d_in32[6:6 + nb].t()          # [cap, nb] view
             self.valid = self.d_in32[6 + nb]
             self.bands = torch.empty((cap, 2, nb), dtype=f32, device=d)
+            self.moments = torch.empty((cap, 3, nb), dtype=f32, device=d)
             self.bar = torch.empty((cap, nb), dtype=f32, device=d)
             self.ws_b = api.Workspace(api.workspace_size(3, eng.ssp_h, eng.flt_h, cap, eng.n_t, "fp32"), d)
             self.g64 = torch.empty((5, cap), dtype=f64, device=d)
@@ -225,12 +226,12 @@ class _Slot:
         if self.kind == KIND_FWD:
             api.mags(e.ssp_h, e.flt_h, e.cosmo, self.pop, precision="bf16", workspace=self.ws, out=self.mags)
         else:
-            api.mags(e.ssp_h, e.flt_h, e.cosmo, self.pop, precision="fp32", with_bands=True,
-                     workspace=self.ws, out=self.mags, bands_out=self.bands)
+            api.mags(e.ssp_h, e.flt_h, e.cosmo, self.pop, precision="fp32", with_moments=True,
+                     workspace=self.ws, out=self.mags, bands_out=self.bands, moments_out=self.moments)
             torch.sub(self.mags, self.targets, out=self.bar)
             self.bar.mul_(self.valid[:, None] * 2.0)
             api.mags_vjp(e.ssp_h, e.flt_h, e.cosmo, self.pop, self.bar, bands=self.bands,
-                         workspace=self.ws_b, outs=self.outs)
+                         moments=self.moments, workspace=self.ws_b, outs=self.outs)
 
     def capture(self, stream):
         self.h_in32[0].fill_(PAD_Z)     # inert galaxies for the eager warm-up
@@ -270,7 +271,7 @@ class ServeEngine:
             ws = api.workspace_size(2, self.ssp_h, self.flt_h, ref, n_t, prec)
             if kind == KIND_GRAD:
                 ws += api.workspace_size(3, self.ssp_h, self.flt_h, ref, n_t, "fp32")
-            io = 5 * 8 + 7 * 4 + self.n_band * 4 * (1 if kind == KIND_FWD else 5) + (60 if kind == KIND_GRAD else 0)
+            io = 5 * 8 + 7 * 4 + self.n_band * 4 * (1 if kind == KIND_FWD else 8) + (60 if kind == KIND_GRAD else 0)
             bpg[kind] = int(math.ceil(ws / ref)) + io
         self.planner = AdmissionPlanner(buckets, bpg, hbm_budget_bytes, slots_per_bucket,
                                         max_inflight_per_kind)
@@ -496,9 +497,9 @@ def serial_baseline(ssp_h, flt_h, cosmo, t_table, arrivals, reqs):
                                    *(torch.tensor(getattr(r, k), device=d) for k in
                                      ("z", "lgmet", "sigma_z", "av", "delta", "bump")))
         if r.grad:
-            m, bands = api.mags(ssp_h, flt_h, cosmo, pop, precision="fp32", with_bands=True)
+            m, bands, mom = api.mags(ssp_h, flt_h, cosmo, pop, precision="fp32", with_moments=True)
             bar = 2.0 * (m - torch.tensor(r.targets, device=d))
-            api.mags_vjp(ssp_h, flt_h, cosmo, pop, bar, bands=bands)
+            api.mags_vjp(ssp_h, flt_h, cosmo, pop, bar, bands=bands, moments=mom)
         else:
             api.mags(ssp_h, flt_h, cosmo, pop, precision="fp32")
         torch.cuda.synchronize()

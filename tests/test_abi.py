@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_error_string(lib):
-    assert lib.dsps_abi_version() == 1
+    assert lib.dsps_abi_version() == 2
     assert isinstance(lib.dsps_last_error(), bytes)
 
 
@@ -73,7 +73,8 @@ def test_host_side_argument_checks_fail_before_any_launch(lib):
     assert lib.dsps_workspace_size(2, None, None, 10, 10, 0, ctypes.byref(size)) == -1
     c = N.Cosmo(0.3, -1.0, 0.7)
     p = N.Pop()
-    assert lib.dsps_mags(None, None, ctypes.byref(c), ctypes.byref(p), 0, None, None, None, 0, None) == -1
+    assert lib.dsps_mags(None, None, ctypes.byref(c), ctypes.byref(p), 0, None, None, None, None, 0,
+                         None) == -1
     # zero-size requests are no-ops
     assert lib.dsps_sfh_table(None, 10, None, 0, None, None) == 0
     assert lib.dsps_quantize_bf16(None, 0, 5, None, None, None) == 0

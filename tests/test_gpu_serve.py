@@ -48,9 +48,9 @@ def _alone(S, eng, r):
                              *(torch.tensor(getattr(r, k), device=d) for k in
                                ("z", "lgmet", "sigma_z", "av", "delta", "bump")))
     if r.grad:
-        m, bands = P.mags(eng.ssp_h, eng.flt_h, eng.cosmo, pop, precision="fp32", with_bands=True)
+        m, bands, mom = P.mags(eng.ssp_h, eng.flt_h, eng.cosmo, pop, precision="fp32", with_moments=True)
         bar = 2.0 * (m - torch.tensor(r.targets, device=d))
-        g = P.mags_vjp(eng.ssp_h, eng.flt_h, eng.cosmo, pop, bar, bands=bands,
+        g = P.mags_vjp(eng.ssp_h, eng.flt_h, eng.cosmo, pop, bar, bands=bands, moments=mom,
                        want=("sfh_params", "lgmet", "sigma_z", "av", "delta", "bump"))
         return m.cpu().numpy(), {k: v.cpu().numpy() for k, v in g.items()}
     m = P.mags(eng.ssp_h, eng.flt_h, eng.cosmo, pop, precision="bf16")

@@ -71,11 +71,11 @@ def test_vjp_matches_oracle_adjoint_64_galaxies(dev, large, use_params):
     inp = oracle_inputs(ssp, pop)
     _say(f"vjp 64 galaxies use_params={use_params}")
     dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr, use_params=use_params)
-    m, bands = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)
+    m, bands, mom = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_moments=True)
     m_ref = oracle.mags(inp)
     bar = _loss_cotangent(m_ref, pop.targets)
     g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, torch.tensor(bar, dtype=torch.float32),
-                     bands=bands)
+                     bands=bands, moments=mom)
     ref = oracle.mags_vjp(inp, bar)
     for k, rk in KEYS.items():
         ok, info = grad_close(g[k].cpu().numpy(), ref[rk])
@@ -160,12 +160,47 @@ def test_vjp_recomputes_band_sums_when_not_given(dev, large):
     pop = synth.make_population(200, n_t=100, z_range=(0.1, 3.0), seed=12)
     _say("vjp bands=None vs bands given")
     dp = dev.DevicePopulation.from_synth(pop, use_params=True)
-    m, bands = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)
+    m, bands, mom = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_moments=True)
     bar = torch.tensor(_loss_cotangent(m.cpu().numpy(), pop.targets), dtype=torch.float32)
-    g1 = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bands)
-    g2 = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=None)
+    g1 = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bands, moments=mom)
+    g2 = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar)
     for k in g1:
         assert torch.equal(g1[k], g2[k]), k
+    with pytest.raises(ValueError):
+        dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bands)
+
+
+def test_dust_moments_match_oracle(dev, large):
+    """Moments of the forward pass against the FP64 oracle: each is the band
+    integral of Eq. restmag with the attenuated SED times the per-wavelength
+    factor k_lambda, k0 (l/5500)^delta log2(l/5500) or the unit bump profile;
+    the magnitudes and band sums equal those of the pass without moments bit
+    for bit."""
+    import torch
+    from oracle import dust, photometry
+    ssp_h, flt_h, ssp = large
+    pop = synth.make_population(40, n_t=100, z_range=(0.1, 3.0), seed=31)
+    inp = oracle_inputs(ssp, pop)
+    _say("dust moments vs oracle, 40 galaxies")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr, use_params=False)
+    m0, b0 = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)
+    m1, b1, mom = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_moments=True)
+    assert torch.equal(m0, m1) and torch.equal(b0, b1)
+    mom = mom.cpu().numpy().astype(np.float64)
+    sed_att = oracle.sed(inp, apply_dust=True)
+    lam = inp.wave
+    y = np.log2(lam / 5500.0)
+    for gi in range(pop.n_gal):
+        k0x = dust.k0(lam) * (lam / 5500.0) ** float(pop.delta[gi])
+        factors = (dust.k_lambda(lam, pop.delta[gi], pop.bump[gi])[0], k0x * y,
+                   dust.drude_bump(lam, 1.0))
+        for k, x in enumerate(factors):
+            ref, _ = photometry.band_integrals(lam, sed_att[gi] * x, pop.z[gi], inp.filt_wave,
+                                               inp.filt_trans)
+            scale, _ = photometry.band_integrals(lam, np.abs(sed_att[gi] * x), pop.z[gi],
+                                                 inp.filt_wave, inp.filt_trans)
+            err = np.abs(mom[gi, k] - ref)
+            assert np.all(err <= 2e-4 * scale + 1e-30), (gi, k, err / np.maximum(scale, 1e-30))
 
 
 def test_autograd_function_matches_oracle(dev, large):
@@ -198,10 +233,10 @@ def test_vjp_full_size_sampled(dev, large):
     pop = synth.make_population(200_000, n_t=100, z_range=(0.1, 3.0), seed=5)
     _say("vjp full size n_gal=200000")
     dp = dev.DevicePopulation.from_synth(pop, use_params=True)
-    m, bands = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)
+    m, bands, mom = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_moments=True)
     bar = torch.tensor(pop.targets, device="cuda", dtype=torch.float32)
     bar = 2.0 * (m - bar)
-    g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bands)
+    g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bands, moments=mom)
     torch.cuda.synchronize()
     rng = np.random.default_rng(1)
     idx = np.sort(rng.choice(pop.n_gal, 32, replace=False))

@@ -92,10 +92,18 @@ struct GalaxyMeta {
   float delta;
   float bump;
 };
+// Blocks of KBLOCK_AGES consecutive (padded) ages in one metallicity row:
+// the unit in which the contraction skips all-zero weights.
+constexpr int KBLOCK_AGES = 16;
+constexpr int KBLOCKS_PER_ROW = AGE_PAD / KBLOCK_AGES;                  // 6
+constexpr int KBLOCK_WORDS = (DSPS_MAX_MET * KBLOCKS_PER_ROW + 31) / 32;  // 3
+
 struct GalaxyRange {
-  int win_lo, win_hi;  // rest-wavelength index window [lo, hi) that any filter sees
-  int met_lo_hi;       // lowest | highest metallicity row with a non-zero weight << 16
-  int age_hi;          // one past the oldest age with a non-zero weight
+  int win_lo, win_hi;            // rest-wavelength index window [lo, hi) that any filter sees
+  // bit 6 j + a set when metallicity row j has a non-zero weight at some age
+  // in [16 a, 16 a + 16)
+  unsigned kblk[KBLOCK_WORDS];
+  int pad;
 };
 
 // ------------------------------------------------------------- device math

@@ -105,9 +105,12 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   __shared__ GemmSmem<PREC> sm;
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
-  // window lo, window hi, metallicity-row mask, age hi, min and max of (1+z)
-  // as float bits (positive floats order like their bit patterns)
-  __shared__ int s_tile[6];
+  // window lo, window hi, min and max of (1+z) as float bits (positive floats
+  // order like their bit patterns), stage count; union of the non-zero
+  // weight blocks; K offset of each stage in order
+  __shared__ int s_tile[5];
+  __shared__ unsigned s_kblk[KBLOCK_WORDS];
+  __shared__ int s_koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];
   // transmission as (T[i], T[i+1] - T[i]) per grid interval: one aligned
   // 8-byte read and one FMA per interpolation
   extern __shared__ float2 s_pair[];   // [n_band][n_pts - 1]
@@ -129,8 +132,9 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
 
   // ---- tile union of windows and non-zero weight blocks
   if (threadIdx.x == 0) {
-    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0; s_tile[3] = 0;
-    s_tile[4] = 0x7f7fffff; s_tile[5] = 0;
+    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0;
+#pragma unroll
+    for (int w = 0; w < KBLOCK_WORDS; ++w) s_kblk[w] = 0u;
   }
   __syncthreads();
   if (threadIdx.x < nvalid) {
@@ -138,19 +142,33 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
     const int zbits = __float_as_int(a.meta[a.s_begin + g0 + threadIdx.x].zp1);
     atomicMin(&s_tile[0], r.win_lo);
     atomicMax(&s_tile[1], r.win_hi);
-    atomicMin(&s_tile[4], zbits);
-    atomicMax(&s_tile[5], zbits);
-    if (r.age_hi > 0) {
-      const int jl = r.met_lo_hi & 0xFFFF, jh = r.met_lo_hi >> 16;
-      atomicOr(&s_tile[2], (int)(((1u << (jh + 1)) - 1u) & ~((1u << jl) - 1u)));
-      atomicMax(&s_tile[3], r.age_hi);
-    }
+    atomicMin(&s_tile[2], zbits);
+    atomicMax(&s_tile[3], zbits);
+#pragma unroll
+    for (int w = 0; w < KBLOCK_WORDS; ++w)
+      if (r.kblk[w]) atomicOr(&s_kblk[w], r.kblk[w]);
+  }
+  __syncthreads();
+  // stages in ascending K: a stage of KT ages covers KT / 16 blocks of a row
+  // and runs when any of them holds a weight for some galaxy of the tile
+  if (threadIdx.x == 0) {
+    constexpr int BPS = C::KT / KBLOCK_AGES;               // blocks per stage
+    int n = 0;
+    for (int j = 0; j < P.n_met; ++j)
+      for (int st = 0; st < AGE_PAD / C::KT; ++st) {
+        bool any = false;
+        for (int u = 0; u < BPS; ++u) {
+          const int bit = j * KBLOCKS_PER_ROW + st * BPS + u;
+          any |= (s_kblk[bit >> 5] >> (bit & 31)) & 1u;
+        }
+        if (any) s_koff[n++] = j * AGE_PAD + st * C::KT;
+      }
+    s_tile[4] = n;
   }
   __syncthreads();
   const int win_lo = s_tile[0], win_hi = s_tile[1];
-  const unsigned met_mask = (unsigned)s_tile[2];
-  const int age_hi = s_tile[3];
-  const float zp1_min = __int_as_float(s_tile[4]), zp1_max = __int_as_float(s_tile[5]);
+  const float zp1_min = __int_as_float(s_tile[2]), zp1_max = __int_as_float(s_tile[3]);
+  const int nk = s_tile[4];
   const int c_first = win_lo / TILE_L;
   const int c_last = max((win_hi + TILE_L - 1) / TILE_L, c_first);   // exclusive
   if (group == 0 && threadIdx.x == 0) a.tile_chunks[tile] = make_int2(c_first, c_last);
@@ -176,10 +194,7 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
     }
   }
 
-  // ---- K steps: metallicity rows in met_mask x age blocks below age_hi
-  const int n_ab = (age_hi + C::KT - 1) / C::KT;
-  const int nk = __builtin_popcount(met_mask) * n_ab;
-  const int j_first = met_mask ? __builtin_ctz(met_mask) : 0;
+  // ---- K steps: the tile's non-zero weight blocks (s_koff)
   const elem *st = PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16;
   const elem *w = (const elem *)a.w_pad;
   const int n_comp = NCOMP * n_band;
@@ -201,19 +216,12 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
         for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
 
     StageRegs<PREC> regs;
-    int j_cur = j_first, ab_cur = 0;    // K block of the stage held in regs
-    if (nk > 0) load_stage<PREC>(regs, st, P.k_pad, l0, w, g0, a.s_count, j_cur * AGE_PAD);
+    if (nk > 0) load_stage<PREC>(regs, st, P.k_pad, l0, w, g0, a.s_count, s_koff[0]);
     for (int ks = 0; ks < nk; ++ks) {
       __syncthreads();
       store_stage<PREC>(regs, sm);
       __syncthreads();
-      if (ks + 1 < nk) {
-        if (++ab_cur == n_ab) {
-          ab_cur = 0;
-          j_cur = __builtin_ctz(met_mask & ~((2u << j_cur) - 1u));
-        }
-        load_stage<PREC>(regs, st, P.k_pad, l0, w, g0, a.s_count, j_cur * AGE_PAD + ab_cur * C::KT);
-      }
+      if (ks + 1 < nk) load_stage<PREC>(regs, st, P.k_pad, l0, w, g0, a.s_count, s_koff[ks + 1]);
       mma_stage(sm, wr, wc, lane, acc);
     }
     __syncthreads();   // s_lc / s_q / filter intervals visible

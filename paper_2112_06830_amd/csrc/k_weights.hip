@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   // ---- metallicity weights and W = m_age * P, lanes over ages.
   const double lgmet = (double)lgmet_f;
   const double inv_sig = 1.0 / (double)sig_f;
-  int jlo = 1 << 20, jhi = -1, ihi = 0;
+  unsigned nzrows[2] = {0u, 0u};   // per age slot: metallicity rows with a non-zero weight
   const int k_pad = P.k_pad;
   float *wp32 = (a.w_pad && !a.w_pad_bf16) ? (float *)a.w_pad + (size_t)local * k_pad : nullptr;
   uint16_t *wp16 = (a.w_pad && a.w_pad_bf16) ? (uint16_t *)a.w_pad + (size_t)local * k_pad : nullptr;
@@ -308,12 +308,25 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
         nz = wf != 0.0f;
       }
       if (wu && real) wu[j * n_age + i] = (float)wv;
-      if (nz) { jlo = min(jlo, j); jhi = max(jhi, j); ihi = max(ihi, i + 1); }
+      if (nz) nzrows[q] |= 1u << j;
     }
   }
-  jlo = wave_min(jlo);
-  jhi = wave_max(jhi);
-  ihi = wave_max(ihi);
+  // non-zero (row, 16-age block) mask: ages 0..63 live in slot 0 of lanes
+  // 0..63, ages 64..95 in slot 1 of lanes 0..31
+  unsigned kblk[KBLOCK_WORDS] = {0u, 0u, 0u};
+  for (int j = 0; j < n_met; ++j) {
+    const unsigned long long b0 = __ballot((nzrows[0] >> j) & 1u);
+    const unsigned long long b1 = __ballot((nzrows[1] >> j) & 1u);
+#pragma unroll
+    for (int blk = 0; blk < KBLOCKS_PER_ROW; ++blk) {
+      const unsigned long long src = blk < 4 ? b0 : b1;
+      const int sh = (blk & 3) * KBLOCK_AGES;
+      if ((src >> sh) & 0xFFFFull) {
+        const int bit = j * KBLOCKS_PER_ROW + blk;
+        kblk[bit >> 5] |= 1u << (bit & 31);
+      }
+    }
+  }
 
   const double dmod = a.mag_offset ? wave_distance_modulus(z, a.cosmo, a.gl, lane) : 0.0;
   // rest wavelengths whose redshifted value can meet a filter: [lo, hi) with
@@ -348,8 +361,9 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
       GalaxyRange r;
       r.win_lo = max(win_lo - 2, 0);
       r.win_hi = min(win_hi + 2, P.n_wave);
-      if (jhi < 0) { r.met_lo_hi = 0; r.age_hi = 0; }
-      else { r.met_lo_hi = jlo | (jhi << 16); r.age_hi = ihi; }
+#pragma unroll
+      for (int w = 0; w < KBLOCK_WORDS; ++w) r.kblk[w] = kblk[w];
+      r.pad = 0;
       a.range[s] = r;
     }
   }

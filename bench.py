@@ -221,8 +221,7 @@ def run_serve(seconds=6.0, rate_hz=200.0):
     flt = synth.make_filters()
     n_req = int(seconds * rate_hz)
     arrivals, reqs = S.make_trace(n_req, rate_hz=rate_hz, seed=6)
-    eng = S.ServeEngine(ssp, flt, buckets=(8192, 16384, 32768, 65536, 131072),
-                        hbm_budget_bytes=48 << 30)
+    eng = S.ServeEngine(ssp, flt, hbm_budget_bytes=48 << 30)
     log("serve: capturing slot graphs")
     eng.warm()
     eng.start()

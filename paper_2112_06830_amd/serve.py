@@ -8,11 +8,12 @@ and gradient requests on the FP32 table (both resident).
 
 Scheduling (continuous batching):
   * Requests wait in one FIFO queue per kind (forward / gradient).
-  * At most `max_inflight_per_kind` batches of a kind run at once (one by
-    default).  While a batch runs, arrivals accumulate in the queue; when it
-    completes, the next batch takes the queued requests in order while their
-    galaxies fit the largest slot, so load is absorbed by larger batches
-    rather than by a queue of launches on the stream.
+  * At most `max_inflight_per_kind` batches of a kind run at once (two by
+    default, each on its own stream, so a new batch never waits behind a
+    running one).  While the limit is reached, arrivals accumulate in the
+    queue; when a batch completes, the next takes the queued requests in order
+    while their galaxies fit the largest slot, so load is absorbed by larger
+    batches rather than by a queue of launches on a stream.
   * A batch runs in the smallest slot bucket that holds it, padded with inert
     galaxies (z = 1000: no filter ever sees them, so they skip the
     contraction).  Slot choice, in order: an idle slot of that bucket; a new
@@ -20,8 +21,9 @@ Scheduling (continuous batching):
     evicting idle slots.
   * Slots (device buffers + pinned staging + a captured hipGraph of the
     batch's whole launch sequence) are allocated under the budget, ahead of
-    traffic by `warm()` or on first use.  A batch's inputs go over the copy
-    stream; its graph replays on the kind's stream.
+    traffic by `warm()` or on first use.  Each slot has its own stream, so
+    batches in flight (of either kind) run concurrently; a batch's inputs go
+    over the copy stream and its graph replays on the slot's stream.
 
 """
 
@@ -216,6 +218,7 @@ class _Slot:
             self.h_g64 = torch.empty((5, cap), dtype=f64, pin_memory=True)
             self.h_g32 = torch.empty((5, cap), dtype=f32, pin_memory=True)
         self.eng = eng
+        self.stream = torch.cuda.Stream(device=d)
         self.graph = None
         self.done = torch.cuda.Event()
         self.batch = None
@@ -233,7 +236,8 @@ class _Slot:
             api.mags_vjp(e.ssp_h, e.flt_h, e.cosmo, self.pop, self.bar, bands=self.bands,
                          moments=self.moments, workspace=self.ws_b, outs=self.outs)
 
-    def capture(self, stream):
+    def capture(self):
+        stream = self.stream
         self.h_in32[0].fill_(PAD_Z)     # inert galaxies for the eager warm-up
         self.h_in64[0].fill_(1.0)
         self.h_in64[1].fill_(1.0)
@@ -253,8 +257,9 @@ class ServeEngine:
     """Continuous-batching server on one GPU (see the module docstring)."""
 
     def __init__(self, ssp, filters, cosmo=None, n_t=100,
-                 buckets=(8192, 16384, 32768, 65536, 131072), hbm_budget_bytes=24 << 30,
-                 slots_per_bucket=1, max_inflight_per_kind=1, use_graphs=True, device="cuda"):
+                 buckets=(8192, 12288, 16384, 24576, 32768, 49152, 65536, 98304, 131072),
+                 hbm_budget_bytes=48 << 30, slots_per_bucket=2, max_inflight_per_kind=2,
+                 use_graphs=True, device="cuda"):
         import synth
         self.device = torch.device(device)
         self.n_t = n_t
@@ -278,8 +283,6 @@ class ServeEngine:
         self.free_slots = {}
         self.inflight = []
         self.copy_stream = torch.cuda.Stream(device=self.device)
-        self.streams = {KIND_FWD: torch.cuda.Stream(device=self.device),
-                        KIND_GRAD: torch.cuda.Stream(device=self.device)}
         self.lock = threading.Lock()
         self.incoming = deque()
         self.completed = []
@@ -316,14 +319,12 @@ class ServeEngine:
         for kind in kinds:
             for b in buckets or self.planner.buckets:
                 key = (kind, b)
-                if self.planner.allocated.get(key, 0) >= self.planner.slots_per_bucket:
-                    continue
-                if self.planner.reserved + self.planner.slot_bytes(kind, b) > self.planner.budget:
-                    continue
-                self.planner._allocate(key)
-                slot = _Slot(self, kind, b)
-                slot.capture(self.streams[kind])
-                self.free_slots.setdefault(key, []).append(slot)
+                while (self.planner.allocated.get(key, 0) < self.planner.slots_per_bucket and
+                       self.planner.reserved + self.planner.slot_bytes(kind, b) <= self.planner.budget):
+                    self.planner._allocate(key)
+                    slot = _Slot(self, kind, b)
+                    slot.capture()
+                    self.free_slots.setdefault(key, []).append(slot)
 
     # -------------------------------------------------------------- engine
     def _get_slot(self, kind, bucket):
@@ -332,7 +333,7 @@ class ServeEngine:
         if lst:
             return lst.pop()
         slot = _Slot(self, kind, bucket)
-        slot.capture(self.streams[kind])
+        slot.capture()
         return slot
 
     def _launch(self, kind, reqs, bucket):
@@ -360,7 +361,7 @@ class ServeEngine:
         h64[:, o:] = 1.0
         if kind == KIND_GRAD:
             h32[6:, o:] = 0.0
-        stream = self.streams[kind]
+        stream = slot.stream
         ev = torch.cuda.Event()
         with torch.cuda.stream(self.copy_stream):
             slot.d_par.copy_(slot.h_in64, non_blocking=True)

@@ -104,8 +104,8 @@ def test_graph_replays_match_eager(S, engine):
     import torch
     _say("graph replay vs eager")
     slot = S._Slot(engine, S.KIND_GRAD, 2048)
-    stream = torch.cuda.Stream()
-    slot.capture(stream)
+    slot.capture()
+    stream = slot.stream
     assert slot.graph is not None
     for seed in (1, 2, 3):
         t, reqs = S.make_trace(2, seed=100 + seed, n_range=(500, 900), grad_fraction=1.0)

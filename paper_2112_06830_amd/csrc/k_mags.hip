@@ -273,10 +273,13 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
           for (int nb = 0; nb < 2; ++nb) {
             const float lobs = zp1[nb] * lam;
             // rounding fixed explicitly, so that both instantiations agree bit
-            // for bit whatever the compiler contracts
-            const float k0x = __fmul_rn(lc.z, exp2f(dl[nb] * lc.y));  // k0 (lambda/5500)^delta
+            // for bit whatever the compiler contracts.  The hardware exp2 is
+            // within 1 ulp; its only difference from the library exp2f is
+            // that results below 2^-126 (attenuation beyond ~380 mag) flush to
+            // zero.
+            const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(dl[nb] * lc.y));  // k0 (lambda/5500)^delta
             const float kl = fmaf(bp[nb], lc.w, k0x);                 // k_lambda
-            const float att = exp2f(da[nb] * kl);
+            const float att = __builtin_amdgcn_exp2f(da[nb] * kl);
             const float e = acc[mb][nb][r] * att * q;
             float x[3];
             if (MOM) { x[0] = e * kl; x[1] = e * k0x * lc.y; x[2] = e * lc.w; }

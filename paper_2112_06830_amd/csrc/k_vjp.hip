@@ -111,8 +111,8 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
         const float2 gr = s_grid[b];
         gs += s_gam[col * DSPS_MAX_BAND + b] * filter_pair_at(s_pair + b * n_int, n_int, (lobs - gr.x) * gr.y);
       }
-      const float k0x = __fmul_rn(lc.z, exp2f(m.z * lc.y));
-      const float att = exp2f(m.y * fmaf(m.w, lc.w, k0x));
+      const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(m.z * lc.y));
+      const float att = __builtin_amdgcn_exp2f(m.y * fmaf(m.w, lc.w, k0x));
       a.lbar[(size_t)(g0 + col) * nwp + l] = (gs * q) * att;
     }
   }

@@ -418,9 +418,26 @@ __global__ void k_fill_int(int *p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_sort_hist(SortLaunch a) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < a.n_gal) atomicAdd(&a.hist[sort_key(a, g)], 1);
+// Galaxies per sort workgroup (1024 threads, 4 each).  Counts are aggregated
+// in LDS first, so a key shared by many galaxies (a narrow redshift range, or
+// the inert padding of a server batch) costs one global atomic per workgroup
+// instead of one per galaxy.
+constexpr int SORT_CHUNK = 4096;
+constexpr int SORT_PER_THREAD = SORT_CHUNK / 1024;
+
+__global__ __launch_bounds__(1024) void k_sort_hist(SortLaunch a) {
+  __shared__ int cnt[SORT_BINS];
+  for (int i = threadIdx.x; i < SORT_BINS; i += 1024) cnt[i] = 0;
+  __syncthreads();
+  const int g0 = blockIdx.x * SORT_CHUNK + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < SORT_PER_THREAD; ++k) {
+    const int g = g0 + k * 1024;
+    if (g < a.n_gal) atomicAdd(&cnt[sort_key(a, g)], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < SORT_BINS; i += 1024)
+    if (cnt[i]) atomicAdd(&a.hist[i], cnt[i]);
 }
 
 // Exclusive scan of SORT_BINS counters by one 1024-thread block, in place.
@@ -444,9 +461,35 @@ __global__ __launch_bounds__(1024) void k_sort_scan(int *hist) {
   for (int i = 0; i < PER; ++i) { hist[PER * t + i] = run; run += v[i]; }
 }
 
-__global__ void k_sort_scatter(SortLaunch a) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < a.n_gal) a.perm[atomicAdd(&a.hist[sort_key(a, g)], 1)] = g;
+// Each workgroup ranks its galaxies per key in LDS, reserves one range per
+// key it holds from the scanned offsets, then writes the permutation.  The
+// order inside a key is arbitrary (it never changes a galaxy's result).
+__global__ __launch_bounds__(1024) void k_sort_scatter(SortLaunch a) {
+  __shared__ int cnt[SORT_BINS];
+  __shared__ int base[SORT_BINS];
+  for (int i = threadIdx.x; i < SORT_BINS; i += 1024) cnt[i] = 0;
+  __syncthreads();
+  const int g0 = blockIdx.x * SORT_CHUNK + threadIdx.x;
+  int key[SORT_PER_THREAD], rank[SORT_PER_THREAD];
+#pragma unroll
+  for (int k = 0; k < SORT_PER_THREAD; ++k) {
+    const int g = g0 + k * 1024;
+    key[k] = 0;
+    rank[k] = 0;
+    if (g < a.n_gal) {
+      key[k] = sort_key(a, g);
+      rank[k] = atomicAdd(&cnt[key[k]], 1);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < SORT_BINS; i += 1024)
+    if (cnt[i]) base[i] = atomicAdd(&a.hist[i], cnt[i]);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < SORT_PER_THREAD; ++k) {
+    const int g = g0 + k * 1024;
+    if (g < a.n_gal) a.perm[base[key[k]] + rank[k]] = g;
+  }
 }
 
 int launch_sort(const SortLaunch &a, hipStream_t stream) {
@@ -454,10 +497,10 @@ int launch_sort(const SortLaunch &a, hipStream_t stream) {
   if (a.n_gal <= 0) return DSPS_OK;
   ProfScope prof(DSPS_KERNEL_ZSORT, stream);
   hipLaunchKernelGGL(k_fill_int, dim3(SORT_BINS / 256), dim3(256), 0, stream, a.hist, SORT_BINS, 0);
-  const int blocks = (a.n_gal + 255) / 256;
-  hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(256), 0, stream, a);
+  const int blocks = (a.n_gal + SORT_CHUNK - 1) / SORT_CHUNK;
+  hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(1024), 0, stream, a);
   hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, stream, a.hist);
-  hipLaunchKernelGGL(k_sort_scatter, dim3(blocks), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(blocks), dim3(1024), 0, stream, a);
   return hip_fail(hipGetLastError(), "ordering sort launch");
 }
 

@@ -10,7 +10,9 @@ tabulated SFH on 100 times, z ~ U[0.1, 3], six Gaussian bands.
 Prints ONE JSON line.  `roofline` describes the dominant kernel
 (k_mags_gemm), timed with HIP events on its launch stream during the timed
 region.  `cpu_baseline` times the FP64 oracle on a bounded sample of the
-same workload on the host cores.
+same workload on the host cores; the same leg reports the per-band error of
+the GPU magnitudes against the oracle on that sample (FP32) and on the first
+1e4 galaxies of the BF16 workload (`extra.error_vs_oracle`).
 """
 
 from __future__ import annotations
@@ -95,7 +97,19 @@ def algorithmic_flops(P, ssp_h, dpop, ssp, flt, z):
     return float(np.sum(2.0 * nnz * neff)), float(nnz.mean()), float(neff.mean())
 
 
-def cpu_baseline(ssp, flt, pop, sfr, min_seconds=10.0, block=512, max_gal=24576):
+def band_errors(got, ref):
+    """Per-band max and RMS of |m_gpu - m_oracle| in mag."""
+    d = np.abs(np.asarray(got, np.float64) - np.asarray(ref, np.float64))
+    return {"max_mag": [float(v) for v in d.max(axis=0)],
+            "rms_mag": [float(v) for v in np.sqrt((d ** 2).mean(axis=0))]}
+
+
+def cpu_baseline(ssp, flt, pop, m32, pop16=None, m16=None, min_seconds=10.0, block=512,
+                 max_gal=24576, n16=10_000):
+    """The FP64 oracle timed on the host on a bounded sample of the FP32
+    workload (it tabulates its own SFR from the parametric history); the GPU
+    magnitudes of the same galaxies are compared with it per band, and the
+    BF16 workload's first n16 galaxies likewise."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -103,18 +117,29 @@ def cpu_baseline(ssp, flt, pop, sfr, min_seconds=10.0, block=512, max_gal=24576)
     except Exception:
         threads = os.cpu_count() or 1
     done = 0
+    ref = []
     t0 = time.perf_counter()
     while done < min(max_gal, pop.n_gal):
         idx = np.arange(done, min(done + block, pop.n_gal))
-        inp = oracle.prepare_inputs(ssp, flt, pop.subset(idx), sfr=sfr[idx])
-        oracle.mags(inp)
+        inp = oracle.prepare_inputs(ssp, flt, pop.subset(idx))
+        ref.append(oracle.mags(inp))
         done += idx.size
         if time.perf_counter() - t0 >= min_seconds:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "galaxies/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {done} galaxies of the same population (FP64 numpy oracle, "
-                      f"{dt:.1f} s, BLAS threads={threads}, host cpus={os.cpu_count()})"}
+    cpu = {"value": done / dt, "unit": "galaxies/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"first {done} galaxies of the same population (FP64 numpy oracle, "
+                     f"{dt:.1f} s, BLAS threads={threads}, host cpus={os.cpu_count()})"}
+    errors = {"fp32_fwd_1e5": dict(band_errors(m32[:done], np.concatenate(ref)), n_gal=done)}
+    if pop16 is not None:
+        idx = np.arange(min(n16, pop16.n_gal))
+        ref16 = []
+        for s0 in range(0, idx.size, block):
+            inp = oracle.prepare_inputs(ssp, flt, pop16.subset(idx[s0:s0 + block]))
+            ref16.append(oracle.mags(inp))
+        errors["bf16_fwd_1e6"] = dict(band_errors(m16[:idx.size], np.concatenate(ref16)),
+                                      n_gal=int(idx.size))
+    return cpu, errors
 
 
 def run_workload(P, name, n_gal, n_t, precision, steps, warmup, seed, want_roofline=True):
@@ -154,7 +179,7 @@ def run_workload(P, name, n_gal, n_t, precision, steps, warmup, seed, want_roofl
         achieved = flops / (gemm_ms / steps * 1e-3) / 1e12
         res.update(alg_flops_per_step=flops, nnz_mean=nnz_mean, n_lambda_eff_mean=neff_mean,
                    achieved_tflops=achieved)
-    return res, (ssp, flt, pop, sfr)
+    return res, (ssp, flt, pop, out.cpu().numpy())
 
 
 def run_grad(P, steps, warmup, n_gal=200_000, seed=5):
@@ -283,15 +308,16 @@ def main():
         sys.exit(1)
     import paper_2112_06830_amd as P
 
-    main_res, (ssp, flt, pop, sfr_dev) = run_workload(
+    main_res, (ssp, flt, pop, m32) = run_workload(
         P, "fwd_fp32_1e5", 100_000, 100, "fp32", args.steps, args.warmup, seed=3)
     log(f"fp32 1e5: {main_res['ms_per_step']:.3f} ms/step, gemm {main_res['gemm_ms_per_step']:.3f} ms/step")
 
+    pop16 = m16 = None
     extra = {"fp32_fwd_1e5": {k: main_res[k] for k in ("ms_per_step", "galaxies_per_s",
                                                          "gemm_ms_per_step", "weights_ms_per_step",
                                                          "nnz_mean", "n_lambda_eff_mean")}}
     if not args.no_extra:
-        bf, _ = run_workload(P, "fwd_bf16_1e6", 1_000_000, 1000, "bf16", max(3, args.steps // 4),
+        bf, (_, _, pop16, m16) = run_workload(P, "fwd_bf16_1e6", 1_000_000, 1000, "bf16", max(3, args.steps // 4),
                              1, seed=4, want_roofline=True)
         extra["bf16_fwd_1e6"] = {
             "ms_per_step": bf["ms_per_step"], "galaxies_per_s": bf["galaxies_per_s"],
@@ -307,7 +333,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle on a bounded sample")
-        cpu = cpu_baseline(ssp, flt, pop, sfr_dev.cpu().numpy())
+        cpu, errors = cpu_baseline(ssp, flt, pop, m32, pop16, m16)
+        extra["error_vs_oracle"] = errors
 
     traffic = read_traffic("fp32", "fp32_1e5")
     achieved = main_res["achieved_tflops"]

@@ -216,3 +216,21 @@ def test_quantize_bf16_bit_exact(dev):
     q_ref, s_ref = oracle.quantize_bf16_rne(rows)
     assert np.array_equal(s.cpu().numpy(), s_ref)
     assert np.array_equal(q.cpu().numpy().view(np.uint16), q_ref)
+
+
+def test_mags_bf16_error_report_1e4_subset(dev, large):
+    """The BF16 workload's error subset: the first 1e4 galaxies of the 1e6
+    population (n_t = 1000, z ~ U[0.1, 3]); per-band max and RMS |dm| against
+    the FP64 oracle, max within the BF16 target."""
+    ssp_h, flt_h, ssp = large
+    pop = synth.make_population(1_000_000, n_t=1000, z_range=(0.1, 3.0), seed=4).subset(np.arange(10_000))
+    _say("mags bf16 error report, 1e4 galaxies of the 1e6 workload, n_t=1000")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    sfr = dev.sfh_table(dp.t_table, dp.sfh_params)
+    m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp.with_sfr(sfr), precision="bf16").cpu().numpy()
+    ref = np.concatenate([oracle.mags(oracle_inputs(ssp, pop.subset(np.arange(s, min(s + 1000, pop.n_gal)))))
+                          for s in range(0, pop.n_gal, 1000)])
+    d = np.abs(m.astype(np.float64) - ref)
+    _say("bf16 per-band max |dm| " + " ".join(f"{v:.2e}" for v in d.max(axis=0)) +
+         "; rms " + " ".join(f"{v:.2e}" for v in np.sqrt((d ** 2).mean(axis=0))))
+    assert d.max() < BF16_TOL_MAG

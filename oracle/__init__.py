@@ -21,6 +21,9 @@ of zero weights), written step by step in the paper's order:
               Eq. restmag)
   pipeline    weights, SEDs, magnitudes and BF16 quantisation of the SSP block
   adjoint     hand-written reverse-mode gradient of the magnitudes
+  summary     the population summary of the Section 4.1 forward model: a
+              red-colour cut and an r-band magnitude histogram, triweight-
+              smoothed (Appendix B), and its gradient
 
 Readings of passages that are silent, ambiguous or garbled are stated in the
 docstring of the function that takes them.  Parity status: every function here

@@ -78,6 +78,7 @@ def luminosity_distance_mpc(z, om0: float = 0.3, h: float = 0.7, w0: float = -1.
 
 
 def distance_modulus(z, om0: float = 0.3, h: float = 0.7, w0: float = -1.0):
-    """D_mod(z) = 5 log10( d_L / 10 pc ) with d_L in Mpc."""
+    """D_mod(z) = 5 log10( d_L / 10 pc ) with d_L in Mpc (-inf at z = 0)."""
     dl = luminosity_distance_mpc(z, om0, h, w0)
-    return 5.0 * np.log10(dl) + 25.0
+    with np.errstate(divide="ignore"):
+        return 5.0 * np.log10(dl) + 25.0

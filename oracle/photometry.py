@@ -48,7 +48,13 @@ def band_integrals(wave_rest, sed_row, z, filt_wave, filt_trans):
 
 
 def apparent_mag(num, den, dmod, z):
-    """m = -2.5 log10( num / (AB0 den) ) + D_mod(z) - 2.5 log10(1+z)."""
+    """m = -2.5 log10( num / (AB0 den) ) + D_mod(z) - 2.5 log10(1+z).
+
+    Reading: at z = 0 the observable is the absolute magnitude M of
+    Eq. restmag itself (a source at 10 pc; the population of the Section 4.1
+    benchmark is observed at z = 0), so the distance terms apply for z > 0
+    only; dmod is ignored there.
+    """
     num = np.asarray(num, dtype=np.float64)
     den = np.asarray(den, dtype=np.float64)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -60,4 +66,6 @@ def apparent_mag(num, den, dmod, z):
     if m_abs.ndim == 2:
         dmod = dmod[:, None]
         z = z[:, None]
-    return m_abs + dmod - 2.5 * np.log10(1.0 + z)
+    with np.errstate(invalid="ignore"):
+        offset = np.where(z > 0.0, dmod - 2.5 * np.log10(1.0 + z), 0.0)
+    return m_abs + offset

@@ -15,8 +15,10 @@ from .ssp import make_ssp, SspTable
 from .population import make_population, Population, TIME_GRID_END_GYR
 from .filters import make_filters, FilterSet
 from .configs import WORKLOADS, Workload, workload
+from .mags import make_mags
 
 __all__ = [
+    "make_mags",
     "make_ssp", "SspTable",
     "make_population", "Population", "TIME_GRID_END_GYR",
     "make_filters", "FilterSet",

@@ -405,3 +405,20 @@ def test_adjoint_closed_forms(small_ssp, filters6):
         # With A_V = 0 the curve shape parameters have no effect.
         assert g["delta_bar"][1] == 0.0 and g["bump_bar"][1] == 0.0
         assert np.all(g["av_bar"] > 0)
+
+
+def test_constant_sfh_flat_fnu_absolute_magnitude_at_z0(filters6):
+    # At z = 0 the observable is the absolute magnitude of Eq. restmag: for a
+    # constant SFR and a flat L_nu the same analytic value without D_mod.
+    pop = _pop(6, seed=22, z_range=(0.1, 1.0))
+    pop.z[:] = 0.0
+    pop.av[:] = 0.0
+    ssp = _flat_ssp()
+    c = 3.1
+    sfr = np.full((pop.n_gal, pop.n_t), c)
+    inp = oracle.prepare_inputs(ssp, filters6, pop, sfr=sfr)
+    m = oracle.mags(inp)
+    mass = 1e9 * c * (cosmology.age_at_z(0.0) - pop.t_table[0])
+    expect = -2.5 * np.log10(mass * 2.0e-15 / constants.AB0_LSUN_PER_HZ)
+    assert np.all(np.isfinite(m))
+    np.testing.assert_allclose(m, expect, atol=1e-10)

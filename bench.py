@@ -233,6 +233,71 @@ def run_grad(P, steps, warmup, n_gal=200_000, seed=5):
     return res
 
 
+def run_forward_model(P, steps, warmup, n_gal=100_000, seed=7):
+    """The Section 4.1 forward model at z = 0: parametric SFH -> SFR table ->
+    six-band absolute magnitudes (FP32) -> red colour cut (g - r above the
+    population median, triweight width 0.05) -> histogram of M_r (40 bins,
+    width 0.1); and the same step plus the population gradient of
+    sum_k (H_k - target_k)^2 w.r.t. every galaxy's parameters."""
+    import torch
+    import synth
+    ssp = synth.make_ssp(n_wave=5994, wave_lo=9.0e2, wave_hi=2.5e4)
+    flt = synth.make_filters()
+    pop = synth.make_population(n_gal, n_t=100, z_range=(0.1, 1.0), seed=seed)
+    pop.z[:] = 0.0
+    log(f"forward_model_z0: {n_gal} galaxies at z = 0")
+    ssp_h = P.SspBlock.from_synth(ssp, precisions=("fp32",))
+    flt_h = P.FilterBank.from_synth(flt)
+    dpar = P.DevicePopulation.from_synth(pop, use_params=True)
+    ws_f = P.Workspace(P.workspace_size(2, ssp_h, flt_h, n_gal, 100, "fp32"), dpar.device)
+    ws_b = P.Workspace(P.workspace_size(3, ssp_h, flt_h, n_gal, 100, "fp32"), dpar.device)
+    m = torch.empty((n_gal, 6), dtype=torch.float32, device="cuda")
+    bands = torch.empty((n_gal, 2, 6), dtype=torch.float32, device="cuda")
+    mom = torch.empty((n_gal, 3, 6), dtype=torch.float32, device="cuda")
+    P.mags(ssp_h, flt_h, P.Cosmology(), dpar, workspace=ws_f, out=m)
+    colour = (m[:, 1] - m[:, 2]).float()
+    spec = P.SummarySpec(band_a=1, band_b=2, colour_cut=float(colour.median()), colour_width=0.05,
+                         band_m=2, edges=torch.linspace(float(m[:, 2].min()) - 0.5,
+                                                        float(m[:, 2].max()) + 0.5, 41,
+                                                        dtype=torch.float64, device="cuda"),
+                         mag_width=0.1)
+    hist = torch.empty(40, dtype=torch.float64, device="cuda")
+    target = torch.full_like(hist, n_gal / 80.0)
+    outs = {"sfh_params": torch.empty((5, n_gal), dtype=torch.float64, device="cuda")}
+    for k in ("lgmet", "sigma_z", "av", "delta", "bump"):
+        outs[k] = torch.empty(n_gal, dtype=torch.float32, device="cuda")
+
+    def forward():
+        # SFH generation (the SFR table), photometry, colour cut and histogram
+        sfr = P.sfh_table(dpar.t_table, dpar.sfh_params)
+        P.mags(ssp_h, flt_h, P.Cosmology(), dpar.with_sfr(sfr), workspace=ws_f, out=m)
+        P.pop_summary(m, spec, out=hist)
+
+    def gradient():
+        # the parametric history is evaluated inside the weights kernels
+        P.mags(ssp_h, flt_h, P.Cosmology(), dpar, with_moments=True, workspace=ws_f, out=m,
+               bands_out=bands, moments_out=mom)
+        P.pop_summary(m, spec, out=hist)
+        mbar = P.pop_summary_vjp(m, spec, 2.0 * (hist - target))
+        P.mags_vjp(ssp_h, flt_h, P.Cosmology(), dpar, mbar, bands=bands, moments=mom,
+                   workspace=ws_b, outs=outs)
+
+    res = {}
+    for name, fn in (("forward", forward), ("forward_grad", gradient)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[name] = {"ms_per_step": ms, "galaxies_per_s": n_gal / (ms * 1e-3)}
+    res["red_fraction"] = float(P.pop_summary(m, spec).sum().item()) / n_gal
+    res["finite"] = bool(all(torch.isfinite(v).all().item() for v in outs.values()))
+    return res
+
+
 def run_serve(seconds=6.0, rate_hz=200.0):
     """Serving workload: Poisson arrivals at 200 req/s, N ~ logU[1e3, 1e5]
     galaxies per request with a per-request redshift range, 30% asking for
@@ -327,6 +392,10 @@ def main():
         log(f"bf16 1e6: {bf['ms_per_step']:.3f} ms/step")
         gr = run_grad(P, max(3, args.steps // 4), 1)
         extra["fp32_fwd_grad_2e5"] = gr
+        fm = run_forward_model(P, max(3, args.steps // 4), 1)
+        extra["forward_model_z0_1e5"] = fm
+        log(f"forward model z=0 1e5: {fm['forward']['ms_per_step']:.3f} ms/step, "
+            f"with population gradient {fm['forward_grad']['ms_per_step']:.3f} ms/step")
         log(f"fp32 fwd+grad 2e5: {gr['ms_per_step']:.3f} ms/step")
         extra["serve_poisson_200hz"] = run_serve(seconds=args.serve_seconds)
 

@@ -198,7 +198,9 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
  * a1-a7. Fused magnitudes: the SED is contracted, attenuated and integrated
  * through every filter without ever being written to memory.
  *   mags     [n_gal*n_band] float32 apparent AB magnitudes
- *            m = -2.5 log10(num / (AB0 den)) + D_mod(z) - 2.5 log10(1+z)
+ *            m = -2.5 log10(num / (AB0 den)) + D_mod(z) - 2.5 log10(1+z);
+ *            at z = 0 the absolute magnitude of Eq. restmag (no distance
+ *            terms), as for the Section 4.1 population observed at z = 0
  *   bands    [n_gal*2*n_band] float32 (num_b then den_b per galaxy): the two
  *            trapezoid sums of Eq. restmag over the redshifted grid, or NULL.
  *   moments  [n_gal*3*n_band] float32 dust moments of the band sums, or NULL
@@ -234,6 +236,42 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
                   hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Population summary of the Section 4.1 forward model: a red-colour cut and
+ * a histogram of one band's magnitude over the selected galaxies, smoothed
+ * with the triweight of Appendix B (Eqs. triweight, terf) so that gradients
+ * reach every galaxy:
+ *   w_g    = T_erf((c_g - colour_cut) / colour_width),   c_g = m_a - m_b
+ *   B_k(m) = T_erf((e_{k+1} - m) / mag_width) - T_erf((e_k - m) / mag_width)
+ *   hist_k = sum_g w_g B_k(m_g, band_m)
+ * with T_erf the cumulative triweight (support +-3 widths).  A zero width
+ * gives the hard cut (c > colour_cut) or the plain histogram with bins
+ * [e_k, e_{k+1}), the last closed on the right.  A galaxy whose colour or
+ * magnitude is not finite contributes nothing.
+ *   mags       [n_gal*n_band] float32, device (e.g. dsps_mags output)
+ *   band_a, band_b, band_m   band indices in [0, n_band)
+ *   colour_width, mag_width  >= 0, finite
+ *   edges      [n_bins+1] float64, device, strictly ascending (not checked);
+ *              1 <= n_bins <= DSPS_MAX_SUMMARY_BINS
+ *   hist       [n_bins] float64, device.  Partial sums are reduced in a
+ *              fixed order, so the result is deterministic.
+ *   workspace  dsps_pop_summary_workspace() bytes, device
+ * dsps_pop_summary_vjp writes mags_bar [n_gal*n_band] float32 (every entry),
+ * the gradient of sum_k hist_bar[k] hist_k (hist_bar float64, device); it is
+ * zero for zero widths (the hard summary is piecewise constant) and for
+ * galaxies that contribute nothing.
+ * ------------------------------------------------------------------------ */
+#define DSPS_MAX_SUMMARY_BINS 4096
+int dsps_pop_summary_workspace(int n_gal, int n_bins, size_t *bytes);
+int dsps_pop_summary(const float *mags, int n_gal, int n_band, int band_a, int band_b,
+                     double colour_cut, double colour_width, int band_m, const double *edges,
+                     int n_bins, double mag_width, double *hist, void *workspace,
+                     size_t workspace_bytes, hipStream_t stream);
+int dsps_pop_summary_vjp(const float *mags, int n_gal, int n_band, int band_a, int band_b,
+                         double colour_cut, double colour_width, int band_m,
+                         const double *edges, int n_bins, double mag_width,
+                         const double *hist_bar, float *mags_bar, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * a8. BF16 quantisation with power-of-two row scales.
  *   x      [rows*cols] float32, finite
  *   q      [rows*cols] bfloat16 bits: round-to-nearest-even of x / scale[row]
@@ -260,7 +298,8 @@ typedef enum {
   DSPS_KERNEL_VJP_LBAR = 5,     /* adjoint: SED cotangent over tile windows  */
   DSPS_KERNEL_VJP_WBAR = 6,     /* adjoint: transposed contraction          */
   DSPS_KERNEL_VJP_WEIGHTS = 7,  /* adjoint: weights -> SFH, MDF parameters  */
-  DSPS_KERNEL_COUNT = 8
+  DSPS_KERNEL_SUMMARY = 8,      /* population summary (partials + reduction) */
+  DSPS_KERNEL_COUNT = 9
 } dsps_kernel_id;
 int dsps_profile_enable(int on);
 int dsps_profile_read(int kernel_id, double *total_ms, int *launches);

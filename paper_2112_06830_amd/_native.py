@@ -24,10 +24,11 @@ EXPORTS = (
     "dsps_ssp_info", "dsps_filters_create", "dsps_filters_destroy", "dsps_filters_info",
     "dsps_workspace_size", "dsps_sfh_table", "dsps_weights", "dsps_sed", "dsps_mags",
     "dsps_mags_vjp", "dsps_quantize_bf16", "dsps_profile_enable", "dsps_profile_read",
+    "dsps_pop_summary_workspace", "dsps_pop_summary", "dsps_pop_summary_vjp",
 )
 
 KERNEL_IDS = {"weights": 0, "mags_gemm": 1, "mags_finalize": 2, "zsort": 3, "sed_gemm": 4,
-              "vjp_lbar": 5, "vjp_wbar": 6, "vjp_weights": 7}
+              "vjp_lbar": 5, "vjp_wbar": 6, "vjp_weights": 7, "summary": 8}
 
 
 class DspsError(RuntimeError):
@@ -54,7 +55,7 @@ _LIB = None
 
 
 def _declare(lib):
-    P, I, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    P, I, S, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
     PP = ctypes.POINTER(ctypes.c_void_p)
     IP = ctypes.POINTER(ctypes.c_int)
     sig = {
@@ -74,6 +75,9 @@ def _declare(lib):
         "dsps_mags_vjp": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P,
                               P, P, P, P, P, P, P, P, S, P]),
         "dsps_quantize_bf16": (I, [P, I, I, P, P, P]),
+        "dsps_pop_summary_workspace": (I, [I, I, ctypes.POINTER(S)]),
+        "dsps_pop_summary": (I, [P, I, I, I, I, D, D, I, P, I, D, P, P, S, P]),
+        "dsps_pop_summary_vjp": (I, [P, I, I, I, I, D, D, I, P, I, D, P, P, P]),
         "dsps_profile_enable": (I, [I]),
         "dsps_profile_read": (I, [I, ctypes.POINTER(ctypes.c_double), IP]),
     }

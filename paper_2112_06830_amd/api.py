@@ -335,3 +335,55 @@ def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePo
                               _ptr(out.get("bump")), workspace.ptr(), workspace.nbytes, _stream(stream))
     N.check(rc, "dsps_mags_vjp")
     return out
+
+
+@dataclass
+class SummarySpec:
+    """Population summary of the Section 4.1 forward model: colour
+    m[band_a] - m[band_b] cut at colour_cut (triweight-smoothed over
+    colour_width), histogram of m[band_m] over `edges` (smoothed over
+    mag_width).  Zero widths give the hard cut and the plain histogram."""
+    band_a: int = 1
+    band_b: int = 2
+    colour_cut: float = 0.55
+    colour_width: float = 0.05
+    band_m: int = 2
+    edges: torch.Tensor | None = None      # [n_bins + 1] float64, device
+    mag_width: float = 0.1
+
+    def args(self, mags):
+        e = self.edges.to(device=mags.device, dtype=torch.float64).contiguous()
+        return e, (int(mags.shape[1]), int(self.band_a), int(self.band_b), float(self.colour_cut),
+                   float(self.colour_width), int(self.band_m))
+
+
+def pop_summary(mags: torch.Tensor, spec: SummarySpec, out=None, workspace=None, stream=None):
+    """dsps_pop_summary: the summary histogram [n_bins] float64."""
+    mags = mags.to(dtype=torch.float32).contiguous()
+    edges, (nb, a, b, cut, cw, bm) = spec.args(mags)
+    n, n_bins = int(mags.shape[0]), int(edges.numel()) - 1
+    hist = out if out is not None else torch.empty(n_bins, dtype=torch.float64, device=mags.device)
+    if workspace is None:
+        size = ctypes.c_size_t()
+        N.check(_lib().dsps_pop_summary_workspace(n, n_bins, ctypes.byref(size)),
+                "dsps_pop_summary_workspace")
+        workspace = Workspace(size.value, mags.device)
+    rc = _lib().dsps_pop_summary(_ptr(mags), n, nb, a, b, cut, cw, bm, _ptr(edges), n_bins,
+                                 float(spec.mag_width), _ptr(hist), workspace.ptr(),
+                                 workspace.nbytes, _stream(stream))
+    N.check(rc, "dsps_pop_summary")
+    return hist
+
+
+def pop_summary_vjp(mags: torch.Tensor, spec: SummarySpec, hist_bar: torch.Tensor, out=None,
+                    stream=None):
+    """dsps_pop_summary_vjp: d(sum_k hist_bar_k hist_k)/d mags [n_gal, n_band]."""
+    mags = mags.to(dtype=torch.float32).contiguous()
+    edges, (nb, a, b, cut, cw, bm) = spec.args(mags)
+    n, n_bins = int(mags.shape[0]), int(edges.numel()) - 1
+    hb = hist_bar.to(device=mags.device, dtype=torch.float64).contiguous()
+    g = out if out is not None else torch.empty_like(mags)
+    rc = _lib().dsps_pop_summary_vjp(_ptr(mags), n, nb, a, b, cut, cw, bm, _ptr(edges), n_bins,
+                                     float(spec.mag_width), _ptr(hb), _ptr(g), _stream(stream))
+    N.check(rc, "dsps_pop_summary_vjp")
+    return g

@@ -63,3 +63,21 @@ def dsps_mags(ssp, filters, cosmo, pop: api.DevicePopulation, sfh_params=None, s
                           sigma_z if sigma_z is not None else pop.sigma_z,
                           av if av is not None else pop.av, delta if delta is not None else pop.delta,
                           bump if bump is not None else pop.bump, pop.lgmet_slope, pop.lg_age_pivot)
+
+
+class PopSummary(torch.autograd.Function):
+    """hist = PopSummary.apply(mags, spec): the Section 4.1 summary of a
+    population's magnitudes, differentiable w.r.t. the magnitudes (chain it
+    after dsps_mags for gradients w.r.t. every galaxy's parameters)."""
+
+    @staticmethod
+    def forward(ctx, mags, spec):
+        ctx.spec = spec
+        m = mags.detach().contiguous()
+        ctx.save_for_backward(m)
+        return api.pop_summary(m, spec)
+
+    @staticmethod
+    def backward(ctx, hist_bar):
+        (m,) = ctx.saved_tensors
+        return api.pop_summary_vjp(m, ctx.spec, hist_bar), None

@@ -751,4 +751,86 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
   return DSPS_OK;
 }
 
+static int check_summary(const float *mags, int n_gal, int n_band, int band_a, int band_b,
+                         double colour_width, int band_m, const double *edges, int n_bins,
+                         double mag_width) {
+  DSPS_CHECK(n_gal >= 0, DSPS_ERR_SHAPE, "n_gal %d negative", n_gal);
+  DSPS_CHECK(n_band >= 1 && n_band <= DSPS_MAX_BAND, DSPS_ERR_SHAPE, "n_band %d outside [1, %d]",
+             n_band, DSPS_MAX_BAND);
+  DSPS_CHECK(band_a >= 0 && band_a < n_band && band_b >= 0 && band_b < n_band && band_m >= 0 &&
+                 band_m < n_band,
+             DSPS_ERR_ARG, "band index outside [0, %d)", n_band);
+  DSPS_CHECK(n_bins >= 1 && n_bins <= DSPS_MAX_SUMMARY_BINS, DSPS_ERR_SHAPE,
+             "n_bins %d outside [1, %d]", n_bins, DSPS_MAX_SUMMARY_BINS);
+  DSPS_CHECK(std::isfinite(colour_width) && colour_width >= 0.0 && std::isfinite(mag_width) &&
+                 mag_width >= 0.0,
+             DSPS_ERR_ARG, "widths must be finite and >= 0");
+  DSPS_CHECK(edges, DSPS_ERR_ARG, "edges is NULL");
+  DSPS_CHECK(n_gal == 0 || mags, DSPS_ERR_ARG, "mags is NULL");
+  return DSPS_OK;
+}
+
+int dsps_pop_summary_workspace(int n_gal, int n_bins, size_t *bytes) {
+  DSPS_CHECK(bytes, DSPS_ERR_ARG, "bytes is NULL");
+  DSPS_CHECK(n_gal >= 0 && n_bins >= 1 && n_bins <= DSPS_MAX_SUMMARY_BINS, DSPS_ERR_SHAPE,
+             "n_gal %d or n_bins %d out of range", n_gal, n_bins);
+  const size_t blocks = ((size_t)n_gal + SUMMARY_CHUNK - 1) / SUMMARY_CHUNK;
+  *bytes = align256(sizeof(double) * std::max<size_t>(blocks, 1) * n_bins);
+  return DSPS_OK;
+}
+
+int dsps_pop_summary(const float *mags, int n_gal, int n_band, int band_a, int band_b,
+                     double colour_cut, double colour_width, int band_m, const double *edges,
+                     int n_bins, double mag_width, double *hist, void *workspace,
+                     size_t workspace_bytes, hipStream_t stream) {
+  DSPS_TRY(check_summary(mags, n_gal, n_band, band_a, band_b, colour_width, band_m, edges,
+                         n_bins, mag_width));
+  DSPS_CHECK(std::isfinite(colour_cut), DSPS_ERR_ARG, "colour_cut must be finite");
+  DSPS_CHECK(hist, DSPS_ERR_ARG, "hist is NULL");
+  size_t need = 0;
+  DSPS_TRY(dsps_pop_summary_workspace(n_gal, n_bins, &need));
+  DSPS_TRY(check_workspace(workspace, workspace_bytes, need));
+  SummaryLaunch a{};
+  a.mags = mags;
+  a.n_gal = n_gal;
+  a.n_band = n_band;
+  a.band_a = band_a;
+  a.band_b = band_b;
+  a.band_m = band_m;
+  a.cut = colour_cut;
+  a.colour_width = colour_width;
+  a.mag_width = mag_width;
+  a.edges = edges;
+  a.n_bins = n_bins;
+  a.partial = (double *)workspace;
+  a.hist = hist;
+  return launch_summary(a, stream);
+}
+
+int dsps_pop_summary_vjp(const float *mags, int n_gal, int n_band, int band_a, int band_b,
+                         double colour_cut, double colour_width, int band_m,
+                         const double *edges, int n_bins, double mag_width,
+                         const double *hist_bar, float *mags_bar, hipStream_t stream) {
+  DSPS_TRY(check_summary(mags, n_gal, n_band, band_a, band_b, colour_width, band_m, edges,
+                         n_bins, mag_width));
+  DSPS_CHECK(std::isfinite(colour_cut), DSPS_ERR_ARG, "colour_cut must be finite");
+  if (n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(hist_bar && mags_bar, DSPS_ERR_ARG, "hist_bar or mags_bar is NULL");
+  SummaryLaunch a{};
+  a.mags = mags;
+  a.n_gal = n_gal;
+  a.n_band = n_band;
+  a.band_a = band_a;
+  a.band_b = band_b;
+  a.band_m = band_m;
+  a.cut = colour_cut;
+  a.colour_width = colour_width;
+  a.mag_width = mag_width;
+  a.edges = edges;
+  a.n_bins = n_bins;
+  a.hist_bar = hist_bar;
+  a.mags_bar = mags_bar;
+  return launch_summary_vjp(a, stream);
+}
+
 }  // extern "C"

@@ -319,4 +319,20 @@ struct VjpLaunch {
 };
 int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream);
 
+// Defined in k_summary.hip.
+constexpr int SUMMARY_CHUNK = 2048;   // galaxies per partial-histogram workgroup
+struct SummaryLaunch {
+  const float *mags;
+  int n_gal, n_band, band_a, band_b, band_m;
+  double cut, colour_width, mag_width;
+  const double *edges;       // [n_bins + 1]
+  int n_bins;
+  double *partial;           // [ceil(n_gal / SUMMARY_CHUNK)][n_bins]
+  double *hist;              // [n_bins]
+  const double *hist_bar;    // [n_bins] (adjoint)
+  float *mags_bar;           // [n_gal][n_band] (adjoint)
+};
+int launch_summary(const SummaryLaunch &a, hipStream_t stream);
+int launch_summary_vjp(const SummaryLaunch &a, hipStream_t stream);
+
 }  // namespace dsps

@@ -354,7 +354,8 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
       m.bump = bump_f;
       a.meta[s] = m;
     }
-    if (a.mag_offset) a.mag_offset[s] = dmod - 2.5 * log10(1.0 + z);
+    // absolute magnitudes at z = 0 (Eq. restmag); distance terms beyond
+    if (a.mag_offset) a.mag_offset[s] = z > 0.0 ? dmod - 2.5 * log10(1.0 + z) : 0.0;
     if (a.range) {
       // padded by two grid points on each side (points outside contribute
       // exact zeros; the padding covers float32 rounding of (1+z) lambda)

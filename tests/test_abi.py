@@ -92,3 +92,22 @@ def test_library_binds_to_torch_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_pop_summary_host_checks(lib):
+    size = ctypes.c_size_t()
+    assert lib.dsps_pop_summary_workspace(10000, 32, ctypes.byref(size)) == 0
+    assert size.value >= 8 * 32 * 5                     # 5 partial blocks of 2048 galaxies
+    assert lib.dsps_pop_summary_workspace(10, 0, ctypes.byref(size)) == -2
+    assert lib.dsps_pop_summary_workspace(10, 4097, ctypes.byref(size)) == -2
+    d = ctypes.c_double
+    dummy = ctypes.c_void_p(1)
+    # band index out of range, negative width, n_bins 0: rejected before any launch
+    assert lib.dsps_pop_summary(dummy, 10, 6, 6, 2, d(0.5), d(0.1), 2, dummy, 8, d(0.1), dummy,
+                                dummy, 1 << 20, None) == -1
+    assert lib.dsps_pop_summary(dummy, 10, 6, 1, 2, d(0.5), d(-0.1), 2, dummy, 8, d(0.1), dummy,
+                                dummy, 1 << 20, None) == -1
+    assert lib.dsps_pop_summary(dummy, 10, 6, 1, 2, d(0.5), d(0.1), 2, dummy, 0, d(0.1), dummy,
+                                dummy, 1 << 20, None) == -2
+    assert lib.dsps_pop_summary_vjp(dummy, 0, 6, 1, 2, d(0.5), d(0.1), 2, dummy, 8, d(0.1), None,
+                                    None, None) == 0

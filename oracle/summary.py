@@ -4,8 +4,9 @@ Test infrastructure (see the package docstring).
 
 The Section 4.1 pipeline selects red galaxies with a colour cut and evaluates
 a histogram of r-band magnitude over the selected sample.  To carry gradients
-from such a summary back to every galaxy (the population-level target of
-Section 5), both steps are smoothed with the triweight kernel of Appendix B:
+from such a summary back to every galaxy (the population-level target that
+the discussion in Section 4.1 points to), both steps are smoothed with the
+triweight kernel of Appendix B:
 
   colour weight   w_g = T_erf((c_g - c_cut) / s_c),  c_g = m_a - m_b
   bin membership  B_k(m) = T_erf((e_{k+1} - m) / s_m) - T_erf((e_k - m) / s_m)

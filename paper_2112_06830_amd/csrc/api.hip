@@ -284,6 +284,7 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   (void)hipGetDevice(&h->device);
   h->precisions = precisions;
   h->k0_reading = k0_reading;
+  h->wave_host.assign(wave, wave + n_wave);
   h->lg_age_first = lg_age[0];
   h->lg_age_last = lg_age[n_age - 1];
   h->v = v;
@@ -394,7 +395,8 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
   L.batch = std::min(n_gal, op == DSPS_OP_MAGS_VJP ? BATCH_VJP : BATCH_FWD);
   L.n_chunks = v.n_wave_pad / TILE_L;
-  L.n_groups = (L.n_chunks + CHUNKS_PER_GROUP - 1) / CHUNKS_PER_GROUP;
+  const int cpg = chunks_per_group(precision);
+  L.n_groups = (L.n_chunks + cpg - 1) / cpg;
   const size_t elem = precision == DSPS_BF16 ? 2 : 4;
   if (op == DSPS_OP_WEIGHTS) { L.total = 0; return L; }
   if (op == DSPS_OP_SED) {
@@ -582,6 +584,26 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, 
   return DSPS_OK;
 }
 
+// Most 128-wavelength chunks one galaxy's window can span: the window holds
+// the rest wavelengths in [obs_lo, obs_hi] / (1+z) plus two points each side,
+// i.e. a range of fixed ratio obs_hi/obs_lo; its widest count on the grid is
+// reached with the lower end on a grid point.  Sizes the contraction's grid
+// (workgroups past a tile's window leave at once, so this only trims them).
+static int max_window_chunks(const SspHandle *ssp, const FiltersHandle *flt) {
+  const std::vector<double> &w = ssp->wave_host;
+  const int n = (int)w.size();
+  const double ratio = flt->obs_hi / flt->obs_lo;
+  int best = 0;
+  for (int i = 0, j = 0; i < n; ++i) {
+    j = std::max(j, i);
+    while (j < n && w[j] <= w[i] * ratio) ++j;
+    best = std::max(best, j - i);
+  }
+  const int span = std::min(best + 4, n);
+  const int n_chunks = ssp->v.n_wave_pad / TILE_L;
+  return std::min((span + TILE_L - 1) / TILE_L + 1, n_chunks);
+}
+
 // Forward pass over the sorted batch [s0, s0 + cnt): weights, fused
 // contraction and finalize.  moments requires the float32 table.
 static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
@@ -613,7 +635,8 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   m.w_pad = ws + L.w;
   m.meta = meta;
   m.range = range;
-  m.n_groups = L.n_groups;
+  const int cpg = chunks_per_group(precision);
+  m.n_groups = std::min(L.n_groups, (max_window_chunks(ssp, filters) + cpg - 1) / cpg);
   m.n_chunks = L.n_chunks;
   m.moments = moments != nullptr;
   m.partial = partial;
@@ -713,7 +736,7 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
     v.ssp = ssp->v;
     v.flt = filters->v;
     v.n_band = n_band;
-    v.n_groups = L.n_groups;
+    v.n_groups = (L.n_chunks + LBAR_CHUNKS - 1) / LBAR_CHUNKS;
     v.s_begin = s0;
     v.s_count = cnt;
     v.perm = perm;

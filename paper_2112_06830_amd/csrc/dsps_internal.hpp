@@ -14,6 +14,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/dsps.h"
 
@@ -23,7 +24,14 @@ namespace dsps {
 constexpr int AGE_PAD = 96;        // ages per metallicity row in the padded K axis
 constexpr int TILE_G = 128;        // galaxies per GEMM tile (N of the MFMA tile)
 constexpr int TILE_L = 128;        // wavelengths per chunk (M of the MFMA tile)
-constexpr int CHUNKS_PER_GROUP = 4;  // wavelength chunks one workgroup walks
+// Wavelength chunks one workgroup of the fused contraction walks: one for
+// float32 (finest load balance; measured fastest), four for bfloat16 (whose
+// cheaper chunks amortise the per-workgroup set-up).  The adjoint's Lbar
+// kernel groups LBAR_CHUNKS chunks per workgroup.
+__host__ __device__ constexpr int chunks_per_group(int precision) {
+  return precision == DSPS_BF16 ? 4 : 1;
+}
+constexpr int LBAR_CHUNKS = 4;
 constexpr int SORT_BINS = 8192;    // keys of the ordering sort (5-bit z bucket, 4+4-bit rows)
 constexpr int GEMM_THREADS = 256;  // 4 wave64s in a 2 x 2 arrangement
 constexpr int WEIGHT_WAVES = 4;    // galaxies per weights workgroup (one per wave)
@@ -69,6 +77,7 @@ struct SspHandle {
   int k0_reading = 0;
   double lg_age_first = 0, lg_age_last = 0;
   SspView v{};
+  std::vector<double> wave_host;   // rest wavelengths (host copy, for launch sizing)
   void *alloc = nullptr;           // single device allocation backing every array
 };
 
@@ -294,7 +303,7 @@ int launch_sed_gemm(const SedLaunch &a, hipStream_t stream);
 struct VjpLaunch {
   SspView ssp;
   FilterView flt;
-  int n_band, n_groups;
+  int n_band, n_groups;         // n_groups: LBAR_CHUNKS-chunk groups per tile
   int s_begin, s_count;
   const int *perm;
   const float *mags_bar;      // [n_gal][n_band] by galaxy index

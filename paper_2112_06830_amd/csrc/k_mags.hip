@@ -172,9 +172,12 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   const int c_first = win_lo / TILE_L;
   const int c_last = max((win_hi + TILE_L - 1) / TILE_L, c_first);   // exclusive
   if (group == 0 && threadIdx.x == 0) a.tile_chunks[tile] = make_int2(c_first, c_last);
-  // groups are aligned to the tile's own window: all but the last are full
-  const int c_begin = c_first + group * CHUNKS_PER_GROUP;
-  const int c_end = min(c_begin + CHUNKS_PER_GROUP, c_last);
+  // groups are aligned to the tile's own window: all but the last are full;
+  // the grid holds a host bound on one galaxy's window; a tile whose members'
+  // windows spread further hands the remaining chunks to its last group
+  constexpr int CPG = chunks_per_group(PREC);
+  const int c_begin = c_first + group * CPG;
+  const int c_end = group == a.n_groups - 1 ? c_last : min(c_begin + CPG, c_last);
   if (c_begin >= c_end) return;
 
   // ---- filter intervals into LDS

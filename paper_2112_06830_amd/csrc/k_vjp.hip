@@ -81,8 +81,8 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
   const int c_first = s_tile[0] / TILE_L;
   const int c_last = (s_tile[1] + TILE_L - 1) / TILE_L;
   const float zp1_min = __int_as_float(s_tile[2]), zp1_max = __int_as_float(s_tile[3]);
-  const int c_begin = max(group * CHUNKS_PER_GROUP, c_first);
-  const int c_end = min((group + 1) * CHUNKS_PER_GROUP, c_last);
+  const int c_begin = max(group * LBAR_CHUNKS, c_first);
+  const int c_end = min((group + 1) * LBAR_CHUNKS, c_last);
   if (c_begin >= c_end) return;
   fill_filter_pairs(F, s_pair);
   for (int i = threadIdx.x; i < TILE_G * n_band; i += blockDim.x) {

@@ -640,6 +640,7 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   m.n_chunks = L.n_chunks;
   m.moments = moments != nullptr;
   m.partial = partial;
+  m.part_rows = L.batch;
   m.tile_chunks = (int2 *)(ws + L.tiles);
   DSPS_TRY(launch_mags_gemm(m, stream));
   FinalizeLaunch f{};
@@ -649,6 +650,7 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   f.s_begin = s0;
   f.s_count = cnt;
   f.partial = partial;
+  f.part_rows = L.batch;
   f.mag_offset = offset;
   f.perm = perm;
   f.moments = m.moments;

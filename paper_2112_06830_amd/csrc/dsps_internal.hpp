@@ -264,9 +264,11 @@ struct MagsLaunch {
   int n_groups;                  // workgroups per tile (upper bound on its chunk groups)
   int n_chunks;                  // n_wave_pad / TILE_L
   int moments;                   // also the three dust moments per band (float32 only)
-  // [s_count][n_chunks][ncomp * n_band], chunks of the tile window; components
-  // num, den and, with moments, the three dust moments
+  // [n_chunks][part_rows][ncomp * n_band], chunk-major, written for the chunks
+  // of each tile's window; components num, den and, with moments, the three
+  // dust moments
   float *partial;
+  int part_rows;                 // galaxy rows per chunk (>= s_count)
   int2 *tile_chunks;             // [n_tiles] first and one-past-last chunk of each tile
 };
 // Components per band of the chunk partials.
@@ -280,6 +282,7 @@ struct FinalizeLaunch {
   const int2 *tile_chunks;
   const double *mag_offset;
   const int *perm;
+  int part_rows;  // galaxy rows per chunk of the partials
   int moments;    // partials carry the dust moments
   float *mags;    // [n_gal][n_band] by galaxy index
   float *bands;   // [n_gal][2][n_band] or null

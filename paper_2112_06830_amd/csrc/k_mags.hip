@@ -201,7 +201,6 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   const elem *st = PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16;
   const elem *w = (const elem *)a.w_pad;
   const int n_comp = NCOMP * n_band;
-  float *part_tile = a.partial + (size_t)g0 * a.n_chunks * n_comp;
 
   for (int c = c_begin; c < c_end; ++c) {
     const int l0 = c * TILE_L;
@@ -236,8 +235,9 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
         active_bands(F, zp1_min * s_lc[0].x, zp1_max * s_lc[TILE_L - 1].x));
     const int b_lo = bmask ? __builtin_ctz(bmask) : 0;
     const int b_hi = bmask ? 31 - __builtin_clz(bmask) : -1;   // inclusive
-    float *part = part_tile + (size_t)c * n_comp;
-    const int stride = a.n_chunks * n_comp;
+    // partials are chunk-major: [chunk][galaxy][component]
+    float *part = a.partial + ((size_t)c * a.part_rows + g0) * n_comp;
+    const int stride = n_comp;
     for (int base = b_lo; base <= b_hi; base += NSLOT) {
       const float2 *tab[NSLOT];
       float w0[NSLOT], wi[NSLOT];
@@ -345,16 +345,31 @@ __global__ void k_mags_finalize(FinalizeLaunch a) {
   if (local >= a.s_count) return;
   const int s = a.s_begin + local;
   const int g = a.perm ? a.perm[s] : s;
-  const int nb = a.n_band, nc = mags_components(a.moments) * nb;
+  const int nb = a.n_band, ncomp = mags_components(a.moments), nc = ncomp * nb;
   const int2 cr = a.tile_chunks[local / TILE_G];
-  const float *p = a.partial + (size_t)local * a.n_chunks * nc;
-  const double offset = a.mag_offset[s];
-  for (int b = 0; b < nb; ++b) {
-    float num = 0.0f, den = 0.0f;
-    for (int c = cr.x; c < cr.y; ++c) {
-      num += p[c * nc + b];
-      den += p[c * nc + nb + b];
+  // per band and component, chunks summed in chunk order; a galaxy's row of
+  // one chunk is contiguous and adjacent galaxies' rows are adjacent
+  float acc[5][DSPS_MAX_BAND];
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+#pragma unroll
+    for (int b = 0; b < DSPS_MAX_BAND; ++b) acc[k][b] = 0.0f;
+  for (int c = cr.x; c < cr.y; ++c) {
+    const float *p = a.partial + ((size_t)c * a.part_rows + local) * nc;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      if (k < ncomp) {
+#pragma unroll
+        for (int b = 0; b < DSPS_MAX_BAND; ++b)
+          if (b < nb) acc[k][b] += p[k * nb + b];
+      }
     }
+  }
+  const double offset = a.mag_offset[s];
+#pragma unroll
+  for (int b = 0; b < DSPS_MAX_BAND; ++b) {
+    if (b >= nb) continue;
+    const float num = acc[0][b], den = acc[1][b];
     double m;
     if (den == 0.0f) m = __builtin_nan("");
     else m = -2.5 * log10((double)num / (AB_ZERO_POINT * (double)den)) + offset;
@@ -364,11 +379,8 @@ __global__ void k_mags_finalize(FinalizeLaunch a) {
       a.bands[(size_t)g * 2 * nb + nb + b] = den;
     }
     if (a.mom) {
-      for (int k = 0; k < 3; ++k) {
-        float v = 0.0f;
-        for (int c = cr.x; c < cr.y; ++c) v += p[c * nc + (2 + k) * nb + b];
-        a.mom[(size_t)g * 3 * nb + k * nb + b] = v;
-      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a.mom[(size_t)g * 3 * nb + k * nb + b] = acc[2 + k][b];
     }
   }
 }

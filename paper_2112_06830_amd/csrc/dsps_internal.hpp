@@ -32,7 +32,7 @@ __host__ __device__ constexpr int chunks_per_group(int precision) {
   return precision == DSPS_BF16 ? 4 : 1;
 }
 constexpr int LBAR_CHUNKS = 4;
-constexpr int SORT_BINS = 8192;    // keys of the ordering sort (5-bit z bucket, 4+4-bit rows)
+constexpr int SORT_BINS = 8192;    // keys of the ordering sort (4+4-bit rows, 5-bit z bucket)
 constexpr int GEMM_THREADS = 256;  // 4 wave64s in a 2 x 2 arrangement
 constexpr int WEIGHT_WAVES = 4;    // galaxies per weights workgroup (one per wave)
 
@@ -233,7 +233,7 @@ int launch_weights(const WeightsLaunch &a, hipStream_t stream);
 
 int launch_sfh_table(const double *t_table, int n_t, const double *params, int n_gal,
                      double *sfr, hipStream_t stream);
-// Counting sort of galaxies by (redshift bucket, metallicity-row range).
+// Counting sort of galaxies by (metallicity-row range, redshift bucket).
 struct SortLaunch {
   const float *z, *lgmet, *sigma_z;
   int n_gal;

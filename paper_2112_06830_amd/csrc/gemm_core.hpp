@@ -2,9 +2,10 @@
 //
 // A workgroup of four wave64s computes a 128 x 128 output tile in a 2 x 2
 // arrangement of 64 x 64 wave tiles (2 x 2 MFMA 32x32 blocks per wave).  Both
-// operands are K-contiguous rows in memory; each K stage is staged through
-// registers into LDS rows padded to a 16-byte-aligned, bank-conflict-free
-// pitch, and every lane feeds MFMA from 16-byte LDS reads.
+// operands are K-contiguous rows in memory.  A K stage is one 64-byte slice of
+// every operand row (16 FP32 or 32 BF16 values); it travels through registers
+// into one of two LDS stage buffers, and every lane feeds MFMA from 16-byte
+// LDS reads.
 #pragma once
 
 #include "dsps_internal.hpp"
@@ -18,36 +19,37 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct GemmCfg;
-// K per LDS stage divides AGE_PAD.  Row pitches keep 16-byte alignment and
-// put the eight rows read by one 8-lane group of a 16-byte LDS read on
-// distinct bank quads.  The FP32 stage is kept short so that the fused kernel
-// fits three workgroups per CU in registers and LDS.
 template <> struct GemmCfg<DSPS_FP32> {
   using elem = float;
   static constexpr int KT = 16;
-  static constexpr int PITCH = 20;
 };
 template <> struct GemmCfg<DSPS_BF16> {
   using elem = uint16_t;
   static constexpr int KT = 32;
-  static constexpr int PITCH = 40;
 };
+constexpr int STAGE_UNITS = 4;   // 16-byte units per operand row and stage
 
+// LDS position of unit j of stage row r.  The XOR of row bits 1..3 into the
+// unit index puts the rows read together by one 16-byte LDS access (8 or 16
+// consecutive rows, one unit) and the units written together (4 units of 2
+// or 4 consecutive rows) on distinct 4-bank groups, without padding.
+__device__ __forceinline__ int stage_unit(int row, int j) {
+  return row * STAGE_UNITS + (j ^ (((row >> 1) ^ (row >> 2)) & 3));
+}
 
 template <int PREC>
 struct GemmSmem {
-  using C = GemmCfg<PREC>;
-  typename C::elem a[TILE_L * C::PITCH];
-  typename C::elem b[TILE_G * C::PITCH];
+  static_assert(GemmCfg<PREC>::KT * sizeof(typename GemmCfg<PREC>::elem) == 16 * STAGE_UNITS,
+                "one stage row is four 16-byte units");
+  u32x4 a[TILE_L * STAGE_UNITS];
+  u32x4 b[TILE_G * STAGE_UNITS];
 };
 
-// Stage one KT-wide slice of 128 rows from a K-contiguous matrix into
-// registers (vectors of 16 bytes).
+// Stage one K slice of 128 rows from a K-contiguous matrix into registers
+// (vectors of 16 bytes).
 template <int PREC>
 struct StageRegs {
-  using C = GemmCfg<PREC>;
-  static constexpr int VPR = C::KT * (int)sizeof(typename C::elem) / 16;  // vectors per row
-  static constexpr int NV = TILE_L * VPR / GEMM_THREADS;                  // vectors per thread
+  static constexpr int NV = TILE_L * STAGE_UNITS / GEMM_THREADS;   // vectors per thread
   u32x4 a[NV];
   u32x4 b[NV];
 };
@@ -61,7 +63,7 @@ __device__ __forceinline__ void load_stage(StageRegs<PREC> &r, const typename Ge
 #pragma unroll
   for (int v = 0; v < S::NV; ++v) {
     const int idx = threadIdx.x + v * GEMM_THREADS;
-    const int row = idx / S::VPR, col = idx % S::VPR;
+    const int row = idx / STAGE_UNITS, col = idx % STAGE_UNITS;
     r.a[v] = *reinterpret_cast<const u32x4 *>(st + (size_t)(l0 + row) * k_pad + kofs + col * EPV);
     u32x4 bv = {0u, 0u, 0u, 0u};
     if (g0 + row < g_count)
@@ -73,73 +75,99 @@ __device__ __forceinline__ void load_stage(StageRegs<PREC> &r, const typename Ge
 template <int PREC>
 __device__ __forceinline__ void store_stage(const StageRegs<PREC> &r, GemmSmem<PREC> &sm) {
   using S = StageRegs<PREC>;
-  using C = GemmCfg<PREC>;
-  constexpr int EPV = 16 / sizeof(typename C::elem);
 #pragma unroll
   for (int v = 0; v < S::NV; ++v) {
     const int idx = threadIdx.x + v * GEMM_THREADS;
-    const int row = idx / S::VPR, col = idx % S::VPR;
-    *reinterpret_cast<u32x4 *>(&sm.a[row * C::PITCH + col * EPV]) = r.a[v];
-    *reinterpret_cast<u32x4 *>(&sm.b[row * C::PITCH + col * EPV]) = r.b[v];
+    const int u = stage_unit(idx / STAGE_UNITS, idx % STAGE_UNITS);
+    sm.a[u] = r.a[v];
+    sm.b[u] = r.b[v];
   }
 }
 
-// acc[mb][nb] += A[rows of mb] . B[cols of nb] over one KT stage.
+__device__ __forceinline__ float4 as_float4(u32x4 v) {
+  return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                     __uint_as_float(v.w));
+}
+
+// acc[mb][nb] += A[rows of mb] . B[cols of nb] over one K stage.
 __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_FP32> &sm, int wr, int wc, int lane,
                                           f32x16 (&acc)[2][2]) {
-  using C = GemmCfg<DSPS_FP32>;
-  constexpr int HALF = C::KT / 2;      // contraction indices owned by one lane half
   const int h = lane >> 5, c = lane & 31;
-  // Lane half h supplies contraction index HALF*h + 8u + t at MFMA step
-  // (u, t), for A and B alike; each lane reads 8 contiguous values per
-  // operand block and sub-step.
+  // Lane half h supplies contraction index 8h + t at MFMA step t, for A and B
+  // alike: each lane reads units 2h and 2h + 1 of its operand rows.
+  float av[2][8], bv[2][8];
 #pragma unroll
-  for (int u = 0; u < HALF / 8; ++u) {
-    float av[2][8], bv[2][8];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      const float *p = &sm.a[(wr * 64 + mb * 32 + c) * C::PITCH + HALF * h + 8 * u];
-      const float4 x0 = *reinterpret_cast<const float4 *>(p);
-      const float4 x1 = *reinterpret_cast<const float4 *>(p + 4);
-      av[mb][0] = x0.x; av[mb][1] = x0.y; av[mb][2] = x0.z; av[mb][3] = x0.w;
-      av[mb][4] = x1.x; av[mb][5] = x1.y; av[mb][6] = x1.z; av[mb][7] = x1.w;
-    }
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-      const float *p = &sm.b[(wc * 64 + nb * 32 + c) * C::PITCH + HALF * h + 8 * u];
-      const float4 x0 = *reinterpret_cast<const float4 *>(p);
-      const float4 x1 = *reinterpret_cast<const float4 *>(p + 4);
-      bv[nb][0] = x0.x; bv[nb][1] = x0.y; bv[nb][2] = x0.z; bv[nb][3] = x0.w;
-      bv[nb][4] = x1.x; bv[nb][5] = x1.y; bv[nb][6] = x1.z; bv[nb][7] = x1.w;
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][t], bv[nb][t], acc[mb][nb], 0, 0, 0);
+  for (int mb = 0; mb < 2; ++mb) {
+    const int row = wr * 64 + mb * 32 + c;
+    const float4 x0 = as_float4(sm.a[stage_unit(row, 2 * h)]);
+    const float4 x1 = as_float4(sm.a[stage_unit(row, 2 * h + 1)]);
+    av[mb][0] = x0.x; av[mb][1] = x0.y; av[mb][2] = x0.z; av[mb][3] = x0.w;
+    av[mb][4] = x1.x; av[mb][5] = x1.y; av[mb][6] = x1.z; av[mb][7] = x1.w;
   }
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int row = wc * 64 + nb * 32 + c;
+    const float4 x0 = as_float4(sm.b[stage_unit(row, 2 * h)]);
+    const float4 x1 = as_float4(sm.b[stage_unit(row, 2 * h + 1)]);
+    bv[nb][0] = x0.x; bv[nb][1] = x0.y; bv[nb][2] = x0.z; bv[nb][3] = x0.w;
+    bv[nb][4] = x1.x; bv[nb][5] = x1.y; bv[nb][6] = x1.z; bv[nb][7] = x1.w;
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][t], bv[nb][t], acc[mb][nb], 0, 0, 0);
 }
 
 __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_BF16> &sm, int wr, int wc, int lane,
                                           f32x16 (&acc)[2][2]) {
-  using C = GemmCfg<DSPS_BF16>;
   const int h = lane >> 5, c = lane & 31;
+  // MFMA step t takes contraction indices 16t .. 16t + 15; lane half h holds
+  // 16t + 8h .. 16t + 8h + 7, which is unit 2t + h.
 #pragma unroll
-  for (int t = 0; t < C::KT / 16; ++t) {
+  for (int t = 0; t < 2; ++t) {
     bf16x8 av[2], bv[2];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
-      av[mb] = *reinterpret_cast<const bf16x8 *>(&sm.a[(wr * 64 + mb * 32 + c) * C::PITCH + 16 * t + 8 * h]);
+      av[mb] = __builtin_bit_cast(bf16x8, sm.a[stage_unit(wr * 64 + mb * 32 + c, 2 * t + h)]);
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
-      bv[nb] = *reinterpret_cast<const bf16x8 *>(&sm.b[(wc * 64 + nb * 32 + c) * C::PITCH + 16 * t + 8 * h]);
+      bv[nb] = __builtin_bit_cast(bf16x8, sm.b[stage_unit(wc * 64 + nb * 32 + c, 2 * t + h)]);
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
         acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+  }
+}
+
+// The K loop of one output tile over nk stages, stage s at K offset koff(s)
+// of both operands (A rows l0.., B rows g0.., rows of B at or past g_count
+// read as zeros).  Two LDS stage buffers: while stage s feeds MFMA, stage
+// s + 1 is written to the other buffer and stage s + 2 is loaded into
+// registers, with one barrier per stage.  On entry no wave may still read
+// sm; on return every wave has passed a barrier after its last read of it.
+template <int PREC, typename KOffset>
+__device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const typename GemmCfg<PREC>::elem *st,
+                                           int k_pad, int l0, const typename GemmCfg<PREC>::elem *w,
+                                           int g0, int g_count, int nk, KOffset koff, int wr, int wc,
+                                           int lane, f32x16 (&acc)[2][2]) {
+  StageRegs<PREC> regs;
+  if (nk > 0) {
+    load_stage<PREC>(regs, st, k_pad, l0, w, g0, g_count, koff(0));
+    store_stage<PREC>(regs, sm[0]);
+    if (nk > 1) load_stage<PREC>(regs, st, k_pad, l0, w, g0, g_count, koff(1));
+  }
+  __syncthreads();
+  for (int ks = 0; ks < nk; ++ks) {
+    mma_stage(sm[ks & 1], wr, wc, lane, acc);
+    if (ks + 1 < nk) {
+      store_stage<PREC>(regs, sm[(ks + 1) & 1]);
+      if (ks + 2 < nk) load_stage<PREC>(regs, st, k_pad, l0, w, g0, g_count, koff(ks + 2));
+    }
+    __syncthreads();
   }
 }
 
@@ -156,25 +184,20 @@ __device__ __forceinline__ unsigned active_bands(const FilterView &F, float o_lo
   return m;
 }
 
-// Filter transmission as (T[i], T[i+1] - T[i]) per grid interval, so that an
-// interpolation is one aligned 8-byte LDS read and one FMA.  Whole workgroup.
-__device__ __forceinline__ void fill_filter_pairs(const FilterView &F, float2 *s_pair) {
-  const int n_int = F.n_pts - 1;
-  for (int i = threadIdx.x; i < F.n_band * n_int; i += blockDim.x) {
-    const int b = i / n_int, k = i - b * n_int;
-    const float t0 = F.trans[b * F.n_pts + k], t1 = F.trans[b * F.n_pts + k + 1];
-    s_pair[i] = make_float2(t0, t1 - t0);
-  }
+// Filter transmission tables into LDS, [n_band][n_pts].  Whole workgroup.
+__device__ __forceinline__ void fill_filter_table(const FilterView &F, float *s_tr) {
+  for (int i = threadIdx.x; i < F.n_band * F.n_pts; i += blockDim.x) s_tr[i] = F.trans[i];
 }
 
-// Transmission of one band at grid coordinate u = (lambda - first) / spacing:
-// linear interpolation between grid points, zero outside [0, n_int].  Matches
-// filter_at below bit for bit.
-__device__ __forceinline__ float filter_pair_at(const float2 *tab, int n_int, float u) {
+// Transmission of one band (table tr of n_int + 1 points) at grid coordinate
+// u = (lambda - first) / spacing: linear interpolation between grid points,
+// zero outside [0, n_int].  The two points come from one paired LDS read.
+// Matches filter_at below bit for bit.
+__device__ __forceinline__ float filter_table_at(const float *tr, int n_int, float u) {
   const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, (float)n_int);
   const int i = min((int)uc, n_int - 1);
-  const float2 pr = tab[i];
-  const float t = fmaf(uc - (float)i, pr.y, pr.x);
+  const float t0 = tr[i], t1 = tr[i + 1];
+  const float t = fmaf(uc - (float)i, t1 - t0, t0);
   return u == uc ? t : 0.0f;
 }
 

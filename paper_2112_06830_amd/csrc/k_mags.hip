@@ -101,8 +101,8 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   using C = GemmCfg<PREC>;
   using elem = typename C::elem;
   constexpr int NCOMP = MOM ? 5 : 2;
-  static_assert(sizeof(GemmSmem<PREC>) >= sizeof(float) * 128 * NCOMP * NSLOT, "reduction alias");
-  __shared__ GemmSmem<PREC> sm;
+  static_assert(2 * sizeof(GemmSmem<PREC>) >= sizeof(float) * 128 * NCOMP * NSLOT, "reduction alias");
+  __shared__ GemmSmem<PREC> sm[2];
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
   // window lo, window hi, min and max of (1+z) as float bits (positive floats
@@ -111,10 +111,8 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   __shared__ int s_tile[5];
   __shared__ unsigned s_kblk[KBLOCK_WORDS];
   __shared__ int s_koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];
-  // transmission as (T[i], T[i+1] - T[i]) per grid interval: one aligned
-  // 8-byte read and one FMA per interpolation
-  extern __shared__ float2 s_pair[];   // [n_band][n_pts - 1]
-  float *s_red = reinterpret_cast<float *>(&sm);
+  extern __shared__ float s_tr[];      // filter transmissions [n_band][n_pts]
+  float *s_red = reinterpret_cast<float *>(&sm[0]);
 
   int tile, group;
   xcd_tile_group(blockIdx.x, a.n_groups, tile, group);
@@ -180,9 +178,9 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   const int c_end = group == a.n_groups - 1 ? c_last : min(c_begin + CPG, c_last);
   if (c_begin >= c_end) return;
 
-  // ---- filter intervals into LDS
+  // ---- filter tables into LDS
   const int n_int = n_pts - 1;
-  fill_filter_pairs(F, s_pair);
+  fill_filter_table(F, s_tr);
 
   // ---- per-galaxy parameters of this lane's two columns
   float zp1[2], da[2], dl[2], bp[2];
@@ -217,16 +215,9 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
 
-    StageRegs<PREC> regs;
-    if (nk > 0) load_stage<PREC>(regs, st, P.k_pad, l0, w, g0, a.s_count, s_koff[0]);
-    for (int ks = 0; ks < nk; ++ks) {
-      __syncthreads();
-      store_stage<PREC>(regs, sm);
-      __syncthreads();
-      if (ks + 1 < nk) load_stage<PREC>(regs, st, P.k_pad, l0, w, g0, a.s_count, s_koff[ks + 1]);
-      mma_stage(sm, wr, wc, lane, acc);
-    }
-    __syncthreads();   // s_lc / s_q / filter intervals visible
+    gemm_kloop<PREC>(sm, st, P.k_pad, l0, w, g0, a.s_count, nk, [&](int ks) { return s_koff[ks]; },
+                     wr, wc, lane, acc);
+    // (the loop's closing barrier makes s_lc, s_q and the filter tables visible)
 
     // ---- epilogue: attenuated SED x resampled transmission, summed over the
     // bands that can see this chunk
@@ -239,13 +230,13 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
     float *part = a.partial + ((size_t)c * a.part_rows + g0) * n_comp;
     const int stride = n_comp;
     for (int base = b_lo; base <= b_hi; base += NSLOT) {
-      const float2 *tab[NSLOT];
+      const float *tab[NSLOT];
       float w0[NSLOT], wi[NSLOT];
 #pragma unroll
       for (int k = 0; k < NSLOT; ++k) {
         const int b = min(base + k, n_band - 1);   // slots past b_hi are computed, not stored
         const float2 gr = F.grid[b];
-        tab[k] = s_pair + b * n_int;
+        tab[k] = s_tr + b * n_pts;
         w0[k] = gr.x;
         wi[k] = gr.y;
       }
@@ -288,7 +279,7 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
             if (MOM) { x[0] = e * kl; x[1] = e * k0x * lc.y; x[2] = e * lc.w; }
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
-              const float t = filter_pair_at(tab[k], n_int, (lobs - w0[k]) * wi[k]);
+              const float t = filter_table_at(tab[k], n_int, (lobs - w0[k]) * wi[k]);
               sum[0][nb][k] += t * e;
               sum[1][nb][k] += t * q;
               if (MOM) {
@@ -325,7 +316,7 @@ int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
   const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
   const int blocks = (n_tiles + 7) / 8 * 8 * a.n_groups;
-  const size_t lds = sizeof(float2) * a.flt.n_band * (a.flt.n_pts - 1);
+  const size_t lds = sizeof(float) * a.flt.n_band * a.flt.n_pts;
   ProfScope prof(DSPS_KERNEL_MAGS_GEMM, stream);
   if (a.precision == DSPS_BF16) {
     if (a.moments) return DSPS_ERR_UNSUPPORTED;

@@ -9,7 +9,7 @@ template <int PREC>
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   using C = GemmCfg<PREC>;
   using elem = typename C::elem;
-  __shared__ GemmSmem<PREC> sm;
+  __shared__ GemmSmem<PREC> sm[2];
   const int chunk = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
@@ -28,15 +28,8 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
       for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
 
   const int nk = P.k_pad / C::KT;
-  StageRegs<PREC> regs;
-  load_stage<PREC>(regs, st, P.k_pad, l0, w, g0, a.g_count, 0);
-  for (int ks = 0; ks < nk; ++ks) {
-    __syncthreads();
-    store_stage<PREC>(regs, sm);
-    __syncthreads();
-    if (ks + 1 < nk) load_stage<PREC>(regs, st, P.k_pad, l0, w, g0, a.g_count, (ks + 1) * C::KT);
-    mma_stage(sm, wr, wc, lane, acc);
-  }
+  gemm_kloop<PREC>(sm, st, P.k_pad, l0, w, g0, a.g_count, nk, [](int ks) { return ks * C::KT; },
+                   wr, wc, lane, acc);
 
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {

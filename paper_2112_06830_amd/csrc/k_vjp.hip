@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
   __shared__ float4 s_meta[TILE_G];    // (1 + z, dust_a, delta, bump)
   __shared__ float2 s_grid[DSPS_MAX_BAND];
   __shared__ int s_tile[4];            // window lo, window hi, min and max of (1+z) bits
-  extern __shared__ float2 s_pair[];   // [n_band][n_pts - 1] filter intervals
+  extern __shared__ float s_tr[];      // filter transmissions [n_band][n_pts]
   const int group = blockIdx.x, tile = blockIdx.y;
   const SspView P = a.ssp;
   const FilterView F = a.flt;
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
   const int c_begin = max(group * LBAR_CHUNKS, c_first);
   const int c_end = min((group + 1) * LBAR_CHUNKS, c_last);
   if (c_begin >= c_end) return;
-  fill_filter_pairs(F, s_pair);
+  fill_filter_table(F, s_tr);
   for (int i = threadIdx.x; i < TILE_G * n_band; i += blockDim.x) {
     const int col = i / n_band, b = i % n_band;
     s_gam[col * DSPS_MAX_BAND + b] =
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
       for (int k = 0; k < n_act; ++k) {
         const int b = b_lo + k;
         const float2 gr = s_grid[b];
-        gs += s_gam[col * DSPS_MAX_BAND + b] * filter_pair_at(s_pair + b * n_int, n_int, (lobs - gr.x) * gr.y);
+        gs += s_gam[col * DSPS_MAX_BAND + b] * filter_table_at(s_tr + b * F.n_pts, n_int, (lobs - gr.x) * gr.y);
       }
       const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(m.z * lc.y));
       const float att = __builtin_amdgcn_exp2f(m.y * fmaf(m.w, lc.w, k0x));
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
 // Rows (M) are SSP rows k, columns (N) galaxies, reduction over wavelength.
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   using C = GemmCfg<DSPS_FP32>;
-  __shared__ GemmSmem<DSPS_FP32> sm;
+  __shared__ GemmSmem<DSPS_FP32> sm[2];
   __shared__ int s_tile[2];
   const int kblk = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -153,16 +153,8 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
       for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
 
   const int nk = l_end > l_begin ? (l_end - l_begin) / C::KT : 0;
-  StageRegs<DSPS_FP32> regs;
-  if (nk > 0) load_stage<DSPS_FP32>(regs, P.sk32, nwp, k0, a.lbar, g0, a.s_count, l_begin);
-  for (int ks = 0; ks < nk; ++ks) {
-    __syncthreads();
-    store_stage<DSPS_FP32>(regs, sm);
-    __syncthreads();
-    if (ks + 1 < nk)
-      load_stage<DSPS_FP32>(regs, P.sk32, nwp, k0, a.lbar, g0, a.s_count, l_begin + (ks + 1) * C::KT);
-    mma_stage(sm, wr, wc, lane, acc);
-  }
+  gemm_kloop<DSPS_FP32>(sm, P.sk32, nwp, k0, a.lbar, g0, a.s_count, nk,
+                        [=](int ks) { return l_begin + ks * C::KT; }, wr, wc, lane, acc);
 
   const int kp = P.k_pad;
 #pragma unroll
@@ -414,7 +406,7 @@ int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
     hipLaunchKernelGGL(k_vjp_gamma, dim3((a.s_count + 255) / 256), dim3(256), 0, stream, a);
   } else if (stage == 1) {
     ProfScope prof(DSPS_KERNEL_VJP_LBAR, stream);
-    const size_t lds = sizeof(float2) * a.flt.n_band * (a.flt.n_pts - 1);
+    const size_t lds = sizeof(float) * a.flt.n_band * a.flt.n_pts;
     hipLaunchKernelGGL(k_vjp_lbar, dim3(a.n_groups, tiles), dim3(256), lds, stream, a);
   } else if (stage == 2) {
     ProfScope prof(DSPS_KERNEL_VJP_WBAR, stream);

@@ -115,14 +115,24 @@ __host__ __device__ inline int coarse_stride(int n_wave) {
   return (n_wave + COARSE_WAVE - 1) / COARSE_WAVE;
 }
 
-// Time-grid rounds (of 64 nodes each) whose SFR values are loaded together.
-constexpr int SFR_BATCH = 8;
+// Consecutive time-grid segments each lane takes per scan round (a round
+// covers 64 * SFR_PER_LANE segments).
+constexpr int SFR_PER_LANE = 4;
+constexpr int SFR_ROUND = 64 * SFR_PER_LANE;
+
+// Orders one wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Block-shared LDS of the weights kernel, in doubles.
 __host__ __device__ inline size_t weights_lds_doubles(int n_t, int n_age, int n_met, int n_wave,
                                                       int k_pad) {
   const int n_coarse = (n_wave + coarse_stride(n_wave) - 1) / coarse_stride(n_wave);
-  return (size_t)n_t + (n_age + 1) + n_age + (n_met + 1) + n_coarse + (k_pad + 1) / 2;
+  return (size_t)n_t + (n_age + 1) + n_age + (n_met + 1) + n_coarse + (k_pad + 1) / 2 +
+         (size_t)WEIGHT_WAVES * 2 * SFR_ROUND;
 }
 
 // TABULATED: the SFR arrives as a table row per galaxy; otherwise it is
@@ -143,6 +153,9 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   float *s_ks = (float *)(s_cw + n_coarse);           // [k_pad]
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  // per wave: cumulative mass before, and mass of, each segment of a round
+  double *s_pre = (double *)(s_ks + ((P.k_pad + 1) & ~1)) + wave * 2 * SFR_ROUND;
+  double *s_seg = s_pre + SFR_ROUND;
   for (int n = threadIdx.x; n < n_t; n += blockDim.x) tt[n] = a.t_table[n];
   for (int n = threadIdx.x; n <= n_age; n += blockDim.x) s_aedge[n] = P.age_edges[n];
   for (int n = threadIdx.x; n < n_age; n += blockDim.x) s_lgage[n] = P.lg_age[n];
@@ -162,14 +175,16 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   const float lgmet_f = a.lgmet[g], sig_f = a.sigma_z[g];
   const float av_f = a.av[g], delta_f = a.delta[g], bump_f = a.bump[g];
   const double *row = TABULATED ? a.sfr + (size_t)g * n_t : nullptr;
-  double v[SFR_BATCH], v_next = 0.0;
+  // SFR at nodes base + SFR_PER_LANE lane + k of the round at base, and at
+  // the first node of the next round (the first round is loaded up front)
+  double v[SFR_PER_LANE], v_end = 0.0;
   if (TABULATED) {
 #pragma unroll
-    for (int r = 0; r < SFR_BATCH; ++r) {
-      const int n = 64 * r + lane;
-      v[r] = n < n_t ? row[n] : 0.0;
+    for (int k = 0; k < SFR_PER_LANE; ++k) {
+      const int n = SFR_PER_LANE * lane + k;
+      v[k] = n < n_t ? row[n] : 0.0;
     }
-    if (64 * SFR_BATCH < n_t) v_next = row[64 * SFR_BATCH];
+    if (SFR_ROUND < n_t) v_end = row[SFR_ROUND];
   }
 
   const double t_obs = wave_age_at_z(z, a.cosmo, a.gl, lane);
@@ -206,11 +221,13 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
       fe[q] = kind[q] == 1 ? (te[q] - tt[lo[q]]) / (tt[lo[q] + 1] - tt[lo[q]]) : 0.0;
   }
 
-  // ---- cumulative trapezoid of the SFR row, one round of 64 segments at a
-  // time: segment m joins nodes m and m + 1 and lives on lane m % 64.  The
-  // mass before a round (carry) plus the wave's exclusive scan gives the
-  // cumulative mass at every node of the round; edges whose interval starts
-  // there read it from the owning lane.  Nothing is stored per node.
+  // ---- cumulative trapezoid of the SFR row, one round of SFR_ROUND segments
+  // at a time: segment m joins nodes m and m + 1; lane l holds segments
+  // base + 4 l .. base + 4 l + 3, sums them locally and joins the wave's
+  // exclusive scan of the lane totals.  The mass before each segment and the
+  // segment's own mass go to the wave's LDS buffer, where every age-bin edge
+  // whose interval lies in the round reads its cumulative mass.  Nothing is
+  // kept per galaxy beyond the round.
   double pa = 0, ptau = 1, palpha = 0, pq = 0, ptq = 0;
   if (!TABULATED) {
     pa = a.sfh_params[g]; ptau = a.sfh_params[a.n_gal + g];
@@ -220,47 +237,52 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   const int n_seg = n_t - 1;
   double carry = 0.0;
   double em[2] = {0.0, 0.0};
-  for (int base = 0; base < n_seg; base += 64 * SFR_BATCH) {
-    // SFR at nodes base + 64 r + lane (the first batch of a tabulated row was
-    // loaded up front) and at the first node of the next batch
-    const int n_next = base + 64 * SFR_BATCH;
+  for (int base = 0; base < n_seg; base += SFR_ROUND) {
+    const int n0 = base + SFR_PER_LANE * lane;
     if (!TABULATED || base > 0) {
 #pragma unroll
-      for (int r = 0; r < SFR_BATCH; ++r) {
-        const int n = base + 64 * r + lane;
-        v[r] = 0.0;
-        if (n < n_t) v[r] = TABULATED ? row[n] : sfr_param(tt[n], pa, ptau, palpha, pq, ptq);
+      for (int k = 0; k < SFR_PER_LANE; ++k) {
+        const int n = n0 + k;
+        v[k] = 0.0;
+        if (n < n_t) v[k] = TABULATED ? row[n] : sfr_param(tt[n], pa, ptau, palpha, pq, ptq);
       }
-      v_next = 0.0;
-      if (n_next < n_t)
-        v_next = TABULATED ? row[n_next] : sfr_param(tt[n_next], pa, ptau, palpha, pq, ptq);
+      const int n_end = base + SFR_ROUND;
+      v_end = 0.0;
+      if (n_end < n_t) v_end = TABULATED ? row[n_end] : sfr_param(tt[n_end], pa, ptau, palpha, pq, ptq);
     }
+    double after = __shfl_down(v[0], 1, 64);          // SFR at node n0 + 4
+    if (lane == 63) after = v_end;
+    double seg[SFR_PER_LANE], part[SFR_PER_LANE];    // segment masses, local inclusive sums
 #pragma unroll
-    for (int r = 0; r < SFR_BATCH; ++r) {
-      const int first = base + 64 * r;
-      if (first >= n_seg) break;                       // uniform
-      const int m = first + lane;
-      double s1 = __shfl_down(v[r], 1, 64);            // SFR at node m + 1
-      const double wrap = r + 1 < SFR_BATCH ? __shfl(v[r + 1 < SFR_BATCH ? r + 1 : r], 0, 64) : v_next;
-      if (lane == 63) s1 = wrap;
-      const double seg = m < n_seg ? 0.5 * (v[r] + s1) * (tt[m + 1] - tt[m]) * YEARS_PER_GYR : 0.0;
-      double incl = seg;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const double up = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += up;
-      }
-      double excl = __shfl_up(incl, 1, 64);
-      if (lane == 0) excl = 0.0;
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int src = lo[q] - first;
-        const double pe = __shfl(excl, src & 63, 64);
-        const double sg = __shfl(seg, src & 63, 64);
-        if (kind[q] == 1 && src >= 0 && src < 64) em[q] = (carry + pe) + fe[q] * sg;
-      }
-      carry += __shfl(incl, 63, 64);
+    for (int k = 0; k < SFR_PER_LANE; ++k) {
+      const int m = n0 + k;
+      const double right = k + 1 < SFR_PER_LANE ? v[k + 1 < SFR_PER_LANE ? k + 1 : k] : after;
+      seg[k] = m < n_seg ? 0.5 * (v[k] + right) * (tt[m + 1] - tt[m]) * YEARS_PER_GYR : 0.0;
+      part[k] = k == 0 ? seg[0] : part[k > 0 ? k - 1 : 0] + seg[k];
     }
+    const double total = part[SFR_PER_LANE - 1];
+    double incl = total;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double up = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += up;
+    }
+    double excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 0.0;
+    const double before = carry + excl;
+#pragma unroll
+    for (int k = 0; k < SFR_PER_LANE; ++k) {
+      s_pre[SFR_PER_LANE * lane + k] = k == 0 ? before : before + part[k > 0 ? k - 1 : 0];
+      s_seg[SFR_PER_LANE * lane + k] = seg[k];
+    }
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int src = lo[q] - base;
+      if (kind[q] == 1 && src >= 0 && src < SFR_ROUND) em[q] = s_pre[src] + fe[q] * s_seg[src];
+    }
+    carry += __shfl(incl, 63, 64);
+    wave_sync();                                      // buffer reused by the next round
   }
 #pragma unroll
   for (int q = 0; q < 2; ++q)
@@ -390,11 +412,13 @@ int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
 }
 
 // ------------------------------------------------------------ ordering sort
-// Key = (redshift bucket of 1/16 in log2(1+z), lowest and highest metallicity
-// row the galaxy's MDF can reach).  Galaxies of one 128-galaxy tile then share
-// a rest-wavelength window and few non-zero metallicity rows, so the GEMM
-// computes fewer chunks and K blocks.  The order never changes a galaxy's
-// result (the kernels' tiling is exact), only the work.
+// Key = (lowest and highest metallicity row the galaxy's MDF can reach,
+// redshift bucket of 1/16 in log2(1+z)).  Galaxies of one 128-galaxy tile then
+// share their non-zero metallicity rows and, within a row range, a narrow
+// redshift span, hence a rest-wavelength window and the age blocks below the
+// lookback time; the rows come first because a mismatch there costs whole
+// K rows for every wavelength of the tile.  The order never changes a
+// galaxy's result (the kernels' tiling is exact), only the work.
 __device__ __forceinline__ int sort_key(const SortLaunch &a, int g) {
   const float z = a.z[g];
   int zb = 0;
@@ -411,7 +435,7 @@ __device__ __forceinline__ int sort_key(const SortLaunch &a, int g) {
     jlo += a.met_edges[j] <= lo;
     jhi += a.met_edges[j] <= hi;
   }
-  return (zb << 8) | (min(jlo, 15) << 4) | min(jhi, 15);
+  return (min(jlo, 15) << 9) | (min(jhi, 15) << 5) | zb;
 }
 
 __global__ void k_fill_int(int *p, int n, int v) {
@@ -494,7 +518,7 @@ __global__ __launch_bounds__(1024) void k_sort_scatter(SortLaunch a) {
 }
 
 int launch_sort(const SortLaunch &a, hipStream_t stream) {
-  static_assert(SORT_BINS % 1024 == 0 && SORT_BINS >= (32 << 8), "key range");
+  static_assert(SORT_BINS % 1024 == 0 && SORT_BINS >= (16 << 9), "key range");
   if (a.n_gal <= 0) return DSPS_OK;
   ProfScope prof(DSPS_KERNEL_ZSORT, stream);
   hipLaunchKernelGGL(k_fill_int, dim3(SORT_BINS / 256), dim3(256), 0, stream, a.hist, SORT_BINS, 0);

@@ -414,7 +414,7 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   // float32 forward passes may carry the dust moments
   const int ncomp = mags_components(precision == DSPS_FP32);
   L.partial = take(sizeof(float) * (size_t)L.batch * L.n_chunks * ncomp * n_band);
-  L.tiles = take(sizeof(int2) * (size_t)((L.batch + TILE_G - 1) / TILE_G));
+  L.tiles = take(sizeof(TilePlan) * (size_t)((L.batch + TILE_G - 1) / TILE_G));
   if (op == DSPS_OP_MAGS_VJP) {
     L.gamma = take(sizeof(float) * (size_t)n_gal * n_band);
     L.dust = take(sizeof(float) * (size_t)L.batch * 3);
@@ -641,12 +641,12 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   m.moments = moments != nullptr;
   m.partial = partial;
   m.part_rows = L.batch;
-  m.tile_chunks = (int2 *)(ws + L.tiles);
+  m.plan = (TilePlan *)(ws + L.tiles);
   DSPS_TRY(launch_mags_gemm(m, stream));
   FinalizeLaunch f{};
   f.n_band = filters->v.n_band;
   f.n_chunks = L.n_chunks;
-  f.tile_chunks = (const int2 *)(ws + L.tiles);
+  f.plan = (const TilePlan *)(ws + L.tiles);
   f.s_begin = s0;
   f.s_count = cnt;
   f.partial = partial;

@@ -253,6 +253,18 @@ int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n
                              int k_pad, int sk_rows, float *sk32, hipStream_t stream);
 
 // Defined in k_mags.hip.
+// Per 128-galaxy tile of the fused contraction, computed once before it: the
+// union of the members' wavelength windows as chunks [c_first, c_last), the
+// range of 1 + z, and the K offsets of the stages that hold a non-zero weight
+// for some member, in ascending order.
+struct TilePlan {
+  int c_first, c_last;
+  int nk;
+  float zp1_min, zp1_max;
+  int pad[3];
+  int koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];
+};
+
 struct MagsLaunch {
   SspView ssp;
   FilterView flt;
@@ -269,7 +281,7 @@ struct MagsLaunch {
   // dust moments
   float *partial;
   int part_rows;                 // galaxy rows per chunk (>= s_count)
-  int2 *tile_chunks;             // [n_tiles] first and one-past-last chunk of each tile
+  TilePlan *plan;                // [n_tiles], written by the planning pass
 };
 // Components per band of the chunk partials.
 __host__ __device__ inline int mags_components(int moments) { return moments ? 5 : 2; }
@@ -279,7 +291,7 @@ struct FinalizeLaunch {
   int n_band, n_chunks;
   int s_begin, s_count;
   const float *partial;
-  const int2 *tile_chunks;
+  const TilePlan *plan;
   const double *mag_offset;
   const int *perm;
   int part_rows;  // galaxy rows per chunk of the partials

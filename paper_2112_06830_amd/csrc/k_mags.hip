@@ -105,12 +105,7 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   __shared__ GemmSmem<PREC> sm[2];
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
-  // window lo, window hi, min and max of (1+z) as float bits (positive floats
-  // order like their bit patterns), stage count; union of the non-zero
-  // weight blocks; K offset of each stage in order
-  __shared__ int s_tile[5];
-  __shared__ unsigned s_kblk[KBLOCK_WORDS];
-  __shared__ int s_koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];
+  __shared__ int s_koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];   // K offset of each stage
   extern __shared__ float s_tr[];      // filter transmissions [n_band][n_pts]
   float *s_red = reinterpret_cast<float *>(&sm[0]);
 
@@ -128,55 +123,19 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   const int g0 = tile * TILE_G;                 // first batch-local galaxy of the tile
   const int nvalid = min(TILE_G, a.s_count - g0);
 
-  // ---- tile union of windows and non-zero weight blocks
-  if (threadIdx.x == 0) {
-    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0;
-#pragma unroll
-    for (int w = 0; w < KBLOCK_WORDS; ++w) s_kblk[w] = 0u;
-  }
-  __syncthreads();
-  if (threadIdx.x < nvalid) {
-    const GalaxyRange r = a.range[a.s_begin + g0 + threadIdx.x];
-    const int zbits = __float_as_int(a.meta[a.s_begin + g0 + threadIdx.x].zp1);
-    atomicMin(&s_tile[0], r.win_lo);
-    atomicMax(&s_tile[1], r.win_hi);
-    atomicMin(&s_tile[2], zbits);
-    atomicMax(&s_tile[3], zbits);
-#pragma unroll
-    for (int w = 0; w < KBLOCK_WORDS; ++w)
-      if (r.kblk[w]) atomicOr(&s_kblk[w], r.kblk[w]);
-  }
-  __syncthreads();
-  // stages in ascending K: a stage of KT ages covers KT / 16 blocks of a row
-  // and runs when any of them holds a weight for some galaxy of the tile
-  if (threadIdx.x == 0) {
-    constexpr int BPS = C::KT / KBLOCK_AGES;               // blocks per stage
-    int n = 0;
-    for (int j = 0; j < P.n_met; ++j)
-      for (int st = 0; st < AGE_PAD / C::KT; ++st) {
-        bool any = false;
-        for (int u = 0; u < BPS; ++u) {
-          const int bit = j * KBLOCKS_PER_ROW + st * BPS + u;
-          any |= (s_kblk[bit >> 5] >> (bit & 31)) & 1u;
-        }
-        if (any) s_koff[n++] = j * AGE_PAD + st * C::KT;
-      }
-    s_tile[4] = n;
-  }
-  __syncthreads();
-  const int win_lo = s_tile[0], win_hi = s_tile[1];
-  const float zp1_min = __int_as_float(s_tile[2]), zp1_max = __int_as_float(s_tile[3]);
-  const int nk = s_tile[4];
-  const int c_first = win_lo / TILE_L;
-  const int c_last = max((win_hi + TILE_L - 1) / TILE_L, c_first);   // exclusive
-  if (group == 0 && threadIdx.x == 0) a.tile_chunks[tile] = make_int2(c_first, c_last);
-  // groups are aligned to the tile's own window: all but the last are full;
-  // the grid holds a host bound on one galaxy's window; a tile whose members'
-  // windows spread further hands the remaining chunks to its last group
+  // ---- the tile's plan: groups are aligned to the tile's own window, all
+  // but the last full; the grid holds a host bound on one galaxy's window,
+  // and a tile whose members' windows spread further hands the remaining
+  // chunks to its last group
+  const TilePlan *pl = a.plan + tile;
+  const int c_first = pl->c_first, c_last = pl->c_last;
   constexpr int CPG = chunks_per_group(PREC);
   const int c_begin = c_first + group * CPG;
   const int c_end = group == a.n_groups - 1 ? c_last : min(c_begin + CPG, c_last);
   if (c_begin >= c_end) return;
+  const int nk = pl->nk;
+  const float zp1_min = pl->zp1_min, zp1_max = pl->zp1_max;
+  for (int t = threadIdx.x; t < nk; t += blockDim.x) s_koff[t] = pl->koff[t];
 
   // ---- filter tables into LDS
   const int n_int = n_pts - 1;
@@ -312,11 +271,68 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   }
 }
 
+// One workgroup of TILE_G threads per tile: union of the members' windows,
+// redshifts and non-zero weight blocks, then the stage list, ascending in K
+// (a stage of KT ages covers KT / 16 blocks of a row and runs when any of them
+// holds a weight for some member).
+template <int PREC>
+__global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
+  using C = GemmCfg<PREC>;
+  // window lo, window hi, min and max of (1+z) as float bits (positive floats
+  // order like their bit patterns)
+  __shared__ int s_tile[4];
+  __shared__ unsigned s_kblk[KBLOCK_WORDS];
+  const int tile = blockIdx.x;
+  const int g0 = tile * TILE_G;
+  const int nvalid = min(TILE_G, a.s_count - g0);
+  if (threadIdx.x == 0) {
+    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0;
+#pragma unroll
+    for (int w = 0; w < KBLOCK_WORDS; ++w) s_kblk[w] = 0u;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nvalid) {
+    const GalaxyRange r = a.range[a.s_begin + g0 + threadIdx.x];
+    const int zbits = __float_as_int(a.meta[a.s_begin + g0 + threadIdx.x].zp1);
+    atomicMin(&s_tile[0], r.win_lo);
+    atomicMax(&s_tile[1], r.win_hi);
+    atomicMin(&s_tile[2], zbits);
+    atomicMax(&s_tile[3], zbits);
+#pragma unroll
+    for (int w = 0; w < KBLOCK_WORDS; ++w)
+      if (r.kblk[w]) atomicOr(&s_kblk[w], r.kblk[w]);
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  TilePlan *pl = a.plan + tile;
+  constexpr int BPS = C::KT / KBLOCK_AGES;   // blocks per stage
+  int n = 0;
+  for (int j = 0; j < a.ssp.n_met; ++j)
+    for (int st = 0; st < AGE_PAD / C::KT; ++st) {
+      bool any = false;
+      for (int u = 0; u < BPS; ++u) {
+        const int bit = j * KBLOCKS_PER_ROW + st * BPS + u;
+        any |= (s_kblk[bit >> 5] >> (bit & 31)) & 1u;
+      }
+      if (any) pl->koff[n++] = j * AGE_PAD + st * C::KT;
+    }
+  const int c_first = s_tile[0] / TILE_L;
+  pl->c_first = c_first;
+  pl->c_last = max((s_tile[1] + TILE_L - 1) / TILE_L, c_first);   // exclusive
+  pl->nk = n;
+  pl->zp1_min = __int_as_float(s_tile[2]);
+  pl->zp1_max = __int_as_float(s_tile[3]);
+}
+
 int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
   const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
   const int blocks = (n_tiles + 7) / 8 * 8 * a.n_groups;
   const size_t lds = sizeof(float) * a.flt.n_band * a.flt.n_pts;
+  if (a.precision == DSPS_BF16)
+    hipLaunchKernelGGL(k_tile_plan<DSPS_BF16>, dim3(n_tiles), dim3(TILE_G), 0, stream, a);
+  else
+    hipLaunchKernelGGL(k_tile_plan<DSPS_FP32>, dim3(n_tiles), dim3(TILE_G), 0, stream, a);
   ProfScope prof(DSPS_KERNEL_MAGS_GEMM, stream);
   if (a.precision == DSPS_BF16) {
     if (a.moments) return DSPS_ERR_UNSUPPORTED;
@@ -337,7 +353,8 @@ __global__ void k_mags_finalize(FinalizeLaunch a) {
   const int s = a.s_begin + local;
   const int g = a.perm ? a.perm[s] : s;
   const int nb = a.n_band, ncomp = mags_components(a.moments), nc = ncomp * nb;
-  const int2 cr = a.tile_chunks[local / TILE_G];
+  const TilePlan &pl = a.plan[local / TILE_G];
+  const int2 cr = make_int2(pl.c_first, pl.c_last);
   // per band and component, chunks summed in chunk order; a galaxy's row of
   // one chunk is contiguous and adjacent galaxies' rows are adjacent
   float acc[5][DSPS_MAX_BAND];

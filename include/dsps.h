@@ -179,6 +179,8 @@ int dsps_sfh_table(const double *t_table, int n_t, const double *sfh_params, int
  *          midpoints of adjacent SSP ages (0 and +inf outermost), metallicity
  *          bins by midpoints of adjacent log10 Z (-inf and +inf outermost).
  *   mstar  [n_gal] float64 total mass formed up to t(z), or NULL
+ *   workspace  dsps_workspace_size(DSPS_OP_WEIGHTS, ...) bytes (the cosmic
+ *          time at each galaxy's redshift)
  * ------------------------------------------------------------------------ */
 int dsps_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
                  float *w, double *mstar, void *workspace, size_t workspace_bytes,
@@ -290,7 +292,7 @@ int dsps_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float *s
  * usable under stream capture.
  * ------------------------------------------------------------------------ */
 typedef enum {
-  DSPS_KERNEL_WEIGHTS = 0,      /* age masses, MDF weights, W rows          */
+  DSPS_KERNEL_WEIGHTS = 0,      /* per-galaxy scalars, age masses, W rows   */
   DSPS_KERNEL_MAGS_GEMM = 1,    /* fused contraction + attenuation + filters */
   DSPS_KERNEL_MAGS_FINALIZE = 2,
   DSPS_KERNEL_ZSORT = 3,

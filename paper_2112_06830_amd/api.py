@@ -209,8 +209,11 @@ def weights(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, with_mstar=F
     """dsps_weights: W [n_gal, n_met, n_age] float32 (and M_star float64)."""
     w = torch.empty((pop.n_gal, ssp.n_met, ssp.n_age), dtype=torch.float32, device=pop.device)
     ms = torch.empty(pop.n_gal, dtype=torch.float64, device=pop.device) if with_mstar else None
+    nbytes = workspace_size(N.OP_WEIGHTS, ssp, None, pop.n_gal, pop.n_t, "fp32")
+    buf, off = _workspace(nbytes, pop.device)
+    ws = ctypes.c_void_p(buf.data_ptr() + off) if buf is not None else None
     c, p = cosmo.c(), pop.c()
-    rc = _lib().dsps_weights(ssp.handle, ctypes.byref(c), ctypes.byref(p), _ptr(w), _ptr(ms), None, 0,
+    rc = _lib().dsps_weights(ssp.handle, ctypes.byref(c), ctypes.byref(p), _ptr(w), _ptr(ms), ws, nbytes,
                              _stream(stream))
     N.check(rc, "dsps_weights")
     return (w, ms) if with_mstar else w

@@ -385,7 +385,7 @@ constexpr int BATCH_VJP = 65536;
 
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
-  size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0;
+  size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0, tobs = 0;
   int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
@@ -398,9 +398,14 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   const int cpg = chunks_per_group(precision);
   L.n_groups = (L.n_chunks + cpg - 1) / cpg;
   const size_t elem = precision == DSPS_BF16 ? 2 : 4;
-  if (op == DSPS_OP_WEIGHTS) { L.total = 0; return L; }
+  if (op == DSPS_OP_WEIGHTS) {
+    L.tobs = take(sizeof(double) * (size_t)n_gal);
+    L.total = off;
+    return L;
+  }
   if (op == DSPS_OP_SED) {
     L.meta = take(sizeof(GalaxyMeta) * (size_t)n_gal);
+    L.tobs = take(sizeof(double) * (size_t)n_gal);
     L.w = take(elem * (size_t)L.batch * v.k_pad);
     L.total = off;
     return L;
@@ -410,6 +415,7 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   L.meta = take(sizeof(GalaxyMeta) * (size_t)n_gal);
   L.range = take(sizeof(GalaxyRange) * (size_t)n_gal);
   L.offset = take(sizeof(double) * (size_t)n_gal);
+  L.tobs = take(sizeof(double) * (size_t)n_gal);
   L.w = take(elem * (size_t)L.batch * v.k_pad);
   // float32 forward passes may carry the dust moments
   const int ncomp = mags_components(precision == DSPS_FP32);
@@ -535,13 +541,15 @@ int dsps_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *p
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(w, DSPS_ERR_ARG, "w is NULL");
   DSPS_TRY(check_device(ssp->device));
-  (void)workspace; (void)workspace_bytes;
+  const Layout L = make_layout(DSPS_OP_WEIGHTS, ssp->v, 0, pop->n_gal, DSPS_FP32);
+  DSPS_TRY(check_workspace(workspace, workspace_bytes, L.total));
   WeightsLaunch a = base_weights(ssp, cosmo, pop);
   a.perm = nullptr;
   a.s_begin = 0;
   a.s_count = pop->n_gal;
   a.w_user = w;
   a.mstar = mstar;
+  a.t_obs = (double *)((char *)workspace + L.tobs);
   return launch_weights(a, stream);
 }
 
@@ -569,6 +577,7 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, 
     a.w_pad = ws + L.w;
     a.w_pad_bf16 = precision == DSPS_BF16;
     a.meta = apply_dust ? meta : nullptr;
+    a.t_obs = (double *)(ws + L.tobs);
     DSPS_TRY(launch_weights(a, stream));
     SedLaunch s{};
     s.ssp = ssp->v;
@@ -625,6 +634,7 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   a.mag_offset = offset;
   a.obs_lo = filters->obs_lo;
   a.obs_hi = filters->obs_hi;
+  a.t_obs = (double *)(ws + L.tobs);
   DSPS_TRY(launch_weights(a, stream));
   MagsLaunch m{};
   m.ssp = ssp->v;

@@ -228,6 +228,9 @@ struct WeightsLaunch {
   GalaxyRange *range;        // [n_gal] by sorted position
   double *mag_offset;        // [n_gal] D_mod(z) - 2.5 log10(1+z), by sorted position
   double obs_lo, obs_hi;     // filter support union for the window
+  // [n_gal] cosmic time at z by sorted position, written by the per-galaxy
+  // scalar pass and read by the weights kernel (required when it runs)
+  double *t_obs;
 };
 int launch_weights(const WeightsLaunch &a, hipStream_t stream);
 

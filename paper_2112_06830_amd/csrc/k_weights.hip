@@ -48,77 +48,100 @@ int launch_sfh_table(const double *t_table, int n_t, const double *params, int n
   return hip_fail(hipGetLastError(), "k_sfh_table launch");
 }
 
-// Cosmic time t(z) in Gyr: closed form for LCDM, else Gauss-Legendre in
-// s = sqrt(a), where t = t_H int_0^{a_z} da / (a E(a)) becomes
-// t_H int_0^{sqrt(a_z)} 2 s^2 / sqrt(Om + OL s^(-6 w)) ds.  Wave-cooperative.
-__device__ double wave_age_at_z(double z, const CosmoArgs &c, const GaussLegendre &gl,
-                                int lane) {
+// Cosmic time t(z) in Gyr: closed form for LCDM, else Gauss-Legendre (4
+// panels of 16 nodes) in s = sqrt(a), where t = t_H int_0^{a_z} da / (a E(a))
+// becomes t_H int_0^{sqrt(a_z)} 2 s^2 / sqrt(Om + OL s^(-6 w)) ds.  One thread.
+__device__ double age_at_z(double z, const CosmoArgs &c, const GaussLegendre &gl) {
   if (c.lcdm) {
-    if (c.ol <= 0.0) return (2.0 / 3.0) * c.hubble_time_gyr * pow(1.0 + z, -1.5) / sqrt(c.om0);
-    return (2.0 / (3.0 * sqrt(c.ol))) * c.hubble_time_gyr *
-           asinh(sqrt(c.ol / c.om0) * pow(1.0 + z, -1.5));
+    const double zp1 = 1.0 + z;
+    const double a32 = 1.0 / (zp1 * sqrt(zp1));   // (1+z)^(-3/2)
+    if (c.ol <= 0.0) return (2.0 / 3.0) * c.hubble_time_gyr * a32 / sqrt(c.om0);
+    return (2.0 / (3.0 * sqrt(c.ol))) * c.hubble_time_gyr * asinh(sqrt(c.ol / c.om0) * a32);
   }
-  const double s_hi = sqrt(1.0 / (1.0 + z));
-  const int panel = lane / GL_N, node = lane % GL_N;  // 4 panels x 16 nodes
-  const double h = s_hi * 0.25;
-  const double s = h * (panel + 0.5) + 0.5 * h * gl.x[node];
-  const double f = 2.0 * s * s / sqrt(c.om0 + c.ol * pow(s, -6.0 * c.w0));
-  const double part = wave_sum(0.5 * h * gl.w[node] * f);
-  return c.hubble_time_gyr * part;
+  const double h = sqrt(1.0 / (1.0 + z)) * 0.25;
+  double sum = 0.0;
+  for (int k = 0; k < 4 * GL_N; ++k) {
+    const int panel = k / GL_N, node = k % GL_N;
+    const double s = h * (panel + 0.5) + 0.5 * h * gl.x[node];
+    sum += 0.5 * h * gl.w[node] * (2.0 * s * s / sqrt(c.om0 + c.ol * pow(s, -6.0 * c.w0)));
+  }
+  return c.hubble_time_gyr * sum;
 }
 
-// Distance modulus 5 log10(d_L / 10 pc), d_L = (1+z) (c/H0) int_0^z dz'/E(z').
-__device__ double wave_distance_modulus(double z, const CosmoArgs &c, const GaussLegendre &gl,
-                                        int lane) {
-  const int panel = lane / GL_N, node = lane % GL_N;
+// Distance modulus 5 log10(d_L / 10 pc), d_L = (1+z) (c/H0) int_0^z dz'/E(z'),
+// Gauss-Legendre with 4 panels of 16 nodes.  One thread.
+__device__ double distance_modulus(double z, const CosmoArgs &c, const GaussLegendre &gl) {
   const double h = z * 0.25;
-  const double x = h * (panel + 0.5) + 0.5 * h * gl.x[node];
-  const double zp1 = 1.0 + x;
-  const double e = sqrt(c.om0 * zp1 * zp1 * zp1 + c.ol * pow(zp1, 3.0 * (1.0 + c.w0)));
-  const double dc = c.hubble_dist_mpc * wave_sum(0.5 * h * gl.w[node] / e);
-  return 5.0 * log10((1.0 + z) * dc) + 25.0;
-}
-
-// Lockstep 64-ary searches over an ascending array x: the first index in
-// [lo1, hi1) with x[i] >= v1 (hi1 if none) and the first in [lo2, hi2) with
-// x[i] > v2.  Each round every lane probes one element of each range, both
-// ranges shrink 64-fold, and the two probe loads overlap.
-__device__ void wave_search_pair(const double *x, double v1, double v2, int lane, int &lo1,
-                                 int hi1, int &lo2, int hi2) {
-  while (lo1 < hi1 || lo2 < hi2) {
-    const int st1 = (hi1 - lo1 + 63) / 64, st2 = (hi2 - lo2 + 63) / 64;
-    const int p1 = lo1 + lane * st1, p2 = lo2 + lane * st2;
-    const bool in1 = lo1 < hi1 && p1 < hi1, in2 = lo2 < hi2 && p2 < hi2;
-    const double x1 = in1 ? x[p1] : 0.0;
-    const double x2 = in2 ? x[p2] : 0.0;
-    // probes at or past the range end count as satisfying the predicate
-    const unsigned long long m1 = __ballot(!in1 || x1 >= v1), m2 = __ballot(!in2 || x2 > v2);
-    if (lo1 < hi1) {
-      const int f = m1 ? __ffsll(m1) - 1 : 64;
-      if (f == 0) hi1 = lo1;
-      else { const int nl = lo1 + (f - 1) * st1 + 1; hi1 = min(lo1 + f * st1, hi1); lo1 = nl; }
-    }
-    if (lo2 < hi2) {
-      const int f = m2 ? __ffsll(m2) - 1 : 64;
-      if (f == 0) hi2 = lo2;
-      else { const int nl = lo2 + (f - 1) * st2 + 1; hi2 = min(lo2 + f * st2, hi2); lo2 = nl; }
-    }
+  double sum = 0.0;
+  for (int k = 0; k < 4 * GL_N; ++k) {
+    const int panel = k / GL_N, node = k % GL_N;
+    const double zp1 = 1.0 + (h * (panel + 0.5) + 0.5 * h * gl.x[node]);
+    const double de = c.lcdm ? c.ol : c.ol * pow(zp1, 3.0 * (1.0 + c.w0));   // dark energy term
+    sum += 0.5 * h * gl.w[node] / sqrt(c.om0 * zp1 * zp1 * zp1 + de);
   }
+  return 5.0 * log10((1.0 + z) * c.hubble_dist_mpc * sum) + 25.0;
 }
 
-// Entries of the block-shared coarse wavelength table (every stride-th rest
-// wavelength): the window search brackets in LDS, then finishes in one or two
-// rounds over the global grid.
-constexpr int COARSE_WAVE = 256;
+// First index i in [0, n) with x[i] >= v (STRICT: x[i] > v) over an ascending
+// array; n if none.
+template <bool STRICT>
+__device__ int first_index(const double *x, int n, double v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const bool ok = STRICT ? x[mid] > v : x[mid] >= v;
+    if (ok) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
 
-__host__ __device__ inline int coarse_stride(int n_wave) {
-  return (n_wave + COARSE_WAVE - 1) / COARSE_WAVE;
+// Per-galaxy scalars, one thread per galaxy of the sorted range: cosmic time
+// at z for the weights kernel, the GEMM's constants (1 + z and the dust
+// parameters), the magnitude offset and the rest-wavelength window.  The
+// window's non-zero weight blocks start as "all" and are narrowed by the
+// weights kernel when it runs.
+__global__ __launch_bounds__(256) void k_galaxy_scalars(WeightsLaunch a) {
+  const int local = blockIdx.x * blockDim.x + threadIdx.x;
+  if (local >= a.s_count) return;
+  const int s = a.s_begin + local;
+  const int g = a.perm ? a.perm[s] : s;
+  const double z = (double)a.z[g];
+  if (a.t_obs) a.t_obs[s] = age_at_z(z, a.cosmo, a.gl);
+  if (a.meta) {
+    GalaxyMeta m;
+    m.zp1 = (float)(1.0 + z);
+    // F = 10^(-0.4 A_V/4.05 k) = 2^(dust_a k)
+    m.dust_a = (float)(-0.4 * 3.32192809488736234787 * (double)a.av[g] / DUST_RV);
+    m.delta = a.delta[g];
+    m.bump = a.bump[g];
+    a.meta[s] = m;
+  }
+  // absolute magnitudes at z = 0 (Eq. restmag); distance terms beyond
+  if (a.mag_offset)
+    a.mag_offset[s] = z > 0.0 ? distance_modulus(z, a.cosmo, a.gl) - 2.5 * log10(1.0 + z) : 0.0;
+  if (a.range) {
+    // rest wavelengths whose redshifted value can meet a filter: [lo, hi)
+    // with wave[lo] >= obs_lo/(1+z) and wave[hi-1] <= obs_hi/(1+z), padded
+    // by two grid points on each side (points outside contribute exact
+    // zeros; the padding covers float32 rounding of (1+z) lambda)
+    const int n_wave = a.ssp.n_wave;
+    const int lo = first_index<false>(a.ssp.wave, n_wave, a.obs_lo / (1.0 + z));
+    const int hi = first_index<true>(a.ssp.wave, n_wave, a.obs_hi / (1.0 + z));
+    GalaxyRange r;
+    r.win_lo = max(lo - 2, 0);
+    r.win_hi = min(hi + 2, n_wave);
+#pragma unroll
+    for (int w = 0; w < KBLOCK_WORDS; ++w) r.kblk[w] = ~0u;
+    r.pad = 0;
+    a.range[s] = r;
+  }
 }
 
 // Consecutive time-grid segments each lane takes per scan round (a round
 // covers 64 * SFR_PER_LANE segments).
 constexpr int SFR_PER_LANE = 4;
 constexpr int SFR_ROUND = 64 * SFR_PER_LANE;
+constexpr int SFR_PRE = SFR_ROUND + 2;   // per-wave LDS: cumulative mass at a round's nodes
 
 // Orders one wave's LDS writes before its later LDS reads by other lanes.
 __device__ __forceinline__ void wave_sync() {
@@ -128,11 +151,9 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Block-shared LDS of the weights kernel, in doubles.
-__host__ __device__ inline size_t weights_lds_doubles(int n_t, int n_age, int n_met, int n_wave,
-                                                      int k_pad) {
-  const int n_coarse = (n_wave + coarse_stride(n_wave) - 1) / coarse_stride(n_wave);
-  return (size_t)n_t + (n_age + 1) + n_age + (n_met + 1) + n_coarse + (k_pad + 1) / 2 +
-         (size_t)WEIGHT_WAVES * 2 * SFR_ROUND;
+__host__ __device__ inline size_t weights_lds_doubles(int n_t, int n_age, int n_met, int k_pad) {
+  return (size_t)n_t + (n_age + 1) + n_age + (n_met + 1) + (k_pad + 1) / 2 +
+         (size_t)WEIGHT_WAVES * SFR_PRE;
 }
 
 // TABULATED: the SFR arrives as a table row per galaxy; otherwise it is
@@ -141,26 +162,21 @@ template <bool TABULATED>
 __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   const SspView P = a.ssp;
   const int n_t = a.n_t, n_age = P.n_age, n_met = P.n_met;
-  const int stride = coarse_stride(P.n_wave);
-  const int n_coarse = (P.n_wave + stride - 1) / stride;
-  // block-shared: time grid, SSP grid constants, coarse wavelengths, row scales
+  // block-shared: time grid, SSP grid constants, row scales
   extern __shared__ double lds[];
   double *tt = lds;                                   // [n_t]
   double *s_aedge = tt + n_t;                         // [n_age + 1]
   double *s_lgage = s_aedge + n_age + 1;              // [n_age]
   double *s_medge = s_lgage + n_age;                  // [n_met + 1]
-  double *s_cw = s_medge + n_met + 1;                 // [n_coarse]
-  float *s_ks = (float *)(s_cw + n_coarse);           // [k_pad]
+  float *s_ks = (float *)(s_medge + n_met + 1);       // [k_pad]
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  // per wave: cumulative mass before, and mass of, each segment of a round
-  double *s_pre = (double *)(s_ks + ((P.k_pad + 1) & ~1)) + wave * 2 * SFR_ROUND;
-  double *s_seg = s_pre + SFR_ROUND;
+  // per wave: cumulative mass at the SFR_ROUND + 1 nodes of a round
+  double *s_pre = (double *)(s_ks + ((P.k_pad + 1) & ~1)) + wave * SFR_PRE;
   for (int n = threadIdx.x; n < n_t; n += blockDim.x) tt[n] = a.t_table[n];
   for (int n = threadIdx.x; n <= n_age; n += blockDim.x) s_aedge[n] = P.age_edges[n];
   for (int n = threadIdx.x; n < n_age; n += blockDim.x) s_lgage[n] = P.lg_age[n];
   for (int n = threadIdx.x; n <= n_met; n += blockDim.x) s_medge[n] = P.met_edges[n];
-  for (int n = threadIdx.x; n < n_coarse; n += blockDim.x) s_cw[n] = P.wave[n * stride];
   if (a.w_pad_bf16)
     for (int n = threadIdx.x; n < P.k_pad; n += blockDim.x) s_ks[n] = P.kscale[n];
   __syncthreads();
@@ -171,9 +187,8 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   const int g = a.perm ? a.perm[s] : s;
 
   // every per-galaxy load is issued before the first use of any of them
-  const double z = (double)a.z[g];
+  const double t_obs = a.t_obs[s];
   const float lgmet_f = a.lgmet[g], sig_f = a.sigma_z[g];
-  const float av_f = a.av[g], delta_f = a.delta[g], bump_f = a.bump[g];
   const double *row = TABULATED ? a.sfr + (size_t)g * n_t : nullptr;
   // SFR at nodes base + SFR_PER_LANE lane + k of the round at base, and at
   // the first node of the next round (the first round is loaded up front)
@@ -187,7 +202,6 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
     if (SFR_ROUND < n_t) v_end = row[SFR_ROUND];
   }
 
-  const double t_obs = wave_age_at_z(z, a.cosmo, a.gl, lane);
 
   // ---- age-bin edges: lane owns edges e = lane and lane + 64.  The mass
   // formed by cosmic time t is 0 at or before t_table[0], the total after the
@@ -224,10 +238,10 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   // ---- cumulative trapezoid of the SFR row, one round of SFR_ROUND segments
   // at a time: segment m joins nodes m and m + 1; lane l holds segments
   // base + 4 l .. base + 4 l + 3, sums them locally and joins the wave's
-  // exclusive scan of the lane totals.  The mass before each segment and the
-  // segment's own mass go to the wave's LDS buffer, where every age-bin edge
-  // whose interval lies in the round reads its cumulative mass.  Nothing is
-  // kept per galaxy beyond the round.
+  // exclusive scan of the lane totals.  The cumulative mass at the round's
+  // nodes goes to the wave's LDS buffer, where every age-bin edge whose
+  // interval lies in the round interpolates it linearly.  A tabulated row's
+  // next round is loaded while the current one is summed.
   double pa = 0, ptau = 1, palpha = 0, pq = 0, ptq = 0;
   if (!TABULATED) {
     pa = a.sfh_params[g]; ptau = a.sfh_params[a.n_gal + g];
@@ -239,29 +253,35 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   double em[2] = {0.0, 0.0};
   for (int base = 0; base < n_seg; base += SFR_ROUND) {
     const int n0 = base + SFR_PER_LANE * lane;
-    if (!TABULATED || base > 0) {
+    double vn[SFR_PER_LANE], vn_end = 0.0;   // next round of a tabulated row
+    if (TABULATED) {
+      const int nb = base + SFR_ROUND;
+#pragma unroll
+      for (int k = 0; k < SFR_PER_LANE; ++k) {
+        const int n = nb + SFR_PER_LANE * lane + k;
+        vn[k] = n < n_t ? row[n] : 0.0;
+      }
+      if (nb + SFR_ROUND < n_t) vn_end = row[nb + SFR_ROUND];
+    } else {
 #pragma unroll
       for (int k = 0; k < SFR_PER_LANE; ++k) {
         const int n = n0 + k;
-        v[k] = 0.0;
-        if (n < n_t) v[k] = TABULATED ? row[n] : sfr_param(tt[n], pa, ptau, palpha, pq, ptq);
+        v[k] = n < n_t ? sfr_param(tt[n], pa, ptau, palpha, pq, ptq) : 0.0;
       }
       const int n_end = base + SFR_ROUND;
-      v_end = 0.0;
-      if (n_end < n_t) v_end = TABULATED ? row[n_end] : sfr_param(tt[n_end], pa, ptau, palpha, pq, ptq);
+      v_end = n_end < n_t ? sfr_param(tt[n_end], pa, ptau, palpha, pq, ptq) : 0.0;
     }
     double after = __shfl_down(v[0], 1, 64);          // SFR at node n0 + 4
     if (lane == 63) after = v_end;
-    double seg[SFR_PER_LANE], part[SFR_PER_LANE];    // segment masses, local inclusive sums
+    double part[SFR_PER_LANE];                        // local inclusive sums
 #pragma unroll
     for (int k = 0; k < SFR_PER_LANE; ++k) {
       const int m = n0 + k;
       const double right = k + 1 < SFR_PER_LANE ? v[k + 1 < SFR_PER_LANE ? k + 1 : k] : after;
-      seg[k] = m < n_seg ? 0.5 * (v[k] + right) * (tt[m + 1] - tt[m]) * YEARS_PER_GYR : 0.0;
-      part[k] = k == 0 ? seg[0] : part[k > 0 ? k - 1 : 0] + seg[k];
+      const double seg = m < n_seg ? 0.5 * (v[k] + right) * (tt[m + 1] - tt[m]) * YEARS_PER_GYR : 0.0;
+      part[k] = k == 0 ? seg : part[k > 0 ? k - 1 : 0] + seg;
     }
-    const double total = part[SFR_PER_LANE - 1];
-    double incl = total;
+    double incl = part[SFR_PER_LANE - 1];
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const double up = __shfl_up(incl, off, 64);
@@ -270,19 +290,26 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
     double excl = __shfl_up(incl, 1, 64);
     if (lane == 0) excl = 0.0;
     const double before = carry + excl;
+    s_pre[SFR_PER_LANE * lane] = before;
 #pragma unroll
-    for (int k = 0; k < SFR_PER_LANE; ++k) {
-      s_pre[SFR_PER_LANE * lane + k] = k == 0 ? before : before + part[k > 0 ? k - 1 : 0];
-      s_seg[SFR_PER_LANE * lane + k] = seg[k];
-    }
+    for (int k = 1; k < SFR_PER_LANE; ++k) s_pre[SFR_PER_LANE * lane + k] = before + part[k - 1];
+    if (lane == 63) s_pre[SFR_ROUND] = before + part[SFR_PER_LANE - 1];
     wave_sync();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int src = lo[q] - base;
-      if (kind[q] == 1 && src >= 0 && src < SFR_ROUND) em[q] = s_pre[src] + fe[q] * s_seg[src];
+      if (kind[q] == 1 && src >= 0 && src < SFR_ROUND) {
+        const double m0 = s_pre[src];
+        em[q] = m0 + fe[q] * (s_pre[src + 1] - m0);
+      }
     }
     carry += __shfl(incl, 63, 64);
     wave_sync();                                      // buffer reused by the next round
+    if (TABULATED) {
+#pragma unroll
+      for (int k = 0; k < SFR_PER_LANE; ++k) v[k] = vn[k];
+      v_end = vn_end;
+    }
   }
 #pragma unroll
   for (int q = 0; q < 2; ++q)
@@ -350,60 +377,33 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
     }
   }
 
-  const double dmod = a.mag_offset ? wave_distance_modulus(z, a.cosmo, a.gl, lane) : 0.0;
-  // rest wavelengths whose redshifted value can meet a filter: [lo, hi) with
-  // wave[lo] >= obs_lo/(1+z) and wave[hi-1] <= obs_hi/(1+z)
-  int win_lo = 0, win_hi = 0;
-  if (a.range) {
-    const double v1 = a.obs_lo / (1.0 + z), v2 = a.obs_hi / (1.0 + z);
-    // coarse entries c: wave[c * stride]; the first satisfying one brackets
-    // the answer to ((c - 1) stride, c stride] of the full grid
-    int c1 = 0, c2 = 0;
-    wave_search_pair(s_cw, v1, v2, lane, c1, n_coarse, c2, n_coarse);
-    win_lo = c1 == 0 ? 0 : (c1 - 1) * stride + 1;
-    win_hi = c2 == 0 ? 0 : (c2 - 1) * stride + 1;
-    const int h1 = c1 == 0 ? 0 : min(c1 * stride, P.n_wave);
-    const int h2 = c2 == 0 ? 0 : min(c2 * stride, P.n_wave);
-    wave_search_pair(P.wave, v1, v2, lane, win_lo, h1, win_hi, h2);
-  }
-  if (lane == 0) {
-    if (a.meta) {
-      GalaxyMeta m;
-      m.zp1 = (float)(1.0 + z);
-      // F = 10^(-0.4 A_V/4.05 k) = 2^(dust_a k)
-      m.dust_a = (float)(-0.4 * 3.32192809488736234787 * (double)av_f / DUST_RV);
-      m.delta = delta_f;
-      m.bump = bump_f;
-      a.meta[s] = m;
-    }
-    // absolute magnitudes at z = 0 (Eq. restmag); distance terms beyond
-    if (a.mag_offset) a.mag_offset[s] = z > 0.0 ? dmod - 2.5 * log10(1.0 + z) : 0.0;
-    if (a.range) {
-      // padded by two grid points on each side (points outside contribute
-      // exact zeros; the padding covers float32 rounding of (1+z) lambda)
-      GalaxyRange r;
-      r.win_lo = max(win_lo - 2, 0);
-      r.win_hi = min(win_hi + 2, P.n_wave);
+  if (a.range && lane == 0) {
 #pragma unroll
-      for (int w = 0; w < KBLOCK_WORDS; ++w) r.kblk[w] = kblk[w];
-      r.pad = 0;
-      a.range[s] = r;
-    }
+    for (int w = 0; w < KBLOCK_WORDS; ++w) a.range[s].kblk[w] = kblk[w];
   }
 }
 
 int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
+  ProfScope prof(DSPS_KERNEL_WEIGHTS, stream);
+  if (a.t_obs || a.meta || a.range || a.mag_offset) {
+    hipLaunchKernelGGL(k_galaxy_scalars, dim3((a.s_count + 255) / 256), dim3(256), 0, stream, a);
+    const int rc = hip_fail(hipGetLastError(), "k_galaxy_scalars launch");
+    if (rc) return rc;
+  }
+  // the weights kernel runs when weight rows or masses are asked for (the
+  // windows' block masks then narrow from "all" to the exact union)
+  if (!a.w_pad && !a.w_user && !a.mstar) return DSPS_OK;
+  if (!a.t_obs) return DSPS_ERR_ARG;
   const int blocks = (a.s_count + WEIGHT_WAVES - 1) / WEIGHT_WAVES;
   const size_t lds = sizeof(double) * weights_lds_doubles(a.n_t, a.ssp.n_age, a.ssp.n_met,
-                                                          a.ssp.n_wave, a.ssp.k_pad);
+                                                          a.ssp.k_pad);
   const void *fn = a.sfr ? (const void *)k_weights<true> : (const void *)k_weights<false>;
   if (lds > 65536) {
     const int rc = hip_fail(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                             "k_weights LDS attribute");
     if (rc) return rc;
   }
-  ProfScope prof(DSPS_KERNEL_WEIGHTS, stream);
   if (a.sfr)
     hipLaunchKernelGGL(k_weights<true>, dim3(blocks), dim3(64 * WEIGHT_WAVES), lds, stream, a);
   else

@@ -203,10 +203,10 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   }
 
 
-  // ---- age-bin edges: lane owns edges e = lane and lane + 64.  The mass
+  // ---- age-bin edges: lane owns edges e = 2 lane and 2 lane + 1.  The mass
   // formed by cosmic time t is 0 at or before t_table[0], the total after the
-  // last node, and otherwise the cumulative trapezoid at node lo plus the
-  // fraction f of segment lo, where t_table[lo] <= t < t_table[lo + 1].
+  // last node, and otherwise the cumulative trapezoid interpolated linearly
+  // between nodes lo and lo + 1, where t_table[lo] <= t < t_table[lo + 1].
   int kind[2], lo[2];            // kind: 0 none formed, 1 inside the grid, 2 all formed
   double fe[2];
   {
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
     int hi[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int e = lane + 64 * q;
+      const int e = 2 * lane + q;
       te[q] = e <= n_age ? t_obs - s_aedge[e] : -1.0 / 0.0;
       kind[q] = !(te[q] > tt[0]) ? 0 : (te[q] >= tt[n_t - 1] ? 2 : 1);
       lo[q] = 0;
@@ -315,62 +315,63 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   for (int q = 0; q < 2; ++q)
     if (kind[q] == 2) em[q] = carry;
 
-  // ---- bin masses m_i = M(t_obs - edge_i) - M(t_obs - edge_{i+1}) in float64
-  double em_up0 = __shfl_down(em[0], 1, 64);
-  const double em64 = __shfl(em[1], 0, 64);
-  if (lane == 63) em_up0 = em64;
-  const double em_up1 = __shfl_down(em[1], 1, 64);
-  const double mage[2] = {lane < n_age ? em[0] - em_up0 : 0.0,
-                          lane + 64 < n_age ? em[1] - em_up1 : 0.0};
+  // ---- bin masses m_i = M(t_obs - edge_i) - M(t_obs - edge_{i+1}) in float64;
+  // lane l holds ages 2l and 2l + 1
+  const double em_next = __shfl_down(em[0], 1, 64);   // edge 2l + 2
+  const int i0 = 2 * lane;
+  const bool real0 = i0 < n_age, real1 = i0 + 1 < n_age;
+  const double mage0 = real0 ? em[0] - em[1] : 0.0;
+  const double mage1 = real1 ? em[1] - em_next : 0.0;
   if (a.mstar && lane == 0) a.mstar[g] = em[0];
 
-  // ---- metallicity weights and W = m_age * P, lanes over ages.
+  // ---- metallicity weights and W = m_age * P: lane l writes ages 2l, 2l + 1
+  // of every metallicity row as one 4-byte (bf16) or 8-byte (float32) store
   const double lgmet = (double)lgmet_f;
   const double inv_sig = 1.0 / (double)sig_f;
-  unsigned nzrows[2] = {0u, 0u};   // per age slot: metallicity rows with a non-zero weight
   const int k_pad = P.k_pad;
   float *wp32 = (a.w_pad && !a.w_pad_bf16) ? (float *)a.w_pad + (size_t)local * k_pad : nullptr;
   uint16_t *wp16 = (a.w_pad && a.w_pad_bf16) ? (uint16_t *)a.w_pad + (size_t)local * k_pad : nullptr;
   float *wu = a.w_user ? a.w_user + (size_t)g * n_met * n_age : nullptr;
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int i = lane + 64 * q;
-    if (i >= AGE_PAD) continue;
-    const bool real = i < n_age;
-    const double mu = real ? lgmet + a.slope * (s_lgage[i] - a.pivot) : 0.0;
-    const double m_i = mage[q];
-    double c_prev = 0.0;  // CDF at the lower edge of metallicity bin 0 (-inf)
-    for (int j = 0; j < n_met; ++j) {
-      double c_next;
-      if (j == n_met - 1) c_next = 1.0;  // upper edge of the last bin is +inf
-      else c_next = triweight_cdf((s_medge[j + 1] - mu) * inv_sig);
-      const double wv = real ? m_i * (c_next - c_prev) : 0.0;
-      c_prev = c_next;
-      bool nz;
-      if (wp16) {
-        const uint16_t qv = f32_to_bf16_rne((float)(wv * (double)s_ks[j * AGE_PAD + i]));
-        wp16[j * AGE_PAD + i] = qv;
-        nz = (qv & 0x7FFFu) != 0;
-      } else {
-        const float wf = (float)wv;
-        if (wp32) wp32[j * AGE_PAD + i] = wf;
-        nz = wf != 0.0f;
-      }
-      if (wu && real) wu[j * n_age + i] = (float)wv;
-      if (nz) nzrows[q] |= 1u << j;
-    }
-  }
-  // non-zero (row, 16-age block) mask: ages 0..63 live in slot 0 of lanes
-  // 0..63, ages 64..95 in slot 1 of lanes 0..31
+  const bool active = i0 < AGE_PAD;
+  const double mu0 = real0 ? lgmet + a.slope * (s_lgage[i0] - a.pivot) : 0.0;
+  const double mu1 = real1 ? lgmet + a.slope * (s_lgage[i0 + 1] - a.pivot) : 0.0;
+  // non-zero (row, 16-age block) mask: block b holds the ages of lanes
+  // 8b .. 8b + 7
   unsigned kblk[KBLOCK_WORDS] = {0u, 0u, 0u};
+  double c_prev0 = 0.0, c_prev1 = 0.0;  // CDF at the lower edge of metallicity bin 0 (-inf)
   for (int j = 0; j < n_met; ++j) {
-    const unsigned long long b0 = __ballot((nzrows[0] >> j) & 1u);
-    const unsigned long long b1 = __ballot((nzrows[1] >> j) & 1u);
+    double c_next0 = 1.0, c_next1 = 1.0;  // upper edge of the last bin is +inf
+    if (j < n_met - 1) {
+      const double edge = s_medge[j + 1];
+      c_next0 = triweight_cdf((edge - mu0) * inv_sig);
+      c_next1 = triweight_cdf((edge - mu1) * inv_sig);
+    }
+    const double wv0 = real0 ? mage0 * (c_next0 - c_prev0) : 0.0;
+    const double wv1 = real1 ? mage1 * (c_next1 - c_prev1) : 0.0;
+    c_prev0 = c_next0;
+    c_prev1 = c_next1;
+    bool nz = false;
+    if (active) {
+      if (wp16) {
+        const float2 ks = *reinterpret_cast<const float2 *>(&s_ks[j * AGE_PAD + i0]);
+        const uint32_t q0 = f32_to_bf16_rne((float)(wv0 * (double)ks.x));
+        const uint32_t q1 = f32_to_bf16_rne((float)(wv1 * (double)ks.y));
+        *reinterpret_cast<uint32_t *>(&wp16[j * AGE_PAD + i0]) = q0 | (q1 << 16);
+        nz = ((q0 | q1) & 0x7FFFu) != 0;
+      } else {
+        const float w0f = (float)wv0, w1f = (float)wv1;
+        if (wp32) *reinterpret_cast<float2 *>(&wp32[j * AGE_PAD + i0]) = make_float2(w0f, w1f);
+        nz = w0f != 0.0f || w1f != 0.0f;
+      }
+      if (wu) {
+        if (real0) wu[j * n_age + i0] = (float)wv0;
+        if (real1) wu[j * n_age + i0 + 1] = (float)wv1;
+      }
+    }
+    const unsigned long long b = __ballot(nz);
 #pragma unroll
     for (int blk = 0; blk < KBLOCKS_PER_ROW; ++blk) {
-      const unsigned long long src = blk < 4 ? b0 : b1;
-      const int sh = (blk & 3) * KBLOCK_AGES;
-      if ((src >> sh) & 0xFFFFull) {
+      if ((b >> (8 * blk)) & 0xFFull) {
         const int bit = j * KBLOCKS_PER_ROW + blk;
         kblk[bit >> 5] |= 1u << (bit & 31);
       }

@@ -143,6 +143,40 @@ constexpr int SFR_PER_LANE = 4;
 constexpr int SFR_ROUND = 64 * SFR_PER_LANE;
 constexpr int SFR_PRE = SFR_ROUND + 2;   // per-wave LDS: cumulative mass at a round's nodes
 
+// A double moved across lanes by one DPP control (GFX9 encodings), both
+// halves alike; lanes whose row is masked off or whose source lies outside
+// the row or wave receive +0.  Every lane of the wave must be active.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int DPP_ROW_SHR = 0x110;     // + shift 1..15, within rows of 16 lanes
+constexpr int DPP_ROW_BCAST15 = 0x142; // lane 15 of each row to the next row
+constexpr int DPP_ROW_BCAST31 = 0x143; // lane 31 to rows 2 and 3
+constexpr int DPP_WAVE_SHL1 = 0x130;   // lane i takes lane i + 1
+constexpr int DPP_WAVE_SHR1 = 0x138;   // lane i takes lane i - 1
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ double wave_inclusive_sum(double x) {
+  x += dpp_f64<DPP_ROW_SHR + 1>(x);
+  x += dpp_f64<DPP_ROW_SHR + 2>(x);
+  x += dpp_f64<DPP_ROW_SHR + 4>(x);
+  x += dpp_f64<DPP_ROW_SHR + 8>(x);
+  x += dpp_f64<DPP_ROW_BCAST15, 0xa>(x);
+  x += dpp_f64<DPP_ROW_BCAST31, 0xc>(x);
+  return x;
+}
+
+__device__ __forceinline__ double lane63_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Orders one wave's LDS writes before its later LDS reads by other lanes.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -190,16 +224,17 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   const double t_obs = a.t_obs[s];
   const float lgmet_f = a.lgmet[g], sig_f = a.sigma_z[g];
   const double *row = TABULATED ? a.sfr + (size_t)g * n_t : nullptr;
-  // SFR at nodes base + SFR_PER_LANE lane + k of the round at base, and at
-  // the first node of the next round (the first round is loaded up front)
-  double v[SFR_PER_LANE], v_end = 0.0;
+  // SFR at nodes base + SFR_PER_LANE lane + k of the next round to be summed
+  // and at the first node of the round after it (a tabulated row's first
+  // round is loaded up front).  Nodes past the row's end only ever enter
+  // segments that are masked out, so their loads read the last node instead:
+  // every path issues the same loads, which lets the next round's requests
+  // stay in flight while the current round is summed.
+  double vn[SFR_PER_LANE], vn_end = 0.0;
   if (TABULATED) {
 #pragma unroll
-    for (int k = 0; k < SFR_PER_LANE; ++k) {
-      const int n = SFR_PER_LANE * lane + k;
-      v[k] = n < n_t ? row[n] : 0.0;
-    }
-    if (SFR_ROUND < n_t) v_end = row[SFR_ROUND];
+    for (int k = 0; k < SFR_PER_LANE; ++k) vn[k] = row[min(SFR_PER_LANE * lane + k, n_t - 1)];
+    vn_end = row[min(SFR_ROUND, n_t - 1)];
   }
 
 
@@ -253,15 +288,18 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   double em[2] = {0.0, 0.0};
   for (int base = 0; base < n_seg; base += SFR_ROUND) {
     const int n0 = base + SFR_PER_LANE * lane;
-    double vn[SFR_PER_LANE], vn_end = 0.0;   // next round of a tabulated row
+    // the current round leaves the prefetch registers before the next round
+    // is requested into them, so its loads stay in flight while this one is
+    // summed
+    double v[SFR_PER_LANE], v_end;
     if (TABULATED) {
+#pragma unroll
+      for (int k = 0; k < SFR_PER_LANE; ++k) v[k] = vn[k];
+      v_end = vn_end;
       const int nb = base + SFR_ROUND;
 #pragma unroll
-      for (int k = 0; k < SFR_PER_LANE; ++k) {
-        const int n = nb + SFR_PER_LANE * lane + k;
-        vn[k] = n < n_t ? row[n] : 0.0;
-      }
-      if (nb + SFR_ROUND < n_t) vn_end = row[nb + SFR_ROUND];
+      for (int k = 0; k < SFR_PER_LANE; ++k) vn[k] = row[min(nb + SFR_PER_LANE * lane + k, n_t - 1)];
+      vn_end = row[min(nb + SFR_ROUND, n_t - 1)];
     } else {
 #pragma unroll
       for (int k = 0; k < SFR_PER_LANE; ++k) {
@@ -271,7 +309,7 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
       const int n_end = base + SFR_ROUND;
       v_end = n_end < n_t ? sfr_param(tt[n_end], pa, ptau, palpha, pq, ptq) : 0.0;
     }
-    double after = __shfl_down(v[0], 1, 64);          // SFR at node n0 + 4
+    double after = dpp_f64<DPP_WAVE_SHL1>(v[0]);      // SFR at node n0 + SFR_PER_LANE
     if (lane == 63) after = v_end;
     double part[SFR_PER_LANE];                        // local inclusive sums
 #pragma unroll
@@ -281,15 +319,8 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
       const double seg = m < n_seg ? 0.5 * (v[k] + right) * (tt[m + 1] - tt[m]) * YEARS_PER_GYR : 0.0;
       part[k] = k == 0 ? seg : part[k > 0 ? k - 1 : 0] + seg;
     }
-    double incl = part[SFR_PER_LANE - 1];
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const double up = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += up;
-    }
-    double excl = __shfl_up(incl, 1, 64);
-    if (lane == 0) excl = 0.0;
-    const double before = carry + excl;
+    const double incl = wave_inclusive_sum(part[SFR_PER_LANE - 1]);
+    const double before = carry + dpp_f64<DPP_WAVE_SHR1>(incl);   // lane 0 takes +0
     s_pre[SFR_PER_LANE * lane] = before;
 #pragma unroll
     for (int k = 1; k < SFR_PER_LANE; ++k) s_pre[SFR_PER_LANE * lane + k] = before + part[k - 1];
@@ -303,13 +334,8 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
         em[q] = m0 + fe[q] * (s_pre[src + 1] - m0);
       }
     }
-    carry += __shfl(incl, 63, 64);
+    carry += lane63_f64(incl);
     wave_sync();                                      // buffer reused by the next round
-    if (TABULATED) {
-#pragma unroll
-      for (int k = 0; k < SFR_PER_LANE; ++k) v[k] = vn[k];
-      v_end = vn_end;
-    }
   }
 #pragma unroll
   for (int q = 0; q < 2; ++q)
@@ -317,7 +343,7 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
 
   // ---- bin masses m_i = M(t_obs - edge_i) - M(t_obs - edge_{i+1}) in float64;
   // lane l holds ages 2l and 2l + 1
-  const double em_next = __shfl_down(em[0], 1, 64);   // edge 2l + 2
+  const double em_next = dpp_f64<DPP_WAVE_SHL1>(em[0]);   // edge 2l + 2
   const int i0 = 2 * lane;
   const bool real0 = i0 < n_age, real1 = i0 + 1 < n_age;
   const double mage0 = real0 ? em[0] - em[1] : 0.0;

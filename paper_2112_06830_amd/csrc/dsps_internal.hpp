@@ -106,11 +106,12 @@ struct GalaxyMeta {
 constexpr int KBLOCK_AGES = 16;
 constexpr int KBLOCKS_PER_ROW = AGE_PAD / KBLOCK_AGES;                  // 6
 constexpr int KBLOCK_WORDS = (DSPS_MAX_MET * KBLOCKS_PER_ROW + 31) / 32;  // 3
+static_assert(DSPS_MAX_MET <= 16 && KBLOCKS_PER_ROW == 2 * KBLOCK_WORDS, "block-major mask layout");
 
 struct GalaxyRange {
   int win_lo, win_hi;            // rest-wavelength index window [lo, hi) that any filter sees
-  // bit 6 j + a set when metallicity row j has a non-zero weight at some age
-  // in [16 a, 16 a + 16)
+  // bit 16 a + j (word a / 2, bit 16 (a % 2) + j) set when metallicity row j
+  // has a non-zero weight at some age in [16 a, 16 a + 16)
   unsigned kblk[KBLOCK_WORDS];
   int pad;
 };

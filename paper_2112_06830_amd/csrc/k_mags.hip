@@ -311,8 +311,8 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
     for (int st = 0; st < AGE_PAD / C::KT; ++st) {
       bool any = false;
       for (int u = 0; u < BPS; ++u) {
-        const int bit = j * KBLOCKS_PER_ROW + st * BPS + u;
-        any |= (s_kblk[bit >> 5] >> (bit & 31)) & 1u;
+        const int blk = st * BPS + u;
+        any |= (s_kblk[blk >> 1] >> (16 * (blk & 1) + j)) & 1u;
       }
       if (any) pl->koff[n++] = j * AGE_PAD + st * C::KT;
     }

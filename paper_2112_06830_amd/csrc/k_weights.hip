@@ -177,6 +177,64 @@ __device__ __forceinline__ double lane63_f64(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned x) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, true);
+}
+
+// One lane's part of the metallicity weights: ages i0 and i0 + 1 (i0 even),
+// their age-bin masses and MDF centres.
+struct MdfLane {
+  const double *medge;   // [n_met + 1] metallicity bin edges (LDS)
+  const float *ks;       // [k_pad] bf16 row scales (LDS)
+  int n_met, n_age, i0;
+  double mu0, mu1, inv_sig, mage0, mage1;
+  bool real0, real1;
+};
+enum { MDF_PAD_BF16, MDF_PAD_F32, MDF_USER };
+
+// W[j][i] = m_i (CDF(e_{j+1}) - CDF(e_j)) for the lane's two ages over every
+// metallicity row j, written in the layout of MODE; returns the rows in which
+// either weight is non-zero (as stored).
+template <int MODE, typename T>
+__device__ __forceinline__ unsigned mdf_rows(const MdfLane &L, T *out) {
+  const bool active = L.i0 < AGE_PAD;
+  unsigned nzr = 0u;
+  double c_prev0 = 0.0, c_prev1 = 0.0;  // CDF at the lower edge of metallicity bin 0 (-inf)
+  for (int j = 0; j < L.n_met; ++j) {
+    double c_next0 = 1.0, c_next1 = 1.0;  // upper edge of the last bin is +inf
+    if (j < L.n_met - 1) {
+      const double edge = L.medge[j + 1];
+      c_next0 = triweight_cdf((edge - L.mu0) * L.inv_sig);
+      c_next1 = triweight_cdf((edge - L.mu1) * L.inv_sig);
+    }
+    const double wv0 = L.real0 ? L.mage0 * (c_next0 - c_prev0) : 0.0;
+    const double wv1 = L.real1 ? L.mage1 * (c_next1 - c_prev1) : 0.0;
+    c_prev0 = c_next0;
+    c_prev1 = c_next1;
+    bool nz;
+    if (MODE == MDF_PAD_BF16) {
+      const float2 ks = active ? *reinterpret_cast<const float2 *>(&L.ks[j * AGE_PAD + L.i0])
+                               : make_float2(0.0f, 0.0f);
+      const uint32_t q0 = f32_to_bf16_rne((float)(wv0 * (double)ks.x));
+      const uint32_t q1 = f32_to_bf16_rne((float)(wv1 * (double)ks.y));
+      if (active) *reinterpret_cast<uint32_t *>((uint16_t *)out + j * AGE_PAD + L.i0) = q0 | (q1 << 16);
+      nz = ((q0 | q1) & 0x7FFFu) != 0;
+    } else {
+      const float w0f = (float)wv0, w1f = (float)wv1;
+      if (MODE == MDF_PAD_F32) {
+        if (active) *reinterpret_cast<float2 *>((float *)out + j * AGE_PAD + L.i0) = make_float2(w0f, w1f);
+      } else {
+        if (L.real0) ((float *)out)[j * L.n_age + L.i0] = w0f;
+        if (L.real1) ((float *)out)[j * L.n_age + L.i0 + 1] = w1f;
+      }
+      nz = w0f != 0.0f || w1f != 0.0f;
+    }
+    nzr |= (nz ? 1u : 0u) << j;
+  }
+  return nzr;
+}
+
 // Orders one wave's LDS writes before its later LDS reads by other lanes.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -354,55 +412,26 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   // of every metallicity row as one 4-byte (bf16) or 8-byte (float32) store
   const double lgmet = (double)lgmet_f;
   const double inv_sig = 1.0 / (double)sig_f;
-  const int k_pad = P.k_pad;
-  float *wp32 = (a.w_pad && !a.w_pad_bf16) ? (float *)a.w_pad + (size_t)local * k_pad : nullptr;
-  uint16_t *wp16 = (a.w_pad && a.w_pad_bf16) ? (uint16_t *)a.w_pad + (size_t)local * k_pad : nullptr;
-  float *wu = a.w_user ? a.w_user + (size_t)g * n_met * n_age : nullptr;
-  const bool active = i0 < AGE_PAD;
   const double mu0 = real0 ? lgmet + a.slope * (s_lgage[i0] - a.pivot) : 0.0;
   const double mu1 = real1 ? lgmet + a.slope * (s_lgage[i0 + 1] - a.pivot) : 0.0;
-  // non-zero (row, 16-age block) mask: block b holds the ages of lanes
-  // 8b .. 8b + 7
-  unsigned kblk[KBLOCK_WORDS] = {0u, 0u, 0u};
-  double c_prev0 = 0.0, c_prev1 = 0.0;  // CDF at the lower edge of metallicity bin 0 (-inf)
-  for (int j = 0; j < n_met; ++j) {
-    double c_next0 = 1.0, c_next1 = 1.0;  // upper edge of the last bin is +inf
-    if (j < n_met - 1) {
-      const double edge = s_medge[j + 1];
-      c_next0 = triweight_cdf((edge - mu0) * inv_sig);
-      c_next1 = triweight_cdf((edge - mu1) * inv_sig);
-    }
-    const double wv0 = real0 ? mage0 * (c_next0 - c_prev0) : 0.0;
-    const double wv1 = real1 ? mage1 * (c_next1 - c_prev1) : 0.0;
-    c_prev0 = c_next0;
-    c_prev1 = c_next1;
-    bool nz = false;
-    if (active) {
-      if (wp16) {
-        const float2 ks = *reinterpret_cast<const float2 *>(&s_ks[j * AGE_PAD + i0]);
-        const uint32_t q0 = f32_to_bf16_rne((float)(wv0 * (double)ks.x));
-        const uint32_t q1 = f32_to_bf16_rne((float)(wv1 * (double)ks.y));
-        *reinterpret_cast<uint32_t *>(&wp16[j * AGE_PAD + i0]) = q0 | (q1 << 16);
-        nz = ((q0 | q1) & 0x7FFFu) != 0;
-      } else {
-        const float w0f = (float)wv0, w1f = (float)wv1;
-        if (wp32) *reinterpret_cast<float2 *>(&wp32[j * AGE_PAD + i0]) = make_float2(w0f, w1f);
-        nz = w0f != 0.0f || w1f != 0.0f;
-      }
-      if (wu) {
-        if (real0) wu[j * n_age + i0] = (float)wv0;
-        if (real1) wu[j * n_age + i0 + 1] = (float)wv1;
-      }
-    }
-    const unsigned long long b = __ballot(nz);
+  const MdfLane L{s_medge, s_ks, n_met, n_age, i0, mu0, mu1, inv_sig, mage0, mage1, real0, real1};
+  unsigned nzr;   // metallicity rows in which either of the lane's ages has a non-zero weight
+  if (a.w_pad && a.w_pad_bf16)
+    nzr = mdf_rows<MDF_PAD_BF16>(L, (uint16_t *)a.w_pad + (size_t)local * P.k_pad);
+  else if (a.w_pad)
+    nzr = mdf_rows<MDF_PAD_F32>(L, (float *)a.w_pad + (size_t)local * P.k_pad);
+  else
+    nzr = mdf_rows<MDF_USER>(L, a.w_user + (size_t)g * n_met * n_age);
+  // non-zero (16-age block, row) mask: block b holds the ages of lanes
+  // 8b .. 8b + 7; after three shifted ORs lane 8b + 7 holds their union
+  nzr |= dpp_u32<DPP_ROW_SHR + 1>(nzr);
+  nzr |= dpp_u32<DPP_ROW_SHR + 2>(nzr);
+  nzr |= dpp_u32<DPP_ROW_SHR + 4>(nzr);
+  unsigned kblk[KBLOCK_WORDS];
 #pragma unroll
-    for (int blk = 0; blk < KBLOCKS_PER_ROW; ++blk) {
-      if ((b >> (8 * blk)) & 0xFFull) {
-        const int bit = j * KBLOCKS_PER_ROW + blk;
-        kblk[bit >> 5] |= 1u << (bit & 31);
-      }
-    }
-  }
+  for (int w = 0; w < KBLOCK_WORDS; ++w)
+    kblk[w] = (unsigned)__builtin_amdgcn_readlane((int)nzr, 16 * w + 7) |
+              ((unsigned)__builtin_amdgcn_readlane((int)nzr, 16 * w + 15) << 16);
 
   if (a.range && lane == 0) {
 #pragma unroll
@@ -418,10 +447,11 @@ int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
     const int rc = hip_fail(hipGetLastError(), "k_galaxy_scalars launch");
     if (rc) return rc;
   }
-  // the weights kernel runs when weight rows or masses are asked for (the
-  // windows' block masks then narrow from "all" to the exact union)
-  if (!a.w_pad && !a.w_user && !a.mstar) return DSPS_OK;
-  if (!a.t_obs) return DSPS_ERR_ARG;
+  // the weights kernel runs when weight rows are asked for, padded or in the
+  // natural layout (the windows' block masks then narrow from "all" to the
+  // exact union)
+  if (!a.w_pad && !a.w_user) return a.mstar ? DSPS_ERR_ARG : DSPS_OK;
+  if (!a.t_obs || (a.w_pad && a.w_user)) return DSPS_ERR_ARG;
   const int blocks = (a.s_count + WEIGHT_WAVES - 1) / WEIGHT_WAVES;
   const size_t lds = sizeof(double) * weights_lds_doubles(a.n_t, a.ssp.n_age, a.ssp.n_met,
                                                           a.ssp.k_pad);

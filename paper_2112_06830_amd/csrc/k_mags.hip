@@ -32,33 +32,34 @@ __device__ __forceinline__ void xcd_tile_group(int b, int groups, int &tile, int
   group = slot % groups;
 }
 
-// Band slots evaluated together in one epilogue pass.
+// Most band slots evaluated together in one epilogue pass (a pass takes as
+// many of the chunk's remaining bands as it can, up to this).
 constexpr int NSLOT = 3;
 // Rows of the accumulator whose filter lookups are scheduled together.
 constexpr int EPI_ROWS = 2;
 
-// Per-galaxy sums of one chunk for bands base .. base + NSLOT - 1 (those not
-// above b_hi), NCOMP components each, reduced over the two lane halves and
-// the two row-waves of each column block and written to the chunk's partial
-// slot (component c of band b at c * n_band + b).  s_red aliases the operand
-// staging area: the leading barrier orders these writes after every wave's
-// last MFMA read and after the previous pass's reads.
-template <int NCOMP>
-__device__ __forceinline__ void write_band_slots(float (&sum)[NCOMP][2][NSLOT], int base, int b_hi,
-                                                 int n_band, float *s_red, int wr, int wc, int lane,
-                                                 int nvalid, float *out_base, int stride) {
+// Per-galaxy sums of one chunk for bands base .. base + NS - 1, NCOMP
+// components each, reduced over the two lane halves and the two row-waves of
+// each column block and written to the chunk's partial slot (component c of
+// band b at c * n_band + b).  s_red aliases the operand staging area: the
+// leading barrier orders these writes after every wave's last MFMA read and
+// after the previous pass's reads.
+template <int NCOMP, int NS>
+__device__ __forceinline__ void write_band_slots(float (&sum)[NCOMP][2][NS], int base, int n_band,
+                                                 float *s_red, int wr, int wc, int lane, int nvalid,
+                                                 float *out_base, int stride) {
   const int h = lane >> 5;
 #pragma unroll
   for (int c = 0; c < NCOMP; ++c)
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-      for (int k = 0; k < NSLOT; ++k) sum[c][nb][k] += __shfl_xor(sum[c][nb][k], 32, 64);
+      for (int k = 0; k < NS; ++k) sum[c][nb][k] += __shfl_xor(sum[c][nb][k], 32, 64);
   // Lane half h finishes column block nb = h.  Every array index below is a
   // compile-time constant (a runtime-selected index would move the
   // accumulators to scratch memory).
   const int col = h * 32 + (lane & 31);
-  float *red = s_red + (wc * 64 + col) * (NCOMP * NSLOT);
+  float *red = s_red + (wc * 64 + col) * (NCOMP * NS);
   __syncthreads();
   if (wr == 1) {
 #pragma unroll
@@ -67,7 +68,7 @@ __device__ __forceinline__ void write_band_slots(float (&sum)[NCOMP][2][NSLOT], 
 #pragma unroll
         for (int c = 0; c < NCOMP; ++c)
 #pragma unroll
-          for (int k = 0; k < NSLOT; ++k) red[c * NSLOT + k] = sum[c][nb][k];
+          for (int k = 0; k < NS; ++k) red[c * NS + k] = sum[c][nb][k];
       }
     }
   }
@@ -80,15 +81,86 @@ __device__ __forceinline__ void write_band_slots(float (&sum)[NCOMP][2][NSLOT], 
       for (int nb = 0; nb < 2; ++nb) {
         if (h == nb) {
 #pragma unroll
-          for (int k = 0; k < NSLOT; ++k) {
-            if (base + k <= b_hi) {
+          for (int k = 0; k < NS; ++k)
 #pragma unroll
-              for (int c = 0; c < NCOMP; ++c)
-                out[c * n_band + base + k] = sum[c][nb][k] + red[c * NSLOT + k];
-            }
+            for (int c = 0; c < NCOMP; ++c) out[c * n_band + base + k] = sum[c][nb][k] + red[c * NS + k];
+        }
+      }
+    }
+  }
+}
+
+// Per-lane state of the epilogue: the lane's two galaxy columns.
+struct EpiLane {
+  float zp1[2], da[2], dl[2], bp[2];
+};
+
+// One epilogue pass over bands base .. base + NS - 1 of a chunk.  Without the
+// moments (MOM false) acc already holds the attenuated SED times the
+// trapezoid weight, e = L F_att q; with them acc holds L and e and the three
+// moment integrands are formed here.  Sums, per band: num += T e,
+// den += T q and, with MOM, T e k_lambda, T e k0 (lambda/5500)^delta
+// log2(lambda/5500) and T e D(lambda).
+template <bool MOM, int NCOMP, int NS>
+__device__ __forceinline__ void band_pass(const f32x16 (&acc)[2][2], const EpiLane &E,
+                                          const FilterView &F, const float *s_tr,
+                                          const float4 *s_lc, const float *s_q, int base, int wr,
+                                          int h, float (&sum)[NCOMP][2][NS]) {
+  const int n_int = F.n_pts - 1;
+  const float *tab[NS];
+  float w0[NS], wi[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const float2 gr = F.grid[base + k];
+    tab[k] = s_tr + (base + k) * F.n_pts;
+    w0[k] = gr.x;
+    wi[k] = gr.y;
+  }
+#pragma unroll
+  for (int c = 0; c < NCOMP; ++c)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int k = 0; k < NS; ++k) sum[c][nb][k] = 0.0f;
+  // An offset the compiler cannot see through keeps the per-row LDS reads
+  // below inside the pass (hoisted out of it they would pin 64 registers).
+  int zero;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+  const float4 *lcp = s_lc + zero;
+  const float *qp = s_q + zero;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+      const float4 lc = lcp[row];   // (lambda, log2(lambda/5500), k0, drude shape)
+      const float q = qp[row];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const float lobs = E.zp1[nb] * lc.x;
+        float e = acc[mb][nb][r];
+        float x[3];
+        if (MOM) {
+          const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(E.dl[nb] * lc.y));
+          const float kl = fmaf(E.bp[nb], lc.w, k0x);
+          e = e * __builtin_amdgcn_exp2f(E.da[nb] * kl) * q;
+          x[0] = e * kl; x[1] = e * k0x * lc.y; x[2] = e * lc.w;
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const float t = filter_table_at(tab[k], n_int, (lobs - w0[k]) * wi[k]);
+          sum[0][nb][k] += t * e;
+          sum[1][nb][k] += t * q;
+          if (MOM) {
+            sum[2 % NCOMP][nb][k] += t * x[0];
+            sum[3 % NCOMP][nb][k] += t * x[1];
+            sum[4 % NCOMP][nb][k] += t * x[2];
           }
         }
       }
+      // bound the scheduler's look-ahead: batching the lookups of a few
+      // rows hides LDS latency, batching all of them spills registers
+      if ((r & (EPI_ROWS - 1)) == EPI_ROWS - 1) __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -138,19 +210,18 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   for (int t = threadIdx.x; t < nk; t += blockDim.x) s_koff[t] = pl->koff[t];
 
   // ---- filter tables into LDS
-  const int n_int = n_pts - 1;
   fill_filter_table(F, s_tr);
 
   // ---- per-galaxy parameters of this lane's two columns
-  float zp1[2], da[2], dl[2], bp[2];
+  EpiLane E;
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const int col = wc * 64 + nb * 32 + (lane & 31);
     if (col < nvalid) {
       const GalaxyMeta m = a.meta[a.s_begin + g0 + col];
-      zp1[nb] = m.zp1; da[nb] = m.dust_a; dl[nb] = m.delta; bp[nb] = m.bump;
+      E.zp1[nb] = m.zp1; E.da[nb] = m.dust_a; E.dl[nb] = m.delta; E.bp[nb] = m.bump;
     } else {
-      zp1[nb] = 1.0f; da[nb] = 0.0f; dl[nb] = 0.0f; bp[nb] = 0.0f;
+      E.zp1[nb] = 1.0f; E.da[nb] = 0.0f; E.dl[nb] = 0.0f; E.bp[nb] = 0.0f;
     }
   }
 
@@ -188,72 +259,45 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
     // partials are chunk-major: [chunk][galaxy][component]
     float *part = a.partial + ((size_t)c * a.part_rows + g0) * n_comp;
     const int stride = n_comp;
-    for (int base = b_lo; base <= b_hi; base += NSLOT) {
-      const float *tab[NSLOT];
-      float w0[NSLOT], wi[NSLOT];
+    if (!MOM && b_lo <= b_hi) {
+      // e = L F_att q in place, once for all passes.  Rounding is fixed
+      // explicitly, so that both instantiations agree bit for bit whatever
+      // the compiler contracts.  The hardware exp2 is within 1 ulp; its only
+      // difference from the library exp2f is that results below 2^-126
+      // (attenuation beyond ~380 mag) flush to zero.
 #pragma unroll
-      for (int k = 0; k < NSLOT; ++k) {
-        const int b = min(base + k, n_band - 1);   // slots past b_hi are computed, not stored
-        const float2 gr = F.grid[b];
-        tab[k] = s_tr + b * n_pts;
-        w0[k] = gr.x;
-        wi[k] = gr.y;
-      }
-      // components: num, den, then with MOM the moments of k_lambda,
-      // k0 (lambda/5500)^delta log2(lambda/5500) and the bump profile
-      float sum[NCOMP][2][NSLOT];
-#pragma unroll
-      for (int c = 0; c < NCOMP; ++c)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-          for (int k = 0; k < NSLOT; ++k) sum[c][nb][k] = 0.0f;
-      // An offset the compiler cannot see through keeps the per-row LDS reads
-      // below inside the pass (hoisted out of it they would pin 64 registers).
-      int zero;
-      asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
-      const float4 *lcp = s_lc + zero;
-      const float *qp = s_q + zero;
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
+      for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int row = wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-          const float4 lc = lcp[row];   // (lambda, log2(lambda/5500), k0, drude shape)
-          const float lam = lc.x;
-          const float q = qp[row];
+          const float4 lc = s_lc[row];
+          const float q = s_q[row];
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb) {
-            const float lobs = zp1[nb] * lam;
-            // rounding fixed explicitly, so that both instantiations agree bit
-            // for bit whatever the compiler contracts.  The hardware exp2 is
-            // within 1 ulp; its only difference from the library exp2f is
-            // that results below 2^-126 (attenuation beyond ~380 mag) flush to
-            // zero.
-            const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(dl[nb] * lc.y));  // k0 (lambda/5500)^delta
-            const float kl = fmaf(bp[nb], lc.w, k0x);                 // k_lambda
-            const float att = __builtin_amdgcn_exp2f(da[nb] * kl);
-            const float e = acc[mb][nb][r] * att * q;
-            float x[3];
-            if (MOM) { x[0] = e * kl; x[1] = e * k0x * lc.y; x[2] = e * lc.w; }
-#pragma unroll
-            for (int k = 0; k < NSLOT; ++k) {
-              const float t = filter_table_at(tab[k], n_int, (lobs - w0[k]) * wi[k]);
-              sum[0][nb][k] += t * e;
-              sum[1][nb][k] += t * q;
-              if (MOM) {
-                sum[2 % NCOMP][nb][k] += t * x[0];
-                sum[3 % NCOMP][nb][k] += t * x[1];
-                sum[4 % NCOMP][nb][k] += t * x[2];
-              }
-            }
+            const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(E.dl[nb] * lc.y));  // k0 (lambda/5500)^delta
+            const float kl = fmaf(E.bp[nb], lc.w, k0x);                                 // k_lambda
+            acc[mb][nb][r] = acc[mb][nb][r] * __builtin_amdgcn_exp2f(E.da[nb] * kl) * q;
           }
-          // bound the scheduler's look-ahead: batching the lookups of a few
-          // rows hides LDS latency, batching all of them spills registers
-          if ((r & (EPI_ROWS - 1)) == EPI_ROWS - 1) __builtin_amdgcn_sched_barrier(0);
         }
+    }
+    for (int base = b_lo; base <= b_hi;) {
+      const int rem = b_hi - base + 1;
+      if (rem >= 3) {
+        float sum[NCOMP][2][3];
+        band_pass<MOM, NCOMP, 3>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
+        write_band_slots<NCOMP, 3>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride);
+        base += 3;
+      } else if (rem == 2) {
+        float sum[NCOMP][2][2];
+        band_pass<MOM, NCOMP, 2>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
+        write_band_slots<NCOMP, 2>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride);
+        base += 2;
+      } else {
+        float sum[NCOMP][2][1];
+        band_pass<MOM, NCOMP, 1>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
+        write_band_slots<NCOMP, 1>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride);
+        base += 1;
       }
-      write_band_slots<NCOMP>(sum, base, b_hi, n_band, s_red, wr, wc, lane, nvalid, part, stride);
     }
     // bands that see none of this chunk contribute exact zeros
     if (wr == 0) {

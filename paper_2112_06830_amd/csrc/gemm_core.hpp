@@ -184,31 +184,30 @@ __device__ __forceinline__ unsigned active_bands(const FilterView &F, float o_lo
   return m;
 }
 
-// Filter transmission tables into LDS, [n_band][n_pts].  Whole workgroup.
+// Filter transmission tables in LDS: band b at b * filter_stride(n_pts), its
+// n_pts points followed by one pad entry repeating the last, so that an
+// interpolation at the table's upper end needs no index clamp.
+__host__ __device__ inline int filter_stride(int n_pts) { return n_pts + 1; }
+
+// Whole workgroup.
 __device__ __forceinline__ void fill_filter_table(const FilterView &F, float *s_tr) {
-  for (int i = threadIdx.x; i < F.n_band * F.n_pts; i += blockDim.x) s_tr[i] = F.trans[i];
+  const int stride = filter_stride(F.n_pts);
+  for (int i = threadIdx.x; i < F.n_band * stride; i += blockDim.x) {
+    const int b = i / stride, k = min(i - b * stride, F.n_pts - 1);
+    s_tr[i] = F.trans[b * F.n_pts + k];
+  }
 }
 
-// Transmission of one band (table tr of n_int + 1 points) at grid coordinate
-// u = (lambda - first) / spacing: linear interpolation between grid points,
-// zero outside [0, n_int].  The two points come from one paired LDS read.
-// Matches filter_at below bit for bit.
+// Transmission of one band (padded table tr, n_int + 1 points) at grid
+// coordinate u = (lambda - first) / spacing, passed as u = lambda * (1 /
+// spacing) - first / spacing: linear interpolation between grid points, zero
+// outside [0, n_int].  The two points come from one paired LDS read.
 __device__ __forceinline__ float filter_table_at(const float *tr, int n_int, float u) {
   const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, (float)n_int);
-  const int i = min((int)uc, n_int - 1);
+  const int i = (int)uc;                          // <= n_int: the pad covers i + 1
   const float t0 = tr[i], t1 = tr[i + 1];
-  const float t = fmaf(uc - (float)i, t1 - t0, t0);
+  const float t = fmaf(__builtin_amdgcn_fractf(uc), t1 - t0, t0);
   return u == uc ? t : 0.0f;
-}
-
-// Linear interpolation of a uniformly gridded filter, zero outside.
-__device__ __forceinline__ float filter_at(const float *tr, int n_pts, float u) {
-  if (!(u >= 0.0f) || !(u <= (float)(n_pts - 1))) return 0.0f;
-  int i = (int)u;
-  i = i > n_pts - 2 ? n_pts - 2 : i;
-  const float f = u - (float)i;
-  const float t0 = tr[i];
-  return t0 + f * (tr[i + 1] - t0);
 }
 
 }  // namespace dsps

@@ -108,13 +108,13 @@ __device__ __forceinline__ void band_pass(const f32x16 (&acc)[2][2], const EpiLa
                                           int h, float (&sum)[NCOMP][2][NS]) {
   const int n_int = F.n_pts - 1;
   const float *tab[NS];
-  float w0[NS], wi[NS];
+  float nw0[NS], wi[NS];   // u = lambda_obs * wi - w0 * wi
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const float2 gr = F.grid[base + k];
-    tab[k] = s_tr + (base + k) * F.n_pts;
-    w0[k] = gr.x;
+    tab[k] = s_tr + (base + k) * filter_stride(F.n_pts);
     wi[k] = gr.y;
+    nw0[k] = -gr.x * gr.y;
   }
 #pragma unroll
   for (int c = 0; c < NCOMP; ++c)
@@ -148,7 +148,7 @@ __device__ __forceinline__ void band_pass(const f32x16 (&acc)[2][2], const EpiLa
         }
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-          const float t = filter_table_at(tab[k], n_int, (lobs - w0[k]) * wi[k]);
+          const float t = filter_table_at(tab[k], n_int, fmaf(lobs, wi[k], nw0[k]));
           sum[0][nb][k] += t * e;
           sum[1][nb][k] += t * q;
           if (MOM) {
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
   __shared__ int s_koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];   // K offset of each stage
-  extern __shared__ float s_tr[];      // filter transmissions [n_band][n_pts]
+  extern __shared__ float s_tr[];      // filter transmissions [n_band][n_pts + 1]
   float *s_red = reinterpret_cast<float *>(&sm[0]);
 
   int tile, group;
@@ -372,7 +372,7 @@ int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
   const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
   const int blocks = (n_tiles + 7) / 8 * 8 * a.n_groups;
-  const size_t lds = sizeof(float) * a.flt.n_band * a.flt.n_pts;
+  const size_t lds = sizeof(float) * a.flt.n_band * filter_stride(a.flt.n_pts);
   if (a.precision == DSPS_BF16)
     hipLaunchKernelGGL(k_tile_plan<DSPS_BF16>, dim3(n_tiles), dim3(TILE_G), 0, stream, a);
   else

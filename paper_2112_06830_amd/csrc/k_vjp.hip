@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
   __shared__ float4 s_meta[TILE_G];    // (1 + z, dust_a, delta, bump)
   __shared__ float2 s_grid[DSPS_MAX_BAND];
   __shared__ int s_tile[4];            // window lo, window hi, min and max of (1+z) bits
-  extern __shared__ float s_tr[];      // filter transmissions [n_band][n_pts]
+  extern __shared__ float s_tr[];      // filter transmissions [n_band][n_pts + 1]
   const int group = blockIdx.x, tile = blockIdx.y;
   const SspView P = a.ssp;
   const FilterView F = a.flt;
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
       for (int k = 0; k < n_act; ++k) {
         const int b = b_lo + k;
         const float2 gr = s_grid[b];
-        gs += s_gam[col * DSPS_MAX_BAND + b] * filter_table_at(s_tr + b * F.n_pts, n_int, (lobs - gr.x) * gr.y);
+        gs += s_gam[col * DSPS_MAX_BAND + b] * filter_table_at(s_tr + b * filter_stride(F.n_pts), n_int, fmaf(lobs, gr.y, -gr.x * gr.y));
       }
       const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(m.z * lc.y));
       const float att = __builtin_amdgcn_exp2f(m.y * fmaf(m.w, lc.w, k0x));
@@ -406,7 +406,7 @@ int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
     hipLaunchKernelGGL(k_vjp_gamma, dim3((a.s_count + 255) / 256), dim3(256), 0, stream, a);
   } else if (stage == 1) {
     ProfScope prof(DSPS_KERNEL_VJP_LBAR, stream);
-    const size_t lds = sizeof(float) * a.flt.n_band * a.flt.n_pts;
+    const size_t lds = sizeof(float) * a.flt.n_band * filter_stride(a.flt.n_pts);
     hipLaunchKernelGGL(k_vjp_lbar, dim3(a.n_groups, tiles), dim3(256), lds, stream, a);
   } else if (stage == 2) {
     ProfScope prof(DSPS_KERNEL_VJP_WBAR, stream);

@@ -61,7 +61,9 @@ def mags_vjp(inp: OracleInputs, mags_bar):
     Returns a dict with float64 arrays:
       sfr_bar [n_gal, n_t], sfh_params_bar [5, n_gal] (only when
       inp.sfh_params is set), lgmet_bar, sigma_bar, av_bar, delta_bar,
-      bump_bar [n_gal].
+      bump_bar [n_gal], and lgmet_old_bar [n_gal] for the transition MDF
+      (d mu_i / d lgmet = 1 - T_i and d mu_i / d lgmet_old = T_i with
+      T_i = T_erf((log10 tau_i - pivot) / width)).
     """
     mags_bar = np.atleast_2d(np.asarray(mags_bar, dtype=np.float64))
     n_gal = inp.n_gal
@@ -81,6 +83,10 @@ def mags_vjp(inp: OracleInputs, mags_bar):
     drude_unit = dust.drude_bump(lam, 1.0)
 
     out = {k: np.zeros(n_gal) for k in ("lgmet_bar", "sigma_bar", "av_bar", "delta_bar", "bump_bar")}
+    terf_mdf = inp.lgmet_old is not None
+    if terf_mdf:
+        out["lgmet_old_bar"] = np.zeros(n_gal)
+        t_age = mdf.transition_weight(inp.lg_age, inp.lg_age_pivot, inp.mdf_width)    # [i]
     out["sfr_bar"] = np.zeros((n_gal, n_t))
     if inp.sfh_params is not None:
         out["sfh_params_bar"] = np.zeros((5, n_gal))
@@ -91,13 +97,17 @@ def mags_vjp(inp: OracleInputs, mags_bar):
         t_edge = t_obs[g] - age_edges_gyr
         m_edge = sfh.mass_formed_at(t_edge, t_table, mcum)
         m_age = m_edge[:-1] - m_edge[1:]
-        mu = inp.lgmet[g] + inp.lgmet_slope * (inp.lg_age - inp.lg_age_pivot)       # [i]
+        mu = mdf.mdf_centres(inp.lgmet[g], inp.lg_age, inp.lgmet_slope, inp.lg_age_pivot,
+                             None if not terf_mdf else inp.lgmet_old[g:g + 1],
+                             inp.mdf_width)[0]                                      # [i]
         sig = inp.sigma_z[g]
         with np.errstate(invalid="ignore"):
             u = (met_edges[:, None] - mu[None, :]) / sig                              # [e, i]
         u = np.where(np.isinf(met_edges)[:, None], np.sign(met_edges)[:, None] * np.inf, u)
         p_met = mdf.mdf_weights(inp.lgmet[g], sig, inp.lgz, inp.lg_age,
-                                inp.lgmet_slope, inp.lg_age_pivot)[0]                # [j, i]
+                                inp.lgmet_slope, inp.lg_age_pivot,
+                                None if not terf_mdf else inp.lgmet_old[g:g + 1],
+                                inp.mdf_width)[0]                                   # [j, i]
         w = (m_age[None, :] * p_met).reshape(-1)
         spec = w @ table                                                             # [l]
         kdust = k0 * np.exp(inp.delta[g] * log_ratio) + inp.bump[g] * drude_unit
@@ -127,7 +137,12 @@ def mags_vjp(inp: OracleInputs, mags_bar):
         cdf_bar[:-1] -= p_bar
         u_bar = cdf_bar * triweight_pdf(np.where(np.isfinite(u), u, 0.0)) * np.isfinite(u)
         u_fin = np.where(np.isfinite(u), u, 0.0)
-        out["lgmet_bar"][g] = np.sum(u_bar * (-1.0 / sig))
+        mu_bar = np.sum(u_bar, axis=0) * (-1.0 / sig)                                # [i]
+        if terf_mdf:
+            out["lgmet_bar"][g] = np.sum(mu_bar * (1.0 - t_age))
+            out["lgmet_old_bar"][g] = np.sum(mu_bar * t_age)
+        else:
+            out["lgmet_bar"][g] = np.sum(mu_bar)
         out["sigma_bar"][g] = np.sum(u_bar * (-u_fin / sig))
 
         # mass at each age edge -> cumulative nodes -> SFR table

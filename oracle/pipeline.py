@@ -44,6 +44,8 @@ class OracleInputs:
     bump: np.ndarray
     lgmet_slope: float = 0.1
     lg_age_pivot: float = 9.0
+    lgmet_old: np.ndarray | None = None   # transition MDF: old-age centre per galaxy
+    mdf_width: float = 0.5                # transition width in dex
     om0: float = 0.3
     h: float = 0.7
     w0: float = -1.0
@@ -59,6 +61,8 @@ class OracleInputs:
         kw = dict(self.__dict__)
         for name in ("sfr", "z", "lgmet", "sigma_z", "av", "delta", "bump"):
             kw[name] = getattr(self, name)[idx]
+        if self.lgmet_old is not None:
+            kw["lgmet_old"] = self.lgmet_old[idx]
         if self.sfh_params is not None:
             kw["sfh_params"] = self.sfh_params[:, idx]
         return OracleInputs(**kw)
@@ -80,6 +84,9 @@ def prepare_inputs(ssp, filters, pop, sfr=None, om0=0.3, h=0.7, w0=-1.0,
         sigma_z=np.asarray(pop.sigma_z, np.float64), av=np.asarray(pop.av, np.float64),
         delta=np.asarray(pop.delta, np.float64), bump=np.asarray(pop.bump, np.float64),
         lgmet_slope=float(pop.lgmet_slope), lg_age_pivot=float(pop.lg_age_pivot),
+        lgmet_old=(None if getattr(pop, "lgmet_old", None) is None
+                   else np.asarray(pop.lgmet_old, np.float64)),
+        mdf_width=float(getattr(pop, "mdf_width", 0.5)),
         om0=om0, h=h, w0=w0, k0_reading=k0_reading,
         sfh_params=np.asarray(pop.sfh_params, np.float64))
 
@@ -93,7 +100,8 @@ def weights(inp: OracleInputs, return_parts: bool = False):
     t_obs = observation_times(inp)
     m_age = sfh.age_bin_masses(t_obs, inp.t_table, inp.sfr, inp.lg_age)       # [g, i]
     p_met = mdf.mdf_weights(inp.lgmet, inp.sigma_z, inp.lgz, inp.lg_age,
-                            inp.lgmet_slope, inp.lg_age_pivot)                  # [g, j, i]
+                            inp.lgmet_slope, inp.lg_age_pivot,
+                            inp.lgmet_old, inp.mdf_width)                       # [g, j, i]
     w = m_age[:, None, :] * p_met
     if return_parts:
         return w, m_age, p_met, t_obs

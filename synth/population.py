@@ -38,6 +38,8 @@ class Population:
     z, lgmet, sigma_z, av, delta, bump: [n_gal] float32-representable float64
     targets:    [n_gal, n_band] target magnitudes for the squared-error loss
     lgmet_slope, lg_age_pivot: age dependence of the metallicity centre
+    lgmet_old:  [n_gal] old-age metallicity centre of the transition MDF, or
+                None for the linear model; mdf_width its width in dex
     """
 
     t_table: np.ndarray
@@ -51,6 +53,8 @@ class Population:
     targets: np.ndarray
     lgmet_slope: float = 0.1
     lg_age_pivot: float = 9.0
+    lgmet_old: np.ndarray | None = None
+    mdf_width: float = 0.5
     seed: int = 0
     meta: dict = field(default_factory=dict)
 
@@ -70,7 +74,9 @@ class Population:
             sigma_z=self.sigma_z[idx].copy(), av=self.av[idx].copy(),
             delta=self.delta[idx].copy(), bump=self.bump[idx].copy(),
             targets=self.targets[idx].copy(), lgmet_slope=self.lgmet_slope,
-            lg_age_pivot=self.lg_age_pivot, seed=self.seed, meta=dict(self.meta))
+            lg_age_pivot=self.lg_age_pivot,
+            lgmet_old=None if self.lgmet_old is None else self.lgmet_old[idx].copy(),
+            mdf_width=self.mdf_width, seed=self.seed, meta=dict(self.meta))
 
 
 def make_time_grid(n_t: int) -> np.ndarray:
@@ -79,13 +85,17 @@ def make_time_grid(n_t: int) -> np.ndarray:
 
 def make_population(n_gal: int, n_t: int = 100, z_range=(0.1, 1.0), seed: int = 2,
                     n_band: int = 6, lgmet_slope: float = 0.1,
-                    lg_age_pivot: float = 9.0) -> Population:
+                    lg_age_pivot: float = 9.0, mdf: str = "linear",
+                    mdf_width: float = 0.5) -> Population:
     """Draw a population with the parameter distributions of the workloads.
 
     log10 A ~ U[0, 2], tau ~ U[1, 5] Gyr, alpha ~ U[0.5, 3], q ~ U[0, 1],
     t_q ~ U[2, 13] Gyr; lgmet ~ U[-3, -1.7], sigma_Z ~ U[0.1, 0.5];
     A_V ~ U[0, 2], delta ~ U[-0.7, 0.3], bump ~ U[0, 3]; z ~ U[z_range];
-    targets ~ N(22, 1) mag per galaxy and band.
+    targets ~ N(22, 1) mag per galaxy and band.  mdf="transition" adds an
+    old-age centre lgmet_old = lgmet - U[0, 0.6] (older stars more metal-poor)
+    for the T_erf transition model, drawn from its own stream so the other
+    parameters are those of the linear model with the same seed.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     n = int(n_gal)
@@ -103,7 +113,13 @@ def make_population(n_gal: int, n_t: int = 100, z_range=(0.1, 1.0), seed: int = 
     z = _f32(rng.uniform(z_range[0], z_range[1], n))
     trng = np.random.Generator(np.random.PCG64(seed + 1000003))
     targets = _f32(trng.normal(22.0, 1.0, (n, n_band)))
+    lgmet_old = None
+    if mdf == "transition":
+        mrng = np.random.Generator(np.random.PCG64(seed + 2000003))
+        lgmet_old = _f32(lgmet - mrng.uniform(0.0, 0.6, n))
+    elif mdf != "linear":
+        raise ValueError(f"unknown mdf model {mdf!r}")
     return Population(t_table=make_time_grid(n_t), sfh_params=np.ascontiguousarray(sfh_params),
                       z=z, lgmet=lgmet, sigma_z=sigma_z, av=av, delta=delta, bump=bump,
                       targets=targets, lgmet_slope=lgmet_slope, lg_age_pivot=lg_age_pivot,
-                      seed=seed)
+                      lgmet_old=lgmet_old, mdf_width=float(mdf_width), seed=seed)

@@ -114,6 +114,20 @@ def test_wcdm_reduces_to_lcdm_at_w_minus_one():
                                cosmology.age_at_z(zs), rtol=1e-9)
 
 
+def test_wcdm_w_minus_third_comoving_distance_closed_form():
+    # Flat wCDM with w = -1/3: E^2 = Om x^3 + (1 - Om) x^2 with x = 1 + z, so
+    # int dz / E = int dx / (x sqrt(Om x + b)), b = 1 - Om, which integrates to
+    # (1/sqrt b) ln[(sqrt(Om x + b) - sqrt b) / (sqrt(Om x + b) + sqrt b)].
+    om0, h = 0.27, 0.68
+    b = 1.0 - om0
+    prim = lambda x: np.log((np.sqrt(om0 * x + b) - np.sqrt(b))
+                            / (np.sqrt(om0 * x + b) + np.sqrt(b))) / np.sqrt(b)
+    zs = np.array([0.05, 0.6, 2.4])
+    dc = constants.C_KM_S / (100.0 * h) * (prim(1.0 + zs) - prim(1.0))
+    np.testing.assert_allclose(cosmology.comoving_distance_mpc(zs, om0=om0, h=h, w0=-1.0 / 3.0),
+                               dc, rtol=1e-11)
+
+
 # ---------------------------------------------------------------- dust
 def test_calzetti_normalisation_at_v():
     # A_V / E(B-V) = R_V: k(lambda_V) equals R_V = 4.05 to the precision of

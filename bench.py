@@ -233,6 +233,61 @@ def run_grad(P, steps, warmup, n_gal=200_000, seed=5):
     return res
 
 
+def run_variants(P, steps, warmup, n_gal=100_000, seed=8, w0=-0.9, width=0.4):
+    """The MDF and cosmology variants on the FP32 forward and forward +
+    gradient of the 1e5-galaxy workload: the T_erf transition of the MDF
+    centre with age (old-age centre per galaxy, width 0.4 dex) in a flat wCDM
+    cosmology (w0 = -0.9).  Returns the timings and, for the oracle check of
+    the CPU-baseline leg, the magnitudes of the first 128 galaxies."""
+    import torch
+    import synth
+    ssp = synth.make_ssp(n_wave=5994, wave_lo=9.0e2, wave_hi=2.5e4)
+    flt = synth.make_filters()
+    pop = synth.make_population(n_gal, n_t=100, z_range=(0.1, 3.0), seed=seed, mdf="transition",
+                                mdf_width=width)
+    log(f"variants_fp32_1e5: transition MDF (width {width}), wCDM w0={w0}")
+    ssp_h = P.SspBlock.from_synth(ssp, precisions=("fp32",))
+    flt_h = P.FilterBank.from_synth(flt)
+    cos = P.Cosmology(w0=w0)
+    dpop = P.DevicePopulation.from_synth(pop, use_params=True)
+    tgt = torch.tensor(pop.targets, dtype=torch.float32, device="cuda")
+    ws_f = P.Workspace(P.workspace_size(2, ssp_h, flt_h, n_gal, 100, "fp32"), dpop.device)
+    ws_b = P.Workspace(P.workspace_size(3, ssp_h, flt_h, n_gal, 100, "fp32"), dpop.device)
+    m = torch.empty((n_gal, 6), dtype=torch.float32, device="cuda")
+    bands = torch.empty((n_gal, 2, 6), dtype=torch.float32, device="cuda")
+    mom = torch.empty((n_gal, 3, 6), dtype=torch.float32, device="cuda")
+    outs = {"sfh_params": torch.empty((5, n_gal), dtype=torch.float64, device="cuda")}
+    for k in ("lgmet", "lgmet_old", "sigma_z", "av", "delta", "bump"):
+        outs[k] = torch.empty(n_gal, dtype=torch.float32, device="cuda")
+    bar = torch.empty_like(m)
+
+    def forward():
+        P.mags(ssp_h, flt_h, cos, dpop, workspace=ws_f, out=m)
+
+    def gradient():
+        P.mags(ssp_h, flt_h, cos, dpop, with_moments=True, workspace=ws_f, out=m,
+               bands_out=bands, moments_out=mom)
+        torch.sub(m, tgt, out=bar)
+        bar.mul_(2.0)
+        P.mags_vjp(ssp_h, flt_h, cos, dpop, bar, bands=bands, moments=mom, workspace=ws_b,
+                   outs=outs)
+
+    res = {}
+    for name, fn in (("forward", forward), ("forward_grad", gradient)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[name] = {"ms_per_step": ms, "galaxies_per_s": n_gal / (ms * 1e-3)}
+    res["finite"] = bool(all(torch.isfinite(v).all().item() for v in outs.values()))
+    forward()
+    return res, (ssp, flt, pop.subset(np.arange(128)), m[:128].cpu().numpy(), w0)
+
+
 def run_forward_model(P, steps, warmup, n_gal=100_000, seed=7):
     """The Section 4.1 forward model at z = 0: parametric SFH -> SFR table ->
     six-band absolute magnitudes (FP32) -> red colour cut (g - r above the
@@ -397,12 +452,21 @@ def main():
         log(f"forward model z=0 1e5: {fm['forward']['ms_per_step']:.3f} ms/step, "
             f"with population gradient {fm['forward_grad']['ms_per_step']:.3f} ms/step")
         log(f"fp32 fwd+grad 2e5: {gr['ms_per_step']:.3f} ms/step")
+        va, va_sample = run_variants(P, max(3, args.steps // 4), 1)
+        extra["variants_transition_mdf_wcdm_1e5"] = va
+        log(f"variants 1e5: forward {va['forward']['ms_per_step']:.3f} ms/step, "
+            f"with gradient {va['forward_grad']['ms_per_step']:.3f} ms/step")
         extra["serve_poisson_200hz"] = run_serve(seconds=args.serve_seconds)
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle on a bounded sample")
         cpu, errors = cpu_baseline(ssp, flt, pop, m32, pop16, m16)
+        if not args.no_extra:
+            import oracle
+            v_ssp, v_flt, v_pop, v_m, v_w0 = va_sample
+            v_ref = oracle.mags(oracle.prepare_inputs(v_ssp, v_flt, v_pop, w0=v_w0))
+            errors["variants_transition_mdf_wcdm_1e5"] = band_errors(v_m, v_ref)
         extra["error_vs_oracle"] = errors
 
     traffic = read_traffic("fp32", "fp32_1e5")

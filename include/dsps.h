@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define DSPS_ABI_VERSION 2
+#define DSPS_ABI_VERSION 3
 
 typedef enum {
   DSPS_OK = 0,
@@ -146,6 +146,15 @@ typedef struct { double om0, w0, h; } dsps_cosmo;
  *   sigma_z     [n_gal] MDF width in dex, > 0
  *   av, delta, bump [n_gal] attenuation A_V, power-law slope, Drude amplitude
  *   lgmet_slope, lg_age_pivot  mu(tau) = lgmet + slope (log10 tau - pivot)
+ *   lgmet_old   [n_gal] old-age MDF centre, or NULL.  When set, the centre
+ *               moves from lgmet (young) to lgmet_old (old) with the
+ *               cumulative triweight of log10 age (Section 3.2.2, Eq.
+ *               agedep_mdf with Appendix B, Eq. terf):
+ *               mu(tau) = lgmet + (lgmet_old - lgmet)
+ *                         T_erf((log10 tau - lg_age_pivot) / mdf_width),
+ *               and lgmet_slope is unused
+ *   mdf_width   transition width in dex (> 0, finite) when lgmet_old is set;
+ *               the transition spans +-3 widths around lg_age_pivot
  * ------------------------------------------------------------------------ */
 typedef struct {
   int n_gal, n_t;
@@ -154,6 +163,8 @@ typedef struct {
   const double *sfh_params;
   const float *z, *lgmet, *sigma_z, *av, *delta, *bump;
   double lgmet_slope, lg_age_pivot;
+  const float *lgmet_old;
+  double mdf_width;
 } dsps_pop;
 
 /* Workspace bytes a call of kind `op` needs for this population shape and
@@ -224,8 +235,9 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
  *   sfr_bar         [n_gal*n_t] float64 gradient w.r.t. the SFR table, or NULL
  *   sfh_params_bar  [5*n_gal] float64 gradient w.r.t. (A, tau, alpha, q, t_q);
  *                   requires pop->sfh_params, else NULL
- *   lgmet_bar, sigma_bar, av_bar, delta_bar, bump_bar
- *                   [n_gal] float32 each, or NULL
+ *   lgmet_bar, lgmet_old_bar, sigma_bar, av_bar, delta_bar, bump_bar
+ *                   [n_gal] float32 each, or NULL (lgmet_old_bar requires
+ *                   pop->lgmet_old)
  * The dust gradients are the band cotangents applied to the moments; the SED
  * cotangent F q sum_b gamma_b T_b needs no SED, so the backward pass holds no
  * forward contraction.  Redshift gets no gradient.
@@ -233,9 +245,9 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
 int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
                   const dsps_pop *pop, int precision, const float *mags_bar,
                   const float *bands, const float *moments, double *sfr_bar,
-                  double *sfh_params_bar, float *lgmet_bar, float *sigma_bar, float *av_bar,
-                  float *delta_bar, float *bump_bar, void *workspace, size_t workspace_bytes,
-                  hipStream_t stream);
+                  double *sfh_params_bar, float *lgmet_bar, float *lgmet_old_bar,
+                  float *sigma_bar, float *av_bar, float *delta_bar, float *bump_bar,
+                  void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Population summary of the Section 4.1 forward model: a red-colour cut and

@@ -48,6 +48,7 @@ class Pop(ctypes.Structure):
         ("z", ctypes.c_void_p), ("lgmet", ctypes.c_void_p), ("sigma_z", ctypes.c_void_p),
         ("av", ctypes.c_void_p), ("delta", ctypes.c_void_p), ("bump", ctypes.c_void_p),
         ("lgmet_slope", ctypes.c_double), ("lg_age_pivot", ctypes.c_double),
+        ("lgmet_old", ctypes.c_void_p), ("mdf_width", ctypes.c_double),
     ]
 
 
@@ -73,7 +74,7 @@ def _declare(lib):
         "dsps_sed": (I, [P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, I, P, P, S, P]),
         "dsps_mags": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P, P, S, P]),
         "dsps_mags_vjp": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P,
-                              P, P, P, P, P, P, P, P, S, P]),
+                              P, P, P, P, P, P, P, P, P, S, P]),
         "dsps_quantize_bf16": (I, [P, I, I, P, P, P]),
         "dsps_pop_summary_workspace": (I, [I, I, ctypes.POINTER(S)]),
         "dsps_pop_summary": (I, [P, I, I, I, I, D, D, I, P, I, D, P, P, S, P]),

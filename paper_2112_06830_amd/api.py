@@ -144,6 +144,8 @@ class DevicePopulation:
     bump: torch.Tensor
     lgmet_slope: float = 0.1
     lg_age_pivot: float = 9.0
+    lgmet_old: torch.Tensor | None = None   # transition MDF: old-age centre, float32
+    mdf_width: float = 0.5
 
     @property
     def n_gal(self):
@@ -160,7 +162,8 @@ class DevicePopulation:
     def c(self):
         return N.Pop(self.n_gal, self.n_t, _ptr(self.t_table), _ptr(self.sfr), _ptr(self.sfh_params),
                      _ptr(self.z), _ptr(self.lgmet), _ptr(self.sigma_z), _ptr(self.av),
-                     _ptr(self.delta), _ptr(self.bump), self.lgmet_slope, self.lg_age_pivot)
+                     _ptr(self.delta), _ptr(self.bump), self.lgmet_slope, self.lg_age_pivot,
+                     _ptr(self.lgmet_old), self.mdf_width)
 
     @classmethod
     def from_synth(cls, pop, device="cuda", sfr=None, use_params=False):
@@ -178,11 +181,15 @@ class DevicePopulation:
         return cls(t_table=_dev(pop.t_table, torch.float64, d), sfr=sfr_t, sfh_params=par,
                    z=f32(pop.z), lgmet=f32(pop.lgmet), sigma_z=f32(pop.sigma_z), av=f32(pop.av),
                    delta=f32(pop.delta), bump=f32(pop.bump), lgmet_slope=float(pop.lgmet_slope),
-                   lg_age_pivot=float(pop.lg_age_pivot))
+                   lg_age_pivot=float(pop.lg_age_pivot),
+                   lgmet_old=(None if getattr(pop, "lgmet_old", None) is None
+                              else f32(pop.lgmet_old)),
+                   mdf_width=float(getattr(pop, "mdf_width", 0.5)))
 
     def with_sfr(self, sfr):
         return DevicePopulation(self.t_table, sfr, None, self.z, self.lgmet, self.sigma_z, self.av,
-                                self.delta, self.bump, self.lgmet_slope, self.lg_age_pivot)
+                                self.delta, self.bump, self.lgmet_slope, self.lg_age_pivot,
+                                self.lgmet_old, self.mdf_width)
 
 
 def workspace_size(op: int, ssp: SspBlock, filters: FilterBank | None, n_gal: int, n_t: int,
@@ -303,7 +310,7 @@ def profile_read(kernel: str):
 def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopulation,
              mags_bar: torch.Tensor, bands: torch.Tensor | None = None,
              moments: torch.Tensor | None = None,
-             want=("sfr", "sfh_params", "lgmet", "sigma_z", "av", "delta", "bump"),
+             want=("sfr", "sfh_params", "lgmet", "lgmet_old", "sigma_z", "av", "delta", "bump"),
              workspace: Workspace | None = None, outs: dict | None = None, stream=None) -> dict:
     """dsps_mags_vjp: cotangents of the population inputs for a magnitude
     cotangent mags_bar [n_gal, n_band] (float32 path).  bands and moments come
@@ -328,13 +335,15 @@ def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePo
     for k in ("lgmet", "sigma_z", "av", "delta", "bump"):
         if k in want:
             out[k] = torch.empty(n, dtype=torch.float32, device=d)
+    if "lgmet_old" in want and pop.lgmet_old is not None:
+        out["lgmet_old"] = torch.empty(n, dtype=torch.float32, device=d)
     if workspace is None:
         workspace = Workspace(workspace_size(N.OP_MAGS_VJP, ssp, filters, n, pop.n_t, "fp32"), d)
     c, p = cosmo.c(), pop.c()
     rc = _lib().dsps_mags_vjp(ssp.handle, filters.handle, ctypes.byref(c), ctypes.byref(p), N.FP32,
                               _ptr(mags_bar), _ptr(bands), _ptr(moments), _ptr(out.get("sfr")),
                               _ptr(out.get("sfh_params")), _ptr(out.get("lgmet")),
-                              _ptr(out.get("sigma_z")), _ptr(out.get("av")), _ptr(out.get("delta")),
+                              _ptr(out.get("lgmet_old")), _ptr(out.get("sigma_z")), _ptr(out.get("av")), _ptr(out.get("delta")),
                               _ptr(out.get("bump")), workspace.ptr(), workspace.nbytes, _stream(stream))
     N.check(rc, "dsps_mags_vjp")
     return out

@@ -11,23 +11,26 @@ from . import api
 
 class DspsMags(torch.autograd.Function):
     """mags = DspsMags.apply(ssp, filters, cosmo, t_table, sfh_params, sfr, z,
-    lgmet, sigma_z, av, delta, bump, slope, pivot)
+    lgmet, sigma_z, av, delta, bump, slope, pivot, lgmet_old, mdf_width)
 
     Exactly one of sfh_params [5, n_gal] (float64) and sfr [n_gal, n_t]
-    (float64) is a tensor, the other None.  Gradients flow to sfh_params or
-    sfr, lgmet, sigma_z, av, delta and bump; z and t_table get none.
+    (float64) is a tensor, the other None; lgmet_old (float32) selects the
+    transition MDF, or is None.  Gradients flow to sfh_params or sfr, lgmet,
+    lgmet_old, sigma_z, av, delta and bump; z and t_table get none.
     """
 
     @staticmethod
     def forward(ctx, ssp, filters, cosmo, t_table, sfh_params, sfr, z, lgmet, sigma_z, av, delta,
-                bump, slope=0.1, pivot=9.0):
+                bump, slope=0.1, pivot=9.0, lgmet_old=None, mdf_width=0.5):
         pop = api.DevicePopulation(t_table.contiguous(),
                                    None if sfr is None else sfr.detach().contiguous(),
                                    None if sfh_params is None else sfh_params.detach().contiguous(),
                                    z.detach().contiguous(), lgmet.detach().contiguous(),
                                    sigma_z.detach().contiguous(), av.detach().contiguous(),
                                    delta.detach().contiguous(), bump.detach().contiguous(),
-                                   float(slope), float(pivot))
+                                   float(slope), float(pivot),
+                                   None if lgmet_old is None else lgmet_old.detach().contiguous(),
+                                   float(mdf_width))
         mags, bands, moments = api.mags(ssp, filters, cosmo, pop, precision="fp32", with_moments=True)
         ctx.ssp, ctx.filters, ctx.cosmo, ctx.pop = ssp, filters, cosmo, pop
         ctx.save_for_backward(bands, moments)
@@ -46,15 +49,17 @@ class DspsMags(torch.autograd.Function):
         for i, k in enumerate(names):
             if ctx.needs_input_grad[7 + i]:
                 want.append(k)
+        if pop.lgmet_old is not None and ctx.needs_input_grad[14]:
+            want.append("lgmet_old")
         g = api.mags_vjp(ctx.ssp, ctx.filters, ctx.cosmo, pop, mags_bar, bands=bands, moments=moments,
                          want=tuple(want))
         return (None, None, None, None, g.get("sfh_params"), g.get("sfr"), None,
                 g.get("lgmet"), g.get("sigma_z"), g.get("av"), g.get("delta"), g.get("bump"),
-                None, None)
+                None, None, g.get("lgmet_old"), None)
 
 
 def dsps_mags(ssp, filters, cosmo, pop: api.DevicePopulation, sfh_params=None, sfr=None,
-              lgmet=None, sigma_z=None, av=None, delta=None, bump=None):
+              lgmet=None, sigma_z=None, av=None, delta=None, bump=None, lgmet_old=None):
     """Differentiable magnitudes; tensors not given are taken from `pop`."""
     return DspsMags.apply(ssp, filters, cosmo, pop.t_table,
                           sfh_params if sfh_params is not None else pop.sfh_params,
@@ -62,7 +67,8 @@ def dsps_mags(ssp, filters, cosmo, pop: api.DevicePopulation, sfh_params=None, s
                           lgmet if lgmet is not None else pop.lgmet,
                           sigma_z if sigma_z is not None else pop.sigma_z,
                           av if av is not None else pop.av, delta if delta is not None else pop.delta,
-                          bump if bump is not None else pop.bump, pop.lgmet_slope, pop.lg_age_pivot)
+                          bump if bump is not None else pop.bump, pop.lgmet_slope, pop.lg_age_pivot,
+                          lgmet_old if lgmet_old is not None else pop.lgmet_old, pop.mdf_width)
 
 
 class PopSummary(torch.autograd.Function):

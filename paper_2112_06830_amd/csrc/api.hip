@@ -445,6 +445,8 @@ static int check_pop(const dsps_pop *p, bool need_dust) {
   if (need_dust) DSPS_CHECK(p->av && p->delta && p->bump, DSPS_ERR_ARG, "av, delta and bump are required");
   DSPS_CHECK(std::isfinite(p->lgmet_slope) && std::isfinite(p->lg_age_pivot), DSPS_ERR_ARG,
              "lgmet_slope and lg_age_pivot must be finite");
+  DSPS_CHECK(!p->lgmet_old || (std::isfinite(p->mdf_width) && p->mdf_width > 0.0), DSPS_ERR_ARG,
+             "mdf_width must be finite and > 0 with lgmet_old, got %g", p->mdf_width);
   return DSPS_OK;
 }
 
@@ -472,6 +474,8 @@ static int sort_population(const dsps_ssp *ssp, const dsps_pop *p, int *hist, in
   s.n_gal = p->n_gal;
   s.slope = p->lgmet_slope;
   s.pivot = p->lg_age_pivot;
+  s.lgmet_old = p->lgmet_old;
+  s.mdf_width = p->mdf_width;
   s.lg_age_first = ssp->lg_age_first;
   s.lg_age_last = ssp->lg_age_last;
   s.met_edges = ssp->v.met_edges;
@@ -492,6 +496,8 @@ static WeightsLaunch base_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, 
   a.n_t = p->n_t;
   a.slope = p->lgmet_slope;
   a.pivot = p->lg_age_pivot;
+  a.lgmet_old = p->lgmet_old;
+  a.mdf_width = p->mdf_width;
   a.cosmo = make_cosmo(*cosmo);
   a.gl = gauss_legendre16();
   a.ssp = ssp->v;
@@ -699,8 +705,8 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
 int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
                   const dsps_pop *pop, int precision, const float *mags_bar, const float *bands,
                   const float *moments, double *sfr_bar, double *sfh_params_bar, float *lgmet_bar,
-                  float *sigma_bar, float *av_bar, float *delta_bar, float *bump_bar,
-                  void *workspace, size_t workspace_bytes, hipStream_t stream) {
+                  float *lgmet_old_bar, float *sigma_bar, float *av_bar, float *delta_bar,
+                  float *bump_bar, void *workspace, size_t workspace_bytes, hipStream_t stream) {
   DSPS_CHECK(ssp && filters, DSPS_ERR_ARG, "ssp or filters is NULL");
   DSPS_TRY(check_cosmo(cosmo));
   DSPS_TRY(check_pop(pop, true));
@@ -712,6 +718,8 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
              "bands and moments must be given together or both be NULL");
   DSPS_CHECK(!sfh_params_bar || pop->sfh_params, DSPS_ERR_ARG,
              "sfh_params_bar requires the population to carry sfh_params");
+  DSPS_CHECK(!lgmet_old_bar || pop->lgmet_old, DSPS_ERR_ARG,
+             "lgmet_old_bar requires the population to carry lgmet_old");
   DSPS_TRY(check_device(ssp->device));
   DSPS_CHECK(filters->device == ssp->device, DSPS_ERR_ARG, "ssp and filters on different devices");
   const int n_band = filters->v.n_band;
@@ -772,6 +780,9 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
     v.n_t = pop->n_t;
     v.slope = pop->lgmet_slope;
     v.pivot = pop->lg_age_pivot;
+    v.lgmet_old = pop->lgmet_old;
+    v.mdf_width = pop->mdf_width;
+    v.lgmet_old_bar = lgmet_old_bar;
     v.cosmo = make_cosmo(*cosmo);
     v.gl = gauss_legendre16();
     v.sfr_bar = sfr_bar;

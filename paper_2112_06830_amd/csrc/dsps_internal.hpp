@@ -129,6 +129,19 @@ __device__ __forceinline__ double triweight_cdf(double z) {
   return 0.5 + z * p;
 }
 
+// MDF centre at log10 age a (Section 3.2.2, Eq. agedep_mdf): linear in log
+// age, or, given an old-age centre, the cumulative-triweight transition from
+// the young value lgmet to it over +-3 widths around the pivot.
+__device__ __forceinline__ double mdf_transition(double a, double pivot, double width) {
+  return triweight_cdf((a - pivot) / width);
+}
+__device__ __forceinline__ double mdf_centre(double a, double lgmet, bool transition,
+                                             double lgmet_old, double slope, double pivot,
+                                             double width) {
+  return transition ? lgmet + (lgmet_old - lgmet) * mdf_transition(a, pivot, width)
+                    : lgmet + slope * (a - pivot);
+}
+
 __device__ __forceinline__ double triweight_pdf(double z) {
   if (z <= -3.0 || z >= 3.0) return 0.0;
   const double u = 1.0 - z * z * (1.0 / 9.0);
@@ -214,6 +227,8 @@ struct WeightsLaunch {
   const float *z, *lgmet, *sigma_z, *av, *delta, *bump;
   int n_gal, n_t;
   double slope, pivot;
+  const float *lgmet_old;    // transition MDF (old-age centre), or null (linear model)
+  double mdf_width;
   CosmoArgs cosmo;
   GaussLegendre gl;
   SspView ssp;
@@ -240,8 +255,9 @@ int launch_sfh_table(const double *t_table, int n_t, const double *params, int n
 // Counting sort of galaxies by (metallicity-row range, redshift bucket).
 struct SortLaunch {
   const float *z, *lgmet, *sigma_z;
+  const float *lgmet_old;    // transition MDF, or null (linear model)
   int n_gal;
-  double slope, pivot, lg_age_first, lg_age_last;
+  double slope, pivot, mdf_width, lg_age_first, lg_age_last;
   const double *met_edges;   // [n_met + 1], device
   int n_met;
   int *hist;                 // [SORT_BINS] scratch
@@ -344,6 +360,9 @@ struct VjpLaunch {
   // outputs (by galaxy index; any may be null)
   double *sfr_bar, *sfh_params_bar;
   float *lgmet_bar, *sigma_bar, *av_bar, *delta_bar, *bump_bar;
+  const float *lgmet_old;     // transition MDF, or null (linear model)
+  double mdf_width;
+  float *lgmet_old_bar;
 };
 int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream);
 

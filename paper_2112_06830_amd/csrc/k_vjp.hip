@@ -285,16 +285,23 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
 
   // ---- Wbar -> metallicity-weight and age-mass cotangents
   const double lgmet = (double)a.lgmet[g];
+  const bool transition = a.lgmet_old != nullptr;
+  const double lgmet_old = transition ? (double)a.lgmet_old[g] : 0.0;
   const double sig = (double)a.sigma_z[g];
   const double inv_sig = 1.0 / sig;
   const float *wb = a.wbar + (size_t)local * P.k_pad;
-  double d_lgmet = 0.0, d_sig = 0.0;
+  // d mu_i / d lgmet = 1 - T_i and d mu_i / d lgmet_old = T_i under the
+  // transition model (T_i its cumulative triweight at age i), 1 and 0 under
+  // the linear one
+  double d_lgmet = 0.0, d_old = 0.0, d_sig = 0.0;
   // wb holds Y[j] = Wbar[j] - Wbar[j-1] (Y[0] = Wbar[0]) from the
   // metallicity-differenced table.  Bin j spans edges j and j+1,
   // P_j = C(u_{j+1}) - C(u_j); the cotangent of the CDF at an interior edge j
   // is Pbar_{j-1} - Pbar_j = -m_age Y[j], and m_age_bar = sum_j Wbar[j] P_j.
   for (int i = lane; i < n_age; i += 64) {
-    const double mu = lgmet + a.slope * (P.lg_age[i] - a.pivot);
+    const double mu = mdf_centre(P.lg_age[i], lgmet, transition, lgmet_old, a.slope, a.pivot,
+                                 a.mdf_width);
+    const double t_i = transition ? mdf_transition(P.lg_age[i], a.pivot, a.mdf_width) : 0.0;
     const double m_i = mage[i];
     double mb = 0.0, wcum = 0.0;
     double c_lo = 0.0, u_lo = 0.0;    // CDF and u at edge j (the lower edge of bin j)
@@ -303,7 +310,8 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
       wcum += y;                       // Wbar[j]
       if (j >= 1) {
         const double ubar = -m_i * y * triweight_pdf(u_lo);
-        d_lgmet -= ubar * inv_sig;
+        d_lgmet -= ubar * inv_sig * (1.0 - t_i);
+        d_old -= ubar * inv_sig * t_i;
         d_sig -= ubar * u_lo * inv_sig;
       }
       double c_hi = 1.0, u_hi = 0.0;   // upper edge of the last bin is +inf
@@ -318,6 +326,7 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
     mbar[i] = mb;
   }
   d_lgmet = wave_sum(d_lgmet);
+  d_old = wave_sum(d_old);
   d_sig = wave_sum(d_sig);
   wave_sync_v();
 
@@ -386,6 +395,7 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
 
   if (lane == 0) {
     if (a.lgmet_bar) a.lgmet_bar[g] = (float)d_lgmet;
+    if (a.lgmet_old_bar) a.lgmet_old_bar[g] = (float)d_old;
     if (a.sigma_bar) a.sigma_bar[g] = (float)d_sig;
     const float *p = a.dust + (size_t)local * 3;
     const double sk = p[0], spw = p[1], sd = p[2];

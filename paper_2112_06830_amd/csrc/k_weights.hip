@@ -281,6 +281,8 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   // every per-galaxy load is issued before the first use of any of them
   const double t_obs = a.t_obs[s];
   const float lgmet_f = a.lgmet[g], sig_f = a.sigma_z[g];
+  const bool transition = a.lgmet_old != nullptr;
+  const double lgmet_old = transition ? (double)a.lgmet_old[g] : 0.0;
   const double *row = TABULATED ? a.sfr + (size_t)g * n_t : nullptr;
   // SFR at nodes base + SFR_PER_LANE lane + k of the next round to be summed
   // and at the first node of the round after it (a tabulated row's first
@@ -412,8 +414,10 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   // of every metallicity row as one 4-byte (bf16) or 8-byte (float32) store
   const double lgmet = (double)lgmet_f;
   const double inv_sig = 1.0 / (double)sig_f;
-  const double mu0 = real0 ? lgmet + a.slope * (s_lgage[i0] - a.pivot) : 0.0;
-  const double mu1 = real1 ? lgmet + a.slope * (s_lgage[i0 + 1] - a.pivot) : 0.0;
+  const double mu0 = real0 ? mdf_centre(s_lgage[i0], lgmet, transition, lgmet_old, a.slope,
+                                        a.pivot, a.mdf_width) : 0.0;
+  const double mu1 = real1 ? mdf_centre(s_lgage[i0 + 1], lgmet, transition, lgmet_old, a.slope,
+                                        a.pivot, a.mdf_width) : 0.0;
   const MdfLane L{s_medge, s_ks, n_met, n_age, i0, mu0, mu1, inv_sig, mage0, mage1, real0, real1};
   unsigned nzr;   // metallicity rows in which either of the lane's ages has a non-zero weight
   if (a.w_pad && a.w_pad_bf16)
@@ -484,8 +488,12 @@ __device__ __forceinline__ int sort_key(const SortLaunch &a, int g) {
     zb = v >= 31.0f ? 31 : (int)v;
   }
   const double lgmet = (double)a.lgmet[g], three_sig = 3.0 * (double)a.sigma_z[g];
-  const double m0 = lgmet + a.slope * (a.lg_age_first - a.pivot);
-  const double m1 = lgmet + a.slope * (a.lg_age_last - a.pivot);
+  // the centre is monotone in age under both models: its extremes sit at the
+  // youngest and oldest ages
+  const bool transition = a.lgmet_old != nullptr;
+  const double old = transition ? (double)a.lgmet_old[g] : 0.0;
+  const double m0 = mdf_centre(a.lg_age_first, lgmet, transition, old, a.slope, a.pivot, a.mdf_width);
+  const double m1 = mdf_centre(a.lg_age_last, lgmet, transition, old, a.slope, a.pivot, a.mdf_width);
   const double lo = fmin(m0, m1) - three_sig, hi = fmax(m0, m1) + three_sig;
   int jlo = 0, jhi = 0;
   for (int j = 1; j < a.n_met; ++j) {       // bin j starts at interior edge j

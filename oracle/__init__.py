@@ -16,7 +16,8 @@ of zero weights), written step by step in the paper's order:
   kernels     triweight kernel and its cumulative T_erf (Appendix B)
   mdf         age-dependent metallicity weights (Section 3.2.2, Eq. agedep_mdf)
   dust        Salim-type attenuation with a Drude bump (Section 3.4,
-              Eqs. attenuation, salim, kzero, uvbump)
+              Eqs. attenuation, salim, kzero, uvbump), and its age-dependent
+              form (Section 3.4.1, Eq. agedep_dust_csp)
   photometry  redshifted filter integrals and AB magnitudes (Section 2.2.1,
               Eq. restmag)
   pipeline    weights, SEDs, magnitudes and BF16 quantisation of the SSP block

@@ -65,6 +65,8 @@ def mags_vjp(inp: OracleInputs, mags_bar):
       (d mu_i / d lgmet = 1 - T_i and d mu_i / d lgmet_old = T_i with
       T_i = T_erf((log10 tau_i - pivot) / width)).
     """
+    if inp.av_old is not None:
+        raise NotImplementedError("the adjoint of the age-dependent attenuation is not written")
     mags_bar = np.atleast_2d(np.asarray(mags_bar, dtype=np.float64))
     n_gal = inp.n_gal
     n_met, n_age, n_wave = inp.lum.shape

@@ -1,4 +1,5 @@
-"""Dust attenuation (Section 3.4, Eqs. attenuation, salim, kzero, uvbump).
+"""Dust attenuation (Section 3.4, Eqs. attenuation, salim, kzero, uvbump) and
+its dependence on stellar age (Section 3.4.1, Eq. agedep_dust_csp).
 
 Test infrastructure (see the package docstring).
 
@@ -21,6 +22,14 @@ Readings:
   * The coefficients of the two k0 curves come from the cited publications
     (Calzetti et al. 2000, Eq. 4; Leitherer et al. 2002, Eq. 14), not from the
     paper's text.
+  * Age-dependent attenuation: A_V and delta move from their young-star
+    values (the per-galaxy av, delta) to old-star values (av_old, delta_old)
+    through the cumulative triweight of log10 age, X_i = X_young + (X_old -
+    X_young) T_erf((log10 tau_i - pivot) / width) (Appendix B, Eq. terf).  The
+    paper names neither the centre nor the width; the default centre is
+    log10 tau = 7 (10 Myr, the birth-cloud time scale of the model it cites)
+    and the width a population-wide scalar.  The bump amplitude stays
+    age-independent: the paper lets only A_V and delta vary.
 """
 
 from __future__ import annotations
@@ -68,6 +77,17 @@ def k_lambda(lam_angstrom, delta, bump, reading: str = "salim"):
     delta = np.atleast_1d(np.asarray(delta, dtype=np.float64))[:, None]
     bump = np.atleast_1d(np.asarray(bump, dtype=np.float64))[:, None]
     return k0(lam, reading) * (lam / LAMBDA_V_ANGSTROM) ** delta + drude_bump(lam, bump)
+
+
+def age_dependent_parameters(av, delta, av_old, delta_old, lg_age, pivot, width):
+    """(A_V[g, i], delta[g, i]) of the age-dependent attenuation (Section
+    3.4.1): each moves from its young-star value to its old-star value with
+    T_erf((log10 tau_i - pivot) / width)."""
+    from .kernels import triweight_blend, triweight_cdf
+    t = triweight_cdf((np.asarray(lg_age, dtype=np.float64) - pivot) / width)[None, :]
+    col = lambda v: np.atleast_1d(np.asarray(v, dtype=np.float64))[:, None]
+    return (triweight_blend(col(av), col(av_old), t),
+            triweight_blend(col(delta), col(delta_old), t))
 
 
 def attenuation(lam_angstrom, av, delta, bump, reading: str = "salim"):

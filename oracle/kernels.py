@@ -38,6 +38,16 @@ def triweight_cdf(z):
     return out
 
 
+def triweight_blend(young, old, t):
+    """young + (old - young) t for a transition weight t = T_erf(...), taken
+    as old where t is exactly 1: both asymptotes are then reproduced exactly,
+    and so is a value that does not change (old = young)."""
+    young = np.asarray(young, dtype=np.float64)
+    old = np.asarray(old, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    return np.where(t == 1.0, old, young + (old - young) * t)
+
+
 def triweight_cdf_x(x, mu, sigma):
     """T_erf(x | mu, sigma) = T_erf((x - mu)/sigma), with +-inf handled."""
     x = np.asarray(x, dtype=np.float64)

@@ -29,7 +29,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .kernels import triweight_cdf, triweight_cdf_x
+from .kernels import triweight_blend, triweight_cdf, triweight_cdf_x
 
 
 def met_bin_edges(lgz):
@@ -59,7 +59,7 @@ def mdf_centres(lgmet, lg_age, slope, pivot, lgmet_old=None, width=None):
         return lgmet[:, None] + slope * (a[None, :] - pivot)
     old = np.atleast_1d(np.asarray(lgmet_old, dtype=np.float64))
     t = transition_weight(a, pivot, width)
-    return lgmet[:, None] + (old - lgmet)[:, None] * t[None, :]
+    return triweight_blend(lgmet[:, None], old[:, None], t[None, :])
 
 
 def mdf_weights(lgmet, sigma, lgz, lg_age, slope=0.1, pivot=9.0, lgmet_old=None, width=None):

@@ -46,6 +46,10 @@ class OracleInputs:
     lg_age_pivot: float = 9.0
     lgmet_old: np.ndarray | None = None   # transition MDF: old-age centre per galaxy
     mdf_width: float = 0.5                # transition width in dex
+    av_old: np.ndarray | None = None      # age-dependent dust: old-star A_V and delta
+    delta_old: np.ndarray | None = None
+    dust_pivot: float = 7.0               # its transition centre (log10 yr) and width (dex)
+    dust_width: float = 0.25
     om0: float = 0.3
     h: float = 0.7
     w0: float = -1.0
@@ -61,8 +65,9 @@ class OracleInputs:
         kw = dict(self.__dict__)
         for name in ("sfr", "z", "lgmet", "sigma_z", "av", "delta", "bump"):
             kw[name] = getattr(self, name)[idx]
-        if self.lgmet_old is not None:
-            kw["lgmet_old"] = self.lgmet_old[idx]
+        for name in ("lgmet_old", "av_old", "delta_old"):
+            if getattr(self, name) is not None:
+                kw[name] = getattr(self, name)[idx]
         if self.sfh_params is not None:
             kw["sfh_params"] = self.sfh_params[:, idx]
         return OracleInputs(**kw)
@@ -87,6 +92,11 @@ def prepare_inputs(ssp, filters, pop, sfr=None, om0=0.3, h=0.7, w0=-1.0,
         lgmet_old=(None if getattr(pop, "lgmet_old", None) is None
                    else np.asarray(pop.lgmet_old, np.float64)),
         mdf_width=float(getattr(pop, "mdf_width", 0.5)),
+        av_old=(None if getattr(pop, "av_old", None) is None else np.asarray(pop.av_old, np.float64)),
+        delta_old=(None if getattr(pop, "delta_old", None) is None
+                   else np.asarray(pop.delta_old, np.float64)),
+        dust_pivot=float(getattr(pop, "dust_pivot", 7.0)),
+        dust_width=float(getattr(pop, "dust_width", 0.25)),
         om0=om0, h=h, w0=w0, k0_reading=k0_reading,
         sfh_params=np.asarray(pop.sfh_params, np.float64))
 
@@ -113,6 +123,8 @@ def sed(inp: OracleInputs, apply_dust: bool = False, block: int = 256):
     n_met, n_age, n_wave = inp.lum.shape
     table = inp.lum.reshape(n_met * n_age, n_wave)
     out = np.empty((inp.n_gal, n_wave))
+    if apply_dust and inp.av_old is not None:
+        return _sed_age_dependent_dust(inp)
     for s in range(0, inp.n_gal, block):
         sub = inp.subset(np.arange(s, min(s + block, inp.n_gal)))
         w = weights(sub).reshape(sub.n_gal, n_met * n_age)
@@ -120,6 +132,24 @@ def sed(inp: OracleInputs, apply_dust: bool = False, block: int = 256):
         if apply_dust:
             spec = spec * dust.attenuation(inp.wave, sub.av, sub.delta, sub.bump, inp.k0_reading)
         out[s:s + sub.n_gal] = spec
+    return out
+
+
+def _sed_age_dependent_dust(inp: OracleInputs, block: int = 8):
+    """Eq. agedep_dust_csp: the attenuation moves inside the sum over ages,
+    L(lambda) = sum_i F_att(lambda | tau_i) sum_j W[j, i] L_SSP[j, i, lambda],
+    with A_V and delta of age i from dust.age_dependent_parameters."""
+    out = np.empty((inp.n_gal, inp.lum.shape[2]))
+    for s in range(0, inp.n_gal, block):
+        sub = inp.subset(np.arange(s, min(s + block, inp.n_gal)))
+        w = weights(sub)                                                     # [g, j, i]
+        per_age = np.einsum("gji,jil->gil", w, inp.lum)                      # [g, i, l]
+        av_i, delta_i = dust.age_dependent_parameters(
+            sub.av, sub.delta, sub.av_old, sub.delta_old, inp.lg_age, inp.dust_pivot, inp.dust_width)
+        for r in range(sub.n_gal):
+            f = dust.attenuation(inp.wave, av_i[r], delta_i[r], np.full(av_i.shape[1], sub.bump[r]),
+                                 inp.k0_reading)                             # [i, l]
+            out[s + r] = np.sum(f * per_age[r], axis=0)
     return out
 
 

@@ -135,10 +135,15 @@ __device__ __forceinline__ double triweight_cdf(double z) {
 __device__ __forceinline__ double mdf_transition(double a, double pivot, double width) {
   return triweight_cdf((a - pivot) / width);
 }
+// young + (old - young) t, taken as old where t is exactly 1, so that both
+// asymptotes, and an unchanged value, come out exactly.
+__device__ __forceinline__ double triweight_blend(double young, double old, double t) {
+  return t == 1.0 ? old : young + (old - young) * t;
+}
 __device__ __forceinline__ double mdf_centre(double a, double lgmet, bool transition,
                                              double lgmet_old, double slope, double pivot,
                                              double width) {
-  return transition ? lgmet + (lgmet_old - lgmet) * mdf_transition(a, pivot, width)
+  return transition ? triweight_blend(lgmet, lgmet_old, mdf_transition(a, pivot, width))
                     : lgmet + slope * (a - pivot);
 }
 

@@ -55,6 +55,10 @@ class Population:
     lg_age_pivot: float = 9.0
     lgmet_old: np.ndarray | None = None
     mdf_width: float = 0.5
+    av_old: np.ndarray | None = None
+    delta_old: np.ndarray | None = None
+    dust_pivot: float = 7.0
+    dust_width: float = 0.25
     seed: int = 0
     meta: dict = field(default_factory=dict)
 
@@ -76,7 +80,11 @@ class Population:
             targets=self.targets[idx].copy(), lgmet_slope=self.lgmet_slope,
             lg_age_pivot=self.lg_age_pivot,
             lgmet_old=None if self.lgmet_old is None else self.lgmet_old[idx].copy(),
-            mdf_width=self.mdf_width, seed=self.seed, meta=dict(self.meta))
+            mdf_width=self.mdf_width,
+            av_old=None if self.av_old is None else self.av_old[idx].copy(),
+            delta_old=None if self.delta_old is None else self.delta_old[idx].copy(),
+            dust_pivot=self.dust_pivot, dust_width=self.dust_width,
+            seed=self.seed, meta=dict(self.meta))
 
 
 def make_time_grid(n_t: int) -> np.ndarray:
@@ -86,7 +94,8 @@ def make_time_grid(n_t: int) -> np.ndarray:
 def make_population(n_gal: int, n_t: int = 100, z_range=(0.1, 1.0), seed: int = 2,
                     n_band: int = 6, lgmet_slope: float = 0.1,
                     lg_age_pivot: float = 9.0, mdf: str = "linear",
-                    mdf_width: float = 0.5) -> Population:
+                    mdf_width: float = 0.5, age_dust: bool = False,
+                    dust_pivot: float = 7.0, dust_width: float = 0.25) -> Population:
     """Draw a population with the parameter distributions of the workloads.
 
     log10 A ~ U[0, 2], tau ~ U[1, 5] Gyr, alpha ~ U[0.5, 3], q ~ U[0, 1],
@@ -96,6 +105,9 @@ def make_population(n_gal: int, n_t: int = 100, z_range=(0.1, 1.0), seed: int = 
     old-age centre lgmet_old = lgmet - U[0, 0.6] (older stars more metal-poor)
     for the T_erf transition model, drawn from its own stream so the other
     parameters are those of the linear model with the same seed.
+    age_dust=True adds old-star attenuation parameters for the age-dependent
+    dust model: A_V,old = A_V * U[0.2, 0.6] (young stars sit behind more dust)
+    and delta_old = U[-0.7, 0.3], from their own stream.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     n = int(n_gal)
@@ -119,7 +131,14 @@ def make_population(n_gal: int, n_t: int = 100, z_range=(0.1, 1.0), seed: int = 
         lgmet_old = _f32(lgmet - mrng.uniform(0.0, 0.6, n))
     elif mdf != "linear":
         raise ValueError(f"unknown mdf model {mdf!r}")
+    av_old = delta_old = None
+    if age_dust:
+        drng = np.random.Generator(np.random.PCG64(seed + 3000003))
+        av_old = _f32(av * drng.uniform(0.2, 0.6, n))
+        delta_old = _f32(drng.uniform(-0.7, 0.3, n))
     return Population(t_table=make_time_grid(n_t), sfh_params=np.ascontiguousarray(sfh_params),
                       z=z, lgmet=lgmet, sigma_z=sigma_z, av=av, delta=delta, bump=bump,
                       targets=targets, lgmet_slope=lgmet_slope, lg_age_pivot=lg_age_pivot,
-                      lgmet_old=lgmet_old, mdf_width=float(mdf_width), seed=seed)
+                      lgmet_old=lgmet_old, mdf_width=float(mdf_width), av_old=av_old,
+                      delta_old=delta_old, dust_pivot=float(dust_pivot),
+                      dust_width=float(dust_width), seed=seed)

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define DSPS_ABI_VERSION 3
+#define DSPS_ABI_VERSION 4
 
 typedef enum {
   DSPS_OK = 0,
@@ -70,6 +70,9 @@ typedef enum { DSPS_FP32 = 0, DSPS_BF16 = 1 } dsps_precision;
  * at and above it (the order of the cited Salim et al. parameterisation).
  * DSPS_K0_PRINTED: the order printed in Eq. kzero (Calzetti below). */
 typedef enum { DSPS_K0_SALIM = 0, DSPS_K0_PRINTED = 1 } dsps_k0_reading;
+
+/* Extra bit of dsps_ssp_create's precisions mask (see there). */
+#define DSPS_SSP_AGE_MAJOR 4
 
 typedef enum {
   DSPS_OP_WEIGHTS = 0, DSPS_OP_SED = 1, DSPS_OP_MAGS = 2, DSPS_OP_MAGS_VJP = 3
@@ -98,7 +101,10 @@ typedef enum {
  *   wave   HOST [n_wave]   rest-frame wavelength in Angstrom, strictly ascending
  *   lum    HOST [n_met*n_age*n_wave] float32, L_sun/Hz per M_sun formed, row
  *                          (met, age) major, finite and >= 0
- *   precisions             bit mask of (1 << DSPS_FP32) | (1 << DSPS_BF16)
+ *   precisions             bit mask of (1 << DSPS_FP32) | (1 << DSPS_BF16),
+ *                          optionally | DSPS_SSP_AGE_MAJOR: also an age-major
+ *                          float32 copy, which dsps_mags needs for the
+ *                          age-dependent attenuation (dsps_pop.av_old)
  *   k0_reading             dsps_k0_reading
  *   out                    receives the handle; unchanged on failure
  * Allocates device memory (the only allocating call besides
@@ -155,6 +161,16 @@ typedef struct { double om0, w0, h; } dsps_cosmo;
  *               and lgmet_slope is unused
  *   mdf_width   transition width in dex (> 0, finite) when lgmet_old is set;
  *               the transition spans +-3 widths around lg_age_pivot
+ *   av_old, delta_old  [n_gal] old-star attenuation parameters, both or
+ *               neither.  When set, the attenuation depends on stellar age
+ *               (Section 3.4.1, Eq. agedep_dust_csp): A_V and delta of age
+ *               tau are av + (av_old - av) T_erf((log10 tau - dust_pivot) /
+ *               dust_width) (the old values where T_erf is 1), and likewise
+ *               for delta; bump stays age-independent.  Only dsps_mags
+ *               supports it (float32, on an SSP handle created with
+ *               DSPS_SSP_AGE_MAJOR); dsps_sed and dsps_mags_vjp return
+ *               DSPS_ERR_UNSUPPORTED.
+ *   dust_pivot, dust_width  transition centre (log10 yr) and width (dex, > 0)
  * ------------------------------------------------------------------------ */
 typedef struct {
   int n_gal, n_t;
@@ -165,6 +181,8 @@ typedef struct {
   double lgmet_slope, lg_age_pivot;
   const float *lgmet_old;
   double mdf_width;
+  const float *av_old, *delta_old;
+  double dust_pivot, dust_width;
 } dsps_pop;
 
 /* Workspace bytes a call of kind `op` needs for this population shape and

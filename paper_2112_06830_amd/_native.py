@@ -49,7 +49,12 @@ class Pop(ctypes.Structure):
         ("av", ctypes.c_void_p), ("delta", ctypes.c_void_p), ("bump", ctypes.c_void_p),
         ("lgmet_slope", ctypes.c_double), ("lg_age_pivot", ctypes.c_double),
         ("lgmet_old", ctypes.c_void_p), ("mdf_width", ctypes.c_double),
+        ("av_old", ctypes.c_void_p), ("delta_old", ctypes.c_void_p),
+        ("dust_pivot", ctypes.c_double), ("dust_width", ctypes.c_double),
     ]
+
+
+SSP_AGE_MAJOR = 4   # dsps_ssp_create: also the age-major float32 table
 
 
 _LIB = None

@@ -51,7 +51,10 @@ def _workspace(nbytes: int, device) -> tuple[torch.Tensor | None, int]:
 class SspBlock:
     """Resident SSP block (dsps_ssp_create)."""
 
-    def __init__(self, lgz, lg_age, wave, lum, precisions=("fp32", "bf16"), k0_reading="salim"):
+    def __init__(self, lgz, lg_age, wave, lum, precisions=("fp32", "bf16"), k0_reading="salim",
+                 age_major=False):
+        """age_major also prepares the age-major float32 table that the
+        age-dependent attenuation needs (dsps_pop.av_old)."""
         lgz = np.ascontiguousarray(lgz, dtype=np.float64)
         lg_age = np.ascontiguousarray(lg_age, dtype=np.float64)
         wave = np.ascontiguousarray(wave, dtype=np.float64)
@@ -59,7 +62,7 @@ class SspBlock:
         n_met, n_age, n_wave = lgz.size, lg_age.size, wave.size
         if lum.size != n_met * n_age * n_wave:
             raise ValueError("lum has the wrong size")
-        mask = 0
+        mask = N.SSP_AGE_MAJOR if age_major else 0
         for p in precisions:
             mask |= 1 << _PREC[p]
         torch.cuda.init()
@@ -146,6 +149,10 @@ class DevicePopulation:
     lg_age_pivot: float = 9.0
     lgmet_old: torch.Tensor | None = None   # transition MDF: old-age centre, float32
     mdf_width: float = 0.5
+    av_old: torch.Tensor | None = None      # age-dependent attenuation: old-star A_V, delta
+    delta_old: torch.Tensor | None = None
+    dust_pivot: float = 7.0
+    dust_width: float = 0.25
 
     @property
     def n_gal(self):
@@ -163,7 +170,8 @@ class DevicePopulation:
         return N.Pop(self.n_gal, self.n_t, _ptr(self.t_table), _ptr(self.sfr), _ptr(self.sfh_params),
                      _ptr(self.z), _ptr(self.lgmet), _ptr(self.sigma_z), _ptr(self.av),
                      _ptr(self.delta), _ptr(self.bump), self.lgmet_slope, self.lg_age_pivot,
-                     _ptr(self.lgmet_old), self.mdf_width)
+                     _ptr(self.lgmet_old), self.mdf_width, _ptr(self.av_old), _ptr(self.delta_old),
+                     self.dust_pivot, self.dust_width)
 
     @classmethod
     def from_synth(cls, pop, device="cuda", sfr=None, use_params=False):
@@ -184,12 +192,18 @@ class DevicePopulation:
                    lg_age_pivot=float(pop.lg_age_pivot),
                    lgmet_old=(None if getattr(pop, "lgmet_old", None) is None
                               else f32(pop.lgmet_old)),
-                   mdf_width=float(getattr(pop, "mdf_width", 0.5)))
+                   mdf_width=float(getattr(pop, "mdf_width", 0.5)),
+                   av_old=(None if getattr(pop, "av_old", None) is None else f32(pop.av_old)),
+                   delta_old=(None if getattr(pop, "delta_old", None) is None
+                              else f32(pop.delta_old)),
+                   dust_pivot=float(getattr(pop, "dust_pivot", 7.0)),
+                   dust_width=float(getattr(pop, "dust_width", 0.25)))
 
     def with_sfr(self, sfr):
         return DevicePopulation(self.t_table, sfr, None, self.z, self.lgmet, self.sigma_z, self.av,
                                 self.delta, self.bump, self.lgmet_slope, self.lg_age_pivot,
-                                self.lgmet_old, self.mdf_width)
+                                self.lgmet_old, self.mdf_width, self.av_old, self.delta_old,
+                                self.dust_pivot, self.dust_width)
 
 
 def workspace_size(op: int, ssp: SspBlock, filters: FilterBank | None, n_gal: int, n_t: int,

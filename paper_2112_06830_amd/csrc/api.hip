@@ -154,7 +154,8 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   DSPS_CHECK(n_met >= 1 && n_met <= DSPS_MAX_MET, DSPS_ERR_SHAPE, "n_met %d outside [1, %d]", n_met, DSPS_MAX_MET);
   DSPS_CHECK(n_age >= 1 && n_age <= DSPS_MAX_AGE, DSPS_ERR_SHAPE, "n_age %d outside [1, %d]", n_age, DSPS_MAX_AGE);
   DSPS_CHECK(n_wave >= 2, DSPS_ERR_SHAPE, "n_wave %d < 2", n_wave);
-  DSPS_CHECK(precisions >= 1 && precisions <= 3, DSPS_ERR_ARG, "precisions mask %d invalid", precisions);
+  DSPS_CHECK((precisions & 3) >= 1 && (precisions & ~(3 | DSPS_SSP_AGE_MAJOR)) == 0, DSPS_ERR_ARG,
+             "precisions mask %d invalid", precisions);
   DSPS_CHECK(k0_reading == DSPS_K0_SALIM || k0_reading == DSPS_K0_PRINTED, DSPS_ERR_ARG,
              "k0_reading %d invalid", k0_reading);
   for (int j = 1; j < n_met; ++j) DSPS_CHECK(lgz[j] > lgz[j - 1], DSPS_ERR_ARG, "lgz not ascending");
@@ -175,6 +176,7 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   v.k_pad = n_met * AGE_PAD;
   const int nwp = v.n_wave_pad, kp = v.k_pad;
   const bool want32 = precisions & (1 << DSPS_FP32), want16 = precisions & (1 << DSPS_BF16);
+  const bool want_age = precisions & DSPS_SSP_AGE_MAJOR;
 
   // host-side derived tables
   std::vector<double> age_edges(n_age + 1), met_edges(n_met + 1);
@@ -207,6 +209,7 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   const size_t o_st16 = want16 ? take(sizeof(uint16_t) * (size_t)nwp * kp) : 0;
   const int sk_rows = (kp + TILE_L - 1) / TILE_L * TILE_L;
   const size_t o_sk = want32 ? take(sizeof(float) * (size_t)sk_rows * nwp) : 0;
+  const size_t o_sa = want_age ? take(sizeof(float) * (size_t)nwp * AGE_K) : 0;
   const size_t o_ks = take(sizeof(float) * kp);
   const size_t o_lc = take(sizeof(float4) * nwp);
   const size_t o_q = take(sizeof(float) * nwp);
@@ -262,6 +265,8 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
     if (want32) rc = launch_pack_table_kmajor(d_rows, n_age, n_wave, nwp, kp, sk_rows,
                                               (float *)(b + o_sk), nullptr);
     if (rc) break;
+    if (want_age) rc = launch_pack_table_age(d_rows, n_met, n_age, n_wave, nwp, (float *)(b + o_sa), nullptr);
+    if (rc) break;
     rc = hip_fail(hipDeviceSynchronize(), "SSP block preparation");
   } while (false);
   cleanup();
@@ -280,6 +285,7 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   v.qweight = (const float *)(b + o_q);
   v.sk32 = want32 ? (const float *)(b + o_sk) : nullptr;
   v.sk_rows = sk_rows;
+  v.sa32 = want_age ? (const float *)(b + o_sa) : nullptr;
   dsps_ssp *h = new dsps_ssp();
   (void)hipGetDevice(&h->device);
   h->precisions = precisions;
@@ -287,6 +293,7 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   h->wave_host.assign(wave, wave + n_wave);
   h->lg_age_first = lg_age[0];
   h->lg_age_last = lg_age[n_age - 1];
+  h->lg_age_host.assign(lg_age, lg_age + n_age);
   h->v = v;
   h->alloc = base;
   *out = h;
@@ -385,7 +392,7 @@ constexpr int BATCH_VJP = 65536;
 
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
-  size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0, tobs = 0;
+  size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0, tobs = 0, dust_old = 0;
   int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
@@ -416,7 +423,11 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   L.range = take(sizeof(GalaxyRange) * (size_t)n_gal);
   L.offset = take(sizeof(double) * (size_t)n_gal);
   L.tobs = take(sizeof(double) * (size_t)n_gal);
-  L.w = take(elem * (size_t)L.batch * v.k_pad);
+  // a handle with the age-major table may run the age-dependent attenuation,
+  // whose weight rows are AGE_K wide
+  const int w_cols = (v.sa32 && op == DSPS_OP_MAGS) ? std::max(v.k_pad, AGE_K) : v.k_pad;
+  L.w = take(elem * (size_t)L.batch * w_cols);
+  if (v.sa32 && op == DSPS_OP_MAGS) L.dust_old = take(sizeof(GalaxyDustOld) * (size_t)n_gal);
   // float32 forward passes may carry the dust moments
   const int ncomp = mags_components(precision == DSPS_FP32);
   L.partial = take(sizeof(float) * (size_t)L.batch * L.n_chunks * ncomp * n_band);
@@ -447,6 +458,11 @@ static int check_pop(const dsps_pop *p, bool need_dust) {
              "lgmet_slope and lg_age_pivot must be finite");
   DSPS_CHECK(!p->lgmet_old || (std::isfinite(p->mdf_width) && p->mdf_width > 0.0), DSPS_ERR_ARG,
              "mdf_width must be finite and > 0 with lgmet_old, got %g", p->mdf_width);
+  DSPS_CHECK((p->av_old == nullptr) == (p->delta_old == nullptr), DSPS_ERR_ARG,
+             "av_old and delta_old must be given together or both be NULL");
+  DSPS_CHECK(!p->av_old || (std::isfinite(p->dust_pivot) && std::isfinite(p->dust_width) &&
+                            p->dust_width > 0.0),
+             DSPS_ERR_ARG, "dust_pivot must be finite and dust_width finite and > 0 with av_old");
   return DSPS_OK;
 }
 
@@ -500,6 +516,8 @@ static WeightsLaunch base_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, 
   a.mdf_width = p->mdf_width;
   a.cosmo = make_cosmo(*cosmo);
   a.gl = gauss_legendre16();
+  a.av_old = p->av_old;
+  a.delta_old = p->delta_old;
   a.ssp = ssp->v;
   return a;
 }
@@ -566,6 +584,8 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, 
   DSPS_TRY(check_cosmo(cosmo));
   DSPS_TRY(check_pop(pop, apply_dust != 0));
   DSPS_CHECK(apply_dust == 0 || apply_dust == 1, DSPS_ERR_ARG, "apply_dust must be 0 or 1");
+  DSPS_CHECK(!(apply_dust && pop->av_old), DSPS_ERR_UNSUPPORTED,
+             "dsps_sed does not apply the age-dependent attenuation (dsps_mags does)");
   DSPS_TRY(check_precision(ssp, precision));
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(sed, DSPS_ERR_ARG, "sed is NULL");
@@ -641,8 +661,30 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   a.obs_lo = filters->obs_lo;
   a.obs_hi = filters->obs_hi;
   a.t_obs = (double *)(ws + L.tobs);
+  const bool age_dust = pop->av_old != nullptr;
+  if (age_dust) {
+    a.w_pad_age = 1;
+    a.dust_old = (GalaxyDustOld *)(ws + L.dust_old);
+  }
   DSPS_TRY(launch_weights(a, stream));
   MagsLaunch m{};
+  if (age_dust) {
+    // ages whose transition weight is exactly 0 (young) or 1 (old): the
+    // triweight's cumulative is 0 at or below -3 widths and 1 at or above +3
+    const std::vector<double> &ag = ssp->lg_age_host;
+    int young = 0, old = (int)ag.size();
+    for (int i = 0; i < (int)ag.size(); ++i) {
+      const double zt = (ag[i] - pop->dust_pivot) / pop->dust_width;
+      if (zt <= -3.0) young = i + 1;
+      if (zt >= 3.0 && old == (int)ag.size()) old = i;
+    }
+    m.age_dust = 1;
+    m.dust_old = (const GalaxyDustOld *)(ws + L.dust_old);
+    m.age_young = young;
+    m.age_old = std::max(old, young);
+    m.dust_pivot = pop->dust_pivot;
+    m.dust_width = pop->dust_width;
+  }
   m.ssp = ssp->v;
   m.flt = filters->v;
   m.precision = precision;
@@ -685,6 +727,9 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
   DSPS_TRY(check_precision(ssp, precision));
   DSPS_CHECK(!moments || precision == DSPS_FP32, DSPS_ERR_UNSUPPORTED,
              "dust moments are computed in float32 only");
+  DSPS_CHECK(!pop->av_old || (precision == DSPS_FP32 && !moments && ssp->v.sa32), DSPS_ERR_UNSUPPORTED,
+             "age-dependent attenuation needs float32, no moments and an SSP handle created with "
+             "DSPS_SSP_AGE_MAJOR");
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(mags, DSPS_ERR_ARG, "mags is NULL");
   DSPS_TRY(check_device(ssp->device));
@@ -712,6 +757,8 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
   DSPS_TRY(check_pop(pop, true));
   DSPS_TRY(check_precision(ssp, precision));
   DSPS_CHECK(precision == DSPS_FP32, DSPS_ERR_UNSUPPORTED, "the adjoint runs in float32 only");
+  DSPS_CHECK(!pop->av_old, DSPS_ERR_UNSUPPORTED,
+             "the adjoint of the age-dependent attenuation is not available");
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(mags_bar, DSPS_ERR_ARG, "mags_bar is NULL");
   DSPS_CHECK((bands == nullptr) == (moments == nullptr), DSPS_ERR_ARG,

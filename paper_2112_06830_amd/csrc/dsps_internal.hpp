@@ -69,13 +69,20 @@ struct SspView {
   const float *qweight;            // [n_wave_pad] trapezoid weight in dlambda/lambda
   const float *sk32;               // [sk_rows][n_wave_pad] K-major, metallicity-differenced (adjoint)
   int sk_rows;                     // k_pad rounded up to a multiple of TILE_L
+  // [n_wave_pad][AGE_K] age-major float32 (age-dependent attenuation) or null:
+  // column age * 16 + met, zero for met >= n_met or age >= n_age
+  const float *sa32;
 };
+// Columns of the age-major table and weight rows: 16 metallicity slots per age.
+constexpr int AGE_MET_SLOTS = 16;
+constexpr int AGE_K = AGE_PAD * AGE_MET_SLOTS;   // 1536
 
 struct SspHandle {
   int device = -1;
   int precisions = 0;
   int k0_reading = 0;
   double lg_age_first = 0, lg_age_last = 0;
+  std::vector<double> lg_age_host;  // SSP log10 ages (host copy, for launch set-up)
   SspView v{};
   std::vector<double> wave_host;   // rest wavelengths (host copy, for launch sizing)
   void *alloc = nullptr;           // single device allocation backing every array
@@ -113,7 +120,12 @@ struct GalaxyRange {
   // bit 16 a + j (word a / 2, bit 16 (a % 2) + j) set when metallicity row j
   // has a non-zero weight at some age in [16 a, 16 a + 16)
   unsigned kblk[KBLOCK_WORDS];
-  int pad;
+  int age_hi;    // ages >= age_hi carry no weight (AGE_PAD when unknown)
+};
+// Old-star attenuation of the age-dependent model, by sorted position.
+struct GalaxyDustOld {
+  float dust_a;  // as GalaxyMeta::dust_a, for av_old
+  float delta;
 };
 
 // ------------------------------------------------------------- device math
@@ -234,6 +246,7 @@ struct WeightsLaunch {
   double slope, pivot;
   const float *lgmet_old;    // transition MDF (old-age centre), or null (linear model)
   double mdf_width;
+  const float *av_old, *delta_old;   // age-dependent attenuation, or null
   CosmoArgs cosmo;
   GaussLegendre gl;
   SspView ssp;
@@ -245,6 +258,8 @@ struct WeightsLaunch {
   double *mstar;             // [n_gal]
   void *w_pad;               // [s_count][k_pad] float32 or bf16 (by sorted position - s_begin)
   int w_pad_bf16;
+  int w_pad_age;             // w_pad is float32 age-major [s_count][AGE_K] instead
+  GalaxyDustOld *dust_old;   // [n_gal] by sorted position (age-dependent attenuation)
   GalaxyMeta *meta;          // [n_gal] by sorted position
   GalaxyRange *range;        // [n_gal] by sorted position
   double *mag_offset;        // [n_gal] D_mod(z) - 2.5 log10(1+z), by sorted position
@@ -274,6 +289,8 @@ int launch_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float 
 int launch_pack_table(const float *lum_rows, const uint16_t *q_rows, int n_met, int n_age,
                       int n_wave, int n_wave_pad, int k_pad, float *st32, uint16_t *st16,
                       hipStream_t stream);
+int launch_pack_table_age(const float *lum_rows, int n_met, int n_age, int n_wave, int n_wave_pad,
+                          float *sa32, hipStream_t stream);
 int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n_wave_pad,
                              int k_pad, int sk_rows, float *sk32, hipStream_t stream);
 
@@ -298,6 +315,13 @@ struct MagsLaunch {
   const void *w_pad;             // [s_count][k_pad]
   const GalaxyMeta *meta;        // full arrays, by sorted position
   const GalaxyRange *range;
+  // age-dependent attenuation (float32 only): W and the table are age-major,
+  // ages [0, age_young) use the young-star dust, ages [age_old, n_age) the
+  // old-star dust, the ages between their own transition values
+  int age_dust;
+  const GalaxyDustOld *dust_old;
+  int age_young, age_old;
+  double dust_pivot, dust_width;
   int n_groups;                  // workgroups per tile (upper bound on its chunk groups)
   int n_chunks;                  // n_wave_pad / TILE_L
   int moments;                   // also the three dust moments per band (float32 only)

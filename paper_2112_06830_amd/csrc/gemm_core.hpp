@@ -149,11 +149,17 @@ __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_BF16> &sm, int wr,
 // s + 1 is written to the other buffer and stage s + 2 is loaded into
 // registers, with one barrier per stage.  On entry no wave may still read
 // sm; on return every wave has passed a barrier after its last read of it.
-template <int PREC, typename KOffset>
+// after(ks) runs in every wave right after the MFMAs of stage ks (register
+// work on the accumulators only).
+struct NoStageHook {
+  __device__ void operator()(int) const {}
+};
+template <int PREC, typename KOffset, typename StageHook = NoStageHook>
 __device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const typename GemmCfg<PREC>::elem *st,
                                            int k_pad, int l0, const typename GemmCfg<PREC>::elem *w,
                                            int g0, int g_count, int nk, KOffset koff, int wr, int wc,
-                                           int lane, f32x16 (&acc)[2][2]) {
+                                           int lane, f32x16 (&acc)[2][2],
+                                           StageHook after = StageHook()) {
   StageRegs<PREC> regs;
   if (nk > 0) {
     load_stage<PREC>(regs, st, k_pad, l0, w, g0, g_count, koff(0));
@@ -163,6 +169,7 @@ __device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const typename Ge
   __syncthreads();
   for (int ks = 0; ks < nk; ++ks) {
     mma_stage(sm[ks & 1], wr, wc, lane, acc);
+    after(ks);
     if (ks + 1 < nk) {
       store_stage<PREC>(regs, sm[(ks + 1) & 1]);
       if (ks + 2 < nk) load_stage<PREC>(regs, st, k_pad, l0, w, g0, g_count, koff(ks + 2));

@@ -166,10 +166,20 @@ __device__ __forceinline__ void band_pass(const f32x16 (&acc)[2][2], const EpiLa
 }
 
 // Three workgroups per CU (at most 168 VGPRs); with the dust moments (MOM),
-// whose extra sums need more registers, two.  The cross-wave reduction buffer
-// of the epilogue reuses the operand staging area, which is idle by then.
-template <int PREC, bool MOM>
-__global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLaunch a) {
+// whose extra sums need more registers, or with age-dependent attenuation
+// (AGED), which keeps a second accumulator, two.  The cross-wave reduction
+// buffer of the epilogue reuses the operand staging area, which is idle by
+// then.
+//
+// AGED (Section 3.4.1, Eq. agedep_dust_csp): the K stages are the ages of the
+// age-major table (16 metallicity slots each), and the attenuation, which
+// depends on age, is applied per group of stages sharing one set of dust
+// parameters: the young-star ages as one group, each age of the transition on
+// its own, the old-star ages as one group.  At a group's last stage every
+// wave folds the group's partial SED into a second accumulator,
+// sed += F_att(group) * acc, and restarts acc.
+template <int PREC, bool MOM, bool AGED = false>
+__global__ __launch_bounds__(GEMM_THREADS, (MOM || AGED) ? 2 : 3) void k_mags_gemm(MagsLaunch a) {
   using C = GemmCfg<PREC>;
   using elem = typename C::elem;
   constexpr int NCOMP = MOM ? 5 : 2;
@@ -214,19 +224,27 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
 
   // ---- per-galaxy parameters of this lane's two columns
   EpiLane E;
+  float da_old[2] = {0.0f, 0.0f}, dl_old[2] = {0.0f, 0.0f};   // AGED: old-star dust
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const int col = wc * 64 + nb * 32 + (lane & 31);
     if (col < nvalid) {
       const GalaxyMeta m = a.meta[a.s_begin + g0 + col];
       E.zp1[nb] = m.zp1; E.da[nb] = m.dust_a; E.dl[nb] = m.delta; E.bp[nb] = m.bump;
+      if (AGED) {
+        const GalaxyDustOld d = a.dust_old[a.s_begin + g0 + col];
+        da_old[nb] = d.dust_a; dl_old[nb] = d.delta;
+      }
     } else {
       E.zp1[nb] = 1.0f; E.da[nb] = 0.0f; E.dl[nb] = 0.0f; E.bp[nb] = 0.0f;
     }
   }
 
-  // ---- K steps: the tile's non-zero weight blocks (s_koff)
-  const elem *st = PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16;
+  // ---- K steps: the tile's non-zero weight blocks (s_koff), or with AGED
+  // its ages
+  const elem *st = AGED ? (const elem *)P.sa32
+                        : (PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16);
+  const int k_cols = AGED ? AGE_K : P.k_pad;
   const elem *w = (const elem *)a.w_pad;
   const int n_comp = NCOMP * n_band;
 
@@ -245,8 +263,54 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
 
-    gemm_kloop<PREC>(sm, st, P.k_pad, l0, w, g0, a.s_count, nk, [&](int ks) { return s_koff[ks]; },
-                     wr, wc, lane, acc);
+    if constexpr (AGED) {
+      f32x16 sed[2][2];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) sed[mb][nb][r] = 0.0f;
+      const int age_young = a.age_young, age_old = a.age_old;
+      auto fold = [&](int ks) {
+        const bool young = ks < age_young, old = ks >= age_old;
+        const bool ends = ks == nk - 1 || (young ? ks + 1 == age_young : !old);
+        if (!ends) return;
+        // the group's transition weight: 0 young, 1 old, T_erf in between
+        const float t = young ? 0.0f
+                              : (old ? 1.0f
+                                     : (float)mdf_transition(P.lg_age[ks], a.dust_pivot, a.dust_width));
+        float da[2], dl[2];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          da[nb] = t == 1.0f ? da_old[nb] : E.da[nb] + (da_old[nb] - E.da[nb]) * t;
+          dl[nb] = t == 1.0f ? dl_old[nb] : E.dl[nb] + (dl_old[nb] - E.dl[nb]) * t;
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            const float4 lc = s_lc[row];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+              const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(dl[nb] * lc.y));
+              const float kl = fmaf(E.bp[nb], lc.w, k0x);
+              sed[mb][nb][r] = fmaf(__builtin_amdgcn_exp2f(da[nb] * kl), acc[mb][nb][r], sed[mb][nb][r]);
+              acc[mb][nb][r] = 0.0f;
+            }
+          }
+      };
+      gemm_kloop<PREC>(sm, st, k_cols, l0, w, g0, a.s_count, nk, [&](int ks) { return s_koff[ks]; },
+                       wr, wc, lane, acc, fold);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = sed[mb][nb];
+    } else {
+      gemm_kloop<PREC>(sm, st, k_cols, l0, w, g0, a.s_count, nk, [&](int ks) { return s_koff[ks]; },
+                       wr, wc, lane, acc);
+    }
     // (the loop's closing barrier makes s_lc, s_q and the filter tables visible)
 
     // ---- epilogue: attenuated SED x resampled transmission, summed over the
@@ -259,7 +323,17 @@ __global__ __launch_bounds__(GEMM_THREADS, MOM ? 2 : 3) void k_mags_gemm(MagsLau
     // partials are chunk-major: [chunk][galaxy][component]
     float *part = a.partial + ((size_t)c * a.part_rows + g0) * n_comp;
     const int stride = n_comp;
-    if (!MOM && b_lo <= b_hi) {
+    if (AGED && b_lo <= b_hi) {
+      // the attenuation is in already: e = L_att q
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float q = s_q[wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) acc[mb][nb][r] *= q;
+        }
+    } else if (!MOM && b_lo <= b_hi) {
       // e = L F_att q in place, once for all passes.  Rounding is fixed
       // explicitly, so that both instantiations agree bit for bit whatever
       // the compiler contracts.  The hardware exp2 is within 1 ulp; its only
@@ -324,13 +398,13 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
   using C = GemmCfg<PREC>;
   // window lo, window hi, min and max of (1+z) as float bits (positive floats
   // order like their bit patterns)
-  __shared__ int s_tile[4];
+  __shared__ int s_tile[5];   // + highest non-zero age (age-major stages)
   __shared__ unsigned s_kblk[KBLOCK_WORDS];
   const int tile = blockIdx.x;
   const int g0 = tile * TILE_G;
   const int nvalid = min(TILE_G, a.s_count - g0);
   if (threadIdx.x == 0) {
-    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0;
+    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0; s_tile[4] = 0;
 #pragma unroll
     for (int w = 0; w < KBLOCK_WORDS; ++w) s_kblk[w] = 0u;
   }
@@ -342,6 +416,7 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
     atomicMax(&s_tile[1], r.win_hi);
     atomicMin(&s_tile[2], zbits);
     atomicMax(&s_tile[3], zbits);
+    atomicMax(&s_tile[4], r.age_hi);
 #pragma unroll
     for (int w = 0; w < KBLOCK_WORDS; ++w)
       if (r.kblk[w]) atomicOr(&s_kblk[w], r.kblk[w]);
@@ -349,17 +424,22 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
   __syncthreads();
   if (threadIdx.x != 0) return;
   TilePlan *pl = a.plan + tile;
-  constexpr int BPS = C::KT / KBLOCK_AGES;   // blocks per stage
   int n = 0;
-  for (int j = 0; j < a.ssp.n_met; ++j)
-    for (int st = 0; st < AGE_PAD / C::KT; ++st) {
-      bool any = false;
-      for (int u = 0; u < BPS; ++u) {
-        const int blk = st * BPS + u;
-        any |= (s_kblk[blk >> 1] >> (16 * (blk & 1) + j)) & 1u;
+  if (a.age_dust) {
+    // age-major: one stage per age that holds a weight for some member
+    for (; n < min(s_tile[4], AGE_PAD); ++n) pl->koff[n] = n * AGE_MET_SLOTS;
+  } else {
+    constexpr int BPS = C::KT / KBLOCK_AGES;   // blocks per stage
+    for (int j = 0; j < a.ssp.n_met; ++j)
+      for (int st = 0; st < AGE_PAD / C::KT; ++st) {
+        bool any = false;
+        for (int u = 0; u < BPS; ++u) {
+          const int blk = st * BPS + u;
+          any |= (s_kblk[blk >> 1] >> (16 * (blk & 1) + j)) & 1u;
+        }
+        if (any) pl->koff[n++] = j * AGE_PAD + st * C::KT;
       }
-      if (any) pl->koff[n++] = j * AGE_PAD + st * C::KT;
-    }
+  }
   const int c_first = s_tile[0] / TILE_L;
   pl->c_first = c_first;
   pl->c_last = max((s_tile[1] + TILE_L - 1) / TILE_L, c_first);   // exclusive
@@ -378,7 +458,11 @@ int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
   else
     hipLaunchKernelGGL(k_tile_plan<DSPS_FP32>, dim3(n_tiles), dim3(TILE_G), 0, stream, a);
   ProfScope prof(DSPS_KERNEL_MAGS_GEMM, stream);
-  if (a.precision == DSPS_BF16) {
+  if (a.age_dust) {
+    if (a.precision != DSPS_FP32 || a.moments || !a.ssp.sa32) return DSPS_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_mags_gemm<DSPS_FP32, false, true>), dim3(blocks), dim3(GEMM_THREADS), lds,
+                       stream, a);
+  } else if (a.precision == DSPS_BF16) {
     if (a.moments) return DSPS_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((k_mags_gemm<DSPS_BF16, false>), dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);
   } else if (a.moments) {

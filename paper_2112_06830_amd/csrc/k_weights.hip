@@ -116,6 +116,12 @@ __global__ __launch_bounds__(256) void k_galaxy_scalars(WeightsLaunch a) {
     m.bump = a.bump[g];
     a.meta[s] = m;
   }
+  if (a.dust_old) {
+    GalaxyDustOld d;
+    d.dust_a = (float)(-0.4 * 3.32192809488736234787 * (double)a.av_old[g] / DUST_RV);
+    d.delta = a.delta_old[g];
+    a.dust_old[s] = d;
+  }
   // absolute magnitudes at z = 0 (Eq. restmag); distance terms beyond
   if (a.mag_offset)
     a.mag_offset[s] = z > 0.0 ? distance_modulus(z, a.cosmo, a.gl) - 2.5 * log10(1.0 + z) : 0.0;
@@ -132,7 +138,7 @@ __global__ __launch_bounds__(256) void k_galaxy_scalars(WeightsLaunch a) {
     r.win_hi = min(hi + 2, n_wave);
 #pragma unroll
     for (int w = 0; w < KBLOCK_WORDS; ++w) r.kblk[w] = ~0u;
-    r.pad = 0;
+    r.age_hi = AGE_PAD;
     a.range[s] = r;
   }
 }
@@ -233,6 +239,48 @@ __device__ __forceinline__ unsigned mdf_rows(const MdfLane &L, T *out) {
     nzr |= (nz ? 1u : 0u) << j;
   }
   return nzr;
+}
+
+// Age-major float32 rows (age-dependent attenuation): each of the lane's two
+// ages becomes 16 metallicity slots (zeros past n_met) written as four
+// 16-byte stores.  Returns the lane's highest age with a non-zero weight plus
+// one (0 if none).
+__device__ __forceinline__ int mdf_rows_age(const MdfLane &L, float *out) {
+  float w0[AGE_MET_SLOTS], w1[AGE_MET_SLOTS];
+  double c_prev0 = 0.0, c_prev1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < AGE_MET_SLOTS; ++j) {
+    float v0 = 0.0f, v1 = 0.0f;
+    if (j < L.n_met) {
+      double c_next0 = 1.0, c_next1 = 1.0;
+      if (j < L.n_met - 1) {
+        const double edge = L.medge[j + 1];
+        c_next0 = triweight_cdf((edge - L.mu0) * L.inv_sig);
+        c_next1 = triweight_cdf((edge - L.mu1) * L.inv_sig);
+      }
+      v0 = L.real0 ? (float)(L.mage0 * (c_next0 - c_prev0)) : 0.0f;
+      v1 = L.real1 ? (float)(L.mage1 * (c_next1 - c_prev1)) : 0.0f;
+      c_prev0 = c_next0;
+      c_prev1 = c_next1;
+    }
+    w0[j] = v0;
+    w1[j] = v1;
+  }
+  bool nz0 = false, nz1 = false;
+#pragma unroll
+  for (int j = 0; j < AGE_MET_SLOTS; ++j) {
+    nz0 |= w0[j] != 0.0f;
+    nz1 |= w1[j] != 0.0f;
+  }
+  if (L.i0 < AGE_PAD) {
+    float4 *p0 = reinterpret_cast<float4 *>(out + (size_t)L.i0 * AGE_MET_SLOTS);
+#pragma unroll
+    for (int q = 0; q < AGE_MET_SLOTS / 4; ++q) {
+      p0[q] = make_float4(w0[4 * q], w0[4 * q + 1], w0[4 * q + 2], w0[4 * q + 3]);
+      p0[q + AGE_MET_SLOTS / 4] = make_float4(w1[4 * q], w1[4 * q + 1], w1[4 * q + 2], w1[4 * q + 3]);
+    }
+  }
+  return nz1 ? L.i0 + 2 : (nz0 ? L.i0 + 1 : 0);
 }
 
 // Orders one wave's LDS writes before its later LDS reads by other lanes.
@@ -419,6 +467,15 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   const double mu1 = real1 ? mdf_centre(s_lgage[i0 + 1], lgmet, transition, lgmet_old, a.slope,
                                         a.pivot, a.mdf_width) : 0.0;
   const MdfLane L{s_medge, s_ks, n_met, n_age, i0, mu0, mu1, inv_sig, mage0, mage1, real0, real1};
+  if (a.w_pad && a.w_pad_age) {
+    // age-major rows: the contraction needs only the highest non-zero age
+    const int hi = mdf_rows_age(L, (float *)a.w_pad + (size_t)local * AGE_K);
+    const unsigned long long any = __ballot(hi > 0);
+    const int top = any ? 63 - __builtin_clzll(any) : 0;
+    const int age_hi = any ? __builtin_amdgcn_readlane(hi, top) : 0;
+    if (a.range && lane == 0) a.range[s].age_hi = age_hi;
+    return;
+  }
   unsigned nzr;   // metallicity rows in which either of the lane's ages has a non-zero weight
   if (a.w_pad && a.w_pad_bf16)
     nzr = mdf_rows<MDF_PAD_BF16>(L, (uint16_t *)a.w_pad + (size_t)local * P.k_pad);
@@ -664,6 +721,28 @@ __global__ void k_pack_table_kmajor(const float *__restrict__ src, int n_age, in
     if (met > 0) v -= (double)src[((size_t)(met - 1) * n_age + age) * n_wave + l];
   }
   dst[idx] = (float)v;
+}
+
+// lum rows -> age-major table for the age-dependent attenuation:
+// SA[l][age * 16 + met] = L[met, age, l], zero for met >= n_met, age >= n_age
+// or l >= n_wave.  One thread per element of the table.
+__global__ void k_pack_table_age(const float *__restrict__ src, int n_met, int n_age, int n_wave,
+                                 int n_wave_pad, float *__restrict__ dst) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n_wave_pad * AGE_K) return;
+  const int l = (int)(idx / AGE_K), k = (int)(idx % AGE_K);
+  const int age = k / AGE_MET_SLOTS, met = k % AGE_MET_SLOTS;
+  float v = 0.0f;
+  if (met < n_met && age < n_age && l < n_wave) v = src[((size_t)met * n_age + age) * n_wave + l];
+  dst[idx] = v;
+}
+
+int launch_pack_table_age(const float *lum_rows, int n_met, int n_age, int n_wave, int n_wave_pad,
+                          float *sa32, hipStream_t stream) {
+  const size_t total = (size_t)n_wave_pad * AGE_K;
+  hipLaunchKernelGGL(k_pack_table_age, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
+                     lum_rows, n_met, n_age, n_wave, n_wave_pad, sa32);
+  return hip_fail(hipGetLastError(), "k_pack_table_age launch");
 }
 
 int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n_wave_pad,

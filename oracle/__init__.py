@@ -20,6 +20,9 @@ of zero weights), written step by step in the paper's order:
               form (Section 3.4.1, Eq. agedep_dust_csp)
   photometry  redshifted filter integrals and AB magnitudes (Section 2.2.1,
               Eq. restmag)
+  nebular     the ionization axis of the SSP block and emission-line
+              equivalent widths (Section 3.3, Eq. nebsed; Section 2.2.2,
+              Eq. eqw)
   pipeline    weights, SEDs, magnitudes and BF16 quantisation of the SSP block
   adjoint     hand-written reverse-mode gradient of the magnitudes
   summary     the population summary of the Section 4.1 forward model: a
@@ -32,13 +35,14 @@ is pinned by a CPU test against closed forms, invariants, brute force on tiny
 inputs or finite differences; none is "parity unpinned".
 """
 
-from . import constants, cosmology, kernels, sfh, mdf, dust, photometry, pipeline, adjoint
+from . import (constants, cosmology, kernels, sfh, mdf, dust, nebular, photometry, pipeline,
+               adjoint)
 from .pipeline import (weights, sed, band_sums, mags, quantize_bf16_rne, bf16_to_f32,
                        OracleInputs, prepare_inputs)
 from .adjoint import mags_vjp
 
 __all__ = [
-    "constants", "cosmology", "kernels", "sfh", "mdf", "dust", "photometry", "pipeline",
+    "constants", "cosmology", "kernels", "sfh", "mdf", "dust", "nebular", "photometry", "pipeline",
     "adjoint", "weights", "sed", "band_sums", "mags", "mags_vjp", "quantize_bf16_rne",
     "bf16_to_f32", "OracleInputs", "prepare_inputs",
 ]

@@ -67,6 +67,8 @@ def mags_vjp(inp: OracleInputs, mags_bar):
     """
     if inp.av_old is not None:
         raise NotImplementedError("the adjoint of the age-dependent attenuation is not written")
+    if inp.lgu_grid is not None:
+        raise NotImplementedError("the adjoint over the ionization axis is not written")
     mags_bar = np.atleast_2d(np.asarray(mags_bar, dtype=np.float64))
     n_gal = inp.n_gal
     n_met, n_age, n_wave = inp.lum.shape

@@ -4,7 +4,8 @@ Test infrastructure (see the package docstring).
 
   weights   W[g, j, i] = m_age[g, i] * P[g, j, i]   (Eqs. cspsum, agedep_mdf)
   sed       L[g, l] = sum_{j,i} W[g, j, i] L_SSP[j, i, l]   (Eqs. cspdeftheta,
-            full_mdf), optionally times F_att (Eq. attenuation)
+            full_mdf), optionally times F_att (Eq. attenuation); with the
+            ionization axis also summed over u with P_neb (Eq. nebsed)
   band_sums num/den of Eq. restmag on the redshifted grid
   mags      apparent AB magnitudes (Section 2.2.1)
 
@@ -23,7 +24,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import cosmology, dust, mdf, photometry, sfh
+from . import cosmology, dust, mdf, nebular, photometry, sfh
 
 
 @dataclass
@@ -31,7 +32,7 @@ class OracleInputs:
     lgz: np.ndarray          # [n_met]
     lg_age: np.ndarray       # [n_age]
     wave: np.ndarray         # [n_wave] rest-frame Angstrom
-    lum: np.ndarray          # [n_met, n_age, n_wave] float64
+    lum: np.ndarray          # [n_met, n_age, n_wave] float64 (or [.., n_u, n_wave])
     filt_wave: np.ndarray    # [n_band, n_pts]
     filt_trans: np.ndarray   # [n_band, n_pts]
     t_table: np.ndarray      # [n_t] Gyr
@@ -50,6 +51,9 @@ class OracleInputs:
     delta_old: np.ndarray | None = None
     dust_pivot: float = 7.0               # its transition centre (log10 yr) and width (dex)
     dust_width: float = 0.25
+    lgu_grid: np.ndarray | None = None    # ionization axis of the SSP block [n_u]
+    lgu: np.ndarray | None = None         # per-galaxy ionization centre and width
+    sigma_u: np.ndarray | None = None
     om0: float = 0.3
     h: float = 0.7
     w0: float = -1.0
@@ -65,7 +69,7 @@ class OracleInputs:
         kw = dict(self.__dict__)
         for name in ("sfr", "z", "lgmet", "sigma_z", "av", "delta", "bump"):
             kw[name] = getattr(self, name)[idx]
-        for name in ("lgmet_old", "av_old", "delta_old"):
+        for name in ("lgmet_old", "av_old", "delta_old", "lgu", "sigma_u"):
             if getattr(self, name) is not None:
                 kw[name] = getattr(self, name)[idx]
         if self.sfh_params is not None:
@@ -97,6 +101,10 @@ def prepare_inputs(ssp, filters, pop, sfr=None, om0=0.3, h=0.7, w0=-1.0,
                    else np.asarray(pop.delta_old, np.float64)),
         dust_pivot=float(getattr(pop, "dust_pivot", 7.0)),
         dust_width=float(getattr(pop, "dust_width", 0.25)),
+        lgu_grid=(None if getattr(ssp, "lgu", None) is None else np.asarray(ssp.lgu, np.float64)),
+        lgu=(None if getattr(pop, "lgu", None) is None else np.asarray(pop.lgu, np.float64)),
+        sigma_u=(None if getattr(pop, "sigma_u", None) is None
+                 else np.asarray(pop.sigma_u, np.float64)),
         om0=om0, h=h, w0=w0, k0_reading=k0_reading,
         sfh_params=np.asarray(pop.sfh_params, np.float64))
 
@@ -118,17 +126,30 @@ def weights(inp: OracleInputs, return_parts: bool = False):
     return w
 
 
+def ionization_weights(inp: OracleInputs):
+    """P_neb[g, k] over the SSP block's ionization axis (Eq. nebsed)."""
+    if inp.lgu is None or inp.sigma_u is None:
+        raise ValueError("the SSP block has an ionization axis: lgu and sigma_u are needed")
+    return nebular.ionization_weights(inp.lgu, inp.sigma_u, inp.lgu_grid)
+
+
 def sed(inp: OracleInputs, apply_dust: bool = False, block: int = 256):
     """Rest-frame composite SED [n_gal, n_wave] in L_sun/Hz."""
-    n_met, n_age, n_wave = inp.lum.shape
-    table = inp.lum.reshape(n_met * n_age, n_wave)
+    n_met, n_age = inp.lum.shape[:2]
+    n_wave = inp.lum.shape[-1]
+    neb = inp.lgu_grid is not None
+    table = None if neb else inp.lum.reshape(n_met * n_age, n_wave)
     out = np.empty((inp.n_gal, n_wave))
     if apply_dust and inp.av_old is not None:
         return _sed_age_dependent_dust(inp)
+    if neb:
+        block = min(block, 64)
     for s in range(0, inp.n_gal, block):
         sub = inp.subset(np.arange(s, min(s + block, inp.n_gal)))
-        w = weights(sub).reshape(sub.n_gal, n_met * n_age)
-        spec = w @ table
+        if neb:
+            spec = nebular.sed_nebular(weights(sub), ionization_weights(sub), inp.lum)
+        else:
+            spec = weights(sub).reshape(sub.n_gal, n_met * n_age) @ table
         if apply_dust:
             spec = spec * dust.attenuation(inp.wave, sub.av, sub.delta, sub.bump, inp.k0_reading)
         out[s:s + sub.n_gal] = spec
@@ -143,7 +164,10 @@ def _sed_age_dependent_dust(inp: OracleInputs, block: int = 8):
     for s in range(0, inp.n_gal, block):
         sub = inp.subset(np.arange(s, min(s + block, inp.n_gal)))
         w = weights(sub)                                                     # [g, j, i]
-        per_age = np.einsum("gji,jil->gil", w, inp.lum)                      # [g, i, l]
+        if inp.lgu_grid is not None:
+            per_age = np.einsum("gji,gk,jikl->gil", w, ionization_weights(sub), inp.lum)
+        else:
+            per_age = np.einsum("gji,jil->gil", w, inp.lum)                  # [g, i, l]
         av_i, delta_i = dust.age_dependent_parameters(
             sub.av, sub.delta, sub.av_old, sub.delta_old, inp.lg_age, inp.dust_pivot, inp.dust_width)
         for r in range(sub.n_gal):

@@ -11,7 +11,7 @@ LSST-like filters (Section 4.1), none of which ship with this repository, so the
 generators below produce stand-ins with the same shapes, units and structure.
 """
 
-from .ssp import make_ssp, SspTable
+from .ssp import make_ssp, make_ssp_nebular, make_line_spectra, SspTable, NEBULAR_LINES
 from .population import make_population, Population, TIME_GRID_END_GYR
 from .filters import make_filters, FilterSet
 from .configs import WORKLOADS, Workload, workload
@@ -19,7 +19,7 @@ from .mags import make_mags
 
 __all__ = [
     "make_mags",
-    "make_ssp", "SspTable",
+    "make_ssp", "make_ssp_nebular", "make_line_spectra", "SspTable", "NEBULAR_LINES",
     "make_population", "Population", "TIME_GRID_END_GYR",
     "make_filters", "FilterSet",
     "WORKLOADS", "Workload", "workload",

@@ -59,6 +59,8 @@ class Population:
     delta_old: np.ndarray | None = None
     dust_pivot: float = 7.0
     dust_width: float = 0.25
+    lgu: np.ndarray | None = None       # ionization distribution centre log10 U_s
+    sigma_u: np.ndarray | None = None   # and width in dex
     seed: int = 0
     meta: dict = field(default_factory=dict)
 
@@ -84,6 +86,8 @@ class Population:
             av_old=None if self.av_old is None else self.av_old[idx].copy(),
             delta_old=None if self.delta_old is None else self.delta_old[idx].copy(),
             dust_pivot=self.dust_pivot, dust_width=self.dust_width,
+            lgu=None if self.lgu is None else self.lgu[idx].copy(),
+            sigma_u=None if self.sigma_u is None else self.sigma_u[idx].copy(),
             seed=self.seed, meta=dict(self.meta))
 
 
@@ -95,7 +99,8 @@ def make_population(n_gal: int, n_t: int = 100, z_range=(0.1, 1.0), seed: int = 
                     n_band: int = 6, lgmet_slope: float = 0.1,
                     lg_age_pivot: float = 9.0, mdf: str = "linear",
                     mdf_width: float = 0.5, age_dust: bool = False,
-                    dust_pivot: float = 7.0, dust_width: float = 0.25) -> Population:
+                    dust_pivot: float = 7.0, dust_width: float = 0.25,
+                    nebular: bool = False) -> Population:
     """Draw a population with the parameter distributions of the workloads.
 
     log10 A ~ U[0, 2], tau ~ U[1, 5] Gyr, alpha ~ U[0.5, 3], q ~ U[0, 1],
@@ -108,6 +113,9 @@ def make_population(n_gal: int, n_t: int = 100, z_range=(0.1, 1.0), seed: int = 
     age_dust=True adds old-star attenuation parameters for the age-dependent
     dust model: A_V,old = A_V * U[0.2, 0.6] (young stars sit behind more dust)
     and delta_old = U[-0.7, 0.3], from their own stream.
+    nebular=True adds the ionization distribution of Section 3.3: centre
+    log10 U_s ~ U[-3.5, -1.5] and width sigma_u ~ U[0.1, 0.4] dex (the
+    paper's example uses 0.25), from their own stream.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     n = int(n_gal)
@@ -136,9 +144,14 @@ def make_population(n_gal: int, n_t: int = 100, z_range=(0.1, 1.0), seed: int = 
         drng = np.random.Generator(np.random.PCG64(seed + 3000003))
         av_old = _f32(av * drng.uniform(0.2, 0.6, n))
         delta_old = _f32(drng.uniform(-0.7, 0.3, n))
+    lgu = sigma_u = None
+    if nebular:
+        urng = np.random.Generator(np.random.PCG64(seed + 4000003))
+        lgu = _f32(urng.uniform(-3.5, -1.5, n))
+        sigma_u = _f32(urng.uniform(0.1, 0.4, n))
     return Population(t_table=make_time_grid(n_t), sfh_params=np.ascontiguousarray(sfh_params),
                       z=z, lgmet=lgmet, sigma_z=sigma_z, av=av, delta=delta, bump=bump,
                       targets=targets, lgmet_slope=lgmet_slope, lg_age_pivot=lg_age_pivot,
                       lgmet_old=lgmet_old, mdf_width=float(mdf_width), av_old=av_old,
                       delta_old=delta_old, dust_pivot=float(dust_pivot),
-                      dust_width=float(dust_width), seed=seed)
+                      dust_width=float(dust_width), lgu=lgu, sigma_u=sigma_u, seed=seed)

@@ -120,10 +120,17 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
 
 // Wbar[s, k] = sum_l Lbar[s, l] L_SSP[k, l] over the tile's wavelength window.
 // Rows (M) are SSP rows k, columns (N) galaxies, reduction over wavelength.
+// Rows above every member's MDF support are not needed: a metallicity bin
+// whose lower edge lies above the largest centre over ages plus 3 sigma has
+// weight zero and zero derivative at every age (the MDF is clipped at +-3
+// sigma), so its cotangent is never used; rows below must stay, because the
+// pull-back sums the differenced rows upwards.  A block whose rows all lie
+// above the tile's highest supported row writes zeros.
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   using C = GemmCfg<DSPS_FP32>;
   __shared__ GemmSmem<DSPS_FP32> sm[2];
   __shared__ int s_tile[2];
+  __shared__ int s_jhi;          // highest metallicity row in some member's MDF support
   const int kblk = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
@@ -132,17 +139,30 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   const int nvalid = min(TILE_G, a.s_count - g0);
   const int nwp = P.n_wave_pad;
 
-  if (threadIdx.x == 0) { s_tile[0] = 1 << 30; s_tile[1] = 0; }
+  if (threadIdx.x == 0) { s_tile[0] = 1 << 30; s_tile[1] = 0; s_jhi = 0; }
   __syncthreads();
   if (threadIdx.x < nvalid) {
-    const GalaxyRange r = a.range[a.s_begin + g0 + threadIdx.x];
+    const int s = a.s_begin + g0 + threadIdx.x;
+    const GalaxyRange r = a.range[s];
     atomicMin(&s_tile[0], r.win_lo);
     atomicMax(&s_tile[1], r.win_hi);
+    // the centre is monotone in age: its largest value sits at an end of the grid
+    const int g = a.perm[s];
+    const bool transition = a.lgmet_old != nullptr;
+    const double lgmet = (double)a.lgmet[g], old = transition ? (double)a.lgmet_old[g] : 0.0;
+    const double m0 = mdf_centre(P.lg_age[0], lgmet, transition, old, a.slope, a.pivot, a.mdf_width);
+    const double m1 = mdf_centre(P.lg_age[P.n_age - 1], lgmet, transition, old, a.slope, a.pivot,
+                                 a.mdf_width);
+    const double top = fmax(m0, m1) + 3.0 * (double)a.sigma_z[g];
+    int j_hi = 0;   // rows 1.. start at interior edge j
+    for (int j = 1; j < P.n_met; ++j) j_hi += P.met_edges[j] <= top;
+    atomicMax(&s_jhi, j_hi);
   }
   __syncthreads();
   const int l_begin = (s_tile[0] / TILE_L) * TILE_L;
   const int l_end = ((s_tile[1] + TILE_L - 1) / TILE_L) * TILE_L;
   const int k0 = kblk * TILE_L;
+  const int j_hi = s_jhi;
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -152,7 +172,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
 
-  const int nk = l_end > l_begin ? (l_end - l_begin) / C::KT : 0;
+  const int nk = (l_end > l_begin && k0 / AGE_PAD <= j_hi) ? (l_end - l_begin) / C::KT : 0;
   gemm_kloop<DSPS_FP32>(sm, P.sk32, nwp, k0, a.lbar, g0, a.s_count, nk,
                         [=](int ks) { return l_begin + ks * C::KT; }, wr, wc, lane, acc);
 

@@ -25,10 +25,13 @@ EXPORTS = (
     "dsps_workspace_size", "dsps_sfh_table", "dsps_weights", "dsps_sed", "dsps_mags",
     "dsps_mags_vjp", "dsps_quantize_bf16", "dsps_profile_enable", "dsps_profile_read",
     "dsps_pop_summary_workspace", "dsps_pop_summary", "dsps_pop_summary_vjp",
+    "dsps_ssp_create_neb", "dsps_ssp_ion_info", "dsps_eqw", "dsps_eqw_jvp",
+    "dsps_sed_ion_tangent",
 )
+MAX_ION, MAX_LINES = 16, 16
 
 KERNEL_IDS = {"weights": 0, "mags_gemm": 1, "mags_finalize": 2, "zsort": 3, "sed_gemm": 4,
-              "vjp_lbar": 5, "vjp_wbar": 6, "vjp_weights": 7, "summary": 8}
+              "vjp_lbar": 5, "vjp_wbar": 6, "vjp_weights": 7, "summary": 8, "eqw": 9}
 
 
 class DspsError(RuntimeError):
@@ -51,7 +54,13 @@ class Pop(ctypes.Structure):
         ("lgmet_old", ctypes.c_void_p), ("mdf_width", ctypes.c_double),
         ("av_old", ctypes.c_void_p), ("delta_old", ctypes.c_void_p),
         ("dust_pivot", ctypes.c_double), ("dust_width", ctypes.c_double),
+        ("lgu", ctypes.c_void_p), ("sigma_u", ctypes.c_void_p),
     ]
+
+
+class Line(ctypes.Structure):
+    _fields_ = [("centre", ctypes.c_double), ("half_width", ctypes.c_double),
+                ("fit_half_width", ctypes.c_double)]
 
 
 SSP_AGE_MAJOR = 4   # dsps_ssp_create: also the age-major float32 table
@@ -68,6 +77,12 @@ def _declare(lib):
         "dsps_abi_version": (I, []),
         "dsps_last_error": (ctypes.c_char_p, []),
         "dsps_ssp_create": (I, [I, I, I, P, P, P, P, I, I, PP]),
+        "dsps_ssp_create_neb": (I, [I, I, I, I, P, P, P, P, P, I, I, PP]),
+        "dsps_ssp_ion_info": (I, [P, IP]),
+        "dsps_eqw": (I, [P, P, I, ctypes.POINTER(Line), I, P, P]),
+        "dsps_eqw_jvp": (I, [P, P, P, I, ctypes.POINTER(Line), I, P, P, P]),
+        "dsps_sed_ion_tangent": (I, [P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, I, P, P, S,
+                                     P]),
         "dsps_ssp_destroy": (None, [P]),
         "dsps_ssp_info": (I, [P, IP, IP, IP, IP, IP]),
         "dsps_filters_create": (I, [I, I, P, P, PP]),
@@ -118,7 +133,7 @@ def load(path: str | None = None):
     if not os.path.exists(p):
         raise ImportError(
             f"libdsps.so not found at {p}; build it with "
-            "`python -m paper_2112_06830_amd.build` (hipcc, gfx950). There is no fallback.")
+            "`python paper_2112_06830_amd/build.py` (hipcc, gfx950). There is no fallback.")
     import torch  # noqa: F401  (loads torch's HIP runtime before ours binds)
     lib = ctypes.CDLL(p, mode=ctypes.RTLD_LOCAL)
     runtimes = _hip_runtimes()

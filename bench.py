@@ -325,6 +325,65 @@ def run_age_dust(P, steps, warmup, n_gal=100_000, seed=9, pivot=7.0, width=0.25)
     return res, (ssp, flt, pop.subset(np.arange(128)), m[:128].cpu().numpy())
 
 
+# [OII], Hbeta, [OIII] 5007, Halpha: (centre, half-width, fit half-width), Angstrom
+NEB_LINES = ((3727.42, 40.0, 150.0), (4862.68, 40.0, 150.0), (5008.24, 40.0, 150.0),
+             (6564.61, 50.0, 180.0))
+
+
+def run_nebular(P, steps, warmup, n_gal=100_000, seed=10, n_u=7):
+    """Nebular ionization axis (Section 3.3, Eq. nebsed) on the FP32 forward
+    of the 1e5-galaxy workload: the 12 x 94 x 5994 block with n_u = 7
+    ionization points (log10 U_s -4..-1), log10 U_s ~ U[-3.5, -1.5] and
+    sigma_u ~ U[0.1, 0.4] per galaxy.  Times the fused magnitudes, and the
+    attenuated SED plus four equivalent widths (Section 2.2.2, Eq. eqw) of
+    every galaxy.  Returns the timings and samples for the oracle check of the
+    CPU-baseline leg."""
+    import torch
+    import synth
+    ssp = synth.make_ssp_nebular(n_u=n_u, n_wave=5994, wave_lo=9.0e2, wave_hi=2.5e4)
+    flt = synth.make_filters()
+    pop = synth.make_population(n_gal, n_t=100, z_range=(0.1, 3.0), seed=seed, nebular=True)
+    log(f"nebular_fp32_1e5: n_u={n_u}")
+    ssp_h = P.SspBlock.from_synth(ssp)
+    flt_h = P.FilterBank.from_synth(flt)
+    dpar = P.DevicePopulation.from_synth(pop, use_params=True)
+    dpop = dpar.with_sfr(P.sfh_table(dpar.t_table, dpar.sfh_params))
+    ws = P.Workspace(P.workspace_size(2, ssp_h, flt_h, n_gal, 100, "fp32"), dpop.device)
+    m = torch.empty((n_gal, 6), dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        P.mags(ssp_h, flt_h, P.Cosmology(), dpop, workspace=ws, out=m)
+    torch.cuda.synchronize()
+    P.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.mags(ssp_h, flt_h, P.Cosmology(), dpop, workspace=ws, out=m)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    gemm_ms, _ = P.profile_read("mags_gemm")
+    P.profile_enable(False)
+    ew = None
+    for _ in range(warmup):
+        sed = P.sed(ssp_h, P.Cosmology(), dpop, apply_dust=True)
+        ew = P.eqw(ssp_h, sed, NEB_LINES)
+    torch.cuda.synchronize()
+    P.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sed = P.sed(ssp_h, P.Cosmology(), dpop, apply_dust=True)
+        ew = P.eqw(ssp_h, sed, NEB_LINES)
+    torch.cuda.synchronize()
+    ms_ew = (time.perf_counter() - t0) * 1e3 / steps
+    eqw_ms, _ = P.profile_read("eqw")
+    P.profile_enable(False)
+    res = {"mags": {"ms_per_step": ms, "galaxies_per_s": n_gal / (ms * 1e-3),
+                    "gemm_ms_per_step": gemm_ms / steps},
+           "sed_and_eqw": {"ms_per_step": ms_ew, "galaxies_per_s": n_gal / (ms_ew * 1e-3),
+                           "eqw_ms_per_step": eqw_ms / steps, "n_lines": len(NEB_LINES)},
+           "finite": bool(torch.isfinite(m).all().item() and torch.isfinite(ew).all().item())}
+    idx = np.arange(64)
+    return res, (ssp, flt, pop.subset(idx), m[:64].cpu().numpy(), ew[:64].cpu().numpy())
+
+
 def run_forward_model(P, steps, warmup, n_gal=100_000, seed=7):
     """The Section 4.1 forward model at z = 0: parametric SFH -> SFR table ->
     six-band absolute magnitudes (FP32) -> red colour cut (g - r above the
@@ -492,6 +551,10 @@ def main():
         ad, ad_sample = run_age_dust(P, max(3, args.steps // 4), 1)
         extra["age_dust_fp32_1e5"] = ad
         log(f"age-dependent dust 1e5: {ad['ms_per_step']:.3f} ms/step, gemm {ad['gemm_ms_per_step']:.3f}")
+        nb, nb_sample = run_nebular(P, max(3, args.steps // 4), 1)
+        extra["nebular_fp32_1e5"] = nb
+        log(f"nebular 1e5: mags {nb['mags']['ms_per_step']:.3f} ms/step, "
+            f"sed + widths {nb['sed_and_eqw']['ms_per_step']:.3f} ms/step")
         va, va_sample = run_variants(P, max(3, args.steps // 4), 1)
         extra["variants_transition_mdf_wcdm_1e5"] = va
         log(f"variants 1e5: forward {va['forward']['ms_per_step']:.3f} ms/step, "
@@ -510,6 +573,15 @@ def main():
             a_ssp, a_flt, a_pop, a_m = ad_sample
             errors["age_dust_fp32_1e5"] = band_errors(
                 a_m, oracle.mags(oracle.prepare_inputs(a_ssp, a_flt, a_pop)))
+            n_ssp, n_flt, n_pop, n_m, n_ew = nb_sample
+            n_inp = oracle.prepare_inputs(n_ssp, n_flt, n_pop)
+            errors["nebular_fp32_1e5"] = band_errors(n_m, oracle.mags(n_inp))
+            n_sed = oracle.sed(n_inp, apply_dust=True)
+            n_ref = np.stack([oracle.nebular.equivalent_width(n_ssp.wave, n_sed, c, h, f)
+                              for c, h, f in NEB_LINES], axis=1)
+            errors["nebular_eqw_1e5"] = {"max_abs_angstrom": float(np.max(np.abs(n_ew - n_ref))),
+                                         "max_rel": float(np.max(np.abs(n_ew - n_ref)
+                                                                 / np.maximum(np.abs(n_ref), 1.0)))}
         extra["error_vs_oracle"] = errors
 
     traffic = read_traffic("fp32", "fp32_1e5")

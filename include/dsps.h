@@ -13,7 +13,10 @@
  *   x dust attenuation                         (Section 3.4, Eqs. attenuation-uvbump)
  *   -> redshifted filter integrals, AB mags    (Section 2.2.1, Eq. restmag)
  *
- * and it returns the reverse-mode gradient of the magnitudes (Section 2.1:
+ * optionally over a third SSP axis, the nebular ionization parameter, with a
+ * triweight weight per grid point (Section 3.3, Eq. nebsed), with emission-
+ * line equivalent widths of the composite SED (Section 2.2.2, Eq. eqw), and
+ * it returns the reverse-mode gradient of the magnitudes (Section 2.1:
  * with the SSP block fixed, every gradient flows through the weights).
  *
  * Conventions shared by every entry point
@@ -51,7 +54,7 @@
 extern "C" {
 #endif
 
-#define DSPS_ABI_VERSION 4
+#define DSPS_ABI_VERSION 5
 
 typedef enum {
   DSPS_OK = 0,
@@ -84,6 +87,8 @@ typedef enum {
 #define DSPS_MAX_BAND 8       /* filters per filter set                     */
 #define DSPS_MAX_NT 2048      /* points of the tabulated SFH                */
 #define DSPS_MAX_FILTER_FLOATS 8192  /* n_band * n_pts of a filter set          */
+#define DSPS_MAX_ION 16       /* points of the ionization axis              */
+#define DSPS_MAX_LINES 16     /* emission lines per dsps_eqw call           */
 
 /* ---------------------------------------------------------------------------
  * Resident SSP block (Section 2.1: the SSP spectra are loaded once as a
@@ -114,6 +119,24 @@ typedef struct dsps_ssp_s dsps_ssp;
 int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz,
                     const double *lg_age, const double *wave, const float *lum,
                     int precisions, int k0_reading, dsps_ssp **out);
+
+/* SSP block with the nebular ionization axis u = log10 U_s (Section 3.3,
+ * Eq. nebsed): L_SSP(lambda | tau_i, Z_j, u_k).
+ *   n_u     1 <= n_u <= 16 ionization points
+ *   lgu     HOST [n_u] log10 U_s, strictly ascending
+ *   lum     HOST [n_met*n_age*n_u*n_wave] float32, row (met, age, u) major
+ *   precisions  (1 << DSPS_FP32) only when n_u > 1 (the axis is supported
+ *           in float32), else as dsps_ssp_create
+ * Other arguments as dsps_ssp_create.  Ionization bins are bounded by the
+ * midpoints of adjacent grid values (-inf and +inf outermost); the weight of
+ * point k is the triweight mass of the galaxy's distribution inside bin k
+ * (dsps_pop.lgu, sigma_u).  dsps_sed and dsps_mags (float32) sum over the
+ * axis; dsps_weights returns the (metallicity, age) weights without the
+ * ionization factor; dsps_mags_vjp returns DSPS_ERR_UNSUPPORTED for n_u > 1.
+ * n_u == 1 is dsps_ssp_create. */
+int dsps_ssp_create_neb(int n_met, int n_age, int n_u, int n_wave, const double *lgz,
+                        const double *lg_age, const double *lgu, const double *wave,
+                        const float *lum, int precisions, int k0_reading, dsps_ssp **out);
 void dsps_ssp_destroy(dsps_ssp *ssp);
 
 /* ---------------------------------------------------------------------------
@@ -171,6 +194,10 @@ typedef struct { double om0, w0, h; } dsps_cosmo;
  *               DSPS_SSP_AGE_MAJOR); dsps_sed and dsps_mags_vjp return
  *               DSPS_ERR_UNSUPPORTED.
  *   dust_pivot, dust_width  transition centre (log10 yr) and width (dex, > 0)
+ *   lgu, sigma_u  [n_gal] centre log10 U_s and width (dex, > 0) of the
+ *               triweight ionization distribution (Section 3.3, Eq. nebsed);
+ *               required when the SSP handle has n_u > 1, ignored when it
+ *               has one ionization point (all weight lands on it)
  * ------------------------------------------------------------------------ */
 typedef struct {
   int n_gal, n_t;
@@ -183,6 +210,7 @@ typedef struct {
   double mdf_width;
   const float *av_old, *delta_old;
   double dust_pivot, dust_width;
+  const float *lgu, *sigma_u;
 } dsps_pop;
 
 /* Workspace bytes a call of kind `op` needs for this population shape and
@@ -225,6 +253,22 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
              int apply_dust, int precision, float *sed, void *workspace,
              size_t workspace_bytes, hipStream_t stream);
 
+/* Derivative of the (optionally attenuated) SED with respect to each
+ * galaxy's ionization centre (wrt 0: pop->lgu) or width (wrt 1: sigma_u)
+ * (Section 3.3: the gradients the paper takes of line strengths).  The SED of
+ * Eq. nebsed is linear in the ionization weights, so this is the same sum
+ * with each weight replaced by its derivative
+ *   dP_k/du = -(T(z_{k+1}) - T(z_k)) / sigma,
+ *   dP_k/dsigma = -(z_{k+1} T(z_{k+1}) - z_k T(z_k)) / sigma,
+ * z_e = (e - u)/sigma at the bin edges, T the triweight density (infinite
+ * outer edges contribute nothing).  Requires an SSP handle with n_u > 1
+ * (else DSPS_ERR_UNSUPPORTED); float32; workspace as dsps_sed
+ * (DSPS_OP_SED).  Each galaxy's SED depends only on its own distribution, so
+ * row g is also the gradient of any linear functional of SED row g. */
+int dsps_sed_ion_tangent(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
+                         int apply_dust, int wrt, float *dsed, void *workspace,
+                         size_t workspace_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * a1-a7. Fused magnitudes: the SED is contracted, attenuated and integrated
  * through every filter without ever being written to memory.
@@ -266,6 +310,34 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
                   double *sfh_params_bar, float *lgmet_bar, float *lgmet_old_bar,
                   float *sigma_bar, float *av_bar, float *delta_bar, float *bump_bar,
                   void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Emission-line equivalent widths of rest-frame SEDs (Section 2.2.2, Eq. eqw).
+ * For each line the continuum L_0 is the least-squares quadratic in
+ * (lambda - centre) fitted to the SED at the grid points of the neighbourhood
+ * |lambda - centre| <= fit_half_width outside the line window
+ * |lambda - centre| <= half_width, every point with equal weight; the width is
+ * the trapezoid rule, over the grid points inside the line window, of
+ * (L - L_0) / L_0 in rest-frame Angstrom (positive for emission).  The fit and
+ * the sums run in float64 on float32 SEDs.
+ *   ssp    handle whose wavelength grid the SEDs are on
+ *   sed    [n_gal*n_wave] float32, device (e.g. dsps_sed output)
+ *   lines  HOST [n_line], 1 <= n_line <= DSPS_MAX_LINES; 0 < half_width <
+ *          fit_half_width; the line window must hold >= 2 grid points and the
+ *          neighbourhood >= 3 points outside it (else DSPS_ERR_SHAPE)
+ *   eqw    [n_gal*n_line] float32, device; a non-positive continuum at a
+ *          window point gives Inf or NaN there
+ * ------------------------------------------------------------------------ */
+typedef struct { double centre, half_width, fit_half_width; } dsps_line;
+int dsps_eqw(const dsps_ssp *ssp, const float *sed, int n_gal, const dsps_line *lines,
+             int n_line, float *eqw, hipStream_t stream);
+/* The widths and their tangent along an SED tangent dsed [n_gal*n_wave]
+ * (e.g. dsps_sed_ion_tangent): the continuum fit is linear, so its tangent
+ * is the same fit of dsed, and the integrand's tangent is
+ * (dL L_0 - L dL_0) / L_0^2.  deqw [n_gal*n_line] float32, device. */
+int dsps_eqw_jvp(const dsps_ssp *ssp, const float *sed, const float *dsed, int n_gal,
+                 const dsps_line *lines, int n_line, float *eqw, float *deqw,
+                 hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Population summary of the Section 4.1 forward model: a red-colour cut and
@@ -331,7 +403,8 @@ typedef enum {
   DSPS_KERNEL_VJP_WBAR = 6,     /* adjoint: transposed contraction          */
   DSPS_KERNEL_VJP_WEIGHTS = 7,  /* adjoint: weights -> SFH, MDF parameters  */
   DSPS_KERNEL_SUMMARY = 8,      /* population summary (partials + reduction) */
-  DSPS_KERNEL_COUNT = 9
+  DSPS_KERNEL_EQW = 9,          /* emission-line equivalent widths          */
+  DSPS_KERNEL_COUNT = 10
 } dsps_kernel_id;
 int dsps_profile_enable(int on);
 int dsps_profile_read(int kernel_id, double *total_ms, int *launches);
@@ -342,6 +415,8 @@ const char *dsps_last_error(void);
 /* Grid sizes of a handle: n_met, n_age, n_wave, precisions, k0_reading. */
 int dsps_ssp_info(const dsps_ssp *ssp, int *n_met, int *n_age, int *n_wave,
                   int *precisions, int *k0_reading);
+/* Points of the ionization axis (1 for a block without it). */
+int dsps_ssp_ion_info(const dsps_ssp *ssp, int *n_u);
 int dsps_filters_info(const dsps_filters *filters, int *n_band, int *n_pts);
 
 #ifdef __cplusplus

@@ -31,13 +31,19 @@ Readings:
   * The integral is the trapezoid rule over the SED grid points inside the
     closed line window, in rest-frame Angstrom.  Emission gives a positive
     width.  Fewer than three fit points or two window points give NaN.
+
+Gradients (the paper differentiates line strengths with respect to u_s):
+the ionization weights are differentiable in the distribution's centre and
+width, the SED is linear in them, and the width is a smooth function of the
+SED, so d(width)/d(u_s) is the width's tangent along
+dL/du_s = sum_k dP_k/du_s L_k, with L_k the SED of ionization point k alone.
 """
 
 from __future__ import annotations
 
 import numpy as np
 
-from .kernels import triweight_cdf_x
+from .kernels import triweight_cdf_x, triweight_pdf
 
 
 def ion_bin_edges(lgu):
@@ -57,6 +63,27 @@ def ionization_weights(lgu_s, sigma_u, lgu):
     edges = ion_bin_edges(lgu)
     cdf = triweight_cdf_x(edges[None, :], centre[:, None], sigma[:, None])
     return cdf[:, 1:] - cdf[:, :-1]
+
+
+def ionization_weight_derivatives(lgu_s, sigma_u, lgu):
+    """(dP/du_s, dP/dsigma_u) [g, n_u] of the ionization weights.
+
+    With z_e = (e - u_s)/sigma and T the triweight density, the weight of bin
+    k is T_erf(z_{k+1}) - T_erf(z_k), so dP_k/du_s = -(T(z_{k+1}) -
+    T(z_k))/sigma and dP_k/dsigma = -(z_{k+1} T(z_{k+1}) - z_k T(z_k))/sigma;
+    the infinite outer edges contribute nothing."""
+    centre = np.atleast_1d(np.asarray(lgu_s, dtype=np.float64))
+    sigma = np.atleast_1d(np.asarray(sigma_u, dtype=np.float64))
+    edges = ion_bin_edges(lgu)
+    with np.errstate(invalid="ignore"):
+        z = (edges[None, :] - centre[:, None]) / sigma[:, None]
+    finite = np.isfinite(z)
+    zf = np.where(finite, z, 0.0)
+    t = np.where(finite, triweight_pdf(zf), 0.0)
+    zt = np.where(finite, zf * t, 0.0)
+    d_u = -(t[:, 1:] - t[:, :-1]) / sigma[:, None]
+    d_s = -(zt[:, 1:] - zt[:, :-1]) / sigma[:, None]
+    return d_u, d_s
 
 
 def sed_nebular(w, p_neb, lum):
@@ -87,6 +114,31 @@ def continuum_fit(wave, spec, centre, fit_half_width, in_fit):
     design = np.stack([np.ones_like(x), x, x * x], axis=1)
     coef, *_ = np.linalg.lstsq(design, np.asarray(spec, dtype=np.float64)[in_fit], rcond=None)
     return coef
+
+
+def equivalent_width_jvp(wave, spec, dspec, centre, half_width, fit_half_width):
+    """(W, dW) for every row: Eq. eqw and its derivative along a tangent
+    dspec of the SED.  The fit is linear in the SED, so the continuum's
+    tangent is the same least-squares fit of dspec; the ratio's derivative is
+    (dL L_0 - L dL_0) / L_0^2, integrated with the same trapezoid rule."""
+    lam = np.asarray(wave, dtype=np.float64)
+    spec = np.atleast_2d(np.asarray(spec, dtype=np.float64))
+    dspec = np.atleast_2d(np.asarray(dspec, dtype=np.float64))
+    in_line, in_fit = line_windows(lam, centre, half_width, fit_half_width)
+    w = np.full(spec.shape[0], np.nan)
+    dw = np.full(spec.shape[0], np.nan)
+    if in_fit.sum() < 3 or in_line.sum() < 2:
+        return w, dw
+    xl = (lam[in_line] - centre) / fit_half_width
+    for g in range(spec.shape[0]):
+        c = continuum_fit(lam, spec[g], centre, fit_half_width, in_fit)
+        dc = continuum_fit(lam, dspec[g], centre, fit_half_width, in_fit)
+        cont = c[0] + c[1] * xl + c[2] * xl * xl
+        dcont = dc[0] + dc[1] * xl + dc[2] * xl * xl
+        line = spec[g, in_line]
+        w[g] = np.trapezoid((line - cont) / cont, lam[in_line])
+        dw[g] = np.trapezoid((dspec[g, in_line] * cont - line * dcont) / (cont * cont), lam[in_line])
+    return w, dw
 
 
 def equivalent_width(wave, spec, centre, half_width, fit_half_width):

@@ -133,6 +133,26 @@ def ionization_weights(inp: OracleInputs):
     return nebular.ionization_weights(inp.lgu, inp.sigma_u, inp.lgu_grid)
 
 
+def sed_ion_tangent(inp: OracleInputs, which: str = "lgu", apply_dust: bool = False,
+                    block: int = 64):
+    """dL/d(lgu) or dL/d(sigma_u) [n_gal, n_wave]: the SED sum of Eq. nebsed
+    with the ionization weights replaced by their derivatives (each galaxy's
+    SED depends only on its own distribution)."""
+    if inp.lgu_grid is None:
+        raise ValueError("the SSP block has no ionization axis")
+    if apply_dust and inp.av_old is not None:
+        raise NotImplementedError("age-dependent attenuation with the ionization tangent")
+    out = np.empty((inp.n_gal, inp.lum.shape[-1]))
+    for s in range(0, inp.n_gal, block):
+        sub = inp.subset(np.arange(s, min(s + block, inp.n_gal)))
+        d_u, d_s = nebular.ionization_weight_derivatives(sub.lgu, sub.sigma_u, inp.lgu_grid)
+        spec = nebular.sed_nebular(weights(sub), d_u if which == "lgu" else d_s, inp.lum)
+        if apply_dust:
+            spec = spec * dust.attenuation(inp.wave, sub.av, sub.delta, sub.bump, inp.k0_reading)
+        out[s:s + sub.n_gal] = spec
+    return out
+
+
 def sed(inp: OracleInputs, apply_dust: bool = False, block: int = 256):
     """Rest-frame composite SED [n_gal, n_wave] in L_sun/Hz."""
     n_met, n_age = inp.lum.shape[:2]

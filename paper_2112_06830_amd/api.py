@@ -49,10 +49,11 @@ def _workspace(nbytes: int, device) -> tuple[torch.Tensor | None, int]:
 
 
 class SspBlock:
-    """Resident SSP block (dsps_ssp_create)."""
+    """Resident SSP block (dsps_ssp_create, or dsps_ssp_create_neb with an
+    ionization grid lgu and lum [n_met, n_age, n_u, n_wave])."""
 
     def __init__(self, lgz, lg_age, wave, lum, precisions=("fp32", "bf16"), k0_reading="salim",
-                 age_major=False):
+                 age_major=False, lgu=None):
         """age_major also prepares the age-major float32 table that the
         age-dependent attenuation needs (dsps_pop.av_old)."""
         lgz = np.ascontiguousarray(lgz, dtype=np.float64)
@@ -60,7 +61,8 @@ class SspBlock:
         wave = np.ascontiguousarray(wave, dtype=np.float64)
         lum = np.ascontiguousarray(lum, dtype=np.float32)
         n_met, n_age, n_wave = lgz.size, lg_age.size, wave.size
-        if lum.size != n_met * n_age * n_wave:
+        n_u = 1 if lgu is None else int(np.size(lgu))
+        if lum.size != n_met * n_age * n_u * n_wave:
             raise ValueError("lum has the wrong size")
         mask = N.SSP_AGE_MAJOR if age_major else 0
         for p in precisions:
@@ -68,17 +70,27 @@ class SspBlock:
         torch.cuda.init()
         self.device = torch.device("cuda", torch.cuda.current_device())
         h = ctypes.c_void_p()
-        rc = _lib().dsps_ssp_create(n_met, n_age, n_wave, lgz.ctypes.data, lg_age.ctypes.data,
-                                    wave.ctypes.data, lum.ctypes.data, mask, _K0[k0_reading],
-                                    ctypes.byref(h))
-        N.check(rc, "dsps_ssp_create")
+        if lgu is None:
+            rc = _lib().dsps_ssp_create(n_met, n_age, n_wave, lgz.ctypes.data, lg_age.ctypes.data,
+                                        wave.ctypes.data, lum.ctypes.data, mask, _K0[k0_reading],
+                                        ctypes.byref(h))
+            N.check(rc, "dsps_ssp_create")
+        else:
+            lgu = np.ascontiguousarray(lgu, dtype=np.float64)
+            rc = _lib().dsps_ssp_create_neb(n_met, n_age, n_u, n_wave, lgz.ctypes.data,
+                                            lg_age.ctypes.data, lgu.ctypes.data, wave.ctypes.data,
+                                            lum.ctypes.data, mask, _K0[k0_reading], ctypes.byref(h))
+            N.check(rc, "dsps_ssp_create_neb")
         self.handle = h
-        self.n_met, self.n_age, self.n_wave = n_met, n_age, n_wave
+        self.n_met, self.n_age, self.n_wave, self.n_u = n_met, n_age, n_wave, n_u
         self.wave = wave
 
     @classmethod
     def from_synth(cls, ssp, **kw):
-        return cls(ssp.lgz, ssp.lg_age, ssp.wave, ssp.lum, **kw)
+        lgu = getattr(ssp, "lgu", None)
+        if lgu is not None and "precisions" not in kw:
+            kw["precisions"] = ("fp32",)
+        return cls(ssp.lgz, ssp.lg_age, ssp.wave, ssp.lum, lgu=lgu, **kw)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -153,6 +165,8 @@ class DevicePopulation:
     delta_old: torch.Tensor | None = None
     dust_pivot: float = 7.0
     dust_width: float = 0.25
+    lgu: torch.Tensor | None = None         # ionization distribution: centre, width
+    sigma_u: torch.Tensor | None = None
 
     @property
     def n_gal(self):
@@ -171,7 +185,7 @@ class DevicePopulation:
                      _ptr(self.z), _ptr(self.lgmet), _ptr(self.sigma_z), _ptr(self.av),
                      _ptr(self.delta), _ptr(self.bump), self.lgmet_slope, self.lg_age_pivot,
                      _ptr(self.lgmet_old), self.mdf_width, _ptr(self.av_old), _ptr(self.delta_old),
-                     self.dust_pivot, self.dust_width)
+                     self.dust_pivot, self.dust_width, _ptr(self.lgu), _ptr(self.sigma_u))
 
     @classmethod
     def from_synth(cls, pop, device="cuda", sfr=None, use_params=False):
@@ -197,13 +211,15 @@ class DevicePopulation:
                    delta_old=(None if getattr(pop, "delta_old", None) is None
                               else f32(pop.delta_old)),
                    dust_pivot=float(getattr(pop, "dust_pivot", 7.0)),
-                   dust_width=float(getattr(pop, "dust_width", 0.25)))
+                   dust_width=float(getattr(pop, "dust_width", 0.25)),
+                   lgu=(None if getattr(pop, "lgu", None) is None else f32(pop.lgu)),
+                   sigma_u=(None if getattr(pop, "sigma_u", None) is None else f32(pop.sigma_u)))
 
     def with_sfr(self, sfr):
         return DevicePopulation(self.t_table, sfr, None, self.z, self.lgmet, self.sigma_z, self.av,
                                 self.delta, self.bump, self.lgmet_slope, self.lg_age_pivot,
                                 self.lgmet_old, self.mdf_width, self.av_old, self.delta_old,
-                                self.dust_pivot, self.dust_width)
+                                self.dust_pivot, self.dust_width, self.lgu, self.sigma_u)
 
 
 def workspace_size(op: int, ssp: SspBlock, filters: FilterBank | None, n_gal: int, n_t: int,
@@ -252,6 +268,47 @@ def sed(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, apply_dust=True,
                          _PREC[precision], _ptr(out), ws, nbytes, _stream(stream))
     N.check(rc, "dsps_sed")
     return out
+
+
+def sed_ion_tangent(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, wrt="lgu",
+                    apply_dust=True, stream=None):
+    """dsps_sed_ion_tangent: dSED/d(lgu) or dSED/d(sigma_u) [n_gal, n_wave]."""
+    out = torch.empty((pop.n_gal, ssp.n_wave), dtype=torch.float32, device=pop.device)
+    nbytes = workspace_size(N.OP_SED, ssp, None, pop.n_gal, pop.n_t, "fp32")
+    buf, off = _workspace(nbytes, pop.device)
+    c, p = cosmo.c(), pop.c()
+    ws = ctypes.c_void_p(buf.data_ptr() + off) if buf is not None else None
+    rc = _lib().dsps_sed_ion_tangent(ssp.handle, ctypes.byref(c), ctypes.byref(p),
+                                     int(bool(apply_dust)), {"lgu": 0, "sigma_u": 1}[wrt], _ptr(out),
+                                     ws, nbytes, _stream(stream))
+    N.check(rc, "dsps_sed_ion_tangent")
+    return out
+
+
+def _lines(lines):
+    lines = list(lines)
+    return (N.Line * len(lines))(*[N.Line(float(c), float(h), float(f)) for c, h, f in lines]), len(lines)
+
+
+def eqw(ssp: SspBlock, sed: torch.Tensor, lines, dsed: torch.Tensor | None = None, stream=None):
+    """dsps_eqw: equivalent widths [n_gal, n_line] float32 (rest-frame
+    Angstrom) of SEDs [n_gal, n_wave] on the block's grid, for lines given as
+    (centre, half_width, fit_half_width) triples.  With an SED tangent dsed
+    (dsps_eqw_jvp) returns (widths, their tangent)."""
+    sed = sed.to(torch.float32).contiguous()
+    arr, n_line = _lines(lines)
+    out = torch.empty((sed.shape[0], n_line), dtype=torch.float32, device=sed.device)
+    if dsed is None:
+        rc = _lib().dsps_eqw(ssp.handle, _ptr(sed), int(sed.shape[0]), arr, n_line, _ptr(out),
+                             _stream(stream))
+        N.check(rc, "dsps_eqw")
+        return out
+    dsed = dsed.to(torch.float32).contiguous()
+    dout = torch.empty_like(out)
+    rc = _lib().dsps_eqw_jvp(ssp.handle, _ptr(sed), _ptr(dsed), int(sed.shape[0]), arr, n_line,
+                             _ptr(out), _ptr(dout), _stream(stream))
+    N.check(rc, "dsps_eqw_jvp")
+    return out, dout
 
 
 class Workspace:

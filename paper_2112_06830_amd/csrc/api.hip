@@ -146,16 +146,25 @@ int dsps_abi_version(void) { return DSPS_ABI_VERSION; }
 
 const char *dsps_last_error(void) { return g_err; }
 
+}  // extern "C"
+
 // ------------------------------------------------------------------ SSP block
-int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const double *lg_age,
-                    const double *wave, const float *lum, int precisions, int k0_reading,
-                    dsps_ssp **out) {
+// Both create calls: lum is [n_met][n_age][n_u][n_wave] (n_u == 1: the plain
+// block, lgu may then be NULL).
+static int ssp_create(int n_met, int n_age, int n_u, int n_wave, const double *lgz,
+                      const double *lg_age, const double *lgu, const double *wave, const float *lum,
+                      int precisions, int k0_reading, dsps_ssp **out) {
   DSPS_CHECK(out && lgz && lg_age && wave && lum, DSPS_ERR_ARG, "NULL argument to dsps_ssp_create");
   DSPS_CHECK(n_met >= 1 && n_met <= DSPS_MAX_MET, DSPS_ERR_SHAPE, "n_met %d outside [1, %d]", n_met, DSPS_MAX_MET);
   DSPS_CHECK(n_age >= 1 && n_age <= DSPS_MAX_AGE, DSPS_ERR_SHAPE, "n_age %d outside [1, %d]", n_age, DSPS_MAX_AGE);
+  DSPS_CHECK(n_u >= 1 && n_u <= DSPS_MAX_ION, DSPS_ERR_SHAPE, "n_u %d outside [1, %d]", n_u, DSPS_MAX_ION);
   DSPS_CHECK(n_wave >= 2, DSPS_ERR_SHAPE, "n_wave %d < 2", n_wave);
   DSPS_CHECK((precisions & 3) >= 1 && (precisions & ~(3 | DSPS_SSP_AGE_MAJOR)) == 0, DSPS_ERR_ARG,
              "precisions mask %d invalid", precisions);
+  DSPS_CHECK(n_u == 1 || precisions == (1 << DSPS_FP32), DSPS_ERR_UNSUPPORTED,
+             "an SSP block with an ionization axis is supported in float32 only");
+  DSPS_CHECK(n_u == 1 || lgu, DSPS_ERR_ARG, "lgu is NULL");
+  for (int k = 1; k < n_u; ++k) DSPS_CHECK(lgu[k] > lgu[k - 1], DSPS_ERR_ARG, "lgu not ascending");
   DSPS_CHECK(k0_reading == DSPS_K0_SALIM || k0_reading == DSPS_K0_PRINTED, DSPS_ERR_ARG,
              "k0_reading %d invalid", k0_reading);
   for (int j = 1; j < n_met; ++j) DSPS_CHECK(lgz[j] > lgz[j - 1], DSPS_ERR_ARG, "lgz not ascending");
@@ -164,7 +173,7 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
     DSPS_CHECK(wave[l] > 0.0 && std::isfinite(wave[l]), DSPS_ERR_ARG, "wave[%d] not positive", l);
     if (l) DSPS_CHECK(wave[l] > wave[l - 1], DSPS_ERR_ARG, "wave not ascending");
   }
-  const size_t n_lum = (size_t)n_met * n_age * n_wave;
+  const size_t n_lum = (size_t)n_met * n_age * n_u * n_wave;
   for (size_t i = 0; i < n_lum; ++i)
     DSPS_CHECK(lum[i] >= 0.0f && std::isfinite(lum[i]), DSPS_ERR_ARG, "lum[%zu] negative or not finite", i);
 
@@ -174,6 +183,8 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   v.n_wave = n_wave;
   v.n_wave_pad = (n_wave + TILE_L - 1) / TILE_L * TILE_L;
   v.k_pad = n_met * AGE_PAD;
+  v.n_u = n_u;
+  v.k_row = n_u * v.k_pad;
   const int nwp = v.n_wave_pad, kp = v.k_pad;
   const bool want32 = precisions & (1 << DSPS_FP32), want16 = precisions & (1 << DSPS_BF16);
   const bool want_age = precisions & DSPS_SSP_AGE_MAJOR;
@@ -186,6 +197,10 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   met_edges[0] = -std::numeric_limits<double>::infinity();
   for (int j = 1; j < n_met; ++j) met_edges[j] = 0.5 * (lgz[j - 1] + lgz[j]);
   met_edges[n_met] = std::numeric_limits<double>::infinity();
+  std::vector<double> ion_edges(n_u + 1);
+  ion_edges[0] = -std::numeric_limits<double>::infinity();
+  for (int k = 1; k < n_u; ++k) ion_edges[k] = 0.5 * (lgu[k - 1] + lgu[k]);
+  ion_edges[n_u] = std::numeric_limits<double>::infinity();
   std::vector<float4> lconst(nwp);
   std::vector<float> qw(nwp, 0.0f);
   for (int l = 0; l < nwp; ++l) {
@@ -205,10 +220,12 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   const size_t o_age = take(sizeof(double) * (n_age + 1));
   const size_t o_met = take(sizeof(double) * (n_met + 1));
   const size_t o_lg = take(sizeof(double) * n_age);
-  const size_t o_st32 = want32 ? take(sizeof(float) * (size_t)nwp * kp) : 0;
+  const size_t o_ion = take(sizeof(double) * (n_u + 1));
+  const size_t o_st32 = want32 ? take(sizeof(float) * (size_t)nwp * v.k_row) : 0;
   const size_t o_st16 = want16 ? take(sizeof(uint16_t) * (size_t)nwp * kp) : 0;
   const int sk_rows = (kp + TILE_L - 1) / TILE_L * TILE_L;
-  const size_t o_sk = want32 ? take(sizeof(float) * (size_t)sk_rows * nwp) : 0;
+  const bool want_sk = want32 && n_u == 1;   // the adjoint's table (no ionization axis)
+  const size_t o_sk = want_sk ? take(sizeof(float) * (size_t)sk_rows * nwp) : 0;
   const size_t o_sa = want_age ? take(sizeof(float) * (size_t)nwp * AGE_K) : 0;
   const size_t o_ks = take(sizeof(float) * kp);
   const size_t o_lc = take(sizeof(float4) * nwp);
@@ -234,6 +251,8 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
     if (rc) break;
     rc = hip_fail(hipMemcpy(b + o_lg, lg_age, sizeof(double) * n_age, hipMemcpyHostToDevice), "upload lg_age");
     if (rc) break;
+    rc = hip_fail(hipMemcpy(b + o_ion, ion_edges.data(), sizeof(double) * (n_u + 1), hipMemcpyHostToDevice), "upload ion edges");
+    if (rc) break;
     rc = hip_fail(hipMemcpy(b + o_lc, lconst.data(), sizeof(float4) * nwp, hipMemcpyHostToDevice), "upload lconst");
     if (rc) break;
     rc = hip_fail(hipMemcpy(b + o_q, qw.data(), sizeof(float) * nwp, hipMemcpyHostToDevice), "upload qweight");
@@ -241,7 +260,18 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
     const int rows = n_met * n_age;
     rc = hip_alloc((void **)&d_rows, sizeof(float) * n_lum, "SSP staging");
     if (rc) break;
-    rc = hip_fail(hipMemcpy(d_rows, lum, sizeof(float) * n_lum, hipMemcpyHostToDevice), "upload lum");
+    if (n_u == 1) {
+      rc = hip_fail(hipMemcpy(d_rows, lum, sizeof(float) * n_lum, hipMemcpyHostToDevice), "upload lum");
+    } else {
+      // one contiguous (met, age) block per ionization point: [u][met][age][l]
+      std::vector<float> slabs(n_lum);
+      const size_t slab = (size_t)rows * n_wave;
+      for (size_t r = 0; r < (size_t)rows; ++r)
+        for (int k = 0; k < n_u; ++k)
+          std::copy(lum + (r * n_u + k) * n_wave, lum + (r * n_u + k + 1) * n_wave,
+                    slabs.begin() + k * slab + r * n_wave);
+      rc = hip_fail(hipMemcpy(d_rows, slabs.data(), sizeof(float) * n_lum, hipMemcpyHostToDevice), "upload lum");
+    }
     if (rc) break;
     std::vector<float> kscale(kp, 1.0f);
     if (want16) {
@@ -258,11 +288,12 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
     }
     rc = hip_fail(hipMemcpy(b + o_ks, kscale.data(), sizeof(float) * kp, hipMemcpyHostToDevice), "upload kscale");
     if (rc) break;
-    rc = launch_pack_table(d_rows, d_q, n_met, n_age, n_wave, nwp, kp,
-                           want32 ? (float *)(b + o_st32) : nullptr,
-                           want16 ? (uint16_t *)(b + o_st16) : nullptr, nullptr);
+    for (int k = 0; k < n_u && !rc; ++k)
+      rc = launch_pack_table(d_rows + (size_t)k * rows * n_wave, d_q, n_met, n_age, n_wave, nwp, kp,
+                             v.k_row, want32 ? (float *)(b + o_st32) + (size_t)k * kp : nullptr,
+                             want16 ? (uint16_t *)(b + o_st16) : nullptr, nullptr);
     if (rc) break;
-    if (want32) rc = launch_pack_table_kmajor(d_rows, n_age, n_wave, nwp, kp, sk_rows,
+    if (want_sk) rc = launch_pack_table_kmajor(d_rows, n_age, n_wave, nwp, kp, sk_rows,
                                               (float *)(b + o_sk), nullptr);
     if (rc) break;
     if (want_age) rc = launch_pack_table_age(d_rows, n_met, n_age, n_wave, nwp, (float *)(b + o_sa), nullptr);
@@ -278,12 +309,13 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   v.age_edges = (const double *)(b + o_age);
   v.met_edges = (const double *)(b + o_met);
   v.lg_age = (const double *)(b + o_lg);
+  v.ion_edges = (const double *)(b + o_ion);
   v.st32 = want32 ? (const float *)(b + o_st32) : nullptr;
   v.st16 = want16 ? (const uint16_t *)(b + o_st16) : nullptr;
   v.kscale = (const float *)(b + o_ks);
   v.lconst = (const float4 *)(b + o_lc);
   v.qweight = (const float *)(b + o_q);
-  v.sk32 = want32 ? (const float *)(b + o_sk) : nullptr;
+  v.sk32 = want_sk ? (const float *)(b + o_sk) : nullptr;
   v.sk_rows = sk_rows;
   v.sa32 = want_age ? (const float *)(b + o_sa) : nullptr;
   dsps_ssp *h = new dsps_ssp();
@@ -297,6 +329,29 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const d
   h->v = v;
   h->alloc = base;
   *out = h;
+  return DSPS_OK;
+}
+
+extern "C" {
+
+int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz, const double *lg_age,
+                    const double *wave, const float *lum, int precisions, int k0_reading,
+                    dsps_ssp **out) {
+  return ssp_create(n_met, n_age, 1, n_wave, lgz, lg_age, nullptr, wave, lum, precisions,
+                    k0_reading, out);
+}
+
+int dsps_ssp_create_neb(int n_met, int n_age, int n_u, int n_wave, const double *lgz,
+                        const double *lg_age, const double *lgu, const double *wave,
+                        const float *lum, int precisions, int k0_reading, dsps_ssp **out) {
+  DSPS_CHECK(lgu, DSPS_ERR_ARG, "lgu is NULL");
+  return ssp_create(n_met, n_age, n_u, n_wave, lgz, lg_age, lgu, wave, lum, precisions, k0_reading,
+                    out);
+}
+
+int dsps_ssp_ion_info(const dsps_ssp *ssp, int *n_u) {
+  DSPS_CHECK(ssp && n_u, DSPS_ERR_ARG, "NULL argument to dsps_ssp_ion_info");
+  *n_u = ssp->v.n_u;
   return DSPS_OK;
 }
 
@@ -393,6 +448,7 @@ constexpr int BATCH_VJP = 65536;
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
   size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0, tobs = 0, dust_old = 0;
+  size_t ion = 0;
   int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
@@ -413,6 +469,7 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   if (op == DSPS_OP_SED) {
     L.meta = take(sizeof(GalaxyMeta) * (size_t)n_gal);
     L.tobs = take(sizeof(double) * (size_t)n_gal);
+    if (v.n_u > 1) L.ion = take(sizeof(GalaxyIon) * (size_t)n_gal);
     L.w = take(elem * (size_t)L.batch * v.k_pad);
     L.total = off;
     return L;
@@ -428,6 +485,7 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   const int w_cols = (v.sa32 && op == DSPS_OP_MAGS) ? std::max(v.k_pad, AGE_K) : v.k_pad;
   L.w = take(elem * (size_t)L.batch * w_cols);
   if (v.sa32 && op == DSPS_OP_MAGS) L.dust_old = take(sizeof(GalaxyDustOld) * (size_t)n_gal);
+  if (v.n_u > 1 && op == DSPS_OP_MAGS) L.ion = take(sizeof(GalaxyIon) * (size_t)n_gal);
   // float32 forward passes may carry the dust moments
   const int ncomp = mags_components(precision == DSPS_FP32);
   L.partial = take(sizeof(float) * (size_t)L.batch * L.n_chunks * ncomp * n_band);
@@ -463,6 +521,13 @@ static int check_pop(const dsps_pop *p, bool need_dust) {
   DSPS_CHECK(!p->av_old || (std::isfinite(p->dust_pivot) && std::isfinite(p->dust_width) &&
                             p->dust_width > 0.0),
              DSPS_ERR_ARG, "dust_pivot must be finite and dust_width finite and > 0 with av_old");
+  return DSPS_OK;
+}
+
+// The ionization distribution is needed exactly when the block has the axis.
+static int check_ion(const dsps_ssp *s, const dsps_pop *p) {
+  DSPS_CHECK(s->v.n_u == 1 || p->n_gal == 0 || (p->lgu && p->sigma_u), DSPS_ERR_ARG,
+             "the SSP block has an ionization axis: lgu and sigma_u are required");
   return DSPS_OK;
 }
 
@@ -518,6 +583,8 @@ static WeightsLaunch base_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, 
   a.gl = gauss_legendre16();
   a.av_old = p->av_old;
   a.delta_old = p->delta_old;
+  a.lgu = p->lgu;
+  a.sigma_u = p->sigma_u;
   a.ssp = ssp->v;
   return a;
 }
@@ -577,9 +644,12 @@ int dsps_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *p
   return launch_weights(a, stream);
 }
 
-int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, int apply_dust,
-             int precision, float *sed, void *workspace, size_t workspace_bytes,
-             hipStream_t stream) {
+}  // extern "C"
+
+// dsps_sed and, with ion_tangent 1 or 2, dsps_sed_ion_tangent.
+static int sed_common(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
+                      int apply_dust, int precision, int ion_tangent, float *sed, void *workspace,
+                      size_t workspace_bytes, hipStream_t stream) {
   DSPS_CHECK(ssp, DSPS_ERR_ARG, "ssp is NULL");
   DSPS_TRY(check_cosmo(cosmo));
   DSPS_TRY(check_pop(pop, apply_dust != 0));
@@ -587,6 +657,7 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, 
   DSPS_CHECK(!(apply_dust && pop->av_old), DSPS_ERR_UNSUPPORTED,
              "dsps_sed does not apply the age-dependent attenuation (dsps_mags does)");
   DSPS_TRY(check_precision(ssp, precision));
+  DSPS_TRY(check_ion(ssp, pop));
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(sed, DSPS_ERR_ARG, "sed is NULL");
   DSPS_TRY(check_device(ssp->device));
@@ -594,6 +665,7 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, 
   DSPS_TRY(check_workspace(workspace, workspace_bytes, L.total));
   char *ws = (char *)workspace;
   GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
+  GalaxyIon *ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
   for (int g0 = 0; g0 < pop->n_gal; g0 += L.batch) {
     const int cnt = std::min(L.batch, pop->n_gal - g0);
     WeightsLaunch a = base_weights(ssp, cosmo, pop);
@@ -603,6 +675,7 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, 
     a.w_pad = ws + L.w;
     a.w_pad_bf16 = precision == DSPS_BF16;
     a.meta = apply_dust ? meta : nullptr;
+    a.ion = ion;
     a.t_obs = (double *)(ws + L.tobs);
     DSPS_TRY(launch_weights(a, stream));
     SedLaunch s{};
@@ -613,10 +686,31 @@ int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, 
     s.g_count = cnt;
     s.w_pad = ws + L.w;
     s.meta = meta;
+    s.ion = ion;
+    s.ion_tangent = ion_tangent;
     s.sed = sed;
     DSPS_TRY(launch_sed_gemm(s, stream));
   }
   return DSPS_OK;
+}
+
+extern "C" {
+
+int dsps_sed(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop, int apply_dust,
+             int precision, float *sed, void *workspace, size_t workspace_bytes,
+             hipStream_t stream) {
+  return sed_common(ssp, cosmo, pop, apply_dust, precision, 0, sed, workspace, workspace_bytes,
+                    stream);
+}
+
+int dsps_sed_ion_tangent(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
+                         int apply_dust, int wrt, float *dsed, void *workspace,
+                         size_t workspace_bytes, hipStream_t stream) {
+  DSPS_CHECK(ssp, DSPS_ERR_ARG, "ssp is NULL");
+  DSPS_CHECK(wrt == 0 || wrt == 1, DSPS_ERR_ARG, "wrt must be 0 (lgu) or 1 (sigma_u)");
+  DSPS_CHECK(ssp->v.n_u > 1, DSPS_ERR_UNSUPPORTED, "the SSP block has no ionization axis");
+  return sed_common(ssp, cosmo, pop, apply_dust, DSPS_FP32, 1 + wrt, dsed, workspace,
+                    workspace_bytes, stream);
 }
 
 // Most 128-wavelength chunks one galaxy's window can span: the window holds
@@ -666,8 +760,11 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
     a.w_pad_age = 1;
     a.dust_old = (GalaxyDustOld *)(ws + L.dust_old);
   }
+  GalaxyIon *ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
+  a.ion = ion;
   DSPS_TRY(launch_weights(a, stream));
   MagsLaunch m{};
+  m.ion = ion;
   if (age_dust) {
     // ages whose transition weight is exactly 0 (young) or 1 (old): the
     // triweight's cumulative is 0 at or below -3 widths and 1 at or above +3
@@ -730,6 +827,10 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
   DSPS_CHECK(!pop->av_old || (precision == DSPS_FP32 && !moments && ssp->v.sa32), DSPS_ERR_UNSUPPORTED,
              "age-dependent attenuation needs float32, no moments and an SSP handle created with "
              "DSPS_SSP_AGE_MAJOR");
+  DSPS_TRY(check_ion(ssp, pop));
+  DSPS_CHECK(ssp->v.n_u == 1 || (!moments && !pop->av_old), DSPS_ERR_UNSUPPORTED,
+             "with an ionization axis dsps_mags computes neither dust moments nor the "
+             "age-dependent attenuation");
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(mags, DSPS_ERR_ARG, "mags is NULL");
   DSPS_TRY(check_device(ssp->device));
@@ -759,6 +860,8 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
   DSPS_CHECK(precision == DSPS_FP32, DSPS_ERR_UNSUPPORTED, "the adjoint runs in float32 only");
   DSPS_CHECK(!pop->av_old, DSPS_ERR_UNSUPPORTED,
              "the adjoint of the age-dependent attenuation is not available");
+  DSPS_CHECK(ssp->v.n_u == 1, DSPS_ERR_UNSUPPORTED,
+             "the adjoint over an ionization axis is not available");
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(mags_bar, DSPS_ERR_ARG, "mags_bar is NULL");
   DSPS_CHECK((bands == nullptr) == (moments == nullptr), DSPS_ERR_ARG,
@@ -842,6 +945,82 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
     for (int stage = 0; stage < 4; ++stage) DSPS_TRY(launch_vjp(v, stage, stream));
   }
   return DSPS_OK;
+}
+
+}  // extern "C"
+
+static int eqw_common(const dsps_ssp *ssp, const float *sed, const float *dsed, int n_gal,
+                      const dsps_line *lines, int n_line, float *eqw, float *deqw,
+                      hipStream_t stream) {
+  DSPS_CHECK(ssp && lines, DSPS_ERR_ARG, "ssp or lines is NULL");
+  DSPS_CHECK(n_gal >= 0, DSPS_ERR_SHAPE, "n_gal %d negative", n_gal);
+  DSPS_CHECK(n_line >= 1 && n_line <= DSPS_MAX_LINES, DSPS_ERR_SHAPE, "n_line %d outside [1, %d]",
+             n_line, DSPS_MAX_LINES);
+  const std::vector<double> &w = ssp->wave_host;
+  const int n_wave = (int)w.size();
+  EqwLaunch a{};
+  a.wave = ssp->v.wave;
+  a.sed = sed;
+  a.dsed = dsed;
+  a.n_gal = n_gal;
+  a.n_wave = n_wave;
+  a.n_line = n_line;
+  a.eqw = eqw;
+  a.deqw = deqw;
+  for (int li = 0; li < n_line; ++li) {
+    const dsps_line &L = lines[li];
+    DSPS_CHECK(std::isfinite(L.centre) && std::isfinite(L.fit_half_width) && L.half_width > 0.0 &&
+                   L.half_width < L.fit_half_width,
+               DSPS_ERR_ARG, "line %d: need finite values with 0 < half_width < fit_half_width", li);
+    // both windows are contiguous on the ascending grid
+    int f0 = n_wave, f1 = 0, m0 = n_wave, m1 = 0;
+    for (int n = 0; n < n_wave; ++n) {
+      const double d = std::fabs(w[n] - L.centre);
+      if (d <= L.fit_half_width) { f0 = std::min(f0, n); f1 = n + 1; }
+      if (d <= L.half_width) { m0 = std::min(m0, n); m1 = n + 1; }
+    }
+    if (m1 <= m0) m0 = m1 = 0;
+    DSPS_CHECK(m1 - m0 >= 2 && (f1 - f0) - (m1 - m0) >= 3, DSPS_ERR_SHAPE,
+               "line %d: %d window and %d continuum points on the grid (need >= 2 and >= 3)", li,
+               m1 - m0, std::max(0, (f1 - f0) - (m1 - m0)));
+    EqwLine &e = a.line[li];
+    e.centre = L.centre;
+    e.inv_fit = 1.0 / L.fit_half_width;
+    e.f0 = f0; e.f1 = f1; e.m0 = m0; e.m1 = m1;
+    // normal matrix of the quadratic fit, inverted by cofactors
+    long double S[5] = {0, 0, 0, 0, 0};
+    for (int n = f0; n < f1; ++n) {
+      if (n >= m0 && n < m1) continue;
+      const long double x = (long double)((w[n] - L.centre) * e.inv_fit);
+      long double p = 1.0L;
+      for (int k = 0; k < 5; ++k) { S[k] += p; p *= x; }
+    }
+    const long double g00 = S[0], g01 = S[1], g02 = S[2], g11 = S[2], g12 = S[3], g22 = S[4];
+    const long double a00 = g11 * g22 - g12 * g12, a01 = g02 * g12 - g01 * g22,
+                      a02 = g01 * g12 - g02 * g11, a11 = g00 * g22 - g02 * g02,
+                      a12 = g01 * g02 - g00 * g12, a22 = g00 * g11 - g01 * g01;
+    const long double det = g00 * a00 + g01 * a01 + g02 * a02;
+    DSPS_CHECK(det > 0.0L, DSPS_ERR_SHAPE, "line %d: continuum fit is singular", li);
+    e.ginv[0] = (double)(a00 / det); e.ginv[1] = (double)(a01 / det); e.ginv[2] = (double)(a02 / det);
+    e.ginv[3] = (double)(a11 / det); e.ginv[4] = (double)(a12 / det); e.ginv[5] = (double)(a22 / det);
+  }
+  if (n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(sed && eqw, DSPS_ERR_ARG, "sed or eqw is NULL");
+  DSPS_TRY(check_device(ssp->device));
+  return launch_eqw(a, stream);
+}
+
+extern "C" {
+
+int dsps_eqw(const dsps_ssp *ssp, const float *sed, int n_gal, const dsps_line *lines, int n_line,
+             float *eqw, hipStream_t stream) {
+  return eqw_common(ssp, sed, nullptr, n_gal, lines, n_line, eqw, nullptr, stream);
+}
+
+int dsps_eqw_jvp(const dsps_ssp *ssp, const float *sed, const float *dsed, int n_gal,
+                 const dsps_line *lines, int n_line, float *eqw, float *deqw, hipStream_t stream) {
+  DSPS_CHECK(n_gal == 0 || (dsed && deqw), DSPS_ERR_ARG, "dsed or deqw is NULL");
+  return eqw_common(ssp, sed, dsed, n_gal, lines, n_line, eqw, deqw, stream);
 }
 
 static int check_summary(const float *mags, int n_gal, int n_band, int band_a, int band_b,

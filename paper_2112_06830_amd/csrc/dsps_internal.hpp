@@ -3,7 +3,8 @@
 // Layout decisions for gfx950 (see the design notes in the repository):
 //  * The SSP block is stored wavelength-major, ST[l][k] with k = met * 96 + age
 //    (ages zero-padded to 96 so that every 16- or 64-wide K block stays inside
-//    one metallicity row).  Both GEMM operands are then K-contiguous rows, which
+//    one metallicity row).  With the nebular ionization axis each table row
+//    holds one such block per ionization point, ST[l][u * k_pad + k].  Both GEMM operands are then K-contiguous rows, which
 //    load as 16-byte vectors and feed MFMA fragments straight from LDS.
 //  * Galaxies are processed in redshift order so that a 128-galaxy tile shares
 //    one rest-frame wavelength window; per-galaxy scalars live in SoA arrays
@@ -58,11 +59,14 @@ struct SspView {
   int n_met, n_age, n_wave;
   int n_wave_pad;                  // multiple of TILE_L
   int k_pad;                       // n_met * AGE_PAD
+  int n_u;                         // ionization points (1 without the axis)
+  int k_row;                       // columns of st32: n_u * k_pad
+  const double *ion_edges;         // [n_u + 1] log10 U_s: -inf, midpoints, +inf
   const double *wave;              // [n_wave] rest Angstrom (float64)
   const double *age_edges;         // [n_age + 1] Gyr: 0, midpoints, +inf
   const double *met_edges;         // [n_met + 1] log10 Z: -inf, midpoints, +inf
   const double *lg_age;            // [n_age]
-  const float *st32;               // [n_wave_pad][k_pad] or null
+  const float *st32;               // [n_wave_pad][k_row] or null
   const uint16_t *st16;            // [n_wave_pad][k_pad] bf16 of lum / scale, or null
   const float *kscale;             // [k_pad] power-of-two row scales (1 on padding)
   const float4 *lconst;            // [n_wave_pad] (lambda, log2(lambda/5500), k0, drude shape)
@@ -127,6 +131,12 @@ struct GalaxyDustOld {
   float dust_a;  // as GalaxyMeta::dust_a, for av_old
   float delta;
 };
+// Ionization distribution of a galaxy (nebular axis), by sorted position:
+// centre, width and the grid points [u_lo, u_hi] its triweight reaches.
+struct GalaxyIon {
+  float lgu, sigma_u;
+  int u_lo, u_hi;
+};
 
 // ------------------------------------------------------------- device math
 __device__ __forceinline__ double triweight_cdf(double z) {
@@ -159,10 +169,38 @@ __device__ __forceinline__ double mdf_centre(double a, double lgmet, bool transi
                     : lgmet + slope * (a - pivot);
 }
 
+// Weight of ionization point u (Section 3.3, Eq. nebsed): the triweight mass
+// of the galaxy's distribution inside the point's bin.
+__device__ __forceinline__ double ion_weight(const double *ion_edges, int u, double centre,
+                                             double sigma) {
+  const double inv = 1.0 / sigma;
+  return triweight_cdf((ion_edges[u + 1] - centre) * inv) - triweight_cdf((ion_edges[u] - centre) * inv);
+}
+
 __device__ __forceinline__ double triweight_pdf(double z) {
   if (z <= -3.0 || z >= 3.0) return 0.0;
   const double u = 1.0 - z * z * (1.0 / 9.0);
   return (35.0 / 96.0) * u * u * u;
+}
+
+// Derivative of ion_weight with respect to the centre (WRT 1) or the width
+// (WRT 2): with z_e = (e - centre)/sigma and T the triweight density,
+// -(T(z_{u+1}) - T(z_u))/sigma and -(z_{u+1} T(z_{u+1}) - z_u T(z_u))/sigma;
+// the infinite outer edges contribute nothing.  WRT 0 is the weight itself.
+template <int WRT>
+__device__ __forceinline__ double ion_weight_d(const double *ion_edges, int u, double centre,
+                                               double sigma) {
+  if (WRT == 0) return ion_weight(ion_edges, u, centre, sigma);
+  const double inv = 1.0 / sigma;
+  double t[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const double e = ion_edges[u + s];
+    const double z = (e - centre) * inv;
+    const double d = triweight_pdf(z);
+    t[s] = isinf(e) ? 0.0 : (WRT == 1 ? d : z * d);
+  }
+  return -(t[1] - t[0]) * inv;
 }
 
 // Round-to-nearest-even float32 -> bfloat16 bits (finite inputs).
@@ -247,6 +285,7 @@ struct WeightsLaunch {
   const float *lgmet_old;    // transition MDF (old-age centre), or null (linear model)
   double mdf_width;
   const float *av_old, *delta_old;   // age-dependent attenuation, or null
+  const float *lgu, *sigma_u;        // ionization distribution (n_u > 1), or null
   CosmoArgs cosmo;
   GaussLegendre gl;
   SspView ssp;
@@ -260,6 +299,7 @@ struct WeightsLaunch {
   int w_pad_bf16;
   int w_pad_age;             // w_pad is float32 age-major [s_count][AGE_K] instead
   GalaxyDustOld *dust_old;   // [n_gal] by sorted position (age-dependent attenuation)
+  GalaxyIon *ion;            // [n_gal] by sorted position (ionization axis), or null
   GalaxyMeta *meta;          // [n_gal] by sorted position
   GalaxyRange *range;        // [n_gal] by sorted position
   double *mag_offset;        // [n_gal] D_mod(z) - 2.5 log10(1+z), by sorted position
@@ -286,9 +326,11 @@ struct SortLaunch {
 int launch_sort(const SortLaunch &a, hipStream_t stream);
 int launch_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float *scale,
                          hipStream_t stream);
+// Tables are written as rows of dst_stride elements (k_pad, or n_u * k_pad
+// for one ionization point's block of a wider row).
 int launch_pack_table(const float *lum_rows, const uint16_t *q_rows, int n_met, int n_age,
-                      int n_wave, int n_wave_pad, int k_pad, float *st32, uint16_t *st16,
-                      hipStream_t stream);
+                      int n_wave, int n_wave_pad, int k_pad, int dst_stride, float *st32,
+                      uint16_t *st16, hipStream_t stream);
 int launch_pack_table_age(const float *lum_rows, int n_met, int n_age, int n_wave, int n_wave_pad,
                           float *sa32, hipStream_t stream);
 int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n_wave_pad,
@@ -297,13 +339,15 @@ int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n
 // Defined in k_mags.hip.
 // Per 128-galaxy tile of the fused contraction, computed once before it: the
 // union of the members' wavelength windows as chunks [c_first, c_last), the
-// range of 1 + z, and the K offsets of the stages that hold a non-zero weight
-// for some member, in ascending order.
+// range of 1 + z, the K offsets of the stages that hold a non-zero weight
+// for some member, in ascending order, and the ionization points [u_lo, u_hi]
+// some member's distribution reaches (0, 0 without the axis).
 struct TilePlan {
   int c_first, c_last;
   int nk;
   float zp1_min, zp1_max;
-  int pad[3];
+  int u_lo, u_hi;
+  int pad;
   int koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];
 };
 
@@ -322,6 +366,7 @@ struct MagsLaunch {
   const GalaxyDustOld *dust_old;
   int age_young, age_old;
   double dust_pivot, dust_width;
+  const GalaxyIon *ion;          // ionization axis (float32 only), by sorted position, or null
   int n_groups;                  // workgroups per tile (upper bound on its chunk groups)
   int n_chunks;                  // n_wave_pad / TILE_L
   int moments;                   // also the three dust moments per band (float32 only)
@@ -351,6 +396,26 @@ struct FinalizeLaunch {
 };
 int launch_mags_finalize(const FinalizeLaunch &a, hipStream_t stream);
 
+// Defined in k_eqw.hip.  Per line: centre, 1 / fit_half_width, the grid
+// index ranges of the neighbourhood [f0, f1) and of the line window [m0, m1)
+// (the continuum points are the first without the second), and the inverse
+// of the continuum fit's normal matrix, upper triangle row by row.
+struct EqwLine {
+  double centre, inv_fit;
+  int f0, f1, m0, m1;
+  double ginv[6];
+};
+struct EqwLaunch {
+  const double *wave;   // [n_wave] rest Angstrom, device
+  const float *sed;     // [n_gal][n_wave]
+  const float *dsed;    // [n_gal][n_wave] tangent of the SED, or null
+  int n_gal, n_wave, n_line;
+  float *eqw;           // [n_gal][n_line]
+  float *deqw;          // [n_gal][n_line] tangent of the widths (with dsed)
+  EqwLine line[DSPS_MAX_LINES];
+};
+int launch_eqw(const EqwLaunch &a, hipStream_t stream);
+
 // Defined in k_sed.hip.
 struct SedLaunch {
   SspView ssp;
@@ -358,6 +423,10 @@ struct SedLaunch {
   int g_begin, g_count;
   const void *w_pad;            // [g_count][k_pad]
   const GalaxyMeta *meta;       // by galaxy index (identity order)
+  const GalaxyIon *ion;         // by galaxy index, or null (no ionization axis)
+  // with ion: 0 the SED, 1 its derivative in the ionization centre, 2 in the
+  // ionization width (the weights of the points replaced by their derivatives)
+  int ion_tangent;
   float *sed;                   // [n_gal][n_wave]
 };
 int launch_sed_gemm(const SedLaunch &a, hipStream_t stream);

@@ -8,6 +8,8 @@
 // LDS reads.
 #pragma once
 
+#include <type_traits>
+
 #include "dsps_internal.hpp"
 
 namespace dsps {
@@ -56,18 +58,18 @@ struct StageRegs {
 
 template <int PREC>
 __device__ __forceinline__ void load_stage(StageRegs<PREC> &r, const typename GemmCfg<PREC>::elem *st,
-                                           int k_pad, int l0, const typename GemmCfg<PREC>::elem *w,
-                                           int g0, int g_count, int kofs) {
+                                           int a_stride, int l0, const typename GemmCfg<PREC>::elem *w,
+                                           int b_stride, int g0, int g_count, int a_ofs, int b_ofs) {
   using S = StageRegs<PREC>;
   constexpr int EPV = 16 / sizeof(typename GemmCfg<PREC>::elem);  // elements per vector
 #pragma unroll
   for (int v = 0; v < S::NV; ++v) {
     const int idx = threadIdx.x + v * GEMM_THREADS;
     const int row = idx / STAGE_UNITS, col = idx % STAGE_UNITS;
-    r.a[v] = *reinterpret_cast<const u32x4 *>(st + (size_t)(l0 + row) * k_pad + kofs + col * EPV);
+    r.a[v] = *reinterpret_cast<const u32x4 *>(st + (size_t)(l0 + row) * a_stride + a_ofs + col * EPV);
     u32x4 bv = {0u, 0u, 0u, 0u};
     if (g0 + row < g_count)
-      bv = *reinterpret_cast<const u32x4 *>(w + (size_t)(g0 + row) * k_pad + kofs + col * EPV);
+      bv = *reinterpret_cast<const u32x4 *>(w + (size_t)(g0 + row) * b_stride + b_ofs + col * EPV);
     r.b[v] = bv;
   }
 }
@@ -83,6 +85,28 @@ __device__ __forceinline__ void store_stage(const StageRegs<PREC> &r, GemmSmem<P
     sm.b[u] = r.b[v];
   }
 }
+
+// B rows times per-row factors (float32 stages): row r of the staged B slice
+// is multiplied by scale[r], rounded once per element.
+__device__ __forceinline__ void scale_stage_b(StageRegs<DSPS_FP32> &r, const float *scale) {
+  using S = StageRegs<DSPS_FP32>;
+#pragma unroll
+  for (int v = 0; v < S::NV; ++v) {
+    const float f = scale[(threadIdx.x + v * GEMM_THREADS) / STAGE_UNITS];
+    r.b[v].x = __float_as_uint(__uint_as_float(r.b[v].x) * f);
+    r.b[v].y = __float_as_uint(__uint_as_float(r.b[v].y) * f);
+    r.b[v].z = __float_as_uint(__uint_as_float(r.b[v].z) * f);
+    r.b[v].w = __float_as_uint(__uint_as_float(r.b[v].w) * f);
+  }
+}
+
+// Where K stage s comes from, for K loops whose operands do not share K
+// offsets: the offset in A and in B, and an LDS row of per-B-row factors
+// applied as the stage is written to LDS (float32 only).
+struct StageSrc {
+  int a, b;
+  const float *bscale;
+};
 
 __device__ __forceinline__ float4 as_float4(u32x4 v) {
   return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
@@ -150,32 +174,62 @@ __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_BF16> &sm, int wr,
 // registers, with one barrier per stage.  On entry no wave may still read
 // sm; on return every wave has passed a barrier after its last read of it.
 // after(ks) runs in every wave right after the MFMAs of stage ks (register
-// work on the accumulators only).
+// work on the accumulators only).  koff(s) returns the common K offset of
+// both operands (an int), or a StageSrc; with StageSrc, A rows are a_stride
+// and B rows b_stride elements apart.
 struct NoStageHook {
   __device__ void operator()(int) const {}
 };
 template <int PREC, typename KOffset, typename StageHook = NoStageHook>
-__device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const typename GemmCfg<PREC>::elem *st,
-                                           int k_pad, int l0, const typename GemmCfg<PREC>::elem *w,
-                                           int g0, int g_count, int nk, KOffset koff, int wr, int wc,
-                                           int lane, f32x16 (&acc)[2][2],
-                                           StageHook after = StageHook()) {
+__device__ __forceinline__ void gemm_kloop_ab(GemmSmem<PREC> *sm,
+                                              const typename GemmCfg<PREC>::elem *st, int a_stride,
+                                              int l0, const typename GemmCfg<PREC>::elem *w,
+                                              int b_stride, int g0, int g_count, int nk,
+                                              KOffset koff, int wr, int wc, int lane,
+                                              f32x16 (&acc)[2][2], StageHook after = StageHook()) {
+  constexpr bool SCALED = std::is_same_v<decltype(koff(0)), StageSrc>;
+  static_assert(!SCALED || PREC == DSPS_FP32, "per-row B factors are float32 only");
   StageRegs<PREC> regs;
+  const float *pending = nullptr;   // B factors of the stage held in regs
+  auto load = [&](int s) {
+    if constexpr (SCALED) {
+      const StageSrc src = koff(s);
+      load_stage<PREC>(regs, st, a_stride, l0, w, b_stride, g0, g_count, src.a, src.b);
+      pending = src.bscale;
+    } else {
+      const int k = koff(s);
+      load_stage<PREC>(regs, st, a_stride, l0, w, b_stride, g0, g_count, k, k);
+    }
+  };
+  auto store = [&](GemmSmem<PREC> &buf) {
+    if constexpr (SCALED) scale_stage_b(regs, pending);
+    store_stage<PREC>(regs, buf);
+  };
   if (nk > 0) {
-    load_stage<PREC>(regs, st, k_pad, l0, w, g0, g_count, koff(0));
-    store_stage<PREC>(regs, sm[0]);
-    if (nk > 1) load_stage<PREC>(regs, st, k_pad, l0, w, g0, g_count, koff(1));
+    load(0);
+    store(sm[0]);
+    if (nk > 1) load(1);
   }
   __syncthreads();
   for (int ks = 0; ks < nk; ++ks) {
     mma_stage(sm[ks & 1], wr, wc, lane, acc);
     after(ks);
     if (ks + 1 < nk) {
-      store_stage<PREC>(regs, sm[(ks + 1) & 1]);
-      if (ks + 2 < nk) load_stage<PREC>(regs, st, k_pad, l0, w, g0, g_count, koff(ks + 2));
+      store(sm[(ks + 1) & 1]);
+      if (ks + 2 < nk) load(ks + 2);
     }
     __syncthreads();
   }
+}
+
+// Both operands with rows of k_pad elements and a common K offset per stage.
+template <int PREC, typename KOffset, typename StageHook = NoStageHook>
+__device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const typename GemmCfg<PREC>::elem *st,
+                                           int k_pad, int l0, const typename GemmCfg<PREC>::elem *w,
+                                           int g0, int g_count, int nk, KOffset koff, int wr, int wc,
+                                           int lane, f32x16 (&acc)[2][2],
+                                           StageHook after = StageHook()) {
+  gemm_kloop_ab<PREC>(sm, st, k_pad, l0, w, k_pad, g0, g_count, nk, koff, wr, wc, lane, acc, after);
 }
 
 // Bands whose support meets the observed wavelengths [o_lo, o_hi] (with a

@@ -178,17 +178,30 @@ __device__ __forceinline__ void band_pass(const f32x16 (&acc)[2][2], const EpiLa
 // its own, the old-star ages as one group.  At a group's last stage every
 // wave folds the group's partial SED into a second accumulator,
 // sed += F_att(group) * acc, and restarts acc.
-template <int PREC, bool MOM, bool AGED = false>
-__global__ __launch_bounds__(GEMM_THREADS, (MOM || AGED) ? 2 : 3) void k_mags_gemm(MagsLaunch a) {
+//
+// NEB (Section 3.3, Eq. nebsed): the table rows hold one (metallicity, age)
+// block per ionization point, and the K loop runs over the tile's stages once
+// per ionization point some member reaches.  A galaxy's weight row is the
+// same for every point; it is multiplied by the galaxy's weight of the point
+// as each stage is staged into LDS, so the accumulator sums the cells of all
+// three axes.
+enum { MAGS_PLAIN = 0, MAGS_AGED = 1, MAGS_NEB = 2 };
+template <int PREC, bool MOM, int VAR = MAGS_PLAIN>
+__global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) void k_mags_gemm(MagsLaunch a) {
   using C = GemmCfg<PREC>;
   using elem = typename C::elem;
+  constexpr bool AGED = VAR == MAGS_AGED, NEB = VAR == MAGS_NEB;
+  static_assert(!(AGED || NEB) || (PREC == DSPS_FP32 && !MOM), "float32 forward only");
   constexpr int NCOMP = MOM ? 5 : 2;
   static_assert(2 * sizeof(GemmSmem<PREC>) >= sizeof(float) * 128 * NCOMP * NSLOT, "reduction alias");
   __shared__ GemmSmem<PREC> sm[2];
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
   __shared__ int s_koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];   // K offset of each stage
-  extern __shared__ float s_tr[];      // filter transmissions [n_band][n_pts + 1]
+  // dynamic: filter transmissions [n_band][n_pts + 1], then with NEB the
+  // members' ionization weights [point - u_lo][column] (n_u points at most)
+  extern __shared__ float s_tr[];
+  float *s_pn = s_tr + a.flt.n_band * filter_stride(a.flt.n_pts);
   float *s_red = reinterpret_cast<float *>(&sm[0]);
 
   int tile, group;
@@ -201,7 +214,7 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || AGED) ? 2 : 3) void k_mags_ge
   const int h = lane >> 5;
   const SspView P = a.ssp;        // by value: a reference into the kernel
   const FilterView F = a.flt;     // argument would force a private-memory copy
-  const int n_band = F.n_band, n_pts = F.n_pts;
+  const int n_band = F.n_band;
   const int g0 = tile * TILE_G;                 // first batch-local galaxy of the tile
   const int nvalid = min(TILE_G, a.s_count - g0);
 
@@ -218,6 +231,20 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || AGED) ? 2 : 3) void k_mags_ge
   const int nk = pl->nk;
   const float zp1_min = pl->zp1_min, zp1_max = pl->zp1_max;
   for (int t = threadIdx.x; t < nk; t += blockDim.x) s_koff[t] = pl->koff[t];
+  int u_lo = 0, n_uu = 1;
+  if constexpr (NEB) {
+    u_lo = pl->u_lo;
+    n_uu = pl->u_hi - pl->u_lo + 1;
+    for (int t = threadIdx.x; t < n_uu * TILE_G; t += blockDim.x) {
+      const int uu = t / TILE_G, col = t - uu * TILE_G;
+      float f = 0.0f;
+      if (col < nvalid) {
+        const GalaxyIon gi = a.ion[a.s_begin + g0 + col];
+        f = (float)ion_weight(P.ion_edges, u_lo + uu, gi.lgu, gi.sigma_u);
+      }
+      s_pn[t] = f;
+    }
+  }
 
   // ---- filter tables into LDS
   fill_filter_table(F, s_tr);
@@ -307,6 +334,15 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || AGED) ? 2 : 3) void k_mags_ge
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = sed[mb][nb];
+    } else if constexpr (NEB) {
+      // stage s: ionization point u_lo + s / nk, K block s_koff[s % nk]
+      gemm_kloop_ab<PREC>(sm, st, P.k_row, l0, w, k_cols, g0, a.s_count, nk * n_uu,
+                          [&](int s) {
+                            const int uu = s / nk;
+                            const int k = s_koff[s - uu * nk];
+                            return StageSrc{(u_lo + uu) * k_cols + k, k, s_pn + uu * TILE_G};
+                          },
+                          wr, wc, lane, acc);
     } else {
       gemm_kloop<PREC>(sm, st, k_cols, l0, w, g0, a.s_count, nk, [&](int ks) { return s_koff[ks]; },
                        wr, wc, lane, acc);
@@ -398,13 +434,14 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
   using C = GemmCfg<PREC>;
   // window lo, window hi, min and max of (1+z) as float bits (positive floats
   // order like their bit patterns)
-  __shared__ int s_tile[5];   // + highest non-zero age (age-major stages)
+  __shared__ int s_tile[7];   // + highest non-zero age (age-major stages), ionization points
   __shared__ unsigned s_kblk[KBLOCK_WORDS];
   const int tile = blockIdx.x;
   const int g0 = tile * TILE_G;
   const int nvalid = min(TILE_G, a.s_count - g0);
   if (threadIdx.x == 0) {
     s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0; s_tile[4] = 0;
+    s_tile[5] = a.ion ? 1 << 30 : 0; s_tile[6] = 0;
 #pragma unroll
     for (int w = 0; w < KBLOCK_WORDS; ++w) s_kblk[w] = 0u;
   }
@@ -417,6 +454,11 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
     atomicMin(&s_tile[2], zbits);
     atomicMax(&s_tile[3], zbits);
     atomicMax(&s_tile[4], r.age_hi);
+    if (a.ion) {
+      const GalaxyIon gi = a.ion[a.s_begin + g0 + threadIdx.x];
+      atomicMin(&s_tile[5], gi.u_lo);
+      atomicMax(&s_tile[6], gi.u_hi);
+    }
 #pragma unroll
     for (int w = 0; w < KBLOCK_WORDS; ++w)
       if (r.kblk[w]) atomicOr(&s_kblk[w], r.kblk[w]);
@@ -446,22 +488,29 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
   pl->nk = n;
   pl->zp1_min = __int_as_float(s_tile[2]);
   pl->zp1_max = __int_as_float(s_tile[3]);
+  pl->u_lo = s_tile[5];
+  pl->u_hi = s_tile[6];
 }
 
 int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
   const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
   const int blocks = (n_tiles + 7) / 8 * 8 * a.n_groups;
-  const size_t lds = sizeof(float) * a.flt.n_band * filter_stride(a.flt.n_pts);
+  size_t lds = sizeof(float) * a.flt.n_band * filter_stride(a.flt.n_pts);
   if (a.precision == DSPS_BF16)
     hipLaunchKernelGGL(k_tile_plan<DSPS_BF16>, dim3(n_tiles), dim3(TILE_G), 0, stream, a);
   else
     hipLaunchKernelGGL(k_tile_plan<DSPS_FP32>, dim3(n_tiles), dim3(TILE_G), 0, stream, a);
   ProfScope prof(DSPS_KERNEL_MAGS_GEMM, stream);
   if (a.age_dust) {
-    if (a.precision != DSPS_FP32 || a.moments || !a.ssp.sa32) return DSPS_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((k_mags_gemm<DSPS_FP32, false, true>), dim3(blocks), dim3(GEMM_THREADS), lds,
-                       stream, a);
+    if (a.precision != DSPS_FP32 || a.moments || !a.ssp.sa32 || a.ion) return DSPS_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_mags_gemm<DSPS_FP32, false, MAGS_AGED>), dim3(blocks), dim3(GEMM_THREADS),
+                       lds, stream, a);
+  } else if (a.ion) {
+    if (a.precision != DSPS_FP32 || a.moments || !a.ssp.st32) return DSPS_ERR_UNSUPPORTED;
+    lds += sizeof(float) * a.ssp.n_u * TILE_G;
+    hipLaunchKernelGGL((k_mags_gemm<DSPS_FP32, false, MAGS_NEB>), dim3(blocks), dim3(GEMM_THREADS),
+                       lds, stream, a);
   } else if (a.precision == DSPS_BF16) {
     if (a.moments) return DSPS_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((k_mags_gemm<DSPS_BF16, false>), dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);

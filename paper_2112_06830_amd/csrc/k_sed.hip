@@ -1,15 +1,23 @@
 // Unfused composite SED: L[g, l] = sum_k W[g, k] L_SSP[k, l] (Section 2.1,
 // Eqs. cspdeftheta and full_mdf), optionally times the attenuation F_att
-// (Section 3.4, Eq. attenuation), written to memory in the rest frame.
+// (Section 3.4, Eq. attenuation), written to memory in the rest frame.  With
+// the ionization axis (NEB; Section 3.3, Eq. nebsed) the sum also runs over
+// the ionization points the tile's galaxies reach, each galaxy's weight row
+// scaled by its weight of the point as it is staged; with ion_tangent the
+// weights are replaced by their derivatives in the distribution's centre or
+// width, which gives the SED's derivative (the sum is linear in them).
 #include "gemm_core.hpp"
 
 namespace dsps {
 
-template <int PREC>
+template <int PREC, bool NEB = false>
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   using C = GemmCfg<PREC>;
   using elem = typename C::elem;
+  static_assert(!NEB || PREC == DSPS_FP32, "the ionization axis is float32 only");
   __shared__ GemmSmem<PREC> sm[2];
+  __shared__ float s_pn[NEB ? DSPS_MAX_ION * TILE_G : 1];
+  __shared__ int s_urange[2];
   const int chunk = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
@@ -28,8 +36,44 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
       for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
 
   const int nk = P.k_pad / C::KT;
-  gemm_kloop<PREC>(sm, st, P.k_pad, l0, w, g0, a.g_count, nk, [](int ks) { return ks * C::KT; },
-                   wr, wc, lane, acc);
+  if constexpr (NEB) {
+    // the tile's ionization points, then every member's weight of each
+    if (threadIdx.x == 0) { s_urange[0] = 1 << 30; s_urange[1] = 0; }
+    __syncthreads();
+    const int nvalid = min(TILE_G, a.g_count - g0);
+    if ((int)threadIdx.x < nvalid) {
+      const GalaxyIon gi = a.ion[a.g_begin + g0 + threadIdx.x];
+      atomicMin(&s_urange[0], gi.u_lo);
+      atomicMax(&s_urange[1], gi.u_hi);
+    }
+    __syncthreads();
+    const int u_lo = s_urange[0], n_uu = s_urange[1] - s_urange[0] + 1;
+    for (int t = threadIdx.x; t < n_uu * TILE_G; t += blockDim.x) {
+      const int uu = t / TILE_G, col = t - uu * TILE_G;
+      float f = 0.0f;
+      if (col < nvalid) {
+        const GalaxyIon gi = a.ion[a.g_begin + g0 + col];
+        const int u = u_lo + uu;
+        const double c = gi.lgu, sg = gi.sigma_u;
+        f = (float)(a.ion_tangent == 1   ? ion_weight_d<1>(P.ion_edges, u, c, sg)
+                    : a.ion_tangent == 2 ? ion_weight_d<2>(P.ion_edges, u, c, sg)
+                                         : ion_weight(P.ion_edges, u, c, sg));
+      }
+      s_pn[t] = f;
+    }
+    __syncthreads();
+    const int kp = P.k_pad;
+    gemm_kloop_ab<PREC>(sm, st, P.k_row, l0, w, kp, g0, a.g_count, nk * n_uu,
+                        [&](int s) {
+                          const int uu = s / nk;
+                          const int k = (s - uu * nk) * C::KT;
+                          return StageSrc{(u_lo + uu) * kp + k, k, s_pn + uu * TILE_G};
+                        },
+                        wr, wc, lane, acc);
+  } else {
+    gemm_kloop<PREC>(sm, st, P.k_pad, l0, w, g0, a.g_count, nk, [](int ks) { return ks * C::KT; },
+                     wr, wc, lane, acc);
+  }
 
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
@@ -63,10 +107,14 @@ int launch_sed_gemm(const SedLaunch &a, hipStream_t stream) {
   if (a.g_count <= 0) return DSPS_OK;
   const dim3 grid(a.ssp.n_wave_pad / TILE_L, (a.g_count + TILE_G - 1) / TILE_G);
   ProfScope prof(DSPS_KERNEL_SED_GEMM, stream);
-  if (a.precision == DSPS_BF16)
+  if (a.ion) {
+    if (a.precision != DSPS_FP32 || !a.ssp.st32) return DSPS_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_sed_gemm<DSPS_FP32, true>), grid, dim3(GEMM_THREADS), 0, stream, a);
+  } else if (a.precision == DSPS_BF16) {
     hipLaunchKernelGGL(k_sed_gemm<DSPS_BF16>, grid, dim3(GEMM_THREADS), 0, stream, a);
-  else
+  } else {
     hipLaunchKernelGGL(k_sed_gemm<DSPS_FP32>, grid, dim3(GEMM_THREADS), 0, stream, a);
+  }
   return hip_fail(hipGetLastError(), "k_sed_gemm launch");
 }
 

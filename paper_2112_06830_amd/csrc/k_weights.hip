@@ -97,7 +97,8 @@ __device__ int first_index(const double *x, int n, double v) {
 
 // Per-galaxy scalars, one thread per galaxy of the sorted range: cosmic time
 // at z for the weights kernel, the GEMM's constants (1 + z and the dust
-// parameters), the magnitude offset and the rest-wavelength window.  The
+// parameters), the magnitude offset, the rest-wavelength window and, with the
+// ionization axis, the first and last grid points of non-zero weight.  The
 // window's non-zero weight blocks start as "all" and are narrowed by the
 // weights kernel when it runs.
 __global__ __launch_bounds__(256) void k_galaxy_scalars(WeightsLaunch a) {
@@ -115,6 +116,21 @@ __global__ __launch_bounds__(256) void k_galaxy_scalars(WeightsLaunch a) {
     m.delta = a.delta[g];
     m.bump = a.bump[g];
     a.meta[s] = m;
+  }
+  if (a.ion) {
+    GalaxyIon gi;
+    gi.lgu = a.lgu[g];
+    gi.sigma_u = a.sigma_u[g];
+    int lo = -1, hi = 0;
+    for (int u = 0; u < a.ssp.n_u; ++u) {
+      if (ion_weight(a.ssp.ion_edges, u, gi.lgu, gi.sigma_u) != 0.0) {
+        if (lo < 0) lo = u;
+        hi = u;
+      }
+    }
+    gi.u_lo = lo < 0 ? 0 : lo;
+    gi.u_hi = lo < 0 ? 0 : hi;
+    a.ion[s] = gi;
   }
   if (a.dust_old) {
     GalaxyDustOld d;
@@ -684,7 +700,7 @@ int launch_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack_table(const T *__restrict__ src, int n_age,
                                                     int n_wave, int n_wave_pad, int k_pad,
-                                                    T *__restrict__ dst) {
+                                                    int dst_stride, T *__restrict__ dst) {
   __shared__ T tile[32][33];
   const int k0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
@@ -698,7 +714,7 @@ __global__ __launch_bounds__(256) void k_pack_table(const T *__restrict__ src, i
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
     const int l = l0 + r, k = k0 + tx;
-    if (l < n_wave_pad && k < k_pad) dst[(size_t)l * k_pad + k] = tile[tx][r];
+    if (l < n_wave_pad && k < k_pad) dst[(size_t)l * dst_stride + k] = tile[tx][r];
   }
 }
 
@@ -754,14 +770,14 @@ int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n
 }
 
 int launch_pack_table(const float *lum_rows, const uint16_t *q_rows, int n_met, int n_age,
-                      int n_wave, int n_wave_pad, int k_pad, float *st32, uint16_t *st16,
-                      hipStream_t stream) {
+                      int n_wave, int n_wave_pad, int k_pad, int dst_stride, float *st32,
+                      uint16_t *st16, hipStream_t stream) {
   (void)n_met;
   const dim3 grid(k_pad / 32, n_wave_pad / 32);
   if (st32) hipLaunchKernelGGL(k_pack_table<float>, grid, dim3(256), 0, stream, lum_rows, n_age,
-                               n_wave, n_wave_pad, k_pad, st32);
+                               n_wave, n_wave_pad, k_pad, dst_stride, st32);
   if (st16) hipLaunchKernelGGL(k_pack_table<uint16_t>, grid, dim3(256), 0, stream, q_rows, n_age,
-                               n_wave, n_wave_pad, k_pad, st16);
+                               n_wave, n_wave_pad, k_pad, dst_stride, st16);
   return hip_fail(hipGetLastError(), "k_pack_table launch");
 }
 

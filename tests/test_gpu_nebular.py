@@ -1,0 +1,277 @@
+"""GPU parity, through the C ABI, of the nebular ionization axis (Section 3.3,
+Eq. nebsed) and of emission-line equivalent widths (Section 2.2.2, Eq. eqw):
+fused FP32 magnitudes and SEDs over the three-axis SSP block against the FP64
+oracle, the limits where the axis must reduce to the two-axis path, batch
+independence, the width kernel on fixed spectra and end to end, and the calls
+that do not support the axis.
+
+Tolerance of the widths: W = sum (L - L_0)/L_0 dlambda over the window.  A
+relative error e of the float32 SED moves each ratio by about e (1 + |r|)
+through L and by a multiple c of that through the continuum, which the fit
+evaluates inside the masked gap; for these windows c stays below 3 (2.3 under
+random +-e perturbations of oracle SEDs).  So |dW| <= 4 e (2 h + |W|) for a
+window of half-width h, 8e-5 (2 h + |W|) with e = 2e-5, the SED bound of the
+forward tests.  On identical float32 input the kernel and the oracle differ
+only by float64 rounding and the final float32 rounding."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import FP32_TOL_MAG, filters6, max_abs
+
+pytestmark = pytest.mark.gpu
+
+# [OII], Hbeta, [OIII] 5007, Halpha: (centre, half-width, fit half-width), Angstrom
+LINES = ((3727.42, 40.0, 150.0), (4862.68, 40.0, 150.0), (5008.24, 40.0, 150.0),
+         (6564.61, 50.0, 180.0))
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_06830_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def small(dev):
+    ssp = synth.make_ssp_nebular(n_u=7, n_wave=1000, wave_lo=1.0e3, wave_hi=2.0e4)
+    return dev.SspBlock.from_synth(ssp), dev.FilterBank.from_synth(filters6()), ssp
+
+
+@pytest.fixture(scope="module")
+def large(dev):
+    ssp = synth.make_ssp_nebular(n_u=7, n_wave=5994, wave_lo=9.0e2, wave_hi=2.5e4)
+    return dev.SspBlock.from_synth(ssp), dev.FilterBank.from_synth(filters6()), ssp
+
+
+def _pop(n, seed, z_range=(0.1, 1.0)):
+    return synth.make_population(n, n_t=100, z_range=z_range, seed=seed, nebular=True)
+
+
+def _inputs(ssp, pop):
+    return oracle.prepare_inputs(ssp, filters6(), pop)
+
+
+def test_nebular_mags_small_grid_match_oracle(dev, small):
+    ssp_h, flt_h, ssp = small
+    pop = _pop(100, seed=91)
+    inp = _inputs(ssp, pop)
+    _say("nebular mags small grid n_u=7 n_gal=100")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
+    assert max_abs(m, oracle.mags(inp)) < FP32_TOL_MAG
+
+
+@pytest.mark.parametrize("n_gal", [1, 129, 300])
+def test_nebular_mags_large_grid_match_oracle(dev, large, n_gal):
+    ssp_h, flt_h, ssp = large
+    pop = _pop(n_gal, seed=93, z_range=(0.1, 3.0))
+    _say(f"nebular mags large grid n_u=7 n_gal={n_gal}")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
+    assert max_abs(m, oracle.mags(_inputs(ssp, pop))) < FP32_TOL_MAG
+
+
+@pytest.mark.parametrize("apply_dust", [False, True])
+def test_nebular_sed_matches_oracle(dev, small, apply_dust):
+    ssp_h, _, ssp = small
+    pop = _pop(70, seed=95)
+    inp = _inputs(ssp, pop)
+    _say(f"nebular sed n_gal=70 dust={apply_dust}")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    got = dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=apply_dust).cpu().numpy()
+    ref = oracle.sed(inp, apply_dust=apply_dust)
+    assert (np.abs(got - ref) / ref).max() < 2e-5
+
+
+def test_nebular_batch_independent(dev, large):
+    """A galaxy's magnitudes are bitwise the same alone and in a population:
+    ionization points outside its own support carry exact zero weight."""
+    ssp_h, flt_h, ssp = large
+    pop = _pop(257, seed=97, z_range=(0.1, 3.0))
+    _say("nebular batch independence n_gal=257")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m_all = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
+    for g in (0, 100, 256):
+        one = dev.DevicePopulation.from_synth(pop.subset([g]), use_params=True)
+        np.testing.assert_array_equal(dev.mags(ssp_h, flt_h, dev.Cosmology(), one).cpu().numpy()[0],
+                                      m_all[g])
+
+
+def test_one_ionization_point_is_the_plain_block(dev):
+    base = synth.make_ssp(n_wave=1000, wave_lo=1.0e3, wave_hi=2.0e4)
+    one = synth.SspTable(lgz=base.lgz, lg_age=base.lg_age, wave=base.wave,
+                         lum=np.ascontiguousarray(base.lum[:, :, None, :]), lgu=np.array([-2.0]))
+    flt_h = dev.FilterBank.from_synth(filters6())
+    plain_h = dev.SspBlock.from_synth(base, precisions=("fp32",))
+    one_h = dev.SspBlock.from_synth(one)
+    pop = _pop(150, seed=99)
+    _say("one-point ionization axis n_gal=150")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    a = dev.mags(plain_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
+    b = dev.mags(one_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+
+
+def test_block_constant_over_u_is_the_plain_block(dev):
+    """Five identical slabs: the same positive terms as the plain block,
+    times weights that sum to one, grouped differently (each weight row is
+    rounded once more and the slabs add in turn).  Both results are float32
+    contractions of positive terms, each within the float32 target of the
+    exact value (checked here against the oracle of the plain block), so they
+    agree to that target; typical differences are ~sqrt(5 x 1128) float32
+    ulps (~5e-6 relative)."""
+    base = synth.make_ssp(n_wave=1000, wave_lo=1.0e3, wave_hi=2.0e4)
+    rep = np.ascontiguousarray(np.repeat(base.lum[:, :, None, :], 5, axis=2))
+    tab = synth.SspTable(lgz=base.lgz, lg_age=base.lg_age, wave=base.wave, lum=rep,
+                         lgu=np.linspace(-4.0, -2.0, 5))
+    flt_h = dev.FilterBank.from_synth(filters6())
+    plain_h = dev.SspBlock.from_synth(base, precisions=("fp32",))
+    rep_h = dev.SspBlock.from_synth(tab)
+    pop = _pop(150, seed=101)
+    _say("ionization axis constant over u n_gal=150")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    a = dev.mags(plain_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
+    b = dev.mags(rep_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
+    ref = oracle.mags(oracle.prepare_inputs(base, filters6(), pop))
+    assert max_abs(b, ref) < FP32_TOL_MAG and max_abs(a, ref) < FP32_TOL_MAG
+    assert max_abs(a, b) < FP32_TOL_MAG
+    assert np.median(np.abs(a - b)) < 2e-6
+
+
+def test_nebular_unsupported_calls(dev, small):
+    import torch
+    ssp_h, flt_h, ssp = small
+    pop = _pop(16, seed=103)
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    with pytest.raises(Exception, match="precision"):
+        dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, precision="bf16")
+    with pytest.raises(Exception, match="ionization"):
+        dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, torch.zeros((16, 6), device="cuda"))
+    with pytest.raises(Exception, match="ionization"):
+        dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_moments=True)
+    dp.lgu = None
+    with pytest.raises(Exception, match="lgu"):
+        dev.mags(ssp_h, flt_h, dev.Cosmology(), dp)
+
+
+# ---------------------------------------------------------------- Eq. eqw
+def test_eqw_matches_oracle_on_fixed_spectra(dev, small):
+    import torch
+    ssp_h, _, ssp = small
+    spec = synth.make_line_spectra(300, ssp.wave, LINES, seed=5)
+    _say("eqw fixed spectra n_gal=300")
+    got = dev.eqw(ssp_h, torch.tensor(spec, device="cuda"), LINES).cpu().numpy()
+    for k, (c, h, f) in enumerate(LINES):
+        ref = oracle.nebular.equivalent_width(ssp.wave, spec.astype(np.float64), c, h, f)
+        np.testing.assert_allclose(got[:, k], ref, rtol=1e-6, atol=1e-6)
+
+
+def test_eqw_end_to_end_matches_oracle(dev, small):
+    ssp_h, _, ssp = small
+    pop = _pop(64, seed=105)
+    pop.sfh_params[3] = 0.2 * pop.sfh_params[3]     # mostly star-forming: lines present
+    inp = _inputs(ssp, pop)
+    _say("eqw end to end n_gal=64")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    got = dev.eqw(ssp_h, dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=True), LINES).cpu().numpy()
+    spec = oracle.sed(inp, apply_dust=True)
+    for k, (c, h, f) in enumerate(LINES):
+        ref = oracle.nebular.equivalent_width(ssp.wave, spec, c, h, f)
+        assert np.all(np.abs(got[:, k] - ref) <= 8e-5 * (2 * h + np.abs(ref))), k
+    assert np.all(got[:, 2] > 0)                     # [OIII] in emission
+
+
+def test_eqw_shape_errors_and_empty(dev, small):
+    import torch
+    ssp_h, _, ssp = small
+    sed = torch.ones((3, ssp.wave.size), device="cuda")
+    with pytest.raises(Exception, match="window"):
+        dev.eqw(ssp_h, sed, [(5000.0, 0.5, 1.0)])          # no grid point in the window
+    with pytest.raises(Exception, match="half_width"):
+        dev.eqw(ssp_h, sed, [(5000.0, 50.0, 20.0)])
+    out = dev.eqw(ssp_h, sed[:0], LINES)
+    assert out.shape == (0, len(LINES))
+
+
+# ---------------------------------------------------------------- tangents
+def _abs_tangent_bound(inp, which, apply_dust):
+    """sum_k |dP_k| L_k (times the attenuation): the size of the terms the
+    tangent sums, against which its float32 error is bounded (the dP_k sum
+    to zero, so the tangent itself can cancel)."""
+    d_u, d_s = oracle.nebular.ionization_weight_derivatives(inp.lgu, inp.sigma_u, inp.lgu_grid)
+    b = oracle.nebular.sed_nebular(oracle.weights(inp), np.abs(d_u if which == "lgu" else d_s),
+                                   inp.lum)
+    if apply_dust:
+        b = b * oracle.dust.attenuation(inp.wave, inp.av, inp.delta, inp.bump, inp.k0_reading)
+    return b
+
+
+@pytest.mark.parametrize("which,apply_dust", [("lgu", True), ("sigma_u", False)])
+def test_sed_ion_tangent_matches_oracle(dev, small, which, apply_dust):
+    ssp_h, _, ssp = small
+    pop = _pop(70, seed=107)
+    inp = _inputs(ssp, pop)
+    _say(f"sed ionization tangent wrt={which} dust={apply_dust} n_gal=70")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    got = dev.sed_ion_tangent(ssp_h, dev.Cosmology(), dp, wrt=which,
+                              apply_dust=apply_dust).cpu().numpy()
+    ref = oracle.pipeline.sed_ion_tangent(inp, which, apply_dust=apply_dust)
+    bound = _abs_tangent_bound(inp, which, apply_dust)
+    assert np.all(np.abs(got - ref) <= 2e-5 * bound + 1e-30)
+    assert np.abs(ref).max() > 0
+
+
+def test_eqw_jvp_matches_oracle_on_fixed_spectra(dev, small):
+    import torch
+    ssp_h, _, ssp = small
+    spec = synth.make_line_spectra(200, ssp.wave, LINES, seed=7)
+    dspec = synth.make_line_spectra(200, ssp.wave, LINES, seed=8) - np.float32(1.0)
+    _say("eqw tangent fixed spectra n_gal=200")
+    w, dw = dev.eqw(ssp_h, torch.tensor(spec, device="cuda"), LINES,
+                    dsed=torch.tensor(dspec, device="cuda"))
+    w, dw = w.cpu().numpy(), dw.cpu().numpy()
+    for k, (c, h, f) in enumerate(LINES):
+        rw, rdw = oracle.nebular.equivalent_width_jvp(ssp.wave, spec.astype(np.float64),
+                                                      dspec.astype(np.float64), c, h, f)
+        np.testing.assert_allclose(w[:, k], rw, rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(dw[:, k], rdw, rtol=1e-6, atol=1e-6 * np.abs(rdw).max())
+
+
+def test_oiii_width_gradient_end_to_end_matches_oracle(dev, small):
+    """d W_[OIII] / d log10 U_s per galaxy (the paper's Section 3.3 example):
+    SED, SED tangent and width tangent on the GPU against the oracle's.  The
+    tangent's float32 error is bounded by 2e-5 of its absolute-value sum, the
+    SED's by 2e-5; through the fit (amplification < 3) the gradient moves by
+    at most 8e-5 (2 h max(|dL|_abs / L_0) + |dW|)."""
+    ssp_h, _, ssp = small
+    pop = _pop(48, seed=109)
+    pop.sfh_params[3] = 0.0                          # star-forming: lines present
+    inp = _inputs(ssp, pop)
+    _say("[OIII] width gradient end to end n_gal=48")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    sed = dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=True)
+    dsed = dev.sed_ion_tangent(ssp_h, dev.Cosmology(), dp, wrt="lgu", apply_dust=True)
+    c, h, f = LINES[2]
+    _, dw = dev.eqw(ssp_h, sed, [LINES[2]], dsed=dsed)
+    dw = dw.cpu().numpy()[:, 0]
+    spec = oracle.sed(inp, apply_dust=True)
+    dspec = oracle.pipeline.sed_ion_tangent(inp, "lgu", apply_dust=True)
+    _, ref = oracle.nebular.equivalent_width_jvp(ssp.wave, spec, dspec, c, h, f)
+    win = np.abs(ssp.wave - c) <= h
+    bound = _abs_tangent_bound(inp, "lgu", True)
+    scale = (bound[:, win] / spec[:, win]).max(axis=1)
+    assert np.all(np.abs(dw - ref) <= 8e-5 * (2 * h * scale + np.abs(ref)))
+    assert np.mean(ref > 0) > 0.9                    # stronger [OIII] at higher U_s

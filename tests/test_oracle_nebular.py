@@ -178,3 +178,79 @@ def test_too_few_points_give_nan():
     lam = np.linspace(4990.0, 5010.0, 5)
     ew = nebular.equivalent_width(lam, np.ones((2, 5)), 5000.0, 6.0, 8.0)
     assert np.all(np.isnan(ew))
+
+
+# ---------------------------------------------------------------- tangents
+def test_ionization_weight_derivatives_match_differences_and_sum_to_zero():
+    grid = np.linspace(-4.0, -1.0, 7)
+    centre = np.array([-3.1, -2.37, -1.6])
+    sigma = np.array([0.3, 0.22, 0.45])
+    d_u, d_s = nebular.ionization_weight_derivatives(centre, sigma, grid)
+    h = 1e-6
+    fd_u = (nebular.ionization_weights(centre + h, sigma, grid)
+            - nebular.ionization_weights(centre - h, sigma, grid)) / (2 * h)
+    fd_s = (nebular.ionization_weights(centre, sigma + h, grid)
+            - nebular.ionization_weights(centre, sigma - h, grid)) / (2 * h)
+    np.testing.assert_allclose(d_u, fd_u, rtol=0, atol=2e-8)
+    np.testing.assert_allclose(d_s, fd_s, rtol=0, atol=2e-8)
+    np.testing.assert_allclose(d_u.sum(axis=1), 0.0, atol=1e-14)
+    np.testing.assert_allclose(d_s.sum(axis=1), 0.0, atol=1e-14)
+    assert np.any(d_u != 0) and np.any(d_s != 0)
+
+
+@pytest.mark.parametrize("which", ["lgu", "sigma_u"])
+def test_sed_tangent_matches_central_difference(which):
+    ssp = synth.make_ssp_nebular(n_u=5, lgu_range=(-4.0, -2.0), n_wave=300, wave_lo=3000.0,
+                                 wave_hi=8000.0, n_met=4, n_age=12, lg_age_range=(6.0, 10.0))
+    pop = synth.make_population(3, n_t=80, z_range=(0.1, 0.3), seed=51, nebular=True)
+    flt = synth.make_filters()
+    got = oracle.pipeline.sed_ion_tangent(oracle.prepare_inputs(ssp, flt, pop), which,
+                                          apply_dust=True)
+    h = 1e-5
+    vals = getattr(pop, which).copy()
+    specs = []
+    for sgn in (1.0, -1.0):
+        setattr(pop, which, vals + sgn * h)
+        specs.append(oracle.sed(oracle.prepare_inputs(ssp, flt, pop), apply_dust=True))
+    setattr(pop, which, vals)
+    fd = (specs[0] - specs[1]) / (2 * h)
+    scale = np.abs(fd).max()
+    assert scale > 0
+    np.testing.assert_allclose(got, fd, rtol=0, atol=1e-6 * scale)
+
+
+def test_width_tangent_matches_central_difference():
+    lam = np.linspace(4800.0, 5200.0, 801)
+    spec = synth.make_line_spectra(4, lam, [(5000.0, 30.0)], seed=3).astype(np.float64)
+    dspec = synth.make_line_spectra(4, lam, [(5010.0, 20.0)], seed=4).astype(np.float64)
+    w, dw = nebular.equivalent_width_jvp(lam, spec, dspec, 5000.0, 30.0, 120.0)
+    np.testing.assert_array_equal(w, nebular.equivalent_width(lam, spec, 5000.0, 30.0, 120.0))
+    h = 1e-6
+    fd = (nebular.equivalent_width(lam, spec + h * dspec, 5000.0, 30.0, 120.0)
+          - nebular.equivalent_width(lam, spec - h * dspec, 5000.0, 30.0, 120.0)) / (2 * h)
+    np.testing.assert_allclose(dw, fd, rtol=1e-6, atol=1e-8)
+
+
+def test_oiii_width_gradient_in_u_is_positive_and_matches_differences():
+    """The paper's [OIII] example: d W / d log10 U_s > 0 for star-forming
+    galaxies, from the SED tangent and the width tangent, against central
+    differences of the width."""
+    ssp = synth.make_ssp_nebular(n_wave=900, wave_lo=3000.0, wave_hi=8000.0, n_met=4, n_age=20,
+                                 lg_age_range=(6.0, 10.0))
+    pop = synth.make_population(3, n_t=100, z_range=(0.1, 0.3), seed=53, nebular=True)
+    pop.sfh_params[3] = 0.0
+    pop.lgu = np.full(3, -2.0)
+    pop.sigma_u = np.full(3, 0.25)
+    flt = synth.make_filters()
+    inp = oracle.prepare_inputs(ssp, flt, pop)
+    spec = oracle.sed(inp)
+    dspec = oracle.pipeline.sed_ion_tangent(inp, "lgu")
+    _, dw = nebular.equivalent_width_jvp(ssp.wave, spec, dspec, 5008.24, 40.0, 150.0)
+    h = 1e-5
+    ws = []
+    for sgn in (1.0, -1.0):
+        pop.lgu = np.full(3, -2.0 + sgn * h)
+        ws.append(nebular.equivalent_width(ssp.wave, oracle.sed(oracle.prepare_inputs(ssp, flt, pop)),
+                                           5008.24, 40.0, 150.0))
+    np.testing.assert_allclose(dw, (ws[0] - ws[1]) / (2 * h), rtol=1e-5)
+    assert np.all(dw > 0)

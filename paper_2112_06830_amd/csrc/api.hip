@@ -561,6 +561,12 @@ static int sort_population(const dsps_ssp *ssp, const dsps_pop *p, int *hist, in
   s.lg_age_last = ssp->lg_age_last;
   s.met_edges = ssp->v.met_edges;
   s.n_met = ssp->v.n_met;
+  if (ssp->v.n_u > 1) {
+    s.lgu = p->lgu;
+    s.sigma_u = p->sigma_u;
+    s.ion_edges = ssp->v.ion_edges;
+    s.n_u = ssp->v.n_u;
+  }
   s.hist = hist;
   s.perm = perm;
   return launch_sort(s, stream);

@@ -320,6 +320,9 @@ struct SortLaunch {
   double slope, pivot, mdf_width, lg_age_first, lg_age_last;
   const double *met_edges;   // [n_met + 1], device
   int n_met;
+  const float *lgu, *sigma_u;  // ionization distribution (n_u > 1), or null
+  const double *ion_edges;     // [n_u + 1], device
+  int n_u;
   int *hist;                 // [SORT_BINS] scratch
   int *perm;                 // [n_gal] sorted position -> galaxy
 };

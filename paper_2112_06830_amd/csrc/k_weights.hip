@@ -553,6 +553,11 @@ int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
 // lookback time; the rows come first because a mismatch there costs whole
 // K rows for every wavelength of the tile.  The order never changes a
 // galaxy's result (the kernels' tiling is exact), only the work.
+//
+// With an ionization axis a tile's K stages run once per ionization point in
+// the union of its members' supports, so the key leads with that support
+// (first point, 3 bits, and extent, 2 bits), then the lowest metallicity row
+// and a redshift bucket of 1/8 in log2(1+z): 13 bits as before.
 __device__ __forceinline__ int sort_key(const SortLaunch &a, int g) {
   const float z = a.z[g];
   int zb = 0;
@@ -572,6 +577,19 @@ __device__ __forceinline__ int sort_key(const SortLaunch &a, int g) {
   for (int j = 1; j < a.n_met; ++j) {       // bin j starts at interior edge j
     jlo += a.met_edges[j] <= lo;
     jhi += a.met_edges[j] <= hi;
+  }
+  if (a.lgu) {
+    // the same support the per-galaxy scalar pass finds
+    const double c = (double)a.lgu[g], sg = (double)a.sigma_u[g];
+    int ulo = -1, uhi = 0;
+    for (int u = 0; u < a.n_u; ++u) {
+      if (ion_weight(a.ion_edges, u, c, sg) != 0.0) {
+        if (ulo < 0) ulo = u;
+        uhi = u;
+      }
+    }
+    if (ulo < 0) ulo = uhi = 0;
+    return (min(ulo, 7) << 10) | (min(uhi - ulo, 3) << 8) | (min(jlo, 15) << 4) | (zb >> 1);
   }
   return (min(jlo, 15) << 9) | (min(jhi, 15) << 5) | zb;
 }

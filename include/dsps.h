@@ -289,6 +289,23 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
               const dsps_pop *pop, int precision, float *mags, float *bands, float *moments,
               void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Derivative of the float32 magnitudes with respect to each galaxy's
+ * ionization centre (wrt 0: pop->lgu) or width (wrt 1: sigma_u) (Section 3.3,
+ * Eq. nebsed): the fused contraction runs with the ionization weights
+ * replaced by their derivatives (as dsps_sed_ion_tangent), giving the band
+ * sums' derivatives dnum_b, and dm_b = -2.5 / ln 10 dnum_b / num_b.
+ *   bands   [n_gal*2*n_band] from dsps_mags with the same inputs, or NULL (the
+ *           forward pass then runs first, in the workspace)
+ *   dmags   [n_gal*n_band] float32, device
+ * Each galaxy's magnitudes depend only on its own distribution, so dmags is
+ * also the per-galaxy gradient; a cotangent m_bar gives
+ * lgu_bar[g] = sum_b m_bar[g, b] dmags[g, b].  Requires n_u > 1; workspace
+ * as dsps_mags (DSPS_OP_MAGS); no age-dependent attenuation. */
+int dsps_mags_ion_tangent(const dsps_ssp *ssp, const dsps_filters *filters,
+                          const dsps_cosmo *cosmo, const dsps_pop *pop, int wrt,
+                          const float *bands, float *dmags, void *workspace,
+                          size_t workspace_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * a9. Vector-Jacobian product of dsps_mags (reverse mode).
  *   mags_bar        [n_gal*n_band] float32 cotangent of the magnitudes

@@ -221,6 +221,20 @@ def mags(inp: OracleInputs, block: int = 256, return_sums: bool = False):
     return m
 
 
+def mags_ion_tangent(inp: OracleInputs, which: str = "lgu"):
+    """dm/d(lgu) or dm/d(sigma_u) [n_gal, n_band]: m_b = -2.5 log10 num_b +
+    terms free of the ionization distribution, and num_b is linear in the
+    attenuated SED, so dm_b = -2.5 / ln 10 num_b(dL) / num_b(L) with dL the SED
+    tangent of sed_ion_tangent."""
+    num, _ = band_sums(inp)
+    dspec = sed_ion_tangent(inp, which, apply_dust=True)
+    dnum = np.empty_like(num)
+    for g in range(inp.n_gal):
+        dnum[g], _ = photometry.band_integrals(inp.wave, dspec[g], inp.z[g], inp.filt_wave,
+                                               inp.filt_trans)
+    return -2.5 / np.log(10.0) * dnum / num
+
+
 def bf16_row_scales(lum_rows_f32):
     """Smallest power of two >= each row maximum, as float32 [rows]."""
     x = np.asarray(lum_rows_f32, dtype=np.float32)

@@ -285,6 +285,25 @@ def sed_ion_tangent(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, wrt=
     return out
 
 
+def mags_ion_tangent(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopulation,
+                     wrt="lgu", bands: torch.Tensor | None = None,
+                     workspace: Workspace | None = None, stream=None) -> torch.Tensor:
+    """dsps_mags_ion_tangent: dm/d(lgu) or dm/d(sigma_u) [n_gal, n_band]
+    float32, per galaxy.  bands: the forward band sums (mags(...,
+    with_bands=True)), or None to run the forward pass inside."""
+    out = torch.empty((pop.n_gal, filters.n_band), dtype=torch.float32, device=pop.device)
+    if workspace is None:
+        workspace = Workspace(workspace_size(N.OP_MAGS, ssp, filters, pop.n_gal, pop.n_t, "fp32"),
+                              pop.device)
+    b = None if bands is None else bands.to(torch.float32).contiguous()
+    c, p = cosmo.c(), pop.c()
+    rc = _lib().dsps_mags_ion_tangent(ssp.handle, filters.handle, ctypes.byref(c), ctypes.byref(p),
+                                      {"lgu": 0, "sigma_u": 1}[wrt], _ptr(b), _ptr(out),
+                                      workspace.ptr(), workspace.nbytes, _stream(stream))
+    N.check(rc, "dsps_mags_ion_tangent")
+    return out
+
+
 def _lines(lines):
     lines = list(lines)
     return (N.Line * len(lines))(*[N.Line(float(c), float(h), float(f)) for c, h, f in lines]), len(lines)

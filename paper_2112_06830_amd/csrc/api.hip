@@ -485,7 +485,11 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   const int w_cols = (v.sa32 && op == DSPS_OP_MAGS) ? std::max(v.k_pad, AGE_K) : v.k_pad;
   L.w = take(elem * (size_t)L.batch * w_cols);
   if (v.sa32 && op == DSPS_OP_MAGS) L.dust_old = take(sizeof(GalaxyDustOld) * (size_t)n_gal);
-  if (v.n_u > 1 && op == DSPS_OP_MAGS) L.ion = take(sizeof(GalaxyIon) * (size_t)n_gal);
+  if (v.n_u > 1 && op == DSPS_OP_MAGS) {
+    L.ion = take(sizeof(GalaxyIon) * (size_t)n_gal);
+    // the forward magnitudes and band sums an ionization tangent may need
+    L.fbands = take(sizeof(float) * (size_t)n_gal * 3 * n_band);
+  }
   // float32 forward passes may carry the dust moments
   const int ncomp = mags_components(precision == DSPS_FP32);
   L.partial = take(sizeof(float) * (size_t)L.batch * L.n_chunks * ncomp * n_band);
@@ -741,9 +745,13 @@ static int max_window_chunks(const SspHandle *ssp, const FiltersHandle *flt) {
 
 // Forward pass over the sorted batch [s0, s0 + cnt): weights, fused
 // contraction and finalize.  moments requires the float32 table.
+// With ion_tangent (1: centre, 2: width) the weights of the ionization points
+// are replaced by their derivatives and `mags` receives dm = -2.5/ln10 dnum/num
+// with num from tangent_bands (the forward band sums).
 static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
                       const dsps_pop *pop, int precision, const Layout &L, char *ws, int s0,
-                      int cnt, float *mags, float *bands, float *moments, hipStream_t stream) {
+                      int cnt, float *mags, float *bands, float *moments, hipStream_t stream,
+                      int ion_tangent = 0, const float *tangent_bands = nullptr) {
   int *perm = (int *)(ws + L.perm);
   GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
   GalaxyRange *range = (GalaxyRange *)(ws + L.range);
@@ -771,6 +779,7 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   DSPS_TRY(launch_weights(a, stream));
   MagsLaunch m{};
   m.ion = ion;
+  m.ion_tangent = ion_tangent;
   if (age_dust) {
     // ages whose transition weight is exactly 0 (young) or 1 (old): the
     // triweight's cumulative is 0 at or below -3 widths and 1 at or above +3
@@ -818,6 +827,7 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   f.mags = mags;
   f.bands = bands;
   f.mom = moments;
+  f.tangent_bands = tangent_bands;
   return launch_mags_finalize(f, stream);
 }
 
@@ -850,6 +860,41 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
     const int cnt = std::min(L.batch, pop->n_gal - s0);
     DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, precision, L, ws, s0, cnt, mags, bands, moments,
                         stream));
+  }
+  return DSPS_OK;
+}
+
+int dsps_mags_ion_tangent(const dsps_ssp *ssp, const dsps_filters *filters,
+                          const dsps_cosmo *cosmo, const dsps_pop *pop, int wrt,
+                          const float *bands, float *dmags, void *workspace,
+                          size_t workspace_bytes, hipStream_t stream) {
+  DSPS_CHECK(ssp && filters, DSPS_ERR_ARG, "ssp or filters is NULL");
+  DSPS_CHECK(wrt == 0 || wrt == 1, DSPS_ERR_ARG, "wrt must be 0 (lgu) or 1 (sigma_u)");
+  DSPS_CHECK(ssp->v.n_u > 1, DSPS_ERR_UNSUPPORTED, "the SSP block has no ionization axis");
+  DSPS_TRY(check_cosmo(cosmo));
+  DSPS_TRY(check_pop(pop, true));
+  DSPS_TRY(check_ion(ssp, pop));
+  DSPS_CHECK(!pop->av_old, DSPS_ERR_UNSUPPORTED,
+             "with an ionization axis dsps_mags does not apply the age-dependent attenuation");
+  if (pop->n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(dmags, DSPS_ERR_ARG, "dmags is NULL");
+  DSPS_TRY(check_device(ssp->device));
+  DSPS_CHECK(filters->device == ssp->device, DSPS_ERR_ARG, "ssp and filters on different devices");
+  const int n_band = filters->v.n_band;
+  const Layout L = make_layout(DSPS_OP_MAGS, ssp->v, n_band, pop->n_gal, DSPS_FP32);
+  DSPS_TRY(check_workspace(workspace, workspace_bytes, L.total));
+  char *ws = (char *)workspace;
+  float *fwd_mags = (float *)(ws + L.fbands);
+  float *fwd_bands = fwd_mags + (size_t)pop->n_gal * n_band;
+  const float *use_bands = bands ? bands : fwd_bands;
+  DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), (int *)(ws + L.perm), stream));
+  for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
+    const int cnt = std::min(L.batch, pop->n_gal - s0);
+    if (!bands)
+      DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, fwd_mags, fwd_bands,
+                          nullptr, stream));
+    DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, dmags, nullptr, nullptr,
+                        stream, 1 + wrt, use_bands));
   }
   return DSPS_OK;
 }

@@ -370,6 +370,7 @@ struct MagsLaunch {
   int age_young, age_old;
   double dust_pivot, dust_width;
   const GalaxyIon *ion;          // ionization axis (float32 only), by sorted position, or null
+  int ion_tangent;               // with ion: 0 weights, 1/2 their derivative in centre/width
   int n_groups;                  // workgroups per tile (upper bound on its chunk groups)
   int n_chunks;                  // n_wave_pad / TILE_L
   int moments;                   // also the three dust moments per band (float32 only)
@@ -396,6 +397,10 @@ struct FinalizeLaunch {
   float *mags;    // [n_gal][n_band] by galaxy index
   float *bands;   // [n_gal][2][n_band] or null
   float *mom;     // [n_gal][3][n_band] or null (requires moments)
+  // tangent pass: the partials hold the derivative's band sums num'; the
+  // output is then dm = -2.5 / ln 10 num' / num with num from these forward
+  // band sums ([n_gal][2][n_band] by galaxy index)
+  const float *tangent_bands;
 };
 int launch_mags_finalize(const FinalizeLaunch &a, hipStream_t stream);
 

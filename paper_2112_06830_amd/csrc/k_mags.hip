@@ -240,7 +240,11 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
       float f = 0.0f;
       if (col < nvalid) {
         const GalaxyIon gi = a.ion[a.s_begin + g0 + col];
-        f = (float)ion_weight(P.ion_edges, u_lo + uu, gi.lgu, gi.sigma_u);
+        const int u = u_lo + uu;
+        const double c = gi.lgu, sg = gi.sigma_u;
+        f = (float)(a.ion_tangent == 1   ? ion_weight_d<1>(P.ion_edges, u, c, sg)
+                    : a.ion_tangent == 2 ? ion_weight_d<2>(P.ion_edges, u, c, sg)
+                                         : ion_weight(P.ion_edges, u, c, sg));
       }
       s_pn[t] = f;
     }
@@ -556,8 +560,15 @@ __global__ void k_mags_finalize(FinalizeLaunch a) {
     if (b >= nb) continue;
     const float num = acc[0][b], den = acc[1][b];
     double m;
-    if (den == 0.0f) m = __builtin_nan("");
-    else m = -2.5 * log10((double)num / (AB_ZERO_POINT * (double)den)) + offset;
+    if (a.tangent_bands) {
+      // d(-2.5 log10 num) = -2.5 / ln 10 dnum / num
+      const float num_fwd = a.tangent_bands[(size_t)g * 2 * nb + b];
+      m = -1.0857362047581294 * (double)num / (double)num_fwd;
+    } else if (den == 0.0f) {
+      m = __builtin_nan("");
+    } else {
+      m = -2.5 * log10((double)num / (AB_ZERO_POINT * (double)den)) + offset;
+    }
     a.mags[(size_t)g * nb + b] = (float)m;
     if (a.bands) {
       a.bands[(size_t)g * 2 * nb + b] = num;

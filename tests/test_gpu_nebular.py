@@ -275,3 +275,29 @@ def test_oiii_width_gradient_end_to_end_matches_oracle(dev, small):
     scale = (bound[:, win] / spec[:, win]).max(axis=1)
     assert np.all(np.abs(dw - ref) <= 8e-5 * (2 * h * scale + np.abs(ref)))
     assert np.mean(ref > 0) > 0.9                    # stronger [OIII] at higher U_s
+
+
+@pytest.mark.parametrize("which", ["lgu", "sigma_u"])
+def test_mags_ion_tangent_matches_oracle(dev, small, which):
+    """dm_b = -2.5/ln10 dnum_b / num_b.  The float32 dnum_b errs by at most
+    2e-5 of the band sum of the absolute-value tangent, num_b by 2e-5 of
+    itself, so |d(dm)| <= 1.09 x 2e-5 (dnum_abs + |dnum|) / num."""
+    ssp_h, flt_h, ssp = small
+    pop = _pop(100, seed=111)
+    inp = _inputs(ssp, pop)
+    _say(f"magnitude ionization tangent wrt={which} n_gal=100")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    got = dev.mags_ion_tangent(ssp_h, flt_h, dev.Cosmology(), dp, wrt=which).cpu().numpy()
+    _, bands = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)
+    again = dev.mags_ion_tangent(ssp_h, flt_h, dev.Cosmology(), dp, wrt=which,
+                                 bands=bands).cpu().numpy()
+    np.testing.assert_array_equal(got, again)
+    ref = oracle.pipeline.mags_ion_tangent(inp, which)
+    num, _ = oracle.band_sums(inp)
+    bound = _abs_tangent_bound(inp, which, True)
+    dnum_abs = np.stack([oracle.photometry.band_integrals(inp.wave, bound[g], inp.z[g],
+                                                          inp.filt_wave, inp.filt_trans)[0]
+                         for g in range(inp.n_gal)])
+    tol = 1.09 * 2e-5 * (dnum_abs + np.abs(ref * num / 1.0857362047581294)) / num
+    assert np.all(np.abs(got - ref) <= tol + 1e-12)
+    assert np.abs(ref).max() > 1e-3

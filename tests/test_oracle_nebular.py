@@ -254,3 +254,22 @@ def test_oiii_width_gradient_in_u_is_positive_and_matches_differences():
                                            5008.24, 40.0, 150.0))
     np.testing.assert_allclose(dw, (ws[0] - ws[1]) / (2 * h), rtol=1e-5)
     assert np.all(dw > 0)
+
+
+@pytest.mark.parametrize("which", ["lgu", "sigma_u"])
+def test_magnitude_tangent_matches_central_difference(which):
+    ssp = synth.make_ssp_nebular(n_u=5, lgu_range=(-4.0, -2.0), n_wave=400, wave_lo=1500.0,
+                                 wave_hi=12000.0, n_met=4, n_age=12, lg_age_range=(6.0, 10.0))
+    pop = synth.make_population(3, n_t=80, z_range=(0.1, 0.3), seed=55, nebular=True)
+    flt = synth.make_filters()
+    got = oracle.pipeline.mags_ion_tangent(oracle.prepare_inputs(ssp, flt, pop), which)
+    h = 1e-5
+    vals = getattr(pop, which).copy()
+    ms = []
+    for sgn in (1.0, -1.0):
+        setattr(pop, which, vals + sgn * h)
+        ms.append(oracle.mags(oracle.prepare_inputs(ssp, flt, pop)))
+    setattr(pop, which, vals)
+    fd = (ms[0] - ms[1]) / (2 * h)
+    np.testing.assert_allclose(got, fd, rtol=1e-5, atol=1e-9 * np.abs(fd).max())
+    assert np.abs(fd).max() > 0

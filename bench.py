@@ -375,10 +375,30 @@ def run_nebular(P, steps, warmup, n_gal=100_000, seed=10, n_u=7):
     ms_ew = (time.perf_counter() - t0) * 1e3 / steps
     eqw_ms, _ = P.profile_read("eqw")
     P.profile_enable(False)
+    # forward + adjoint of the squared error to target magnitudes, every
+    # cotangent including the ionization centre and width
+    targets = torch.tensor(pop.targets, dtype=torch.float32, device="cuda")
+    ws_v = P.Workspace(P.workspace_size(3, ssp_h, flt_h, n_gal, 100, "fp32"), dpop.device)
+
+    def fwd_grad():
+        mm, bands, mom = P.mags(ssp_h, flt_h, P.Cosmology(), dpar, with_moments=True, workspace=ws)
+        return P.mags_vjp(ssp_h, flt_h, P.Cosmology(), dpar, 2.0 * (mm - targets), bands=bands,
+                          moments=mom, workspace=ws_v)
+    for _ in range(warmup):
+        fwd_grad()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        grads = fwd_grad()
+    torch.cuda.synchronize()
+    ms_grad = (time.perf_counter() - t0) * 1e3 / steps
     res = {"mags": {"ms_per_step": ms, "galaxies_per_s": n_gal / (ms * 1e-3),
                     "gemm_ms_per_step": gemm_ms / steps},
            "sed_and_eqw": {"ms_per_step": ms_ew, "galaxies_per_s": n_gal / (ms_ew * 1e-3),
                            "eqw_ms_per_step": eqw_ms / steps, "n_lines": len(NEB_LINES)},
+           "mags_and_gradient": {"ms_per_step": ms_grad, "galaxies_per_s": n_gal / (ms_grad * 1e-3),
+                                 "finite": bool(all(torch.isfinite(v).all().item()
+                                                    for v in grads.values()))},
            "finite": bool(torch.isfinite(m).all().item() and torch.isfinite(ew).all().item())}
     idx = np.arange(64)
     return res, (ssp, flt, pop.subset(idx), m[:64].cpu().numpy(), ew[:64].cpu().numpy())
@@ -554,7 +574,8 @@ def main():
         nb, nb_sample = run_nebular(P, max(3, args.steps // 4), 1)
         extra["nebular_fp32_1e5"] = nb
         log(f"nebular 1e5: mags {nb['mags']['ms_per_step']:.3f} ms/step, "
-            f"sed + widths {nb['sed_and_eqw']['ms_per_step']:.3f} ms/step")
+            f"sed + widths {nb['sed_and_eqw']['ms_per_step']:.3f} ms/step, "
+            f"mags + gradient {nb['mags_and_gradient']['ms_per_step']:.3f} ms/step")
         va, va_sample = run_variants(P, max(3, args.steps // 4), 1)
         extra["variants_transition_mdf_wcdm_1e5"] = va
         log(f"variants 1e5: forward {va['forward']['ms_per_step']:.3f} ms/step, "

@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define DSPS_ABI_VERSION 5
+#define DSPS_ABI_VERSION 6
 
 typedef enum {
   DSPS_OK = 0,
@@ -132,8 +132,8 @@ int dsps_ssp_create(int n_met, int n_age, int n_wave, const double *lgz,
  * point k is the triweight mass of the galaxy's distribution inside bin k
  * (dsps_pop.lgu, sigma_u).  dsps_sed and dsps_mags (float32) sum over the
  * axis; dsps_weights returns the (metallicity, age) weights without the
- * ionization factor; dsps_mags_vjp returns DSPS_ERR_UNSUPPORTED for n_u > 1.
- * n_u == 1 is dsps_ssp_create. */
+ * ionization factor; dsps_mags_vjp adds the gradients w.r.t. the ionization
+ * centre and width.  n_u == 1 is dsps_ssp_create. */
 int dsps_ssp_create_neb(int n_met, int n_age, int n_u, int n_wave, const double *lgz,
                         const double *lg_age, const double *lgu, const double *wave,
                         const float *lum, int precisions, int k0_reading, dsps_ssp **out);
@@ -317,6 +317,15 @@ int dsps_mags_ion_tangent(const dsps_ssp *ssp, const dsps_filters *filters,
  *   lgmet_bar, lgmet_old_bar, sigma_bar, av_bar, delta_bar, bump_bar
  *                   [n_gal] float32 each, or NULL (lgmet_old_bar requires
  *                   pop->lgmet_old)
+ *   lgu_bar, sigma_u_bar  [n_gal] float32, or NULL: gradients w.r.t. the
+ *                   ionization centre and width (SSP handle with n_u > 1,
+ *                   else DSPS_ERR_ARG); each costs one more fused pass with
+ *                   the derivative weights (dsps_mags_ion_tangent), dotted
+ *                   with mags_bar per galaxy
+ * With an ionization axis (Section 3.3, Eq. nebsed) the transposed
+ * contraction runs once per ionization point a tile's members reach, against
+ * that point's block of the adjoint table, each galaxy's SED cotangent scaled
+ * by its weight of the point.
  * The dust gradients are the band cotangents applied to the moments; the SED
  * cotangent F q sum_b gamma_b T_b needs no SED, so the backward pass holds no
  * forward contraction.  Redshift gets no gradient.
@@ -326,7 +335,8 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
                   const float *bands, const float *moments, double *sfr_bar,
                   double *sfh_params_bar, float *lgmet_bar, float *lgmet_old_bar,
                   float *sigma_bar, float *av_bar, float *delta_bar, float *bump_bar,
-                  void *workspace, size_t workspace_bytes, hipStream_t stream);
+                  float *lgu_bar, float *sigma_u_bar, void *workspace, size_t workspace_bytes,
+                  hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Emission-line equivalent widths of rest-frame SEDs (Section 2.2.2, Eq. eqw).

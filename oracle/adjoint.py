@@ -20,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 from scipy import special
 
-from . import cosmology, dust, mdf, photometry, sfh
+from . import cosmology, dust, mdf, nebular, photometry, sfh
 from .constants import (LAMBDA_V_ANGSTROM, R_V_SALIM, SFH_QUENCH_WIDTH_GYR, YR_PER_GYR)
 from .kernels import triweight_pdf
 from .pipeline import OracleInputs
@@ -64,15 +64,19 @@ def mags_vjp(inp: OracleInputs, mags_bar):
       bump_bar [n_gal], and lgmet_old_bar [n_gal] for the transition MDF
       (d mu_i / d lgmet = 1 - T_i and d mu_i / d lgmet_old = T_i with
       T_i = T_erf((log10 tau_i - pivot) / width)).
+    With the ionization axis (Eq. nebsed) each galaxy contracts against its
+    own table sum_k P_k L[:, :, k, :], and lgu_bar, sigma_u_bar [n_gal] follow
+    from P_bar_k = sum_{j,i} W[j, i] (L[j, i, k, :] . spec_bar) through the
+    derivatives of the ionization weights.
     """
     if inp.av_old is not None:
         raise NotImplementedError("the adjoint of the age-dependent attenuation is not written")
-    if inp.lgu_grid is not None:
-        raise NotImplementedError("the adjoint over the ionization axis is not written")
     mags_bar = np.atleast_2d(np.asarray(mags_bar, dtype=np.float64))
     n_gal = inp.n_gal
-    n_met, n_age, n_wave = inp.lum.shape
-    table = inp.lum.reshape(n_met * n_age, n_wave)
+    n_met, n_age = inp.lum.shape[:2]
+    n_wave = inp.lum.shape[-1]
+    neb = inp.lgu_grid is not None
+    table = None if neb else inp.lum.reshape(n_met * n_age, n_wave)
     n_band = inp.filt_wave.shape[0]
     t_table = np.asarray(inp.t_table, dtype=np.float64)
     n_t = t_table.size
@@ -91,6 +95,11 @@ def mags_vjp(inp: OracleInputs, mags_bar):
     if terf_mdf:
         out["lgmet_old_bar"] = np.zeros(n_gal)
         t_age = mdf.transition_weight(inp.lg_age, inp.lg_age_pivot, inp.mdf_width)    # [i]
+    if neb:
+        out["lgu_bar"] = np.zeros(n_gal)
+        out["sigma_u_bar"] = np.zeros(n_gal)
+        p_neb_all = nebular.ionization_weights(inp.lgu, inp.sigma_u, inp.lgu_grid)      # [g, k]
+        dp_u, dp_s = nebular.ionization_weight_derivatives(inp.lgu, inp.sigma_u, inp.lgu_grid)
     out["sfr_bar"] = np.zeros((n_gal, n_t))
     if inp.sfh_params is not None:
         out["sfh_params_bar"] = np.zeros((5, n_gal))
@@ -113,6 +122,8 @@ def mags_vjp(inp: OracleInputs, mags_bar):
                                 None if not terf_mdf else inp.lgmet_old[g:g + 1],
                                 inp.mdf_width)[0]                                   # [j, i]
         w = (m_age[None, :] * p_met).reshape(-1)
+        if neb:
+            table = np.einsum("k,jikl->jil", p_neb_all[g], inp.lum).reshape(n_met * n_age, n_wave)
         spec = w @ table                                                             # [l]
         kdust = k0 * np.exp(inp.delta[g] * log_ratio) + inp.bump[g] * drude_unit
         att = 10.0 ** (-0.4 * inp.av[g] / R_V_SALIM * kdust)
@@ -134,6 +145,11 @@ def mags_vjp(inp: OracleInputs, mags_bar):
         out["bump_bar"][g] = np.sum(att_bar * att * dlnf_dk * drude_unit)
 
         w_bar = (table @ spec_bar).reshape(n_met, n_age)                             # [j, i]
+        if neb:
+            per_point = np.einsum("jikl,l->jik", inp.lum, spec_bar)                  # [j, i, k]
+            p_neb_bar = np.einsum("ji,jik->k", w.reshape(n_met, n_age), per_point)
+            out["lgu_bar"][g] = np.dot(p_neb_bar, dp_u[g])
+            out["sigma_u_bar"][g] = np.dot(p_neb_bar, dp_s[g])
         m_age_bar = np.sum(w_bar * p_met, axis=0)                                    # [i]
         p_bar = w_bar * m_age[None, :]                                               # [j, i]
         cdf_bar = np.zeros((n_met + 1, n_age))

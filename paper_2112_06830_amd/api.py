@@ -400,7 +400,8 @@ def profile_read(kernel: str):
 def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopulation,
              mags_bar: torch.Tensor, bands: torch.Tensor | None = None,
              moments: torch.Tensor | None = None,
-             want=("sfr", "sfh_params", "lgmet", "lgmet_old", "sigma_z", "av", "delta", "bump"),
+             want=("sfr", "sfh_params", "lgmet", "lgmet_old", "sigma_z", "av", "delta", "bump",
+                   "lgu", "sigma_u"),
              workspace: Workspace | None = None, outs: dict | None = None, stream=None) -> dict:
     """dsps_mags_vjp: cotangents of the population inputs for a magnitude
     cotangent mags_bar [n_gal, n_band] (float32 path).  bands and moments come
@@ -427,6 +428,9 @@ def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePo
             out[k] = torch.empty(n, dtype=torch.float32, device=d)
     if "lgmet_old" in want and pop.lgmet_old is not None:
         out["lgmet_old"] = torch.empty(n, dtype=torch.float32, device=d)
+    for k in ("lgu", "sigma_u"):
+        if k in want and getattr(ssp, "n_u", 1) > 1:
+            out[k] = torch.empty(n, dtype=torch.float32, device=d)
     if workspace is None:
         workspace = Workspace(workspace_size(N.OP_MAGS_VJP, ssp, filters, n, pop.n_t, "fp32"), d)
     c, p = cosmo.c(), pop.c()
@@ -434,7 +438,8 @@ def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePo
                               _ptr(mags_bar), _ptr(bands), _ptr(moments), _ptr(out.get("sfr")),
                               _ptr(out.get("sfh_params")), _ptr(out.get("lgmet")),
                               _ptr(out.get("lgmet_old")), _ptr(out.get("sigma_z")), _ptr(out.get("av")), _ptr(out.get("delta")),
-                              _ptr(out.get("bump")), workspace.ptr(), workspace.nbytes, _stream(stream))
+                              _ptr(out.get("bump")), _ptr(out.get("lgu")), _ptr(out.get("sigma_u")),
+                              workspace.ptr(), workspace.nbytes, _stream(stream))
     N.check(rc, "dsps_mags_vjp")
     return out
 

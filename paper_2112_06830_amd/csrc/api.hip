@@ -224,8 +224,8 @@ static int ssp_create(int n_met, int n_age, int n_u, int n_wave, const double *l
   const size_t o_st32 = want32 ? take(sizeof(float) * (size_t)nwp * v.k_row) : 0;
   const size_t o_st16 = want16 ? take(sizeof(uint16_t) * (size_t)nwp * kp) : 0;
   const int sk_rows = (kp + TILE_L - 1) / TILE_L * TILE_L;
-  const bool want_sk = want32 && n_u == 1;   // the adjoint's table (no ionization axis)
-  const size_t o_sk = want_sk ? take(sizeof(float) * (size_t)sk_rows * nwp) : 0;
+  const bool want_sk = want32;   // the adjoint's table, one block per ionization point
+  const size_t o_sk = want_sk ? take(sizeof(float) * (size_t)n_u * sk_rows * nwp) : 0;
   const size_t o_sa = want_age ? take(sizeof(float) * (size_t)nwp * AGE_K) : 0;
   const size_t o_ks = take(sizeof(float) * kp);
   const size_t o_lc = take(sizeof(float4) * nwp);
@@ -293,8 +293,10 @@ static int ssp_create(int n_met, int n_age, int n_u, int n_wave, const double *l
                              v.k_row, want32 ? (float *)(b + o_st32) + (size_t)k * kp : nullptr,
                              want16 ? (uint16_t *)(b + o_st16) : nullptr, nullptr);
     if (rc) break;
-    if (want_sk) rc = launch_pack_table_kmajor(d_rows, n_age, n_wave, nwp, kp, sk_rows,
-                                              (float *)(b + o_sk), nullptr);
+    for (int k = 0; want_sk && k < n_u && !rc; ++k)
+      rc = launch_pack_table_kmajor(d_rows + (size_t)k * rows * n_wave, n_age, n_wave, nwp, kp,
+                                    sk_rows, (float *)(b + o_sk) + (size_t)k * sk_rows * nwp,
+                                    nullptr);
     if (rc) break;
     if (want_age) rc = launch_pack_table_age(d_rows, n_met, n_age, n_wave, nwp, (float *)(b + o_sa), nullptr);
     if (rc) break;
@@ -448,7 +450,7 @@ constexpr int BATCH_VJP = 65536;
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
   size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0, tobs = 0, dust_old = 0;
-  size_t ion = 0;
+  size_t ion = 0, dion = 0;
   int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
@@ -501,6 +503,12 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
     L.wbar = take(sizeof(float) * (size_t)L.batch * v.k_pad);
     // bands, moments and magnitudes of the forward pass when not supplied
     L.fbands = take(sizeof(float) * (size_t)n_gal * 6 * n_band);
+    if (v.n_u > 1) {
+      // the members' ionization distributions, and the magnitudes'
+      // derivatives in the ionization centre and width
+      L.ion = take(sizeof(GalaxyIon) * (size_t)n_gal);
+      L.dion = take(sizeof(float) * (size_t)n_gal * 2 * n_band);
+    }
   }
   L.total = off;
   return L;
@@ -844,9 +852,8 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
              "age-dependent attenuation needs float32, no moments and an SSP handle created with "
              "DSPS_SSP_AGE_MAJOR");
   DSPS_TRY(check_ion(ssp, pop));
-  DSPS_CHECK(ssp->v.n_u == 1 || (!moments && !pop->av_old), DSPS_ERR_UNSUPPORTED,
-             "with an ionization axis dsps_mags computes neither dust moments nor the "
-             "age-dependent attenuation");
+  DSPS_CHECK(ssp->v.n_u == 1 || !pop->av_old, DSPS_ERR_UNSUPPORTED,
+             "with an ionization axis dsps_mags does not apply the age-dependent attenuation");
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(mags, DSPS_ERR_ARG, "mags is NULL");
   DSPS_TRY(check_device(ssp->device));
@@ -903,7 +910,8 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
                   const dsps_pop *pop, int precision, const float *mags_bar, const float *bands,
                   const float *moments, double *sfr_bar, double *sfh_params_bar, float *lgmet_bar,
                   float *lgmet_old_bar, float *sigma_bar, float *av_bar, float *delta_bar,
-                  float *bump_bar, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+                  float *bump_bar, float *lgu_bar, float *sigma_u_bar, void *workspace,
+                  size_t workspace_bytes, hipStream_t stream) {
   DSPS_CHECK(ssp && filters, DSPS_ERR_ARG, "ssp or filters is NULL");
   DSPS_TRY(check_cosmo(cosmo));
   DSPS_TRY(check_pop(pop, true));
@@ -911,8 +919,9 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
   DSPS_CHECK(precision == DSPS_FP32, DSPS_ERR_UNSUPPORTED, "the adjoint runs in float32 only");
   DSPS_CHECK(!pop->av_old, DSPS_ERR_UNSUPPORTED,
              "the adjoint of the age-dependent attenuation is not available");
-  DSPS_CHECK(ssp->v.n_u == 1, DSPS_ERR_UNSUPPORTED,
-             "the adjoint over an ionization axis is not available");
+  DSPS_TRY(check_ion(ssp, pop));
+  DSPS_CHECK(ssp->v.n_u > 1 || (!lgu_bar && !sigma_u_bar), DSPS_ERR_ARG,
+             "lgu_bar and sigma_u_bar need an SSP block with an ionization axis");
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(mags_bar, DSPS_ERR_ARG, "mags_bar is NULL");
   DSPS_CHECK((bands == nullptr) == (moments == nullptr), DSPS_ERR_ARG,
@@ -948,6 +957,7 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
       a.mag_offset = (double *)(ws + L.offset);
       a.obs_lo = filters->obs_lo;
       a.obs_hi = filters->obs_hi;
+      a.ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
       DSPS_TRY(launch_weights(a, stream));
     } else {
       DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, fwd_mags, fwd_bands,
@@ -993,8 +1003,24 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
     v.av_bar = av_bar;
     v.delta_bar = delta_bar;
     v.bump_bar = bump_bar;
+    v.ion = ssp->v.n_u > 1 ? (const GalaxyIon *)(ws + L.ion) : nullptr;
     for (int stage = 0; stage < 4; ++stage) DSPS_TRY(launch_vjp(v, stage, stream));
+    // the ionization parameters: each galaxy's magnitudes depend only on its
+    // own distribution, so lgu_bar[g] = sum_b mags_bar[g, b] dm[g, b] / dlgu[g]
+    float *dion = (float *)(ws + L.dion);
+    if (lgu_bar)
+      DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, dion, nullptr,
+                          nullptr, stream, 1, use_bands));
+    if (sigma_u_bar)
+      DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt,
+                          dion + (size_t)pop->n_gal * n_band, nullptr, nullptr, stream, 2, use_bands));
   }
+  if (lgu_bar)
+    DSPS_TRY(launch_row_dot(mags_bar, (const float *)(ws + L.dion), pop->n_gal, n_band, lgu_bar,
+                            stream));
+  if (sigma_u_bar)
+    DSPS_TRY(launch_row_dot(mags_bar, (const float *)(ws + L.dion) + (size_t)pop->n_gal * n_band,
+                            pop->n_gal, n_band, sigma_u_bar, stream));
   return DSPS_OK;
 }
 

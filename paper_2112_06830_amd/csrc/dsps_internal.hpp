@@ -71,7 +71,9 @@ struct SspView {
   const float *kscale;             // [k_pad] power-of-two row scales (1 on padding)
   const float4 *lconst;            // [n_wave_pad] (lambda, log2(lambda/5500), k0, drude shape)
   const float *qweight;            // [n_wave_pad] trapezoid weight in dlambda/lambda
-  const float *sk32;               // [sk_rows][n_wave_pad] K-major, metallicity-differenced (adjoint)
+  // [n_u][sk_rows][n_wave_pad] K-major, metallicity-differenced (adjoint),
+  // one block per ionization point
+  const float *sk32;
   int sk_rows;                     // k_pad rounded up to a multiple of TILE_L
   // [n_wave_pad][AGE_K] age-major float32 (age-dependent attenuation) or null:
   // column age * 16 + met, zero for met >= n_met or age >= n_age
@@ -469,8 +471,14 @@ struct VjpLaunch {
   const float *lgmet_old;     // transition MDF, or null (linear model)
   double mdf_width;
   float *lgmet_old_bar;
+  // ionization axis: the members' distributions by sorted position, or null;
+  // then the adjoint table holds one K-major block per ionization point
+  const GalaxyIon *ion;
 };
 int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream);
+// out[g] = sum_b x[g][b] y[g][b] for n rows of n_band values (float64 sums).
+int launch_row_dot(const float *x, const float *y, int n, int n_band, float *out,
+                   hipStream_t stream);
 
 // Defined in k_summary.hip.
 constexpr int SUMMARY_CHUNK = 2048;   // galaxies per partial-histogram workgroup

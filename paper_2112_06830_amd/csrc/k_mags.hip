@@ -191,7 +191,8 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   using C = GemmCfg<PREC>;
   using elem = typename C::elem;
   constexpr bool AGED = VAR == MAGS_AGED, NEB = VAR == MAGS_NEB;
-  static_assert(!(AGED || NEB) || (PREC == DSPS_FP32 && !MOM), "float32 forward only");
+  static_assert(!(AGED || NEB) || PREC == DSPS_FP32, "float32 only");
+  static_assert(!(AGED && MOM), "no dust moments with the age-dependent attenuation");
   constexpr int NCOMP = MOM ? 5 : 2;
   static_assert(2 * sizeof(GemmSmem<PREC>) >= sizeof(float) * 128 * NCOMP * NSLOT, "reduction alias");
   __shared__ GemmSmem<PREC> sm[2];
@@ -511,10 +512,14 @@ int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
     hipLaunchKernelGGL((k_mags_gemm<DSPS_FP32, false, MAGS_AGED>), dim3(blocks), dim3(GEMM_THREADS),
                        lds, stream, a);
   } else if (a.ion) {
-    if (a.precision != DSPS_FP32 || a.moments || !a.ssp.st32) return DSPS_ERR_UNSUPPORTED;
+    if (a.precision != DSPS_FP32 || !a.ssp.st32) return DSPS_ERR_UNSUPPORTED;
     lds += sizeof(float) * a.ssp.n_u * TILE_G;
-    hipLaunchKernelGGL((k_mags_gemm<DSPS_FP32, false, MAGS_NEB>), dim3(blocks), dim3(GEMM_THREADS),
-                       lds, stream, a);
+    if (a.moments)
+      hipLaunchKernelGGL((k_mags_gemm<DSPS_FP32, true, MAGS_NEB>), dim3(blocks), dim3(GEMM_THREADS),
+                         lds, stream, a);
+    else
+      hipLaunchKernelGGL((k_mags_gemm<DSPS_FP32, false, MAGS_NEB>), dim3(blocks), dim3(GEMM_THREADS),
+                         lds, stream, a);
   } else if (a.precision == DSPS_BF16) {
     if (a.moments) return DSPS_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((k_mags_gemm<DSPS_BF16, false>), dim3(blocks), dim3(GEMM_THREADS), lds, stream, a);

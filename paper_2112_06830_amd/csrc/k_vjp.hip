@@ -126,11 +126,20 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
 // sigma), so its cotangent is never used; rows below must stay, because the
 // pull-back sums the differenced rows upwards.  A block whose rows all lie
 // above the tile's highest supported row writes zeros.
+//
+// NEB (Section 3.3, Eq. nebsed): each galaxy contracts against its own table
+// sum_u P_neb[u] L_u, so the reduction over wavelength runs once per
+// ionization point the tile's members reach, against that point's block of
+// the adjoint table, with each member's Lbar row multiplied by its P_neb[u]
+// as it is staged.
+template <bool NEB>
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   using C = GemmCfg<DSPS_FP32>;
   __shared__ GemmSmem<DSPS_FP32> sm[2];
   __shared__ int s_tile[2];
   __shared__ int s_jhi;          // highest metallicity row in some member's MDF support
+  __shared__ int s_urange[2];    // NEB: the members' ionization points
+  __shared__ float s_pn[NEB ? DSPS_MAX_ION * TILE_G : 1];
   const int kblk = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
@@ -139,13 +148,20 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   const int nvalid = min(TILE_G, a.s_count - g0);
   const int nwp = P.n_wave_pad;
 
-  if (threadIdx.x == 0) { s_tile[0] = 1 << 30; s_tile[1] = 0; s_jhi = 0; }
+  if (threadIdx.x == 0) {
+    s_tile[0] = 1 << 30; s_tile[1] = 0; s_jhi = 0;
+    s_urange[0] = NEB ? 1 << 30 : 0; s_urange[1] = 0;
+  }
   __syncthreads();
   if (threadIdx.x < nvalid) {
     const int s = a.s_begin + g0 + threadIdx.x;
     const GalaxyRange r = a.range[s];
     atomicMin(&s_tile[0], r.win_lo);
     atomicMax(&s_tile[1], r.win_hi);
+    if (NEB) {
+      atomicMin(&s_urange[0], a.ion[s].u_lo);
+      atomicMax(&s_urange[1], a.ion[s].u_hi);
+    }
     // the centre is monotone in age: its largest value sits at an end of the grid
     const int g = a.perm[s];
     const bool transition = a.lgmet_old != nullptr;
@@ -173,8 +189,30 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
       for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
 
   const int nk = (l_end > l_begin && k0 / AGE_PAD <= j_hi) ? (l_end - l_begin) / C::KT : 0;
-  gemm_kloop<DSPS_FP32>(sm, P.sk32, nwp, k0, a.lbar, g0, a.s_count, nk,
-                        [=](int ks) { return l_begin + ks * C::KT; }, wr, wc, lane, acc);
+  if constexpr (NEB) {
+    const int u_lo = s_urange[0], n_uu = s_urange[1] - s_urange[0] + 1;
+    for (int t = threadIdx.x; t < n_uu * TILE_G; t += blockDim.x) {
+      const int uu = t / TILE_G, col = t - uu * TILE_G;
+      float f = 0.0f;
+      if (col < nvalid) {
+        const GalaxyIon gi = a.ion[a.s_begin + g0 + col];
+        f = (float)ion_weight(P.ion_edges, u_lo + uu, gi.lgu, gi.sigma_u);
+      }
+      s_pn[t] = f;
+    }
+    __syncthreads();
+    const int slab = P.sk_rows * nwp;   // one point's block of the adjoint table
+    gemm_kloop_ab<DSPS_FP32>(sm, P.sk32, nwp, k0, a.lbar, nwp, g0, a.s_count, nk * n_uu,
+                             [&](int s) {
+                               const int uu = nk > 0 ? s / nk : 0;
+                               const int l = l_begin + (s - uu * nk) * C::KT;
+                               return StageSrc{(u_lo + uu) * slab + l, l, s_pn + uu * TILE_G};
+                             },
+                             wr, wc, lane, acc);
+  } else {
+    gemm_kloop<DSPS_FP32>(sm, P.sk32, nwp, k0, a.lbar, g0, a.s_count, nk,
+                          [=](int ks) { return l_begin + ks * C::KT; }, wr, wc, lane, acc);
+  }
 
   const int kp = P.k_pad;
 #pragma unroll
@@ -429,6 +467,22 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   }
 }
 
+__global__ void k_row_dot(const float *__restrict__ x, const float *__restrict__ y, int n,
+                          int n_band, float *__restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < n_band; ++b) s += (double)x[(size_t)g * n_band + b] * (double)y[(size_t)g * n_band + b];
+  out[g] = (float)s;
+}
+
+int launch_row_dot(const float *x, const float *y, int n, int n_band, float *out,
+                   hipStream_t stream) {
+  if (n <= 0) return DSPS_OK;
+  hipLaunchKernelGGL(k_row_dot, dim3((n + 255) / 256), dim3(256), 0, stream, x, y, n, n_band, out);
+  return hip_fail(hipGetLastError(), "k_row_dot launch");
+}
+
 int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
   const int tiles = (a.s_count + TILE_G - 1) / TILE_G;
@@ -440,7 +494,12 @@ int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
     hipLaunchKernelGGL(k_vjp_lbar, dim3(a.n_groups, tiles), dim3(256), lds, stream, a);
   } else if (stage == 2) {
     ProfScope prof(DSPS_KERNEL_VJP_WBAR, stream);
-    hipLaunchKernelGGL(k_vjp_wbar, dim3(a.ssp.sk_rows / TILE_L, tiles), dim3(GEMM_THREADS), 0, stream, a);
+    if (a.ion)
+      hipLaunchKernelGGL(k_vjp_wbar<true>, dim3(a.ssp.sk_rows / TILE_L, tiles), dim3(GEMM_THREADS), 0,
+                         stream, a);
+    else
+      hipLaunchKernelGGL(k_vjp_wbar<false>, dim3(a.ssp.sk_rows / TILE_L, tiles), dim3(GEMM_THREADS), 0,
+                         stream, a);
   } else {
     const size_t lds = sizeof(double) * (a.n_t + WEIGHT_WAVES * (2 * a.n_t + 3 * AGE_PAD + 2));
     if (lds > 65536) {

@@ -152,19 +152,76 @@ def test_block_constant_over_u_is_the_plain_block(dev):
 
 
 def test_nebular_unsupported_calls(dev, small):
-    import torch
     ssp_h, flt_h, ssp = small
-    pop = _pop(16, seed=103)
+    pop = _pop(16, seed=103, )
     dp = dev.DevicePopulation.from_synth(pop, use_params=True)
     with pytest.raises(Exception, match="precision"):
         dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, precision="bf16")
-    with pytest.raises(Exception, match="ionization"):
-        dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, torch.zeros((16, 6), device="cuda"))
-    with pytest.raises(Exception, match="ionization"):
-        dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_moments=True)
+    aged = synth.make_population(16, n_t=100, z_range=(0.1, 1.0), seed=103, nebular=True,
+                                 age_dust=True)
+    with pytest.raises(Exception, match="age-dependent"):
+        dev.mags(ssp_h, flt_h, dev.Cosmology(), dev.DevicePopulation.from_synth(aged, use_params=True))
     dp.lgu = None
     with pytest.raises(Exception, match="lgu"):
         dev.mags(ssp_h, flt_h, dev.Cosmology(), dp)
+
+
+def test_nebular_moments_leave_magnitudes_unchanged(dev, large):
+    ssp_h, flt_h, ssp = large
+    pop = _pop(200, seed=115, z_range=(0.1, 3.0))
+    _say("nebular forward with dust moments n_gal=200")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
+    m2, _, mom = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_moments=True)
+    np.testing.assert_array_equal(m, m2.cpu().numpy())
+    assert np.all(np.isfinite(mom.cpu().numpy()))
+
+
+def _grad_close(got, ref, tol=1e-3):
+    """Relative L2 error and elementwise error with a floor at 1e-2 of the
+    RMS (gradients that cancel to near zero), as for the plain adjoint."""
+    got = np.asarray(got, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    rms = np.sqrt(np.mean(ref**2))
+    l2 = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+    elem = np.abs(got - ref) <= tol * np.maximum(np.abs(ref), 1e-2 * rms)
+    return l2 <= tol and bool(elem.all()), (l2, float(np.mean(~elem)))
+
+
+def test_nebular_vjp_matches_oracle_adjoint(dev, large):
+    """Every cotangent against the oracle adjoint.  The ionization ones are
+    sum_b mbar_b dm_b / du per galaxy; the derivative weights sum to zero, so
+    dm_b cancels and its float32 error is bounded as in the magnitude-tangent
+    test, |d(dm_b)| <= 1.09 x 2e-5 (dnum_abs_b + |dnum_b|) / num_b, hence
+    |d ubar| <= sum_b |mbar_b| times that."""
+    import torch
+    ssp_h, flt_h, ssp = large
+    pop = _pop(64, seed=117, z_range=(0.1, 3.0))
+    inp = _inputs(ssp, pop)
+    _say("nebular vjp n_gal=64")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp).cpu().numpy().astype(np.float64)
+    bar = 2.0 * (m - pop.targets)
+    g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, torch.tensor(bar, dtype=torch.float32))
+    ref = oracle.mags_vjp(inp, bar)
+    for key, rkey in (("lgmet", "lgmet_bar"), ("sigma_z", "sigma_bar"), ("av", "av_bar"),
+                      ("delta", "delta_bar"), ("bump", "bump_bar")):
+        ok, info = _grad_close(g[key].cpu().numpy(), ref[rkey])
+        assert ok, (key, info)
+    num, _ = oracle.band_sums(inp)
+    for key, rkey in (("lgu", "lgu_bar"), ("sigma_u", "sigma_u_bar")):
+        dm = oracle.pipeline.mags_ion_tangent(inp, key)
+        bound = _abs_tangent_bound(inp, key, True)
+        dnum_abs = np.stack([oracle.photometry.band_integrals(inp.wave, bound[i], inp.z[i],
+                                                              inp.filt_wave, inp.filt_trans)[0]
+                             for i in range(inp.n_gal)])
+        tol = np.sum(np.abs(bar) * 1.09 * 2e-5 * (dnum_abs + np.abs(dm) * num / 1.0857362047581294)
+                     / num, axis=1)
+        got = g[key].cpu().numpy()
+        assert np.all(np.abs(got - ref[rkey]) <= tol + 1e-9), key
+        assert np.linalg.norm(got - ref[rkey]) <= 1e-3 * np.linalg.norm(ref[rkey]), key
+    ok, info = _grad_close(g["sfh_params"].cpu().numpy(), ref["sfh_params_bar"])
+    assert ok, ("sfh_params", info)
 
 
 # ---------------------------------------------------------------- Eq. eqw

@@ -273,3 +273,36 @@ def test_magnitude_tangent_matches_central_difference(which):
     fd = (ms[0] - ms[1]) / (2 * h)
     np.testing.assert_allclose(got, fd, rtol=1e-5, atol=1e-9 * np.abs(fd).max())
     assert np.abs(fd).max() > 0
+
+
+# ---------------------------------------------------------------- adjoint
+def test_adjoint_over_the_ionization_axis_matches_central_differences():
+    ssp = synth.make_ssp_nebular(n_u=5, lgu_range=(-4.0, -2.0), n_wave=400, wave_lo=1500.0,
+                                 wave_hi=12000.0, n_met=5, n_age=14, lg_age_range=(6.0, 10.0))
+    flt = synth.make_filters()
+    pop = synth.make_population(3, n_t=80, z_range=(0.1, 0.5), seed=57, nebular=True)
+    inp = oracle.prepare_inputs(ssp, flt, pop)
+    m = oracle.mags(inp)
+    g = oracle.mags_vjp(inp, 2 * (m - pop.targets))
+
+    def loss(mod):
+        p2 = oracle.prepare_inputs(ssp, flt, pop)
+        mod(p2)
+        p2.sfr = oracle.sfh.sfr_from_params(p2.t_table, p2.sfh_params)
+        return np.sum((oracle.mags(p2) - pop.targets) ** 2)
+
+    fields = {"lgu": "lgu_bar", "sigma_u": "sigma_u_bar", "lgmet": "lgmet_bar",
+              "sigma_z": "sigma_bar", "av": "av_bar", "delta": "delta_bar", "bump": "bump_bar"}
+    for gi in range(pop.n_gal):
+        for fld, key in fields.items():
+            h = 1e-5
+            def shift(p, s):
+                arr = getattr(p, fld).copy(); arr[gi] += s * h; setattr(p, fld, arr)
+            fd = (loss(lambda p: shift(p, 1)) - loss(lambda p: shift(p, -1))) / (2 * h)
+            assert g[key][gi] == pytest.approx(fd, rel=1e-5, abs=1e-7), (fld, gi)
+        k = 2                                              # alpha of the parametric history
+        h = 1e-5 * max(1.0, abs(inp.sfh_params[k, gi]))
+        def pp(p, s):
+            arr = p.sfh_params.copy(); arr[k, gi] += s * h; p.sfh_params = arr
+        fd = (loss(lambda p: pp(p, 1)) - loss(lambda p: pp(p, -1))) / (2 * h)
+        assert g["sfh_params_bar"][k, gi] == pytest.approx(fd, rel=1e-5, abs=1e-7)

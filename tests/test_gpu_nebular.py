@@ -358,3 +358,29 @@ def test_mags_ion_tangent_matches_oracle(dev, small, which):
     tol = 1.09 * 2e-5 * (dnum_abs + np.abs(ref * num / 1.0857362047581294)) / num
     assert np.all(np.abs(got - ref) <= tol + 1e-12)
     assert np.abs(ref).max() > 1e-3
+
+
+def test_nebular_limits_and_edges(dev):
+    """16 ionization points (the build's maximum) on a 16 x 96 grid; centres
+    beyond both ends of the ionization grid (the weight piles into the end
+    bins), a near-one-hot width, and an empty population."""
+    import torch
+    ssp = synth.make_ssp_nebular(n_u=16, lgu_range=(-4.0, -0.25), n_wave=700, wave_lo=1.0e3,
+                                 wave_hi=2.0e4, n_met=16, n_age=96, lg_age_range=(5.3, 10.15))
+    ssp_h = dev.SspBlock.from_synth(ssp)
+    flt_h = dev.FilterBank.from_synth(filters6())
+    pop = _pop(150, seed=119)
+    pop.lgu[:3] = np.array([-6.0, 1.5, -2.0])
+    pop.sigma_u[:3] = np.array([0.3, 0.3, 1e-4])
+    inp = _inputs(ssp, pop)
+    _say("nebular limits: n_u=16, 16 x 96 grid, n_gal=150")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
+    assert max_abs(m, oracle.mags(inp)) < FP32_TOL_MAG
+    sed = dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=False).cpu().numpy()
+    ref = oracle.sed(inp)
+    assert (np.abs(sed - ref) / ref).max() < 2e-5
+    empty = dev.DevicePopulation.from_synth(pop.subset(np.array([], dtype=int)), sfr=inp.sfr[:0])
+    assert dev.mags(ssp_h, flt_h, dev.Cosmology(), empty).shape == (0, 6)
+    assert dev.sed(ssp_h, dev.Cosmology(), empty).shape == (0, ssp.wave.size)
+    torch.cuda.synchronize()

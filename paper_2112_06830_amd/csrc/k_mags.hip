@@ -1,6 +1,8 @@
 // Fused magnitudes: SED tile = W . SSP on MFMA, then attenuation and the
 // redshifted filter integrals in registers (Section 2.1 Eqs. cspdeftheta and
-// full_mdf; Section 3.4 Eqs. attenuation-uvbump; Section 2.2.1 Eq. restmag).
+// full_mdf; Section 3.4 Eqs. attenuation-uvbump; Section 2.2.1 Eq. restmag),
+// optionally with age-dependent attenuation (Section 3.4.1) or over the
+// nebular ionization axis (Section 3.3, Eq. nebsed).
 // The SED never reaches memory: each workgroup reduces its 128 x 128
 // (wavelength x galaxy) tile straight into per-galaxy band sums.
 //

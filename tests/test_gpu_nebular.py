@@ -153,7 +153,7 @@ def test_block_constant_over_u_is_the_plain_block(dev):
 
 def test_nebular_unsupported_calls(dev, small):
     ssp_h, flt_h, ssp = small
-    pop = _pop(16, seed=103, )
+    pop = _pop(16, seed=103)
     dp = dev.DevicePopulation.from_synth(pop, use_params=True)
     with pytest.raises(Exception, match="precision"):
         dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, precision="bf16")

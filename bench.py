@@ -375,6 +375,22 @@ def run_nebular(P, steps, warmup, n_gal=100_000, seed=10, n_u=7):
     ms_ew = (time.perf_counter() - t0) * 1e3 / steps
     eqw_ms, _ = P.profile_read("eqw")
     P.profile_enable(False)
+    # the same widths, and their derivative in log10 U_s, straight from the
+    # population (the SED is computed only on the chunks near the lines)
+    for _ in range(warmup):
+        P.eqw_pop(ssp_h, P.Cosmology(), dpop, NEB_LINES)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ew_pop = P.eqw_pop(ssp_h, P.Cosmology(), dpop, NEB_LINES)
+    torch.cuda.synchronize()
+    ms_ew_pop = (time.perf_counter() - t0) * 1e3 / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, dew = P.eqw_pop(ssp_h, P.Cosmology(), dpop, NEB_LINES, wrt="lgu")
+    torch.cuda.synchronize()
+    ms_ew_pop_d = (time.perf_counter() - t0) * 1e3 / steps
+    same = bool(torch.equal(ew_pop, ew))
     # forward + adjoint of the squared error to target magnitudes, every
     # cotangent including the ionization centre and width
     targets = torch.tensor(pop.targets, dtype=torch.float32, device="cuda")
@@ -396,6 +412,10 @@ def run_nebular(P, steps, warmup, n_gal=100_000, seed=10, n_u=7):
                     "gemm_ms_per_step": gemm_ms / steps},
            "sed_and_eqw": {"ms_per_step": ms_ew, "galaxies_per_s": n_gal / (ms_ew * 1e-3),
                            "eqw_ms_per_step": eqw_ms / steps, "n_lines": len(NEB_LINES)},
+           "eqw_from_population": {"ms_per_step": ms_ew_pop,
+                                   "galaxies_per_s": n_gal / (ms_ew_pop * 1e-3),
+                                   "with_dW_dlgu_ms_per_step": ms_ew_pop_d,
+                                   "equal_to_sed_then_eqw": same},
            "mags_and_gradient": {"ms_per_step": ms_grad, "galaxies_per_s": n_gal / (ms_grad * 1e-3),
                                  "finite": bool(all(torch.isfinite(v).all().item()
                                                     for v in grads.values()))},
@@ -575,6 +595,7 @@ def main():
         extra["nebular_fp32_1e5"] = nb
         log(f"nebular 1e5: mags {nb['mags']['ms_per_step']:.3f} ms/step, "
             f"sed + widths {nb['sed_and_eqw']['ms_per_step']:.3f} ms/step, "
+            f"widths from the population {nb['eqw_from_population']['ms_per_step']:.3f} ms/step, "
             f"mags + gradient {nb['mags_and_gradient']['ms_per_step']:.3f} ms/step")
         va, va_sample = run_variants(P, max(3, args.steps // 4), 1)
         extra["variants_transition_mdf_wcdm_1e5"] = va

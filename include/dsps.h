@@ -365,6 +365,22 @@ int dsps_eqw(const dsps_ssp *ssp, const float *sed, int n_gal, const dsps_line *
 int dsps_eqw_jvp(const dsps_ssp *ssp, const float *sed, const float *dsed, int n_gal,
                  const dsps_line *lines, int n_line, float *eqw, float *deqw,
                  hipStream_t stream);
+/* Equivalent widths straight from a population, without the SED in memory:
+ * the (optionally attenuated) SED contraction of dsps_sed runs only on the
+ * 128-point wavelength chunks the lines' neighbourhoods touch (at most 64 in
+ * all, else DSPS_ERR_SHAPE), into workspace rows, and the widths follow as in
+ * dsps_eqw.  Every width equals dsps_eqw on dsps_sed's output bit for bit.
+ *   wrt    -1: widths only; 0 / 1: also their derivative in each galaxy's
+ *          ionization centre / width (as dsps_sed_ion_tangent then
+ *          dsps_eqw_jvp; SSP handle with n_u > 1)
+ *   eqw, deqw  [n_gal*n_line] float32, device (deqw only with wrt >= 0)
+ *   workspace  dsps_eqw_pop_workspace() bytes
+ * Float32; the handle needs the float32 table. */
+int dsps_eqw_pop_workspace(const dsps_ssp *ssp, int n_gal, const dsps_line *lines, int n_line,
+                           int wrt, size_t *bytes);
+int dsps_eqw_pop(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
+                 int apply_dust, const dsps_line *lines, int n_line, int wrt, float *eqw,
+                 float *deqw, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Population summary of the Section 4.1 forward model: a red-colour cut and

@@ -26,7 +26,7 @@ EXPORTS = (
     "dsps_mags_vjp", "dsps_quantize_bf16", "dsps_profile_enable", "dsps_profile_read",
     "dsps_pop_summary_workspace", "dsps_pop_summary", "dsps_pop_summary_vjp",
     "dsps_ssp_create_neb", "dsps_ssp_ion_info", "dsps_eqw", "dsps_eqw_jvp",
-    "dsps_sed_ion_tangent", "dsps_mags_ion_tangent",
+    "dsps_sed_ion_tangent", "dsps_mags_ion_tangent", "dsps_eqw_pop", "dsps_eqw_pop_workspace",
 )
 MAX_ION, MAX_LINES = 16, 16
 
@@ -81,6 +81,9 @@ def _declare(lib):
         "dsps_ssp_ion_info": (I, [P, IP]),
         "dsps_eqw": (I, [P, P, I, ctypes.POINTER(Line), I, P, P]),
         "dsps_eqw_jvp": (I, [P, P, P, I, ctypes.POINTER(Line), I, P, P, P]),
+        "dsps_eqw_pop_workspace": (I, [P, I, ctypes.POINTER(Line), I, I, ctypes.POINTER(S)]),
+        "dsps_eqw_pop": (I, [P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, ctypes.POINTER(Line), I,
+                             I, P, P, P, S, P]),
         "dsps_sed_ion_tangent": (I, [P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, I, P, P, S,
                                      P]),
         "dsps_mags_ion_tangent": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P,

@@ -330,6 +330,27 @@ def eqw(ssp: SspBlock, sed: torch.Tensor, lines, dsed: torch.Tensor | None = Non
     return out, dout
 
 
+def eqw_pop(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, lines, apply_dust=True,
+            wrt: str | None = None, stream=None):
+    """dsps_eqw_pop: equivalent widths [n_gal, n_line] straight from the
+    population (the SED is computed only near the lines); with wrt ("lgu" or
+    "sigma_u") returns (widths, their derivative)."""
+    arr, n_line = _lines(lines)
+    w = -1 if wrt is None else {"lgu": 0, "sigma_u": 1}[wrt]
+    nbytes = ctypes.c_size_t()
+    N.check(_lib().dsps_eqw_pop_workspace(ssp.handle, pop.n_gal, arr, n_line, w, ctypes.byref(nbytes)),
+            "dsps_eqw_pop_workspace")
+    buf, off = _workspace(int(nbytes.value), pop.device)
+    ws = ctypes.c_void_p(buf.data_ptr() + off) if buf is not None else None
+    out = torch.empty((pop.n_gal, n_line), dtype=torch.float32, device=pop.device)
+    dout = torch.empty_like(out) if w >= 0 else None
+    c, p = cosmo.c(), pop.c()
+    rc = _lib().dsps_eqw_pop(ssp.handle, ctypes.byref(c), ctypes.byref(p), int(bool(apply_dust)), arr,
+                             n_line, w, _ptr(out), _ptr(dout), ws, int(nbytes.value), _stream(stream))
+    N.check(rc, "dsps_eqw_pop")
+    return out if w < 0 else (out, dout)
+
+
 class Workspace:
     """Reusable workspace for repeated calls of one shape."""
 

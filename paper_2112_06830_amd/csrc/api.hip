@@ -450,7 +450,7 @@ constexpr int BATCH_VJP = 65536;
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
   size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0, tobs = 0, dust_old = 0;
-  size_t ion = 0, dion = 0;
+  size_t ion = 0, dion = 0, ebuf = 0, dbuf = 0;
   int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
@@ -1026,24 +1026,17 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
 
 }  // extern "C"
 
-static int eqw_common(const dsps_ssp *ssp, const float *sed, const float *dsed, int n_gal,
-                      const dsps_line *lines, int n_line, float *eqw, float *deqw,
-                      hipStream_t stream) {
+// Checks the lines and fills a.line (grid index ranges, inverted normal
+// matrices; sed_off 0) and a.wave / a.n_wave / a.n_line.
+static int prepare_lines(const dsps_ssp *ssp, const dsps_line *lines, int n_line, EqwLaunch &a) {
   DSPS_CHECK(ssp && lines, DSPS_ERR_ARG, "ssp or lines is NULL");
-  DSPS_CHECK(n_gal >= 0, DSPS_ERR_SHAPE, "n_gal %d negative", n_gal);
   DSPS_CHECK(n_line >= 1 && n_line <= DSPS_MAX_LINES, DSPS_ERR_SHAPE, "n_line %d outside [1, %d]",
              n_line, DSPS_MAX_LINES);
   const std::vector<double> &w = ssp->wave_host;
   const int n_wave = (int)w.size();
-  EqwLaunch a{};
   a.wave = ssp->v.wave;
-  a.sed = sed;
-  a.dsed = dsed;
-  a.n_gal = n_gal;
   a.n_wave = n_wave;
   a.n_line = n_line;
-  a.eqw = eqw;
-  a.deqw = deqw;
   for (int li = 0; li < n_line; ++li) {
     const dsps_line &L = lines[li];
     DSPS_CHECK(std::isfinite(L.centre) && std::isfinite(L.fit_half_width) && L.half_width > 0.0 &&
@@ -1080,11 +1073,57 @@ static int eqw_common(const dsps_ssp *ssp, const float *sed, const float *dsed, 
     DSPS_CHECK(det > 0.0L, DSPS_ERR_SHAPE, "line %d: continuum fit is singular", li);
     e.ginv[0] = (double)(a00 / det); e.ginv[1] = (double)(a01 / det); e.ginv[2] = (double)(a02 / det);
     e.ginv[3] = (double)(a11 / det); e.ginv[4] = (double)(a12 / det); e.ginv[5] = (double)(a22 / det);
+    e.sed_off = 0;
   }
+  return DSPS_OK;
+}
+
+static int eqw_common(const dsps_ssp *ssp, const float *sed, const float *dsed, int n_gal,
+                      const dsps_line *lines, int n_line, float *eqw, float *deqw,
+                      hipStream_t stream) {
+  DSPS_CHECK(n_gal >= 0, DSPS_ERR_SHAPE, "n_gal %d negative", n_gal);
+  EqwLaunch a{};
+  DSPS_TRY(prepare_lines(ssp, lines, n_line, a));
+  a.sed = sed;
+  a.dsed = dsed;
+  a.sed_stride = a.n_wave;
+  a.n_gal = n_gal;
+  a.eqw = eqw;
+  a.deqw = deqw;
   if (n_gal == 0) return DSPS_OK;
   DSPS_CHECK(sed && eqw, DSPS_ERR_ARG, "sed or eqw is NULL");
   DSPS_TRY(check_device(ssp->device));
   return launch_eqw(a, stream);
+}
+
+// Wavelength chunks the lines' neighbourhoods touch, line by line (a chunk
+// shared by two lines is listed twice), and each line's offset into the
+// compact rows that hold them.
+static int select_chunks(EqwLaunch &a, SedLaunch &s) {
+  s.n_sel = 0;
+  for (int li = 0; li < a.n_line; ++li) {
+    EqwLine &e = a.line[li];
+    const int c0 = e.f0 / TILE_L, c1 = (e.f1 - 1) / TILE_L + 1;
+    DSPS_CHECK(s.n_sel + (c1 - c0) <= SED_MAX_CHUNKS, DSPS_ERR_SHAPE,
+               "the lines' neighbourhoods span more than %d wavelength chunks of %d points",
+               SED_MAX_CHUNKS, TILE_L);
+    e.sed_off = (s.n_sel - c0) * TILE_L;
+    for (int c = c0; c < c1; ++c) s.chunk_list[s.n_sel++] = c;
+  }
+  s.out_stride = s.n_sel * TILE_L;
+  return DSPS_OK;
+}
+
+// Workspace of dsps_eqw_pop: the SED call's, then the compact SED rows (and
+// their tangent) of one batch.
+static size_t eqw_pop_bytes(const SspView &v, int n_gal, int n_sel, bool tangent, Layout *out) {
+  Layout L = make_layout(DSPS_OP_SED, v, 0, n_gal, DSPS_FP32);
+  const size_t rows = align256(sizeof(float) * (size_t)L.batch * n_sel * TILE_L);
+  L.ebuf = L.total;
+  L.dbuf = L.total + rows;
+  L.total += rows * (tangent ? 2 : 1);
+  if (out) *out = L;
+  return L.total;
 }
 
 extern "C" {
@@ -1098,6 +1137,83 @@ int dsps_eqw_jvp(const dsps_ssp *ssp, const float *sed, const float *dsed, int n
                  const dsps_line *lines, int n_line, float *eqw, float *deqw, hipStream_t stream) {
   DSPS_CHECK(n_gal == 0 || (dsed && deqw), DSPS_ERR_ARG, "dsed or deqw is NULL");
   return eqw_common(ssp, sed, dsed, n_gal, lines, n_line, eqw, deqw, stream);
+}
+
+int dsps_eqw_pop_workspace(const dsps_ssp *ssp, int n_gal, const dsps_line *lines, int n_line,
+                           int wrt, size_t *bytes) {
+  DSPS_CHECK(bytes, DSPS_ERR_ARG, "bytes is NULL");
+  DSPS_CHECK(n_gal >= 0, DSPS_ERR_SHAPE, "n_gal %d negative", n_gal);
+  EqwLaunch a{};
+  SedLaunch s{};
+  DSPS_TRY(prepare_lines(ssp, lines, n_line, a));
+  DSPS_TRY(select_chunks(a, s));
+  *bytes = eqw_pop_bytes(ssp->v, n_gal, s.n_sel, wrt >= 0, nullptr);
+  return DSPS_OK;
+}
+
+int dsps_eqw_pop(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
+                 int apply_dust, const dsps_line *lines, int n_line, int wrt, float *eqw,
+                 float *deqw, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  DSPS_CHECK(ssp, DSPS_ERR_ARG, "ssp is NULL");
+  DSPS_TRY(check_cosmo(cosmo));
+  DSPS_TRY(check_pop(pop, apply_dust != 0));
+  DSPS_CHECK(apply_dust == 0 || apply_dust == 1, DSPS_ERR_ARG, "apply_dust must be 0 or 1");
+  DSPS_CHECK(wrt >= -1 && wrt <= 1, DSPS_ERR_ARG, "wrt must be -1 (none), 0 (lgu) or 1 (sigma_u)");
+  DSPS_CHECK(wrt < 0 || ssp->v.n_u > 1, DSPS_ERR_UNSUPPORTED, "the SSP block has no ionization axis");
+  DSPS_CHECK(!(apply_dust && pop->av_old), DSPS_ERR_UNSUPPORTED,
+             "dsps_eqw_pop does not apply the age-dependent attenuation");
+  DSPS_TRY(check_precision(ssp, DSPS_FP32));
+  DSPS_TRY(check_ion(ssp, pop));
+  EqwLaunch e{};
+  SedLaunch s{};
+  DSPS_TRY(prepare_lines(ssp, lines, n_line, e));
+  DSPS_TRY(select_chunks(e, s));
+  if (pop->n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(eqw && (wrt < 0 || deqw), DSPS_ERR_ARG, "eqw or deqw is NULL");
+  DSPS_TRY(check_device(ssp->device));
+  Layout L;
+  DSPS_TRY(check_workspace(workspace, workspace_bytes,
+                           eqw_pop_bytes(ssp->v, pop->n_gal, s.n_sel, wrt >= 0, &L)));
+  char *ws = (char *)workspace;
+  GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
+  GalaxyIon *ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
+  float *rows = (float *)(ws + L.ebuf), *drows = (float *)(ws + L.dbuf);
+  for (int g0 = 0; g0 < pop->n_gal; g0 += L.batch) {
+    const int cnt = std::min(L.batch, pop->n_gal - g0);
+    WeightsLaunch a = base_weights(ssp, cosmo, pop);
+    a.perm = nullptr;
+    a.s_begin = g0;
+    a.s_count = cnt;
+    a.w_pad = ws + L.w;
+    a.meta = apply_dust ? meta : nullptr;
+    a.ion = ion;
+    a.t_obs = (double *)(ws + L.tobs);
+    DSPS_TRY(launch_weights(a, stream));
+    s.ssp = ssp->v;
+    s.precision = DSPS_FP32;
+    s.apply_dust = apply_dust;
+    s.g_begin = g0;
+    s.g_count = cnt;
+    s.w_pad = ws + L.w;
+    s.meta = meta;
+    s.ion = ion;
+    s.ion_tangent = 0;
+    s.sed = rows;
+    DSPS_TRY(launch_sed_gemm(s, stream));
+    if (wrt >= 0) {
+      s.ion_tangent = 1 + wrt;
+      s.sed = drows;
+      DSPS_TRY(launch_sed_gemm(s, stream));
+    }
+    e.sed = rows;
+    e.dsed = wrt >= 0 ? drows : nullptr;
+    e.sed_stride = s.out_stride;
+    e.n_gal = cnt;
+    e.eqw = eqw + (size_t)g0 * n_line;
+    e.deqw = wrt >= 0 ? deqw + (size_t)g0 * n_line : nullptr;
+    DSPS_TRY(launch_eqw(e, stream));
+  }
+  return DSPS_OK;
 }
 
 static int check_summary(const float *mags, int n_gal, int n_band, int band_a, int band_b,

@@ -408,23 +408,29 @@ int launch_mags_finalize(const FinalizeLaunch &a, hipStream_t stream);
 
 // Defined in k_eqw.hip.  Per line: centre, 1 / fit_half_width, the grid
 // index ranges of the neighbourhood [f0, f1) and of the line window [m0, m1)
-// (the continuum points are the first without the second), and the inverse
-// of the continuum fit's normal matrix, upper triangle row by row.
+// (the continuum points are the first without the second), the inverse of
+// the continuum fit's normal matrix, upper triangle row by row, and the
+// offset of grid point n in an SED row (n + sed_off: 0 for full rows).
 struct EqwLine {
   double centre, inv_fit;
   int f0, f1, m0, m1;
+  int sed_off, pad;
   double ginv[6];
 };
 struct EqwLaunch {
   const double *wave;   // [n_wave] rest Angstrom, device
-  const float *sed;     // [n_gal][n_wave]
-  const float *dsed;    // [n_gal][n_wave] tangent of the SED, or null
+  const float *sed;     // [n_gal][sed_stride]
+  const float *dsed;    // [n_gal][sed_stride] tangent of the SED, or null
+  int sed_stride;
   int n_gal, n_wave, n_line;
   float *eqw;           // [n_gal][n_line]
   float *deqw;          // [n_gal][n_line] tangent of the widths (with dsed)
   EqwLine line[DSPS_MAX_LINES];
 };
 int launch_eqw(const EqwLaunch &a, hipStream_t stream);
+
+// Wavelength chunks one selective SED launch may compute.
+constexpr int SED_MAX_CHUNKS = 64;
 
 // Defined in k_sed.hip.
 struct SedLaunch {
@@ -437,6 +443,12 @@ struct SedLaunch {
   // with ion: 0 the SED, 1 its derivative in the ionization centre, 2 in the
   // ionization width (the weights of the points replaced by their derivatives)
   int ion_tangent;
+  // chunk selection (n_sel > 0): block x computes wavelength chunk
+  // chunk_list[x] and writes it to columns x * TILE_L.. of row g - g_begin of
+  // rows of out_stride floats (whole chunks, padding included); n_sel == 0:
+  // every chunk, row g of n_wave floats
+  int n_sel, out_stride;
+  int chunk_list[SED_MAX_CHUNKS];
   float *sed;                   // [n_gal][n_wave]
 };
 int launch_sed_gemm(const SedLaunch &a, hipStream_t stream);

@@ -31,17 +31,19 @@ __global__ __launch_bounds__(256) void k_eqw(EqwLaunch a) {
   const int lane = threadIdx.x & 63;
   const int g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (g >= a.n_gal) return;   // whole waves leave together
-  const float *row = a.sed + (size_t)g * a.n_wave;
   const bool tangent = a.dsed != nullptr;
-  const float *drow = tangent ? a.dsed + (size_t)g * a.n_wave : row;
   for (int li = 0; li < a.n_line; ++li) {
     const EqwLine &ln = a.line[li];
+    // grid point n sits at row[n + off] (off is 0 for full rows)
+    const float *row = a.sed + (size_t)g * a.sed_stride;
+    const float *drow = tangent ? a.dsed + (size_t)g * a.sed_stride : row;
+    const int off = ln.sed_off;
     // moments of the SED (and of its tangent) over the continuum points
     double b[3] = {0.0, 0.0, 0.0}, db[3] = {0.0, 0.0, 0.0};
     for (int n = ln.f0 + lane; n < ln.f1; n += 64) {
       if (n >= ln.m0 && n < ln.m1) continue;
       const double x = (a.wave[n] - ln.centre) * ln.inv_fit;
-      const double v = (double)row[n], dv = (double)drow[n];
+      const double v = (double)row[n + off], dv = (double)drow[n + off];
       b[0] += v;
       b[1] += v * x;
       b[2] += v * x * x;
@@ -59,13 +61,13 @@ __global__ __launch_bounds__(256) void k_eqw(EqwLaunch a) {
       const double x0 = (l0 - ln.centre) * ln.inv_fit, x1 = (l1 - ln.centre) * ln.inv_fit;
       const double k0 = c[0] + c[1] * x0 + c[2] * x0 * x0;
       const double k1 = c[0] + c[1] * x1 + c[2] * x1 * x1;
-      const double v0 = (double)row[n], v1 = (double)row[n + 1];
+      const double v0 = (double)row[n + off], v1 = (double)row[n + 1 + off];
       s += 0.5 * ((v0 - k0) / k0 + (v1 - k1) / k1) * (l1 - l0);
       if (tangent) {
         const double dk0 = dc[0] + dc[1] * x0 + dc[2] * x0 * x0;
         const double dk1 = dc[0] + dc[1] * x1 + dc[2] * x1 * x1;
-        const double r0 = ((double)drow[n] * k0 - v0 * dk0) / (k0 * k0);
-        const double r1 = ((double)drow[n + 1] * k1 - v1 * dk1) / (k1 * k1);
+        const double r0 = ((double)drow[n + off] * k0 - v0 * dk0) / (k0 * k0);
+        const double r1 = ((double)drow[n + 1 + off] * k1 - v1 * dk1) / (k1 * k1);
         ds += 0.5 * (r0 + r1) * (l1 - l0);
       }
     }

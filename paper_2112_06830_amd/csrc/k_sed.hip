@@ -18,7 +18,8 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   __shared__ GemmSmem<PREC> sm[2];
   __shared__ float s_pn[NEB ? DSPS_MAX_ION * TILE_G : 1];
   __shared__ int s_urange[2];
-  const int chunk = blockIdx.x, tile = blockIdx.y;
+  const int chunk = a.n_sel ? a.chunk_list[blockIdx.x] : (int)blockIdx.x;
+  const int tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
   const SspView P = a.ssp;
@@ -85,13 +86,16 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
       const GalaxyMeta m = a.meta[g];
       da = m.dust_a; dl = m.delta; bp = m.bump;
     }
-    float *out = a.sed + (size_t)g * P.n_wave;
+    // out[l] is grid point l of the galaxy's row (full rows), or of its
+    // slot of the selected chunks
+    float *out = a.n_sel ? a.sed + (size_t)(g - a.g_begin) * a.out_stride + blockIdx.x * TILE_L - l0
+                         : a.sed + (size_t)g * P.n_wave;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int l = l0 + wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        if (l >= P.n_wave) continue;
+        if (!a.n_sel && l >= P.n_wave) continue;
         float v = acc[mb][nb][r];
         if (a.apply_dust) {
           const float4 lc = P.lconst[l];
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
 
 int launch_sed_gemm(const SedLaunch &a, hipStream_t stream) {
   if (a.g_count <= 0) return DSPS_OK;
-  const dim3 grid(a.ssp.n_wave_pad / TILE_L, (a.g_count + TILE_G - 1) / TILE_G);
+  const dim3 grid(a.n_sel ? a.n_sel : a.ssp.n_wave_pad / TILE_L, (a.g_count + TILE_G - 1) / TILE_G);
   ProfScope prof(DSPS_KERNEL_SED_GEMM, stream);
   if (a.ion) {
     if (a.precision != DSPS_FP32 || !a.ssp.st32) return DSPS_ERR_UNSUPPORTED;

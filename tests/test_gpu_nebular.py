@@ -384,3 +384,54 @@ def test_nebular_limits_and_edges(dev):
     assert dev.mags(ssp_h, flt_h, dev.Cosmology(), empty).shape == (0, 6)
     assert dev.sed(ssp_h, dev.Cosmology(), empty).shape == (0, ssp.wave.size)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("apply_dust,wrt", [(True, None), (False, "lgu"), (True, "sigma_u")])
+def test_eqw_pop_equals_sed_then_widths(dev, small, apply_dust, wrt):
+    """The widths straight from the population, computed on the line chunks
+    only, are bit for bit those of dsps_sed (or dsps_sed_ion_tangent)
+    followed by dsps_eqw (or dsps_eqw_jvp): the same tiles run the same
+    contraction on those chunks.  One galaxy is also checked against the
+    oracle's width."""
+    ssp_h, _, ssp = small
+    pop = _pop(300, seed=121)
+    pop.sfh_params[3] = 0.3 * pop.sfh_params[3]
+    inp = _inputs(ssp, pop)
+    _say(f"eqw straight from the population dust={apply_dust} wrt={wrt} n_gal=300")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    sed = dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=apply_dust)
+    if wrt is None:
+        got = dev.eqw_pop(ssp_h, dev.Cosmology(), dp, LINES, apply_dust=apply_dust).cpu().numpy()
+        ref = dev.eqw(ssp_h, sed, LINES).cpu().numpy()
+        np.testing.assert_array_equal(got, ref)
+    else:
+        w, dw = dev.eqw_pop(ssp_h, dev.Cosmology(), dp, LINES, apply_dust=apply_dust, wrt=wrt)
+        dsed = dev.sed_ion_tangent(ssp_h, dev.Cosmology(), dp, wrt=wrt, apply_dust=apply_dust)
+        rw, rdw = dev.eqw(ssp_h, sed, LINES, dsed=dsed)
+        np.testing.assert_array_equal(w.cpu().numpy(), rw.cpu().numpy())
+        np.testing.assert_array_equal(dw.cpu().numpy(), rdw.cpu().numpy())
+        got = w.cpu().numpy()
+    c, h, f = LINES[2]
+    one = oracle.nebular.equivalent_width(ssp.wave, oracle.sed(inp.subset([7]), apply_dust=apply_dust),
+                                          c, h, f)
+    assert abs(got[7, 2] - one[0]) <= 8e-5 * (2 * h + abs(one[0]))
+
+
+def test_eqw_pop_plain_block_limits_and_errors(dev):
+    import torch
+    base = synth.make_ssp(n_wave=1000, wave_lo=1.0e3, wave_hi=2.0e4)
+    plain_h = dev.SspBlock.from_synth(base, precisions=("fp32",))
+    pop = synth.make_population(40, n_t=100, z_range=(0.1, 1.0), seed=123)
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    _say("eqw straight from the population, plain block n_gal=40")
+    got = dev.eqw_pop(plain_h, dev.Cosmology(), dp, LINES).cpu().numpy()
+    ref = dev.eqw(plain_h, dev.sed(plain_h, dev.Cosmology(), dp), LINES).cpu().numpy()
+    np.testing.assert_array_equal(got, ref)
+    with pytest.raises(Exception, match="ionization"):
+        dev.eqw_pop(plain_h, dev.Cosmology(), dp, LINES, wrt="lgu")
+    wide = [(c, 40.0, 6000.0) for c in np.linspace(7000.0, 13000.0, 16)]   # 79 chunks
+    with pytest.raises(Exception, match="chunks"):
+        dev.eqw_pop(plain_h, dev.Cosmology(), dp, wide)
+    empty = dev.DevicePopulation.from_synth(pop.subset(np.array([], dtype=int)), use_params=True)
+    assert dev.eqw_pop(plain_h, dev.Cosmology(), empty, LINES).shape == (0, len(LINES))
+    torch.cuda.synchronize()

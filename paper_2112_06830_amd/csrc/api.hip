@@ -469,10 +469,14 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
     return L;
   }
   if (op == DSPS_OP_SED) {
+    L.hist = take(sizeof(int) * SORT_BINS);
+    L.perm = take(sizeof(int) * (size_t)n_gal);
     L.meta = take(sizeof(GalaxyMeta) * (size_t)n_gal);
+    L.range = take(sizeof(GalaxyRange) * (size_t)n_gal);
     L.tobs = take(sizeof(double) * (size_t)n_gal);
     if (v.n_u > 1) L.ion = take(sizeof(GalaxyIon) * (size_t)n_gal);
     L.w = take(elem * (size_t)L.batch * v.k_pad);
+    L.tiles = take(sizeof(TilePlan) * (size_t)((L.batch + TILE_G - 1) / TILE_G));
     L.total = off;
     return L;
   }
@@ -664,6 +668,54 @@ int dsps_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *p
 
 }  // extern "C"
 
+// Unfused SED set-up for the sorted batch [s0, s0 + cnt): weights (W rows,
+// per-galaxy scalars, non-zero block masks, ionization supports) and the
+// tiles' stage lists.  The ordering sort has run.
+static int sed_batch_prepare(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
+                             int precision, const Layout &L, char *ws, int s0, int cnt,
+                             hipStream_t stream) {
+  GalaxyIon *ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
+  WeightsLaunch a = base_weights(ssp, cosmo, pop);
+  a.perm = (const int *)(ws + L.perm);
+  a.s_begin = s0;
+  a.s_count = cnt;
+  a.w_pad = ws + L.w;
+  a.w_pad_bf16 = precision == DSPS_BF16;
+  a.meta = (GalaxyMeta *)(ws + L.meta);
+  a.range = (GalaxyRange *)(ws + L.range);
+  a.obs_lo = 0.0;   // the whole grid (the window is not used here)
+  a.obs_hi = std::numeric_limits<double>::infinity();
+  a.ion = ion;
+  a.t_obs = (double *)(ws + L.tobs);
+  DSPS_TRY(launch_weights(a, stream));
+  MagsLaunch m{};
+  m.ssp = ssp->v;
+  m.precision = precision;
+  m.s_begin = s0;
+  m.s_count = cnt;
+  m.meta = (const GalaxyMeta *)(ws + L.meta);
+  m.range = (const GalaxyRange *)(ws + L.range);
+  m.ion = ion;
+  m.plan = (TilePlan *)(ws + L.tiles);
+  return launch_tile_plan(m, stream);
+}
+
+static SedLaunch sed_launch(const dsps_ssp *ssp, const Layout &L, char *ws, int precision,
+                            int apply_dust, int s0, int cnt) {
+  SedLaunch s{};
+  s.ssp = ssp->v;
+  s.precision = precision;
+  s.apply_dust = apply_dust;
+  s.g_begin = s0;
+  s.g_count = cnt;
+  s.perm = (const int *)(ws + L.perm);
+  s.plan = (const TilePlan *)(ws + L.tiles);
+  s.w_pad = ws + L.w;
+  s.meta = (const GalaxyMeta *)(ws + L.meta);
+  s.ion = ssp->v.n_u > 1 ? (const GalaxyIon *)(ws + L.ion) : nullptr;
+  return s;
+}
+
 // dsps_sed and, with ion_tangent 1 or 2, dsps_sed_ion_tangent.
 static int sed_common(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
                       int apply_dust, int precision, int ion_tangent, float *sed, void *workspace,
@@ -682,29 +734,11 @@ static int sed_common(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_p
   const Layout L = make_layout(DSPS_OP_SED, ssp->v, 0, pop->n_gal, precision);
   DSPS_TRY(check_workspace(workspace, workspace_bytes, L.total));
   char *ws = (char *)workspace;
-  GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
-  GalaxyIon *ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
-  for (int g0 = 0; g0 < pop->n_gal; g0 += L.batch) {
-    const int cnt = std::min(L.batch, pop->n_gal - g0);
-    WeightsLaunch a = base_weights(ssp, cosmo, pop);
-    a.perm = nullptr;
-    a.s_begin = g0;
-    a.s_count = cnt;
-    a.w_pad = ws + L.w;
-    a.w_pad_bf16 = precision == DSPS_BF16;
-    a.meta = apply_dust ? meta : nullptr;
-    a.ion = ion;
-    a.t_obs = (double *)(ws + L.tobs);
-    DSPS_TRY(launch_weights(a, stream));
-    SedLaunch s{};
-    s.ssp = ssp->v;
-    s.precision = precision;
-    s.apply_dust = apply_dust;
-    s.g_begin = g0;
-    s.g_count = cnt;
-    s.w_pad = ws + L.w;
-    s.meta = meta;
-    s.ion = ion;
+  DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), (int *)(ws + L.perm), stream));
+  for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
+    const int cnt = std::min(L.batch, pop->n_gal - s0);
+    DSPS_TRY(sed_batch_prepare(ssp, cosmo, pop, precision, L, ws, s0, cnt, stream));
+    SedLaunch s = sed_launch(ssp, L, ws, precision, apply_dust, s0, cnt);
     s.ion_tangent = ion_tangent;
     s.sed = sed;
     DSPS_TRY(launch_sed_gemm(s, stream));
@@ -1175,42 +1209,32 @@ int dsps_eqw_pop(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *p
   DSPS_TRY(check_workspace(workspace, workspace_bytes,
                            eqw_pop_bytes(ssp->v, pop->n_gal, s.n_sel, wrt >= 0, &L)));
   char *ws = (char *)workspace;
-  GalaxyMeta *meta = (GalaxyMeta *)(ws + L.meta);
-  GalaxyIon *ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
   float *rows = (float *)(ws + L.ebuf), *drows = (float *)(ws + L.dbuf);
-  for (int g0 = 0; g0 < pop->n_gal; g0 += L.batch) {
-    const int cnt = std::min(L.batch, pop->n_gal - g0);
-    WeightsLaunch a = base_weights(ssp, cosmo, pop);
-    a.perm = nullptr;
-    a.s_begin = g0;
-    a.s_count = cnt;
-    a.w_pad = ws + L.w;
-    a.meta = apply_dust ? meta : nullptr;
-    a.ion = ion;
-    a.t_obs = (double *)(ws + L.tobs);
-    DSPS_TRY(launch_weights(a, stream));
-    s.ssp = ssp->v;
-    s.precision = DSPS_FP32;
-    s.apply_dust = apply_dust;
-    s.g_begin = g0;
-    s.g_count = cnt;
-    s.w_pad = ws + L.w;
-    s.meta = meta;
-    s.ion = ion;
-    s.ion_tangent = 0;
-    s.sed = rows;
-    DSPS_TRY(launch_sed_gemm(s, stream));
+  DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), (int *)(ws + L.perm), stream));
+  for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
+    const int cnt = std::min(L.batch, pop->n_gal - s0);
+    DSPS_TRY(sed_batch_prepare(ssp, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, stream));
+    SedLaunch b = sed_launch(ssp, L, ws, DSPS_FP32, apply_dust, s0, cnt);
+    b.n_sel = s.n_sel;
+    b.out_stride = s.out_stride;
+    for (int x = 0; x < s.n_sel; ++x) b.chunk_list[x] = s.chunk_list[x];
+    b.ion_tangent = 0;
+    b.sed = rows;
+    DSPS_TRY(launch_sed_gemm(b, stream));
     if (wrt >= 0) {
-      s.ion_tangent = 1 + wrt;
-      s.sed = drows;
-      DSPS_TRY(launch_sed_gemm(s, stream));
+      b.ion_tangent = 1 + wrt;
+      b.sed = drows;
+      DSPS_TRY(launch_sed_gemm(b, stream));
     }
+    // compact rows are in sorted order: row r is galaxy perm[s0 + r]
     e.sed = rows;
     e.dsed = wrt >= 0 ? drows : nullptr;
     e.sed_stride = s.out_stride;
     e.n_gal = cnt;
-    e.eqw = eqw + (size_t)g0 * n_line;
-    e.deqw = wrt >= 0 ? deqw + (size_t)g0 * n_line : nullptr;
+    e.perm = (const int *)(ws + L.perm);
+    e.row_begin = s0;
+    e.eqw = eqw;
+    e.deqw = wrt >= 0 ? deqw : nullptr;
     DSPS_TRY(launch_eqw(e, stream));
   }
   return DSPS_OK;

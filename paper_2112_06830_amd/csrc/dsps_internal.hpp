@@ -386,6 +386,9 @@ struct MagsLaunch {
 // Components per band of the chunk partials.
 __host__ __device__ inline int mags_components(int moments) { return moments ? 5 : 2; }
 int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream);
+// The planning pass alone (reads ssp, precision, s_begin, s_count, meta,
+// range, ion, age_dust; writes plan), for the unfused SED.
+int launch_tile_plan(const MagsLaunch &a, hipStream_t stream);
 
 struct FinalizeLaunch {
   int n_band, n_chunks;
@@ -425,6 +428,10 @@ struct EqwLaunch {
   int n_gal, n_wave, n_line;
   float *eqw;           // [n_gal][n_line]
   float *deqw;          // [n_gal][n_line] tangent of the widths (with dsed)
+  // SED row r holds galaxy perm[row_begin + r] (rows in sorted order), or
+  // galaxy r when perm is null; the widths go to that galaxy's row
+  const int *perm;
+  int row_begin;
   EqwLine line[DSPS_MAX_LINES];
 };
 int launch_eqw(const EqwLaunch &a, hipStream_t stream);
@@ -433,20 +440,25 @@ int launch_eqw(const EqwLaunch &a, hipStream_t stream);
 constexpr int SED_MAX_CHUNKS = 64;
 
 // Defined in k_sed.hip.
+// Galaxies are in the ordering sort's order: g_begin, g_count is a range of
+// sorted positions, perm maps a position to its galaxy, and plan holds each
+// 128-galaxy tile's stage list (non-zero weight blocks) and ionization range.
 struct SedLaunch {
   SspView ssp;
   int precision, apply_dust;
   int g_begin, g_count;
-  const void *w_pad;            // [g_count][k_pad]
-  const GalaxyMeta *meta;       // by galaxy index (identity order)
-  const GalaxyIon *ion;         // by galaxy index, or null (no ionization axis)
+  const int *perm;
+  const TilePlan *plan;         // [tiles of the range]
+  const void *w_pad;            // [g_count][k_pad], by sorted position - g_begin
+  const GalaxyMeta *meta;       // by sorted position
+  const GalaxyIon *ion;         // by sorted position, or null (no ionization axis)
   // with ion: 0 the SED, 1 its derivative in the ionization centre, 2 in the
   // ionization width (the weights of the points replaced by their derivatives)
   int ion_tangent;
   // chunk selection (n_sel > 0): block x computes wavelength chunk
-  // chunk_list[x] and writes it to columns x * TILE_L.. of row g - g_begin of
-  // rows of out_stride floats (whole chunks, padding included); n_sel == 0:
-  // every chunk, row g of n_wave floats
+  // chunk_list[x] and writes it to columns x * TILE_L.. of row s - g_begin
+  // (s the sorted position) of rows of out_stride floats (whole chunks,
+  // padding included); n_sel == 0: every chunk, row perm[s] of n_wave floats
   int n_sel, out_stride;
   int chunk_list[SED_MAX_CHUNKS];
   float *sed;                   // [n_gal][n_wave]

@@ -72,10 +72,11 @@ __global__ __launch_bounds__(256) void k_eqw(EqwLaunch a) {
       }
     }
     s = wave_sum(s);
-    if (lane == 0) a.eqw[(size_t)g * a.n_line + li] = (float)s;
+    const size_t go = a.perm ? (size_t)a.perm[a.row_begin + g] : (size_t)g;   // output galaxy
+    if (lane == 0) a.eqw[go * a.n_line + li] = (float)s;
     if (tangent) {
       ds = wave_sum(ds);
-      if (lane == 0) a.deqw[(size_t)g * a.n_line + li] = (float)ds;
+      if (lane == 0) a.deqw[go * a.n_line + li] = (float)ds;
     }
   }
 }

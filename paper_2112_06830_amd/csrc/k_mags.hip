@@ -499,15 +499,22 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
   pl->u_hi = s_tile[6];
 }
 
+int launch_tile_plan(const MagsLaunch &a, hipStream_t stream) {
+  if (a.s_count <= 0) return DSPS_OK;
+  const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
+  if (a.precision == DSPS_BF16)
+    hipLaunchKernelGGL(k_tile_plan<DSPS_BF16>, dim3(n_tiles), dim3(TILE_G), 0, stream, a);
+  else
+    hipLaunchKernelGGL(k_tile_plan<DSPS_FP32>, dim3(n_tiles), dim3(TILE_G), 0, stream, a);
+  return hip_fail(hipGetLastError(), "k_tile_plan launch");
+}
+
 int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
   const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
   const int blocks = (n_tiles + 7) / 8 * 8 * a.n_groups;
   size_t lds = sizeof(float) * a.flt.n_band * filter_stride(a.flt.n_pts);
-  if (a.precision == DSPS_BF16)
-    hipLaunchKernelGGL(k_tile_plan<DSPS_BF16>, dim3(n_tiles), dim3(TILE_G), 0, stream, a);
-  else
-    hipLaunchKernelGGL(k_tile_plan<DSPS_FP32>, dim3(n_tiles), dim3(TILE_G), 0, stream, a);
+  if (int rc = launch_tile_plan(a, stream)) return rc;
   ProfScope prof(DSPS_KERNEL_MAGS_GEMM, stream);
   if (a.age_dust) {
     if (a.precision != DSPS_FP32 || a.moments || !a.ssp.sa32 || a.ion) return DSPS_ERR_UNSUPPORTED;

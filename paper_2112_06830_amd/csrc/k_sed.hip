@@ -6,6 +6,12 @@
 // scaled by its weight of the point as it is staged; with ion_tangent the
 // weights are replaced by their derivatives in the distribution's centre or
 // width, which gives the SED's derivative (the sum is linear in them).
+//
+// Galaxies come in the ordering sort's order, so a tile's members share few
+// metallicity rows and ages: the K loop runs over the tile's stage list (the
+// weight blocks non-zero for some member), as in the fused kernel.  Skipped
+// blocks are zero for every member, so a galaxy's result does not depend on
+// its tile.
 #include "gemm_core.hpp"
 
 namespace dsps {
@@ -17,7 +23,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   static_assert(!NEB || PREC == DSPS_FP32, "the ionization axis is float32 only");
   __shared__ GemmSmem<PREC> sm[2];
   __shared__ float s_pn[NEB ? DSPS_MAX_ION * TILE_G : 1];
-  __shared__ int s_urange[2];
+  __shared__ int s_koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];   // K offset of each stage
   const int chunk = a.n_sel ? a.chunk_list[blockIdx.x] : (int)blockIdx.x;
   const int tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -36,19 +42,13 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
 
-  const int nk = P.k_pad / C::KT;
+  const TilePlan *pl = a.plan + tile;
+  const int nk = pl->nk;
+  for (int t = threadIdx.x; t < nk; t += blockDim.x) s_koff[t] = pl->koff[t];
   if constexpr (NEB) {
-    // the tile's ionization points, then every member's weight of each
-    if (threadIdx.x == 0) { s_urange[0] = 1 << 30; s_urange[1] = 0; }
-    __syncthreads();
+    // every member's weight of each of the tile's ionization points
     const int nvalid = min(TILE_G, a.g_count - g0);
-    if ((int)threadIdx.x < nvalid) {
-      const GalaxyIon gi = a.ion[a.g_begin + g0 + threadIdx.x];
-      atomicMin(&s_urange[0], gi.u_lo);
-      atomicMax(&s_urange[1], gi.u_hi);
-    }
-    __syncthreads();
-    const int u_lo = s_urange[0], n_uu = s_urange[1] - s_urange[0] + 1;
+    const int u_lo = pl->u_lo, n_uu = pl->u_hi - pl->u_lo + 1;
     for (int t = threadIdx.x; t < n_uu * TILE_G; t += blockDim.x) {
       const int uu = t / TILE_G, col = t - uu * TILE_G;
       float f = 0.0f;
@@ -67,12 +67,13 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
     gemm_kloop_ab<PREC>(sm, st, P.k_row, l0, w, kp, g0, a.g_count, nk * n_uu,
                         [&](int s) {
                           const int uu = s / nk;
-                          const int k = (s - uu * nk) * C::KT;
+                          const int k = s_koff[s - uu * nk];
                           return StageSrc{(u_lo + uu) * kp + k, k, s_pn + uu * TILE_G};
                         },
                         wr, wc, lane, acc);
   } else {
-    gemm_kloop<PREC>(sm, st, P.k_pad, l0, w, g0, a.g_count, nk, [](int ks) { return ks * C::KT; },
+    __syncthreads();
+    gemm_kloop<PREC>(sm, st, P.k_pad, l0, w, g0, a.g_count, nk, [&](int ks) { return s_koff[ks]; },
                      wr, wc, lane, acc);
   }
 
@@ -80,16 +81,16 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   for (int nb = 0; nb < 2; ++nb) {
     const int col = wc * 64 + nb * 32 + (lane & 31);
     if (g0 + col >= a.g_count) continue;
-    const int g = a.g_begin + g0 + col;
+    const int s = a.g_begin + g0 + col;     // sorted position
     float da = 0.0f, dl = 0.0f, bp = 0.0f;
     if (a.apply_dust) {
-      const GalaxyMeta m = a.meta[g];
+      const GalaxyMeta m = a.meta[s];
       da = m.dust_a; dl = m.delta; bp = m.bump;
     }
     // out[l] is grid point l of the galaxy's row (full rows), or of its
     // slot of the selected chunks
-    float *out = a.n_sel ? a.sed + (size_t)(g - a.g_begin) * a.out_stride + blockIdx.x * TILE_L - l0
-                         : a.sed + (size_t)g * P.n_wave;
+    float *out = a.n_sel ? a.sed + (size_t)(g0 + col) * a.out_stride + blockIdx.x * TILE_L - l0
+                         : a.sed + (size_t)a.perm[s] * P.n_wave;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll

@@ -435,3 +435,22 @@ def test_eqw_pop_plain_block_limits_and_errors(dev):
     empty = dev.DevicePopulation.from_synth(pop.subset(np.array([], dtype=int)), use_params=True)
     assert dev.eqw_pop(plain_h, dev.Cosmology(), empty, LINES).shape == (0, len(LINES))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("nebular", [False, True])
+def test_sed_rows_independent_of_the_population(dev, nebular):
+    """The unfused SED runs over the ordering sort's tiles and skips the
+    weight blocks that are zero for every member; a galaxy's row must not
+    depend on which galaxies share its tile."""
+    if nebular:
+        ssp = synth.make_ssp_nebular(n_u=7, n_wave=1000, wave_lo=1.0e3, wave_hi=2.0e4)
+    else:
+        ssp = synth.make_ssp(n_wave=1000, wave_lo=1.0e3, wave_hi=2.0e4)
+    ssp_h = dev.SspBlock.from_synth(ssp, precisions=("fp32",))
+    pop = synth.make_population(300, n_t=100, z_range=(0.1, 3.0), seed=125, nebular=nebular)
+    _say(f"sed rows alone and in a population nebular={nebular} n_gal=300")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    full = dev.sed(ssp_h, dev.Cosmology(), dp).cpu().numpy()
+    idx = np.array([0, 150, 299])
+    sub = dev.DevicePopulation.from_synth(pop.subset(idx), use_params=True)
+    np.testing.assert_array_equal(dev.sed(ssp_h, dev.Cosmology(), sub).cpu().numpy(), full[idx])

@@ -78,9 +78,10 @@ def effective_wavelengths(wave, z, obs_lo, obs_hi):
     return np.maximum(hi - lo, 0)
 
 
-def algorithmic_flops(P, ssp_h, dpop, ssp, flt, z):
+def algorithmic_flops(P, ssp_h, dpop, ssp, flt, z, per_galaxy=False):
     """2 * nnz(W_g) * n_lambda_eff(z_g) summed over galaxies: the multiply-adds
-    the contraction must do for the wavelengths any filter sees."""
+    the contraction must do for the wavelengths any filter sees (per galaxy
+    with per_galaxy)."""
     import torch
     nnz = torch.zeros(dpop.n_gal, dtype=torch.int64, device="cuda")
     step = 16384
@@ -94,6 +95,8 @@ def algorithmic_flops(P, ssp_h, dpop, ssp, flt, z):
         nnz[s:e] = (w.view(e - s, -1) != 0).sum(dim=1)
     nnz = nnz.cpu().numpy().astype(np.float64)
     neff = effective_wavelengths(ssp.wave, z, flt.wave[:, 0].min(), flt.wave[:, -1].max())
+    if per_galaxy:
+        return 2.0 * nnz * neff
     return float(np.sum(2.0 * nnz * neff)), float(nnz.mean()), float(neff.mean())
 
 
@@ -408,8 +411,19 @@ def run_nebular(P, steps, warmup, n_gal=100_000, seed=10, n_u=7):
         grads = fwd_grad()
     torch.cuda.synchronize()
     ms_grad = (time.perf_counter() - t0) * 1e3 / steps
+    # algorithmic work of the fused GEMM: 2 nnz(W_g) n_u,nz(g) n_lambda_eff(z_g),
+    # n_u,nz the ionization points inside the galaxy's +-3 sigma support
+    per_g = algorithmic_flops(P, ssp_h, dpar, ssp, flt, pop.z, per_galaxy=True)
+    edges = np.concatenate([[-np.inf], 0.5 * (ssp.lgu[1:] + ssp.lgu[:-1]), [np.inf]])
+    lo, hi = pop.lgu - 3.0 * pop.sigma_u, pop.lgu + 3.0 * pop.sigma_u
+    n_unz = ((edges[None, :-1] < hi[:, None]) & (edges[None, 1:] > lo[:, None])).sum(axis=1)
+    alg = float(np.sum(n_unz * per_g))
+    gemm_s = gemm_ms / steps * 1e-3
     res = {"mags": {"ms_per_step": ms, "galaxies_per_s": n_gal / (ms * 1e-3),
-                    "gemm_ms_per_step": gemm_ms / steps},
+                    "gemm_ms_per_step": gemm_ms / steps,
+                    "alg_flops_per_step": alg, "achieved_tflops": alg / gemm_s / 1e12,
+                    "mfma_frac_fp32": alg / gemm_s / 1e12 / PEAK_TFLOPS["fp32"],
+                    "mean_ion_points": float(n_unz.mean())},
            "sed_and_eqw": {"ms_per_step": ms_ew, "galaxies_per_s": n_gal / (ms_ew * 1e-3),
                            "eqw_ms_per_step": eqw_ms / steps, "n_lines": len(NEB_LINES)},
            "eqw_from_population": {"ms_per_step": ms_ew_pop,

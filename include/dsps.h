@@ -189,10 +189,10 @@ typedef struct { double om0, w0, h; } dsps_cosmo;
  *               (Section 3.4.1, Eq. agedep_dust_csp): A_V and delta of age
  *               tau are av + (av_old - av) T_erf((log10 tau - dust_pivot) /
  *               dust_width) (the old values where T_erf is 1), and likewise
- *               for delta; bump stays age-independent.  Only dsps_mags
- *               supports it (float32, on an SSP handle created with
- *               DSPS_SSP_AGE_MAJOR); dsps_sed and dsps_mags_vjp return
- *               DSPS_ERR_UNSUPPORTED.
+ *               for delta; bump stays age-independent.  dsps_mags,
+ *               dsps_sed (apply_dust) and dsps_eqw_pop support it (float32,
+ *               on an SSP handle created with DSPS_SSP_AGE_MAJOR, without an
+ *               ionization axis); dsps_mags_vjp returns DSPS_ERR_UNSUPPORTED.
  *   dust_pivot, dust_width  transition centre (log10 yr) and width (dex, > 0)
  *   lgu, sigma_u  [n_gal] centre log10 U_s and width (dex, > 0) of the
  *               triweight ionization distribution (Section 3.3, Eq. nebsed);

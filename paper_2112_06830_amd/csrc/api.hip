@@ -475,7 +475,9 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
     L.range = take(sizeof(GalaxyRange) * (size_t)n_gal);
     L.tobs = take(sizeof(double) * (size_t)n_gal);
     if (v.n_u > 1) L.ion = take(sizeof(GalaxyIon) * (size_t)n_gal);
-    L.w = take(elem * (size_t)L.batch * v.k_pad);
+    // a handle with the age-major table may run the age-dependent attenuation
+    L.w = take(elem * (size_t)L.batch * (v.sa32 ? std::max(v.k_pad, AGE_K) : v.k_pad));
+    if (v.sa32) L.dust_old = take(sizeof(GalaxyDustOld) * (size_t)n_gal);
     L.tiles = take(sizeof(TilePlan) * (size_t)((L.batch + TILE_G - 1) / TILE_G));
     L.total = off;
     return L;
@@ -671,9 +673,24 @@ int dsps_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *p
 // Unfused SED set-up for the sorted batch [s0, s0 + cnt): weights (W rows,
 // per-galaxy scalars, non-zero block masks, ionization supports) and the
 // tiles' stage lists.  The ordering sort has run.
+// Ages whose dust transition weight is exactly 0 (young: [0, young)) or 1
+// (old: [old, n_age)): the triweight's cumulative is 0 at or below -3 widths
+// and 1 at or above +3.
+static void age_groups(const dsps_ssp *ssp, const dsps_pop *pop, int &young, int &old) {
+  const std::vector<double> &ag = ssp->lg_age_host;
+  young = 0;
+  old = (int)ag.size();
+  for (int i = 0; i < (int)ag.size(); ++i) {
+    const double zt = (ag[i] - pop->dust_pivot) / pop->dust_width;
+    if (zt <= -3.0) young = i + 1;
+    if (zt >= 3.0 && old == (int)ag.size()) old = i;
+  }
+  old = std::max(old, young);
+}
+
 static int sed_batch_prepare(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *pop,
-                             int precision, const Layout &L, char *ws, int s0, int cnt,
-                             hipStream_t stream) {
+                             int precision, bool age_dust, const Layout &L, char *ws, int s0,
+                             int cnt, hipStream_t stream) {
   GalaxyIon *ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
   WeightsLaunch a = base_weights(ssp, cosmo, pop);
   a.perm = (const int *)(ws + L.perm);
@@ -687,8 +704,13 @@ static int sed_batch_prepare(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const
   a.obs_hi = std::numeric_limits<double>::infinity();
   a.ion = ion;
   a.t_obs = (double *)(ws + L.tobs);
+  if (age_dust) {
+    a.w_pad_age = 1;
+    a.dust_old = (GalaxyDustOld *)(ws + L.dust_old);
+  }
   DSPS_TRY(launch_weights(a, stream));
   MagsLaunch m{};
+  m.age_dust = age_dust;
   m.ssp = ssp->v;
   m.precision = precision;
   m.s_begin = s0;
@@ -700,9 +722,16 @@ static int sed_batch_prepare(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const
   return launch_tile_plan(m, stream);
 }
 
-static SedLaunch sed_launch(const dsps_ssp *ssp, const Layout &L, char *ws, int precision,
-                            int apply_dust, int s0, int cnt) {
+static SedLaunch sed_launch(const dsps_ssp *ssp, const dsps_pop *pop, const Layout &L, char *ws,
+                            int precision, int apply_dust, bool age_dust, int s0, int cnt) {
   SedLaunch s{};
+  if (age_dust) {
+    s.age_dust = 1;
+    s.dust_old = (const GalaxyDustOld *)(ws + L.dust_old);
+    age_groups(ssp, pop, s.age_young, s.age_old);
+    s.dust_pivot = pop->dust_pivot;
+    s.dust_width = pop->dust_width;
+  }
   s.ssp = ssp->v;
   s.precision = precision;
   s.apply_dust = apply_dust;
@@ -724,8 +753,11 @@ static int sed_common(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_p
   DSPS_TRY(check_cosmo(cosmo));
   DSPS_TRY(check_pop(pop, apply_dust != 0));
   DSPS_CHECK(apply_dust == 0 || apply_dust == 1, DSPS_ERR_ARG, "apply_dust must be 0 or 1");
-  DSPS_CHECK(!(apply_dust && pop->av_old), DSPS_ERR_UNSUPPORTED,
-             "dsps_sed does not apply the age-dependent attenuation (dsps_mags does)");
+  const bool age_dust = apply_dust && pop->av_old;
+  DSPS_CHECK(!age_dust || (precision == DSPS_FP32 && ssp->v.sa32 && ssp->v.n_u == 1 && !ion_tangent),
+             DSPS_ERR_UNSUPPORTED,
+             "the age-dependent attenuation needs float32 and an SSP handle created with "
+             "DSPS_SSP_AGE_MAJOR (and no ionization axis)");
   DSPS_TRY(check_precision(ssp, precision));
   DSPS_TRY(check_ion(ssp, pop));
   if (pop->n_gal == 0) return DSPS_OK;
@@ -737,8 +769,8 @@ static int sed_common(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_p
   DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), (int *)(ws + L.perm), stream));
   for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
     const int cnt = std::min(L.batch, pop->n_gal - s0);
-    DSPS_TRY(sed_batch_prepare(ssp, cosmo, pop, precision, L, ws, s0, cnt, stream));
-    SedLaunch s = sed_launch(ssp, L, ws, precision, apply_dust, s0, cnt);
+    DSPS_TRY(sed_batch_prepare(ssp, cosmo, pop, precision, age_dust, L, ws, s0, cnt, stream));
+    SedLaunch s = sed_launch(ssp, pop, L, ws, precision, apply_dust, age_dust, s0, cnt);
     s.ion_tangent = ion_tangent;
     s.sed = sed;
     DSPS_TRY(launch_sed_gemm(s, stream));
@@ -823,19 +855,9 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   m.ion = ion;
   m.ion_tangent = ion_tangent;
   if (age_dust) {
-    // ages whose transition weight is exactly 0 (young) or 1 (old): the
-    // triweight's cumulative is 0 at or below -3 widths and 1 at or above +3
-    const std::vector<double> &ag = ssp->lg_age_host;
-    int young = 0, old = (int)ag.size();
-    for (int i = 0; i < (int)ag.size(); ++i) {
-      const double zt = (ag[i] - pop->dust_pivot) / pop->dust_width;
-      if (zt <= -3.0) young = i + 1;
-      if (zt >= 3.0 && old == (int)ag.size()) old = i;
-    }
     m.age_dust = 1;
     m.dust_old = (const GalaxyDustOld *)(ws + L.dust_old);
-    m.age_young = young;
-    m.age_old = std::max(old, young);
+    age_groups(ssp, pop, m.age_young, m.age_old);
     m.dust_pivot = pop->dust_pivot;
     m.dust_width = pop->dust_width;
   }
@@ -1194,8 +1216,10 @@ int dsps_eqw_pop(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *p
   DSPS_CHECK(apply_dust == 0 || apply_dust == 1, DSPS_ERR_ARG, "apply_dust must be 0 or 1");
   DSPS_CHECK(wrt >= -1 && wrt <= 1, DSPS_ERR_ARG, "wrt must be -1 (none), 0 (lgu) or 1 (sigma_u)");
   DSPS_CHECK(wrt < 0 || ssp->v.n_u > 1, DSPS_ERR_UNSUPPORTED, "the SSP block has no ionization axis");
-  DSPS_CHECK(!(apply_dust && pop->av_old), DSPS_ERR_UNSUPPORTED,
-             "dsps_eqw_pop does not apply the age-dependent attenuation");
+  const bool age_dust = apply_dust && pop->av_old;
+  DSPS_CHECK(!age_dust || (ssp->v.sa32 && ssp->v.n_u == 1), DSPS_ERR_UNSUPPORTED,
+             "the age-dependent attenuation needs an SSP handle created with DSPS_SSP_AGE_MAJOR "
+             "(and no ionization axis)");
   DSPS_TRY(check_precision(ssp, DSPS_FP32));
   DSPS_TRY(check_ion(ssp, pop));
   EqwLaunch e{};
@@ -1213,8 +1237,8 @@ int dsps_eqw_pop(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *p
   DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), (int *)(ws + L.perm), stream));
   for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
     const int cnt = std::min(L.batch, pop->n_gal - s0);
-    DSPS_TRY(sed_batch_prepare(ssp, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, stream));
-    SedLaunch b = sed_launch(ssp, L, ws, DSPS_FP32, apply_dust, s0, cnt);
+    DSPS_TRY(sed_batch_prepare(ssp, cosmo, pop, DSPS_FP32, age_dust, L, ws, s0, cnt, stream));
+    SedLaunch b = sed_launch(ssp, pop, L, ws, DSPS_FP32, apply_dust, age_dust, s0, cnt);
     b.n_sel = s.n_sel;
     b.out_stride = s.out_stride;
     for (int x = 0; x < s.n_sel; ++x) b.chunk_list[x] = s.chunk_list[x];

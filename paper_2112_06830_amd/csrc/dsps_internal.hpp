@@ -455,6 +455,13 @@ struct SedLaunch {
   // with ion: 0 the SED, 1 its derivative in the ionization centre, 2 in the
   // ionization width (the weights of the points replaced by their derivatives)
   int ion_tangent;
+  // age-dependent attenuation (float32, apply_dust): W rows and the table
+  // are age-major and the attenuation is folded per age group, as in the
+  // fused kernel
+  int age_dust;
+  const GalaxyDustOld *dust_old;   // by sorted position
+  int age_young, age_old;
+  double dust_pivot, dust_width;
   // chunk selection (n_sel > 0): block x computes wavelength chunk
   // chunk_list[x] and writes it to columns x * TILE_L.. of row s - g_begin
   // (s the sorted position) of rows of out_stride floats (whole chunks,

@@ -232,6 +232,51 @@ __device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const typename Ge
   gemm_kloop_ab<PREC>(sm, st, k_pad, l0, w, k_pad, g0, g_count, nk, koff, wr, wc, lane, acc, after);
 }
 
+// Age-dependent attenuation (Section 3.4.1, Eq. agedep_dust_csp) over an
+// age-major K loop whose stage ks is age ks.  Ages [0, age_young) share the
+// young-star dust, ages [age_old, ...) the old-star dust, each age between
+// has its own transition value.  At the last stage of such a group every
+// wave folds the group's partial SED into sed += F_att(group) acc and
+// restarts acc; lc holds the tile's per-row (lambda, log2(lambda/5500), k0,
+// bump shape) constants.  Per column block nb: the young and old dust
+// exponents and slopes and the bump amplitude.
+struct AgeFold {
+  int nk, age_young, age_old;
+  double pivot, width;
+  const double *lg_age;
+  float da_y[2], dl_y[2], da_o[2], dl_o[2], bp[2];
+
+  __device__ __forceinline__ void operator()(int ks, f32x16 (&sed)[2][2], f32x16 (&acc)[2][2],
+                                             const float4 *lc, int wr, int h) const {
+    const bool young = ks < age_young, old = ks >= age_old;
+    const bool ends = ks == nk - 1 || (young ? ks + 1 == age_young : !old);
+    if (!ends) return;
+    // the group's transition weight: 0 young, 1 old, T_erf in between
+    const float t = young ? 0.0f
+                          : (old ? 1.0f : (float)mdf_transition(lg_age[ks], pivot, width));
+    float da[2], dl[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      da[nb] = t == 1.0f ? da_o[nb] : da_y[nb] + (da_o[nb] - da_y[nb]) * t;
+      dl[nb] = t == 1.0f ? dl_o[nb] : dl_y[nb] + (dl_o[nb] - dl_y[nb]) * t;
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const float4 c = lc[row];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const float k0x = __fmul_rn(c.z, __builtin_amdgcn_exp2f(dl[nb] * c.y));
+          const float kl = fmaf(bp[nb], c.w, k0x);
+          sed[mb][nb][r] = fmaf(__builtin_amdgcn_exp2f(da[nb] * kl), acc[mb][nb][r], sed[mb][nb][r]);
+          acc[mb][nb][r] = 0.0f;
+        }
+      }
+  }
+};
+
 // Bands whose support meets the observed wavelengths [o_lo, o_hi] (with a
 // relative margin far above float rounding): any band left out has zero
 // transmission for every element of the chunk, so skipping it is exact.

@@ -305,36 +305,14 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
         for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
           for (int r = 0; r < 16; ++r) sed[mb][nb][r] = 0.0f;
-      const int age_young = a.age_young, age_old = a.age_old;
-      auto fold = [&](int ks) {
-        const bool young = ks < age_young, old = ks >= age_old;
-        const bool ends = ks == nk - 1 || (young ? ks + 1 == age_young : !old);
-        if (!ends) return;
-        // the group's transition weight: 0 young, 1 old, T_erf in between
-        const float t = young ? 0.0f
-                              : (old ? 1.0f
-                                     : (float)mdf_transition(P.lg_age[ks], a.dust_pivot, a.dust_width));
-        float da[2], dl[2];
+      AgeFold af{nk, a.age_young, a.age_old, a.dust_pivot, a.dust_width, P.lg_age, {}, {}, {}, {}, {}};
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          da[nb] = t == 1.0f ? da_old[nb] : E.da[nb] + (da_old[nb] - E.da[nb]) * t;
-          dl[nb] = t == 1.0f ? dl_old[nb] : E.dl[nb] + (dl_old[nb] - E.dl[nb]) * t;
-        }
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int row = wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-            const float4 lc = s_lc[row];
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-              const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(dl[nb] * lc.y));
-              const float kl = fmaf(E.bp[nb], lc.w, k0x);
-              sed[mb][nb][r] = fmaf(__builtin_amdgcn_exp2f(da[nb] * kl), acc[mb][nb][r], sed[mb][nb][r]);
-              acc[mb][nb][r] = 0.0f;
-            }
-          }
-      };
+      for (int nb = 0; nb < 2; ++nb) {
+        af.da_y[nb] = E.da[nb]; af.dl_y[nb] = E.dl[nb];
+        af.da_o[nb] = da_old[nb]; af.dl_o[nb] = dl_old[nb];
+        af.bp[nb] = E.bp[nb];
+      }
+      auto fold = [&](int ks) { af(ks, sed, acc, s_lc, wr, h); };
       gemm_kloop<PREC>(sm, st, k_cols, l0, w, g0, a.s_count, nk, [&](int ks) { return s_koff[ks]; },
                        wr, wc, lane, acc, fold);
 #pragma unroll

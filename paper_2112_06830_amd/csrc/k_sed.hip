@@ -7,6 +7,10 @@
 // weights are replaced by their derivatives in the distribution's centre or
 // width, which gives the SED's derivative (the sum is linear in them).
 //
+// AGED (Section 3.4.1, Eq. agedep_dust_csp): the age-major table and weight
+// rows, one stage per age, and the attenuation folded per group of ages that
+// share dust parameters (AgeFold), so the output is already attenuated.
+//
 // Galaxies come in the ordering sort's order, so a tile's members share few
 // metallicity rows and ages: the K loop runs over the tile's stage list (the
 // weight blocks non-zero for some member), as in the fused kernel.  Skipped
@@ -16,11 +20,13 @@
 
 namespace dsps {
 
-template <int PREC, bool NEB = false>
+template <int PREC, bool NEB = false, bool AGED = false>
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   using C = GemmCfg<PREC>;
   using elem = typename C::elem;
-  static_assert(!NEB || PREC == DSPS_FP32, "the ionization axis is float32 only");
+  static_assert(!(NEB || AGED) || PREC == DSPS_FP32, "float32 only");
+  static_assert(!(NEB && AGED), "not both");
+  __shared__ float4 s_lc[AGED ? TILE_L : 1];
   __shared__ GemmSmem<PREC> sm[2];
   __shared__ float s_pn[NEB ? DSPS_MAX_ION * TILE_G : 1];
   __shared__ int s_koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];   // K offset of each stage
@@ -31,7 +37,8 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   const SspView P = a.ssp;
   const int l0 = chunk * TILE_L;
   const int g0 = tile * TILE_G;
-  const elem *st = PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16;
+  const elem *st = AGED ? (const elem *)P.sa32
+                        : (PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16);
   const elem *w = (const elem *)a.w_pad;
 
   f32x16 acc[2][2];
@@ -71,6 +78,36 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
                           return StageSrc{(u_lo + uu) * kp + k, k, s_pn + uu * TILE_G};
                         },
                         wr, wc, lane, acc);
+  } else if constexpr (AGED) {
+    if (threadIdx.x < TILE_L) s_lc[threadIdx.x] = P.lconst[l0 + threadIdx.x];
+    AgeFold af{nk, a.age_young, a.age_old, a.dust_pivot, a.dust_width, P.lg_age, {}, {}, {}, {}, {}};
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int col = wc * 64 + nb * 32 + (lane & 31);
+      float v[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      if (g0 + col < a.g_count) {
+        const int s = a.g_begin + g0 + col;
+        const GalaxyMeta m = a.meta[s];
+        const GalaxyDustOld d = a.dust_old[s];
+        v[0] = m.dust_a; v[1] = m.delta; v[2] = d.dust_a; v[3] = d.delta; v[4] = m.bump;
+      }
+      af.da_y[nb] = v[0]; af.dl_y[nb] = v[1]; af.da_o[nb] = v[2]; af.dl_o[nb] = v[3];
+      af.bp[nb] = v[4];
+    }
+    f32x16 sed[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sed[mb][nb][r] = 0.0f;
+    __syncthreads();
+    gemm_kloop<PREC>(sm, st, AGE_K, l0, w, g0, a.g_count, nk, [&](int ks) { return s_koff[ks]; },
+                     wr, wc, lane, acc, [&](int ks) { af(ks, sed, acc, s_lc, wr, h); });
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = sed[mb][nb];
   } else {
     __syncthreads();
     gemm_kloop<PREC>(sm, st, P.k_pad, l0, w, g0, a.g_count, nk, [&](int ks) { return s_koff[ks]; },
@@ -83,7 +120,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
     if (g0 + col >= a.g_count) continue;
     const int s = a.g_begin + g0 + col;     // sorted position
     float da = 0.0f, dl = 0.0f, bp = 0.0f;
-    if (a.apply_dust) {
+    if (a.apply_dust && !AGED) {   // AGED: the folds attenuated already
       const GalaxyMeta m = a.meta[s];
       da = m.dust_a; dl = m.delta; bp = m.bump;
     }
@@ -98,7 +135,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
         const int l = l0 + wr * 64 + mb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
         if (!a.n_sel && l >= P.n_wave) continue;
         float v = acc[mb][nb][r];
-        if (a.apply_dust) {
+        if (a.apply_dust && !AGED) {
           const float4 lc = P.lconst[l];
           v *= exp2f(da * (lc.z * exp2f(dl * lc.y) + bp * lc.w));
         }
@@ -112,7 +149,10 @@ int launch_sed_gemm(const SedLaunch &a, hipStream_t stream) {
   if (a.g_count <= 0) return DSPS_OK;
   const dim3 grid(a.n_sel ? a.n_sel : a.ssp.n_wave_pad / TILE_L, (a.g_count + TILE_G - 1) / TILE_G);
   ProfScope prof(DSPS_KERNEL_SED_GEMM, stream);
-  if (a.ion) {
+  if (a.age_dust) {
+    if (a.precision != DSPS_FP32 || !a.ssp.sa32 || a.ion || !a.apply_dust) return DSPS_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_sed_gemm<DSPS_FP32, false, true>), grid, dim3(GEMM_THREADS), 0, stream, a);
+  } else if (a.ion) {
     if (a.precision != DSPS_FP32 || !a.ssp.st32) return DSPS_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((k_sed_gemm<DSPS_FP32, true>), grid, dim3(GEMM_THREADS), 0, stream, a);
   } else if (a.precision == DSPS_BF16) {

@@ -1,8 +1,9 @@
 """GPU parity, through the C ABI, of the age-dependent attenuation (Section
-3.4.1, Eq. agedep_dust_csp): fused FP32 magnitudes against the FP64 oracle
-over several transition centres and widths, the limits where it must equal
-the age-independent path, batch independence, and the calls that do not
-support it."""
+3.4.1, Eq. agedep_dust_csp): fused FP32 magnitudes and the unfused SED
+against the FP64 oracle over several transition centres and widths, the
+limits where it must equal the age-independent path, batch independence,
+widths straight from the population, and the calls that do not support
+it."""
 
 import sys
 
@@ -108,7 +109,35 @@ def test_age_dust_unsupported_calls(dev, small):
     with pytest.raises(Exception, match="age-dependent"):
         dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, torch.zeros((16, 6), device="cuda"))
     with pytest.raises(Exception, match="age-dependent"):
-        dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=True)
+        dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=True, precision="bf16")
     plain = dev.SspBlock.from_synth(ssp, precisions=("fp32",))
     with pytest.raises(Exception, match="DSPS_SSP_AGE_MAJOR"):
         dev.mags(plain, flt_h, dev.Cosmology(), dp)
+    with pytest.raises(Exception, match="DSPS_SSP_AGE_MAJOR"):
+        dev.sed(plain, dev.Cosmology(), dp, apply_dust=True)
+
+
+@pytest.mark.parametrize("pivot,width", [(7.0, 0.25), (8.5, 0.1)])
+def test_age_dust_sed_matches_oracle(dev, small, pivot, width):
+    ssp_h, _, ssp = small
+    pop = _pop(100, seed=81, dust_pivot=pivot, dust_width=width)
+    inp = oracle_inputs(ssp, pop)
+    _say(f"age-dust sed n_gal=100 pivot={pivot} width={width}")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    got = dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=True).cpu().numpy()
+    ref = oracle.sed(inp, apply_dust=True)
+    assert (np.abs(got - ref) / ref).max() < 2e-5
+    # without dust the old-star parameters play no part
+    bare = dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=False).cpu().numpy()
+    assert (np.abs(bare - oracle.sed(inp)) / oracle.sed(inp)).max() < 2e-5
+
+
+def test_age_dust_widths_from_population_equal_sed_then_widths(dev, small):
+    ssp_h, _, ssp = small
+    pop = _pop(200, seed=83)
+    lines = ((4862.68, 40.0, 150.0), (5008.24, 40.0, 150.0), (6564.61, 50.0, 180.0))
+    _say("age-dust widths straight from the population n_gal=200")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    got = dev.eqw_pop(ssp_h, dev.Cosmology(), dp, lines).cpu().numpy()
+    ref = dev.eqw(ssp_h, dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=True), lines).cpu().numpy()
+    np.testing.assert_array_equal(got, ref)

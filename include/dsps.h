@@ -62,7 +62,7 @@ typedef enum {
   DSPS_ERR_SHAPE = -2,        /* sizes inconsistent or outside the limits    */
   DSPS_ERR_DEVICE = -3,       /* HIP runtime error                           */
   DSPS_ERR_WORKSPACE = -4,    /* workspace too small or misaligned           */
-  DSPS_ERR_UNSUPPORTED = -5,  /* valid request this build does not implement */
+  DSPS_ERR_UNSUPPORTED = -5,  /* valid request the library does not implement */
   DSPS_ERR_ALLOC = -6         /* device allocation failed in a create call   */
 } dsps_status;
 
@@ -81,7 +81,7 @@ typedef enum {
   DSPS_OP_WEIGHTS = 0, DSPS_OP_SED = 1, DSPS_OP_MAGS = 2, DSPS_OP_MAGS_VJP = 3
 } dsps_op;
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define DSPS_MAX_MET 16       /* metallicities in the SSP block             */
 #define DSPS_MAX_AGE 96       /* ages in the SSP block                      */
 #define DSPS_MAX_BAND 8       /* filters per filter set                     */

@@ -23,7 +23,7 @@ def _say(msg):
 
 def grad_close(got, ref, tol=GRAD_TOL):
     """Per-parameter metric: relative L2 error and elementwise error with a
-    floor of 1e-2 rms (gradients that nearly cancel are judged against the
+    floor of 1e-2 rms (gradients that nearly cancel are compared against the
     scale of their parameter, not against zero)."""
     got = np.asarray(got, dtype=np.float64).ravel()
     ref = np.asarray(ref, dtype=np.float64).ravel()

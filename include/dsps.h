@@ -319,9 +319,10 @@ int dsps_mags_ion_tangent(const dsps_ssp *ssp, const dsps_filters *filters,
  *                   pop->lgmet_old)
  *   lgu_bar, sigma_u_bar  [n_gal] float32, or NULL: gradients w.r.t. the
  *                   ionization centre and width (SSP handle with n_u > 1,
- *                   else DSPS_ERR_ARG); each costs one more fused pass with
- *                   the derivative weights (dsps_mags_ion_tangent), dotted
- *                   with mags_bar per galaxy
+ *                   else DSPS_ERR_ARG): the transposed contraction also
+ *                   returns each ionization point's cotangent
+ *                   sum_k W[k] (Lbar . L_u[k]), which the derivatives of the
+ *                   ionization weights carry to the centre and width
  * With an ionization axis (Section 3.3, Eq. nebsed) the transposed
  * contraction runs once per ionization point a tile's members reach, against
  * that point's block of the adjoint table, each galaxy's SED cotangent scaled

@@ -450,7 +450,7 @@ constexpr int BATCH_VJP = 65536;
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
   size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0, tobs = 0, dust_old = 0;
-  size_t ion = 0, dion = 0, ebuf = 0, dbuf = 0;
+  size_t ion = 0, wsuf = 0, ipart = 0, ebuf = 0, dbuf = 0;
   int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
@@ -510,10 +510,12 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
     // bands, moments and magnitudes of the forward pass when not supplied
     L.fbands = take(sizeof(float) * (size_t)n_gal * 6 * n_band);
     if (v.n_u > 1) {
-      // the members' ionization distributions, and the magnitudes'
-      // derivatives in the ionization centre and width
+      // the members' ionization distributions, the W rows' suffix sums over
+      // metallicity and the transposed contraction's per-block partials of
+      // the ionization cotangents
       L.ion = take(sizeof(GalaxyIon) * (size_t)n_gal);
-      L.dion = take(sizeof(float) * (size_t)n_gal * 2 * n_band);
+      L.wsuf = take(sizeof(float) * (size_t)L.batch * v.k_pad);
+      L.ipart = take(sizeof(float) * (size_t)(v.sk_rows / TILE_L) * L.batch * 2);
     }
   }
   L.total = off;
@@ -1014,6 +1016,10 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
       a.obs_lo = filters->obs_lo;
       a.obs_hi = filters->obs_hi;
       a.ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
+      if (ssp->v.n_u > 1) {   // the W rows for the ionization cotangents
+        a.w_pad = ws + L.w;
+        a.t_obs = (double *)(ws + L.tobs);
+      }
       DSPS_TRY(launch_weights(a, stream));
     } else {
       DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, fwd_mags, fwd_bands,
@@ -1059,24 +1065,16 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
     v.av_bar = av_bar;
     v.delta_bar = delta_bar;
     v.bump_bar = bump_bar;
-    v.ion = ssp->v.n_u > 1 ? (const GalaxyIon *)(ws + L.ion) : nullptr;
+    if (ssp->v.n_u > 1) {
+      v.ion = (const GalaxyIon *)(ws + L.ion);
+      v.w_rows = (const float *)(ws + L.w);
+      v.wsuf = (float *)(ws + L.wsuf);
+      v.ion_part = (float *)(ws + L.ipart);
+      v.lgu_bar = lgu_bar;
+      v.sigma_u_bar = sigma_u_bar;
+    }
     for (int stage = 0; stage < 4; ++stage) DSPS_TRY(launch_vjp(v, stage, stream));
-    // the ionization parameters: each galaxy's magnitudes depend only on its
-    // own distribution, so lgu_bar[g] = sum_b mags_bar[g, b] dm[g, b] / dlgu[g]
-    float *dion = (float *)(ws + L.dion);
-    if (lgu_bar)
-      DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, dion, nullptr,
-                          nullptr, stream, 1, use_bands));
-    if (sigma_u_bar)
-      DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt,
-                          dion + (size_t)pop->n_gal * n_band, nullptr, nullptr, stream, 2, use_bands));
   }
-  if (lgu_bar)
-    DSPS_TRY(launch_row_dot(mags_bar, (const float *)(ws + L.dion), pop->n_gal, n_band, lgu_bar,
-                            stream));
-  if (sigma_u_bar)
-    DSPS_TRY(launch_row_dot(mags_bar, (const float *)(ws + L.dion) + (size_t)pop->n_gal * n_band,
-                            pop->n_gal, n_band, sigma_u_bar, stream));
   return DSPS_OK;
 }
 

@@ -505,11 +505,13 @@ struct VjpLaunch {
   // ionization axis: the members' distributions by sorted position, or null;
   // then the adjoint table holds one K-major block per ionization point
   const GalaxyIon *ion;
+  const float *w_rows;        // [s_count][k_pad] float32 W rows (with ion)
+  float *wsuf;                // [s_count][k_pad] their suffix sums over metallicity
+  float *ion_part;            // [sk_rows / TILE_L][s_count][2] partial lgu_bar, sigma_u_bar
+  float *lgu_bar, *sigma_u_bar;   // by galaxy index, or null
 };
 int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream);
-// out[g] = sum_b x[g][b] y[g][b] for n rows of n_band values (float64 sums).
-int launch_row_dot(const float *x, const float *y, int n, int n_band, float *out,
-                   hipStream_t stream);
+
 
 // Defined in k_summary.hip.
 constexpr int SUMMARY_CHUNK = 2048;   // galaxies per partial-histogram workgroup

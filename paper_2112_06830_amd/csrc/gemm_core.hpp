@@ -107,6 +107,10 @@ struct StageSrc {
   int a, b;
   const float *bscale;
 };
+// The same without B factors.
+struct StageAB {
+  int a, b;
+};
 
 __device__ __forceinline__ float4 as_float4(u32x4 v) {
   return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
@@ -175,8 +179,8 @@ __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_BF16> &sm, int wr,
 // sm; on return every wave has passed a barrier after its last read of it.
 // after(ks) runs in every wave right after the MFMAs of stage ks (register
 // work on the accumulators only).  koff(s) returns the common K offset of
-// both operands (an int), or a StageSrc; with StageSrc, A rows are a_stride
-// and B rows b_stride elements apart.
+// both operands (an int), a StageAB (separate offsets) or a StageSrc (also
+// B factors); A rows are a_stride and B rows b_stride elements apart.
 struct NoStageHook {
   __device__ void operator()(int) const {}
 };
@@ -188,6 +192,7 @@ __device__ __forceinline__ void gemm_kloop_ab(GemmSmem<PREC> *sm,
                                               KOffset koff, int wr, int wc, int lane,
                                               f32x16 (&acc)[2][2], StageHook after = StageHook()) {
   constexpr bool SCALED = std::is_same_v<decltype(koff(0)), StageSrc>;
+  constexpr bool SPLIT = std::is_same_v<decltype(koff(0)), StageAB>;
   static_assert(!SCALED || PREC == DSPS_FP32, "per-row B factors are float32 only");
   StageRegs<PREC> regs;
   const float *pending = nullptr;   // B factors of the stage held in regs
@@ -196,6 +201,9 @@ __device__ __forceinline__ void gemm_kloop_ab(GemmSmem<PREC> *sm,
       const StageSrc src = koff(s);
       load_stage<PREC>(regs, st, a_stride, l0, w, b_stride, g0, g_count, src.a, src.b);
       pending = src.bscale;
+    } else if constexpr (SPLIT) {
+      const StageAB src = koff(s);
+      load_stage<PREC>(regs, st, a_stride, l0, w, b_stride, g0, g_count, src.a, src.b);
     } else {
       const int k = koff(s);
       load_stage<PREC>(regs, st, a_stride, l0, w, b_stride, g0, g_count, k, k);

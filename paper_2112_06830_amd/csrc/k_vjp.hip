@@ -130,8 +130,12 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
 // NEB (Section 3.3, Eq. nebsed): each galaxy contracts against its own table
 // sum_u P_neb[u] L_u, so the reduction over wavelength runs once per
 // ionization point the tile's members reach, against that point's block of
-// the adjoint table, with each member's Lbar row multiplied by its P_neb[u]
-// as it is staged.
+// the adjoint table.  At the end of each point's stages the partial result
+// X_u (differenced over metallicity) is folded into Wbar with the member's
+// P_neb[u], and dotted with the suffix sums of its W rows over metallicity:
+// sum_k W X_u = sum_k Wsuf Xdiff_u is the cotangent of P_neb[u], which the
+// derivatives of the weights turn into lgu_bar and sigma_u_bar partials
+// (rows above the MDF support have Wsuf = 0, so skipping them is exact).
 template <bool NEB>
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   using C = GemmCfg<DSPS_FP32>;
@@ -139,7 +143,9 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   __shared__ int s_tile[2];
   __shared__ int s_jhi;          // highest metallicity row in some member's MDF support
   __shared__ int s_urange[2];    // NEB: the members' ionization points
-  __shared__ float s_pn[NEB ? DSPS_MAX_ION * TILE_G : 1];
+  // NEB: per point and column the weight, its derivatives in centre and width
+  __shared__ float s_pn[NEB ? 3 * DSPS_MAX_ION * TILE_G : 1];
+  __shared__ float s_ured[NEB ? 2 * TILE_G : 1];
   const int kblk = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
@@ -191,24 +197,99 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   const int nk = (l_end > l_begin && k0 / AGE_PAD <= j_hi) ? (l_end - l_begin) / C::KT : 0;
   if constexpr (NEB) {
     const int u_lo = s_urange[0], n_uu = s_urange[1] - s_urange[0] + 1;
-    for (int t = threadIdx.x; t < n_uu * TILE_G; t += blockDim.x) {
+    const int plane = n_uu * TILE_G;
+    for (int t = threadIdx.x; t < plane; t += blockDim.x) {
       const int uu = t / TILE_G, col = t - uu * TILE_G;
-      float f = 0.0f;
+      float f = 0.0f, fu = 0.0f, fs = 0.0f;
       if (col < nvalid) {
         const GalaxyIon gi = a.ion[a.s_begin + g0 + col];
-        f = (float)ion_weight(P.ion_edges, u_lo + uu, gi.lgu, gi.sigma_u);
+        const int u = u_lo + uu;
+        f = (float)ion_weight(P.ion_edges, u, gi.lgu, gi.sigma_u);
+        fu = (float)ion_weight_d<1>(P.ion_edges, u, gi.lgu, gi.sigma_u);
+        fs = (float)ion_weight_d<2>(P.ion_edges, u, gi.lgu, gi.sigma_u);
       }
       s_pn[t] = f;
+      s_pn[plane + t] = fu;
+      s_pn[2 * plane + t] = fs;
     }
     __syncthreads();
+    f32x16 tot[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tot[mb][nb][r] = 0.0f;
+    float ub[2] = {0.0f, 0.0f}, sb[2] = {0.0f, 0.0f};
+    const int kp = P.k_pad;
+    auto fold = [&](int s) {
+      if ((s + 1) % nk != 0) return;   // the point's last stage
+      const int uu = s / nk;
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int col = wc * 64 + nb * 32 + (lane & 31);
+        const bool live = col < nvalid;
+        const float p = s_pn[uu * TILE_G + col];
+        const float *ws = a.wsuf + (size_t)(g0 + (live ? col : 0)) * kp + k0;
+        float dot = 0.0f;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) {
+            const int row0 = wr * 64 + mb * 32 + 8 * r4 + 4 * h;
+            float4 wv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (live && k0 + row0 < kp) wv = *reinterpret_cast<const float4 *>(ws + row0);
+            const float wq[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float x = acc[mb][nb][4 * r4 + q];
+              tot[mb][nb][4 * r4 + q] = fmaf(p, x, tot[mb][nb][4 * r4 + q]);
+              dot = fmaf(wq[q], x, dot);
+              acc[mb][nb][4 * r4 + q] = 0.0f;
+            }
+          }
+        ub[nb] = fmaf(s_pn[plane + uu * TILE_G + col], dot, ub[nb]);
+        sb[nb] = fmaf(s_pn[2 * plane + uu * TILE_G + col], dot, sb[nb]);
+      }
+    };
     const int slab = P.sk_rows * nwp;   // one point's block of the adjoint table
     gemm_kloop_ab<DSPS_FP32>(sm, P.sk32, nwp, k0, a.lbar, nwp, g0, a.s_count, nk * n_uu,
                              [&](int s) {
-                               const int uu = nk > 0 ? s / nk : 0;
+                               const int uu = s / nk;
                                const int l = l_begin + (s - uu * nk) * C::KT;
-                               return StageSrc{(u_lo + uu) * slab + l, l, s_pn + uu * TILE_G};
+                               return StageAB{(u_lo + uu) * slab + l, l};
                              },
-                             wr, wc, lane, acc);
+                             wr, wc, lane, acc, fold);
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = tot[mb][nb];
+    // partials over this block's rows: lane halves, then the two row waves
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      ub[nb] += __shfl_xor(ub[nb], 32, 64);
+      sb[nb] += __shfl_xor(sb[nb], 32, 64);
+    }
+    if (wr == 1 && h == 0) {
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int col = wc * 64 + nb * 32 + (lane & 31);
+        s_ured[2 * col] = ub[nb];
+        s_ured[2 * col + 1] = sb[nb];
+      }
+    }
+    __syncthreads();
+    if (wr == 0 && h == 0) {
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int col = wc * 64 + nb * 32 + (lane & 31);
+        if (col < nvalid) {
+          float *out = a.ion_part + ((size_t)kblk * a.s_count + g0 + col) * 2;
+          out[0] = ub[nb] + s_ured[2 * col];
+          out[1] = sb[nb] + s_ured[2 * col + 1];
+        }
+      }
+    }
   } else {
     gemm_kloop<DSPS_FP32>(sm, P.sk32, nwp, k0, a.lbar, g0, a.s_count, nk,
                           [=](int ks) { return l_begin + ks * C::KT; }, wr, wc, lane, acc);
@@ -464,23 +545,33 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
     if (a.av_bar) a.av_bar[g] = (float)(c1 * sk);
     if (a.delta_bar) a.delta_bar[g] = (float)(c1 * av * LN2_D * spw);
     if (a.bump_bar) a.bump_bar[g] = (float)(c1 * av * sd);
+    if (a.ion && (a.lgu_bar || a.sigma_u_bar)) {
+      // the wbar blocks' partials, summed in block order
+      double su = 0.0, ss = 0.0;
+      for (int kb = 0; kb < P.sk_rows / TILE_L; ++kb) {
+        su += a.ion_part[((size_t)kb * a.s_count + local) * 2];
+        ss += a.ion_part[((size_t)kb * a.s_count + local) * 2 + 1];
+      }
+      if (a.lgu_bar) a.lgu_bar[g] = (float)su;
+      if (a.sigma_u_bar) a.sigma_u_bar[g] = (float)ss;
+    }
   }
 }
 
-__global__ void k_row_dot(const float *__restrict__ x, const float *__restrict__ y, int n,
-                          int n_band, float *__restrict__ out) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  double s = 0.0;
-  for (int b = 0; b < n_band; ++b) s += (double)x[(size_t)g * n_band + b] * (double)y[(size_t)g * n_band + b];
-  out[g] = (float)s;
-}
-
-int launch_row_dot(const float *x, const float *y, int n, int n_band, float *out,
-                   hipStream_t stream) {
-  if (n <= 0) return DSPS_OK;
-  hipLaunchKernelGGL(k_row_dot, dim3((n + 255) / 256), dim3(256), 0, stream, x, y, n, n_band, out);
-  return hip_fail(hipGetLastError(), "k_row_dot launch");
+// Suffix sums of the float32 W rows over metallicity:
+// wsuf[s][j * 96 + i] = sum_{j' >= j} W[s][j' * 96 + i].
+__global__ void k_wsuf(const float *__restrict__ w, int n_rows, int n_met, int k_pad,
+                       float *__restrict__ wsuf) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_rows * AGE_PAD) return;
+  const int r = idx / AGE_PAD, i = idx - r * AGE_PAD;
+  const float *wr = w + (size_t)r * k_pad + i;
+  float *out = wsuf + (size_t)r * k_pad + i;
+  float acc = 0.0f;
+  for (int j = n_met - 1; j >= 0; --j) {
+    acc += wr[j * AGE_PAD];
+    out[j * AGE_PAD] = acc;
+  }
 }
 
 int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
@@ -494,6 +585,10 @@ int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
     hipLaunchKernelGGL(k_vjp_lbar, dim3(a.n_groups, tiles), dim3(256), lds, stream, a);
   } else if (stage == 2) {
     ProfScope prof(DSPS_KERNEL_VJP_WBAR, stream);
+    if (a.ion) {
+      hipLaunchKernelGGL(k_wsuf, dim3((a.s_count * AGE_PAD + 255) / 256), dim3(256), 0, stream,
+                         a.w_rows, a.s_count, a.ssp.n_met, a.ssp.k_pad, a.wsuf);
+    }
     if (a.ion)
       hipLaunchKernelGGL(k_vjp_wbar<true>, dim3(a.ssp.sk_rows / TILE_L, tiles), dim3(GEMM_THREADS), 0,
                          stream, a);

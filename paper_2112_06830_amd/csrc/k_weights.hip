@@ -527,8 +527,15 @@ int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
   // the weights kernel runs when weight rows are asked for, padded or in the
   // natural layout (the windows' block masks then narrow from "all" to the
   // exact union)
-  if (!a.w_pad && !a.w_user) return a.mstar ? DSPS_ERR_ARG : DSPS_OK;
-  if (!a.t_obs || (a.w_pad && a.w_user)) return DSPS_ERR_ARG;
+  if (!a.w_pad && !a.w_user) {
+    if (!a.mstar) return DSPS_OK;
+    set_error("internal: the mass formed needs the weight rows");
+    return DSPS_ERR_ARG;
+  }
+  if (!a.t_obs || (a.w_pad && a.w_user)) {
+    set_error("internal: weight rows need the cosmic-time workspace and one output layout");
+    return DSPS_ERR_ARG;
+  }
   const int blocks = (a.s_count + WEIGHT_WAVES - 1) / WEIGHT_WAVES;
   const size_t lds = sizeof(double) * weights_lds_doubles(a.n_t, a.ssp.n_age, a.ssp.n_met,
                                                           a.ssp.k_pad);

@@ -190,10 +190,13 @@ def _grad_close(got, ref, tol=1e-3):
 
 def test_nebular_vjp_matches_oracle_adjoint(dev, large):
     """Every cotangent against the oracle adjoint.  The ionization ones are
-    sum_b mbar_b dm_b / du per galaxy; the derivative weights sum to zero, so
-    dm_b cancels and its float32 error is bounded as in the magnitude-tangent
-    test, |d(dm_b)| <= 1.09 x 2e-5 (dnum_abs_b + |dnum_b|) / num_b, hence
-    |d ubar| <= sum_b |mbar_b| times that."""
+    sum_u dP_u/du Pbar_u with Pbar_u = sum_l Lbar(l) S_u(l) (S_u the SED of
+    point u, Lbar = q F sum_b gamma_b T_b, gamma_b = -2.5/ln10 mbar_b/num_b).
+    A float32 error of 2e-5 relative to the terms' absolute sum gives
+    |d Pbar_u| <= 2e-5 sum_b |gamma_b| num_b,u, and summing |dP_u/du| over u,
+    |d ubar| <= 2e-5 sum_b |gamma_b| dnum_abs_b; the tolerance below (with an
+    extra |dnum_b| term) is at least that.  The derivative weights sum to
+    zero, so ubar itself cancels and is not a usable scale."""
     import torch
     ssp_h, flt_h, ssp = large
     pop = _pop(64, seed=117, z_range=(0.1, 3.0))
@@ -454,3 +457,21 @@ def test_sed_rows_independent_of_the_population(dev, nebular):
     idx = np.array([0, 150, 299])
     sub = dev.DevicePopulation.from_synth(pop.subset(idx), use_params=True)
     np.testing.assert_array_equal(dev.sed(ssp_h, dev.Cosmology(), sub).cpu().numpy(), full[idx])
+
+
+def test_nebular_vjp_with_forward_sums_equals_internal_forward(dev, small):
+    """dsps_mags_vjp given the forward band sums and moments (the path that
+    computes only the scalars and W rows) returns the same cotangents, bit
+    for bit, as when it runs the forward pass itself."""
+    import torch
+    ssp_h, flt_h, ssp = small
+    pop = _pop(150, seed=127)
+    _say("nebular vjp with given forward sums n_gal=150")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m, bands, mom = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_moments=True)
+    bar = 2.0 * (m - torch.tensor(pop.targets, dtype=torch.float32, device="cuda"))
+    g1 = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar)
+    g2 = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bands, moments=mom)
+    assert set(g1) == set(g2) and {"lgu", "sigma_u"} <= set(g1)
+    for k in g1:
+        np.testing.assert_array_equal(g1[k].cpu().numpy(), g2[k].cpu().numpy(), err_msg=k)

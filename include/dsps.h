@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define DSPS_ABI_VERSION 6
+#define DSPS_ABI_VERSION 7
 
 typedef enum {
   DSPS_OK = 0,
@@ -192,7 +192,7 @@ typedef struct { double om0, w0, h; } dsps_cosmo;
  *               for delta; bump stays age-independent.  dsps_mags,
  *               dsps_sed (apply_dust) and dsps_eqw_pop support it (float32,
  *               on an SSP handle created with DSPS_SSP_AGE_MAJOR, without an
- *               ionization axis); dsps_mags_vjp returns DSPS_ERR_UNSUPPORTED.
+ *               ionization axis), and so does dsps_mags_vjp (av_old_bar, delta_old_bar).
  *   dust_pivot, dust_width  transition centre (log10 yr) and width (dex, > 0)
  *   lgu, sigma_u  [n_gal] centre log10 U_s and width (dex, > 0) of the
  *               triweight ionization distribution (Section 3.3, Eq. nebsed);
@@ -323,6 +323,16 @@ int dsps_mags_ion_tangent(const dsps_ssp *ssp, const dsps_filters *filters,
  *                   returns each ionization point's cotangent
  *                   sum_k W[k] (Lbar . L_u[k]), which the derivatives of the
  *                   ionization weights carry to the centre and width
+ *   av_old_bar, delta_old_bar  [n_gal] float32, or NULL: gradients w.r.t. the
+ *                   old-star attenuation (requires pop->av_old, else
+ *                   DSPS_ERR_ARG)
+ * With the age-dependent attenuation (Section 3.4.1, Eq. agedep_dust_csp;
+ * float32, an SSP handle created with DSPS_SSP_AGE_MAJOR, no ionization
+ * axis) every age has its own F_i: the SED cotangent is taken without the
+ * attenuation and the transposed contraction applies F_i per age,
+ * Wbar[j, i] = sum_l G F_i L[j, i]; the dust cotangents collect per age
+ * (split between the young and old parameters by 1 - T_erf and T_erf), so
+ * there are no moments: pass moments = NULL (bands may still be given).
  * With an ionization axis (Section 3.3, Eq. nebsed) the transposed
  * contraction runs once per ionization point a tile's members reach, against
  * that point's block of the adjoint table, each galaxy's SED cotangent scaled
@@ -336,8 +346,8 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
                   const float *bands, const float *moments, double *sfr_bar,
                   double *sfh_params_bar, float *lgmet_bar, float *lgmet_old_bar,
                   float *sigma_bar, float *av_bar, float *delta_bar, float *bump_bar,
-                  float *lgu_bar, float *sigma_u_bar, void *workspace, size_t workspace_bytes,
-                  hipStream_t stream);
+                  float *av_old_bar, float *delta_old_bar, float *lgu_bar, float *sigma_u_bar,
+                  void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Emission-line equivalent widths of rest-frame SEDs (Section 2.2.2, Eq. eqw).

@@ -99,7 +99,7 @@ def _declare(lib):
         "dsps_sed": (I, [P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, I, P, P, S, P]),
         "dsps_mags": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P, P, S, P]),
         "dsps_mags_vjp": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P,
-                              P, P, P, P, P, P, P, P, P, P, P, S, P]),
+                              P, P, P, P, P, P, P, P, P, P, P, P, P, S, P]),
         "dsps_quantize_bf16": (I, [P, I, I, P, P, P]),
         "dsps_pop_summary_workspace": (I, [I, I, ctypes.POINTER(S)]),
         "dsps_pop_summary": (I, [P, I, I, I, I, D, D, I, P, I, D, P, P, S, P]),

@@ -422,19 +422,24 @@ def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePo
              mags_bar: torch.Tensor, bands: torch.Tensor | None = None,
              moments: torch.Tensor | None = None,
              want=("sfr", "sfh_params", "lgmet", "lgmet_old", "sigma_z", "av", "delta", "bump",
-                   "lgu", "sigma_u"),
+                   "av_old", "delta_old", "lgu", "sigma_u"),
              workspace: Workspace | None = None, outs: dict | None = None, stream=None) -> dict:
     """dsps_mags_vjp: cotangents of the population inputs for a magnitude
     cotangent mags_bar [n_gal, n_band] (float32 path).  bands and moments come
     from mags(..., with_moments=True) on the same inputs, or are both None
-    (the forward pass then runs inside).  `outs` may supply preallocated
-    output tensors (then `want` is ignored)."""
+    (the forward pass then runs inside).  With the age-dependent attenuation
+    there are no moments: bands alone (from mags) or nothing.  `outs` may
+    supply preallocated output tensors (then `want` is ignored)."""
     n, d = pop.n_gal, pop.device
-    if (bands is None) != (moments is None):
+    aged = pop.av_old is not None
+    if aged and moments is not None:
+        raise ValueError("the age-dependent attenuation takes no moments")
+    if not aged and (bands is None) != (moments is None):
         raise ValueError("bands and moments are given together or not at all")
     mags_bar = mags_bar.to(device=d, dtype=torch.float32).contiguous()
     if bands is not None:
         bands = bands.to(device=d, dtype=torch.float32).contiguous()
+    if moments is not None:
         moments = moments.to(device=d, dtype=torch.float32).contiguous()
     out = {}
     if outs is not None:
@@ -449,6 +454,9 @@ def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePo
             out[k] = torch.empty(n, dtype=torch.float32, device=d)
     if "lgmet_old" in want and pop.lgmet_old is not None:
         out["lgmet_old"] = torch.empty(n, dtype=torch.float32, device=d)
+    for k in ("av_old", "delta_old"):
+        if k in want and aged:
+            out[k] = torch.empty(n, dtype=torch.float32, device=d)
     for k in ("lgu", "sigma_u"):
         if k in want and getattr(ssp, "n_u", 1) > 1:
             out[k] = torch.empty(n, dtype=torch.float32, device=d)
@@ -459,7 +467,8 @@ def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePo
                               _ptr(mags_bar), _ptr(bands), _ptr(moments), _ptr(out.get("sfr")),
                               _ptr(out.get("sfh_params")), _ptr(out.get("lgmet")),
                               _ptr(out.get("lgmet_old")), _ptr(out.get("sigma_z")), _ptr(out.get("av")), _ptr(out.get("delta")),
-                              _ptr(out.get("bump")), _ptr(out.get("lgu")), _ptr(out.get("sigma_u")),
+                              _ptr(out.get("bump")), _ptr(out.get("av_old")),
+                              _ptr(out.get("delta_old")), _ptr(out.get("lgu")), _ptr(out.get("sigma_u")),
                               workspace.ptr(), workspace.nbytes, _stream(stream))
     N.check(rc, "dsps_mags_vjp")
     return out

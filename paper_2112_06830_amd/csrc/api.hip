@@ -450,7 +450,7 @@ constexpr int BATCH_VJP = 65536;
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
   size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0, tobs = 0, dust_old = 0;
-  size_t ion = 0, wsuf = 0, ipart = 0, ebuf = 0, dbuf = 0;
+  size_t ion = 0, wsuf = 0, ipart = 0, apart = 0, ebuf = 0, dbuf = 0;
   int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
@@ -490,9 +490,10 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   L.tobs = take(sizeof(double) * (size_t)n_gal);
   // a handle with the age-major table may run the age-dependent attenuation,
   // whose weight rows are AGE_K wide
-  const int w_cols = (v.sa32 && op == DSPS_OP_MAGS) ? std::max(v.k_pad, AGE_K) : v.k_pad;
+  const bool aged_ok = v.sa32 && (op == DSPS_OP_MAGS || op == DSPS_OP_MAGS_VJP);
+  const int w_cols = aged_ok ? std::max(v.k_pad, AGE_K) : v.k_pad;
   L.w = take(elem * (size_t)L.batch * w_cols);
-  if (v.sa32 && op == DSPS_OP_MAGS) L.dust_old = take(sizeof(GalaxyDustOld) * (size_t)n_gal);
+  if (aged_ok) L.dust_old = take(sizeof(GalaxyDustOld) * (size_t)n_gal);
   if (v.n_u > 1 && op == DSPS_OP_MAGS) {
     L.ion = take(sizeof(GalaxyIon) * (size_t)n_gal);
     // the forward magnitudes and band sums an ionization tangent may need
@@ -517,6 +518,8 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
       L.wsuf = take(sizeof(float) * (size_t)L.batch * v.k_pad);
       L.ipart = take(sizeof(float) * (size_t)(v.sk_rows / TILE_L) * L.batch * 2);
     }
+    // the age-dependent attenuation's per-age dust partials
+    if (v.sa32) L.apart = take(sizeof(float) * (size_t)v.n_age * L.batch * 3);
   }
   L.total = off;
   return L;
@@ -968,22 +971,31 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
                   const dsps_pop *pop, int precision, const float *mags_bar, const float *bands,
                   const float *moments, double *sfr_bar, double *sfh_params_bar, float *lgmet_bar,
                   float *lgmet_old_bar, float *sigma_bar, float *av_bar, float *delta_bar,
-                  float *bump_bar, float *lgu_bar, float *sigma_u_bar, void *workspace,
-                  size_t workspace_bytes, hipStream_t stream) {
+                  float *bump_bar, float *av_old_bar, float *delta_old_bar, float *lgu_bar,
+                  float *sigma_u_bar, void *workspace, size_t workspace_bytes,
+                  hipStream_t stream) {
   DSPS_CHECK(ssp && filters, DSPS_ERR_ARG, "ssp or filters is NULL");
   DSPS_TRY(check_cosmo(cosmo));
   DSPS_TRY(check_pop(pop, true));
   DSPS_TRY(check_precision(ssp, precision));
   DSPS_CHECK(precision == DSPS_FP32, DSPS_ERR_UNSUPPORTED, "the adjoint runs in float32 only");
-  DSPS_CHECK(!pop->av_old, DSPS_ERR_UNSUPPORTED,
-             "the adjoint of the age-dependent attenuation is not available");
+  const bool age_dust = pop->av_old != nullptr;
+  DSPS_CHECK(!age_dust || (ssp->v.sa32 && ssp->v.n_u == 1), DSPS_ERR_UNSUPPORTED,
+             "the age-dependent attenuation needs an SSP handle created with DSPS_SSP_AGE_MAJOR "
+             "(and no ionization axis)");
+  DSPS_CHECK(age_dust || (!av_old_bar && !delta_old_bar), DSPS_ERR_ARG,
+             "av_old_bar and delta_old_bar require the population to carry av_old");
   DSPS_TRY(check_ion(ssp, pop));
   DSPS_CHECK(ssp->v.n_u > 1 || (!lgu_bar && !sigma_u_bar), DSPS_ERR_ARG,
              "lgu_bar and sigma_u_bar need an SSP block with an ionization axis");
   if (pop->n_gal == 0) return DSPS_OK;
   DSPS_CHECK(mags_bar, DSPS_ERR_ARG, "mags_bar is NULL");
-  DSPS_CHECK((bands == nullptr) == (moments == nullptr), DSPS_ERR_ARG,
-             "bands and moments must be given together or both be NULL");
+  if (age_dust)
+    DSPS_CHECK(!moments, DSPS_ERR_ARG,
+               "the age-dependent attenuation has no dust moments: pass moments = NULL");
+  else
+    DSPS_CHECK((bands == nullptr) == (moments == nullptr), DSPS_ERR_ARG,
+               "bands and moments must be given together or both be NULL");
   DSPS_CHECK(!sfh_params_bar || pop->sfh_params, DSPS_ERR_ARG,
              "sfh_params_bar requires the population to carry sfh_params");
   DSPS_CHECK(!lgmet_old_bar || pop->lgmet_old, DSPS_ERR_ARG,
@@ -1016,14 +1028,18 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
       a.obs_lo = filters->obs_lo;
       a.obs_hi = filters->obs_hi;
       a.ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
-      if (ssp->v.n_u > 1) {   // the W rows for the ionization cotangents
+      if (ssp->v.n_u > 1 || age_dust) {   // the W rows for the ionization or dust cotangents
         a.w_pad = ws + L.w;
         a.t_obs = (double *)(ws + L.tobs);
+      }
+      if (age_dust) {
+        a.w_pad_age = 1;
+        a.dust_old = (GalaxyDustOld *)(ws + L.dust_old);
       }
       DSPS_TRY(launch_weights(a, stream));
     } else {
       DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, fwd_mags, fwd_bands,
-                          fwd_mom, stream));
+                          age_dust ? nullptr : fwd_mom, stream));
     }
     VjpLaunch v{};
     v.ssp = ssp->v;
@@ -1035,7 +1051,7 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
     v.perm = perm;
     v.mags_bar = mags_bar;
     v.bands = use_bands;
-    v.moments = use_mom;
+    v.moments = age_dust ? nullptr : use_mom;
     v.gamma = (float *)(ws + L.gamma);
     v.meta = (const GalaxyMeta *)(ws + L.meta);
     v.range = (const GalaxyRange *)(ws + L.range);
@@ -1072,6 +1088,18 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
       v.ion_part = (float *)(ws + L.ipart);
       v.lgu_bar = lgu_bar;
       v.sigma_u_bar = sigma_u_bar;
+    }
+    if (age_dust) {
+      v.aged = 1;
+      v.dust_old = (const GalaxyDustOld *)(ws + L.dust_old);
+      age_groups(ssp, pop, v.age_young, v.age_old);
+      v.dust_pivot = pop->dust_pivot;
+      v.dust_width = pop->dust_width;
+      v.av_old = pop->av_old;
+      v.w_rows = (const float *)(ws + L.w);
+      v.aged_part = (float *)(ws + L.apart);
+      v.av_old_bar = av_old_bar;
+      v.delta_old_bar = delta_old_bar;
     }
     for (int stage = 0; stage < 4; ++stage) DSPS_TRY(launch_vjp(v, stage, stream));
   }

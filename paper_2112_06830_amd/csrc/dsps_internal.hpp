@@ -509,6 +509,16 @@ struct VjpLaunch {
   float *wsuf;                // [s_count][k_pad] their suffix sums over metallicity
   float *ion_part;            // [sk_rows / TILE_L][s_count][2] partial lgu_bar, sigma_u_bar
   float *lgu_bar, *sigma_u_bar;   // by galaxy index, or null
+  // age-dependent attenuation: Lbar is written without the attenuation and
+  // the transposed contraction applies each age's own; w_rows then holds the
+  // age-major float32 rows [s_count][AGE_K]
+  int aged;
+  const GalaxyDustOld *dust_old;   // by sorted position
+  int age_young, age_old;          // ages below take the young, from age_old the old parameters
+  double dust_pivot, dust_width;
+  const float *av_old;             // by galaxy index
+  float *aged_part;                // [n_age][s_count][3] per-age dust partials
+  float *av_old_bar, *delta_old_bar;   // by galaxy index, or null
 };
 int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream);
 

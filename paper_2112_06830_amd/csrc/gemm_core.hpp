@@ -15,6 +15,7 @@
 namespace dsps {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // Native 16-byte vector for staging (HIP's uint4 is a struct wrapper that the
 // optimiser does not always keep in registers).

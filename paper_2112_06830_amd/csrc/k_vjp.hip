@@ -30,7 +30,9 @@ __global__ void k_vjp_gamma(VjpLaunch a) {
   const int s = a.s_begin + local;
   const int g = a.perm[s];
   const int nb = a.n_band;
-  const float *mom = a.moments + (size_t)g * 3 * nb;
+  // no moments under the age-dependent attenuation: its dust cotangents come
+  // from the transposed contraction
+  const float *mom = a.moments ? a.moments + (size_t)g * 3 * nb : nullptr;
   double dust[3] = {0.0, 0.0, 0.0};
   for (int b = 0; b < nb; ++b) {
     const float num = a.bands[(size_t)g * 2 * nb + b];
@@ -38,7 +40,7 @@ __global__ void k_vjp_gamma(VjpLaunch a) {
     // a zero cotangent contributes nothing, also for a band with num = 0
     const float gam = bar == 0.0f ? 0.0f : -2.5f * bar / (LN10_F * num);
     a.gamma[(size_t)s * nb + b] = gam;
-    if (gam != 0.0f)
+    if (gam != 0.0f && a.moments)
       for (int k = 0; k < 3; ++k) dust[k] += (double)gam * (double)mom[k * nb + b];
   }
   for (int k = 0; k < 3; ++k) a.dust[(size_t)local * 3 + k] = (float)dust[k];
@@ -111,8 +113,11 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
         const float2 gr = s_grid[b];
         gs += s_gam[col * DSPS_MAX_BAND + b] * filter_table_at(s_tr + b * filter_stride(F.n_pts), n_int, fmaf(lobs, gr.y, -gr.x * gr.y));
       }
-      const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(m.z * lc.y));
-      const float att = __builtin_amdgcn_exp2f(m.y * fmaf(m.w, lc.w, k0x));
+      float att = 1.0f;   // each age's own attenuation is applied later when aged
+      if (!a.aged) {
+        const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(m.z * lc.y));
+        att = __builtin_amdgcn_exp2f(m.y * fmaf(m.w, lc.w, k0x));
+      }
       a.lbar[(size_t)(g0 + col) * nwp + l] = (gs * q) * att;
     }
   }
@@ -311,6 +316,158 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
             make_float4(acc[mb][nb][4 * r4], acc[mb][nb][4 * r4 + 1], acc[mb][nb][4 * r4 + 2],
                         acc[mb][nb][4 * r4 + 3]);
       }
+  }
+}
+
+// Age-dependent attenuation (Section 3.4.1, Eq. agedep_dust_csp): age i has
+// its own F_i, so with G the cotangent of the attenuated SED (Lbar without
+// the attenuation)
+//   Wbar[j, i] = sum_l G(l) F_i(l) L_SSP[j, i, l],
+// and the dust cotangents collect per age: with A_i = sum_j W[j, i] L[j, i]
+// and the per-wavelength factors of d ln F_i (k_i for the amplitude,
+// k0 (l/5500)^delta_i log2(l/5500) for the slope, D for the bump),
+//   R_x[i] = sum_l G F_i A_i factor_x = sum_j Wsuf[j, i] sum_l G F_i factor_x Ldiff[j, i, l],
+// where Ldiff is the metallicity-differenced table and Wsuf the suffix sums of
+// W over metallicity.  So one pass over the differenced table gives both:
+// four contractions (G F, G F k, G F k0x log2(l/5500), G F D) share its rows.
+//
+// Block (age i, tile): the four waves take 32 members each; M = the 16
+// metallicity slots of age i, N = 16 members, K = wavelength, on the
+// 16x16x4 float32 MFMA.  Lane (g, c) feeds A[c][g] and B[g][c] and holds
+// D rows 4 g + r of column c.  Within a 32-wavelength chunk, lane group g
+// takes wavelengths 8 g .. 8 g + 7, one per MFMA step: any split of the
+// wavelengths over (step, k) is the same sum as long as A and B agree.
+// Outputs: Wbar rows (metallicity-differenced, as the pull-back reads them)
+// and R[i][member][x].
+__global__ __launch_bounds__(256) void k_vjp_wbar_aged(VjpLaunch a) {
+  const int i = blockIdx.x, tile = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane >> 4, c = lane & 15;
+  const SspView P = a.ssp;
+  const int nwp = P.n_wave_pad, n_met = P.n_met;
+  const int g0 = tile * TILE_G + wave * 32;   // the wave's first member (batch position)
+  const int nvalid = min(32, a.s_count - g0);
+  if (nvalid <= 0) return;                    // whole waves leave together
+  // age i's transition weight as the forward pass takes it
+  const float t = i < a.age_young
+                      ? 0.0f
+                      : (i >= a.age_old ? 1.0f
+                                        : (float)mdf_transition(P.lg_age[i], a.dust_pivot, a.dust_width));
+  float da[2], dl[2], bp[2];
+  bool live[2];
+  int lo = 1 << 30, hi = 0;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int col = nb * 16 + c;
+    live[nb] = col < nvalid;
+    da[nb] = dl[nb] = bp[nb] = 0.0f;
+    if (live[nb]) {
+      const int s = a.s_begin + g0 + col;
+      const GalaxyMeta m = a.meta[s];
+      const GalaxyDustOld d = a.dust_old[s];
+      da[nb] = t == 1.0f ? d.dust_a : m.dust_a + (d.dust_a - m.dust_a) * t;
+      dl[nb] = t == 1.0f ? d.delta : m.delta + (d.delta - m.delta) * t;
+      bp[nb] = m.bump;
+      const GalaxyRange r = a.range[s];
+      lo = min(lo, r.win_lo);
+      hi = max(hi, r.win_hi);
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    lo = min(lo, __shfl_xor(lo, off, 64));
+    hi = max(hi, __shfl_xor(hi, off, 64));
+  }
+  // the window in 32-wavelength chunks (inside the Lbar window, which is
+  // written in TILE_L chunks)
+  const int l_begin = hi > lo ? (lo / 32) * 32 : 0;
+  const int l_end = hi > lo ? min(nwp, (hi + 31) / 32 * 32) : 0;
+
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int x = 0; x < 4; ++x) acc[nb][x] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  const bool arow_live = c < n_met;
+  const float *arow = P.sk32 + (size_t)(arow_live ? c * AGE_PAD + i : 0) * nwp;
+  const float *grow[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) grow[nb] = a.lbar + (size_t)(g0 + (live[nb] ? nb * 16 + c : 0)) * nwp;
+
+  for (int l0 = l_begin; l0 < l_end; l0 += 32) {
+    const int lb = l0 + 8 * grp;
+    float4 a0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), a1 = a0;
+    if (arow_live) {
+      a0 = *reinterpret_cast<const float4 *>(arow + lb);
+      a1 = *reinterpret_cast<const float4 *>(arow + lb + 4);
+    }
+    const float av8[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+    float4 g4[2][2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      g4[nb][0] = g4[nb][1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (live[nb]) {
+        g4[nb][0] = *reinterpret_cast<const float4 *>(grow[nb] + lb);
+        g4[nb][1] = *reinterpret_cast<const float4 *>(grow[nb] + lb + 4);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const float4 lc = P.lconst[lb + kk];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const float4 gq = g4[nb][kk >> 2];
+        const float gv = (kk & 3) == 0 ? gq.x : (kk & 3) == 1 ? gq.y : (kk & 3) == 2 ? gq.z : gq.w;
+        const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(dl[nb] * lc.y));
+        const float kl = fmaf(bp[nb], lc.w, k0x);
+        const float b = gv * __builtin_amdgcn_exp2f(da[nb] * kl);
+        acc[nb][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[kk], b, acc[nb][0], 0, 0, 0);
+        acc[nb][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[kk], b * kl, acc[nb][1], 0, 0, 0);
+        acc[nb][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[kk], b * (k0x * lc.y), acc[nb][2], 0, 0, 0);
+        acc[nb][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[kk], b * lc.w, acc[nb][3], 0, 0, 0);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int col = nb * 16 + c;
+    const int local = g0 + (live[nb] ? col : 0);
+    // suffix sums over metallicity of the member's weights at age i, for the
+    // lane's rows 4 grp .. 4 grp + 3
+    float4 w[4];
+    const float *wr = a.w_rows + (size_t)local * AGE_K + i * AGE_MET_SLOTS;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      w[q] = live[nb] ? reinterpret_cast<const float4 *>(wr)[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float tot[4] = {w[0].x + w[0].y + w[0].z + w[0].w, w[1].x + w[1].y + w[1].z + w[1].w,
+                          w[2].x + w[2].y + w[2].z + w[2].w, w[3].x + w[3].y + w[3].z + w[3].w};
+    const float above = (grp < 1 ? tot[1] : 0.0f) + (grp < 2 ? tot[2] : 0.0f) + (grp < 3 ? tot[3] : 0.0f);
+    const float4 own = grp == 0 ? w[0] : grp == 1 ? w[1] : grp == 2 ? w[2] : w[3];
+    float suf[4];
+    suf[3] = above + own.w;
+    suf[2] = suf[3] + own.z;
+    suf[1] = suf[2] + own.y;
+    suf[0] = suf[1] + own.x;
+    float part[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 4 * grp + r;
+      if (live[nb] && j < n_met) a.wbar[(size_t)local * P.k_pad + j * AGE_PAD + i] = acc[nb][0][r];
+#pragma unroll
+      for (int x = 0; x < 3; ++x) part[x] = fmaf(suf[r], acc[nb][1 + x][r], part[x]);
+    }
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      part[x] += __shfl_xor(part[x], 16, 64);
+      part[x] += __shfl_xor(part[x], 32, 64);
+    }
+    if (live[nb] && grp == 0) {
+      float *out = a.aged_part + ((size_t)i * a.s_count + local) * 3;
+      out[0] = part[0];
+      out[1] = part[1];
+      out[2] = part[2];
+    }
   }
 }
 
@@ -532,6 +689,31 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
     }
   }
 
+  // age-dependent attenuation: the per-age partials R_x[i] of the transposed
+  // contraction, with d ln F_i / d(A_V,i, delta_i, bump) = c (k_i,
+  // A_V,i k0x_i ln(l/5500), A_V,i D) and A_V,i, delta_i blended by 1 - T_i, T_i
+  double aged[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // av, av_old, delta, delta_old, bump
+  if (a.aged) {
+    const double c1 = -0.4 * LN10_D / DUST_RV;
+    const double av = (double)a.av[g], av_old = (double)a.av_old[g];
+    for (int i = lane; i < n_age; i += 64) {
+      const double t = i < a.age_young ? 0.0
+                                       : (i >= a.age_old ? 1.0
+                                                         : (double)(float)mdf_transition(P.lg_age[i], a.dust_pivot, a.dust_width));
+      const float *p = a.aged_part + ((size_t)i * a.s_count + local) * 3;
+      const double av_i = av + (av_old - av) * t;
+      const double rk = c1 * (double)p[0];
+      const double rd = c1 * av_i * LN2_D * (double)p[1];
+      aged[0] += (1.0 - t) * rk;
+      aged[1] += t * rk;
+      aged[2] += (1.0 - t) * rd;
+      aged[3] += t * rd;
+      aged[4] += c1 * av_i * (double)p[2];
+    }
+#pragma unroll
+    for (int x = 0; x < 5; ++x) aged[x] = wave_sum(aged[x]);
+  }
+
   if (lane == 0) {
     if (a.lgmet_bar) a.lgmet_bar[g] = (float)d_lgmet;
     if (a.lgmet_old_bar) a.lgmet_old_bar[g] = (float)d_old;
@@ -542,9 +724,17 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
     // k0 (l/5500)^delta ln(l/5500);  dF/d bump = F (-0.4 ln10 A_V / 4.05) D
     const double c1 = -0.4 * LN10_D / DUST_RV;
     const double av = (double)a.av[g];
-    if (a.av_bar) a.av_bar[g] = (float)(c1 * sk);
-    if (a.delta_bar) a.delta_bar[g] = (float)(c1 * av * LN2_D * spw);
-    if (a.bump_bar) a.bump_bar[g] = (float)(c1 * av * sd);
+    if (a.aged) {
+      if (a.av_bar) a.av_bar[g] = (float)aged[0];
+      if (a.av_old_bar) a.av_old_bar[g] = (float)aged[1];
+      if (a.delta_bar) a.delta_bar[g] = (float)aged[2];
+      if (a.delta_old_bar) a.delta_old_bar[g] = (float)aged[3];
+      if (a.bump_bar) a.bump_bar[g] = (float)aged[4];
+    } else {
+      if (a.av_bar) a.av_bar[g] = (float)(c1 * sk);
+      if (a.delta_bar) a.delta_bar[g] = (float)(c1 * av * LN2_D * spw);
+      if (a.bump_bar) a.bump_bar[g] = (float)(c1 * av * sd);
+    }
     if (a.ion && (a.lgu_bar || a.sigma_u_bar)) {
       // the wbar blocks' partials, summed in block order
       double su = 0.0, ss = 0.0;
@@ -589,7 +779,9 @@ int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
       hipLaunchKernelGGL(k_wsuf, dim3((a.s_count * AGE_PAD + 255) / 256), dim3(256), 0, stream,
                          a.w_rows, a.s_count, a.ssp.n_met, a.ssp.k_pad, a.wsuf);
     }
-    if (a.ion)
+    if (a.aged)
+      hipLaunchKernelGGL(k_vjp_wbar_aged, dim3(a.ssp.n_age, tiles), dim3(256), 0, stream, a);
+    else if (a.ion)
       hipLaunchKernelGGL(k_vjp_wbar<true>, dim3(a.ssp.sk_rows / TILE_L, tiles), dim3(GEMM_THREADS), 0,
                          stream, a);
     else

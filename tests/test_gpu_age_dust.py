@@ -2,8 +2,8 @@
 3.4.1, Eq. agedep_dust_csp): fused FP32 magnitudes and the unfused SED
 against the FP64 oracle over several transition centres and widths, the
 limits where it must equal the age-independent path, batch independence,
-widths straight from the population, and the calls that do not support
-it."""
+widths straight from the population, the adjoint (every cotangent, the
+old-star ones included) and the calls that do not support it."""
 
 import sys
 
@@ -107,14 +107,14 @@ def test_age_dust_unsupported_calls(dev, small):
     with pytest.raises(Exception, match="age-dependent"):
         dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, precision="bf16")
     with pytest.raises(Exception, match="age-dependent"):
-        dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, torch.zeros((16, 6), device="cuda"))
-    with pytest.raises(Exception, match="age-dependent"):
         dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=True, precision="bf16")
     plain = dev.SspBlock.from_synth(ssp, precisions=("fp32",))
     with pytest.raises(Exception, match="DSPS_SSP_AGE_MAJOR"):
         dev.mags(plain, flt_h, dev.Cosmology(), dp)
     with pytest.raises(Exception, match="DSPS_SSP_AGE_MAJOR"):
         dev.sed(plain, dev.Cosmology(), dp, apply_dust=True)
+    with pytest.raises(Exception, match="DSPS_SSP_AGE_MAJOR"):
+        dev.mags_vjp(plain, flt_h, dev.Cosmology(), dp, torch.zeros((16, 6), device="cuda"))
 
 
 @pytest.mark.parametrize("pivot,width", [(7.0, 0.25), (8.5, 0.1)])
@@ -141,3 +141,106 @@ def test_age_dust_widths_from_population_equal_sed_then_widths(dev, small):
     got = dev.eqw_pop(ssp_h, dev.Cosmology(), dp, lines).cpu().numpy()
     ref = dev.eqw(ssp_h, dev.sed(ssp_h, dev.Cosmology(), dp, apply_dust=True), lines).cpu().numpy()
     np.testing.assert_array_equal(got, ref)
+
+
+GRAD_TOL = 1e-3   # relative, per parameter (as for the age-independent adjoint)
+
+
+def grad_close(got, ref, tol=GRAD_TOL):
+    """Relative L2 error and elementwise error with a floor of 1e-2 rms."""
+    got = np.asarray(got, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    rms = np.sqrt(np.mean(ref**2))
+    l2 = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+    elem = np.abs(got - ref) <= tol * np.maximum(np.abs(ref), 1e-2 * rms)
+    return l2 <= tol and bool(elem.all()), (l2, float(np.mean(~elem)))
+
+
+AGED_KEYS = {"lgmet": "lgmet_bar", "sigma_z": "sigma_bar", "av": "av_bar", "delta": "delta_bar",
+             "bump": "bump_bar", "av_old": "av_old_bar", "delta_old": "delta_old_bar"}
+
+
+@pytest.mark.parametrize("pivot,width", [(7.0, 0.25), (8.5, 0.1)])
+def test_age_dust_vjp_matches_oracle(dev, large, pivot, width):
+    """The adjoint with per-age attenuation (Section 3.4.1): every cotangent,
+    the old-star ones included, against the FP64 oracle's reverse sweep on
+    the gradient check set's shape (48 galaxies, z ~ U[0.1, 3])."""
+    import torch
+    ssp_h, flt_h, ssp = large
+    pop = _pop(48, seed=81, z_range=(0.1, 3.0), dust_pivot=pivot, dust_width=width)
+    inp = oracle_inputs(ssp, pop)
+    _say(f"age-dust vjp n_gal=48 pivot={pivot} width={width}")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    bar = 2.0 * (oracle.mags(inp) - pop.targets)
+    g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, torch.tensor(bar, dtype=torch.float32))
+    ref = oracle.mags_vjp(inp, bar)
+    for k, rk in AGED_KEYS.items():
+        ok, info = grad_close(g[k].cpu().numpy(), ref[rk])
+        assert ok, (k, info)
+    for j in range(5):
+        ok, info = grad_close(g["sfh_params"].cpu().numpy()[j], ref["sfh_params_bar"][j])
+        assert ok, (j, info)
+    ok, info = grad_close(g["sfr"].cpu().numpy(), ref["sfr_bar"])
+    assert ok, ("sfr", info)
+
+
+def test_age_dust_vjp_given_bands_equals_internal_forward(dev, large):
+    """Band sums from the forward call give the same cotangents, bit for bit,
+    as the forward pass run inside the adjoint; a galaxy's cotangents do not
+    depend on the rest of the population (two batch sizes)."""
+    import torch
+    ssp_h, flt_h, ssp = large
+    pop = _pop(200, seed=83, z_range=(0.1, 3.0))
+    _say("age-dust vjp given bands n_gal=200")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m, bands = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)
+    bar = torch.tensor(2.0 * (m.cpu().numpy() - pop.targets), dtype=torch.float32)
+    g_in = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar)
+    g_bd = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bands)
+    for k in list(AGED_KEYS) + ["sfh_params", "sfr"]:
+        assert torch.equal(g_in[k], g_bd[k]), k
+    sub = pop.subset([7])
+    g_one = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dev.DevicePopulation.from_synth(sub, use_params=True),
+                         bar[7:8])
+    for k in AGED_KEYS:
+        assert torch.equal(g_one[k][0], g_in[k][7]), k
+
+
+def test_age_dust_vjp_equal_young_and_old_match_age_independent(dev, large):
+    """With av_old = av and delta_old = delta the model is the age-independent
+    one: the young and old cotangents add up to the age-independent
+    adjoint's, and the other cotangents agree."""
+    import torch
+    ssp_h, flt_h, ssp = large
+    pop = _pop(96, seed=85, z_range=(0.1, 3.0))
+    pop.av_old, pop.delta_old = pop.av.copy(), pop.delta.copy()
+    _say("age-dust vjp equal young/old n_gal=96")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp)
+    bar = torch.tensor(2.0 * (m.cpu().numpy() - pop.targets), dtype=torch.float32)
+    g_age = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar)
+    dp.av_old = dp.delta_old = None
+    g_flat = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar)
+    pairs = {"av": g_age["av"] + g_age["av_old"], "delta": g_age["delta"] + g_age["delta_old"]}
+    for k in ("lgmet", "sigma_z", "bump", "sfh_params"):
+        pairs[k] = g_age[k]
+    for k, v in pairs.items():
+        ok, info = grad_close(v.cpu().numpy(), g_flat[k].cpu().numpy())
+        assert ok, (k, info)
+
+
+def test_age_dust_vjp_argument_checks(dev, small):
+    """Host-side checks (no kernel runs): moments are refused under the
+    age-dependent attenuation, and the old-star cotangents need av_old."""
+    import torch
+    ssp_h, flt_h, ssp = small
+    pop = _pop(16, seed=87)
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    bar = torch.zeros((16, 6), device="cuda")
+    with pytest.raises(ValueError, match="no moments"):
+        dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bar.repeat(1, 2),
+                     moments=bar.repeat(1, 3))
+    dp.av_old = dp.delta_old = None
+    with pytest.raises(Exception, match="av_old"):
+        dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar,
+                     outs={"av_old": torch.empty(16, device="cuda")})

@@ -325,6 +325,37 @@ def run_age_dust(P, steps, warmup, n_gal=100_000, seed=9, pivot=7.0, width=0.25)
     res = {"ms_per_step": ms, "galaxies_per_s": n_gal / (ms * 1e-3),
            "gemm_ms_per_step": gemm_ms / steps, "weights_ms_per_step": w_ms / steps,
            "finite": bool(torch.isfinite(m).all().item())}
+    # forward + adjoint of the squared error to target magnitudes, the
+    # old-star cotangents included
+    targets = torch.tensor(pop.targets, dtype=torch.float32, device="cuda")
+    ws_v = P.Workspace(P.workspace_size(3, ssp_h, flt_h, n_gal, 100, "fp32"), dpop.device)
+
+    def fwd_grad():
+        mm, bands = P.mags(ssp_h, flt_h, P.Cosmology(), dpar, with_bands=True, workspace=ws)
+        return P.mags_vjp(ssp_h, flt_h, P.Cosmology(), dpar, 2.0 * (mm - targets), bands=bands,
+                          workspace=ws_v)
+    for _ in range(warmup):
+        fwd_grad()
+    torch.cuda.synchronize()
+    P.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        grads = fwd_grad()
+    torch.cuda.synchronize()
+    ms_grad = (time.perf_counter() - t0) * 1e3 / steps
+    wbar_ms, _ = P.profile_read("vjp_wbar")
+    P.profile_enable(False)
+    # the per-age transposed contraction: four contractions (G F and its three
+    # dust factors) of n_met rows per age over the wavelengths any filter sees
+    neff = effective_wavelengths(ssp.wave, pop.z, flt.wave[:, 0].min(), flt.wave[:, -1].max())
+    alg = 8.0 * ssp.lum.shape[0] * ssp.lum.shape[1] * float(np.sum(neff))
+    wbar_s = wbar_ms / steps * 1e-3
+    res["mags_and_gradient"] = {
+        "ms_per_step": ms_grad, "galaxies_per_s": n_gal / (ms_grad * 1e-3),
+        "wbar_ms_per_step": wbar_ms / steps, "wbar_alg_flops": alg,
+        "wbar_achieved_tflops": alg / wbar_s / 1e12,
+        "wbar_mfma_frac_fp32": alg / wbar_s / 1e12 / PEAK_TFLOPS["fp32"],
+        "finite": bool(all(torch.isfinite(v).all().item() for v in grads.values()))}
     return res, (ssp, flt, pop.subset(np.arange(128)), m[:128].cpu().numpy())
 
 

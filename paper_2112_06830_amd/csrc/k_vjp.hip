@@ -331,16 +331,25 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
 // W over metallicity.  So one pass over the differenced table gives both:
 // four contractions (G F, G F k, G F k0x log2(l/5500), G F D) share its rows.
 //
-// Block (age i, tile): the four waves take 32 members each; M = the 16
-// metallicity slots of age i, N = 16 members, K = wavelength, on the
-// 16x16x4 float32 MFMA.  Lane (g, c) feeds A[c][g] and B[g][c] and holds
-// D rows 4 g + r of column c.  Within a 32-wavelength chunk, lane group g
-// takes wavelengths 8 g .. 8 g + 7, one per MFMA step: any split of the
-// wavelengths over (step, k) is the same sum as long as A and B agree.
-// Outputs: Wbar rows (metallicity-differenced, as the pull-back reads them)
-// and R[i][member][x].
-__global__ __launch_bounds__(256) void k_vjp_wbar_aged(VjpLaunch a) {
-  const int i = blockIdx.x, tile = blockIdx.y;
+// Block (age unit, tile): a unit is up to AGED_UNIT consecutive ages that
+// share their attenuation (all young or all old), or one age of the
+// transition, so the factors G F_i are formed once per unit.  The four waves
+// take 32 members each; M = the 16 metallicity slots of an age, N = 16
+// members, K = wavelength, on the 16x16x4 float32 MFMA.  Lane (g, c) feeds
+// A[c][g] and B[g][c] and holds D rows 4 g + r of column c.  Within a
+// 32-wavelength chunk, lane group g takes wavelengths 8 g .. 8 g + 7, one per
+// MFMA step: any split of the wavelengths over (step, k) is the same sum as
+// long as A and B agree.  Outputs: Wbar rows (metallicity-differenced, as the
+// pull-back reads them) and R[i][member][x].
+constexpr int AGED_UNIT = 2;
+
+__host__ __device__ inline int aged_units(int n_age, int young, int old) {
+  return (young + AGED_UNIT - 1) / AGED_UNIT + (old - young) +
+         (n_age - old + AGED_UNIT - 1) / AGED_UNIT;
+}
+
+__global__ __launch_bounds__(256, 4) void k_vjp_wbar_aged(VjpLaunch a) {
+  const int unit = blockIdx.x, tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane >> 4, c = lane & 15;
   const SspView P = a.ssp;
@@ -348,11 +357,25 @@ __global__ __launch_bounds__(256) void k_vjp_wbar_aged(VjpLaunch a) {
   const int g0 = tile * TILE_G + wave * 32;   // the wave's first member (batch position)
   const int nvalid = min(32, a.s_count - g0);
   if (nvalid <= 0) return;                    // whole waves leave together
-  // age i's transition weight as the forward pass takes it
-  const float t = i < a.age_young
-                      ? 0.0f
-                      : (i >= a.age_old ? 1.0f
-                                        : (float)mdf_transition(P.lg_age[i], a.dust_pivot, a.dust_width));
+  // the unit's ages [i0, i0 + n_ages) and their shared transition weight,
+  // taken as the forward pass takes it
+  const int young = a.age_young, old = a.age_old;
+  const int n_young = (young + AGED_UNIT - 1) / AGED_UNIT;
+  int i0, n_ages;
+  float t;
+  if (unit < n_young) {
+    i0 = unit * AGED_UNIT;
+    n_ages = min(AGED_UNIT, young - i0);
+    t = 0.0f;
+  } else if (unit < n_young + (old - young)) {
+    i0 = young + (unit - n_young);
+    n_ages = 1;
+    t = (float)mdf_transition(P.lg_age[i0], a.dust_pivot, a.dust_width);
+  } else {
+    i0 = old + (unit - n_young - (old - young)) * AGED_UNIT;
+    n_ages = min(AGED_UNIT, P.n_age - i0);
+    t = 1.0f;
+  }
   float da[2], dl[2], bp[2];
   bool live[2];
   int lo = 1 << 30, hi = 0;
@@ -383,25 +406,33 @@ __global__ __launch_bounds__(256) void k_vjp_wbar_aged(VjpLaunch a) {
   const int l_begin = hi > lo ? (lo / 32) * 32 : 0;
   const int l_end = hi > lo ? min(nwp, (hi + 31) / 32 * 32) : 0;
 
-  f32x4 acc[2][4];
+  f32x4 acc[AGED_UNIT][2][4];
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb)
+  for (int u = 0; u < AGED_UNIT; ++u)
 #pragma unroll
-    for (int x = 0; x < 4; ++x) acc[nb][x] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) acc[u][nb][x] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   const bool arow_live = c < n_met;
-  const float *arow = P.sk32 + (size_t)(arow_live ? c * AGE_PAD + i : 0) * nwp;
+  // the differenced table's row (met c, age i0 + u) sits u rows after age i0's
+  const float *arow = P.sk32 + (size_t)(arow_live ? c * AGE_PAD + i0 : 0) * nwp;
   const float *grow[2];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) grow[nb] = a.lbar + (size_t)(g0 + (live[nb] ? nb * 16 + c : 0)) * nwp;
 
   for (int l0 = l_begin; l0 < l_end; l0 += 32) {
     const int lb = l0 + 8 * grp;
-    float4 a0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), a1 = a0;
-    if (arow_live) {
-      a0 = *reinterpret_cast<const float4 *>(arow + lb);
-      a1 = *reinterpret_cast<const float4 *>(arow + lb + 4);
+    float av8[AGED_UNIT][8];
+#pragma unroll
+    for (int u = 0; u < AGED_UNIT; ++u) {
+      float4 a0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), a1 = a0;
+      if (arow_live && u < n_ages) {
+        a0 = *reinterpret_cast<const float4 *>(arow + (size_t)u * nwp + lb);
+        a1 = *reinterpret_cast<const float4 *>(arow + (size_t)u * nwp + lb + 4);
+      }
+      av8[u][0] = a0.x; av8[u][1] = a0.y; av8[u][2] = a0.z; av8[u][3] = a0.w;
+      av8[u][4] = a1.x; av8[u][5] = a1.y; av8[u][6] = a1.z; av8[u][7] = a1.w;
     }
-    const float av8[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
     float4 g4[2][2];
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
@@ -421,52 +452,62 @@ __global__ __launch_bounds__(256) void k_vjp_wbar_aged(VjpLaunch a) {
         const float k0x = __fmul_rn(lc.z, __builtin_amdgcn_exp2f(dl[nb] * lc.y));
         const float kl = fmaf(bp[nb], lc.w, k0x);
         const float b = gv * __builtin_amdgcn_exp2f(da[nb] * kl);
-        acc[nb][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[kk], b, acc[nb][0], 0, 0, 0);
-        acc[nb][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[kk], b * kl, acc[nb][1], 0, 0, 0);
-        acc[nb][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[kk], b * (k0x * lc.y), acc[nb][2], 0, 0, 0);
-        acc[nb][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[kk], b * lc.w, acc[nb][3], 0, 0, 0);
+        const float bk = b * kl, bd = b * (k0x * lc.y), bb = b * lc.w;
+#pragma unroll
+        for (int u = 0; u < AGED_UNIT; ++u) {
+          if (u >= n_ages) break;   // uniform across the block
+          acc[u][nb][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[u][kk], b, acc[u][nb][0], 0, 0, 0);
+          acc[u][nb][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[u][kk], bk, acc[u][nb][1], 0, 0, 0);
+          acc[u][nb][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[u][kk], bd, acc[u][nb][2], 0, 0, 0);
+          acc[u][nb][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av8[u][kk], bb, acc[u][nb][3], 0, 0, 0);
+        }
       }
     }
   }
 
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    const int col = nb * 16 + c;
-    const int local = g0 + (live[nb] ? col : 0);
-    // suffix sums over metallicity of the member's weights at age i, for the
-    // lane's rows 4 grp .. 4 grp + 3
-    float4 w[4];
-    const float *wr = a.w_rows + (size_t)local * AGE_K + i * AGE_MET_SLOTS;
+  for (int u = 0; u < AGED_UNIT; ++u) {
+    if (u >= n_ages) break;
+    const int i = i0 + u;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      w[q] = live[nb] ? reinterpret_cast<const float4 *>(wr)[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    const float tot[4] = {w[0].x + w[0].y + w[0].z + w[0].w, w[1].x + w[1].y + w[1].z + w[1].w,
-                          w[2].x + w[2].y + w[2].z + w[2].w, w[3].x + w[3].y + w[3].z + w[3].w};
-    const float above = (grp < 1 ? tot[1] : 0.0f) + (grp < 2 ? tot[2] : 0.0f) + (grp < 3 ? tot[3] : 0.0f);
-    const float4 own = grp == 0 ? w[0] : grp == 1 ? w[1] : grp == 2 ? w[2] : w[3];
-    float suf[4];
-    suf[3] = above + own.w;
-    suf[2] = suf[3] + own.z;
-    suf[1] = suf[2] + own.y;
-    suf[0] = suf[1] + own.x;
-    float part[3] = {0.0f, 0.0f, 0.0f};
+    for (int nb = 0; nb < 2; ++nb) {
+      const int col = nb * 16 + c;
+      const int local = g0 + (live[nb] ? col : 0);
+      // suffix sums over metallicity of the member's weights at age i, for
+      // the lane's rows 4 grp .. 4 grp + 3
+      float4 w[4];
+      const float *wr = a.w_rows + (size_t)local * AGE_K + i * AGE_MET_SLOTS;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int j = 4 * grp + r;
-      if (live[nb] && j < n_met) a.wbar[(size_t)local * P.k_pad + j * AGE_PAD + i] = acc[nb][0][r];
+      for (int q = 0; q < 4; ++q)
+        w[q] = live[nb] ? reinterpret_cast<const float4 *>(wr)[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      const float tot[4] = {w[0].x + w[0].y + w[0].z + w[0].w, w[1].x + w[1].y + w[1].z + w[1].w,
+                            w[2].x + w[2].y + w[2].z + w[2].w, w[3].x + w[3].y + w[3].z + w[3].w};
+      const float above = (grp < 1 ? tot[1] : 0.0f) + (grp < 2 ? tot[2] : 0.0f) + (grp < 3 ? tot[3] : 0.0f);
+      const float4 own = grp == 0 ? w[0] : grp == 1 ? w[1] : grp == 2 ? w[2] : w[3];
+      float suf[4];
+      suf[3] = above + own.w;
+      suf[2] = suf[3] + own.z;
+      suf[1] = suf[2] + own.y;
+      suf[0] = suf[1] + own.x;
+      float part[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int x = 0; x < 3; ++x) part[x] = fmaf(suf[r], acc[nb][1 + x][r], part[x]);
-    }
+      for (int r = 0; r < 4; ++r) {
+        const int j = 4 * grp + r;
+        if (live[nb] && j < n_met) a.wbar[(size_t)local * P.k_pad + j * AGE_PAD + i] = acc[u][nb][0][r];
 #pragma unroll
-    for (int x = 0; x < 3; ++x) {
-      part[x] += __shfl_xor(part[x], 16, 64);
-      part[x] += __shfl_xor(part[x], 32, 64);
-    }
-    if (live[nb] && grp == 0) {
-      float *out = a.aged_part + ((size_t)i * a.s_count + local) * 3;
-      out[0] = part[0];
-      out[1] = part[1];
-      out[2] = part[2];
+        for (int x = 0; x < 3; ++x) part[x] = fmaf(suf[r], acc[u][nb][1 + x][r], part[x]);
+      }
+#pragma unroll
+      for (int x = 0; x < 3; ++x) {
+        part[x] += __shfl_xor(part[x], 16, 64);
+        part[x] += __shfl_xor(part[x], 32, 64);
+      }
+      if (live[nb] && grp == 0) {
+        float *out = a.aged_part + ((size_t)i * a.s_count + local) * 3;
+        out[0] = part[0];
+        out[1] = part[1];
+        out[2] = part[2];
+      }
     }
   }
 }
@@ -780,7 +821,8 @@ int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
                          a.w_rows, a.s_count, a.ssp.n_met, a.ssp.k_pad, a.wsuf);
     }
     if (a.aged)
-      hipLaunchKernelGGL(k_vjp_wbar_aged, dim3(a.ssp.n_age, tiles), dim3(256), 0, stream, a);
+      hipLaunchKernelGGL(k_vjp_wbar_aged, dim3(aged_units(a.ssp.n_age, a.age_young, a.age_old), tiles),
+                         dim3(256), 0, stream, a);
     else if (a.ion)
       hipLaunchKernelGGL(k_vjp_wbar<true>, dim3(a.ssp.sk_rows / TILE_L, tiles), dim3(GEMM_THREADS), 0,
                          stream, a);

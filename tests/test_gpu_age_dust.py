@@ -292,3 +292,31 @@ def test_age_dust_autograd_equals_adjoint(dev, large):
                      bands=dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)[1])
     for k, v in leaves.items():
         assert torch.equal(v.grad, g[k]), k
+
+
+def test_age_dust_full_size_sampled(dev, large):
+    """The benchmarked age-dependent workload size (1e5 galaxies, so the
+    adjoint runs in two batches) in one call each: magnitudes and every
+    cotangent of 32 sampled galaxies (the first and last among them)
+    against the oracle."""
+    import torch
+    ssp_h, flt_h, ssp = large
+    pop = _pop(100_000, seed=9, z_range=(0.1, 3.0))
+    _say("age-dust full size n_gal=100000")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m, bands = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_bands=True)
+    bar = 2.0 * (m - torch.tensor(pop.targets, device="cuda", dtype=torch.float32))
+    g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp, bar, bands=bands)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2)
+    idx = np.unique(np.concatenate([[0, 99_999], rng.choice(pop.n_gal, 30, replace=False)]))
+    sub = pop.subset(idx)
+    inp = oracle_inputs(ssp, sub)
+    assert max_abs(m.cpu().numpy()[idx], oracle.mags(inp)) < FP32_TOL_MAG
+    ref = oracle.mags_vjp(inp, bar.cpu().numpy()[idx].astype(np.float64))
+    for k, rk in AGED_KEYS.items():
+        ok, info = grad_close(g[k].cpu().numpy()[idx], ref[rk])
+        assert ok, (k, info)
+    for j in range(5):
+        ok, info = grad_close(g["sfh_params"].cpu().numpy()[j, idx], ref["sfh_params_bar"][j])
+        assert ok, (j, info)

@@ -147,6 +147,44 @@ def test_k0_branches_meet_at_switch():
     assert k_s[3] == dust.k_calzetti00(0.3) and k_p[3] == dust.k_leitherer02(0.3)
 
 
+def _calzetti_golden():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "calzetti2000_k.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_calzetti_near_infrared_branch_published_values():
+    # Calzetti et al. (2000) Eq. 4, near-infrared branch (0.63-2.2 micron):
+    # hand-evaluated values of the published curve from the seam to the K
+    # band.  A changed digit in either coefficient of the branch, or in its
+    # 2.659 factor, moves the K-band value by > 1%.
+    g = _calzetti_golden()["near_infrared"]
+    lam = np.array(g["lambda_micron"])
+    np.testing.assert_allclose(dust.k_calzetti00(lam), g["k"], rtol=2e-6)
+    # the baseline curve of Eq. kzero takes this branch at and above 0.63 micron
+    np.testing.assert_allclose(dust.k0(lam * 1.0e4), g["k"], rtol=2e-6)
+    # linear in 1/lambda: equal steps in 1/lambda give equal steps in k
+    k = dust.k_calzetti00(np.array([0.7, 1.0, 1.75]))     # 1/lambda = 10/7, 1, 4/7
+    assert k[0] - k[1] == pytest.approx(k[1] - k[2], rel=1e-12)
+
+
+def test_calzetti_branches_meet_at_063_micron():
+    # The published curve switches branch at 0.63 micron; the two branches
+    # are not continuous there but agree to 0.72% (3.4766 vs 3.5017).
+    g = _calzetti_golden()
+    uv = dust.k_calzetti00(0.63 - 1e-12)
+    ir = dust.k_calzetti00(0.63)
+    assert uv == pytest.approx(g["ultraviolet_optical_at_0.63"], rel=2e-6)
+    assert ir == pytest.approx(g["near_infrared"]["k"][0], rel=2e-6)
+    assert abs(ir / uv - 1.0) < 1e-2
+    # the curve stays positive over the whole branch (A_V > 0 always dims)
+    lam = np.linspace(0.63, 2.5, 200)
+    assert np.all(dust.k_calzetti00(lam) > 0.0)
+    assert np.all(np.diff(dust.k_calzetti00(lam)) < 0.0)
+
+
 def test_attenuation_identity_and_v_band():
     lam = np.geomspace(900, 25000, 50)
     f0 = dust.attenuation(lam, [0.0, 0.0], [-0.3, 0.2], [1.0, 2.0])

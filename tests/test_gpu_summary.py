@@ -136,8 +136,8 @@ def test_forward_model_at_z0_and_population_gradient(dev):
     mbar = osum.histogram_vjp(m_ref, A, B, cut, 0.05, M, edges, 0.3, hbar)
     ref = oracle.mags_vjp(inp, mbar)
     for k, rk in KEYS.items():
-        ok, info = grad_close(leaves[k].grad.cpu().numpy(), ref[rk], tol=2e-3)
+        ok, info = grad_close(leaves[k].grad.cpu().numpy(), ref[rk])
         assert ok, (k, info)
     for j in range(5):
-        ok, info = grad_close(par.grad.cpu().numpy()[j], ref["sfh_params_bar"][j], tol=2e-3)
+        ok, info = grad_close(par.grad.cpu().numpy()[j], ref["sfh_params_bar"][j])
         assert ok, (j, info)

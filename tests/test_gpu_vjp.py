@@ -134,6 +134,46 @@ def test_vjp_matches_central_differences(dev, small):
         assert ok, (j, info)
 
 
+def test_vjp_matches_central_differences_64_gradient_workload(dev, large):
+    """The gradient workload's check set (64 galaxies, 5994 wavelengths,
+    z ~ U[0.1, 3]): the GPU gradient of sum (m - target)^2 against central
+    differences of the FP64 oracle forward, h = 1e-4 in each parameter's
+    natural units (relative for the SFH parameters).  Galaxies are
+    independent, so one perturbation of a parameter in every galaxy at once
+    gives each galaxy's partial from its own loss term."""
+    import torch
+    ssp_h, flt_h, ssp = large
+    pop = synth.make_population(64, n_t=100, z_range=(0.1, 3.0), seed=5)
+    _say("vjp vs central differences, 64 galaxies, 5994 wavelengths")
+    dp = dev.DevicePopulation.from_synth(pop, use_params=True)
+    m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp).cpu().numpy().astype(np.float64)
+    g = dev.mags_vjp(ssp_h, flt_h, dev.Cosmology(), dp,
+                     torch.tensor(_loss_cotangent(m, pop.targets), dtype=torch.float32))
+
+    def per_galaxy_loss(p):
+        p.sfr = oracle.sfh.sfr_from_params(p.t_table, p.sfh_params)
+        return np.sum((oracle.mags(p) - pop.targets) ** 2, axis=1)
+
+    for k in KEYS:
+        vals = []
+        for sgn in (1, -1):
+            p = oracle_inputs(ssp, pop)
+            setattr(p, k, getattr(p, k) + sgn * 1e-4)
+            vals.append(per_galaxy_loss(p))
+        ok, info = grad_close(g[k].cpu().numpy(), (vals[0] - vals[1]) / 2e-4)
+        assert ok, (k, info)
+    for j in range(5):
+        h = 1e-4 * np.maximum(1.0, np.abs(pop.sfh_params[j]))
+        vals = []
+        for sgn in (1, -1):
+            p = oracle_inputs(ssp, pop)
+            p.sfh_params = p.sfh_params.copy()
+            p.sfh_params[j] += sgn * h
+            vals.append(per_galaxy_loss(p))
+        ok, info = grad_close(g["sfh_params"].cpu().numpy()[j], (vals[0] - vals[1]) / (2 * h))
+        assert ok, (j, info)
+
+
 def test_vjp_closed_forms(dev, small):
     import torch
     ssp_h, flt_h, ssp = small

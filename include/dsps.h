@@ -32,6 +32,8 @@
  *    on the host before any launch; a failed check enqueues nothing.
  *  - Scratch memory comes from a caller-provided workspace whose size
  *    dsps_workspace_size() reports; a smaller workspace is DSPS_ERR_WORKSPACE.
+ *    (dsps_mags_noalloc instead uses a fixed array the library holds per
+ *    device.)
  *  - Outputs are fully overwritten.  Inputs are const.  n_gal == 0 is a no-op
  *    that returns DSPS_OK.  NaN and Inf inputs are not checked; they
  *    propagate.  A band whose transmission misses the SED grid entirely
@@ -54,7 +56,7 @@
 extern "C" {
 #endif
 
-#define DSPS_ABI_VERSION 7
+#define DSPS_ABI_VERSION 8
 
 typedef enum {
   DSPS_OK = 0,
@@ -288,6 +290,26 @@ int dsps_sed_ion_tangent(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsp
 int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
               const dsps_pop *pop, int precision, float *mags, float *bands, float *moments,
               void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* dsps_mags for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results (bit for bit) and errors as dsps_mags, without the
+ * workspace: its scratch is a fixed array of DSPS_NOALLOC_SCRATCH_BYTES
+ * bytes that the library holds on each device it runs on until the process
+ * ends.  The call allocates and frees nothing (kernel instrumentation,
+ * dsps_profile_enable, is not recorded for it).  The population runs in as
+ * many batches of whole 128-galaxy tiles as the array needs; a population
+ * whose per-galaxy arrays alone do not fit beside one tile's batch (about
+ * two million galaxies on the 12 x 94 x 5994 grid) is refused with
+ * DSPS_ERR_SHAPE before any launch.  Every call on one device shares that
+ * device's array: calls that overlap in time on one device (on different
+ * streams, or from different threads) race and give undefined results;
+ * calls in stream order on one stream are safe.  The array's contents from
+ * an earlier call are never read. */
+#define DSPS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int dsps_mags_noalloc(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
+                      const dsps_pop *pop, int precision, float *mags, float *bands,
+                      float *moments, hipStream_t stream);
 
 /* Derivative of the float32 magnitudes with respect to each galaxy's
  * ionization centre (wrt 0: pop->lgu) or width (wrt 1: sigma_u) (Section 3.3,

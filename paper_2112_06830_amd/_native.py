@@ -27,6 +27,7 @@ EXPORTS = (
     "dsps_pop_summary_workspace", "dsps_pop_summary", "dsps_pop_summary_vjp",
     "dsps_ssp_create_neb", "dsps_ssp_ion_info", "dsps_eqw", "dsps_eqw_jvp",
     "dsps_sed_ion_tangent", "dsps_mags_ion_tangent", "dsps_eqw_pop", "dsps_eqw_pop_workspace",
+    "dsps_mags_noalloc",
 )
 MAX_ION, MAX_LINES = 16, 16
 
@@ -98,6 +99,7 @@ def _declare(lib):
         "dsps_weights": (I, [P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), P, P, P, S, P]),
         "dsps_sed": (I, [P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, I, P, P, S, P]),
         "dsps_mags": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P, P, S, P]),
+        "dsps_mags_noalloc": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P, P]),
         "dsps_mags_vjp": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P,
                               P, P, P, P, P, P, P, P, P, P, P, P, P, S, P]),
         "dsps_quantize_bf16": (I, [P, I, I, P, P, P]),

@@ -393,6 +393,21 @@ def mags(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopula
     return (m, bands) if with_bands else m
 
 
+def mags_noalloc(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopulation,
+                 out: torch.Tensor, precision="fp32", bands_out: torch.Tensor | None = None,
+                 moments_out: torch.Tensor | None = None, stream=None):
+    """dsps_mags_noalloc: dsps_mags on the library's fixed per-device scratch,
+    allocating nothing; the caller passes the outputs (out [n_gal, n_band],
+    optionally bands_out [n_gal, 2, n_band] and moments_out [n_gal, 3,
+    n_band], float32).  Calls that overlap on one device race."""
+    c, p = cosmo.c(), pop.c()
+    rc = _lib().dsps_mags_noalloc(ssp.handle, filters.handle, ctypes.byref(c), ctypes.byref(p),
+                                  _PREC[precision], _ptr(out), _ptr(bands_out), _ptr(moments_out),
+                                  _stream(stream))
+    N.check(rc, "dsps_mags_noalloc")
+    return out
+
+
 def quantize_bf16(x: torch.Tensor, stream=None):
     """dsps_quantize_bf16: (bf16 bits as int16 [rows, cols], scale float32 [rows])."""
     x = x.to(torch.float32).contiguous()

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <vector>
 
 namespace dsps {
@@ -454,11 +455,14 @@ struct Layout {
   int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
-static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int precision) {
+// batch_cap > 0 lowers the galaxies per batch below the default.
+static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int precision,
+                          int batch_cap = 0) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
   L.batch = std::min(n_gal, op == DSPS_OP_MAGS_VJP ? BATCH_VJP : BATCH_FWD);
+  if (batch_cap > 0) L.batch = std::min(L.batch, batch_cap);
   L.n_chunks = v.n_wave_pad / TILE_L;
   const int cpg = chunks_per_group(precision);
   L.n_groups = (L.n_chunks + cpg - 1) / cpg;
@@ -923,6 +927,96 @@ int dsps_mags(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo
   const Layout L = make_layout(DSPS_OP_MAGS, ssp->v, n_band, pop->n_gal, precision);
   DSPS_TRY(check_workspace(workspace, workspace_bytes, L.total));
   char *ws = (char *)workspace;
+  DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), (int *)(ws + L.perm), stream));
+  for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
+    const int cnt = std::min(L.batch, pop->n_gal - s0);
+    DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, precision, L, ws, s0, cnt, mags, bands, moments,
+                        stream));
+  }
+  return DSPS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- no-allocation scratch
+namespace dsps {
+
+// Scratch of dsps_mags_noalloc.  In host code this name is a host-side
+// stand-in, not a device address: only the per-device pointer that
+// hipGetSymbolAddress returns may reach a kernel or a copy.
+static __device__ __align__(256) unsigned char scratch[DSPS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
+
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current) and kept.
+static int noalloc_scratch(int device, void **ptr) {
+  DSPS_CHECK(device >= 0 && device < MAX_DEVICES, DSPS_ERR_DEVICE, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    DSPS_TRY(hip_fail(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"));
+    DSPS_CHECK(p && ((uintptr_t)p & 255u) == 0, DSPS_ERR_DEVICE, "scratch array misplaced");
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return DSPS_OK;
+}
+
+// The largest batch (a whole number of 128-galaxy tiles, at most the
+// default) whose forward layout fits the scratch array; 0 when even one
+// tile's batch does not.
+static int noalloc_batch(const SspView &v, int n_band, int n_gal, int precision, Layout *out) {
+  int lo = 0, hi = (std::min(n_gal, BATCH_FWD) + TILE_G - 1) / TILE_G;   // in tiles
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (make_layout(DSPS_OP_MAGS, v, n_band, n_gal, precision, mid * TILE_G).total <=
+        DSPS_NOALLOC_SCRATCH_BYTES)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  if (lo > 0) *out = make_layout(DSPS_OP_MAGS, v, n_band, n_gal, precision, lo * TILE_G);
+  return lo * TILE_G;
+}
+
+}  // namespace dsps
+
+extern "C" {
+
+int dsps_mags_noalloc(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
+                      const dsps_pop *pop, int precision, float *mags, float *bands,
+                      float *moments, hipStream_t stream) {
+  DSPS_CHECK(ssp && filters, DSPS_ERR_ARG, "ssp or filters is NULL");
+  DSPS_TRY(check_cosmo(cosmo));
+  DSPS_TRY(check_pop(pop, true));
+  DSPS_TRY(check_precision(ssp, precision));
+  DSPS_CHECK(!moments || precision == DSPS_FP32, DSPS_ERR_UNSUPPORTED,
+             "dust moments are computed in float32 only");
+  DSPS_CHECK(!pop->av_old || (precision == DSPS_FP32 && !moments && ssp->v.sa32), DSPS_ERR_UNSUPPORTED,
+             "age-dependent attenuation needs float32, no moments and an SSP handle created with "
+             "DSPS_SSP_AGE_MAJOR");
+  DSPS_TRY(check_ion(ssp, pop));
+  DSPS_CHECK(ssp->v.n_u == 1 || !pop->av_old, DSPS_ERR_UNSUPPORTED,
+             "with an ionization axis dsps_mags does not apply the age-dependent attenuation");
+  if (pop->n_gal == 0) return DSPS_OK;
+  DSPS_CHECK(mags, DSPS_ERR_ARG, "mags is NULL");
+  const int n_band = filters->v.n_band;
+  Layout L;
+  const int batch = noalloc_batch(ssp->v, n_band, pop->n_gal, precision, &L);
+  DSPS_CHECK(batch > 0, DSPS_ERR_SHAPE,
+             "n_gal %d does not fit the %zu-byte scratch of dsps_mags_noalloc (it needs %zu bytes "
+             "at one tile per batch); use dsps_mags with a workspace",
+             pop->n_gal, (size_t)DSPS_NOALLOC_SCRATCH_BYTES,
+             make_layout(DSPS_OP_MAGS, ssp->v, n_band, pop->n_gal, precision, TILE_G).total);
+  DSPS_TRY(check_device(ssp->device));
+  DSPS_CHECK(filters->device == ssp->device, DSPS_ERR_ARG, "ssp and filters on different devices");
+  void *ptr = nullptr;
+  DSPS_TRY(noalloc_scratch(ssp->device, &ptr));
+  char *ws = (char *)ptr;
+  ProfQuiet quiet;   // instrumentation would create events
   DSPS_TRY(sort_population(ssp, pop, (int *)(ws + L.hist), (int *)(ws + L.perm), stream));
   for (int s0 = 0; s0 < pop->n_gal; s0 += L.batch) {
     const int cnt = std::min(L.batch, pop->n_gal - s0);

@@ -259,6 +259,16 @@ class ProfScope {
   hipEvent_t start_ = nullptr, stop_ = nullptr;
 };
 
+// While an instance lives, ProfScope records nothing on this thread (for
+// entry points that must not create events).
+class ProfQuiet {
+ public:
+  ProfQuiet();
+  ~ProfQuiet();
+  ProfQuiet(const ProfQuiet &) = delete;
+  ProfQuiet &operator=(const ProfQuiet &) = delete;
+};
+
 // Cosmology parameters passed by value to kernels.
 struct CosmoArgs {
   double om0, ol, w0, hubble_time_gyr, hubble_dist_mpc;

@@ -17,6 +17,7 @@ std::atomic<bool> g_on{false};
 std::mutex g_mu;
 std::vector<Record> g_records;
 std::vector<hipEvent_t> g_pool;
+thread_local int g_quiet = 0;
 
 hipEvent_t take_event() {
   if (!g_pool.empty()) {
@@ -38,8 +39,11 @@ void recycle_all() {
 }
 }  // namespace
 
+ProfQuiet::ProfQuiet() { ++g_quiet; }
+ProfQuiet::~ProfQuiet() { --g_quiet; }
+
 ProfScope::ProfScope(int kernel_id, hipStream_t stream) : kid_(kernel_id), stream_(stream) {
-  if (!g_on.load(std::memory_order_relaxed)) return;
+  if (g_quiet || !g_on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> lock(g_mu);
   start_ = take_event();
   stop_ = take_event();

@@ -145,6 +145,25 @@ def cpu_baseline(ssp, flt, pop, m32, pop16=None, m16=None, min_seconds=10.0, blo
     return cpu, errors
 
 
+def cpu_baseline_single_thread(ssp, flt, pop, min_seconds=10.0, block=256, max_gal=8192):
+    """The same oracle timing with the BLAS thread pools held to one thread."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    done = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while done < min(max_gal, pop.n_gal):
+            idx = np.arange(done, min(done + block, pop.n_gal))
+            oracle.mags(oracle.prepare_inputs(ssp, flt, pop.subset(idx)))
+            done += idx.size
+            if time.perf_counter() - t0 >= min_seconds:
+                break
+        dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "galaxies/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} galaxies of the same population (FP64 numpy oracle, "
+                      f"{dt:.1f} s, BLAS threads=1)"}
+
+
 def run_workload(P, name, n_gal, n_t, precision, steps, warmup, seed, want_roofline=True):
     import torch
     import synth
@@ -233,6 +252,18 @@ def run_grad(P, steps, warmup, n_gal=200_000, seed=5):
         res[f"{k}_ms_per_step"] = ms / steps
     P.profile_enable(False)
     res["finite"] = bool(all(torch.isfinite(v).all().item() for v in outs.values()))
+    # algorithmic work: the forward contraction and the transposed one (W-bar)
+    # each do 2 nnz(W_g) n_lambda_eff(z_g) flops per galaxy
+    flops, _, _ = algorithmic_flops(P, ssp_h, dpop, ssp, flt, pop.z)
+    peak = PEAK_TFLOPS["fp32"]
+    roof = {"bound": "mfma", "peak": peak, "unit": "TFLOP/s", "alg_flops_per_contraction": flops}
+    for k in ("mags_gemm", "vjp_wbar"):
+        t = res[f"{k}_ms_per_step"] * 1e-3
+        roof[k] = {"achieved": flops / t / 1e12, "frac": flops / t / 1e12 / peak}
+    step_s = res["ms_per_step"] * 1e-3
+    roof["step"] = {"alg_flops": 2.0 * flops, "achieved": 2.0 * flops / step_s / 1e12,
+                    "frac": 2.0 * flops / step_s / 1e12 / peak}
+    res["roofline"] = roof
     return res
 
 
@@ -575,8 +606,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the BF16 1e6, forward+gradient and serving legs")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
-    ap.add_argument("--pmc-pass", action="store_true",
-                    help="short FP32 run plus a calibration copy, for rocprofv3 --pmc")
+    ap.add_argument("--pmc-pass", nargs="?", const="fp32_1e5", default=None,
+                    choices=("fp32_1e5", "bf16_1e6", "grad_2e5"),
+                    help="short run of one leg (default the FP32 forward) plus a calibration "
+                         "copy, for rocprofv3 --pmc")
     args = ap.parse_args()
 
     if args.pmc_pass:
@@ -586,7 +619,12 @@ def main():
         # CALIBRATION_BYTES).
         import torch
         import paper_2112_06830_amd as P
-        run_workload(P, "fwd_fp32_1e5", 100_000, 100, "fp32", 3, 1, seed=3, want_roofline=False)
+        if args.pmc_pass == "fp32_1e5":
+            run_workload(P, "fwd_fp32_1e5", 100_000, 100, "fp32", 3, 1, seed=3, want_roofline=False)
+        elif args.pmc_pass == "bf16_1e6":
+            run_workload(P, "fwd_bf16_1e6", 1_000_000, 1000, "bf16", 3, 1, seed=4, want_roofline=False)
+        else:
+            run_grad(P, 3, 1)
         n = CALIBRATION_BYTES // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -652,6 +690,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle on a bounded sample")
         cpu, errors = cpu_baseline(ssp, flt, pop, m32, pop16, m16)
+        extra["cpu_baseline_single_thread"] = cpu_baseline_single_thread(ssp, flt, pop)
         if not args.no_extra:
             import oracle
             v_ssp, v_flt, v_pop, v_m, v_w0 = va_sample

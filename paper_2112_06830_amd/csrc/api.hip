@@ -226,7 +226,8 @@ static int ssp_create(int n_met, int n_age, int n_u, int n_wave, const double *l
   const size_t o_st16 = want16 ? take(sizeof(uint16_t) * (size_t)nwp * kp) : 0;
   const int sk_rows = (kp + TILE_L - 1) / TILE_L * TILE_L;
   const bool want_sk = want32;   // the adjoint's table, one block per ionization point
-  const size_t o_sk = want_sk ? take(sizeof(float) * (size_t)n_u * sk_rows * nwp) : 0;
+  // without the ionization axis the plain K-major rows follow the differenced ones
+  const size_t o_sk = want_sk ? take(sizeof(float) * (size_t)(n_u == 1 ? 2 : n_u) * sk_rows * nwp) : 0;
   const size_t o_sa = want_age ? take(sizeof(float) * (size_t)nwp * AGE_K) : 0;
   const size_t o_ks = take(sizeof(float) * kp);
   const size_t o_lc = take(sizeof(float4) * nwp);
@@ -296,8 +297,12 @@ static int ssp_create(int n_met, int n_age, int n_u, int n_wave, const double *l
     if (rc) break;
     for (int k = 0; want_sk && k < n_u && !rc; ++k)
       rc = launch_pack_table_kmajor(d_rows + (size_t)k * rows * n_wave, n_age, n_wave, nwp, kp,
-                                    sk_rows, (float *)(b + o_sk) + (size_t)k * sk_rows * nwp,
+                                    sk_rows, 1, (float *)(b + o_sk) + (size_t)k * sk_rows * nwp,
                                     nullptr);
+    if (rc) break;
+    if (want_sk && n_u == 1)
+      rc = launch_pack_table_kmajor(d_rows, n_age, n_wave, nwp, kp, sk_rows, 0,
+                                    (float *)(b + o_sk) + (size_t)sk_rows * nwp, nullptr);
     if (rc) break;
     if (want_age) rc = launch_pack_table_age(d_rows, n_met, n_age, n_wave, nwp, (float *)(b + o_sa), nullptr);
     if (rc) break;
@@ -451,7 +456,7 @@ constexpr int BATCH_VJP = 65536;
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
   size_t gamma = 0, dust = 0, lbar = 0, wbar = 0, fbands = 0, tiles = 0, tobs = 0, dust_old = 0;
-  size_t ion = 0, wsuf = 0, ipart = 0, apart = 0, ebuf = 0, dbuf = 0;
+  size_t ion = 0, wsuf = 0, ipart = 0, apart = 0, ebuf = 0, dbuf = 0, wabs = 0;
   int batch = 0, n_groups = 0, n_chunks = 0;
 };
 
@@ -512,6 +517,7 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
     L.dust = take(sizeof(float) * (size_t)L.batch * 3);
     L.lbar = take(sizeof(float) * (size_t)L.batch * v.n_wave_pad);
     L.wbar = take(sizeof(float) * (size_t)L.batch * v.k_pad);
+    L.wabs = take(sizeof(float) * (size_t)L.batch * AGE_PAD);
     // bands, moments and magnitudes of the forward pass when not supplied
     L.fbands = take(sizeof(float) * (size_t)n_gal * 6 * n_band);
     if (v.n_u > 1) {
@@ -1122,10 +1128,9 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
       a.obs_lo = filters->obs_lo;
       a.obs_hi = filters->obs_hi;
       a.ion = ssp->v.n_u > 1 ? (GalaxyIon *)(ws + L.ion) : nullptr;
-      if (ssp->v.n_u > 1 || age_dust) {   // the W rows for the ionization or dust cotangents
+      a.t_obs = (double *)(ws + L.tobs);
+      if (ssp->v.n_u > 1 || age_dust)     // the W rows for the ionization or dust cotangents
         a.w_pad = ws + L.w;
-        a.t_obs = (double *)(ws + L.tobs);
-      }
       if (age_dust) {
         a.w_pad_age = 1;
         a.dust_old = (GalaxyDustOld *)(ws + L.dust_old);
@@ -1152,6 +1157,10 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
     v.dust = (float *)(ws + L.dust);
     v.lbar = (float *)(ws + L.lbar);
     v.wbar = (float *)(ws + L.wbar);
+    // the plain transposed contraction starts each galaxy at its lowest
+    // support row (k_vjp_wbar_rows)
+    v.wabs = (ssp->v.n_u == 1 && !age_dust) ? (float *)(ws + L.wabs) : nullptr;
+    v.t_obs = (const double *)(ws + L.tobs);
     v.t_table = pop->t_table;
     v.sfr = pop->sfr;
     v.sfh_params = pop->sfh_params;

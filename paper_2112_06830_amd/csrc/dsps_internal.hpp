@@ -72,7 +72,8 @@ struct SspView {
   const float4 *lconst;            // [n_wave_pad] (lambda, log2(lambda/5500), k0, drude shape)
   const float *qweight;            // [n_wave_pad] trapezoid weight in dlambda/lambda
   // [n_u][sk_rows][n_wave_pad] K-major, metallicity-differenced (adjoint),
-  // one block per ionization point
+  // one block per ionization point; without the ionization axis followed by
+  // the plain K-major rows [sk_rows][n_wave_pad] (row sk_rows + k is L[k])
   const float *sk32;
   int sk_rows;                     // k_pad rounded up to a multiple of TILE_L
   // [n_wave_pad][AGE_K] age-major float32 (age-dependent attenuation) or null:
@@ -115,16 +116,21 @@ struct GalaxyMeta {
   float bump;
 };
 // Blocks of KBLOCK_AGES consecutive (padded) ages in one metallicity row:
-// the unit in which the contraction skips all-zero weights.
-constexpr int KBLOCK_AGES = 16;
-constexpr int KBLOCKS_PER_ROW = AGE_PAD / KBLOCK_AGES;                  // 6
-constexpr int KBLOCK_WORDS = (DSPS_MAX_MET * KBLOCKS_PER_ROW + 31) / 32;  // 3
+// the unit in which the contraction skips all-zero weights (one 16-byte unit
+// of a float32 weight row; two blocks make a bfloat16 unit).
+constexpr int KBLOCK_AGES = 4;
+constexpr int KBLOCKS_PER_ROW = AGE_PAD / KBLOCK_AGES;                  // 24
+constexpr int KBLOCK_WORDS = (DSPS_MAX_MET * KBLOCKS_PER_ROW + 31) / 32;  // 12
 static_assert(DSPS_MAX_MET <= 16 && KBLOCKS_PER_ROW == 2 * KBLOCK_WORDS, "block-major mask layout");
+// K units of a tile's stage list: one per (row, block) for float32, per
+// (row, pair of blocks) for bfloat16, four per age for the age-major layout.
+constexpr int MAX_UNITS = DSPS_MAX_MET * KBLOCKS_PER_ROW;               // 384
+static_assert(MAX_UNITS >= AGE_PAD * 4 && MAX_UNITS % 4 == 0, "unit list size");
 
 struct GalaxyRange {
   int win_lo, win_hi;            // rest-wavelength index window [lo, hi) that any filter sees
-  // bit 16 a + j (word a / 2, bit 16 (a % 2) + j) set when metallicity row j
-  // has a non-zero weight at some age in [16 a, 16 a + 16)
+  // bit 16 (a % 2) + j of word a / 2 set when metallicity row j has a
+  // non-zero weight at some age in [4 a, 4 a + 4)
   unsigned kblk[KBLOCK_WORDS];
   int age_hi;    // ages >= age_hi carry no weight (AGE_PAD when unknown)
 };
@@ -349,21 +355,23 @@ int launch_pack_table(const float *lum_rows, const uint16_t *q_rows, int n_met, 
 int launch_pack_table_age(const float *lum_rows, int n_met, int n_age, int n_wave, int n_wave_pad,
                           float *sa32, hipStream_t stream);
 int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n_wave_pad,
-                             int k_pad, int sk_rows, float *sk32, hipStream_t stream);
+                             int k_pad, int sk_rows, int differenced, float *sk32,
+                             hipStream_t stream);
 
 // Defined in k_mags.hip.
 // Per 128-galaxy tile of the fused contraction, computed once before it: the
 // union of the members' wavelength windows as chunks [c_first, c_last), the
-// range of 1 + z, the K offsets of the stages that hold a non-zero weight
-// for some member, in ascending order, and the ionization points [u_lo, u_hi]
-// some member's distribution reaches (0, 0 without the axis).
+// range of 1 + z, the K units that hold a non-zero weight for some member, in
+// ascending order and padded with -1 (a unit of zeros) to whole stages of
+// four, and the ionization points [u_lo, u_hi] some member's distribution
+// reaches (0, 0 without the axis).
 struct TilePlan {
   int c_first, c_last;
-  int nk;
+  int nk;                        // stages (four units each)
   float zp1_min, zp1_max;
   int u_lo, u_hi;
-  int pad;
-  int koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];
+  int n_units;                   // units before the padding
+  int koff[MAX_UNITS];           // K offset of each unit in elements, or -1
 };
 
 struct MagsLaunch {
@@ -499,6 +507,10 @@ struct VjpLaunch {
   float *dust;                // [s_count][3] sum_b gamma_b x each moment
   float *lbar;                // [s_count][n_wave_pad], the tile windows
   float *wbar;                // [s_count][k_pad]
+  // [s_count][AGE_PAD] plain Wbar of the lowest row of each galaxy's MDF
+  // support (k_vjp_wbar_rows), or null: wbar row 0 is then plain as well
+  float *wabs;
+  const double *t_obs;        // [n_gal] cosmic time at z, by sorted position
   // population (for the per-galaxy pull-back)
   const double *t_table, *sfr, *sfh_params;
   const float *z, *lgmet, *sigma_z, *av;

@@ -22,13 +22,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct GemmCfg;
+// KT: K elements per stage.  A stage is UNITS units of UNIT_K consecutive K
+// elements each, from anywhere in K: the stage lists of the fused kernels
+// skip units that are zero for every member of a tile.  A unit is what one
+// MFMA step takes from each operand row (float32: two steps), so a galaxy's
+// sum adds its own units in ascending K order whatever else its tile holds,
+// and units of zeros add exact zeros.
 template <> struct GemmCfg<DSPS_FP32> {
   using elem = float;
   static constexpr int KT = 16;
+  static constexpr int UNITS = 2, UNIT_K = 8;
 };
 template <> struct GemmCfg<DSPS_BF16> {
   using elem = uint16_t;
   static constexpr int KT = 32;
+  static constexpr int UNITS = 2, UNIT_K = 16;
 };
 constexpr int STAGE_UNITS = 4;   // 16-byte units per operand row and stage
 
@@ -57,24 +65,118 @@ struct StageRegs {
   u32x4 b[NV];
 };
 
+// Blocks are dispatched round-robin over the 8 XCDs by linear id.  All
+// groups of one galaxy tile go to the same XCD (the tile's operand rows then
+// stay in that XCD's L2): block b runs on XCD b % 8 and takes tile
+// (b / 8 / G) * 8 + b % 8, group (b / 8) % G.  A grid of
+// ceil(tiles / 8) * 8 * G blocks covers every (tile, group).
+__device__ __forceinline__ void xcd_tile_group(int b, int groups, int &tile, int &group) {
+  const int xcd = b & 7, slot = b >> 3;
+  tile = (slot / groups) * 8 + xcd;
+  group = slot % groups;
+}
+
+// The A rows this thread stages, one per staging vector: vector v of thread
+// t holds unit (t + 256 v) % 4 of tile row (t + 256 v) / 4, read from A row
+// r[v] (l0 + the tile row for a contiguous block of rows).
 template <int PREC>
-__device__ __forceinline__ void load_stage(StageRegs<PREC> &r, const typename GemmCfg<PREC>::elem *st,
-                                           int a_stride, int l0, const typename GemmCfg<PREC>::elem *w,
-                                           int b_stride, int g0, int g_count, int a_ofs, int b_ofs) {
-  using S = StageRegs<PREC>;
-  constexpr int EPV = 16 / sizeof(typename GemmCfg<PREC>::elem);  // elements per vector
+struct ARows {
+  int r[StageRegs<PREC>::NV];
+};
+template <int PREC>
+__device__ __forceinline__ ARows<PREC> linear_rows(int l0) {
+  ARows<PREC> a;
 #pragma unroll
-  for (int v = 0; v < S::NV; ++v) {
-    const int idx = threadIdx.x + v * GEMM_THREADS;
-    const int row = idx / STAGE_UNITS, col = idx % STAGE_UNITS;
-    r.a[v] = *reinterpret_cast<const u32x4 *>(st + (size_t)(l0 + row) * a_stride + a_ofs + col * EPV);
-    u32x4 bv = {0u, 0u, 0u, 0u};
-    if (g0 + row < g_count)
-      bv = *reinterpret_cast<const u32x4 *>(w + (size_t)(g0 + row) * b_stride + b_ofs + col * EPV);
-    r.b[v] = bv;
+  for (int v = 0; v < StageRegs<PREC>::NV; ++v)
+    a.r[v] = l0 + (int)(threadIdx.x + v * GEMM_THREADS) / STAGE_UNITS;
+  return a;
+}
+// Tile row of staging vector v of this thread.
+template <int PREC>
+__device__ __forceinline__ int stage_row(int v) {
+  return (int)(threadIdx.x + v * GEMM_THREADS) / STAGE_UNITS;
+}
+
+// The operands of a K loop as buffer resources, plus this thread's row byte
+// offsets (one per staging vector).  A buffer load outside its resource's
+// range returns zeros: B rows past the tile's last galaxy, and units of
+// zeros, cost no branch.
+template <int PREC>
+struct GemmOps {
+  __amdgpu_buffer_rsrc_t a, b;
+  int ra[StageRegs<PREC>::NV], rb[StageRegs<PREC>::NV];
+};
+// Raw buffer resource over n_bytes from p (dword 3 of the gfx9 family).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, size_t n_bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n_bytes, 0x00020000);
+}
+// A: a matrix of a_elems elements in rows of a_stride, this thread's rows ar;
+// B: the tile's rows from b_tile (its first galaxy), b_stride apart, of which
+// the first b_valid hold data.
+template <int PREC>
+__device__ __forceinline__ GemmOps<PREC> gemm_ops(const typename GemmCfg<PREC>::elem *a_base,
+                                                  size_t a_elems, int a_stride, const ARows<PREC> &ar,
+                                                  const typename GemmCfg<PREC>::elem *b_tile,
+                                                  int b_valid, int b_stride) {
+  using elem = typename GemmCfg<PREC>::elem;
+  GemmOps<PREC> o;
+  o.a = buffer_rsrc(a_base, a_elems * sizeof(elem));
+  o.b = buffer_rsrc(b_tile, (size_t)max(b_valid, 0) * b_stride * sizeof(elem));
+#pragma unroll
+  for (int v = 0; v < StageRegs<PREC>::NV; ++v) {
+    o.ra[v] = ar.r[v] * a_stride * (int)sizeof(elem);
+    o.rb[v] = stage_row<PREC>(v) * b_stride * (int)sizeof(elem);
+  }
+  return o;
+}
+
+// Where this thread's 16 bytes of a K stage come from: element offsets in
+// its A and B rows (b < 0: zeros) and, float32 only, factors of the B rows
+// applied as the stage is written to LDS (or null).  Thread t stages LDS
+// unit c = t % 4 of each of its rows: in float32 piece c / 2 of K unit c % 2
+// (MFMA step s pairs LDS units s / 4 and 2 + s / 4), in bfloat16 piece c % 2
+// of K unit c / 2 (MFMA step s takes LDS units 2s and 2s + 1).
+struct UnitSrc {
+  int a, b;
+  const float *bscale;
+};
+__device__ __forceinline__ int stage_col() { return (int)(threadIdx.x % STAGE_UNITS); }
+// This thread's piece of stage s from a list of K units (-1: a unit of zeros).
+template <int PREC>
+__device__ __forceinline__ int unit_piece(const int *units, int s, int col) {
+  using C = GemmCfg<PREC>;
+  constexpr int EPP = 16 / (int)sizeof(typename C::elem);   // elements per piece
+  const int v = PREC == DSPS_FP32 ? col & 1 : col >> 1;
+  const int q = PREC == DSPS_FP32 ? col >> 1 : col & 1;
+  const int k = units[C::UNITS * s + v];
+  return k < 0 ? -1 : k + q * EPP;
+}
+// The same for K units of a contiguous range from k0: unit v of stage s
+// starts at k0 + KT s + UNIT_K v.
+template <int PREC>
+__device__ __forceinline__ int contiguous_piece(int k0, int s, int col) {
+  using C = GemmCfg<PREC>;
+  constexpr int EPP = 16 / (int)sizeof(typename C::elem);
+  const int v = PREC == DSPS_FP32 ? col & 1 : col >> 1;
+  const int q = PREC == DSPS_FP32 ? col >> 1 : col & 1;
+  return k0 + C::KT * s + C::UNIT_K * v + q * EPP;
+}
+// An offset past the end of every B resource (tile rows stay far below it).
+constexpr int ZERO_UNIT_BYTES = 0x40000000;
+
+template <int PREC>
+__device__ __forceinline__ void load_units(StageRegs<PREC> &r, const GemmOps<PREC> &o, UnitSrc u) {
+  constexpr int ES = (int)sizeof(typename GemmCfg<PREC>::elem);
+  const int oa = u.a * ES;
+  const int ob = u.b < 0 ? ZERO_UNIT_BYTES : u.b * ES;
+#pragma unroll
+  for (int v = 0; v < StageRegs<PREC>::NV; ++v) {
+    r.a[v] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(o.a, o.ra[v] + oa, 0, 0));
+    r.b[v] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(o.b, o.rb[v] + ob, 0, 0));
   }
 }
 
+// A thread's 16 bytes go to LDS unit t % 4 of their row.
 template <int PREC>
 __device__ __forceinline__ void store_stage(const StageRegs<PREC> &r, GemmSmem<PREC> &sm) {
   using S = StageRegs<PREC>;
@@ -101,18 +203,6 @@ __device__ __forceinline__ void scale_stage_b(StageRegs<DSPS_FP32> &r, const flo
   }
 }
 
-// Where K stage s comes from, for K loops whose operands do not share K
-// offsets: the offset in A and in B, and an LDS row of per-B-row factors
-// applied as the stage is written to LDS (float32 only).
-struct StageSrc {
-  int a, b;
-  const float *bscale;
-};
-// The same without B factors.
-struct StageAB {
-  int a, b;
-};
-
 __device__ __forceinline__ float4 as_float4(u32x4 v) {
   return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
                      __uint_as_float(v.w));
@@ -122,8 +212,10 @@ __device__ __forceinline__ float4 as_float4(u32x4 v) {
 __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_FP32> &sm, int wr, int wc, int lane,
                                           f32x16 (&acc)[2][2]) {
   const int h = lane >> 5, c = lane & 31;
-  // Lane half h supplies contraction index 8h + t at MFMA step t, for A and B
-  // alike: each lane reads units 2h and 2h + 1 of its operand rows.
+  // Lane half h supplies LDS row position 8h + t at MFMA step t, for A and B
+  // alike: each lane reads units 2h and 2h + 1 of its rows.  With K unit v's
+  // two 16-byte pieces in LDS units v and v + 2 (unit_piece), step t takes
+  // elements t % 4 and 4 + t % 4 of K unit t / 4.
   float av[2][8], bv[2][8];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb) {
@@ -172,47 +264,32 @@ __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_BF16> &sm, int wr,
   }
 }
 
-// The K loop of one output tile over nk stages, stage s at K offset koff(s)
-// of both operands (A rows l0.., B rows g0.., rows of B at or past g_count
-// read as zeros).  Two LDS stage buffers: while stage s feeds MFMA, stage
-// s + 1 is written to the other buffer and stage s + 2 is loaded into
-// registers, with one barrier per stage.  On entry no wave may still read
-// sm; on return every wave has passed a barrier after its last read of it.
-// after(ks) runs in every wave right after the MFMAs of stage ks (register
-// work on the accumulators only).  koff(s) returns the common K offset of
-// both operands (an int), a StageAB (separate offsets) or a StageSrc (also
-// B factors); A rows are a_stride and B rows b_stride elements apart.
+// The K loop of one output tile over nk stages; unit(s) says where this
+// thread's unit of stage s comes from (a UnitSrc).  Two LDS stage buffers:
+// while stage s feeds MFMA, stage s + 1 is written to the other buffer and
+// stage s + 2 is loaded into registers, with one barrier per stage.  On
+// entry no wave may still read sm; on return every wave has passed a barrier
+// after its last read of it.  after(ks) runs in every wave right after the
+// MFMAs of stage ks (register work on the accumulators only).
 struct NoStageHook {
   __device__ void operator()(int) const {}
 };
-template <int PREC, typename KOffset, typename StageHook = NoStageHook>
-__device__ __forceinline__ void gemm_kloop_ab(GemmSmem<PREC> *sm,
-                                              const typename GemmCfg<PREC>::elem *st, int a_stride,
-                                              int l0, const typename GemmCfg<PREC>::elem *w,
-                                              int b_stride, int g0, int g_count, int nk,
-                                              KOffset koff, int wr, int wc, int lane,
-                                              f32x16 (&acc)[2][2], StageHook after = StageHook()) {
-  constexpr bool SCALED = std::is_same_v<decltype(koff(0)), StageSrc>;
-  constexpr bool SPLIT = std::is_same_v<decltype(koff(0)), StageAB>;
-  static_assert(!SCALED || PREC == DSPS_FP32, "per-row B factors are float32 only");
+template <int PREC, typename UnitFn, typename StageHook = NoStageHook>
+__device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const GemmOps<PREC> &ops, int nk,
+                                           UnitFn unit, int wr, int wc, int lane,
+                                           f32x16 (&acc)[2][2], StageHook after = StageHook()) {
   StageRegs<PREC> regs;
   const float *pending = nullptr;   // B factors of the stage held in regs
   auto load = [&](int s) {
-    if constexpr (SCALED) {
-      const StageSrc src = koff(s);
-      load_stage<PREC>(regs, st, a_stride, l0, w, b_stride, g0, g_count, src.a, src.b);
-      pending = src.bscale;
-    } else if constexpr (SPLIT) {
-      const StageAB src = koff(s);
-      load_stage<PREC>(regs, st, a_stride, l0, w, b_stride, g0, g_count, src.a, src.b);
-    } else {
-      const int k = koff(s);
-      load_stage<PREC>(regs, st, a_stride, l0, w, b_stride, g0, g_count, k, k);
-    }
+    const UnitSrc u = unit(s);
+    load_units<PREC>(regs, ops, u);
+    pending = u.bscale;
   };
   auto store = [&](GemmSmem<PREC> &buf) {
-    if constexpr (SCALED) scale_stage_b(regs, pending);
-    store_stage<PREC>(regs, buf);
+    if constexpr (PREC == DSPS_FP32) {
+      if (pending) scale_stage_b(regs, pending);
+    }
+    store_stage(regs, buf);
   };
   if (nk > 0) {
     load(0);
@@ -229,16 +306,6 @@ __device__ __forceinline__ void gemm_kloop_ab(GemmSmem<PREC> *sm,
     }
     __syncthreads();
   }
-}
-
-// Both operands with rows of k_pad elements and a common K offset per stage.
-template <int PREC, typename KOffset, typename StageHook = NoStageHook>
-__device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const typename GemmCfg<PREC>::elem *st,
-                                           int k_pad, int l0, const typename GemmCfg<PREC>::elem *w,
-                                           int g0, int g_count, int nk, KOffset koff, int wr, int wc,
-                                           int lane, f32x16 (&acc)[2][2],
-                                           StageHook after = StageHook()) {
-  gemm_kloop_ab<PREC>(sm, st, k_pad, l0, w, k_pad, g0, g_count, nk, koff, wr, wc, lane, acc, after);
 }
 
 // Age-dependent attenuation (Section 3.4.1, Eq. agedep_dust_csp) over an
@@ -299,6 +366,19 @@ __device__ __forceinline__ unsigned active_bands(const FilterView &F, float o_lo
   return m;
 }
 
+// Bands whose table covers the observed wavelengths [o_lo, o_hi] with a
+// relative margin far above float rounding: every lookup of such a band lands
+// inside its table, so the clamp and the outside test can be left out.
+__device__ __forceinline__ unsigned interior_bands(const FilterView &F, float o_lo, float o_hi) {
+  unsigned m = 0;
+  for (int b = 0; b < F.n_band; ++b) {
+    const float2 gr = F.grid[b];
+    const float lo = gr.x, hi = gr.x + (float)(F.n_pts - 1) / gr.y;
+    if (o_lo >= lo * 1.00002f && o_hi <= hi * 0.99998f) m |= 1u << b;
+  }
+  return m;
+}
+
 // Filter transmission tables in LDS: band b at b * filter_stride(n_pts), its
 // n_pts points followed by one pad entry repeating the last, so that an
 // interpolation at the table's upper end needs no index clamp.
@@ -323,6 +403,13 @@ __device__ __forceinline__ float filter_table_at(const float *tr, int n_int, flo
   const float t0 = tr[i], t1 = tr[i + 1];
   const float t = fmaf(__builtin_amdgcn_fractf(uc), t1 - t0, t0);
   return u == uc ? t : 0.0f;
+}
+// The same for a u known to lie in [0, n_int] (an interior band): equal to
+// filter_table_at there, without the clamp and the outside test.
+__device__ __forceinline__ float filter_table_inside(const float *tr, float u) {
+  const int i = (int)u;
+  const float t0 = tr[i], t1 = tr[i + 1];
+  return fmaf(__builtin_amdgcn_fractf(u), t1 - t0, t0);
 }
 
 }  // namespace dsps

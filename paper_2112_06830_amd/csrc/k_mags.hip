@@ -24,16 +24,6 @@
 namespace dsps {
 
 
-// Blocks are dispatched round-robin over the 8 XCDs by linear id.  All
-// wavelength groups of one galaxy tile go to the same XCD (its W tile then
-// stays in that XCD's L2): block b runs on XCD b % 8 and takes tile
-// (b / 8 / G) * 8 + b % 8, group (b / 8) % G.
-__device__ __forceinline__ void xcd_tile_group(int b, int groups, int &tile, int &group) {
-  const int xcd = b & 7, slot = b >> 3;
-  tile = (slot / groups) * 8 + xcd;
-  group = slot % groups;
-}
-
 // Most band slots evaluated together in one epilogue pass (a pass takes as
 // many of the chunk's remaining bands as it can, up to this).
 constexpr int NSLOT = 3;
@@ -103,7 +93,7 @@ struct EpiLane {
 // moment integrands are formed here.  Sums, per band: num += T e,
 // den += T q and, with MOM, T e k_lambda, T e k0 (lambda/5500)^delta
 // log2(lambda/5500) and T e D(lambda).
-template <bool MOM, int NCOMP, int NS>
+template <bool MOM, int NCOMP, int NS, bool INSIDE>
 __device__ __forceinline__ void band_pass(const f32x16 (&acc)[2][2], const EpiLane &E,
                                           const FilterView &F, const float *s_tr,
                                           const float4 *s_lc, const float *s_q, int base, int wr,
@@ -150,7 +140,8 @@ __device__ __forceinline__ void band_pass(const f32x16 (&acc)[2][2], const EpiLa
         }
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-          const float t = filter_table_at(tab[k], n_int, fmaf(lobs, wi[k], nw0[k]));
+          const float u = fmaf(lobs, wi[k], nw0[k]);
+          const float t = INSIDE ? filter_table_inside(tab[k], u) : filter_table_at(tab[k], n_int, u);
           sum[0][nb][k] += t * e;
           sum[1][nb][k] += t * q;
           if (MOM) {
@@ -200,7 +191,7 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   __shared__ GemmSmem<PREC> sm[2];
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
-  __shared__ int s_koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];   // K offset of each stage
+  __shared__ int s_koff[MAX_UNITS];   // K offset of each unit of the tile's stages
   // dynamic: filter transmissions [n_band][n_pts + 1], then with NEB the
   // members' ionization weights [point - u_lo][column] (n_u points at most)
   extern __shared__ float s_tr[];
@@ -233,7 +224,7 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   if (c_begin >= c_end) return;
   const int nk = pl->nk;
   const float zp1_min = pl->zp1_min, zp1_max = pl->zp1_max;
-  for (int t = threadIdx.x; t < nk; t += blockDim.x) s_koff[t] = pl->koff[t];
+  for (int t = threadIdx.x; t < C::UNITS * nk; t += blockDim.x) s_koff[t] = pl->koff[t];
   int u_lo = 0, n_uu = 1;
   if constexpr (NEB) {
     u_lo = pl->u_lo;
@@ -270,7 +261,9 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
         da_old[nb] = d.dust_a; dl_old[nb] = d.delta;
       }
     } else {
-      E.zp1[nb] = 1.0f; E.da[nb] = 0.0f; E.dl[nb] = 0.0f; E.bp[nb] = 0.0f;
+      // padding columns: zero weights; 1 + z inside the tile's range keeps
+      // their filter lookups inside the tables
+      E.zp1[nb] = zp1_min; E.da[nb] = 0.0f; E.dl[nb] = 0.0f; E.bp[nb] = 0.0f;
     }
   }
 
@@ -279,8 +272,16 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   const elem *st = AGED ? (const elem *)P.sa32
                         : (PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16);
   const int k_cols = AGED ? AGE_K : P.k_pad;
-  const elem *w = (const elem *)a.w_pad;
+  const int a_stride = NEB ? P.k_row : k_cols;     // table row length
+  const size_t a_elems = (size_t)P.n_wave_pad * a_stride;
+  const elem *w_tile = (const elem *)a.w_pad + (size_t)g0 * k_cols;
   const int n_comp = NCOMP * n_band;
+  const int ucol = stage_col();
+  // this thread's unit of stage s from the tile's unit list (-1: zeros)
+  auto unit = [&](int s) {
+    const int k = unit_piece<PREC>(s_koff, s, ucol);
+    return UnitSrc{max(k, 0), k, nullptr};
+  };
 
   for (int c = c_begin; c < c_end; ++c) {
     const int l0 = c * TILE_L;
@@ -296,6 +297,8 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
       for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
+    const GemmOps<PREC> ops =
+        gemm_ops<PREC>(st, a_elems, a_stride, linear_rows<PREC>(l0), w_tile, nvalid, k_cols);
 
     if constexpr (AGED) {
       f32x16 sed[2][2];
@@ -313,32 +316,33 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
         af.bp[nb] = E.bp[nb];
       }
       auto fold = [&](int ks) { af(ks, sed, acc, s_lc, wr, h); };
-      gemm_kloop<PREC>(sm, st, k_cols, l0, w, g0, a.s_count, nk, [&](int ks) { return s_koff[ks]; },
-                       wr, wc, lane, acc, fold);
+      gemm_kloop<PREC>(sm, ops, nk, unit, wr, wc, lane, acc, fold);
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = sed[mb][nb];
     } else if constexpr (NEB) {
-      // stage s: ionization point u_lo + s / nk, K block s_koff[s % nk]
-      gemm_kloop_ab<PREC>(sm, st, P.k_row, l0, w, k_cols, g0, a.s_count, nk * n_uu,
-                          [&](int s) {
-                            const int uu = s / nk;
-                            const int k = s_koff[s - uu * nk];
-                            return StageSrc{(u_lo + uu) * k_cols + k, k, s_pn + uu * TILE_G};
-                          },
-                          wr, wc, lane, acc);
-    } else {
-      gemm_kloop<PREC>(sm, st, k_cols, l0, w, g0, a.s_count, nk, [&](int ks) { return s_koff[ks]; },
+      // stage s: ionization point u_lo + s / nk, units of stage s % nk
+      gemm_kloop<PREC>(sm, ops, nk * n_uu,
+                       [&](int s) {
+                         const int uu = s / nk;
+                         const int k = unit_piece<PREC>(s_koff, s - uu * nk, ucol);
+                         return UnitSrc{(u_lo + uu) * k_cols + max(k, 0), k, s_pn + uu * TILE_G};
+                       },
                        wr, wc, lane, acc);
+    } else {
+      gemm_kloop<PREC>(sm, ops, nk, unit, wr, wc, lane, acc);
     }
     // (the loop's closing barrier makes s_lc, s_q and the filter tables visible)
 
     // ---- epilogue: attenuated SED x resampled transmission, summed over the
     // bands that can see this chunk
     // (wavelengths of the chunk are non-decreasing; padding repeats the last)
-    const unsigned bmask = __builtin_amdgcn_readfirstlane(
-        active_bands(F, zp1_min * s_lc[0].x, zp1_max * s_lc[TILE_L - 1].x));
+    const float o_lo = zp1_min * s_lc[0].x, o_hi = zp1_max * s_lc[TILE_L - 1].x;
+    const unsigned bmask = __builtin_amdgcn_readfirstlane(active_bands(F, o_lo, o_hi));
+    // bands every element of the chunk sees inside its table (every column's
+    // 1 + z lies in the tile's range, padding columns included)
+    const unsigned imask = __builtin_amdgcn_readfirstlane(interior_bands(F, o_lo, o_hi));
     const int b_lo = bmask ? __builtin_ctz(bmask) : 0;
     const int b_hi = bmask ? 31 - __builtin_clz(bmask) : -1;   // inclusive
     // partials are chunk-major: [chunk][galaxy][component]
@@ -377,19 +381,29 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
     }
     for (int base = b_lo; base <= b_hi;) {
       const int rem = b_hi - base + 1;
+      // a pass whose bands are all interior takes the lookup without clamp
       if (rem >= 3) {
         float sum[NCOMP][2][3];
-        band_pass<MOM, NCOMP, 3>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
+        if (((imask >> base) & 7u) == 7u)
+          band_pass<MOM, NCOMP, 3, true>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
+        else
+          band_pass<MOM, NCOMP, 3, false>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
         write_band_slots<NCOMP, 3>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride);
         base += 3;
       } else if (rem == 2) {
         float sum[NCOMP][2][2];
-        band_pass<MOM, NCOMP, 2>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
+        if (((imask >> base) & 3u) == 3u)
+          band_pass<MOM, NCOMP, 2, true>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
+        else
+          band_pass<MOM, NCOMP, 2, false>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
         write_band_slots<NCOMP, 2>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride);
         base += 2;
       } else {
         float sum[NCOMP][2][1];
-        band_pass<MOM, NCOMP, 1>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
+        if ((imask >> base) & 1u)
+          band_pass<MOM, NCOMP, 1, true>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
+        else
+          band_pass<MOM, NCOMP, 1, false>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
         write_band_slots<NCOMP, 1>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride);
         base += 1;
       }
@@ -411,12 +425,14 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
 }
 
 // One workgroup of TILE_G threads per tile: union of the members' windows,
-// redshifts and non-zero weight blocks, then the stage list, ascending in K
-// (a stage of KT ages covers KT / 16 blocks of a row and runs when any of them
-// holds a weight for some member).
+// redshifts and non-zero weight blocks, then the unit list, ascending in K:
+// a float32 unit is one 4-age block of a row and a bfloat16 unit two (16
+// bytes of the weight row either way), kept when it holds a weight for some
+// member; the age-major layout takes the four units of every age below the
+// highest non-zero one.  The list is padded with -1 (zero units) to whole
+// stages of four units.
 template <int PREC>
 __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
-  using C = GemmCfg<PREC>;
   // window lo, window hi, min and max of (1+z) as float bits (positive floats
   // order like their bit patterns)
   __shared__ int s_tile[7];   // + highest non-zero age (age-major stages), ionization points
@@ -427,9 +443,8 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
   if (threadIdx.x == 0) {
     s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0; s_tile[4] = 0;
     s_tile[5] = a.ion ? 1 << 30 : 0; s_tile[6] = 0;
-#pragma unroll
-    for (int w = 0; w < KBLOCK_WORDS; ++w) s_kblk[w] = 0u;
   }
+  if (threadIdx.x < KBLOCK_WORDS) s_kblk[threadIdx.x] = 0u;
   __syncthreads();
   if ((int)threadIdx.x < nvalid) {
     const GalaxyRange r = a.range[a.s_begin + g0 + threadIdx.x];
@@ -449,32 +464,55 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
       if (r.kblk[w]) atomicOr(&s_kblk[w], r.kblk[w]);
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x >= 64) return;   // wave 0 writes the plan
+  const int lane = threadIdx.x;
   TilePlan *pl = a.plan + tile;
+  const int n_met = a.ssp.n_met;
+  // candidate unit c: age-major (age c / 2, slots 8 (c % 2) ..); float32
+  // (row c / 12, 8 ages from 8 (c % 12): 4-age blocks 2 (c % 12) and + 1,
+  // both in mask word c % 12); bfloat16 (row c / 6, 16 ages from 16 (c % 6):
+  // mask words 2 (c % 6) and + 1)
+  constexpr int UNITS_PER_ROW = AGE_PAD / GemmCfg<PREC>::UNIT_K;   // 12 or 6
+  const int n_cand = a.age_dust ? 2 * min(s_tile[4], AGE_PAD) : n_met * UNITS_PER_ROW;
   int n = 0;
-  if (a.age_dust) {
-    // age-major: one stage per age that holds a weight for some member
-    for (; n < min(s_tile[4], AGE_PAD); ++n) pl->koff[n] = n * AGE_MET_SLOTS;
-  } else {
-    constexpr int BPS = C::KT / KBLOCK_AGES;   // blocks per stage
-    for (int j = 0; j < a.ssp.n_met; ++j)
-      for (int st = 0; st < AGE_PAD / C::KT; ++st) {
-        bool any = false;
-        for (int u = 0; u < BPS; ++u) {
-          const int blk = st * BPS + u;
-          any |= (s_kblk[blk >> 1] >> (16 * (blk & 1) + j)) & 1u;
-        }
-        if (any) pl->koff[n++] = j * AGE_PAD + st * C::KT;
+  for (int base = 0; base < n_cand; base += 64) {
+    const int c = base + lane;
+    bool keep = false;
+    int koff = 0;
+    if (c < n_cand) {
+      if (a.age_dust) {
+        keep = true;
+        koff = c * 8;   // age c / 2 at column 16 (c / 2), slots 8 (c % 2) ..
+      } else if (PREC == DSPS_BF16) {
+        const int j = c / UNITS_PER_ROW, q = c % UNITS_PER_ROW;
+        const unsigned m2 = s_kblk[2 * q] | s_kblk[2 * q + 1];
+        keep = ((m2 >> j) | (m2 >> (16 + j))) & 1u;
+        koff = j * AGE_PAD + 16 * q;
+      } else {
+        const int j = c / UNITS_PER_ROW, q = c % UNITS_PER_ROW;
+        keep = ((s_kblk[q] >> j) | (s_kblk[q] >> (16 + j))) & 1u;
+        koff = j * AGE_PAD + 8 * q;
       }
+    }
+    const unsigned long long m = __ballot(keep);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (keep) pl->koff[n + before] = koff;
+    n += __popcll(m);
   }
-  const int c_first = s_tile[0] / TILE_L;
-  pl->c_first = c_first;
-  pl->c_last = max((s_tile[1] + TILE_L - 1) / TILE_L, c_first);   // exclusive
-  pl->nk = n;
-  pl->zp1_min = __int_as_float(s_tile[2]);
-  pl->zp1_max = __int_as_float(s_tile[3]);
-  pl->u_lo = s_tile[5];
-  pl->u_hi = s_tile[6];
+  constexpr int UPS = GemmCfg<PREC>::UNITS;     // units per stage
+  const int n_pad = (n + UPS - 1) / UPS * UPS;
+  if (n + lane < n_pad) pl->koff[n + lane] = -1;
+  if (lane == 0) {
+    const int c_first = s_tile[0] / TILE_L;
+    pl->c_first = c_first;
+    pl->c_last = max((s_tile[1] + TILE_L - 1) / TILE_L, c_first);   // exclusive
+    pl->nk = n_pad / UPS;
+    pl->n_units = n;
+    pl->zp1_min = __int_as_float(s_tile[2]);
+    pl->zp1_max = __int_as_float(s_tile[3]);
+    pl->u_lo = s_tile[5];
+    pl->u_hi = s_tile[6];
+  }
 }
 
 int launch_tile_plan(const MagsLaunch &a, hipStream_t stream) {

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   __shared__ float4 s_lc[AGED ? TILE_L : 1];
   __shared__ GemmSmem<PREC> sm[2];
   __shared__ float s_pn[NEB ? DSPS_MAX_ION * TILE_G : 1];
-  __shared__ int s_koff[DSPS_MAX_MET * KBLOCKS_PER_ROW];   // K offset of each stage
+  __shared__ int s_koff[MAX_UNITS];   // K offset of each unit of the tile's stages
   const int chunk = a.n_sel ? a.chunk_list[blockIdx.x] : (int)blockIdx.x;
   const int tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -39,7 +39,17 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   const int g0 = tile * TILE_G;
   const elem *st = AGED ? (const elem *)P.sa32
                         : (PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16);
-  const elem *w = (const elem *)a.w_pad;
+  const int k_cols = AGED ? AGE_K : P.k_pad;
+  const int a_stride = NEB ? P.k_row : k_cols;
+  const int nvalid = min(TILE_G, a.g_count - g0);
+  const GemmOps<PREC> ops =
+      gemm_ops<PREC>(st, (size_t)P.n_wave_pad * a_stride, a_stride, linear_rows<PREC>(l0),
+                     (const elem *)a.w_pad + (size_t)g0 * k_cols, nvalid, k_cols);
+  const int ucol = stage_col();
+  auto unit = [&](int s) {
+    const int k = unit_piece<PREC>(s_koff, s, ucol);
+    return UnitSrc{max(k, 0), k, nullptr};
+  };
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -51,10 +61,9 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
 
   const TilePlan *pl = a.plan + tile;
   const int nk = pl->nk;
-  for (int t = threadIdx.x; t < nk; t += blockDim.x) s_koff[t] = pl->koff[t];
+  for (int t = threadIdx.x; t < C::UNITS * nk; t += blockDim.x) s_koff[t] = pl->koff[t];
   if constexpr (NEB) {
     // every member's weight of each of the tile's ionization points
-    const int nvalid = min(TILE_G, a.g_count - g0);
     const int u_lo = pl->u_lo, n_uu = pl->u_hi - pl->u_lo + 1;
     for (int t = threadIdx.x; t < n_uu * TILE_G; t += blockDim.x) {
       const int uu = t / TILE_G, col = t - uu * TILE_G;
@@ -71,13 +80,13 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
     }
     __syncthreads();
     const int kp = P.k_pad;
-    gemm_kloop_ab<PREC>(sm, st, P.k_row, l0, w, kp, g0, a.g_count, nk * n_uu,
-                        [&](int s) {
-                          const int uu = s / nk;
-                          const int k = s_koff[s - uu * nk];
-                          return StageSrc{(u_lo + uu) * kp + k, k, s_pn + uu * TILE_G};
-                        },
-                        wr, wc, lane, acc);
+    gemm_kloop<PREC>(sm, ops, nk * n_uu,
+                     [&](int s) {
+                       const int uu = s / nk;
+                       const int k = unit_piece<PREC>(s_koff, s - uu * nk, ucol);
+                       return UnitSrc{(u_lo + uu) * kp + max(k, 0), k, s_pn + uu * TILE_G};
+                     },
+                     wr, wc, lane, acc);
   } else if constexpr (AGED) {
     if (threadIdx.x < TILE_L) s_lc[threadIdx.x] = P.lconst[l0 + threadIdx.x];
     AgeFold af{nk, a.age_young, a.age_old, a.dust_pivot, a.dust_width, P.lg_age, {}, {}, {}, {}, {}};
@@ -102,16 +111,15 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) sed[mb][nb][r] = 0.0f;
     __syncthreads();
-    gemm_kloop<PREC>(sm, st, AGE_K, l0, w, g0, a.g_count, nk, [&](int ks) { return s_koff[ks]; },
-                     wr, wc, lane, acc, [&](int ks) { af(ks, sed, acc, s_lc, wr, h); });
+    gemm_kloop<PREC>(sm, ops, nk, unit, wr, wc, lane, acc,
+                     [&](int ks) { af(ks, sed, acc, s_lc, wr, h); });
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = sed[mb][nb];
   } else {
     __syncthreads();
-    gemm_kloop<PREC>(sm, st, P.k_pad, l0, w, g0, a.g_count, nk, [&](int ks) { return s_koff[ks]; },
-                     wr, wc, lane, acc);
+    gemm_kloop<PREC>(sm, ops, nk, unit, wr, wc, lane, acc);
   }
 
 #pragma unroll

@@ -123,6 +123,50 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
   }
 }
 
+// Highest metallicity row in a galaxy's MDF support: bins whose lower edge
+// lies above the largest centre over ages plus 3 sigma have weight zero and
+// zero derivative at every age (the MDF is clipped at +-3 sigma).
+__device__ __forceinline__ int support_top_row(const SspView &P, double lgmet, bool transition,
+                                               double lgmet_old, double slope, double pivot,
+                                               double width, double sigma) {
+  // the centre is monotone in age: its largest value sits at an end of the grid
+  const double m0 = mdf_centre(P.lg_age[0], lgmet, transition, lgmet_old, slope, pivot, width);
+  const double m1 = mdf_centre(P.lg_age[P.n_age - 1], lgmet, transition, lgmet_old, slope, pivot,
+                               width);
+  const double top = fmax(m0, m1) + 3.0 * sigma;
+  int j_hi = 0;   // rows 1.. start at interior edge j
+  for (int j = 1; j < P.n_met; ++j) j_hi += P.met_edges[j] <= top;
+  return j_hi;
+}
+
+// Lowest metallicity row of a galaxy's MDF support: bins below it have
+// weight zero and zero derivative at every age, and the CDF is exactly 0 at
+// its lower edge, so a galaxy's metallicity cotangents start there.
+__device__ __forceinline__ int support_bottom_row(const SspView &P, double lgmet, bool transition,
+                                                  double lgmet_old, double slope, double pivot,
+                                                  double width, double sigma) {
+  const double m0 = mdf_centre(P.lg_age[0], lgmet, transition, lgmet_old, slope, pivot, width);
+  const double m1 = mdf_centre(P.lg_age[P.n_age - 1], lgmet, transition, lgmet_old, slope, pivot,
+                               width);
+  const double bottom = fmin(m0, m1) - 3.0 * sigma;
+  int j_lo = 0;
+  for (int j = 1; j < P.n_met; ++j) j_lo += P.met_edges[j] <= bottom;
+  return j_lo;
+}
+
+// Ages a galaxy observed at cosmic time t_obs needs: the first age-bin edge e
+// whose time t_obs - edge is not after t_table[0].  Bins from e on form no
+// mass (both their edges lie before the time grid) and have no sensitivity
+// to any parameter, so their cotangents are never used.
+__device__ __forceinline__ int ages_with_mass(const SspView &P, double t_obs, double t0) {
+  int lo = 0, hi = P.n_age;      // the last edge is +inf: always a candidate
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (!(t_obs - P.age_edges[mid] > t0)) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
 // Wbar[s, k] = sum_l Lbar[s, l] L_SSP[k, l] over the tile's wavelength window.
 // Rows (M) are SSP rows k, columns (N) galaxies, reduction over wavelength.
 // Rows above every member's MDF support are not needed: a metallicity bin
@@ -173,17 +217,11 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
       atomicMin(&s_urange[0], a.ion[s].u_lo);
       atomicMax(&s_urange[1], a.ion[s].u_hi);
     }
-    // the centre is monotone in age: its largest value sits at an end of the grid
     const int g = a.perm[s];
     const bool transition = a.lgmet_old != nullptr;
-    const double lgmet = (double)a.lgmet[g], old = transition ? (double)a.lgmet_old[g] : 0.0;
-    const double m0 = mdf_centre(P.lg_age[0], lgmet, transition, old, a.slope, a.pivot, a.mdf_width);
-    const double m1 = mdf_centre(P.lg_age[P.n_age - 1], lgmet, transition, old, a.slope, a.pivot,
-                                 a.mdf_width);
-    const double top = fmax(m0, m1) + 3.0 * (double)a.sigma_z[g];
-    int j_hi = 0;   // rows 1.. start at interior edge j
-    for (int j = 1; j < P.n_met; ++j) j_hi += P.met_edges[j] <= top;
-    atomicMax(&s_jhi, j_hi);
+    atomicMax(&s_jhi, support_top_row(P, (double)a.lgmet[g], transition,
+                                      transition ? (double)a.lgmet_old[g] : 0.0, a.slope, a.pivot,
+                                      a.mdf_width, (double)a.sigma_z[g]));
   }
   __syncthreads();
   const int l_begin = (s_tile[0] / TILE_L) * TILE_L;
@@ -258,13 +296,17 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
       }
     };
     const int slab = P.sk_rows * nwp;   // one point's block of the adjoint table
-    gemm_kloop_ab<DSPS_FP32>(sm, P.sk32, nwp, k0, a.lbar, nwp, g0, a.s_count, nk * n_uu,
-                             [&](int s) {
-                               const int uu = s / nk;
-                               const int l = l_begin + (s - uu * nk) * C::KT;
-                               return StageAB{(u_lo + uu) * slab + l, l};
-                             },
-                             wr, wc, lane, acc, fold);
+    const GemmOps<DSPS_FP32> ops =
+        gemm_ops<DSPS_FP32>(P.sk32, (size_t)P.n_u * slab, nwp, linear_rows<DSPS_FP32>(k0),
+                            a.lbar + (size_t)g0 * nwp, nvalid, nwp);
+    const int ucol = stage_col();
+    gemm_kloop<DSPS_FP32>(sm, ops, nk * n_uu,
+                          [&](int s) {
+                            const int uu = s / nk;
+                            const int l = contiguous_piece<DSPS_FP32>(l_begin, s - uu * nk, ucol);
+                            return UnitSrc{(u_lo + uu) * slab + l, l, nullptr};
+                          },
+                          wr, wc, lane, acc, fold);
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -296,8 +338,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
       }
     }
   } else {
-    gemm_kloop<DSPS_FP32>(sm, P.sk32, nwp, k0, a.lbar, g0, a.s_count, nk,
-                          [=](int ks) { return l_begin + ks * C::KT; }, wr, wc, lane, acc);
+    static_assert(NEB, "the plain transposed contraction is k_vjp_wbar_rows");
   }
 
   const int kp = P.k_pad;
@@ -315,6 +356,135 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
         *reinterpret_cast<float4 *>(out + row0) =
             make_float4(acc[mb][nb][4 * r4], acc[mb][nb][4 * r4 + 1], acc[mb][nb][4 * r4 + 2],
                         acc[mb][nb][4 * r4 + 3]);
+      }
+  }
+}
+
+// The transposed contraction without the ionization axis, over only the rows
+// a tile needs.  A galaxy needs, for each age with mass (ages_with_mass),
+// the plain Wbar of the lowest row of its MDF support and the differences
+// Wbar[j] - Wbar[j-1] of the rows above it up to the top of the support;
+// rows outside the support carry no weight and no derivative.  Per tile: the
+// plain rows j_lo .. j_lo' (the members' lowest support rows, usually one),
+// from the plain K-major table, then the differenced rows j_lo + 1 .. j_top,
+// each for the ages below the members' largest count with mass (A).  Needed
+// row r counts the plain rows first: (j_lo + r / A, r % A), then the
+// differenced ones; block (tile, kb) computes r in [128 kb, 128 kb + 128),
+// its A rows gathered from the two tables, so the work follows the tile's
+// metallicity and age support.  Plain rows are stored (in wabs) only for the
+// members whose lowest row they are.  All blocks of a tile run on one XCD,
+// where its Lbar rows are read into one L2.  A galaxy's cotangents do not
+// depend on its tile mates: each needed value is the same dot product
+// whatever the tile, and stages outside its own window add exact zeros.
+// Most row blocks a tile can need: plain rows for every distinct lowest row
+// plus the differenced rows above the lowest, at most 2 n_met - 1 rows per age.
+__host__ __device__ inline int wbar_row_blocks(int n_met, int n_age) {
+  return ((2 * n_met - 1) * n_age + TILE_L - 1) / TILE_L;
+}
+
+__global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar_rows(VjpLaunch a) {
+  using C = GemmCfg<DSPS_FP32>;
+  __shared__ GemmSmem<DSPS_FP32> sm[2];
+  // window lo, window hi, lowest and highest j_lo, highest j_top, ages with mass
+  __shared__ int s_tile[6];
+  __shared__ int s_jlo[TILE_G];
+  const SspView P = a.ssp;
+  int tile, kb;
+  xcd_tile_group(blockIdx.x, wbar_row_blocks(P.n_met, P.n_age), tile, kb);
+  const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
+  if (tile >= n_tiles) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
+  const int g0 = tile * TILE_G;
+  const int nvalid = min(TILE_G, a.s_count - g0);
+  const int nwp = P.n_wave_pad;
+
+  if (threadIdx.x == 0) {
+    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 1 << 30; s_tile[3] = 0; s_tile[4] = 0;
+    s_tile[5] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < nvalid) {
+    const int s = a.s_begin + g0 + threadIdx.x;
+    const GalaxyRange r = a.range[s];
+    const int g = a.perm[s];
+    const bool transition = a.lgmet_old != nullptr;
+    const double lgmet = (double)a.lgmet[g], old = transition ? (double)a.lgmet_old[g] : 0.0;
+    const double sig = (double)a.sigma_z[g];
+    const int j_lo = support_bottom_row(P, lgmet, transition, old, a.slope, a.pivot, a.mdf_width, sig);
+    const int j_top = support_top_row(P, lgmet, transition, old, a.slope, a.pivot, a.mdf_width, sig);
+    s_jlo[threadIdx.x] = j_lo;
+    atomicMin(&s_tile[0], r.win_lo);
+    atomicMax(&s_tile[1], r.win_hi);
+    atomicMin(&s_tile[2], j_lo);
+    atomicMax(&s_tile[3], j_lo);
+    atomicMax(&s_tile[4], j_top);
+    atomicMax(&s_tile[5], ages_with_mass(P, a.t_obs[s], a.t_table[0]));
+  }
+  __syncthreads();
+  const int n_ages = s_tile[5];
+  const int j_lo = s_tile[2];
+  const int n_plain = (s_tile[3] - j_lo + 1) * n_ages;     // plain rows come first
+  const int n_rows = n_plain + max(s_tile[4] - j_lo, 0) * n_ages;
+  const int r0 = kb * TILE_L;
+  if (r0 >= n_rows) return;      // the whole block: nothing needed here
+  const int l_begin = (s_tile[0] / TILE_L) * TILE_L;
+  const int l_end = ((s_tile[1] + TILE_L - 1) / TILE_L) * TILE_L;
+  // needed row r -> metallicity row j and age i
+  auto row_of = [&](int r, int &j, int &i) {
+    const int q = r < n_plain ? r : r - n_plain;
+    j = j_lo + q / n_ages + (r < n_plain ? 0 : 1);
+    i = q % n_ages;
+  };
+  // A row of needed row r: the plain table follows the differenced one
+  // (rows past the needed ones read row 0 and are never stored)
+  ARows<DSPS_FP32> ar;
+#pragma unroll
+  for (int v = 0; v < StageRegs<DSPS_FP32>::NV; ++v) {
+    const int r = r0 + stage_row<DSPS_FP32>(v);
+    int j, i;
+    row_of(r, j, i);
+    ar.r[v] = r < n_rows ? (r < n_plain ? P.sk_rows : 0) + j * AGE_PAD + i : 0;
+  }
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mb][nb][r] = 0.0f;
+  const int nk = l_end > l_begin ? (l_end - l_begin) / C::KT : 0;
+  // the differenced and the plain K-major tables, one after the other
+  const GemmOps<DSPS_FP32> ops =
+      gemm_ops<DSPS_FP32>(P.sk32, (size_t)2 * P.sk_rows * nwp, nwp, ar, a.lbar + (size_t)g0 * nwp,
+                          nvalid, nwp);
+  const int ucol = stage_col();
+  gemm_kloop<DSPS_FP32>(sm, ops, nk,
+                        [=](int ks) {
+                          const int l = contiguous_piece<DSPS_FP32>(l_begin, ks, ucol);
+                          return UnitSrc{l, l, nullptr};
+                        },
+                        wr, wc, lane, acc);
+
+  const int kp = P.k_pad;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int col = wc * 64 + nb * 32 + (lane & 31);
+    if (col >= nvalid) continue;
+    const int my_lo = s_jlo[col];
+    float *out = a.wbar + (size_t)(g0 + col) * kp;
+    float *out_abs = a.wabs + (size_t)(g0 + col) * AGE_PAD;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int r = r0 + wr * 64 + mb * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
+        if (r >= n_rows) continue;
+        int j, i;
+        row_of(r, j, i);
+        if (r >= n_plain) out[j * AGE_PAD + i] = acc[mb][nb][q];
+        else if (j == my_lo) out_abs[i] = acc[mb][nb][q];
       }
   }
 }
@@ -569,7 +739,9 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   const SspView P = a.ssp;
   const int n_age = P.n_age, n_met = P.n_met;
   const double z = (double)a.z[g];
-  const double t_obs = vjp_age_at_z(z, a.cosmo, a.gl, lane);
+  // the per-galaxy scalar pass's t(z), so that the rows needed here are the
+  // rows the transposed contraction computed
+  const double t_obs = a.t_obs ? a.t_obs[s] : vjp_age_at_z(z, a.cosmo, a.gl, lane);
 
   double pa = 0, ptau = 0, palpha = 0, pq = 0, ptq = 0;
   if (a.sfr) {
@@ -635,17 +807,36 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   // metallicity-differenced table.  Bin j spans edges j and j+1,
   // P_j = C(u_{j+1}) - C(u_j); the cotangent of the CDF at an interior edge j
   // is Pbar_{j-1} - Pbar_j = -m_age Y[j], and m_age_bar = sum_j Wbar[j] P_j.
+  // Only rows up to the top of the MDF support and ages with mass are read:
+  // above the support P_j = 0 and the density at edge j is 0, and ages past
+  // ages_with_mass have m_age = 0 and a cotangent that reaches no SFR node,
+  // so what they would add is exactly zero (and the transposed contraction
+  // need not compute those rows).
+  // With wabs the sum starts at the lowest support row j_lo from its plain
+  // Wbar (the CDF is 0 at that row's lower edge, so its density term is 0);
+  // otherwise row 0 of wb is plain and the sum starts there.
+  const int j_top = support_top_row(P, lgmet, transition, lgmet_old, a.slope, a.pivot,
+                                    a.mdf_width, sig);
+  const int j_lo = a.wabs ? support_bottom_row(P, lgmet, transition, lgmet_old, a.slope, a.pivot,
+                                               a.mdf_width, sig)
+                          : 0;
+  const float *wab = a.wabs ? a.wabs + (size_t)local * AGE_PAD : nullptr;
+  const int n_live = ages_with_mass(P, t_obs, tt[0]);
   for (int i = lane; i < n_age; i += 64) {
+    if (i >= n_live) {
+      mbar[i] = 0.0;
+      continue;
+    }
     const double mu = mdf_centre(P.lg_age[i], lgmet, transition, lgmet_old, a.slope, a.pivot,
                                  a.mdf_width);
     const double t_i = transition ? mdf_transition(P.lg_age[i], a.pivot, a.mdf_width) : 0.0;
     const double m_i = mage[i];
     double mb = 0.0, wcum = 0.0;
     double c_lo = 0.0, u_lo = 0.0;    // CDF and u at edge j (the lower edge of bin j)
-    for (int j = 0; j < n_met; ++j) {
-      const double y = (double)wb[j * AGE_PAD + i];
+    for (int j = j_lo; j <= j_top; ++j) {
+      const double y = (double)(j == j_lo && wab ? wab[i] : wb[j * AGE_PAD + i]);
       wcum += y;                       // Wbar[j]
-      if (j >= 1) {
+      if (j > j_lo) {
         const double ubar = -m_i * y * triweight_pdf(u_lo);
         d_lgmet -= ubar * inv_sig * (1.0 - t_i);
         d_old -= ubar * inv_sig * t_i;
@@ -827,8 +1018,9 @@ int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
       hipLaunchKernelGGL(k_vjp_wbar<true>, dim3(a.ssp.sk_rows / TILE_L, tiles), dim3(GEMM_THREADS), 0,
                          stream, a);
     else
-      hipLaunchKernelGGL(k_vjp_wbar<false>, dim3(a.ssp.sk_rows / TILE_L, tiles), dim3(GEMM_THREADS), 0,
-                         stream, a);
+      hipLaunchKernelGGL(k_vjp_wbar_rows,
+                         dim3((tiles + 7) / 8 * 8 * wbar_row_blocks(a.ssp.n_met, a.ssp.n_age)),
+                         dim3(GEMM_THREADS), 0, stream, a);
   } else {
     const size_t lds = sizeof(double) * (a.n_t + WEIGHT_WAVES * (2 * a.n_t + 3 * AGE_PAD + 2));
     if (lds > 65536) {

@@ -499,21 +499,14 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
     nzr = mdf_rows<MDF_PAD_F32>(L, (float *)a.w_pad + (size_t)local * P.k_pad);
   else
     nzr = mdf_rows<MDF_USER>(L, a.w_user + (size_t)g * n_met * n_age);
-  // non-zero (16-age block, row) mask: block b holds the ages of lanes
-  // 8b .. 8b + 7; after three shifted ORs lane 8b + 7 holds their union
+  // non-zero (4-age block, row) mask: block b holds the ages of lanes 2b and
+  // 2b + 1, so after one shifted OR lane 2b + 1 holds its rows; word w packs
+  // blocks 2w (low half) and 2w + 1 (high half), which lane 4w + 3 joins
+  // from lane 4w + 1 and itself and stores
   nzr |= dpp_u32<DPP_ROW_SHR + 1>(nzr);
-  nzr |= dpp_u32<DPP_ROW_SHR + 2>(nzr);
-  nzr |= dpp_u32<DPP_ROW_SHR + 4>(nzr);
-  unsigned kblk[KBLOCK_WORDS];
-#pragma unroll
-  for (int w = 0; w < KBLOCK_WORDS; ++w)
-    kblk[w] = (unsigned)__builtin_amdgcn_readlane((int)nzr, 16 * w + 7) |
-              ((unsigned)__builtin_amdgcn_readlane((int)nzr, 16 * w + 15) << 16);
-
-  if (a.range && lane == 0) {
-#pragma unroll
-    for (int w = 0; w < KBLOCK_WORDS; ++w) a.range[s].kblk[w] = kblk[w];
-  }
+  const unsigned low = dpp_u32<DPP_ROW_SHR + 2>(nzr);
+  if (a.range && (lane & 3) == 3 && (lane >> 2) < KBLOCK_WORDS)
+    a.range[s].kblk[lane >> 2] = (low & 0xffffu) | (nzr << 16);
 }
 
 int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
@@ -749,9 +742,12 @@ __global__ __launch_bounds__(256) void k_pack_table(const T *__restrict__ src, i
 // returns Wbar[0] and the differences Wbar[j] - Wbar[j-1] directly, which are
 // what the metallicity-weight gradients need (adjacent metallicity rows are
 // nearly equal, so differencing Wbar afterwards would cancel in float32).
-// Rows are padded to sk_rows and wavelengths to n_wave_pad with zeros.
+// Rows are padded to sk_rows and wavelengths to n_wave_pad with zeros.  With
+// differenced == 0 the rows are the plain L[met, age, l] (the adjoint starts
+// each galaxy's sum at the lowest row of its metallicity support from there).
 __global__ void k_pack_table_kmajor(const float *__restrict__ src, int n_age, int n_wave,
-                                    int n_wave_pad, int k_pad, int sk_rows, float *__restrict__ dst) {
+                                    int n_wave_pad, int k_pad, int sk_rows, int differenced,
+                                    float *__restrict__ dst) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)sk_rows * n_wave_pad) return;
   const int k = (int)(idx / n_wave_pad), l = (int)(idx % n_wave_pad);
@@ -759,7 +755,7 @@ __global__ void k_pack_table_kmajor(const float *__restrict__ src, int n_age, in
   double v = 0.0;
   if (k < k_pad && age < n_age && l < n_wave) {
     v = (double)src[((size_t)met * n_age + age) * n_wave + l];
-    if (met > 0) v -= (double)src[((size_t)(met - 1) * n_age + age) * n_wave + l];
+    if (differenced && met > 0) v -= (double)src[((size_t)(met - 1) * n_age + age) * n_wave + l];
   }
   dst[idx] = (float)v;
 }
@@ -787,10 +783,11 @@ int launch_pack_table_age(const float *lum_rows, int n_met, int n_age, int n_wav
 }
 
 int launch_pack_table_kmajor(const float *lum_rows, int n_age, int n_wave, int n_wave_pad,
-                             int k_pad, int sk_rows, float *sk32, hipStream_t stream) {
+                             int k_pad, int sk_rows, int differenced, float *sk32,
+                             hipStream_t stream) {
   const size_t total = (size_t)sk_rows * n_wave_pad;
   hipLaunchKernelGGL(k_pack_table_kmajor, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                     stream, lum_rows, n_age, n_wave, n_wave_pad, k_pad, sk_rows, sk32);
+                     stream, lum_rows, n_age, n_wave, n_wave_pad, k_pad, sk_rows, differenced, sk32);
   return hip_fail(hipGetLastError(), "k_pack_table_kmajor launch");
 }
 

@@ -122,10 +122,10 @@ constexpr int KBLOCK_AGES = 4;
 constexpr int KBLOCKS_PER_ROW = AGE_PAD / KBLOCK_AGES;                  // 24
 constexpr int KBLOCK_WORDS = (DSPS_MAX_MET * KBLOCKS_PER_ROW + 31) / 32;  // 12
 static_assert(DSPS_MAX_MET <= 16 && KBLOCKS_PER_ROW == 2 * KBLOCK_WORDS, "block-major mask layout");
-// K units of a tile's stage list: one per (row, block) for float32, per
-// (row, pair of blocks) for bfloat16, four per age for the age-major layout.
-constexpr int MAX_UNITS = DSPS_MAX_MET * KBLOCKS_PER_ROW;               // 384
-static_assert(MAX_UNITS >= AGE_PAD * 4 && MAX_UNITS % 4 == 0, "unit list size");
+// K units of a tile's stage list: 8 ages of a row for float32 (two 4-age
+// blocks), 16 for bfloat16, two per age for the age-major layout.
+constexpr int MAX_UNITS = DSPS_MAX_MET * KBLOCKS_PER_ROW / 2;           // 192
+static_assert(MAX_UNITS >= AGE_PAD * 2 && MAX_UNITS % 2 == 0, "unit list size");
 
 struct GalaxyRange {
   int win_lo, win_hi;            // rest-wavelength index window [lo, hi) that any filter sees

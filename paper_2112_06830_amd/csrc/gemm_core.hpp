@@ -130,9 +130,9 @@ __device__ __forceinline__ GemmOps<PREC> gemm_ops(const typename GemmCfg<PREC>::
   return o;
 }
 
-// Where this thread's 16 bytes of a K stage come from: element offsets in
-// its A and B rows (b < 0: zeros) and, float32 only, factors of the B rows
-// applied as the stage is written to LDS (or null).  Thread t stages LDS
+// Where this thread's 16 bytes of a K stage come from: byte offsets in its A
+// and B rows (ZERO_UNIT_BYTES in B: zeros) and, float32 only, factors of the
+// B rows applied as the stage is written to LDS (or null).  Thread t stages LDS
 // unit c = t % 4 of each of its rows: in float32 piece c / 2 of K unit c % 2
 // (MFMA step s pairs LDS units s / 4 and 2 + s / 4), in bfloat16 piece c % 2
 // of K unit c / 2 (MFMA step s takes LDS units 2s and 2s + 1).
@@ -164,15 +164,20 @@ __device__ __forceinline__ int contiguous_piece(int k0, int s, int col) {
 // An offset past the end of every B resource (tile rows stay far below it).
 constexpr int ZERO_UNIT_BYTES = 0x40000000;
 
+// Byte offsets of a 16-byte piece at element offset k of both operands
+// (k < 0: a piece of zeros, read from the start of A and past the end of B).
+template <int PREC>
+__device__ __forceinline__ int2 piece_bytes(int k) {
+  constexpr int ES = (int)sizeof(typename GemmCfg<PREC>::elem);
+  return make_int2(max(k, 0) * ES, k < 0 ? ZERO_UNIT_BYTES : k * ES);
+}
+
 template <int PREC>
 __device__ __forceinline__ void load_units(StageRegs<PREC> &r, const GemmOps<PREC> &o, UnitSrc u) {
-  constexpr int ES = (int)sizeof(typename GemmCfg<PREC>::elem);
-  const int oa = u.a * ES;
-  const int ob = u.b < 0 ? ZERO_UNIT_BYTES : u.b * ES;
 #pragma unroll
   for (int v = 0; v < StageRegs<PREC>::NV; ++v) {
-    r.a[v] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(o.a, o.ra[v] + oa, 0, 0));
-    r.b[v] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(o.b, o.rb[v] + ob, 0, 0));
+    r.a[v] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(o.a, o.ra[v] + u.a, 0, 0));
+    r.b[v] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(o.b, o.rb[v] + u.b, 0, 0));
   }
 }
 

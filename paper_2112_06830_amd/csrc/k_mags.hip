@@ -191,7 +191,9 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   __shared__ GemmSmem<PREC> sm[2];
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
-  __shared__ int s_koff[MAX_UNITS];   // K offset of each unit of the tile's stages
+  // byte offsets (A, B) of each thread's 16-byte piece of every stage of the
+  // tile's unit list, by stage and piece
+  __shared__ int2 s_piece[4 * MAX_UNITS / GemmCfg<PREC>::UNITS];
   // dynamic: filter transmissions [n_band][n_pts + 1], then with NEB the
   // members' ionization weights [point - u_lo][column] (n_u points at most)
   extern __shared__ float s_tr[];
@@ -224,7 +226,8 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   if (c_begin >= c_end) return;
   const int nk = pl->nk;
   const float zp1_min = pl->zp1_min, zp1_max = pl->zp1_max;
-  for (int t = threadIdx.x; t < C::UNITS * nk; t += blockDim.x) s_koff[t] = pl->koff[t];
+  for (int t = threadIdx.x; t < STAGE_UNITS * nk; t += blockDim.x)
+    s_piece[t] = piece_bytes<PREC>(unit_piece<PREC>(pl->koff, t / STAGE_UNITS, t % STAGE_UNITS));
   int u_lo = 0, n_uu = 1;
   if constexpr (NEB) {
     u_lo = pl->u_lo;
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
     }
   }
 
-  // ---- K steps: the tile's non-zero weight blocks (s_koff), or with AGED
+  // ---- K steps: the tile's non-zero weight units (s_piece), or with AGED
   // its ages
   const elem *st = AGED ? (const elem *)P.sa32
                         : (PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16);
@@ -279,8 +282,8 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   const int ucol = stage_col();
   // this thread's unit of stage s from the tile's unit list (-1: zeros)
   auto unit = [&](int s) {
-    const int k = unit_piece<PREC>(s_koff, s, ucol);
-    return UnitSrc{max(k, 0), k, nullptr};
+    const int2 p = s_piece[STAGE_UNITS * s + ucol];
+    return UnitSrc{p.x, p.y, nullptr};
   };
 
   for (int c = c_begin; c < c_end; ++c) {
@@ -326,8 +329,9 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
       gemm_kloop<PREC>(sm, ops, nk * n_uu,
                        [&](int s) {
                          const int uu = s / nk;
-                         const int k = unit_piece<PREC>(s_koff, s - uu * nk, ucol);
-                         return UnitSrc{(u_lo + uu) * k_cols + max(k, 0), k, s_pn + uu * TILE_G};
+                         const int2 p = s_piece[STAGE_UNITS * (s - uu * nk) + ucol];
+                         return UnitSrc{(u_lo + uu) * k_cols * (int)sizeof(elem) + p.x, p.y,
+                                        s_pn + uu * TILE_G};
                        },
                        wr, wc, lane, acc);
     } else {

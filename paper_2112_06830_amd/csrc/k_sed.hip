@@ -29,7 +29,8 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   __shared__ float4 s_lc[AGED ? TILE_L : 1];
   __shared__ GemmSmem<PREC> sm[2];
   __shared__ float s_pn[NEB ? DSPS_MAX_ION * TILE_G : 1];
-  __shared__ int s_koff[MAX_UNITS];   // K offset of each unit of the tile's stages
+  // byte offsets (A, B) of each thread's 16-byte piece of every stage
+  __shared__ int2 s_piece[4 * MAX_UNITS / GemmCfg<PREC>::UNITS];
   const int chunk = a.n_sel ? a.chunk_list[blockIdx.x] : (int)blockIdx.x;
   const int tile = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -47,8 +48,8 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
                      (const elem *)a.w_pad + (size_t)g0 * k_cols, nvalid, k_cols);
   const int ucol = stage_col();
   auto unit = [&](int s) {
-    const int k = unit_piece<PREC>(s_koff, s, ucol);
-    return UnitSrc{max(k, 0), k, nullptr};
+    const int2 p = s_piece[STAGE_UNITS * s + ucol];
+    return UnitSrc{p.x, p.y, nullptr};
   };
 
   f32x16 acc[2][2];
@@ -61,7 +62,8 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
 
   const TilePlan *pl = a.plan + tile;
   const int nk = pl->nk;
-  for (int t = threadIdx.x; t < C::UNITS * nk; t += blockDim.x) s_koff[t] = pl->koff[t];
+  for (int t = threadIdx.x; t < STAGE_UNITS * nk; t += blockDim.x)
+    s_piece[t] = piece_bytes<PREC>(unit_piece<PREC>(pl->koff, t / STAGE_UNITS, t % STAGE_UNITS));
   if constexpr (NEB) {
     // every member's weight of each of the tile's ionization points
     const int u_lo = pl->u_lo, n_uu = pl->u_hi - pl->u_lo + 1;
@@ -83,8 +85,9 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
     gemm_kloop<PREC>(sm, ops, nk * n_uu,
                      [&](int s) {
                        const int uu = s / nk;
-                       const int k = unit_piece<PREC>(s_koff, s - uu * nk, ucol);
-                       return UnitSrc{(u_lo + uu) * kp + max(k, 0), k, s_pn + uu * TILE_G};
+                       const int2 p = s_piece[STAGE_UNITS * (s - uu * nk) + ucol];
+                       return UnitSrc{(u_lo + uu) * kp * (int)sizeof(elem) + p.x, p.y,
+                                      s_pn + uu * TILE_G};
                      },
                      wr, wc, lane, acc);
   } else if constexpr (AGED) {

@@ -304,7 +304,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
                           [&](int s) {
                             const int uu = s / nk;
                             const int l = contiguous_piece<DSPS_FP32>(l_begin, s - uu * nk, ucol);
-                            return UnitSrc{(u_lo + uu) * slab + l, l, nullptr};
+                            return UnitSrc{((u_lo + uu) * slab + l) * 4, l * 4, nullptr};
                           },
                           wr, wc, lane, acc, fold);
 #pragma unroll
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar_rows(VjpLaunch a) 
   gemm_kloop<DSPS_FP32>(sm, ops, nk,
                         [=](int ks) {
                           const int l = contiguous_piece<DSPS_FP32>(l_begin, ks, ucol);
-                          return UnitSrc{l, l, nullptr};
+                          return UnitSrc{l * 4, l * 4, nullptr};
                         },
                         wr, wc, lane, acc);
 

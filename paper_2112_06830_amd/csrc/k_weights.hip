@@ -212,7 +212,26 @@ struct MdfLane {
   int n_met, n_age, i0;
   double mu0, mu1, inv_sig, mage0, mage1;
   bool real0, real1;
+  double mu_lo, mu_hi;   // the galaxy's smallest and largest centre over ages
 };
+
+// CDF of the MDF at interior edge e for the lane's two ages, c0 and c1.  An
+// edge at least 3 sigma (plus a margin far above rounding) above every age's
+// centre has CDF exactly 1 for all of them, one as far below exactly 0: the
+// wave then skips the polynomial (the test is the same for all its lanes).
+__device__ __forceinline__ void mdf_edge_cdf(const MdfLane &L, double e, double &c0, double &c1) {
+  const double margin = 3.0 + 1e-9;
+  const bool all_one = (e - L.mu_hi) * L.inv_sig >= margin;
+  const bool all_zero = (e - L.mu_lo) * L.inv_sig <= -margin;
+  if (__builtin_amdgcn_readfirstlane((int)all_one)) {
+    c0 = c1 = 1.0;
+  } else if (__builtin_amdgcn_readfirstlane((int)all_zero)) {
+    c0 = c1 = 0.0;
+  } else {
+    c0 = triweight_cdf((e - L.mu0) * L.inv_sig);
+    c1 = triweight_cdf((e - L.mu1) * L.inv_sig);
+  }
+}
 enum { MDF_PAD_BF16, MDF_PAD_F32, MDF_USER };
 
 // W[j][i] = m_i (CDF(e_{j+1}) - CDF(e_j)) for the lane's two ages over every
@@ -225,11 +244,7 @@ __device__ __forceinline__ unsigned mdf_rows(const MdfLane &L, T *out) {
   double c_prev0 = 0.0, c_prev1 = 0.0;  // CDF at the lower edge of metallicity bin 0 (-inf)
   for (int j = 0; j < L.n_met; ++j) {
     double c_next0 = 1.0, c_next1 = 1.0;  // upper edge of the last bin is +inf
-    if (j < L.n_met - 1) {
-      const double edge = L.medge[j + 1];
-      c_next0 = triweight_cdf((edge - L.mu0) * L.inv_sig);
-      c_next1 = triweight_cdf((edge - L.mu1) * L.inv_sig);
-    }
+    if (j < L.n_met - 1) mdf_edge_cdf(L, L.medge[j + 1], c_next0, c_next1);
     const double wv0 = L.real0 ? L.mage0 * (c_next0 - c_prev0) : 0.0;
     const double wv1 = L.real1 ? L.mage1 * (c_next1 - c_prev1) : 0.0;
     c_prev0 = c_next0;
@@ -238,8 +253,10 @@ __device__ __forceinline__ unsigned mdf_rows(const MdfLane &L, T *out) {
     if (MODE == MDF_PAD_BF16) {
       const float2 ks = active ? *reinterpret_cast<const float2 *>(&L.ks[j * AGE_PAD + L.i0])
                                : make_float2(0.0f, 0.0f);
-      const uint32_t q0 = f32_to_bf16_rne((float)(wv0 * (double)ks.x));
-      const uint32_t q1 = f32_to_bf16_rne((float)(wv1 * (double)ks.y));
+      // the row scales are powers of two: scaling after the rounding to
+      // float32 is exact and equals rounding the scaled value
+      const uint32_t q0 = f32_to_bf16_rne((float)wv0 * ks.x);
+      const uint32_t q1 = f32_to_bf16_rne((float)wv1 * ks.y);
       if (active) *reinterpret_cast<uint32_t *>((uint16_t *)out + j * AGE_PAD + L.i0) = q0 | (q1 << 16);
       nz = ((q0 | q1) & 0x7FFFu) != 0;
     } else {
@@ -269,11 +286,7 @@ __device__ __forceinline__ int mdf_rows_age(const MdfLane &L, float *out) {
     float v0 = 0.0f, v1 = 0.0f;
     if (j < L.n_met) {
       double c_next0 = 1.0, c_next1 = 1.0;
-      if (j < L.n_met - 1) {
-        const double edge = L.medge[j + 1];
-        c_next0 = triweight_cdf((edge - L.mu0) * L.inv_sig);
-        c_next1 = triweight_cdf((edge - L.mu1) * L.inv_sig);
-      }
+      if (j < L.n_met - 1) mdf_edge_cdf(L, L.medge[j + 1], c_next0, c_next1);
       v0 = L.real0 ? (float)(L.mage0 * (c_next0 - c_prev0)) : 0.0f;
       v1 = L.real1 ? (float)(L.mage1 * (c_next1 - c_prev1)) : 0.0f;
       c_prev0 = c_next0;
@@ -482,7 +495,13 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
                                         a.pivot, a.mdf_width) : 0.0;
   const double mu1 = real1 ? mdf_centre(s_lgage[i0 + 1], lgmet, transition, lgmet_old, a.slope,
                                         a.pivot, a.mdf_width) : 0.0;
-  const MdfLane L{s_medge, s_ks, n_met, n_age, i0, mu0, mu1, inv_sig, mage0, mage1, real0, real1};
+  // the centre is monotone in age: its extremes sit at the first and last age
+  const double mu_a = mdf_centre(s_lgage[0], lgmet, transition, lgmet_old, a.slope, a.pivot,
+                                 a.mdf_width);
+  const double mu_b = mdf_centre(s_lgage[n_age - 1], lgmet, transition, lgmet_old, a.slope,
+                                 a.pivot, a.mdf_width);
+  const MdfLane L{s_medge, s_ks, n_met, n_age, i0, mu0, mu1, inv_sig, mage0, mage1, real0, real1,
+                  fmin(mu_a, mu_b), fmax(mu_a, mu_b)};
   if (a.w_pad && a.w_pad_age) {
     // age-major rows: the contraction needs only the highest non-zero age
     const int hi = mdf_rows_age(L, (float *)a.w_pad + (size_t)local * AGE_K);

@@ -565,34 +565,48 @@ def run_forward_model(P, steps, warmup, n_gal=100_000, seed=7):
     return res
 
 
-def run_serve(seconds=6.0, rate_hz=200.0):
+def run_serve(seconds=30.0, rate_hz=200.0):
     """Serving workload: Poisson arrivals at 200 req/s, N ~ logU[1e3, 1e5]
     galaxies per request with a per-request redshift range, 30% asking for
-    gradients (FP32), the rest forward on the BF16 table; then the same trace
-    served request by request on the plain FP32 path."""
+    gradients of the squared residual (FP32), the rest forward on the BF16
+    table; then the same trace served request by request through the plain
+    calls with the same arithmetic."""
     import torch
     import synth
     import paper_2112_06830_amd as P
     import paper_2112_06830_amd.serve as S
-    ssp = synth.make_ssp(n_wave=5994, wave_lo=9.0e2, wave_hi=2.5e4)
-    flt = synth.make_filters()
+    ssp = P.SspBlock.from_synth(synth.make_ssp(n_wave=5994, wave_lo=9.0e2, wave_hi=2.5e4),
+                                precisions=("fp32", "bf16"))
+    flt = P.FilterBank.from_synth(synth.make_filters())
+    t_table = synth.population.make_time_grid(100)
     n_req = int(seconds * rate_hz)
     arrivals, reqs = S.make_trace(n_req, rate_hz=rate_hz, seed=6)
-    eng = S.ServeEngine(ssp, flt, hbm_budget_bytes=48 << 30)
+    eng = S.ServeEngine(ssp, flt, t_table, hbm_budget_bytes=48 << 30)
     log("serve: capturing slot graphs")
     eng.warm()
+    log(f"serve: {eng.stats['captures_in_warm']} slots captured in {eng.stats['warm_s']:.1f} s; "
+        f"replaying {n_req} requests over {seconds:.0f} s")
     eng.start()
     wall = S.replay_trace(eng, arrivals, reqs, timeout_s=300)
     eng.stop()
     res = S.latency_summary(reqs, wall)
-    res["batches"] = eng.batches_run
-    res["gradient_requests"] = int(sum(r.grad for r in reqs))
-    log(f"serve: p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms, "
+    st = eng.stats
+    res["engine"] = {
+        "slots": st["captures_in_warm"], "warm_s": st["warm_s"],
+        "captures_in_loop": st["captures_in_loop"], "evictions": st["evictions"],
+        "batches": dict(st["batches"]),
+        "mean_batch_galaxies": {k: st["galaxies"][k] / max(st["batches"][k], 1) for k in S.KINDS},
+        "slot_fill": {k: st["galaxies"][k] / max(st["slot_galaxies"][k], 1) for k in S.KINDS},
+        "grad_batch_galaxies": eng.planner.batch_galaxies.get(S.KIND_GRAD)}
+    log(f"serve: p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms "
+        f"(fwd p99 {res['fwd']['p99_ms']:.1f}, grad p99 {res['grad']['p99_ms']:.1f}), "
         f"{res['throughput_galaxies_per_s']:.3e} gal/s")
     _, reqs2 = S.make_trace(n_req, rate_hz=rate_hz, seed=6)
-    base = S.serial_baseline(eng.ssp_h, eng.flt_h, eng.cosmo, eng.t_table, arrivals, reqs2)
-    log(f"serial fp32: p50 {base['p50_ms']:.1f} ms p99 {base['p99_ms']:.1f} ms")
-    res["request_by_request_fp32"] = base
+    log("serve: the same trace request by request")
+    base = S.serial_baseline(ssp, flt, eng.cosmo, t_table, arrivals, reqs2)
+    log(f"request by request: p50 {base['p50_ms']:.1f} ms p99 {base['p99_ms']:.1f} ms "
+        f"(fwd p99 {base['fwd']['p99_ms']:.1f}, grad p99 {base['grad']['p99_ms']:.1f})")
+    res["request_by_request"] = base
     torch.cuda.synchronize()
     return res
 
@@ -605,7 +619,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the BF16 1e6, forward+gradient and serving legs")
-    ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--pmc-pass", nargs="?", const="fp32_1e5", default=None,
                     choices=("fp32_1e5", "bf16_1e6", "grad_2e5"),
                     help="short run of one leg (default the FP32 forward) plus a calibration "

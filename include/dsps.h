@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define DSPS_ABI_VERSION 8
+#define DSPS_ABI_VERSION 9
 
 typedef enum {
   DSPS_OK = 0,
@@ -200,6 +200,19 @@ typedef struct { double om0, w0, h; } dsps_cosmo;
  *               triweight ionization distribution (Section 3.3, Eq. nebsed);
  *               required when the SSP handle has n_u > 1, ignored when it
  *               has one ionization point (all weight lands on it)
+ *   n_live      DEVICE pointer to one int, or NULL (all n_gal galaxies are
+ *               live).  Galaxies with index >= *n_live (clamped to
+ *               [0, n_gal]) are padding: no kernel reads their inputs and
+ *               their rows of every output are left as they were; the live
+ *               galaxies' results are bit for bit those of a call with
+ *               n_gal = *n_live.  The count is read on the device when the
+ *               kernels run, so a captured graph sized for n_gal serves any
+ *               smaller batch (n_gal only bounds the launch grids and the
+ *               workspace).  Honoured by dsps_weights, dsps_sed,
+ *               dsps_sed_ion_tangent, dsps_mags, dsps_mags_noalloc,
+ *               dsps_mags_ion_tangent, dsps_mags_vjp and
+ *               dsps_mags_residual_vjp; dsps_eqw_pop refuses a population
+ *               that sets it (DSPS_ERR_UNSUPPORTED).
  * ------------------------------------------------------------------------ */
 typedef struct {
   int n_gal, n_t;
@@ -213,6 +226,7 @@ typedef struct {
   const float *av_old, *delta_old;
   double dust_pivot, dust_width;
   const float *lgu, *sigma_u;
+  const int *n_live;
 } dsps_pop;
 
 /* Workspace bytes a call of kind `op` needs for this population shape and
@@ -370,6 +384,31 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
                   float *sigma_bar, float *av_bar, float *delta_bar, float *bump_bar,
                   float *av_old_bar, float *delta_old_bar, float *lgu_bar, float *sigma_u_bar,
                   void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Forward magnitudes and the reverse pass of the weighted squared residual
+ *   L = sum_g sum_b wt[g, b] (m[g, b] - target[g, b])^2,
+ * the chi-square term of the likelihood analyses that gradient-based
+ * optimisers and Hamiltonian Monte Carlo evaluate (Section 1), in one call:
+ * the ordering sort, the per-galaxy scalars and the weights run once, the
+ * forward contraction writes the magnitudes, and the reverse pass takes the
+ * cotangent mags_bar = (m - target) * (2 wt), formed in float32 on the device
+ * from the magnitudes just computed.
+ *   target  [n_gal*n_band] float32 target magnitudes, device
+ *   wt      [n_gal*n_band] float32 weights (for example 1 / sigma^2), or NULL
+ *           (all 1); a row of zeros removes a galaxy from the loss
+ *   mags    [n_gal*n_band] float32 output: the magnitudes, as dsps_mags
+ *   gradient outputs as dsps_mags_vjp (any may be NULL)
+ *   workspace  dsps_workspace_size(DSPS_OP_MAGS_VJP, ..., DSPS_FP32) bytes
+ * Float32 only.  mags and every gradient equal, bit for bit, dsps_mags
+ * (DSPS_FP32, with bands and moments) followed by dsps_mags_vjp with that
+ * cotangent; errors as those two calls (target NULL: DSPS_ERR_ARG). */
+int dsps_mags_residual_vjp(const dsps_ssp *ssp, const dsps_filters *filters,
+                           const dsps_cosmo *cosmo, const dsps_pop *pop, const float *target,
+                           const float *wt, float *mags, double *sfr_bar, double *sfh_params_bar,
+                           float *lgmet_bar, float *lgmet_old_bar, float *sigma_bar,
+                           float *av_bar, float *delta_bar, float *bump_bar, float *av_old_bar,
+                           float *delta_old_bar, float *lgu_bar, float *sigma_u_bar,
+                           void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Emission-line equivalent widths of rest-frame SEDs (Section 2.2.2, Eq. eqw).

@@ -27,7 +27,7 @@ EXPORTS = (
     "dsps_pop_summary_workspace", "dsps_pop_summary", "dsps_pop_summary_vjp",
     "dsps_ssp_create_neb", "dsps_ssp_ion_info", "dsps_eqw", "dsps_eqw_jvp",
     "dsps_sed_ion_tangent", "dsps_mags_ion_tangent", "dsps_eqw_pop", "dsps_eqw_pop_workspace",
-    "dsps_mags_noalloc",
+    "dsps_mags_noalloc", "dsps_mags_residual_vjp",
 )
 MAX_ION, MAX_LINES = 16, 16
 
@@ -56,6 +56,7 @@ class Pop(ctypes.Structure):
         ("av_old", ctypes.c_void_p), ("delta_old", ctypes.c_void_p),
         ("dust_pivot", ctypes.c_double), ("dust_width", ctypes.c_double),
         ("lgu", ctypes.c_void_p), ("sigma_u", ctypes.c_void_p),
+        ("n_live", ctypes.c_void_p),
     ]
 
 
@@ -102,6 +103,8 @@ def _declare(lib):
         "dsps_mags_noalloc": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P, P]),
         "dsps_mags_vjp": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), I, P, P, P,
                               P, P, P, P, P, P, P, P, P, P, P, P, P, S, P]),
+        "dsps_mags_residual_vjp": (I, [P, P, ctypes.POINTER(Cosmo), ctypes.POINTER(Pop), P, P, P,
+                                       P, P, P, P, P, P, P, P, P, P, P, P, P, S, P]),
         "dsps_quantize_bf16": (I, [P, I, I, P, P, P]),
         "dsps_pop_summary_workspace": (I, [I, I, ctypes.POINTER(S)]),
         "dsps_pop_summary": (I, [P, I, I, I, I, D, D, I, P, I, D, P, P, S, P]),

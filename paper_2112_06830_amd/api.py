@@ -167,6 +167,9 @@ class DevicePopulation:
     dust_width: float = 0.25
     lgu: torch.Tensor | None = None         # ionization distribution: centre, width
     sigma_u: torch.Tensor | None = None
+    # int32 [1] on the device, or None: galaxies at and past it are padding
+    # (not read, their output rows left as they were)
+    n_live: torch.Tensor | None = None
 
     @property
     def n_gal(self):
@@ -185,7 +188,8 @@ class DevicePopulation:
                      _ptr(self.z), _ptr(self.lgmet), _ptr(self.sigma_z), _ptr(self.av),
                      _ptr(self.delta), _ptr(self.bump), self.lgmet_slope, self.lg_age_pivot,
                      _ptr(self.lgmet_old), self.mdf_width, _ptr(self.av_old), _ptr(self.delta_old),
-                     self.dust_pivot, self.dust_width, _ptr(self.lgu), _ptr(self.sigma_u))
+                     self.dust_pivot, self.dust_width, _ptr(self.lgu), _ptr(self.sigma_u),
+                     _ptr(self.n_live))
 
     @classmethod
     def from_synth(cls, pop, device="cuda", sfr=None, use_params=False):
@@ -219,7 +223,8 @@ class DevicePopulation:
         return DevicePopulation(self.t_table, sfr, None, self.z, self.lgmet, self.sigma_z, self.av,
                                 self.delta, self.bump, self.lgmet_slope, self.lg_age_pivot,
                                 self.lgmet_old, self.mdf_width, self.av_old, self.delta_old,
-                                self.dust_pivot, self.dust_width, self.lgu, self.sigma_u)
+                                self.dust_pivot, self.dust_width, self.lgu, self.sigma_u,
+                                self.n_live)
 
 
 def workspace_size(op: int, ssp: SspBlock, filters: FilterBank | None, n_gal: int, n_t: int,
@@ -242,10 +247,16 @@ def sfh_table(t_table: torch.Tensor, sfh_params: torch.Tensor, stream=None) -> t
     return out
 
 
-def weights(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, with_mstar=False, stream=None):
-    """dsps_weights: W [n_gal, n_met, n_age] float32 (and M_star float64)."""
-    w = torch.empty((pop.n_gal, ssp.n_met, ssp.n_age), dtype=torch.float32, device=pop.device)
-    ms = torch.empty(pop.n_gal, dtype=torch.float64, device=pop.device) if with_mstar else None
+def weights(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, with_mstar=False, out=None,
+            mstar_out=None, stream=None):
+    """dsps_weights: W [n_gal, n_met, n_age] float32 (and M_star float64);
+    `out` and `mstar_out` may supply the output tensors."""
+    w = out if out is not None else torch.empty((pop.n_gal, ssp.n_met, ssp.n_age),
+                                                dtype=torch.float32, device=pop.device)
+    ms = None
+    if with_mstar:
+        ms = mstar_out if mstar_out is not None else torch.empty(pop.n_gal, dtype=torch.float64,
+                                                                 device=pop.device)
     nbytes = workspace_size(N.OP_WEIGHTS, ssp, None, pop.n_gal, pop.n_t, "fp32")
     buf, off = _workspace(nbytes, pop.device)
     ws = ctypes.c_void_p(buf.data_ptr() + off) if buf is not None else None
@@ -257,9 +268,10 @@ def weights(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, with_mstar=F
 
 
 def sed(ssp: SspBlock, cosmo: Cosmology, pop: DevicePopulation, apply_dust=True, precision="fp32",
-        stream=None):
-    """dsps_sed: rest-frame SED [n_gal, n_wave] float32."""
-    out = torch.empty((pop.n_gal, ssp.n_wave), dtype=torch.float32, device=pop.device)
+        out=None, stream=None):
+    """dsps_sed: rest-frame SED [n_gal, n_wave] float32 (into `out` if given)."""
+    if out is None:
+        out = torch.empty((pop.n_gal, ssp.n_wave), dtype=torch.float32, device=pop.device)
     nbytes = workspace_size(N.OP_SED, ssp, None, pop.n_gal, pop.n_t, precision)
     buf, off = _workspace(nbytes, pop.device)
     c, p = cosmo.c(), pop.c()
@@ -456,6 +468,30 @@ def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePo
         bands = bands.to(device=d, dtype=torch.float32).contiguous()
     if moments is not None:
         moments = moments.to(device=d, dtype=torch.float32).contiguous()
+    out = _grad_outputs(ssp, pop, want, outs)
+    if workspace is None:
+        workspace = Workspace(workspace_size(N.OP_MAGS_VJP, ssp, filters, n, pop.n_t, "fp32"), d)
+    c, p = cosmo.c(), pop.c()
+    rc = _lib().dsps_mags_vjp(ssp.handle, filters.handle, ctypes.byref(c), ctypes.byref(p), N.FP32,
+                              _ptr(mags_bar), _ptr(bands), _ptr(moments), *_grad_ptrs(out),
+                              workspace.ptr(), workspace.nbytes, _stream(stream))
+    N.check(rc, "dsps_mags_vjp")
+    return out
+
+
+_GRAD_ORDER = ("sfr", "sfh_params", "lgmet", "lgmet_old", "sigma_z", "av", "delta", "bump",
+               "av_old", "delta_old", "lgu", "sigma_u")
+
+
+def _grad_ptrs(out):
+    return [_ptr(out.get(k)) for k in _GRAD_ORDER]
+
+
+def _grad_outputs(ssp, pop, want, outs):
+    """Gradient tensors by input name: `outs` as given, else fresh ones for
+    the names in `want` the population carries."""
+    n, d = pop.n_gal, pop.device
+    aged = pop.av_old is not None
     out = {}
     if outs is not None:
         out = dict(outs)
@@ -475,18 +511,31 @@ def mags_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePo
     for k in ("lgu", "sigma_u"):
         if k in want and getattr(ssp, "n_u", 1) > 1:
             out[k] = torch.empty(n, dtype=torch.float32, device=d)
+    return out
+
+
+def mags_residual_vjp(ssp: SspBlock, filters: FilterBank, cosmo: Cosmology, pop: DevicePopulation,
+                      target: torch.Tensor, wt: torch.Tensor | None = None,
+                      want=_GRAD_ORDER, workspace: Workspace | None = None, out=None,
+                      outs: dict | None = None, stream=None):
+    """dsps_mags_residual_vjp: float32 magnitudes [n_gal, n_band] and the
+    gradients of sum wt (m - target)^2 (wt None: all 1) in one call that
+    sorts and computes the weights once.  Returns (mags, gradients by
+    input name); `out` and `outs` may supply the output tensors."""
+    n, d = pop.n_gal, pop.device
+    target = target.to(device=d, dtype=torch.float32).contiguous()
+    if wt is not None:
+        wt = wt.to(device=d, dtype=torch.float32).contiguous()
+    m = out if out is not None else torch.empty((n, filters.n_band), dtype=torch.float32, device=d)
+    grads = _grad_outputs(ssp, pop, want, outs)
     if workspace is None:
         workspace = Workspace(workspace_size(N.OP_MAGS_VJP, ssp, filters, n, pop.n_t, "fp32"), d)
     c, p = cosmo.c(), pop.c()
-    rc = _lib().dsps_mags_vjp(ssp.handle, filters.handle, ctypes.byref(c), ctypes.byref(p), N.FP32,
-                              _ptr(mags_bar), _ptr(bands), _ptr(moments), _ptr(out.get("sfr")),
-                              _ptr(out.get("sfh_params")), _ptr(out.get("lgmet")),
-                              _ptr(out.get("lgmet_old")), _ptr(out.get("sigma_z")), _ptr(out.get("av")), _ptr(out.get("delta")),
-                              _ptr(out.get("bump")), _ptr(out.get("av_old")),
-                              _ptr(out.get("delta_old")), _ptr(out.get("lgu")), _ptr(out.get("sigma_u")),
-                              workspace.ptr(), workspace.nbytes, _stream(stream))
-    N.check(rc, "dsps_mags_vjp")
-    return out
+    rc = _lib().dsps_mags_residual_vjp(ssp.handle, filters.handle, ctypes.byref(c), ctypes.byref(p),
+                                       _ptr(target), _ptr(wt), _ptr(m), *_grad_ptrs(grads),
+                                       workspace.ptr(), workspace.nbytes, _stream(stream))
+    N.check(rc, "dsps_mags_residual_vjp")
+    return m, grads
 
 
 @dataclass

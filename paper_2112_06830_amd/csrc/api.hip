@@ -602,6 +602,7 @@ static int sort_population(const dsps_ssp *ssp, const dsps_pop *p, int *hist, in
   }
   s.hist = hist;
   s.perm = perm;
+  s.n_live = p->n_live;
   return launch_sort(s, stream);
 }
 
@@ -613,6 +614,7 @@ static WeightsLaunch base_weights(const dsps_ssp *ssp, const dsps_cosmo *cosmo, 
   a.z = p->z; a.lgmet = p->lgmet; a.sigma_z = p->sigma_z;
   a.av = p->av; a.delta = p->delta; a.bump = p->bump;
   a.n_gal = p->n_gal;
+  a.n_live = p->n_live;
   a.n_t = p->n_t;
   a.slope = p->lgmet_slope;
   a.pivot = p->lg_age_pivot;
@@ -730,6 +732,7 @@ static int sed_batch_prepare(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const
   m.precision = precision;
   m.s_begin = s0;
   m.s_count = cnt;
+  m.n_live = pop->n_live;
   m.meta = (const GalaxyMeta *)(ws + L.meta);
   m.range = (const GalaxyRange *)(ws + L.range);
   m.ion = ion;
@@ -752,6 +755,7 @@ static SedLaunch sed_launch(const dsps_ssp *ssp, const dsps_pop *pop, const Layo
   s.apply_dust = apply_dust;
   s.g_begin = s0;
   s.g_count = cnt;
+  s.n_live = pop->n_live;
   s.perm = (const int *)(ws + L.perm);
   s.plan = (const TilePlan *)(ws + L.tiles);
   s.w_pad = ws + L.w;
@@ -881,6 +885,7 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   m.precision = precision;
   m.s_begin = s0;
   m.s_count = cnt;
+  m.n_live = pop->n_live;
   m.w_pad = ws + L.w;
   m.meta = meta;
   m.range = range;
@@ -898,6 +903,7 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   f.plan = (const TilePlan *)(ws + L.tiles);
   f.s_begin = s0;
   f.s_count = cnt;
+  f.n_live = pop->n_live;
   f.partial = partial;
   f.part_rows = L.batch;
   f.mag_offset = offset;
@@ -1067,13 +1073,29 @@ int dsps_mags_ion_tangent(const dsps_ssp *ssp, const dsps_filters *filters,
   return DSPS_OK;
 }
 
-int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
-                  const dsps_pop *pop, int precision, const float *mags_bar, const float *bands,
-                  const float *moments, double *sfr_bar, double *sfh_params_bar, float *lgmet_bar,
-                  float *lgmet_old_bar, float *sigma_bar, float *av_bar, float *delta_bar,
-                  float *bump_bar, float *av_old_bar, float *delta_old_bar, float *lgu_bar,
-                  float *sigma_u_bar, void *workspace, size_t workspace_bytes,
-                  hipStream_t stream) {
+}  // extern "C"
+
+namespace dsps {
+
+// The cotangent of the magnitudes: given (mags_bar), or in residual mode
+// (target set) the cotangent of sum wt (m - target)^2, formed on the device
+// from the forward magnitudes, which go to mags_out.
+struct MagsCotangent {
+  const float *mags_bar;
+  const float *target, *wt;
+  float *mags_out;
+};
+
+static int mags_vjp_common(const dsps_ssp *ssp, const dsps_filters *filters,
+                           const dsps_cosmo *cosmo, const dsps_pop *pop, int precision,
+                           const MagsCotangent &ct, const float *bands, const float *moments,
+                           double *sfr_bar, double *sfh_params_bar, float *lgmet_bar,
+                           float *lgmet_old_bar, float *sigma_bar, float *av_bar, float *delta_bar,
+                           float *bump_bar, float *av_old_bar, float *delta_old_bar,
+                           float *lgu_bar, float *sigma_u_bar, void *workspace,
+                           size_t workspace_bytes, hipStream_t stream) {
+  const float *mags_bar = ct.mags_bar;
+  const bool residual = ct.target != nullptr;
   DSPS_CHECK(ssp && filters, DSPS_ERR_ARG, "ssp or filters is NULL");
   DSPS_TRY(check_cosmo(cosmo));
   DSPS_TRY(check_pop(pop, true));
@@ -1089,7 +1111,10 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
   DSPS_CHECK(ssp->v.n_u > 1 || (!lgu_bar && !sigma_u_bar), DSPS_ERR_ARG,
              "lgu_bar and sigma_u_bar need an SSP block with an ionization axis");
   if (pop->n_gal == 0) return DSPS_OK;
-  DSPS_CHECK(mags_bar, DSPS_ERR_ARG, "mags_bar is NULL");
+  if (residual)
+    DSPS_CHECK(ct.mags_out && !bands && !moments, DSPS_ERR_ARG, "mags is NULL");
+  else
+    DSPS_CHECK(mags_bar, DSPS_ERR_ARG, "mags_bar is NULL");
   if (age_dust)
     DSPS_CHECK(!moments, DSPS_ERR_ARG,
                "the age-dependent attenuation has no dust moments: pass moments = NULL");
@@ -1137,7 +1162,8 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
       }
       DSPS_TRY(launch_weights(a, stream));
     } else {
-      DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt, fwd_mags, fwd_bands,
+      DSPS_TRY(mags_batch(ssp, filters, cosmo, pop, DSPS_FP32, L, ws, s0, cnt,
+                          residual ? ct.mags_out : fwd_mags, fwd_bands,
                           age_dust ? nullptr : fwd_mom, stream));
     }
     VjpLaunch v{};
@@ -1147,8 +1173,14 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
     v.n_groups = (L.n_chunks + LBAR_CHUNKS - 1) / LBAR_CHUNKS;
     v.s_begin = s0;
     v.s_count = cnt;
+    v.n_live = pop->n_live;
     v.perm = perm;
     v.mags_bar = mags_bar;
+    if (residual) {
+      v.target = ct.target;
+      v.resid_wt = ct.wt;
+      v.fwd_mags = ct.mags_out;
+    }
     v.bands = use_bands;
     v.moments = age_dust ? nullptr : use_mom;
     v.gamma = (float *)(ws + L.gamma);
@@ -1207,6 +1239,38 @@ int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_c
     for (int stage = 0; stage < 4; ++stage) DSPS_TRY(launch_vjp(v, stage, stream));
   }
   return DSPS_OK;
+}
+
+}  // namespace dsps
+
+extern "C" {
+
+int dsps_mags_vjp(const dsps_ssp *ssp, const dsps_filters *filters, const dsps_cosmo *cosmo,
+                  const dsps_pop *pop, int precision, const float *mags_bar, const float *bands,
+                  const float *moments, double *sfr_bar, double *sfh_params_bar, float *lgmet_bar,
+                  float *lgmet_old_bar, float *sigma_bar, float *av_bar, float *delta_bar,
+                  float *bump_bar, float *av_old_bar, float *delta_old_bar, float *lgu_bar,
+                  float *sigma_u_bar, void *workspace, size_t workspace_bytes,
+                  hipStream_t stream) {
+  return mags_vjp_common(ssp, filters, cosmo, pop, precision, {mags_bar, nullptr, nullptr, nullptr},
+                         bands, moments, sfr_bar, sfh_params_bar, lgmet_bar, lgmet_old_bar,
+                         sigma_bar, av_bar, delta_bar, bump_bar, av_old_bar, delta_old_bar,
+                         lgu_bar, sigma_u_bar, workspace, workspace_bytes, stream);
+}
+
+int dsps_mags_residual_vjp(const dsps_ssp *ssp, const dsps_filters *filters,
+                           const dsps_cosmo *cosmo, const dsps_pop *pop, const float *target,
+                           const float *wt, float *mags, double *sfr_bar, double *sfh_params_bar,
+                           float *lgmet_bar, float *lgmet_old_bar, float *sigma_bar,
+                           float *av_bar, float *delta_bar, float *bump_bar, float *av_old_bar,
+                           float *delta_old_bar, float *lgu_bar, float *sigma_u_bar,
+                           void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  DSPS_CHECK(target || (pop && pop->n_gal == 0), DSPS_ERR_ARG, "target is NULL");
+  return mags_vjp_common(ssp, filters, cosmo, pop, DSPS_FP32,
+                         {nullptr, target, wt, mags}, nullptr,
+                         nullptr, sfr_bar, sfh_params_bar, lgmet_bar, lgmet_old_bar, sigma_bar,
+                         av_bar, delta_bar, bump_bar, av_old_bar, delta_old_bar, lgu_bar,
+                         sigma_u_bar, workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"
@@ -1351,6 +1415,7 @@ int dsps_eqw_pop(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const dsps_pop *p
              "(and no ionization axis)");
   DSPS_TRY(check_precision(ssp, DSPS_FP32));
   DSPS_TRY(check_ion(ssp, pop));
+  DSPS_CHECK(!pop->n_live, DSPS_ERR_UNSUPPORTED, "dsps_eqw_pop does not take a live count");
   EqwLaunch e{};
   SedLaunch s{};
   DSPS_TRY(prepare_lines(ssp, lines, n_line, e));

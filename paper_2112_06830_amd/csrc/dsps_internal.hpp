@@ -292,6 +292,15 @@ const GaussLegendre &gauss_legendre16();
 
 // ------------------------------------------------------------- launchers
 // Defined in k_weights.hip.
+// Live galaxies of a launch's range [begin, begin + count) of sorted
+// positions.  With a device-side count (a server's padded batch) the ordering
+// sort puts the galaxies at and past it last, in their own order, and every
+// kernel stops there: their inputs are not read and their outputs not
+// written.  Grids stay sized by the host's count; the extra blocks leave.
+__device__ __forceinline__ int live_in_range(const int *n_live, int begin, int count) {
+  return n_live ? min(count, max(0, *n_live - begin)) : count;
+}
+
 struct WeightsLaunch {
   // inputs
   const double *t_table;
@@ -310,6 +319,7 @@ struct WeightsLaunch {
   // ordering: sorted position s -> galaxy perm[s]; null means identity
   const int *perm;
   int s_begin, s_count;      // sorted range processed by this launch
+  const int *n_live;         // device count of live galaxies, or null (live_in_range)
   // outputs (any may be null)
   float *w_user;             // [n_gal][n_met][n_age] natural order (by galaxy index)
   double *mstar;             // [n_gal]
@@ -343,6 +353,9 @@ struct SortLaunch {
   int n_u;
   int *hist;                 // [SORT_BINS] scratch
   int *perm;                 // [n_gal] sorted position -> galaxy
+  // device count of live galaxies, or null: galaxies at and past it are
+  // not read and keep their own positions at the end of the order
+  const int *n_live;
 };
 int launch_sort(const SortLaunch &a, hipStream_t stream);
 int launch_quantize_bf16(const float *x, int rows, int cols, uint16_t *q, float *scale,
@@ -379,6 +392,7 @@ struct MagsLaunch {
   FilterView flt;
   int precision;
   int s_begin, s_count;          // sorted range of this batch
+  const int *n_live;             // device count of live galaxies, or null
   const void *w_pad;             // [s_count][k_pad]
   const GalaxyMeta *meta;        // full arrays, by sorted position
   const GalaxyRange *range;
@@ -411,6 +425,7 @@ int launch_tile_plan(const MagsLaunch &a, hipStream_t stream);
 struct FinalizeLaunch {
   int n_band, n_chunks;
   int s_begin, s_count;
+  const int *n_live;  // device count of live galaxies, or null
   const float *partial;
   const TilePlan *plan;
   const double *mag_offset;
@@ -465,6 +480,7 @@ struct SedLaunch {
   SspView ssp;
   int precision, apply_dust;
   int g_begin, g_count;
+  const int *n_live;            // device count of live galaxies, or null
   const int *perm;
   const TilePlan *plan;         // [tiles of the range]
   const void *w_pad;            // [g_count][k_pad], by sorted position - g_begin
@@ -497,8 +513,13 @@ struct VjpLaunch {
   FilterView flt;
   int n_band, n_groups;         // n_groups: LBAR_CHUNKS-chunk groups per tile
   int s_begin, s_count;
+  const int *n_live;            // device count of live galaxies, or null
   const int *perm;
   const float *mags_bar;      // [n_gal][n_band] by galaxy index
+  // residual mode (target set, mags_bar unused): the cotangent is
+  // (fwd_mags - target) * 2 resid_wt (resid_wt null: 1), all [n_gal][n_band]
+  // by galaxy index
+  const float *target, *resid_wt, *fwd_mags;
   const float *bands;         // [n_gal][2][n_band] by galaxy index
   const float *moments;       // [n_gal][3][n_band] by galaxy index
   float *gamma;               // [n_gal][n_band] by sorted position

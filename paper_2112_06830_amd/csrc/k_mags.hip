@@ -202,7 +202,8 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
 
   int tile, group;
   xcd_tile_group(blockIdx.x, a.n_groups, tile, group);
-  const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
+  const int live = live_in_range(a.n_live, a.s_begin, a.s_count);
+  const int n_tiles = (live + TILE_G - 1) / TILE_G;
   if (tile >= n_tiles) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   const FilterView F = a.flt;     // argument would force a private-memory copy
   const int n_band = F.n_band;
   const int g0 = tile * TILE_G;                 // first batch-local galaxy of the tile
-  const int nvalid = min(TILE_G, a.s_count - g0);
+  const int nvalid = min(TILE_G, live - g0);
 
   // ---- the tile's plan: groups are aligned to the tile's own window, all
   // but the last full; the grid holds a host bound on one galaxy's window,
@@ -443,7 +444,8 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
   __shared__ unsigned s_kblk[KBLOCK_WORDS];
   const int tile = blockIdx.x;
   const int g0 = tile * TILE_G;
-  const int nvalid = min(TILE_G, a.s_count - g0);
+  const int nvalid = min(TILE_G, live_in_range(a.n_live, a.s_begin, a.s_count) - g0);
+  if (nvalid <= 0) return;   // past the live galaxies: no reader looks at this plan
   if (threadIdx.x == 0) {
     s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0; s_tile[4] = 0;
     s_tile[5] = a.ion ? 1 << 30 : 0; s_tile[6] = 0;
@@ -564,7 +566,7 @@ int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
 // m = -2.5 log10(num / (AB0 den)) + [D_mod(z) - 2.5 log10(1+z)] in float64.
 __global__ void k_mags_finalize(FinalizeLaunch a) {
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
-  if (local >= a.s_count) return;
+  if (local >= live_in_range(a.n_live, a.s_begin, a.s_count)) return;
   const int s = a.s_begin + local;
   const int g = a.perm ? a.perm[s] : s;
   const int nb = a.n_band, ncomp = mags_components(a.moments), nc = ncomp * nb;

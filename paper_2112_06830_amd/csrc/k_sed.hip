@@ -33,6 +33,8 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   __shared__ int2 s_piece[4 * MAX_UNITS / GemmCfg<PREC>::UNITS];
   const int chunk = a.n_sel ? a.chunk_list[blockIdx.x] : (int)blockIdx.x;
   const int tile = blockIdx.y;
+  const int live = live_in_range(a.n_live, a.g_begin, a.g_count);
+  if (tile * TILE_G >= live) return;   // the whole workgroup: no barrier has run
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
   const SspView P = a.ssp;
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
                         : (PREC == DSPS_FP32 ? (const elem *)P.st32 : (const elem *)P.st16);
   const int k_cols = AGED ? AGE_K : P.k_pad;
   const int a_stride = NEB ? P.k_row : k_cols;
-  const int nvalid = min(TILE_G, a.g_count - g0);
+  const int nvalid = min(TILE_G, live - g0);
   const GemmOps<PREC> ops =
       gemm_ops<PREC>(st, (size_t)P.n_wave_pad * a_stride, a_stride, linear_rows<PREC>(l0),
                      (const elem *)a.w_pad + (size_t)g0 * k_cols, nvalid, k_cols);
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
     for (int nb = 0; nb < 2; ++nb) {
       const int col = wc * 64 + nb * 32 + (lane & 31);
       float v[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-      if (g0 + col < a.g_count) {
+      if (col < nvalid) {
         const int s = a.g_begin + g0 + col;
         const GalaxyMeta m = a.meta[s];
         const GalaxyDustOld d = a.dust_old[s];
@@ -128,7 +130,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const int col = wc * 64 + nb * 32 + (lane & 31);
-    if (g0 + col >= a.g_count) continue;
+    if (col >= nvalid) continue;
     const int s = a.g_begin + g0 + col;     // sorted position
     float da = 0.0f, dl = 0.0f, bp = 0.0f;
     if (a.apply_dust && !AGED) {   // AGED: the folds attenuated already

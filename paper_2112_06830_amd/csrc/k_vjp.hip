@@ -26,7 +26,7 @@ constexpr double LN10_D = 2.30258509299404568402;
 
 __global__ void k_vjp_gamma(VjpLaunch a) {
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
-  if (local >= a.s_count) return;
+  if (local >= live_in_range(a.n_live, a.s_begin, a.s_count)) return;
   const int s = a.s_begin + local;
   const int g = a.perm[s];
   const int nb = a.n_band;
@@ -36,7 +36,10 @@ __global__ void k_vjp_gamma(VjpLaunch a) {
   double dust[3] = {0.0, 0.0, 0.0};
   for (int b = 0; b < nb; ++b) {
     const float num = a.bands[(size_t)g * 2 * nb + b];
-    const float bar = a.mags_bar[(size_t)g * nb + b];
+    const size_t i = (size_t)g * nb + b;
+    // residual mode: the cotangent of sum wt (m - target)^2
+    const float bar = a.target ? (a.fwd_mags[i] - a.target[i]) * (2.0f * (a.resid_wt ? a.resid_wt[i] : 1.0f))
+                               : a.mags_bar[i];
     // a zero cotangent contributes nothing, also for a band with num = 0
     const float gam = bar == 0.0f ? 0.0f : -2.5f * bar / (LN10_F * num);
     a.gamma[(size_t)s * nb + b] = gam;
@@ -65,7 +68,8 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
   const FilterView F = a.flt;
   const int n_band = F.n_band, n_int = F.n_pts - 1;
   const int g0 = tile * TILE_G;
-  const int nvalid = min(TILE_G, a.s_count - g0);
+  const int nvalid = min(TILE_G, live_in_range(a.n_live, a.s_begin, a.s_count) - g0);
+  if (nvalid <= 0) return;   // the whole workgroup, before any barrier
   const int nwp = P.n_wave_pad;
 
   if (threadIdx.x == 0) { s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0; }
@@ -200,7 +204,8 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
   const SspView P = a.ssp;
   const int g0 = tile * TILE_G;
-  const int nvalid = min(TILE_G, a.s_count - g0);
+  const int nvalid = min(TILE_G, live_in_range(a.n_live, a.s_begin, a.s_count) - g0);
+  if (nvalid <= 0) return;   // the whole workgroup, before any barrier
   const int nwp = P.n_wave_pad;
 
   if (threadIdx.x == 0) {
@@ -391,12 +396,13 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar_rows(VjpLaunch a) 
   const SspView P = a.ssp;
   int tile, kb;
   xcd_tile_group(blockIdx.x, wbar_row_blocks(P.n_met, P.n_age), tile, kb);
-  const int n_tiles = (a.s_count + TILE_G - 1) / TILE_G;
+  const int live = live_in_range(a.n_live, a.s_begin, a.s_count);
+  const int n_tiles = (live + TILE_G - 1) / TILE_G;
   if (tile >= n_tiles) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave & 1, wc = wave >> 1, h = lane >> 5;
   const int g0 = tile * TILE_G;
-  const int nvalid = min(TILE_G, a.s_count - g0);
+  const int nvalid = min(TILE_G, live - g0);
   const int nwp = P.n_wave_pad;
 
   if (threadIdx.x == 0) {
@@ -525,7 +531,7 @@ __global__ __launch_bounds__(256, 4) void k_vjp_wbar_aged(VjpLaunch a) {
   const SspView P = a.ssp;
   const int nwp = P.n_wave_pad, n_met = P.n_met;
   const int g0 = tile * TILE_G + wave * 32;   // the wave's first member (batch position)
-  const int nvalid = min(32, a.s_count - g0);
+  const int nvalid = min(32, live_in_range(a.n_live, a.s_begin, a.s_count) - g0);
   if (nvalid <= 0) return;                    // whole waves leave together
   // the unit's ages [i0, i0 + n_ages) and their shared transition weight,
   // taken as the forward pass takes it
@@ -733,7 +739,7 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   for (int n = threadIdx.x; n < n_t; n += blockDim.x) tt[n] = a.t_table[n];
   __syncthreads();
   const int local = blockIdx.x * WEIGHT_WAVES + wave;
-  if (local >= a.s_count) return;
+  if (local >= live_in_range(a.n_live, a.s_begin, a.s_count)) return;
   const int s = a.s_begin + local;
   const int g = a.perm[s];
   const SspView P = a.ssp;

@@ -103,7 +103,7 @@ __device__ int first_index(const double *x, int n, double v) {
 // weights kernel when it runs.
 __global__ __launch_bounds__(256) void k_galaxy_scalars(WeightsLaunch a) {
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
-  if (local >= a.s_count) return;
+  if (local >= live_in_range(a.n_live, a.s_begin, a.s_count)) return;
   const int s = a.s_begin + local;
   const int g = a.perm ? a.perm[s] : s;
   const double z = (double)a.z[g];
@@ -351,7 +351,8 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   __syncthreads();
 
   const int local = blockIdx.x * WEIGHT_WAVES + wave;
-  if (local >= a.s_count) return;   // whole wave leaves; no block barrier follows
+  // whole wave leaves; no block barrier follows
+  if (local >= live_in_range(a.n_live, a.s_begin, a.s_count)) return;
   const int s = a.s_begin + local;
   const int g = a.perm ? a.perm[s] : s;
 
@@ -630,10 +631,11 @@ __global__ __launch_bounds__(1024) void k_sort_hist(SortLaunch a) {
   for (int i = threadIdx.x; i < SORT_BINS; i += 1024) cnt[i] = 0;
   __syncthreads();
   const int g0 = blockIdx.x * SORT_CHUNK + threadIdx.x;
+  const int live = live_in_range(a.n_live, 0, a.n_gal);
 #pragma unroll
   for (int k = 0; k < SORT_PER_THREAD; ++k) {
     const int g = g0 + k * 1024;
-    if (g < a.n_gal) atomicAdd(&cnt[sort_key(a, g)], 1);
+    if (g < live) atomicAdd(&cnt[sort_key(a, g)], 1);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < SORT_BINS; i += 1024)
@@ -670,13 +672,14 @@ __global__ __launch_bounds__(1024) void k_sort_scatter(SortLaunch a) {
   for (int i = threadIdx.x; i < SORT_BINS; i += 1024) cnt[i] = 0;
   __syncthreads();
   const int g0 = blockIdx.x * SORT_CHUNK + threadIdx.x;
+  const int live = live_in_range(a.n_live, 0, a.n_gal);
   int key[SORT_PER_THREAD], rank[SORT_PER_THREAD];
 #pragma unroll
   for (int k = 0; k < SORT_PER_THREAD; ++k) {
     const int g = g0 + k * 1024;
     key[k] = 0;
     rank[k] = 0;
-    if (g < a.n_gal) {
+    if (g < live) {
       key[k] = sort_key(a, g);
       rank[k] = atomicAdd(&cnt[key[k]], 1);
     }
@@ -688,7 +691,10 @@ __global__ __launch_bounds__(1024) void k_sort_scatter(SortLaunch a) {
 #pragma unroll
   for (int k = 0; k < SORT_PER_THREAD; ++k) {
     const int g = g0 + k * 1024;
-    if (g < a.n_gal) a.perm[base[key[k]] + rank[k]] = g;
+    if (g < live)
+      a.perm[base[key[k]] + rank[k]] = g;
+    else if (g < a.n_gal)
+      a.perm[g] = g;       // padding keeps its place after the live galaxies
   }
 }
 

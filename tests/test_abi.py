@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_error_string(lib):
-    assert lib.dsps_abi_version() == 8
+    assert lib.dsps_abi_version() == 9
     assert isinstance(lib.dsps_last_error(), bytes)
 
 

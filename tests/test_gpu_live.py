@@ -1,0 +1,227 @@
+"""The device-side live count (dsps_pop.n_live) and the fused residual
+reverse pass (dsps_mags_residual_vjp).
+
+A population of n_gal galaxies whose count says n_live must give, for its
+first n_live galaxies, bit for bit what a call on those n_live galaxies alone
+gives, and leave every output row past n_live as it was; the padding galaxies
+carry valid but different inputs, so any leak of theirs into a live result
+shows as a difference.  The fused residual call must equal dsps_mags followed
+by dsps_mags_vjp with the cotangent (m - target) * (2 wt), bit for bit."""
+
+import sys
+
+import pytest
+
+import synth
+from gpu_common import filters6, ssp_large
+
+pytestmark = pytest.mark.gpu
+
+SENTINEL = 7.25
+N_GAL, N_LIVE = 2600, 1701      # several 128-galaxy tiles, a ragged live edge
+GRADS = ("sfr", "sfh_params", "lgmet", "sigma_z", "av", "delta", "bump")
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_06830_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def handles(dev):
+    return (dev.SspBlock.from_synth(ssp_large(), precisions=("fp32", "bf16")),
+            dev.FilterBank.from_synth(filters6()))
+
+
+def _populations(P, n, n_live, seed, use_params=True):
+    """(padded population with its live count, the live galaxies alone)."""
+    import torch
+    pop = synth.make_population(n, n_t=100, z_range=(0.1, 3.0), seed=seed)
+    sfr = None
+    if not use_params:
+        import oracle
+        sfr = oracle.sfh.sfr_from_params(pop.t_table, pop.sfh_params)
+    full = P.DevicePopulation.from_synth(pop, sfr=sfr, use_params=use_params)
+    full.n_live = torch.tensor([n_live], dtype=torch.int32, device="cuda")
+    k = min(max(n_live, 0), n)
+    head = P.DevicePopulation(
+        full.t_table,
+        None if full.sfr is None else full.sfr[:k].contiguous(),
+        None if full.sfh_params is None else full.sfh_params[:, :k].contiguous(),
+        full.z[:k].contiguous(), full.lgmet[:k].contiguous(), full.sigma_z[:k].contiguous(),
+        full.av[:k].contiguous(), full.delta[:k].contiguous(), full.bump[:k].contiguous(),
+        full.lgmet_slope, full.lg_age_pivot)
+    return full, head, k
+
+
+def _filled(shape, dtype=None):
+    import torch
+    return torch.full(shape, SENTINEL, dtype=dtype or torch.float32, device="cuda")
+
+
+def _check_rows(got, ref, k, axis=0):
+    """Rows [0, k) along `axis` equal ref bit for bit; the rest keep the sentinel."""
+    import torch
+    g = got if axis == 0 else got.transpose(0, axis)
+    r = ref if axis == 0 else ref.transpose(0, axis)
+    assert torch.equal(g[:k], r), float((g[:k].double() - r.double()).abs().max())
+    assert bool((g[k:] == SENTINEL).all())
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_live_count_mags_equal_the_live_galaxies_alone(dev, handles, precision):
+    P = dev
+    ssp_h, flt_h = handles
+    full, head, k = _populations(P, N_GAL, N_LIVE, seed=71)
+    _say(f"live count mags n_gal={N_GAL} n_live={N_LIVE} precision={precision}")
+    moments = precision == "fp32"
+    if moments:
+        ref, ref_b, ref_m = P.mags(ssp_h, flt_h, P.Cosmology(), head, precision=precision,
+                                   with_moments=True)
+    else:
+        ref, ref_b = P.mags(ssp_h, flt_h, P.Cosmology(), head, precision=precision, with_bands=True)
+    m, b = _filled((N_GAL, 6)), _filled((N_GAL, 2, 6))
+    mom = _filled((N_GAL, 3, 6)) if moments else None
+    P.mags(ssp_h, flt_h, P.Cosmology(), full, precision=precision, with_bands=True,
+           with_moments=moments, out=m, bands_out=b, moments_out=mom)
+    _check_rows(m, ref, k)
+    _check_rows(b, ref_b, k)
+    if moments:
+        _check_rows(mom, ref_m, k)
+    # the no-allocation entry point honours the count the same way
+    m2 = _filled((N_GAL, 6))
+    P.mags_noalloc(ssp_h, flt_h, P.Cosmology(), full, m2, precision=precision)
+    _check_rows(m2, ref, k)
+
+
+def test_live_count_reverse_pass_equals_the_live_galaxies_alone(dev, handles):
+    import torch
+    P = dev
+    ssp_h, flt_h = handles
+    full, head, k = _populations(P, N_GAL, N_LIVE, seed=72)
+    _say(f"live count vjp n_gal={N_GAL} n_live={N_LIVE}")
+    m, b, mom = P.mags(ssp_h, flt_h, P.Cosmology(), head, precision="fp32", with_moments=True)
+    gen = torch.Generator(device="cpu").manual_seed(3)
+    bar_full = torch.randn((N_GAL, 6), generator=gen).to("cuda")
+    ref = P.mags_vjp(ssp_h, flt_h, P.Cosmology(), head, bar_full[:k].contiguous(), bands=b,
+                     moments=mom, want=GRADS)
+    # the padded call's bands and moments: live rows from the forward pass,
+    # padding rows the sentinel (never read)
+    fb, fm = _filled((N_GAL, 2, 6)), _filled((N_GAL, 3, 6))
+    P.mags(ssp_h, flt_h, P.Cosmology(), full, precision="fp32", with_moments=True,
+           out=_filled((N_GAL, 6)), bands_out=fb, moments_out=fm)
+    outs = {"sfr": _filled((N_GAL, 100), torch.float64),
+            "sfh_params": _filled((5, N_GAL), torch.float64)}
+    for name in ("lgmet", "sigma_z", "av", "delta", "bump"):
+        outs[name] = _filled((N_GAL,))
+    got = P.mags_vjp(ssp_h, flt_h, P.Cosmology(), full, bar_full, bands=fb, moments=fm, outs=outs)
+    _check_rows(got["sfr"], ref["sfr"], k)
+    _check_rows(got["sfh_params"], ref["sfh_params"], k, axis=1)
+    for name in ("lgmet", "sigma_z", "av", "delta", "bump"):
+        _check_rows(got[name], ref[name], k)
+
+
+def test_residual_call_equals_mags_then_vjp(dev, handles):
+    import torch
+    P = dev
+    ssp_h, flt_h = handles
+    n = 3000
+    pop = synth.make_population(n, n_t=100, z_range=(0.1, 3.0), seed=73)
+    dp = P.DevicePopulation.from_synth(pop, use_params=True)
+    gen = torch.Generator(device="cpu").manual_seed(4)
+    target = (22.0 + torch.randn((n, 6), generator=gen)).to("cuda")
+    wt = torch.rand((n, 6), generator=gen).to("cuda")
+    wt[::7] = 0.0                       # galaxies left out of the loss
+    for w in (None, wt):
+        _say(f"residual call n_gal={n} weights={'yes' if w is not None else 'none'}")
+        m, b, mom = P.mags(ssp_h, flt_h, P.Cosmology(), dp, precision="fp32", with_moments=True)
+        bar = (m - target) * (2.0 if w is None else w * 2.0)
+        ref = P.mags_vjp(ssp_h, flt_h, P.Cosmology(), dp, bar, bands=b, moments=mom, want=GRADS)
+        got_m, got = P.mags_residual_vjp(ssp_h, flt_h, P.Cosmology(), dp, target, w, want=GRADS)
+        assert torch.equal(got_m, m)
+        for name in GRADS:
+            assert torch.equal(got[name], ref[name]), name
+        if w is not None:
+            # a zero weight row removes the galaxy from the loss
+            assert bool((got["lgmet"][::7] == 0).all())
+
+
+def test_residual_call_with_live_count(dev, handles):
+    import torch
+    P = dev
+    ssp_h, flt_h = handles
+    full, head, k = _populations(P, N_GAL, N_LIVE, seed=74)
+    _say(f"residual call with live count n_gal={N_GAL} n_live={N_LIVE}")
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    target = (22.0 + torch.randn((N_GAL, 6), generator=gen)).to("cuda")
+    ref_m, ref = P.mags_residual_vjp(ssp_h, flt_h, P.Cosmology(), head, target[:k].contiguous(),
+                                     want=GRADS)
+    outs = {"sfr": _filled((N_GAL, 100), torch.float64),
+            "sfh_params": _filled((5, N_GAL), torch.float64)}
+    for name in ("lgmet", "sigma_z", "av", "delta", "bump"):
+        outs[name] = _filled((N_GAL,))
+    m = _filled((N_GAL, 6))
+    P.mags_residual_vjp(ssp_h, flt_h, P.Cosmology(), full, target, out=m, outs=outs)
+    _check_rows(m, ref_m, k)
+    _check_rows(outs["sfr"], ref["sfr"], k)
+    _check_rows(outs["sfh_params"], ref["sfh_params"], k, axis=1)
+    for name in ("lgmet", "sigma_z", "av", "delta", "bump"):
+        _check_rows(outs[name], ref[name], k)
+
+
+@pytest.mark.parametrize("use_params", [True, False])
+def test_live_count_weights_and_sed(dev, handles, use_params):
+    import torch
+    P = dev
+    ssp_h, _ = handles
+    full, head, k = _populations(P, 900, 517, seed=75, use_params=use_params)
+    _say(f"live count weights/sed n_gal=900 n_live=517 use_params={use_params}")
+    w_ref, ms_ref = P.weights(ssp_h, P.Cosmology(), head, with_mstar=True)
+    w, ms = P.weights(ssp_h, P.Cosmology(), full, with_mstar=True,
+                      out=_filled((900,) + tuple(w_ref.shape[1:])),
+                      mstar_out=_filled((900,), torch.float64))
+    _check_rows(w, w_ref, k)
+    _check_rows(ms, ms_ref, k)
+    s_ref = P.sed(ssp_h, P.Cosmology(), head, apply_dust=True, precision="fp32")
+    s = P.sed(ssp_h, P.Cosmology(), full, apply_dust=True, precision="fp32",
+              out=_filled((900, s_ref.shape[1])))
+    _check_rows(s, s_ref, k)
+
+
+@pytest.mark.parametrize("n_live", [0, 128, N_GAL + 5])
+def test_live_count_edges(dev, handles, n_live):
+    """No live galaxy (nothing written), exactly one tile, and a count past
+    n_gal (clamped: the whole population)."""
+    P = dev
+    ssp_h, flt_h = handles
+    full, head, k = _populations(P, N_GAL, n_live, seed=76)
+    _say(f"live count edge n_gal={N_GAL} n_live={n_live}")
+    m = _filled((N_GAL, 6))
+    P.mags(ssp_h, flt_h, P.Cosmology(), full, precision="fp32", out=m)
+    if k:
+        ref = P.mags(ssp_h, flt_h, P.Cosmology(), head, precision="fp32")
+    else:
+        import torch
+        ref = torch.empty((0, 6), dtype=torch.float32, device="cuda")
+    _check_rows(m, ref, k)
+
+
+def test_eqw_pop_refuses_a_live_count(dev, handles):
+    import torch
+    P = dev
+    ssp_h, _ = handles
+    full, _, _ = _populations(P, 300, 200, seed=77)
+    lines = [(6564.6, 15.0, 60.0)]
+    with pytest.raises(P.DspsError) as e:
+        P.eqw_pop(ssp_h, P.Cosmology(), full, lines)
+    assert e.value.status == -5
+    torch.cuda.synchronize()

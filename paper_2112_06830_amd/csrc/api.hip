@@ -728,6 +728,7 @@ static int sed_batch_prepare(const dsps_ssp *ssp, const dsps_cosmo *cosmo, const
   DSPS_TRY(launch_weights(a, stream));
   MagsLaunch m{};
   m.age_dust = age_dust;
+  if (age_dust) age_groups(ssp, pop, m.age_young, m.age_old);   // the plan groups ages by them
   m.ssp = ssp->v;
   m.precision = precision;
   m.s_begin = s0;

@@ -35,7 +35,10 @@ __host__ __device__ constexpr int chunks_per_group(int precision) {
 constexpr int LBAR_CHUNKS = 4;
 constexpr int SORT_BINS = 8192;    // keys of the ordering sort (4+4-bit rows, 5-bit z bucket)
 constexpr int GEMM_THREADS = 256;  // 4 wave64s in a 2 x 2 arrangement
-constexpr int WEIGHT_WAVES = 4;    // galaxies per weights workgroup (one per wave)
+constexpr int WEIGHT_WAVES = 4;    // galaxies per adjoint weights workgroup (one per wave)
+// galaxies per forward weights workgroup: its grid tables are filled once per
+// workgroup, so more waves share the fill
+constexpr int WEIGHTS_FWD_WAVES = 8;
 
 // ------------------------------------------------------------- constants
 // AB zero point of a source at 10 pc, L_sun/Hz (Section 2.2.1).
@@ -123,14 +126,31 @@ constexpr int KBLOCKS_PER_ROW = AGE_PAD / KBLOCK_AGES;                  // 24
 constexpr int KBLOCK_WORDS = (DSPS_MAX_MET * KBLOCKS_PER_ROW + 31) / 32;  // 12
 static_assert(DSPS_MAX_MET <= 16 && KBLOCKS_PER_ROW == 2 * KBLOCK_WORDS, "block-major mask layout");
 // K units of a tile's stage list: 8 ages of a row for float32 (two 4-age
-// blocks), 16 for bfloat16, two per age for the age-major layout.
+// blocks), 16 for bfloat16.
 constexpr int MAX_UNITS = DSPS_MAX_MET * KBLOCKS_PER_ROW / 2;           // 192
-static_assert(MAX_UNITS >= AGE_PAD * 2 && MAX_UNITS % 2 == 0, "unit list size");
+static_assert(MAX_UNITS % 2 == 0, "unit list size");
+// The age-major layout's units are the two halves of an age's 16
+// metallicity slots (unit u of age i: slots 8u .. 8u + 7, which is what one
+// MFMA step pair reduces, so a galaxy's sums do not depend on its tile), the
+// tile's non-zero ones grouped by attenuation group (all young ages, each
+// transition age, all old ages) and each group padded to whole stages, so
+// that no stage mixes two groups.  A galaxy's mask has bit 4 i + p of the
+// same twelve words (KBLOCK_WORDS) set when slots 4p .. 4p + 3 of age i hold
+// a weight.
+constexpr int AGED_PIECES_PER_AGE = AGE_MET_SLOTS / 4;                   // 4
+static_assert(AGED_PIECES_PER_AGE * AGE_PAD == 32 * KBLOCK_WORDS, "age-major piece mask");
+// two units per age plus at most one of padding per group (at most
+// AGE_PAD + 1 groups)
+constexpr int MAX_AGED_UNITS = (2 * AGE_PAD + (AGE_PAD + 1) + 15) / 16 * 16;   // 304
+constexpr int MAX_PLAN_K = MAX_AGED_UNITS > MAX_UNITS ? MAX_AGED_UNITS : MAX_UNITS;
+constexpr int MAX_AGED_STAGES = MAX_AGED_UNITS / 2;
 
 struct GalaxyRange {
   int win_lo, win_hi;            // rest-wavelength index window [lo, hi) that any filter sees
   // bit 16 (a % 2) + j of word a / 2 set when metallicity row j has a
-  // non-zero weight at some age in [4 a, 4 a + 4)
+  // non-zero weight at some age in [4 a, 4 a + 4); in the age-major layout,
+  // bit c % 32 of word c / 32 set when piece c (age c / 4, slots 4 (c % 4) ..)
+  // holds a non-zero weight
   unsigned kblk[KBLOCK_WORDS];
   int age_hi;    // ages >= age_hi carry no weight (AGE_PAD when unknown)
 };
@@ -384,7 +404,10 @@ struct TilePlan {
   float zp1_min, zp1_max;
   int u_lo, u_hi;
   int n_units;                   // units before the padding
-  int koff[MAX_UNITS];           // K offset of each unit in elements, or -1
+  int koff[MAX_PLAN_K];           // K offset of each unit in elements, or -1
+  // age-major: after stage s, fold the accumulated SED of the group whose
+  // ages include tag[s] (-1: the group goes on)
+  short tag[MAX_AGED_STAGES];
 };
 
 struct MagsLaunch {

@@ -314,27 +314,29 @@ __device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const GemmOps<PRE
 }
 
 // Age-dependent attenuation (Section 3.4.1, Eq. agedep_dust_csp) over an
-// age-major K loop whose stage ks is age ks.  Ages [0, age_young) share the
-// young-star dust, ages [age_old, ...) the old-star dust, each age between
-// has its own transition value.  At the last stage of such a group every
-// wave folds the group's partial SED into sed += F_att(group) acc and
-// restarts acc; lc holds the tile's per-row (lambda, log2(lambda/5500), k0,
+// age-major K loop of metallicity pieces grouped by attenuation group: ages
+// [0, age_young) share the young-star dust, ages [age_old, ...) the old-star
+// dust, each age between has its own transition value, and no stage mixes
+// two groups.  After the last stage of a group (tag >= 0: an age of the
+// group) every wave folds the group's partial SED into sed += F_att(group)
+// acc and restarts acc; lc holds the tile's per-row (lambda, log2(lambda/5500), k0,
 // bump shape) constants.  Per column block nb: the young and old dust
 // exponents and slopes and the bump amplitude.
 struct AgeFold {
-  int nk, age_young, age_old;
+  const short *tag;    // per stage: an age of the group to fold after it, or -1
+  int age_young, age_old;
   double pivot, width;
   const double *lg_age;
   float da_y[2], dl_y[2], da_o[2], dl_o[2], bp[2];
 
   __device__ __forceinline__ void operator()(int ks, f32x16 (&sed)[2][2], f32x16 (&acc)[2][2],
                                              const float4 *lc, int wr, int h) const {
-    const bool young = ks < age_young, old = ks >= age_old;
-    const bool ends = ks == nk - 1 || (young ? ks + 1 == age_young : !old);
-    if (!ends) return;
+    const int age = tag[ks];
+    if (age < 0) return;
+    const bool young = age < age_young, old = age >= age_old;
     // the group's transition weight: 0 young, 1 old, T_erf in between
     const float t = young ? 0.0f
-                          : (old ? 1.0f : (float)mdf_transition(lg_age[ks], pivot, width));
+                          : (old ? 1.0f : (float)mdf_transition(lg_age[age], pivot, width));
     float da[2], dl[2];
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {

@@ -192,8 +192,8 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   __shared__ float4 s_lc[TILE_L];
   __shared__ float s_q[TILE_L];
   // byte offsets (A, B) of each thread's 16-byte piece of every stage of the
-  // tile's unit list, by stage and piece
-  __shared__ int2 s_piece[4 * MAX_UNITS / GemmCfg<PREC>::UNITS];
+  // tile's unit list (age-major: its piece list), by stage and piece
+  __shared__ int2 s_piece[4 * (AGED ? MAX_AGED_UNITS : MAX_UNITS) / GemmCfg<PREC>::UNITS];
   // dynamic: filter transmissions [n_band][n_pts + 1], then with NEB the
   // members' ionization weights [point - u_lo][column] (n_u points at most)
   extern __shared__ float s_tr[];
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
         for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
           for (int r = 0; r < 16; ++r) sed[mb][nb][r] = 0.0f;
-      AgeFold af{nk, a.age_young, a.age_old, a.dust_pivot, a.dust_width, P.lg_age, {}, {}, {}, {}, {}};
+      AgeFold af{pl->tag, a.age_young, a.age_old, a.dust_pivot, a.dust_width, P.lg_age, {}, {}, {}, {}, {}};
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) {
         af.da_y[nb] = E.da[nb]; af.dl_y[nb] = E.dl[nb];
@@ -433,9 +433,10 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
 // redshifts and non-zero weight blocks, then the unit list, ascending in K:
 // a float32 unit is one 4-age block of a row and a bfloat16 unit two (16
 // bytes of the weight row either way), kept when it holds a weight for some
-// member; the age-major layout takes the four units of every age below the
-// highest non-zero one.  The list is padded with -1 (zero units) to whole
-// stages of four units.
+// member, padded with -1 (zero units) to whole stages.  The age-major layout
+// lists the halves of an age's metallicity slots that some member holds a
+// weight in, attenuation group by group, each group padded to whole stages
+// and its last stage tagged with one of its ages.
 template <int PREC>
 __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
   // window lo, window hi, min and max of (1+z) as float bits (positive floats
@@ -474,22 +475,62 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
   const int lane = threadIdx.x;
   TilePlan *pl = a.plan + tile;
   const int n_met = a.ssp.n_met;
-  // candidate unit c: age-major (age c / 2, slots 8 (c % 2) ..); float32
-  // (row c / 12, 8 ages from 8 (c % 12): 4-age blocks 2 (c % 12) and + 1,
-  // both in mask word c % 12); bfloat16 (row c / 6, 16 ages from 16 (c % 6):
-  // mask words 2 (c % 6) and + 1)
+  if (a.age_dust) {
+    // groups of ages [a0, a1): all young ages, one transition age, all old
+    // ages, up to the tile's highest age with a weight; candidate unit c is
+    // half c % 2 of age c / 2: mask bits 2c and 2c + 1
+    using C32 = GemmCfg<DSPS_FP32>;             // the age-major layout is float32
+    static_assert(AGED_PIECES_PER_AGE == 4 && AGE_MET_SLOTS == 2 * C32::UNIT_K,
+                  "two units of two pieces per age");
+    constexpr int UPS = C32::UNITS;             // units per stage
+    const int age_hi = min(s_tile[4], AGE_PAD);
+    int n = 0;
+    for (int a0 = 0; a0 < age_hi;) {
+      const int a1 = a0 < a.age_young ? min(a.age_young, age_hi)
+                                      : (a0 < a.age_old ? a0 + 1 : age_hi);
+      const int n_start = n;
+      for (int base = 2 * a0; base < 2 * a1; base += 64) {
+        const int c = base + lane;
+        const bool keep = c < 2 * a1 && ((s_kblk[(2 * c) >> 5] >> ((2 * c) & 31)) & 3u);
+        const unsigned long long m = __ballot(keep);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (keep) pl->koff[n + before] = AGE_MET_SLOTS * (c / 2) + C32::UNIT_K * (c % 2);
+        n += __popcll(m);
+      }
+      if (n > n_start) {
+        const int n_pad = (n + UPS - 1) / UPS * UPS;
+        if (n + lane < n_pad) pl->koff[n + lane] = -1;
+        for (int q = n_start / UPS + lane; q < n_pad / UPS; q += 64)
+          pl->tag[q] = q == n_pad / UPS - 1 ? (short)(a1 - 1) : (short)-1;
+        n = n_pad;
+      }
+      a0 = a1;
+    }
+    if (lane == 0) {
+      const int c_first = s_tile[0] / TILE_L;
+      pl->c_first = c_first;
+      pl->c_last = max((s_tile[1] + TILE_L - 1) / TILE_L, c_first);   // exclusive
+      pl->nk = n / UPS;
+      pl->n_units = n;
+      pl->zp1_min = __int_as_float(s_tile[2]);
+      pl->zp1_max = __int_as_float(s_tile[3]);
+      pl->u_lo = 0;
+      pl->u_hi = 0;
+    }
+    return;
+  }
+  // candidate unit c: float32 (row c / 12, 8 ages from 8 (c % 12): 4-age
+  // blocks 2 (c % 12) and + 1, both in mask word c % 12); bfloat16 (row
+  // c / 6, 16 ages from 16 (c % 6): mask words 2 (c % 6) and + 1)
   constexpr int UNITS_PER_ROW = AGE_PAD / GemmCfg<PREC>::UNIT_K;   // 12 or 6
-  const int n_cand = a.age_dust ? 2 * min(s_tile[4], AGE_PAD) : n_met * UNITS_PER_ROW;
+  const int n_cand = n_met * UNITS_PER_ROW;
   int n = 0;
   for (int base = 0; base < n_cand; base += 64) {
     const int c = base + lane;
     bool keep = false;
     int koff = 0;
     if (c < n_cand) {
-      if (a.age_dust) {
-        keep = true;
-        koff = c * 8;   // age c / 2 at column 16 (c / 2), slots 8 (c % 2) ..
-      } else if (PREC == DSPS_BF16) {
+      if (PREC == DSPS_BF16) {
         const int j = c / UNITS_PER_ROW, q = c % UNITS_PER_ROW;
         const unsigned m2 = s_kblk[2 * q] | s_kblk[2 * q + 1];
         keep = ((m2 >> j) | (m2 >> (16 + j))) & 1u;

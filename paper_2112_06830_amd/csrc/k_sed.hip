@@ -30,7 +30,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
   __shared__ GemmSmem<PREC> sm[2];
   __shared__ float s_pn[NEB ? DSPS_MAX_ION * TILE_G : 1];
   // byte offsets (A, B) of each thread's 16-byte piece of every stage
-  __shared__ int2 s_piece[4 * MAX_UNITS / GemmCfg<PREC>::UNITS];
+  __shared__ int2 s_piece[4 * (AGED ? MAX_AGED_UNITS : MAX_UNITS) / GemmCfg<PREC>::UNITS];
   const int chunk = a.n_sel ? a.chunk_list[blockIdx.x] : (int)blockIdx.x;
   const int tile = blockIdx.y;
   const int live = live_in_range(a.n_live, a.g_begin, a.g_count);
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
                      wr, wc, lane, acc);
   } else if constexpr (AGED) {
     if (threadIdx.x < TILE_L) s_lc[threadIdx.x] = P.lconst[l0 + threadIdx.x];
-    AgeFold af{nk, a.age_young, a.age_old, a.dust_pivot, a.dust_width, P.lg_age, {}, {}, {}, {}, {}};
+    AgeFold af{pl->tag, a.age_young, a.age_old, a.dust_pivot, a.dust_width, P.lg_age, {}, {}, {}, {}, {}};
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
       const int col = wc * 64 + nb * 32 + (lane & 31);

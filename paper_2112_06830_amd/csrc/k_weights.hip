@@ -277,8 +277,9 @@ __device__ __forceinline__ unsigned mdf_rows(const MdfLane &L, T *out) {
 // Age-major float32 rows (age-dependent attenuation): each of the lane's two
 // ages becomes 16 metallicity slots (zeros past n_met) written as four
 // 16-byte stores.  Returns the lane's highest age with a non-zero weight plus
-// one (0 if none).
-__device__ __forceinline__ int mdf_rows_age(const MdfLane &L, float *out) {
+// one (0 if none); pieces gets bit 4 q + p set when slots 4 p .. 4 p + 3 of
+// age i0 + q hold a non-zero weight.
+__device__ __forceinline__ int mdf_rows_age(const MdfLane &L, float *out, unsigned &pieces) {
   float w0[AGE_MET_SLOTS], w1[AGE_MET_SLOTS];
   double c_prev0 = 0.0, c_prev1 = 0.0;
 #pragma unroll
@@ -295,12 +296,14 @@ __device__ __forceinline__ int mdf_rows_age(const MdfLane &L, float *out) {
     w0[j] = v0;
     w1[j] = v1;
   }
-  bool nz0 = false, nz1 = false;
+  unsigned pm = 0u;
 #pragma unroll
   for (int j = 0; j < AGE_MET_SLOTS; ++j) {
-    nz0 |= w0[j] != 0.0f;
-    nz1 |= w1[j] != 0.0f;
+    if (w0[j] != 0.0f) pm |= 1u << (j / 4);
+    if (w1[j] != 0.0f) pm |= 1u << (AGED_PIECES_PER_AGE + j / 4);
   }
+  pieces = L.i0 < AGE_PAD ? pm : 0u;
+  const bool nz0 = (pm & 0xfu) != 0u, nz1 = (pm >> AGED_PIECES_PER_AGE) != 0u;
   if (L.i0 < AGE_PAD) {
     float4 *p0 = reinterpret_cast<float4 *>(out + (size_t)L.i0 * AGE_MET_SLOTS);
 #pragma unroll
@@ -322,13 +325,13 @@ __device__ __forceinline__ void wave_sync() {
 // Block-shared LDS of the weights kernel, in doubles.
 __host__ __device__ inline size_t weights_lds_doubles(int n_t, int n_age, int n_met, int k_pad) {
   return (size_t)n_t + (n_age + 1) + n_age + (n_met + 1) + (k_pad + 1) / 2 +
-         (size_t)WEIGHT_WAVES * SFR_PRE;
+         (size_t)WEIGHTS_FWD_WAVES * SFR_PRE;
 }
 
 // TABULATED: the SFR arrives as a table row per galaxy; otherwise it is
 // evaluated from the parametric history at the time-grid nodes.
 template <bool TABULATED>
-__global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
+__global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunch a) {
   const SspView P = a.ssp;
   const int n_t = a.n_t, n_age = P.n_age, n_met = P.n_met;
   // block-shared: time grid, SSP grid constants, row scales
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
     for (int n = threadIdx.x; n < P.k_pad; n += blockDim.x) s_ks[n] = P.kscale[n];
   __syncthreads();
 
-  const int local = blockIdx.x * WEIGHT_WAVES + wave;
+  const int local = blockIdx.x * WEIGHTS_FWD_WAVES + wave;
   // whole wave leaves; no block barrier follows
   if (local >= live_in_range(a.n_live, a.s_begin, a.s_count)) return;
   const int s = a.s_begin + local;
@@ -385,13 +388,28 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   {
     double te[2];
     int hi[2];
+    // the node a uniform grid would put t at, from the grid's mean spacing
+    const double t_first = tt[0], t_last = tt[n_t - 1];
+    const double per_node = (double)(n_t - 1) / (t_last - t_first);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int e = 2 * lane + q;
       te[q] = e <= n_age ? t_obs - s_aedge[e] : -1.0 / 0.0;
-      kind[q] = !(te[q] > tt[0]) ? 0 : (te[q] >= tt[n_t - 1] ? 2 : 1);
+      kind[q] = !(te[q] > t_first) ? 0 : (te[q] >= t_last ? 2 : 1);
       lo[q] = 0;
-      hi[q] = n_t - 1;
+      hi[q] = kind[q] == 1 ? n_t - 1 : 1;   // only an edge inside the grid searches
+      if (kind[q] == 1) {
+        // check the guess against the two nodes around it: on a (near)
+        // uniform grid it brackets t, otherwise it narrows the bisection
+        const int g = min(max((int)((te[q] - t_first) * per_node), 0), n_t - 2);
+        if (tt[g] <= te[q]) {
+          lo[q] = g;
+          if (te[q] < tt[g + 1]) hi[q] = g + 1;
+          else lo[q] = g + 1;
+        } else {
+          hi[q] = g;
+        }
+      }
     }
     // bisection of both edges together (tt[lo] <= t < tt[hi] for kind 1)
     while (hi[0] - lo[0] > 1 || hi[1] - lo[1] > 1) {
@@ -504,12 +522,30 @@ __global__ __launch_bounds__(256) void k_weights(WeightsLaunch a) {
   const MdfLane L{s_medge, s_ks, n_met, n_age, i0, mu0, mu1, inv_sig, mage0, mage1, real0, real1,
                   fmin(mu_a, mu_b), fmax(mu_a, mu_b)};
   if (a.w_pad && a.w_pad_age) {
-    // age-major rows: the contraction needs only the highest non-zero age
-    const int hi = mdf_rows_age(L, (float *)a.w_pad + (size_t)local * AGE_K);
+    // age-major rows: the contraction needs the highest non-zero age and the
+    // pieces holding a weight
+    unsigned pieces;
+    const int hi = mdf_rows_age(L, (float *)a.w_pad + (size_t)local * AGE_K, pieces);
     const unsigned long long any = __ballot(hi > 0);
     const int top = any ? 63 - __builtin_clzll(any) : 0;
     const int age_hi = any ? __builtin_amdgcn_readlane(hi, top) : 0;
-    if (a.range && lane == 0) a.range[s].age_hi = age_hi;
+    if (a.range) {
+      if (lane == 0) a.range[s].age_hi = age_hi;
+      // lane l holds bits 8 l .. 8 l + 7 of the piece mask (ages 2 l, 2 l + 1):
+      // word w gathers lanes 4 w .. 4 w + 3
+      unsigned long long bit[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) bit[k] = __ballot((pieces >> k) & 1u);
+      if (lane < KBLOCK_WORDS) {
+        unsigned word = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            word |= (unsigned)((bit[k] >> (4 * lane + q)) & 1ull) << (8 * q + k);
+        a.range[s].kblk[lane] = word;
+      }
+    }
     return;
   }
   unsigned nzr;   // metallicity rows in which either of the lane's ages has a non-zero weight
@@ -549,7 +585,7 @@ int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
     set_error("internal: weight rows need the cosmic-time workspace and one output layout");
     return DSPS_ERR_ARG;
   }
-  const int blocks = (a.s_count + WEIGHT_WAVES - 1) / WEIGHT_WAVES;
+  const int blocks = (a.s_count + WEIGHTS_FWD_WAVES - 1) / WEIGHTS_FWD_WAVES;
   const size_t lds = sizeof(double) * weights_lds_doubles(a.n_t, a.ssp.n_age, a.ssp.n_met,
                                                           a.ssp.k_pad);
   const void *fn = a.sfr ? (const void *)k_weights<true> : (const void *)k_weights<false>;
@@ -559,9 +595,9 @@ int launch_weights(const WeightsLaunch &a, hipStream_t stream) {
     if (rc) return rc;
   }
   if (a.sfr)
-    hipLaunchKernelGGL(k_weights<true>, dim3(blocks), dim3(64 * WEIGHT_WAVES), lds, stream, a);
+    hipLaunchKernelGGL(k_weights<true>, dim3(blocks), dim3(64 * WEIGHTS_FWD_WAVES), lds, stream, a);
   else
-    hipLaunchKernelGGL(k_weights<false>, dim3(blocks), dim3(64 * WEIGHT_WAVES), lds, stream, a);
+    hipLaunchKernelGGL(k_weights<false>, dim3(blocks), dim3(64 * WEIGHTS_FWD_WAVES), lds, stream, a);
   return hip_fail(hipGetLastError(), "k_weights launch");
 }
 

@@ -446,12 +446,12 @@ int dsps_filters_info(const dsps_filters *f, int *n_band, int *n_pts) {
 // ------------------------------------------------------------------ workspace
 namespace dsps {
 
-// Galaxies per weights + GEMM round trip.  The forward keeps whole
-// populations of up to 256k galaxies in one launch (no small tail launch);
-// the adjoint's per-galaxy scratch (Lbar, Wbar) is 28 KB, so it runs in
-// batches of 64k.
+// Most galaxies per weights + GEMM round trip.  Populations of up to 256k
+// galaxies run in one launch per kernel; the adjoint's per-galaxy scratch
+// (Lbar, Wbar and the forward's partials, about 40 KB) then takes about
+// 10 GB, which the device's HBM affords.
 constexpr int BATCH_FWD = 262144;
-constexpr int BATCH_VJP = 65536;
+constexpr int BATCH_VJP = 262144;
 
 struct Layout {
   size_t hist = 0, perm = 0, meta = 0, range = 0, offset = 0, w = 0, partial = 0, total = 0;
@@ -466,7 +466,11 @@ static Layout make_layout(int op, const SspView &v, int n_band, int n_gal, int p
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
-  L.batch = std::min(n_gal, op == DSPS_OP_MAGS_VJP ? BATCH_VJP : BATCH_FWD);
+  // as few batches as the cap allows, of equal size in whole tiles (no small
+  // last batch that would leave most of the device idle)
+  const int cap = op == DSPS_OP_MAGS_VJP ? BATCH_VJP : BATCH_FWD;
+  const int n_batches = std::max((n_gal + cap - 1) / cap, 1);
+  L.batch = std::min(n_gal, ((n_gal + n_batches - 1) / n_batches + TILE_G - 1) / TILE_G * TILE_G);
   if (batch_cap > 0) L.batch = std::min(L.batch, batch_cap);
   L.n_chunks = v.n_wave_pad / TILE_L;
   const int cpg = chunks_per_group(precision);

@@ -605,37 +605,36 @@ int launch_mags_gemm(const MagsLaunch &a, hipStream_t stream) {
 
 // Sum the per-chunk partial band sums in chunk order and form magnitudes
 // m = -2.5 log10(num / (AB0 den)) + [D_mod(z) - 2.5 log10(1+z)] in float64.
-__global__ void k_mags_finalize(FinalizeLaunch a) {
-  const int local = blockIdx.x * blockDim.x + threadIdx.x;
-  if (local >= live_in_range(a.n_live, a.s_begin, a.s_count)) return;
+// One workgroup per 128-galaxy tile: the tile's partial rows of one chunk are
+// contiguous, so consecutive threads sum consecutive (galaxy, component)
+// entries over the tile's chunks (each entry in chunk order) into LDS; then
+// one thread per galaxy forms its magnitudes.
+constexpr int FINALIZE_THREADS = 256;
+__global__ __launch_bounds__(FINALIZE_THREADS) void k_mags_finalize(FinalizeLaunch a) {
+  __shared__ float s_sum[TILE_G * 5 * DSPS_MAX_BAND];
+  const int tile = blockIdx.x;
+  const int g0 = tile * TILE_G;
+  const int nvalid = min(TILE_G, live_in_range(a.n_live, a.s_begin, a.s_count) - g0);
+  if (nvalid <= 0) return;   // the whole workgroup, before any barrier
+  const int nb = a.n_band, ncomp = mags_components(a.moments), nc = ncomp * nb;
+  const TilePlan &pl = a.plan[tile];
+  const int c_first = pl.c_first, c_last = pl.c_last;
+  const int n_el = nvalid * nc;
+  for (int e = threadIdx.x; e < n_el; e += FINALIZE_THREADS) {
+    float v = 0.0f;
+    for (int c = c_first; c < c_last; ++c)
+      v += a.partial[((size_t)c * a.part_rows + g0) * nc + e];
+    s_sum[e] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x >= nvalid) return;
+  const int local = g0 + threadIdx.x;
   const int s = a.s_begin + local;
   const int g = a.perm ? a.perm[s] : s;
-  const int nb = a.n_band, ncomp = mags_components(a.moments), nc = ncomp * nb;
-  const TilePlan &pl = a.plan[local / TILE_G];
-  const int2 cr = make_int2(pl.c_first, pl.c_last);
-  // per band and component, chunks summed in chunk order; a galaxy's row of
-  // one chunk is contiguous and adjacent galaxies' rows are adjacent
-  float acc[5][DSPS_MAX_BAND];
-#pragma unroll
-  for (int k = 0; k < 5; ++k)
-#pragma unroll
-    for (int b = 0; b < DSPS_MAX_BAND; ++b) acc[k][b] = 0.0f;
-  for (int c = cr.x; c < cr.y; ++c) {
-    const float *p = a.partial + ((size_t)c * a.part_rows + local) * nc;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      if (k < ncomp) {
-#pragma unroll
-        for (int b = 0; b < DSPS_MAX_BAND; ++b)
-          if (b < nb) acc[k][b] += p[k * nb + b];
-      }
-    }
-  }
+  const float *acc = s_sum + threadIdx.x * nc;   // component k of band b at k * nb + b
   const double offset = a.mag_offset[s];
-#pragma unroll
-  for (int b = 0; b < DSPS_MAX_BAND; ++b) {
-    if (b >= nb) continue;
-    const float num = acc[0][b], den = acc[1][b];
+  for (int b = 0; b < nb; ++b) {
+    const float num = acc[b], den = acc[nb + b];
     double m;
     if (a.tangent_bands) {
       // d(-2.5 log10 num) = -2.5 / ln 10 dnum / num
@@ -651,17 +650,16 @@ __global__ void k_mags_finalize(FinalizeLaunch a) {
       a.bands[(size_t)g * 2 * nb + b] = num;
       a.bands[(size_t)g * 2 * nb + nb + b] = den;
     }
-    if (a.mom) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) a.mom[(size_t)g * 3 * nb + k * nb + b] = acc[2 + k][b];
-    }
+    if (a.mom)
+      for (int k = 0; k < 3; ++k) a.mom[(size_t)g * 3 * nb + k * nb + b] = acc[(2 + k) * nb + b];
   }
 }
 
 int launch_mags_finalize(const FinalizeLaunch &a, hipStream_t stream) {
   if (a.s_count <= 0) return DSPS_OK;
   ProfScope prof(DSPS_KERNEL_MAGS_FINALIZE, stream);
-  hipLaunchKernelGGL(k_mags_finalize, dim3((a.s_count + 255) / 256), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL(k_mags_finalize, dim3((a.s_count + TILE_G - 1) / TILE_G),
+                     dim3(FINALIZE_THREADS), 0, stream, a);
   return hip_fail(hipGetLastError(), "k_mags_finalize launch");
 }
 

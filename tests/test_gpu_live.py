@@ -225,3 +225,76 @@ def test_eqw_pop_refuses_a_live_count(dev, handles):
         P.eqw_pop(ssp_h, P.Cosmology(), full, lines)
     assert e.value.status == -5
     torch.cuda.synchronize()
+
+
+def _head_of(P, full, k):
+    """The first k galaxies of a device population, every optional field
+    included."""
+    sl = lambda t: None if t is None else t[:k].contiguous()
+    return P.DevicePopulation(
+        full.t_table, sl(full.sfr),
+        None if full.sfh_params is None else full.sfh_params[:, :k].contiguous(),
+        sl(full.z), sl(full.lgmet), sl(full.sigma_z), sl(full.av), sl(full.delta), sl(full.bump),
+        full.lgmet_slope, full.lg_age_pivot, sl(full.lgmet_old), full.mdf_width, sl(full.av_old),
+        sl(full.delta_old), full.dust_pivot, full.dust_width, sl(full.lgu), sl(full.sigma_u))
+
+
+def test_live_count_age_dependent_attenuation(dev):
+    """The age-major stage lists, per-group folds and the age-dependent
+    reverse pass stop at the live count too."""
+    import torch
+    P = dev
+    ssp_h = P.SspBlock.from_synth(ssp_large(), precisions=("fp32",), age_major=True)
+    flt_h = P.FilterBank.from_synth(filters6())
+    n, k = 700, 389
+    pop = synth.make_population(n, n_t=100, z_range=(0.1, 3.0), seed=79, age_dust=True)
+    full = P.DevicePopulation.from_synth(pop, use_params=True)
+    full.n_live = torch.tensor([k], dtype=torch.int32, device="cuda")
+    head = _head_of(P, full, k)
+    _say(f"live count, age-dependent attenuation n_gal={n} n_live={k}")
+    ref = P.mags(ssp_h, flt_h, P.Cosmology(), head, precision="fp32")
+    m = _filled((n, 6))
+    P.mags(ssp_h, flt_h, P.Cosmology(), full, precision="fp32", out=m)
+    _check_rows(m, ref, k)
+    gen = torch.Generator(device="cpu").manual_seed(6)
+    bar = torch.randn((n, 6), generator=gen).to("cuda")
+    names = ("lgmet", "sigma_z", "av", "delta", "bump", "av_old", "delta_old")
+    g_ref = P.mags_vjp(ssp_h, flt_h, P.Cosmology(), head, bar[:k].contiguous(),
+                       want=names + ("sfh_params",))
+    outs = {"sfh_params": _filled((5, n), torch.float64)}
+    for name in names:
+        outs[name] = _filled((n,))
+    P.mags_vjp(ssp_h, flt_h, P.Cosmology(), full, bar, outs=outs)
+    _check_rows(outs["sfh_params"], g_ref["sfh_params"], k, axis=1)
+    for name in names:
+        _check_rows(outs[name], g_ref[name], k)
+
+
+def test_live_count_ionization_axis(dev):
+    """The nebular stages (one pass per ionization point of the tile) and the
+    ionization cotangents stop at the live count."""
+    import torch
+    P = dev
+    ssp = synth.make_ssp_nebular(n_u=7, n_wave=1000, wave_lo=1.0e3, wave_hi=2.0e4)
+    ssp_h = P.SspBlock.from_synth(ssp)
+    flt_h = P.FilterBank.from_synth(filters6())
+    n, k = 600, 257
+    pop = synth.make_population(n, n_t=100, z_range=(0.1, 1.0), seed=80, nebular=True)
+    full = P.DevicePopulation.from_synth(pop, use_params=True)
+    full.n_live = torch.tensor([k], dtype=torch.int32, device="cuda")
+    head = _head_of(P, full, k)
+    _say(f"live count, ionization axis n_gal={n} n_live={k}")
+    ref, ref_b, ref_m = P.mags(ssp_h, flt_h, P.Cosmology(), head, precision="fp32", with_moments=True)
+    m, b, mom = _filled((n, 6)), _filled((n, 2, 6)), _filled((n, 3, 6))
+    P.mags(ssp_h, flt_h, P.Cosmology(), full, precision="fp32", with_moments=True, out=m,
+           bands_out=b, moments_out=mom)
+    _check_rows(m, ref, k)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    bar = torch.randn((n, 6), generator=gen).to("cuda")
+    names = ("lgmet", "sigma_z", "av", "lgu", "sigma_u")
+    g_ref = P.mags_vjp(ssp_h, flt_h, P.Cosmology(), head, bar[:k].contiguous(), bands=ref_b,
+                       moments=ref_m, want=names)
+    outs = {name: _filled((n,)) for name in names}
+    P.mags_vjp(ssp_h, flt_h, P.Cosmology(), full, bar, bands=b, moments=mom, outs=outs)
+    for name in names:
+        _check_rows(outs[name], g_ref[name], k)

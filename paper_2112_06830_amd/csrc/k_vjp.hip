@@ -229,8 +229,11 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
                                       a.mdf_width, (double)a.sigma_z[g]));
   }
   __syncthreads();
-  const int l_begin = (s_tile[0] / TILE_L) * TILE_L;
-  const int l_end = ((s_tile[1] + TILE_L - 1) / TILE_L) * TILE_L;
+  // the members' window union on whole K steps: Lbar is zero outside every
+  // member's window, and steps keep each MFMA step pair at the same
+  // wavelengths whatever the tile
+  const int l_begin = (s_tile[0] / C::KT) * C::KT;
+  const int l_end = ((s_tile[1] + C::KT - 1) / C::KT) * C::KT;
   const int k0 = kblk * TILE_L;
   const int j_hi = s_jhi;
 
@@ -434,8 +437,11 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar_rows(VjpLaunch a) 
   const int n_rows = n_plain + max(s_tile[4] - j_lo, 0) * n_ages;
   const int r0 = kb * TILE_L;
   if (r0 >= n_rows) return;      // the whole block: nothing needed here
-  const int l_begin = (s_tile[0] / TILE_L) * TILE_L;
-  const int l_end = ((s_tile[1] + TILE_L - 1) / TILE_L) * TILE_L;
+  // the members' window union on whole K steps: Lbar is zero outside every
+  // member's window, and steps keep each MFMA step pair at the same
+  // wavelengths whatever the tile
+  const int l_begin = (s_tile[0] / C::KT) * C::KT;
+  const int l_end = ((s_tile[1] + C::KT - 1) / C::KT) * C::KT;
   // needed row r -> metallicity row j and age i
   auto row_of = [&](int r, int &j, int &i) {
     const int q = r < n_plain ? r : r - n_plain;

@@ -59,5 +59,44 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# The host-side check (tests/host_check.cpp against the whole library) with the
+# address and undefined-behaviour sanitizers on the host code only: each
+# sanitizer flag goes to the host compilation (-Xarch_host); the device code is
+# built as for the library.
+HOST_CHECK = os.path.join(HERE, "dsps_host_check")
+SAN = ("-Xarch_host -fsanitize=address,undefined -Xarch_host -fno-sanitize-recover=undefined "
+       "-Xarch_host -fno-omit-frame-pointer").split()
+
+
+def _compile_san(src: str, out_dir: str) -> str:
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *COMMON, "-O1", *SAN, "-c", src, "-o", obj]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{res.stdout}\n{res.stderr}")
+    return obj
+
+
+def build_host_check(verbose: bool = False) -> str:
+    out_dir = os.path.join(BUILD, "host_check")
+    os.makedirs(out_dir, exist_ok=True)
+    sources = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    sources.append(os.path.join(ROOT, "tests", "host_check.cpp"))
+    jobs = min(len(sources), int(os.environ.get("MAX_JOBS", "8")))
+    with cf.ThreadPoolExecutor(max_workers=max(jobs, 1)) as ex:
+        objs = list(ex.map(lambda src: _compile_san(src, out_dir), sources))
+    tmp = HOST_CHECK + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", *SAN, *objs, "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, HOST_CHECK)
+    if verbose:
+        print(f"built {HOST_CHECK}")
+    return HOST_CHECK
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    if "--host-check" in sys.argv:
+        build_host_check(verbose=True)

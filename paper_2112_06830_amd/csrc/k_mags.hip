@@ -164,12 +164,13 @@ __device__ __forceinline__ void band_pass(const f32x16 (&acc)[2][2], const EpiLa
 // buffer of the epilogue reuses the operand staging area, which is idle by
 // then.
 //
-// AGED (Section 3.4.1, Eq. agedep_dust_csp): the K stages are the ages of the
-// age-major table (16 metallicity slots each), and the attenuation, which
-// depends on age, is applied per group of stages sharing one set of dust
-// parameters: the young-star ages as one group, each age of the transition on
-// its own, the old-star ages as one group.  At a group's last stage every
-// wave folds the group's partial SED into a second accumulator,
+// AGED (Section 3.4.1, Eq. agedep_dust_csp): the K units are halves of an
+// age's 16 metallicity slots in the age-major table, those some member holds
+// a weight in, and the attenuation, which depends on age, is applied per group
+// of stages sharing one set of dust parameters: the young-star ages as one
+// group, each age of the transition on its own, the old-star ages as one
+// group (no stage mixes two groups).  After a group's last stage every wave
+// folds the group's partial SED into a second accumulator,
 // sed += F_att(group) * acc, and restarts acc.
 //
 // NEB (Section 3.3, Eq. nebsed): the table rows hold one (metallicity, age)

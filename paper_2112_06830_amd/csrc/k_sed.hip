@@ -8,8 +8,9 @@
 // width, which gives the SED's derivative (the sum is linear in them).
 //
 // AGED (Section 3.4.1, Eq. agedep_dust_csp): the age-major table and weight
-// rows, one stage per age, and the attenuation folded per group of ages that
-// share dust parameters (AgeFold), so the output is already attenuated.
+// rows, the stage list grouped by the ages that share dust parameters, and
+// the attenuation folded after each group (AgeFold), so the output is already
+// attenuated.
 //
 // Galaxies come in the ordering sort's order, so a tile's members share few
 // metallicity rows and ages: the K loop runs over the tile's stage list (the

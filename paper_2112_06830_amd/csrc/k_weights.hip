@@ -210,22 +210,37 @@ struct MdfLane {
   const double *medge;   // [n_met + 1] metallicity bin edges (LDS)
   const float *ks;       // [k_pad] bf16 row scales (LDS)
   int n_met, n_age, i0;
-  double mu0, mu1, inv_sig, mage0, mage1;
+  double mu0, mu1, inv_sig, mage0, mage1;   // mage0, mage1 are 0 past the last age
   bool real0, real1;
   double mu_lo, mu_hi;   // the galaxy's smallest and largest centre over ages
+  // interior edges 1 .. n_zero have CDF exactly 0 for every age, edges from
+  // first_one on exactly 1 (mdf_edge_regions)
+  int n_zero, first_one;
 };
 
-// CDF of the MDF at interior edge e for the lane's two ages, c0 and c1.  An
-// edge at least 3 sigma (plus a margin far above rounding) above every age's
-// centre has CDF exactly 1 for all of them, one as far below exactly 0: the
-// wave then skips the polynomial (the test is the same for all its lanes).
-__device__ __forceinline__ void mdf_edge_cdf(const MdfLane &L, double e, double &c0, double &c1) {
+// An edge at least 3 sigma (plus a margin far above rounding) above every
+// age's centre has CDF exactly 1 for all of them, one as far below exactly
+// 0.  The edges are ascending, so the all-zero edges are a prefix and the
+// all-one edges a suffix of the interior ones: one test per edge for the
+// whole wave (lane k takes edge k + 1) gives both as counts the wave shares.
+__device__ __forceinline__ void mdf_edge_regions(MdfLane &L, int lane) {
   const double margin = 3.0 + 1e-9;
-  const bool all_one = (e - L.mu_hi) * L.inv_sig >= margin;
-  const bool all_zero = (e - L.mu_lo) * L.inv_sig <= -margin;
-  if (__builtin_amdgcn_readfirstlane((int)all_one)) {
+  const int ne = L.n_met - 1;
+  const double e = lane < ne ? L.medge[lane + 1] : 0.0;
+  const bool z = lane < ne && (e - L.mu_lo) * L.inv_sig <= -margin;
+  const bool o = lane < ne && (e - L.mu_hi) * L.inv_sig >= margin;
+  const unsigned long long zm = __ballot(z), om = __ballot(o);
+  L.n_zero = __popcll(zm);
+  L.first_one = om ? __builtin_ctzll(om) + 1 : L.n_met;
+}
+
+// CDF of the MDF at interior edge j (value e) for the lane's two ages, c0
+// and c1; the polynomial only between the all-zero and all-one edges.
+__device__ __forceinline__ void mdf_edge_cdf(const MdfLane &L, int j, double e, double &c0,
+                                             double &c1) {
+  if (j >= L.first_one) {
     c0 = c1 = 1.0;
-  } else if (__builtin_amdgcn_readfirstlane((int)all_zero)) {
+  } else if (j <= L.n_zero) {
     c0 = c1 = 0.0;
   } else {
     c0 = triweight_cdf((e - L.mu0) * L.inv_sig);
@@ -243,10 +258,25 @@ __device__ __forceinline__ unsigned mdf_rows(const MdfLane &L, T *out) {
   unsigned nzr = 0u;
   double c_prev0 = 0.0, c_prev1 = 0.0;  // CDF at the lower edge of metallicity bin 0 (-inf)
   for (int j = 0; j < L.n_met; ++j) {
+    // a row whose upper edge is all-zero, or whose lower edge is all-one, has
+    // equal CDFs at both edges: its weights are exactly 0
+    if (j + 1 <= L.n_zero || j >= L.first_one) {
+      c_prev0 = c_prev1 = j + 1 <= L.n_zero ? 0.0 : 1.0;
+      if (MODE == MDF_PAD_BF16) {
+        if (active) *reinterpret_cast<uint32_t *>((uint16_t *)out + j * AGE_PAD + L.i0) = 0u;
+      } else if (MODE == MDF_PAD_F32) {
+        if (active) *reinterpret_cast<float2 *>((float *)out + j * AGE_PAD + L.i0) = make_float2(0.0f, 0.0f);
+      } else {
+        if (L.real0) ((float *)out)[j * L.n_age + L.i0] = 0.0f;
+        if (L.real1) ((float *)out)[j * L.n_age + L.i0 + 1] = 0.0f;
+      }
+      continue;
+    }
     double c_next0 = 1.0, c_next1 = 1.0;  // upper edge of the last bin is +inf
-    if (j < L.n_met - 1) mdf_edge_cdf(L, L.medge[j + 1], c_next0, c_next1);
-    const double wv0 = L.real0 ? L.mage0 * (c_next0 - c_prev0) : 0.0;
-    const double wv1 = L.real1 ? L.mage1 * (c_next1 - c_prev1) : 0.0;
+    if (j < L.n_met - 1) mdf_edge_cdf(L, j + 1, L.medge[j + 1], c_next0, c_next1);
+    // mage is 0 past the last age, and the CDF difference is finite and >= 0
+    const double wv0 = L.mage0 * (c_next0 - c_prev0);
+    const double wv1 = L.mage1 * (c_next1 - c_prev1);
     c_prev0 = c_next0;
     c_prev1 = c_next1;
     bool nz;
@@ -254,11 +284,15 @@ __device__ __forceinline__ unsigned mdf_rows(const MdfLane &L, T *out) {
       const float2 ks = active ? *reinterpret_cast<const float2 *>(&L.ks[j * AGE_PAD + L.i0])
                                : make_float2(0.0f, 0.0f);
       // the row scales are powers of two: scaling after the rounding to
-      // float32 is exact and equals rounding the scaled value
-      const uint32_t q0 = f32_to_bf16_rne((float)wv0 * ks.x);
-      const uint32_t q1 = f32_to_bf16_rne((float)wv1 * ks.y);
-      if (active) *reinterpret_cast<uint32_t *>((uint16_t *)out + j * AGE_PAD + L.i0) = q0 | (q1 << 16);
-      nz = ((q0 | q1) & 0x7FFFu) != 0;
+      // float32 is exact and equals rounding the scaled value.  Both values
+      // round to nearest even in one packed conversion (finite inputs: the
+      // same bits as f32_to_bf16_rne)
+      typedef float f32x2_t __attribute__((ext_vector_type(2)));
+      typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+      const f32x2_t v = {(float)wv0 * ks.x, (float)wv1 * ks.y};
+      const uint32_t q = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+      if (active) *reinterpret_cast<uint32_t *>((uint16_t *)out + j * AGE_PAD + L.i0) = q;
+      nz = (q & 0x7FFF7FFFu) != 0;
     } else {
       const float w0f = (float)wv0, w1f = (float)wv1;
       if (MODE == MDF_PAD_F32) {
@@ -287,7 +321,7 @@ __device__ __forceinline__ int mdf_rows_age(const MdfLane &L, float *out, unsign
     float v0 = 0.0f, v1 = 0.0f;
     if (j < L.n_met) {
       double c_next0 = 1.0, c_next1 = 1.0;
-      if (j < L.n_met - 1) mdf_edge_cdf(L, L.medge[j + 1], c_next0, c_next1);
+      if (j < L.n_met - 1) mdf_edge_cdf(L, j + 1, L.medge[j + 1], c_next0, c_next1);
       v0 = L.real0 ? (float)(L.mage0 * (c_next0 - c_prev0)) : 0.0f;
       v1 = L.real1 ? (float)(L.mage1 * (c_next1 - c_prev1)) : 0.0f;
       c_prev0 = c_next0;
@@ -519,8 +553,9 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
                                  a.mdf_width);
   const double mu_b = mdf_centre(s_lgage[n_age - 1], lgmet, transition, lgmet_old, a.slope,
                                  a.pivot, a.mdf_width);
-  const MdfLane L{s_medge, s_ks, n_met, n_age, i0, mu0, mu1, inv_sig, mage0, mage1, real0, real1,
-                  fmin(mu_a, mu_b), fmax(mu_a, mu_b)};
+  MdfLane L{s_medge, s_ks, n_met, n_age, i0, mu0, mu1, inv_sig, mage0, mage1, real0, real1,
+            fmin(mu_a, mu_b), fmax(mu_a, mu_b), 0, 0};
+  mdf_edge_regions(L, lane);
   if (a.w_pad && a.w_pad_age) {
     // age-major rows: the contraction needs the highest non-zero age and the
     // pieces holding a weight

@@ -163,7 +163,14 @@ __global__ __launch_bounds__(256) void k_galaxy_scalars(WeightsLaunch a) {
 // covers 64 * SFR_PER_LANE segments).
 constexpr int SFR_PER_LANE = 4;
 constexpr int SFR_ROUND = 64 * SFR_PER_LANE;
-constexpr int SFR_PRE = SFR_ROUND + 2;   // per-wave LDS: cumulative mass at a round's nodes
+// Per-wave LDS: cumulative mass at a round's SFR_ROUND + 1 nodes.  Node
+// 4 l + k (lane l's k-th) sits at k * SFR_PRE_K + l, so that the lanes' writes
+// of one k fall on consecutive words; the round's last node sits at 64.
+constexpr int SFR_PRE_K = 65;
+constexpr int SFR_PRE = SFR_PER_LANE * SFR_PRE_K;
+__device__ __forceinline__ int pre_slot(int n) { return (n & 3) * SFR_PRE_K + (n >> 2); }
+// Scan rounds over a time grid of n_t nodes (n_t - 1 segments).
+__host__ __device__ inline int sfr_rounds(int n_t) { return (n_t - 1 + SFR_ROUND - 1) / SFR_ROUND; }
 
 // A double moved across lanes by one DPP control (GFX9 encodings), both
 // halves alike; lanes whose row is masked off or whose source lies outside
@@ -247,7 +254,7 @@ __device__ __forceinline__ void mdf_edge_cdf(const MdfLane &L, int j, double e, 
     c1 = triweight_cdf((e - L.mu1) * L.inv_sig);
   }
 }
-enum { MDF_PAD_BF16, MDF_PAD_F32, MDF_USER };
+enum { MDF_PAD_F32, MDF_USER };
 
 // W[j][i] = m_i (CDF(e_{j+1}) - CDF(e_j)) for the lane's two ages over every
 // metallicity row j, written in the layout of MODE; returns the rows in which
@@ -262,9 +269,7 @@ __device__ __forceinline__ unsigned mdf_rows(const MdfLane &L, T *out) {
     // equal CDFs at both edges: its weights are exactly 0
     if (j + 1 <= L.n_zero || j >= L.first_one) {
       c_prev0 = c_prev1 = j + 1 <= L.n_zero ? 0.0 : 1.0;
-      if (MODE == MDF_PAD_BF16) {
-        if (active) *reinterpret_cast<uint32_t *>((uint16_t *)out + j * AGE_PAD + L.i0) = 0u;
-      } else if (MODE == MDF_PAD_F32) {
+      if (MODE == MDF_PAD_F32) {
         if (active) *reinterpret_cast<float2 *>((float *)out + j * AGE_PAD + L.i0) = make_float2(0.0f, 0.0f);
       } else {
         if (L.real0) ((float *)out)[j * L.n_age + L.i0] = 0.0f;
@@ -279,31 +284,66 @@ __device__ __forceinline__ unsigned mdf_rows(const MdfLane &L, T *out) {
     const double wv1 = L.mage1 * (c_next1 - c_prev1);
     c_prev0 = c_next0;
     c_prev1 = c_next1;
-    bool nz;
-    if (MODE == MDF_PAD_BF16) {
+    const float w0f = (float)wv0, w1f = (float)wv1;
+    if (MODE == MDF_PAD_F32) {
+      if (active) *reinterpret_cast<float2 *>((float *)out + j * AGE_PAD + L.i0) = make_float2(w0f, w1f);
+    } else {
+      if (L.real0) ((float *)out)[j * L.n_age + L.i0] = w0f;
+      if (L.real1) ((float *)out)[j * L.n_age + L.i0 + 1] = w1f;
+    }
+    nzr |= (w0f != 0.0f || w1f != 0.0f ? 1u : 0u) << j;
+  }
+  return nzr;
+}
+
+// The triweight CDF in float32 (the same polynomial as triweight_cdf), exactly
+// 0 and 1 from +-3 on.
+__device__ __forceinline__ float triweight_cdf_f32(float z) {
+  const float z2 = z * z;
+  float p = fmaf(-5.0f / 69984.0f, z2, 7.0f / 2592.0f);
+  p = fmaf(p, z2, -35.0f / 864.0f);
+  p = fmaf(p, z2, 35.0f / 96.0f);
+  const float c = fmaf(z, p, 0.5f);
+  return z <= -3.0f ? 0.0f : (z >= 3.0f ? 1.0f : c);
+}
+
+// mdf_rows for the BF16 GEMM layout, with the CDF differences in float32.
+// The rows are rounded to 8 significant bits next; the float32 CDF differs
+// from the float64 one by about 1e-7, far below that rounding (2^-9 of each
+// weight) for every weight above 1e-4 of its age's mass, and the smaller ones
+// carry a correspondingly small share of the light.
+__device__ __forceinline__ unsigned mdf_rows_bf16(const MdfLane &L, uint16_t *out) {
+  const bool active = L.i0 < AGE_PAD;
+  const float mu0 = (float)L.mu0, mu1 = (float)L.mu1, inv_sig = (float)L.inv_sig;
+  const float mage0 = (float)L.mage0, mage1 = (float)L.mage1;
+  unsigned nzr = 0u;
+  float c_prev0 = 0.0f, c_prev1 = 0.0f;  // CDF at the lower edge of metallicity bin 0 (-inf)
+  for (int j = 0; j < L.n_met; ++j) {
+    uint32_t q = 0u;
+    if (j + 1 <= L.n_zero || j >= L.first_one) {
+      // upper edge all-zero or lower edge all-one: equal CDFs, weights 0
+      c_prev0 = c_prev1 = j + 1 <= L.n_zero ? 0.0f : 1.0f;
+    } else {
+      float c_next0 = 1.0f, c_next1 = 1.0f;  // upper edge of the last bin is +inf
+      if (j + 1 < L.first_one) {             // (then j + 1 < n_met as well)
+        const float e = (float)L.medge[j + 1];
+        c_next0 = triweight_cdf_f32((e - mu0) * inv_sig);
+        c_next1 = triweight_cdf_f32((e - mu1) * inv_sig);
+      }
       const float2 ks = active ? *reinterpret_cast<const float2 *>(&L.ks[j * AGE_PAD + L.i0])
                                : make_float2(0.0f, 0.0f);
-      // the row scales are powers of two: scaling after the rounding to
-      // float32 is exact and equals rounding the scaled value.  Both values
-      // round to nearest even in one packed conversion (finite inputs: the
-      // same bits as f32_to_bf16_rne)
+      // the row scales are powers of two; both values round to nearest even
+      // in one packed conversion (finite inputs: the same bits as
+      // f32_to_bf16_rne)
       typedef float f32x2_t __attribute__((ext_vector_type(2)));
       typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-      const f32x2_t v = {(float)wv0 * ks.x, (float)wv1 * ks.y};
-      const uint32_t q = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
-      if (active) *reinterpret_cast<uint32_t *>((uint16_t *)out + j * AGE_PAD + L.i0) = q;
-      nz = (q & 0x7FFF7FFFu) != 0;
-    } else {
-      const float w0f = (float)wv0, w1f = (float)wv1;
-      if (MODE == MDF_PAD_F32) {
-        if (active) *reinterpret_cast<float2 *>((float *)out + j * AGE_PAD + L.i0) = make_float2(w0f, w1f);
-      } else {
-        if (L.real0) ((float *)out)[j * L.n_age + L.i0] = w0f;
-        if (L.real1) ((float *)out)[j * L.n_age + L.i0 + 1] = w1f;
-      }
-      nz = w0f != 0.0f || w1f != 0.0f;
+      const f32x2_t v = {mage0 * (c_next0 - c_prev0) * ks.x, mage1 * (c_next1 - c_prev1) * ks.y};
+      q = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+      c_prev0 = c_next0;
+      c_prev1 = c_next1;
     }
-    nzr |= (nz ? 1u : 0u) << j;
+    if (active) *reinterpret_cast<uint32_t *>(out + j * AGE_PAD + L.i0) = q;
+    nzr |= ((q & 0x7FFF7FFFu) != 0u ? 1u : 0u) << j;
   }
   return nzr;
 }
@@ -358,8 +398,8 @@ __device__ __forceinline__ void wave_sync() {
 
 // Block-shared LDS of the weights kernel, in doubles.
 __host__ __device__ inline size_t weights_lds_doubles(int n_t, int n_age, int n_met, int k_pad) {
-  return (size_t)n_t + (n_age + 1) + n_age + (n_met + 1) + (k_pad + 1) / 2 +
-         (size_t)WEIGHTS_FWD_WAVES * SFR_PRE;
+  return (size_t)n_t + (size_t)sfr_rounds(n_t) * SFR_ROUND + 1 + (n_age + 1) + n_age +
+         (n_met + 1) + (k_pad + 1) / 2 + (size_t)WEIGHTS_FWD_WAVES * SFR_PRE;
 }
 
 // TABULATED: the SFR arrives as a table row per galaxy; otherwise it is
@@ -370,16 +410,34 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
   const int n_t = a.n_t, n_age = P.n_age, n_met = P.n_met;
   // block-shared: time grid, SSP grid constants, row scales
   extern __shared__ double lds[];
+  const int n_seg = n_t - 1;
+  const int n_round = sfr_rounds(n_t);
   double *tt = lds;                                   // [n_t]
-  double *s_aedge = tt + n_t;                         // [n_age + 1]
+  double *s_segw = tt + n_t;                          // [n_round * SFR_ROUND]
+  double *s_per_node = s_segw + n_round * SFR_ROUND;  // [1]
+  double *s_aedge = s_per_node + 1;                   // [n_age + 1]
   double *s_lgage = s_aedge + n_age + 1;              // [n_age]
   double *s_medge = s_lgage + n_age;                  // [n_met + 1]
   float *s_ks = (float *)(s_medge + n_met + 1);       // [k_pad]
-  const int wave = threadIdx.x >> 6;
+  // one galaxy per wave.  With a tabulated SFR the wave's index is made
+  // uniform, which keeps the galaxy's scalars and its row's base address in
+  // scalar registers; the parametric history's five float64 parameters would
+  // not fit there beside the rest and stay in vector registers.
+  const int wave = TABULATED ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   // per wave: cumulative mass at the SFR_ROUND + 1 nodes of a round
   double *s_pre = (double *)(s_ks + ((P.k_pad + 1) & ~1)) + wave * SFR_PRE;
   for (int n = threadIdx.x; n < n_t; n += blockDim.x) tt[n] = a.t_table[n];
+  // trapezoid weight of every segment, (t_{m+1} - t_m) / 2 in years, in the
+  // order the scan reads it: round r, lane l, k-th segment of the lane at
+  // r * SFR_ROUND + 64 k + l; 0 past the last segment, which masks those out
+  for (int i = threadIdx.x; i < n_round * SFR_ROUND; i += blockDim.x) {
+    const int w = i & (SFR_ROUND - 1);
+    const int m = (i - w) + SFR_PER_LANE * (w & 63) + (w >> 6);
+    s_segw[i] = m < n_seg ? (a.t_table[m + 1] - a.t_table[m]) * (0.5 * YEARS_PER_GYR) : 0.0;
+  }
+  // the node a uniform grid would put a time at, from the mean spacing
+  if (threadIdx.x == 0) s_per_node[0] = (double)n_seg / (a.t_table[n_seg] - a.t_table[0]);
   for (int n = threadIdx.x; n <= n_age; n += blockDim.x) s_aedge[n] = P.age_edges[n];
   for (int n = threadIdx.x; n < n_age; n += blockDim.x) s_lgage[n] = P.lg_age[n];
   for (int n = threadIdx.x; n <= n_met; n += blockDim.x) s_medge[n] = P.met_edges[n];
@@ -399,18 +457,26 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
   const bool transition = a.lgmet_old != nullptr;
   const double lgmet_old = transition ? (double)a.lgmet_old[g] : 0.0;
   const double *row = TABULATED ? a.sfr + (size_t)g * n_t : nullptr;
-  // SFR at nodes base + SFR_PER_LANE lane + k of the next round to be summed
+  // SFR at nodes nb + SFR_PER_LANE lane + k of the next round to be summed
   // and at the first node of the round after it (a tabulated row's first
-  // round is loaded up front).  Nodes past the row's end only ever enter
-  // segments that are masked out, so their loads read the last node instead:
-  // every path issues the same loads, which lets the next round's requests
-  // stay in flight while the current round is summed.
+  // round is loaded up front, each later one while its predecessor is
+  // summed).  A whole round reads no node past its own last one; in the
+  // round that reaches past the row's end, those nodes only enter segments
+  // of weight 0 and read the last node in their place.
   double vn[SFR_PER_LANE], vn_end = 0.0;
-  if (TABULATED) {
+  auto load_round = [&](int nb) {
+    if (nb + SFR_ROUND <= n_t - 1) {
+      const double *r = row + nb + SFR_PER_LANE * lane;
 #pragma unroll
-    for (int k = 0; k < SFR_PER_LANE; ++k) vn[k] = row[min(SFR_PER_LANE * lane + k, n_t - 1)];
-    vn_end = row[min(SFR_ROUND, n_t - 1)];
-  }
+      for (int k = 0; k < SFR_PER_LANE; ++k) vn[k] = r[k];
+      vn_end = row[nb + SFR_ROUND];
+    } else {
+#pragma unroll
+      for (int k = 0; k < SFR_PER_LANE; ++k) vn[k] = row[min(nb + SFR_PER_LANE * lane + k, n_t - 1)];
+      vn_end = row[min(nb + SFR_ROUND, n_t - 1)];
+    }
+  };
+  if (TABULATED) load_round(0);
 
 
   // ---- age-bin edges: lane owns edges e = 2 lane and 2 lane + 1.  The mass
@@ -422,9 +488,8 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
   {
     double te[2];
     int hi[2];
-    // the node a uniform grid would put t at, from the grid's mean spacing
     const double t_first = tt[0], t_last = tt[n_t - 1];
-    const double per_node = (double)(n_t - 1) / (t_last - t_first);
+    const double per_node = s_per_node[0];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int e = 2 * lane + q;
@@ -465,31 +530,34 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
   // base + 4 l .. base + 4 l + 3, sums them locally and joins the wave's
   // exclusive scan of the lane totals.  The cumulative mass at the round's
   // nodes goes to the wave's LDS buffer, where every age-bin edge whose
-  // interval lies in the round interpolates it linearly.  A tabulated row's
-  // next round is loaded while the current one is summed.
+  // interval lies in the round interpolates it linearly.
   double pa = 0, ptau = 1, palpha = 0, pq = 0, ptq = 0;
   if (!TABULATED) {
     pa = a.sfh_params[g]; ptau = a.sfh_params[a.n_gal + g];
     palpha = a.sfh_params[2 * a.n_gal + g]; pq = a.sfh_params[3 * a.n_gal + g];
     ptq = a.sfh_params[4 * a.n_gal + g];
   }
-  const int n_seg = n_t - 1;
+  static_assert(SFR_PER_LANE == 4, "pre_slot assumes four segments per lane");
+  // an edge inside the grid interpolates in the round holding its interval
+  // [lo, lo + 1], between the same two buffer slots whichever round it is
+  int e_round[2], e_slot0[2], e_slot1[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int src = lo[q] & (SFR_ROUND - 1);
+    e_round[q] = kind[q] == 1 ? lo[q] / SFR_ROUND : -1;
+    e_slot0[q] = pre_slot(src);
+    e_slot1[q] = pre_slot(src + 1);
+  }
   double carry = 0.0;
   double em[2] = {0.0, 0.0};
-  for (int base = 0; base < n_seg; base += SFR_ROUND) {
+  for (int base = 0, round = 0; base < n_seg; base += SFR_ROUND, ++round) {
     const int n0 = base + SFR_PER_LANE * lane;
-    // the current round leaves the prefetch registers before the next round
-    // is requested into them, so its loads stay in flight while this one is
-    // summed
     double v[SFR_PER_LANE], v_end;
     if (TABULATED) {
 #pragma unroll
       for (int k = 0; k < SFR_PER_LANE; ++k) v[k] = vn[k];
       v_end = vn_end;
-      const int nb = base + SFR_ROUND;
-#pragma unroll
-      for (int k = 0; k < SFR_PER_LANE; ++k) vn[k] = row[min(nb + SFR_PER_LANE * lane + k, n_t - 1)];
-      vn_end = row[min(nb + SFR_ROUND, n_t - 1)];
+      if (base + SFR_ROUND < n_seg) load_round(base + SFR_ROUND);
     } else {
 #pragma unroll
       for (int k = 0; k < SFR_PER_LANE; ++k) {
@@ -501,27 +569,26 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
     }
     double after = dpp_f64<DPP_WAVE_SHL1>(v[0]);      // SFR at node n0 + SFR_PER_LANE
     if (lane == 63) after = v_end;
+    const double *w = s_segw + base + lane;           // the lane's segment weights
     double part[SFR_PER_LANE];                        // local inclusive sums
 #pragma unroll
     for (int k = 0; k < SFR_PER_LANE; ++k) {
-      const int m = n0 + k;
       const double right = k + 1 < SFR_PER_LANE ? v[k + 1 < SFR_PER_LANE ? k + 1 : k] : after;
-      const double seg = m < n_seg ? 0.5 * (v[k] + right) * (tt[m + 1] - tt[m]) * YEARS_PER_GYR : 0.0;
+      const double seg = (v[k] + right) * w[64 * k];
       part[k] = k == 0 ? seg : part[k > 0 ? k - 1 : 0] + seg;
     }
     const double incl = wave_inclusive_sum(part[SFR_PER_LANE - 1]);
     const double before = carry + dpp_f64<DPP_WAVE_SHR1>(incl);   // lane 0 takes +0
-    s_pre[SFR_PER_LANE * lane] = before;
+    s_pre[lane] = before;                             // node n0 (pre_slot(4 lane))
 #pragma unroll
-    for (int k = 1; k < SFR_PER_LANE; ++k) s_pre[SFR_PER_LANE * lane + k] = before + part[k - 1];
-    if (lane == 63) s_pre[SFR_ROUND] = before + part[SFR_PER_LANE - 1];
+    for (int k = 1; k < SFR_PER_LANE; ++k) s_pre[k * SFR_PRE_K + lane] = before + part[k - 1];
+    if (lane == 63) s_pre[pre_slot(SFR_ROUND)] = before + part[SFR_PER_LANE - 1];
     wave_sync();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int src = lo[q] - base;
-      if (kind[q] == 1 && src >= 0 && src < SFR_ROUND) {
-        const double m0 = s_pre[src];
-        em[q] = m0 + fe[q] * (s_pre[src + 1] - m0);
+      if (e_round[q] == round) {
+        const double m0 = s_pre[e_slot0[q]];
+        em[q] = m0 + fe[q] * (s_pre[e_slot1[q]] - m0);
       }
     }
     carry += lane63_f64(incl);
@@ -585,7 +652,7 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
   }
   unsigned nzr;   // metallicity rows in which either of the lane's ages has a non-zero weight
   if (a.w_pad && a.w_pad_bf16)
-    nzr = mdf_rows<MDF_PAD_BF16>(L, (uint16_t *)a.w_pad + (size_t)local * P.k_pad);
+    nzr = mdf_rows_bf16(L, (uint16_t *)a.w_pad + (size_t)local * P.k_pad);
   else if (a.w_pad)
     nzr = mdf_rows<MDF_PAD_F32>(L, (float *)a.w_pad + (size_t)local * P.k_pad);
   else

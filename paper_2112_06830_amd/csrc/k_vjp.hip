@@ -721,8 +721,20 @@ __device__ double vjp_age_at_z(double z, const CosmoArgs &c, const GaussLegendre
   return c.hubble_time_gyr * wave_sum(0.5 * hh * gl.w[node] * f);
 }
 
-__device__ __forceinline__ int bracket(double t, const double *tt, int n_t) {
+// The node interval holding t, tt[lo] <= t < tt[lo + 1], for tt[0] < t <
+// tt[n_t - 1].  The node a uniform grid would put t at (per_node = (n_t - 1) /
+// (tt[n_t - 1] - tt[0])) is checked against its two neighbours, which on a
+// (near) uniform grid settles it; otherwise a bisection finishes on the side
+// the guess leaves.  The interval is the same either way.
+__device__ __forceinline__ int bracket(double t, const double *tt, int n_t, double per_node) {
   int lo = 0, hi = n_t - 1;
+  const int guess = min(max((int)((t - tt[0]) * per_node), 0), n_t - 2);
+  if (tt[guess] <= t) {
+    if (t < tt[guess + 1]) return guess;
+    lo = guess + 1;
+  } else {
+    hi = guess;
+  }
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (tt[mid] <= t) lo = mid; else hi = mid;
@@ -733,7 +745,10 @@ __device__ __forceinline__ int bracket(double t, const double *tt, int n_t) {
 __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   extern __shared__ double lds[];
   const int n_t = a.n_t;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // one galaxy per wave: a uniform wave index keeps the galaxy's float64
+  // scalars in scalar registers, which leaves the vector registers for four
+  // waves per SIMD
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   double *tt = lds;
   double *wbase = lds + n_t + wave * (2 * n_t + 3 * AGE_PAD + 2);
   double *buf = wbase;                 // SFR values, then the cumulative-mass cotangent
@@ -754,6 +769,7 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   // the per-galaxy scalar pass's t(z), so that the rows needed here are the
   // rows the transposed contraction computed
   const double t_obs = a.t_obs ? a.t_obs[s] : vjp_age_at_z(z, a.cosmo, a.gl, lane);
+  const double per_node = (double)(n_t - 1) / (tt[n_t - 1] - tt[0]);
 
   double pa = 0, ptau = 0, palpha = 0, pq = 0, ptq = 0;
   if (a.sfr) {
@@ -793,7 +809,7 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
     if (t > tt[0]) {
       if (t >= tt[n_t - 1]) m = mc[n_t - 1];
       else {
-        const int lo = bracket(t, tt, n_t);
+        const int lo = bracket(t, tt, n_t, per_node);
         const double f = (t - tt[lo]) / (tt[lo + 1] - tt[lo]);
         m = mc[lo] + f * (mc[lo + 1] - mc[lo]);
       }
@@ -879,7 +895,7 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
     const double t = t_obs - P.age_edges[e];
     if (!(t > tt[0]) || ebar == 0.0) continue;
     if (t >= tt[n_t - 1]) { atomicAdd(&mcb[n_t - 1], ebar); continue; }
-    const int lo = bracket(t, tt, n_t);
+    const int lo = bracket(t, tt, n_t, per_node);
     const double f = (t - tt[lo]) / (tt[lo + 1] - tt[lo]);
     atomicAdd(&mcb[lo], (1.0 - f) * ebar);
     atomicAdd(&mcb[lo + 1], f * ebar);

@@ -25,12 +25,13 @@ namespace dsps {
 constexpr int AGE_PAD = 96;        // ages per metallicity row in the padded K axis
 constexpr int TILE_G = 128;        // galaxies per GEMM tile (N of the MFMA tile)
 constexpr int TILE_L = 128;        // wavelengths per chunk (M of the MFMA tile)
-// Wavelength chunks one workgroup of the fused contraction walks: one for
-// float32 (finest load balance; measured fastest), four for bfloat16 (whose
-// cheaper chunks amortise the per-workgroup set-up).  The adjoint's Lbar
-// kernel groups LBAR_CHUNKS chunks per workgroup.
+// Wavelength chunks one workgroup of the fused contraction walks, which
+// amortises the per-workgroup set-up against load balance: two for float32
+// (measured: 1.5% faster than one, three no better, four slower), four for
+// bfloat16, whose chunks are cheaper.  The adjoint's Lbar kernel groups
+// LBAR_CHUNKS chunks per workgroup.
 __host__ __device__ constexpr int chunks_per_group(int precision) {
-  return precision == DSPS_BF16 ? 4 : 1;
+  return precision == DSPS_BF16 ? 4 : 2;
 }
 constexpr int LBAR_CHUNKS = 4;
 constexpr int SORT_BINS = 8192;    // keys of the ordering sort (4+4-bit rows, 5-bit z bucket)

@@ -559,13 +559,19 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
       v_end = vn_end;
       if (base + SFR_ROUND < n_seg) load_round(base + SFR_ROUND);
     } else {
-#pragma unroll
-      for (int k = 0; k < SFR_PER_LANE; ++k) {
-        const int n = n0 + k;
-        v[k] = n < n_t ? sfr_param(tt[n], pa, ptau, palpha, pq, ptq) : 0.0;
+      // the round's nodes inside the grid, evaluated node-major (lane l takes
+      // nodes base + l + 64 q, so a short grid costs few evaluations) into
+      // the wave's buffer, then read back in the scan's order
+      const int n_here = min(SFR_ROUND + 1, n_t - base);
+      for (int q = 0; q * 64 < n_here; ++q) {
+        const int j = q * 64 + lane;
+        if (j < n_here) s_pre[pre_slot(j)] = sfr_param(tt[base + j], pa, ptau, palpha, pq, ptq);
       }
-      const int n_end = base + SFR_ROUND;
-      v_end = n_end < n_t ? sfr_param(tt[n_end], pa, ptau, palpha, pq, ptq) : 0.0;
+      wave_sync();
+#pragma unroll
+      for (int k = 0; k < SFR_PER_LANE; ++k)
+        v[k] = SFR_PER_LANE * lane + k < n_here ? s_pre[k * SFR_PRE_K + lane] : 0.0;
+      v_end = SFR_ROUND < n_here ? s_pre[pre_slot(SFR_ROUND)] : 0.0;
     }
     double after = dpp_f64<DPP_WAVE_SHL1>(v[0]);      // SFR at node n0 + SFR_PER_LANE
     if (lane == 63) after = v_end;

@@ -621,11 +621,32 @@ __global__ __launch_bounds__(FINALIZE_THREADS) void k_mags_finalize(FinalizeLaun
   const TilePlan &pl = a.plan[tile];
   const int c_first = pl.c_first, c_last = pl.c_last;
   const int n_el = nvalid * nc;
-  for (int e = threadIdx.x; e < n_el; e += FINALIZE_THREADS) {
-    float v = 0.0f;
-    for (int c = c_first; c < c_last; ++c)
-      v += a.partial[((size_t)c * a.part_rows + g0) * nc + e];
-    s_sum[e] = v;
+  // each thread sums up to FIN_ELEMS elements FINALIZE_THREADS apart, taking
+  // FIN_CHUNKS chunks at a time: all their loads are issued before the first
+  // add, and every element's sum still runs in chunk order
+  constexpr int FIN_ELEMS = 8, FIN_CHUNKS = 8;
+  for (int e0 = threadIdx.x; e0 < n_el; e0 += FINALIZE_THREADS * FIN_ELEMS) {
+    float v[FIN_ELEMS];
+#pragma unroll
+    for (int i = 0; i < FIN_ELEMS; ++i) v[i] = 0.0f;
+    for (int c0 = c_first; c0 < c_last; c0 += FIN_CHUNKS) {
+      float x[FIN_CHUNKS][FIN_ELEMS];
+#pragma unroll
+      for (int k = 0; k < FIN_CHUNKS; ++k) {
+        const float *p = a.partial + ((size_t)(c0 + k) * a.part_rows + g0) * nc + e0;
+#pragma unroll
+        for (int i = 0; i < FIN_ELEMS; ++i)
+          x[k][i] = c0 + k < c_last && e0 + i * FINALIZE_THREADS < n_el ? p[i * FINALIZE_THREADS] : 0.0f;
+      }
+#pragma unroll
+      for (int k = 0; k < FIN_CHUNKS; ++k)
+        if (c0 + k < c_last)
+#pragma unroll
+          for (int i = 0; i < FIN_ELEMS; ++i) v[i] += x[k][i];
+    }
+#pragma unroll
+    for (int i = 0; i < FIN_ELEMS; ++i)
+      if (e0 + i * FINALIZE_THREADS < n_el) s_sum[e0 + i * FINALIZE_THREADS] = v[i];
   }
   __syncthreads();
   if ((int)threadIdx.x >= nvalid) return;

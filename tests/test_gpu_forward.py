@@ -57,12 +57,16 @@ def test_sfh_table_matches_oracle(dev):
     np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-300)
 
 
+# time grids of one scan round (100), one full round plus its closing node
+# (257), a second round of one segment (258) and four rounds, the last partial
+# (1000), for the table and the parametric history
+@pytest.mark.parametrize("n_t", [100, 257, 258, 1000])
 @pytest.mark.parametrize("use_params", [False, True])
-def test_weights_match_oracle(dev, small, use_params):
+def test_weights_match_oracle(dev, small, use_params, n_t):
     ssp_h, _, ssp = small
-    pop = _pop(131, seed=7)
+    pop = _pop(131, seed=7, n_t=n_t)
     inp = oracle_inputs(ssp, pop)
-    _say(f"weights n_gal=131 use_params={use_params}")
+    _say(f"weights n_gal=131 n_t={n_t} use_params={use_params}")
     dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr, use_params=use_params)
     w, ms = dev.weights(ssp_h, dev.Cosmology(), dp, with_mstar=True)
     w = w.cpu().numpy().astype(np.float64)
@@ -106,11 +110,12 @@ def test_mags_fp32_small_workload(dev, small):
     np.testing.assert_allclose(b[:, 1, :], den, rtol=2e-5)
 
 
-def test_mags_params_path_matches_table_path(dev, small):
+@pytest.mark.parametrize("n_t", [100, 300])
+def test_mags_params_path_matches_table_path(dev, small, n_t):
     ssp_h, flt_h, ssp = small
-    pop = _pop(100, seed=2)
+    pop = _pop(100, seed=2, n_t=n_t)
     inp = oracle_inputs(ssp, pop)
-    _say("mags fp32 params path n_gal=100")
+    _say(f"mags fp32 params path n_gal=100 n_t={n_t}")
     dp = dev.DevicePopulation.from_synth(pop, use_params=True)
     m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
     assert max_abs(m, oracle.mags(inp)) < FP32_TOL_MAG

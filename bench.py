@@ -648,18 +648,19 @@ def main():
     args = ap.parse_args()
 
     if args.pmc_pass:
-        # A short run for hardware-counter collection: the FP32 workload for a
-        # few steps, then a device copy of known size whose FETCH_SIZE and
+        # A short run for hardware-counter collection: one leg's workload for
+        # enough steps that the first (cold) launch weighs little in the
+        # trace average, then a device copy of known size whose FETCH_SIZE and
         # WRITE_SIZE calibrate the counters (bytes read = bytes written =
         # CALIBRATION_BYTES).
         import torch
         import paper_2112_06830_amd as P
         if args.pmc_pass == "fp32_1e5":
-            run_workload(P, "fwd_fp32_1e5", 100_000, 100, "fp32", 3, 1, seed=3, want_roofline=False)
+            run_workload(P, "fwd_fp32_1e5", 100_000, 100, "fp32", 12, 2, seed=3, want_roofline=False)
         elif args.pmc_pass == "bf16_1e6":
-            run_workload(P, "fwd_bf16_1e6", 1_000_000, 1000, "bf16", 3, 1, seed=4, want_roofline=False)
+            run_workload(P, "fwd_bf16_1e6", 1_000_000, 1000, "bf16", 5, 1, seed=4, want_roofline=False)
         else:
-            run_grad(P, 3, 1)
+            run_grad(P, 6, 1)
         n = CALIBRATION_BYTES // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -430,6 +430,29 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   }
 }
 
+// A wave's reduction (OP 0: bitwise or, 1: minimum, 2: maximum of ints),
+// left in lane 63 and read from there: prefix steps within rows of 16 lanes,
+// then row broadcasts.  A lane whose source is outside its row keeps its own
+// value, which every OP leaves unchanged.
+template <int OP>
+__device__ __forceinline__ int plan_op(int x, int y) {
+  return OP == 0 ? (x | y) : (OP == 1 ? min(x, y) : max(x, y));
+}
+template <int OP, int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int plan_step(int x) {
+  return plan_op<OP>(x, __builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xf, false));
+}
+template <int OP>
+__device__ __forceinline__ int plan_wave_reduce(int x) {
+  x = plan_step<OP, 0x111>(x);         // row_shr:1
+  x = plan_step<OP, 0x112>(x);         // row_shr:2
+  x = plan_step<OP, 0x114>(x);         // row_shr:4
+  x = plan_step<OP, 0x118>(x);         // row_shr:8
+  x = plan_step<OP, 0x142, 0xa>(x);    // row_bcast:15
+  x = plan_step<OP, 0x143, 0xc>(x);    // row_bcast:31
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
 // One workgroup of TILE_G threads per tile: union of the members' windows,
 // redshifts and non-zero weight blocks, then the unit list, ascending in K:
 // a float32 unit is one 4-age block of a row and a bfloat16 unit two (16
@@ -440,40 +463,67 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
 // and its last stage tagged with one of its ages.
 template <int PREC>
 __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
-  // window lo, window hi, min and max of (1+z) as float bits (positive floats
-  // order like their bit patterns)
-  __shared__ int s_tile[7];   // + highest non-zero age (age-major stages), ionization points
+  // per wave: window lo, window hi, min and max of (1+z) as float bits
+  // (positive floats order like their bit patterns), highest non-zero age
+  // (age-major stages), first and last ionization point, then the block mask
+  constexpr int NV = 7;
+  __shared__ int s_wave[TILE_G / 64][NV + KBLOCK_WORDS];
+  __shared__ int s_tile[NV];
   __shared__ unsigned s_kblk[KBLOCK_WORDS];
   const int tile = blockIdx.x;
   const int g0 = tile * TILE_G;
   const int nvalid = min(TILE_G, live_in_range(a.n_live, a.s_begin, a.s_count) - g0);
   if (nvalid <= 0) return;   // past the live galaxies: no reader looks at this plan
-  if (threadIdx.x == 0) {
-    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0; s_tile[4] = 0;
-    s_tile[5] = a.ion ? 1 << 30 : 0; s_tile[6] = 0;
-  }
-  if (threadIdx.x < KBLOCK_WORDS) s_kblk[threadIdx.x] = 0u;
-  __syncthreads();
-  if ((int)threadIdx.x < nvalid) {
-    const GalaxyRange r = a.range[a.s_begin + g0 + threadIdx.x];
-    const int zbits = __float_as_int(a.meta[a.s_begin + g0 + threadIdx.x].zp1);
-    atomicMin(&s_tile[0], r.win_lo);
-    atomicMax(&s_tile[1], r.win_hi);
-    atomicMin(&s_tile[2], zbits);
-    atomicMax(&s_tile[3], zbits);
-    atomicMax(&s_tile[4], r.age_hi);
-    if (a.ion) {
-      const GalaxyIon gi = a.ion[a.s_begin + g0 + threadIdx.x];
-      atomicMin(&s_tile[5], gi.u_lo);
-      atomicMax(&s_tile[6], gi.u_hi);
-    }
+  // each wave reduces its members (lanes past the tile's last galaxy hold
+  // the identities), the two waves' results are joined in LDS: no atomics
+  {
+    const int wave = threadIdx.x >> 6;
+    const bool live = (int)threadIdx.x < nvalid;
+    GalaxyRange r;
+    int zbits = 0x7f7fffff, zhi = 0, u_lo = 1 << 30, u_hi = 0;
+    if (live) {
+      r = a.range[a.s_begin + g0 + threadIdx.x];
+      zbits = zhi = __float_as_int(a.meta[a.s_begin + g0 + threadIdx.x].zp1);
+      if (a.ion) {
+        const GalaxyIon gi = a.ion[a.s_begin + g0 + threadIdx.x];
+        u_lo = gi.u_lo;
+        u_hi = gi.u_hi;
+      }
+    } else {
+      r.win_lo = 1 << 30;
+      r.win_hi = 0;
+      r.age_hi = 0;
 #pragma unroll
-    for (int w = 0; w < KBLOCK_WORDS; ++w)
-      if (r.kblk[w]) atomicOr(&s_kblk[w], r.kblk[w]);
+      for (int w = 0; w < KBLOCK_WORDS; ++w) r.kblk[w] = 0u;
+    }
+    int v[NV + KBLOCK_WORDS];
+    v[0] = plan_wave_reduce<1>(r.win_lo);
+    v[1] = plan_wave_reduce<2>(r.win_hi);
+    v[2] = plan_wave_reduce<1>(zbits);
+    v[3] = plan_wave_reduce<2>(zhi);
+    v[4] = plan_wave_reduce<2>(r.age_hi);
+    v[5] = a.ion ? plan_wave_reduce<1>(u_lo) : 0;
+    v[6] = a.ion ? plan_wave_reduce<2>(u_hi) : 0;
+#pragma unroll
+    for (int w = 0; w < KBLOCK_WORDS; ++w) v[NV + w] = plan_wave_reduce<0>((int)r.kblk[w]);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < NV + KBLOCK_WORDS; ++k)
+      if (lane == k) s_wave[wave][k] = v[k];
   }
   __syncthreads();
-  if (threadIdx.x >= 64) return;   // wave 0 writes the plan
+  if (threadIdx.x >= 64) return;   // wave 0 joins the waves and writes the plan
   const int lane = threadIdx.x;
+  static_assert(TILE_G == 128, "two waves per plan block");
+  if (lane < NV + KBLOCK_WORDS) {
+    const int x = s_wave[0][lane], y = s_wave[1][lane];
+    const bool is_min = lane == 0 || lane == 2 || lane == 5;
+    const int j = lane < NV ? (is_min ? min(x, y) : max(x, y)) : (x | y);
+    if (lane < NV) s_tile[lane] = j; else s_kblk[lane - NV] = (unsigned)j;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   TilePlan *pl = a.plan + tile;
   const int n_met = a.ssp.n_met;
   if (a.age_dust) {

@@ -360,6 +360,31 @@ struct AgeFold {
   }
 };
 
+// A wave's reduction of one int per lane (bitwise or, minimum or maximum),
+// left in lane 63 and read from there: prefix steps within rows of 16 lanes,
+// then row broadcasts.  A lane whose source is outside its row keeps its own
+// value, which every operation leaves unchanged.  Every lane of the wave must
+// be active.
+enum { WAVE_OR, WAVE_MIN, WAVE_MAX };
+template <int OP>
+__device__ __forceinline__ int wave_join_op(int x, int y) {
+  return OP == WAVE_OR ? (x | y) : (OP == WAVE_MIN ? min(x, y) : max(x, y));
+}
+template <int OP, int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int wave_join_step(int x) {
+  return wave_join_op<OP>(x, __builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xf, false));
+}
+template <int OP>
+__device__ __forceinline__ int wave_join(int x) {
+  x = wave_join_step<OP, 0x111>(x);         // row_shr:1
+  x = wave_join_step<OP, 0x112>(x);         // row_shr:2
+  x = wave_join_step<OP, 0x114>(x);         // row_shr:4
+  x = wave_join_step<OP, 0x118>(x);         // row_shr:8
+  x = wave_join_step<OP, 0x142, 0xa>(x);    // row_bcast:15
+  x = wave_join_step<OP, 0x143, 0xc>(x);    // row_bcast:31
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
 // Bands whose support meets the observed wavelengths [o_lo, o_hi] (with a
 // relative margin far above float rounding): any band left out has zero
 // transmission for every element of the chunk, so skipping it is exact.

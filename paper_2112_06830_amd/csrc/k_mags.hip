@@ -430,29 +430,6 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   }
 }
 
-// A wave's reduction (OP 0: bitwise or, 1: minimum, 2: maximum of ints),
-// left in lane 63 and read from there: prefix steps within rows of 16 lanes,
-// then row broadcasts.  A lane whose source is outside its row keeps its own
-// value, which every OP leaves unchanged.
-template <int OP>
-__device__ __forceinline__ int plan_op(int x, int y) {
-  return OP == 0 ? (x | y) : (OP == 1 ? min(x, y) : max(x, y));
-}
-template <int OP, int CTRL, int ROW_MASK = 0xf>
-__device__ __forceinline__ int plan_step(int x) {
-  return plan_op<OP>(x, __builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xf, false));
-}
-template <int OP>
-__device__ __forceinline__ int plan_wave_reduce(int x) {
-  x = plan_step<OP, 0x111>(x);         // row_shr:1
-  x = plan_step<OP, 0x112>(x);         // row_shr:2
-  x = plan_step<OP, 0x114>(x);         // row_shr:4
-  x = plan_step<OP, 0x118>(x);         // row_shr:8
-  x = plan_step<OP, 0x142, 0xa>(x);    // row_bcast:15
-  x = plan_step<OP, 0x143, 0xc>(x);    // row_bcast:31
-  return __builtin_amdgcn_readlane(x, 63);
-}
-
 // One workgroup of TILE_G threads per tile: union of the members' windows,
 // redshifts and non-zero weight blocks, then the unit list, ascending in K:
 // a float32 unit is one 4-age block of a row and a bfloat16 unit two (16
@@ -497,15 +474,15 @@ __global__ __launch_bounds__(TILE_G) void k_tile_plan(MagsLaunch a) {
       for (int w = 0; w < KBLOCK_WORDS; ++w) r.kblk[w] = 0u;
     }
     int v[NV + KBLOCK_WORDS];
-    v[0] = plan_wave_reduce<1>(r.win_lo);
-    v[1] = plan_wave_reduce<2>(r.win_hi);
-    v[2] = plan_wave_reduce<1>(zbits);
-    v[3] = plan_wave_reduce<2>(zhi);
-    v[4] = plan_wave_reduce<2>(r.age_hi);
-    v[5] = a.ion ? plan_wave_reduce<1>(u_lo) : 0;
-    v[6] = a.ion ? plan_wave_reduce<2>(u_hi) : 0;
+    v[0] = wave_join<WAVE_MIN>(r.win_lo);
+    v[1] = wave_join<WAVE_MAX>(r.win_hi);
+    v[2] = wave_join<WAVE_MIN>(zbits);
+    v[3] = wave_join<WAVE_MAX>(zhi);
+    v[4] = wave_join<WAVE_MAX>(r.age_hi);
+    v[5] = a.ion ? wave_join<WAVE_MIN>(u_lo) : 0;
+    v[6] = a.ion ? wave_join<WAVE_MAX>(u_hi) : 0;
 #pragma unroll
-    for (int w = 0; w < KBLOCK_WORDS; ++w) v[NV + w] = plan_wave_reduce<0>((int)r.kblk[w]);
+    for (int w = 0; w < KBLOCK_WORDS; ++w) v[NV + w] = wave_join<WAVE_OR>((int)r.kblk[w]);
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 0; k < NV + KBLOCK_WORDS; ++k)

@@ -61,7 +61,8 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
   __shared__ float s_gam[TILE_G * DSPS_MAX_BAND];
   __shared__ float4 s_meta[TILE_G];    // (1 + z, dust_a, delta, bump)
   __shared__ float2 s_grid[DSPS_MAX_BAND];
-  __shared__ int s_tile[4];            // window lo, window hi, min and max of (1+z) bits
+  // per member wave: window lo, window hi, min and max of (1+z) bits
+  __shared__ int s_tile[TILE_G / 64][4];
   extern __shared__ float s_tr[];      // filter transmissions [n_band][n_pts + 1]
   const int group = blockIdx.x, tile = blockIdx.y;
   const SspView P = a.ssp;
@@ -72,21 +73,33 @@ __global__ __launch_bounds__(256) void k_vjp_lbar(VjpLaunch a) {
   if (nvalid <= 0) return;   // the whole workgroup, before any barrier
   const int nwp = P.n_wave_pad;
 
-  if (threadIdx.x == 0) { s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 0x7f7fffff; s_tile[3] = 0; }
-  __syncthreads();
-  if (threadIdx.x < nvalid) {
-    const GalaxyRange r = a.range[a.s_begin + g0 + threadIdx.x];
-    const GalaxyMeta m = a.meta[a.s_begin + g0 + threadIdx.x];
-    atomicMin(&s_tile[0], r.win_lo);
-    atomicMax(&s_tile[1], r.win_hi);
-    atomicMin(&s_tile[2], __float_as_int(m.zp1));
-    atomicMax(&s_tile[3], __float_as_int(m.zp1));
-    s_meta[threadIdx.x] = make_float4(m.zp1, m.dust_a, m.delta, m.bump);
+  // the tile's union: the waves holding its members reduce them (lanes past
+  // the last member hold the identities) and the results join in LDS
+  if (threadIdx.x < TILE_G) {
+    int lo = 1 << 30, hi = 0, zlo = 0x7f7fffff, zhi = 0;
+    if ((int)threadIdx.x < nvalid) {
+      const int s = a.s_begin + g0 + threadIdx.x;
+      const GalaxyMeta m = a.meta[s];
+      lo = a.range[s].win_lo;
+      hi = a.range[s].win_hi;
+      zlo = zhi = __float_as_int(m.zp1);
+      s_meta[threadIdx.x] = make_float4(m.zp1, m.dust_a, m.delta, m.bump);
+    }
+    lo = wave_join<WAVE_MIN>(lo);
+    hi = wave_join<WAVE_MAX>(hi);
+    zlo = wave_join<WAVE_MIN>(zlo);
+    zhi = wave_join<WAVE_MAX>(zhi);
+    if ((threadIdx.x & 63) == 0) {
+      int *t = s_tile[threadIdx.x >> 6];
+      t[0] = lo; t[1] = hi; t[2] = zlo; t[3] = zhi;
+    }
   }
   __syncthreads();
-  const int c_first = s_tile[0] / TILE_L;
-  const int c_last = (s_tile[1] + TILE_L - 1) / TILE_L;
-  const float zp1_min = __int_as_float(s_tile[2]), zp1_max = __int_as_float(s_tile[3]);
+  static_assert(TILE_G == 128, "two member waves per tile");
+  const int c_first = min(s_tile[0][0], s_tile[1][0]) / TILE_L;
+  const int c_last = (max(s_tile[0][1], s_tile[1][1]) + TILE_L - 1) / TILE_L;
+  const float zp1_min = __int_as_float(min(s_tile[0][2], s_tile[1][2]));
+  const float zp1_max = __int_as_float(max(s_tile[0][3], s_tile[1][3]));
   const int c_begin = max(group * LBAR_CHUNKS, c_first);
   const int c_end = min((group + 1) * LBAR_CHUNKS, c_last);
   if (c_begin >= c_end) return;
@@ -393,8 +406,9 @@ __host__ __device__ inline int wbar_row_blocks(int n_met, int n_age) {
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar_rows(VjpLaunch a) {
   using C = GemmCfg<DSPS_FP32>;
   __shared__ GemmSmem<DSPS_FP32> sm[2];
-  // window lo, window hi, lowest and highest j_lo, highest j_top, ages with mass
-  __shared__ int s_tile[6];
+  // per member wave: window lo, window hi, lowest and highest j_lo, highest
+  // j_top, ages with mass
+  __shared__ int s_wave[TILE_G / 64][6];
   __shared__ int s_jlo[TILE_G];
   const SspView P = a.ssp;
   int tile, kb;
@@ -408,40 +422,50 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar_rows(VjpLaunch a) 
   const int nvalid = min(TILE_G, live - g0);
   const int nwp = P.n_wave_pad;
 
-  if (threadIdx.x == 0) {
-    s_tile[0] = 1 << 30; s_tile[1] = 0; s_tile[2] = 1 << 30; s_tile[3] = 0; s_tile[4] = 0;
-    s_tile[5] = 0;
+  // the tile's union: the waves holding its members reduce them (lanes past
+  // the last member hold the identities) and the results join in LDS
+  if (threadIdx.x < TILE_G) {
+    int v[6] = {1 << 30, 0, 1 << 30, 0, 0, 0};
+    if ((int)threadIdx.x < nvalid) {
+      const int s = a.s_begin + g0 + threadIdx.x;
+      const int g = a.perm[s];
+      const bool transition = a.lgmet_old != nullptr;
+      const double lgmet = (double)a.lgmet[g], old = transition ? (double)a.lgmet_old[g] : 0.0;
+      const double sig = (double)a.sigma_z[g];
+      const int j_lo = support_bottom_row(P, lgmet, transition, old, a.slope, a.pivot, a.mdf_width, sig);
+      s_jlo[threadIdx.x] = j_lo;
+      v[0] = a.range[s].win_lo;
+      v[1] = a.range[s].win_hi;
+      v[2] = v[3] = j_lo;
+      v[4] = support_top_row(P, lgmet, transition, old, a.slope, a.pivot, a.mdf_width, sig);
+      v[5] = ages_with_mass(P, a.t_obs[s], a.t_table[0]);
+    }
+    v[0] = wave_join<WAVE_MIN>(v[0]);
+    v[1] = wave_join<WAVE_MAX>(v[1]);
+    v[2] = wave_join<WAVE_MIN>(v[2]);
+#pragma unroll
+    for (int k = 3; k < 6; ++k) v[k] = wave_join<WAVE_MAX>(v[k]);
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) s_wave[wave][k] = v[k];
   }
   __syncthreads();
-  if (threadIdx.x < nvalid) {
-    const int s = a.s_begin + g0 + threadIdx.x;
-    const GalaxyRange r = a.range[s];
-    const int g = a.perm[s];
-    const bool transition = a.lgmet_old != nullptr;
-    const double lgmet = (double)a.lgmet[g], old = transition ? (double)a.lgmet_old[g] : 0.0;
-    const double sig = (double)a.sigma_z[g];
-    const int j_lo = support_bottom_row(P, lgmet, transition, old, a.slope, a.pivot, a.mdf_width, sig);
-    const int j_top = support_top_row(P, lgmet, transition, old, a.slope, a.pivot, a.mdf_width, sig);
-    s_jlo[threadIdx.x] = j_lo;
-    atomicMin(&s_tile[0], r.win_lo);
-    atomicMax(&s_tile[1], r.win_hi);
-    atomicMin(&s_tile[2], j_lo);
-    atomicMax(&s_tile[3], j_lo);
-    atomicMax(&s_tile[4], j_top);
-    atomicMax(&s_tile[5], ages_with_mass(P, a.t_obs[s], a.t_table[0]));
-  }
-  __syncthreads();
-  const int n_ages = s_tile[5];
-  const int j_lo = s_tile[2];
-  const int n_plain = (s_tile[3] - j_lo + 1) * n_ages;     // plain rows come first
-  const int n_rows = n_plain + max(s_tile[4] - j_lo, 0) * n_ages;
+  static_assert(TILE_G == 128, "two member waves per tile");
+  int tu[6];   // the tile's union, as listed for s_wave
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    tu[k] = k == 0 || k == 2 ? min(s_wave[0][k], s_wave[1][k]) : max(s_wave[0][k], s_wave[1][k]);
+  const int n_ages = tu[5];
+  const int j_lo = tu[2];
+  const int n_plain = (tu[3] - j_lo + 1) * n_ages;     // plain rows come first
+  const int n_rows = n_plain + max(tu[4] - j_lo, 0) * n_ages;
   const int r0 = kb * TILE_L;
   if (r0 >= n_rows) return;      // the whole block: nothing needed here
   // the members' window union on whole K steps: Lbar is zero outside every
   // member's window, and steps keep each MFMA step pair at the same
   // wavelengths whatever the tile
-  const int l_begin = (s_tile[0] / C::KT) * C::KT;
-  const int l_end = ((s_tile[1] + C::KT - 1) / C::KT) * C::KT;
+  const int l_begin = (tu[0] / C::KT) * C::KT;
+  const int l_end = ((tu[1] + C::KT - 1) / C::KT) * C::KT;
   // needed row r -> metallicity row j and age i
   auto row_of = [&](int r, int &j, int &i) {
     const int q = r < n_plain ? r : r - n_plain;

@@ -206,9 +206,9 @@ template <bool NEB>
 __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   using C = GemmCfg<DSPS_FP32>;
   __shared__ GemmSmem<DSPS_FP32> sm[2];
-  __shared__ int s_tile[2];
-  __shared__ int s_jhi;          // highest metallicity row in some member's MDF support
-  __shared__ int s_urange[2];    // NEB: the members' ionization points
+  // per member wave: window lo, window hi, highest metallicity row in some
+  // member's MDF support, NEB: first and last ionization point
+  __shared__ int s_wave[TILE_G / 64][5];
   // NEB: per point and column the weight, its derivatives in centre and width
   __shared__ float s_pn[NEB ? 3 * DSPS_MAX_ION * TILE_G : 1];
   __shared__ float s_ured[NEB ? 2 * TILE_G : 1];
@@ -221,34 +221,45 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
   if (nvalid <= 0) return;   // the whole workgroup, before any barrier
   const int nwp = P.n_wave_pad;
 
-  if (threadIdx.x == 0) {
-    s_tile[0] = 1 << 30; s_tile[1] = 0; s_jhi = 0;
-    s_urange[0] = NEB ? 1 << 30 : 0; s_urange[1] = 0;
-  }
-  __syncthreads();
-  if (threadIdx.x < nvalid) {
-    const int s = a.s_begin + g0 + threadIdx.x;
-    const GalaxyRange r = a.range[s];
-    atomicMin(&s_tile[0], r.win_lo);
-    atomicMax(&s_tile[1], r.win_hi);
-    if (NEB) {
-      atomicMin(&s_urange[0], a.ion[s].u_lo);
-      atomicMax(&s_urange[1], a.ion[s].u_hi);
+  // the tile's union: the waves holding its members reduce them (lanes past
+  // the last member hold the identities) and the results join in LDS
+  if (threadIdx.x < TILE_G) {
+    int v[5] = {1 << 30, 0, 0, NEB ? 1 << 30 : 0, 0};
+    if ((int)threadIdx.x < nvalid) {
+      const int s = a.s_begin + g0 + threadIdx.x;
+      v[0] = a.range[s].win_lo;
+      v[1] = a.range[s].win_hi;
+      if (NEB) {
+        v[3] = a.ion[s].u_lo;
+        v[4] = a.ion[s].u_hi;
+      }
+      const int g = a.perm[s];
+      const bool transition = a.lgmet_old != nullptr;
+      v[2] = support_top_row(P, (double)a.lgmet[g], transition,
+                             transition ? (double)a.lgmet_old[g] : 0.0, a.slope, a.pivot,
+                             a.mdf_width, (double)a.sigma_z[g]);
     }
-    const int g = a.perm[s];
-    const bool transition = a.lgmet_old != nullptr;
-    atomicMax(&s_jhi, support_top_row(P, (double)a.lgmet[g], transition,
-                                      transition ? (double)a.lgmet_old[g] : 0.0, a.slope, a.pivot,
-                                      a.mdf_width, (double)a.sigma_z[g]));
+    v[0] = wave_join<WAVE_MIN>(v[0]);
+    v[1] = wave_join<WAVE_MAX>(v[1]);
+    v[2] = wave_join<WAVE_MAX>(v[2]);
+    v[3] = wave_join<WAVE_MIN>(v[3]);
+    v[4] = wave_join<WAVE_MAX>(v[4]);
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) s_wave[wave][k] = v[k];
   }
   __syncthreads();
+  static_assert(TILE_G == 128, "two member waves per tile");
+  // the tile's union, as listed for s_wave
+  const int win_lo = min(s_wave[0][0], s_wave[1][0]), win_hi = max(s_wave[0][1], s_wave[1][1]);
+  const int u_first = min(s_wave[0][3], s_wave[1][3]), u_last = max(s_wave[0][4], s_wave[1][4]);
   // the members' window union on whole K steps: Lbar is zero outside every
   // member's window, and steps keep each MFMA step pair at the same
   // wavelengths whatever the tile
-  const int l_begin = (s_tile[0] / C::KT) * C::KT;
-  const int l_end = ((s_tile[1] + C::KT - 1) / C::KT) * C::KT;
+  const int l_begin = (win_lo / C::KT) * C::KT;
+  const int l_end = ((win_hi + C::KT - 1) / C::KT) * C::KT;
   const int k0 = kblk * TILE_L;
-  const int j_hi = s_jhi;
+  const int j_hi = max(s_wave[0][2], s_wave[1][2]);
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -260,7 +271,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
 
   const int nk = (l_end > l_begin && k0 / AGE_PAD <= j_hi) ? (l_end - l_begin) / C::KT : 0;
   if constexpr (NEB) {
-    const int u_lo = s_urange[0], n_uu = s_urange[1] - s_urange[0] + 1;
+    const int u_lo = u_first, n_uu = u_last - u_first + 1;
     const int plane = n_uu * TILE_G;
     for (int t = threadIdx.x; t < plane; t += blockDim.x) {
       const int uu = t / TILE_G, col = t - uu * TILE_G;

@@ -94,6 +94,27 @@ __device__ int first_index(const double *x, int n, double v) {
   }
   return lo;
 }
+// The same from a first guess: the index a log-uniform grid would hold v at
+// (lx0 = ln x[0], inv_lspan = 1 / (ln x[n-1] - ln x[0])) is checked against
+// its neighbour, which on such a grid settles it in one round of loads;
+// otherwise a bisection finishes on the side the guess leaves.  The index is
+// the same either way (the predicate is monotone over the ascending array).
+template <bool STRICT>
+__device__ int first_index_guess(const double *x, int n, double v, double lx0, double inv_lspan) {
+  if (n <= 2 || !(v > 0.0)) return first_index<STRICT>(x, n, v);
+  const double f = (log(v) - lx0) * inv_lspan * (double)(n - 1);
+  const int g = (int)fmin(fmax(f, 0.0), (double)(n - 2));
+  const bool ok_g = STRICT ? x[g] > v : x[g] >= v;
+  const bool ok_next = STRICT ? x[g + 1] > v : x[g + 1] >= v;
+  if (!ok_g && ok_next) return g + 1;
+  int lo = ok_g ? 0 : g + 2, hi = ok_g ? g : n;   // the first index lies in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const bool ok = STRICT ? x[mid] > v : x[mid] >= v;
+    if (ok) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
 
 // Per-galaxy scalars, one thread per galaxy of the sorted range: cosmic time
 // at z for the weights kernel, the GEMM's constants (1 + z and the dust
@@ -147,8 +168,10 @@ __global__ __launch_bounds__(256) void k_galaxy_scalars(WeightsLaunch a) {
     // by two grid points on each side (points outside contribute exact
     // zeros; the padding covers float32 rounding of (1+z) lambda)
     const int n_wave = a.ssp.n_wave;
-    const int lo = first_index<false>(a.ssp.wave, n_wave, a.obs_lo / (1.0 + z));
-    const int hi = first_index<true>(a.ssp.wave, n_wave, a.obs_hi / (1.0 + z));
+    const double lx0 = log(a.ssp.wave[0]);
+    const double inv_lspan = 1.0 / (log(a.ssp.wave[n_wave - 1]) - lx0);
+    const int lo = first_index_guess<false>(a.ssp.wave, n_wave, a.obs_lo / (1.0 + z), lx0, inv_lspan);
+    const int hi = first_index_guess<true>(a.ssp.wave, n_wave, a.obs_hi / (1.0 + z), lx0, inv_lspan);
     GalaxyRange r;
     r.win_lo = max(lo - 2, 0);
     r.win_hi = min(hi + 2, n_wave);

@@ -895,7 +895,9 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   m.meta = meta;
   m.range = range;
   const int cpg = chunks_per_group(precision);
-  m.n_groups = std::min(L.n_groups, (max_window_chunks(ssp, filters) + cpg - 1) / cpg);
+  // groups aligned to multiples of cpg (float32): a window may straddle one more
+  const int pcg = partial_chunks(precision);
+  m.n_groups = std::min(L.n_groups, (max_window_chunks(ssp, filters) + cpg - 1) / cpg + (pcg > 1));
   m.n_chunks = L.n_chunks;
   m.moments = moments != nullptr;
   m.partial = partial;
@@ -911,6 +913,7 @@ static int mags_batch(const dsps_ssp *ssp, const dsps_filters *filters, const ds
   f.n_live = pop->n_live;
   f.partial = partial;
   f.part_rows = L.batch;
+  f.pcg = pcg;
   f.mag_offset = offset;
   f.perm = perm;
   f.moments = m.moments;

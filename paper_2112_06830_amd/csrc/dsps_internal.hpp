@@ -33,6 +33,14 @@ constexpr int TILE_L = 128;        // wavelengths per chunk (M of the MFMA tile)
 __host__ __device__ constexpr int chunks_per_group(int precision) {
   return precision == DSPS_BF16 ? 4 : 2;
 }
+// Chunks whose band sums one partial slot holds: the workgroup's whole group
+// in float32 (each later chunk adds its sums to the slot, and groups start at
+// multiples of their size, so a slot does not depend on the tile); one in
+// bfloat16, whose VALU-bound epilogue measured 13% slower waiting on the
+// slot's read.
+__host__ __device__ constexpr int partial_chunks(int precision) {
+  return precision == DSPS_BF16 ? 1 : chunks_per_group(precision);
+}
 constexpr int LBAR_CHUNKS = 4;
 constexpr int SORT_BINS = 8192;    // keys of the ordering sort (4+4-bit rows, 5-bit z bucket)
 constexpr int GEMM_THREADS = 256;  // 4 wave64s in a 2 x 2 arrangement
@@ -432,11 +440,12 @@ struct MagsLaunch {
   int n_groups;                  // workgroups per tile (upper bound on its chunk groups)
   int n_chunks;                  // n_wave_pad / TILE_L
   int moments;                   // also the three dust moments per band (float32 only)
-  // [n_chunks][part_rows][ncomp * n_band], chunk-major, written for the chunks
-  // of each tile's window; components num, den and, with moments, the three
-  // dust moments
+  // [n_chunks / partial_chunks][part_rows][ncomp * n_band], slot-major: the
+  // sums over the chunks of each slot (partial_chunks whole chunks from a
+  // multiple of it) inside each tile's window; components num, den and, with
+  // moments, the three dust moments
   float *partial;
-  int part_rows;                 // galaxy rows per chunk (>= s_count)
+  int part_rows;                 // galaxy rows per partial slot (>= s_count)
   TilePlan *plan;                // [n_tiles], written by the planning pass
 };
 // Components per band of the chunk partials.
@@ -454,7 +463,8 @@ struct FinalizeLaunch {
   const TilePlan *plan;
   const double *mag_offset;
   const int *perm;
-  int part_rows;  // galaxy rows per chunk of the partials
+  int part_rows;  // galaxy rows per slot of the partials
+  int pcg;        // chunks per partial slot (partial_chunks)
   int moments;    // partials carry the dust moments
   float *mags;    // [n_gal][n_band] by galaxy index
   float *bands;   // [n_gal][2][n_band] or null

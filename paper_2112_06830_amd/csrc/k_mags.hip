@@ -32,14 +32,14 @@ constexpr int EPI_ROWS = 2;
 
 // Per-galaxy sums of one chunk for bands base .. base + NS - 1, NCOMP
 // components each, reduced over the two lane halves and the two row-waves of
-// each column block and written to the chunk's partial slot (component c of
-// band b at c * n_band + b).  s_red aliases the operand staging area: the
+// each column block and stored to (or, with add, added to) the chunk's
+// partial slot (component c of band b at c * n_band + b).  s_red aliases the operand staging area: the
 // leading barrier orders these writes after every wave's last MFMA read and
 // after the previous pass's reads.
 template <int NCOMP, int NS>
 __device__ __forceinline__ void write_band_slots(float (&sum)[NCOMP][2][NS], int base, int n_band,
                                                  float *s_red, int wr, int wc, int lane, int nvalid,
-                                                 float *out_base, int stride) {
+                                                 float *out_base, int stride, bool add) {
   const int h = lane >> 5;
 #pragma unroll
   for (int c = 0; c < NCOMP; ++c)
@@ -75,7 +75,11 @@ __device__ __forceinline__ void write_band_slots(float (&sum)[NCOMP][2][NS], int
 #pragma unroll
           for (int k = 0; k < NS; ++k)
 #pragma unroll
-            for (int c = 0; c < NCOMP; ++c) out[c * n_band + base + k] = sum[c][nb][k] + red[c * NS + k];
+            for (int c = 0; c < NCOMP; ++c) {
+              const float v = sum[c][nb][k] + red[c * NS + k];
+              float *o = out + c * n_band + base + k;
+              *o = add ? *o + v : v;
+            }
         }
       }
     }
@@ -216,15 +220,22 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
   const int g0 = tile * TILE_G;                 // first batch-local galaxy of the tile
   const int nvalid = min(TILE_G, live - g0);
 
-  // ---- the tile's plan: groups are aligned to the tile's own window, all
-  // but the last full; the grid holds a host bound on one galaxy's window,
-  // and a tile whose members' windows spread further hands the remaining
-  // chunks to its last group
+  // ---- the tile's plan.  A workgroup takes a group of CPG chunks of the
+  // tile's window.  Where a partial slot holds a whole group (PCG = CPG),
+  // groups are CPG whole chunks from a multiple of CPG, clipped to the
+  // window: a slot's sum (its chunks in order; chunks outside a galaxy's own
+  // window add exact zeros) is then the same in any tile.  Otherwise groups
+  // start at the window's first chunk.  Workgroup `group` takes the tile's
+  // group-th group; the grid holds a host bound on one galaxy's window, and
+  // a tile whose members' windows spread further hands every remaining chunk
+  // to its last workgroup.
   const TilePlan *pl = a.plan + tile;
   const int c_first = pl->c_first, c_last = pl->c_last;
-  constexpr int CPG = chunks_per_group(PREC);
-  const int c_begin = c_first + group * CPG;
-  const int c_end = group == a.n_groups - 1 ? c_last : min(c_begin + CPG, c_last);
+  constexpr int CPG = chunks_per_group(PREC), PCG = partial_chunks(PREC);
+  static_assert(PCG == 1 || PCG == CPG, "a slot holds one chunk or a whole group");
+  const int c_base = PCG > 1 ? c_first / CPG * CPG : c_first;
+  const int c_begin = max(c_base + group * CPG, c_first);
+  const int c_end = group == a.n_groups - 1 ? c_last : min(c_base + (group + 1) * CPG, c_last);
   if (c_begin >= c_end) return;
   const int nk = pl->nk;
   const float zp1_min = pl->zp1_min, zp1_max = pl->zp1_max;
@@ -351,8 +362,10 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
     const unsigned imask = __builtin_amdgcn_readfirstlane(interior_bands(F, o_lo, o_hi));
     const int b_lo = bmask ? __builtin_ctz(bmask) : 0;
     const int b_hi = bmask ? 31 - __builtin_clz(bmask) : -1;   // inclusive
-    // partials are chunk-major: [chunk][galaxy][component]
-    float *part = a.partial + ((size_t)c * a.part_rows + g0) * n_comp;
+    // partials are slot-major, [slot][galaxy][component]: a slot's first
+    // chunk stores, each later one adds its sums in chunk order
+    float *part = a.partial + ((size_t)(c / PCG) * a.part_rows + g0) * n_comp;
+    const bool add = c != c_begin && c % PCG != 0;
     const int stride = n_comp;
     if (AGED && b_lo <= b_hi) {
       // the attenuation is in already: e = L_att q
@@ -394,7 +407,7 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
           band_pass<MOM, NCOMP, 3, true>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
         else
           band_pass<MOM, NCOMP, 3, false>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
-        write_band_slots<NCOMP, 3>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride);
+        write_band_slots<NCOMP, 3>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride, add);
         base += 3;
       } else if (rem == 2) {
         float sum[NCOMP][2][2];
@@ -402,7 +415,7 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
           band_pass<MOM, NCOMP, 2, true>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
         else
           band_pass<MOM, NCOMP, 2, false>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
-        write_band_slots<NCOMP, 2>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride);
+        write_band_slots<NCOMP, 2>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride, add);
         base += 2;
       } else {
         float sum[NCOMP][2][1];
@@ -410,12 +423,13 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
           band_pass<MOM, NCOMP, 1, true>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
         else
           band_pass<MOM, NCOMP, 1, false>(acc, E, F, s_tr, s_lc, s_q, base, wr, h, sum);
-        write_band_slots<NCOMP, 1>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride);
+        write_band_slots<NCOMP, 1>(sum, base, n_band, s_red, wr, wc, lane, nvalid, part, stride, add);
         base += 1;
       }
     }
-    // bands that see none of this chunk contribute exact zeros
-    if (wr == 0) {
+    // bands that see none of this chunk contribute exact zeros: stored by the
+    // slot's first chunk, nothing to add for a later one
+    if (wr == 0 && !add) {
       const int tcol = wc * 64 + h * 32 + (lane & 31);
       if (tcol < nvalid) {
         float *out = part + (size_t)tcol * stride;
@@ -646,11 +660,14 @@ __global__ __launch_bounds__(FINALIZE_THREADS) void k_mags_finalize(FinalizeLaun
   if (nvalid <= 0) return;   // the whole workgroup, before any barrier
   const int nb = a.n_band, ncomp = mags_components(a.moments), nc = ncomp * nb;
   const TilePlan &pl = a.plan[tile];
-  const int c_first = pl.c_first, c_last = pl.c_last;
+  // the partial slots of the tile's window (see k_mags_gemm); none if it is
+  // empty
+  const int c_first = pl.c_first / a.pcg;
+  const int c_last = pl.c_last > pl.c_first ? (pl.c_last - 1) / a.pcg + 1 : c_first;
   const int n_el = nvalid * nc;
   // each thread sums up to FIN_ELEMS elements FINALIZE_THREADS apart, taking
-  // FIN_CHUNKS chunks at a time: all their loads are issued before the first
-  // add, and every element's sum still runs in chunk order
+  // FIN_CHUNKS slots at a time: all their loads are issued before the first
+  // add, and every element's sum still runs in slot order
   constexpr int FIN_ELEMS = 8, FIN_CHUNKS = 8;
   for (int e0 = threadIdx.x; e0 < n_el; e0 += FINALIZE_THREADS * FIN_ELEMS) {
     float v[FIN_ELEMS];

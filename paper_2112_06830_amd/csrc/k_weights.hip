@@ -574,7 +574,6 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
   double carry = 0.0;
   double em[2] = {0.0, 0.0};
   for (int base = 0, round = 0; base < n_seg; base += SFR_ROUND, ++round) {
-    const int n0 = base + SFR_PER_LANE * lane;
     double v[SFR_PER_LANE], v_end;
     if (TABULATED) {
 #pragma unroll
@@ -596,7 +595,7 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
         v[k] = SFR_PER_LANE * lane + k < n_here ? s_pre[k * SFR_PRE_K + lane] : 0.0;
       v_end = SFR_ROUND < n_here ? s_pre[pre_slot(SFR_ROUND)] : 0.0;
     }
-    double after = dpp_f64<DPP_WAVE_SHL1>(v[0]);      // SFR at node n0 + SFR_PER_LANE
+    double after = dpp_f64<DPP_WAVE_SHL1>(v[0]);      // SFR at the next lane's first node
     if (lane == 63) after = v_end;
     const double *w = s_segw + base + lane;           // the lane's segment weights
     double part[SFR_PER_LANE];                        // local inclusive sums

@@ -195,6 +195,26 @@ def test_mags_deterministic_and_batch_independent(dev, large):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_mags_each_galaxy_alone_equals_batch(dev, large, precision):
+    """Each of a few galaxies across the redshift range, computed on its own
+    (its tile's window is then its own, starting at an odd or an even chunk),
+    is bitwise the same as inside the 700-galaxy batch, where its tile's
+    window is its z-sorted mates' union."""
+    ssp_h, flt_h, ssp = large
+    pop = _pop(700, seed=31, z_range=(0.1, 3.0))
+    inp = oracle_inputs(ssp, pop)
+    _say(f"mags each galaxy alone vs batch, {precision}")
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    m_all = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, precision=precision).cpu().numpy()
+    order = np.argsort(pop.z)
+    for i in order[np.linspace(0, pop.n_gal - 1, 9).astype(int)]:
+        sub = pop.subset(np.array([i]))
+        d1 = dev.DevicePopulation.from_synth(sub, sfr=inp.sfr[[i]])
+        m1 = dev.mags(ssp_h, flt_h, dev.Cosmology(), d1, precision=precision).cpu().numpy()
+        assert np.array_equal(m1[0], m_all[i]), (int(i), float(pop.z[i]))
+
+
 def test_mags_fp32_full_size_sampled(dev, large):
     """1e5 galaxies, 12x94x5994, z ~ U[0.1, 3] in one call (the FP32 bench
     configuration); 48 sampled galaxies against the oracle."""

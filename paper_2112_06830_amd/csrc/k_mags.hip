@@ -662,29 +662,29 @@ __global__ __launch_bounds__(FINALIZE_THREADS) void k_mags_finalize(FinalizeLaun
   const TilePlan &pl = a.plan[tile];
   // the partial slots of the tile's window (see k_mags_gemm); none if it is
   // empty
-  const int c_first = pl.c_first / a.pcg;
-  const int c_last = pl.c_last > pl.c_first ? (pl.c_last - 1) / a.pcg + 1 : c_first;
+  const int q_first = pl.c_first / a.pcg;
+  const int q_last = pl.c_last > pl.c_first ? (pl.c_last - 1) / a.pcg + 1 : q_first;
   const int n_el = nvalid * nc;
   // each thread sums up to FIN_ELEMS elements FINALIZE_THREADS apart, taking
-  // FIN_CHUNKS slots at a time: all their loads are issued before the first
+  // FIN_SLOTS slots at a time: all their loads are issued before the first
   // add, and every element's sum still runs in slot order
-  constexpr int FIN_ELEMS = 8, FIN_CHUNKS = 8;
+  constexpr int FIN_ELEMS = 8, FIN_SLOTS = 8;
   for (int e0 = threadIdx.x; e0 < n_el; e0 += FINALIZE_THREADS * FIN_ELEMS) {
     float v[FIN_ELEMS];
 #pragma unroll
     for (int i = 0; i < FIN_ELEMS; ++i) v[i] = 0.0f;
-    for (int c0 = c_first; c0 < c_last; c0 += FIN_CHUNKS) {
-      float x[FIN_CHUNKS][FIN_ELEMS];
+    for (int q0 = q_first; q0 < q_last; q0 += FIN_SLOTS) {
+      float x[FIN_SLOTS][FIN_ELEMS];
 #pragma unroll
-      for (int k = 0; k < FIN_CHUNKS; ++k) {
-        const float *p = a.partial + ((size_t)(c0 + k) * a.part_rows + g0) * nc + e0;
+      for (int k = 0; k < FIN_SLOTS; ++k) {
+        const float *p = a.partial + ((size_t)(q0 + k) * a.part_rows + g0) * nc + e0;
 #pragma unroll
         for (int i = 0; i < FIN_ELEMS; ++i)
-          x[k][i] = c0 + k < c_last && e0 + i * FINALIZE_THREADS < n_el ? p[i * FINALIZE_THREADS] : 0.0f;
+          x[k][i] = q0 + k < q_last && e0 + i * FINALIZE_THREADS < n_el ? p[i * FINALIZE_THREADS] : 0.0f;
       }
 #pragma unroll
-      for (int k = 0; k < FIN_CHUNKS; ++k)
-        if (c0 + k < c_last)
+      for (int k = 0; k < FIN_SLOTS; ++k)
+        if (q0 + k < q_last)
 #pragma unroll
           for (int i = 0; i < FIN_ELEMS; ++i) v[i] += x[k][i];
     }

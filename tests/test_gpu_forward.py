@@ -215,6 +215,27 @@ def test_mags_each_galaxy_alone_equals_batch(dev, large, precision):
         assert np.array_equal(m1[0], m_all[i]), (int(i), float(pop.z[i]))
 
 
+@pytest.mark.parametrize("n_gal", [77, 129])
+def test_mags_five_bands_unaligned_partial_slots(dev, n_gal):
+    """Five bands (10 partial components per galaxy, 25 with the dust
+    moments) and galaxy counts that leave a ragged last tile: FP32
+    magnitudes without and with the moments against the FP64 oracle, and the
+    moment instantiation's magnitudes equal to the plain ones bit for bit."""
+    ssp = ssp_large()
+    flt = synth.make_filters(n_band=5)
+    pop = synth.make_population(n_gal, n_t=100, z_range=(0.1, 3.0), seed=61, n_band=5)
+    inp = oracle.prepare_inputs(ssp, flt, pop)
+    _say(f"mags five bands n_gal={n_gal}")
+    ssp_h = dev.SspBlock.from_synth(ssp, precisions=("fp32",))
+    flt_h = dev.FilterBank.from_synth(flt)
+    dp = dev.DevicePopulation.from_synth(pop, sfr=inp.sfr)
+    ref = oracle.mags(inp)
+    m = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp).cpu().numpy()
+    assert max_abs(m, ref) < FP32_TOL_MAG
+    m2, _, _ = dev.mags(ssp_h, flt_h, dev.Cosmology(), dp, with_moments=True)
+    assert np.array_equal(m2.cpu().numpy(), m)
+
+
 def test_mags_fp32_full_size_sampled(dev, large):
     """1e5 galaxies, 12x94x5994, z ~ U[0.1, 3] in one call (the FP32 bench
     configuration); 48 sampled galaxies against the oracle."""

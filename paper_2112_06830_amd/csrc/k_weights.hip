@@ -277,43 +277,30 @@ __device__ __forceinline__ void mdf_edge_cdf(const MdfLane &L, int j, double e, 
     c1 = triweight_cdf((e - L.mu1) * L.inv_sig);
   }
 }
-enum { MDF_PAD_F32, MDF_USER };
-
 // W[j][i] = m_i (CDF(e_{j+1}) - CDF(e_j)) for the lane's two ages over every
-// metallicity row j, written in the layout of MODE; returns the rows in which
-// either weight is non-zero (as stored).
-template <int MODE, typename T>
-__device__ __forceinline__ unsigned mdf_rows(const MdfLane &L, T *out) {
-  const bool active = L.i0 < AGE_PAD;
+// metallicity row j, in float64 and rounded once, into the natural layout
+// [n_met][n_age] (the weights the library hands out); returns the rows in
+// which either weight is non-zero (as stored).
+__device__ __forceinline__ unsigned mdf_rows_user(const MdfLane &L, float *out) {
   unsigned nzr = 0u;
   double c_prev0 = 0.0, c_prev1 = 0.0;  // CDF at the lower edge of metallicity bin 0 (-inf)
   for (int j = 0; j < L.n_met; ++j) {
+    float w0f = 0.0f, w1f = 0.0f;
     // a row whose upper edge is all-zero, or whose lower edge is all-one, has
     // equal CDFs at both edges: its weights are exactly 0
     if (j + 1 <= L.n_zero || j >= L.first_one) {
       c_prev0 = c_prev1 = j + 1 <= L.n_zero ? 0.0 : 1.0;
-      if (MODE == MDF_PAD_F32) {
-        if (active) *reinterpret_cast<float2 *>((float *)out + j * AGE_PAD + L.i0) = make_float2(0.0f, 0.0f);
-      } else {
-        if (L.real0) ((float *)out)[j * L.n_age + L.i0] = 0.0f;
-        if (L.real1) ((float *)out)[j * L.n_age + L.i0 + 1] = 0.0f;
-      }
-      continue;
-    }
-    double c_next0 = 1.0, c_next1 = 1.0;  // upper edge of the last bin is +inf
-    if (j < L.n_met - 1) mdf_edge_cdf(L, j + 1, L.medge[j + 1], c_next0, c_next1);
-    // mage is 0 past the last age, and the CDF difference is finite and >= 0
-    const double wv0 = L.mage0 * (c_next0 - c_prev0);
-    const double wv1 = L.mage1 * (c_next1 - c_prev1);
-    c_prev0 = c_next0;
-    c_prev1 = c_next1;
-    const float w0f = (float)wv0, w1f = (float)wv1;
-    if (MODE == MDF_PAD_F32) {
-      if (active) *reinterpret_cast<float2 *>((float *)out + j * AGE_PAD + L.i0) = make_float2(w0f, w1f);
     } else {
-      if (L.real0) ((float *)out)[j * L.n_age + L.i0] = w0f;
-      if (L.real1) ((float *)out)[j * L.n_age + L.i0 + 1] = w1f;
+      double c_next0 = 1.0, c_next1 = 1.0;  // upper edge of the last bin is +inf
+      if (j < L.n_met - 1) mdf_edge_cdf(L, j + 1, L.medge[j + 1], c_next0, c_next1);
+      // mage is 0 past the last age, and the CDF difference is finite and >= 0
+      w0f = (float)(L.mage0 * (c_next0 - c_prev0));
+      w1f = (float)(L.mage1 * (c_next1 - c_prev1));
+      c_prev0 = c_next0;
+      c_prev1 = c_next1;
     }
+    if (L.real0) out[j * L.n_age + L.i0] = w0f;
+    if (L.real1) out[j * L.n_age + L.i0 + 1] = w1f;
     nzr |= (w0f != 0.0f || w1f != 0.0f ? 1u : 0u) << j;
   }
   return nzr;
@@ -330,19 +317,22 @@ __device__ __forceinline__ float triweight_cdf_f32(float z) {
   return z <= -3.0f ? 0.0f : (z >= 3.0f ? 1.0f : c);
 }
 
-// mdf_rows for the BF16 GEMM layout, with the CDF differences in float32.
-// The rows are rounded to 8 significant bits next; the float32 CDF differs
-// from the float64 one by about 1e-7, far below that rounding (2^-9 of each
-// weight) for every weight above 1e-4 of its age's mass, and the smaller ones
-// carry a correspondingly small share of the light.
-__device__ __forceinline__ unsigned mdf_rows_bf16(const MdfLane &L, uint16_t *out) {
+// The same W rows in the GEMM's padded layouts (BF16 with the row scales,
+// or float32), with the CDF differences in float32.  The float32 CDF differs
+// from the float64 one by about 1e-7.  BF16 rows round to 8 significant bits
+// next: far coarser for every weight above 1e-4 of its age's mass, and the
+// smaller ones carry a correspondingly small share of the light.  For float32
+// rows the difference moves a band sum by about 1e-7 of the light (1e-7 mag),
+// three orders below the path's 1e-4 mag target.
+template <bool BF16>
+__device__ __forceinline__ unsigned mdf_rows_pad(const MdfLane &L, void *out) {
   const bool active = L.i0 < AGE_PAD;
   const float mu0 = (float)L.mu0, mu1 = (float)L.mu1, inv_sig = (float)L.inv_sig;
   const float mage0 = (float)L.mage0, mage1 = (float)L.mage1;
   unsigned nzr = 0u;
   float c_prev0 = 0.0f, c_prev1 = 0.0f;  // CDF at the lower edge of metallicity bin 0 (-inf)
   for (int j = 0; j < L.n_met; ++j) {
-    uint32_t q = 0u;
+    float w0 = 0.0f, w1 = 0.0f;
     if (j + 1 <= L.n_zero || j >= L.first_one) {
       // upper edge all-zero or lower edge all-one: equal CDFs, weights 0
       c_prev0 = c_prev1 = j + 1 <= L.n_zero ? 0.0f : 1.0f;
@@ -353,6 +343,13 @@ __device__ __forceinline__ unsigned mdf_rows_bf16(const MdfLane &L, uint16_t *ou
         c_next0 = triweight_cdf_f32((e - mu0) * inv_sig);
         c_next1 = triweight_cdf_f32((e - mu1) * inv_sig);
       }
+      w0 = mage0 * (c_next0 - c_prev0);
+      w1 = mage1 * (c_next1 - c_prev1);
+      c_prev0 = c_next0;
+      c_prev1 = c_next1;
+    }
+    bool nz;
+    if (BF16) {
       const float2 ks = active ? *reinterpret_cast<const float2 *>(&L.ks[j * AGE_PAD + L.i0])
                                : make_float2(0.0f, 0.0f);
       // the row scales are powers of two; both values round to nearest even
@@ -360,13 +357,15 @@ __device__ __forceinline__ unsigned mdf_rows_bf16(const MdfLane &L, uint16_t *ou
       // f32_to_bf16_rne)
       typedef float f32x2_t __attribute__((ext_vector_type(2)));
       typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-      const f32x2_t v = {mage0 * (c_next0 - c_prev0) * ks.x, mage1 * (c_next1 - c_prev1) * ks.y};
-      q = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
-      c_prev0 = c_next0;
-      c_prev1 = c_next1;
+      const f32x2_t v = {w0 * ks.x, w1 * ks.y};
+      const uint32_t q = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+      if (active) *reinterpret_cast<uint32_t *>((uint16_t *)out + j * AGE_PAD + L.i0) = q;
+      nz = (q & 0x7FFF7FFFu) != 0u;
+    } else {
+      if (active) *reinterpret_cast<float2 *>((float *)out + j * AGE_PAD + L.i0) = make_float2(w0, w1);
+      nz = w0 != 0.0f || w1 != 0.0f;
     }
-    if (active) *reinterpret_cast<uint32_t *>(out + j * AGE_PAD + L.i0) = q;
-    nzr |= ((q & 0x7FFF7FFFu) != 0u ? 1u : 0u) << j;
+    nzr |= (nz ? 1u : 0u) << j;
   }
   return nzr;
 }
@@ -680,11 +679,11 @@ __global__ __launch_bounds__(64 * WEIGHTS_FWD_WAVES) void k_weights(WeightsLaunc
   }
   unsigned nzr;   // metallicity rows in which either of the lane's ages has a non-zero weight
   if (a.w_pad && a.w_pad_bf16)
-    nzr = mdf_rows_bf16(L, (uint16_t *)a.w_pad + (size_t)local * P.k_pad);
+    nzr = mdf_rows_pad<true>(L, (uint16_t *)a.w_pad + (size_t)local * P.k_pad);
   else if (a.w_pad)
-    nzr = mdf_rows<MDF_PAD_F32>(L, (float *)a.w_pad + (size_t)local * P.k_pad);
+    nzr = mdf_rows_pad<false>(L, (float *)a.w_pad + (size_t)local * P.k_pad);
   else
-    nzr = mdf_rows<MDF_USER>(L, a.w_user + (size_t)g * n_met * n_age);
+    nzr = mdf_rows_user(L, a.w_user + (size_t)g * n_met * n_age);
   // non-zero (4-age block, row) mask: block b holds the ages of lanes 2b and
   // 2b + 1, so after one shifted OR lane 2b + 1 holds its rows; word w packs
   // blocks 2w (low half) and 2w + 1 (high half), which lane 4w + 3 joins

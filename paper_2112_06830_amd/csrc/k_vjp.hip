@@ -777,6 +777,17 @@ __device__ __forceinline__ int bracket(double t, const double *tt, int n_t, doub
   return lo;
 }
 
+// Per-wave LDS doubles of k_vjp_weights: SFR / cotangent and cumulative mass
+// rows, the edge, age-mass and cotangent vectors and, with KEEP, the
+// parametric history's base term and quench factor at every node.
+__host__ __device__ inline int vjp_weights_wave_doubles(int n_t, bool keep) {
+  return (keep ? 4 : 2) * n_t + 3 * AGE_PAD + 2;
+}
+
+// KEEP (parametric history only): the base term and quench factor of every
+// node stay in LDS from the SFR evaluation to the pull-back, which then
+// evaluates neither again.
+template <bool KEEP>
 __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   extern __shared__ double lds[];
   const int n_t = a.n_t;
@@ -785,12 +796,14 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
   // waves per SIMD
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   double *tt = lds;
-  double *wbase = lds + n_t + wave * (2 * n_t + 3 * AGE_PAD + 2);
+  double *wbase = lds + n_t + wave * vjp_weights_wave_doubles(n_t, KEEP);
   double *buf = wbase;                 // SFR values, then the cumulative-mass cotangent
   double *mc = wbase + n_t;            // cumulative mass
   double *em = wbase + 2 * n_t;        // [n_age + 1] mass at the edges
   double *mage = em + AGE_PAD + 1;     // [n_age]
   double *mbar = mage + AGE_PAD;       // [n_age] age-mass cotangent (+1 pad)
+  double *s_base = mbar + AGE_PAD + 1; // KEEP: [n_t] A (t/tau)^alpha exp(-t/tau)
+  double *s_phi = s_base + n_t;        // KEEP: [n_t] Phi((t - t_q)/width)
 
   for (int n = threadIdx.x; n < n_t; n += blockDim.x) tt[n] = a.t_table[n];
   __syncthreads();
@@ -815,7 +828,13 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
     pq = a.sfh_params[3 * a.n_gal + g]; ptq = a.sfh_params[4 * a.n_gal + g];
     for (int n = lane; n < n_t; n += 64) {
       const double v = (tt[n] - ptq) * (1.0 / QUENCH_WIDTH);
-      buf[n] = sfr_base(tt[n], pa, ptau, palpha) * (1.0 - pq * 0.5 * erfc(-v * 0.70710678118654752440));
+      const double base = sfr_base(tt[n], pa, ptau, palpha);
+      const double phi = 0.5 * erfc(-v * 0.70710678118654752440);
+      buf[n] = base * (1.0 - pq * phi);
+      if (KEEP) {
+        s_base[n] = base;
+        s_phi[n] = phi;
+      }
     }
   }
   wave_sync_v();
@@ -963,9 +982,9 @@ __global__ __launch_bounds__(256) void k_vjp_weights(VjpLaunch a) {
     if (a.sfr_bar) a.sfr_bar[(size_t)g * n_t + n] = sb;
     if (!a.sfr) {
       const double t = tt[n];
-      const double base = sfr_base(t, pa, ptau, palpha);
+      const double base = KEEP ? s_base[n] : sfr_base(t, pa, ptau, palpha);
       const double v = (t - ptq) * (1.0 / QUENCH_WIDTH);
-      const double phi = 0.5 * erfc(-v * 0.70710678118654752440);
+      const double phi = KEEP ? s_phi[n] : 0.5 * erfc(-v * 0.70710678118654752440);
       const double pdf = exp(-0.5 * v * v) * 0.39894228040143267794;
       const double quench = 1.0 - pq * phi;
       const double sv = base * quench;
@@ -1085,16 +1104,26 @@ int launch_vjp(const VjpLaunch &a, int stage, hipStream_t stream) {
                          dim3((tiles + 7) / 8 * 8 * wbar_row_blocks(a.ssp.n_met, a.ssp.n_age)),
                          dim3(GEMM_THREADS), 0, stream, a);
   } else {
-    const size_t lds = sizeof(double) * (a.n_t + WEIGHT_WAVES * (2 * a.n_t + 3 * AGE_PAD + 2));
+    // the parametric history keeps its per-node terms while the block's LDS
+    // stays within 64 KB (a short grid; occupancy is then set by registers)
+    auto lds_of = [&](bool keep) {
+      return sizeof(double) * (a.n_t + (size_t)WEIGHT_WAVES * vjp_weights_wave_doubles(a.n_t, keep));
+    };
+    const bool keep = !a.sfr && lds_of(true) <= 65536;
+    const size_t lds = lds_of(keep);
+    const void *fn = keep ? (const void *)k_vjp_weights<true> : (const void *)k_vjp_weights<false>;
     if (lds > 65536) {
-      const int rc = hip_fail(hipFuncSetAttribute((const void *)k_vjp_weights,
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+      const int rc = hip_fail(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                               "k_vjp_weights LDS attribute");
       if (rc) return rc;
     }
     ProfScope prof(DSPS_KERNEL_VJP_WEIGHTS, stream);
-    hipLaunchKernelGGL(k_vjp_weights, dim3((a.s_count + WEIGHT_WAVES - 1) / WEIGHT_WAVES),
-                       dim3(64 * WEIGHT_WAVES), lds, stream, a);
+    if (keep)
+      hipLaunchKernelGGL(k_vjp_weights<true>, dim3((a.s_count + WEIGHT_WAVES - 1) / WEIGHT_WAVES),
+                         dim3(64 * WEIGHT_WAVES), lds, stream, a);
+    else
+      hipLaunchKernelGGL(k_vjp_weights<false>, dim3((a.s_count + WEIGHT_WAVES - 1) / WEIGHT_WAVES),
+                         dim3(64 * WEIGHT_WAVES), lds, stream, a);
   }
   return hip_fail(hipGetLastError(), "vjp launch");
 }

@@ -374,18 +374,30 @@ __device__ __forceinline__ unsigned mdf_rows_pad(const MdfLane &L, void *out) {
 // ages becomes 16 metallicity slots (zeros past n_met) written as four
 // 16-byte stores.  Returns the lane's highest age with a non-zero weight plus
 // one (0 if none); pieces gets bit 4 q + p set when slots 4 p .. 4 p + 3 of
-// age i0 + q hold a non-zero weight.
+// age i0 + q hold a non-zero weight.  The CDF differences are taken in
+// float32, as for the padded rows (mdf_rows_pad): these rows feed only the
+// float32 contraction.
 __device__ __forceinline__ int mdf_rows_age(const MdfLane &L, float *out, unsigned &pieces) {
   float w0[AGE_MET_SLOTS], w1[AGE_MET_SLOTS];
-  double c_prev0 = 0.0, c_prev1 = 0.0;
+  const float mu0 = (float)L.mu0, mu1 = (float)L.mu1, inv_sig = (float)L.inv_sig;
+  const float mage0 = (float)L.mage0, mage1 = (float)L.mage1;   // 0 past the last age
+  float c_prev0 = 0.0f, c_prev1 = 0.0f;
 #pragma unroll
   for (int j = 0; j < AGE_MET_SLOTS; ++j) {
     float v0 = 0.0f, v1 = 0.0f;
     if (j < L.n_met) {
-      double c_next0 = 1.0, c_next1 = 1.0;
-      if (j < L.n_met - 1) mdf_edge_cdf(L, j + 1, L.medge[j + 1], c_next0, c_next1);
-      v0 = L.real0 ? (float)(L.mage0 * (c_next0 - c_prev0)) : 0.0f;
-      v1 = L.real1 ? (float)(L.mage1 * (c_next1 - c_prev1)) : 0.0f;
+      float c_next0 = 1.0f, c_next1 = 1.0f;   // all-one edges and the last bin's +inf
+      if (j + 1 < L.first_one) {               // (then j + 1 < n_met as well)
+        if (j + 1 <= L.n_zero) {
+          c_next0 = c_next1 = 0.0f;
+        } else {
+          const float e = (float)L.medge[j + 1];
+          c_next0 = triweight_cdf_f32((e - mu0) * inv_sig);
+          c_next1 = triweight_cdf_f32((e - mu1) * inv_sig);
+        }
+      }
+      v0 = L.real0 ? mage0 * (c_next0 - c_prev0) : 0.0f;
+      v1 = L.real1 ? mage1 * (c_next1 - c_prev1) : 0.0f;
       c_prev0 = c_next0;
       c_prev1 = c_next1;
     }

@@ -269,6 +269,30 @@ __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_BF16> &sm, int wr,
   }
 }
 
+// One half of a float32 stage's MFMA operands: half j holds LDS units 2h + j
+// of the lane's A and B rows (steps 4j .. 4j + 3 of mma_stage).
+struct HalfStage {
+  float4 a[2], b[2];
+};
+__device__ __forceinline__ void read_half(const GemmSmem<DSPS_FP32> &sm, int j, int wr, int wc,
+                                          int lane, HalfStage &f) {
+  const int h = lane >> 5, c = lane & 31;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) f.a[mb] = as_float4(sm.a[stage_unit(wr * 64 + mb * 32 + c, 2 * h + j)]);
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) f.b[nb] = as_float4(sm.b[stage_unit(wc * 64 + nb * 32 + c, 2 * h + j)]);
+}
+// Steps 4j .. 4j + 3 of mma_stage, in its order for every accumulator.
+__device__ __forceinline__ void mma_half(const HalfStage &f, f32x16 (&acc)[2][2]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[mb][t], f.b[nb][t], acc[mb][nb], 0, 0, 0);
+}
+
 // The K loop of one output tile over nk stages; unit(s) says where this
 // thread's unit of stage s comes from (a UnitSrc).  Two LDS stage buffers:
 // while stage s feeds MFMA, stage s + 1 is written to the other buffer and
@@ -279,10 +303,17 @@ __device__ __forceinline__ void mma_stage(const GemmSmem<DSPS_BF16> &sm, int wr,
 struct NoStageHook {
   __device__ void operator()(int) const {}
 };
-template <int PREC, typename UnitFn, typename StageHook = NoStageHook>
+//
+// SPLIT (float32): the barrier sits between the two halves of a stage's
+// MFMAs, and the first half of the next stage's operands is read from LDS
+// right after it, while the second half runs, so that no stage starts by
+// waiting on its LDS reads.  Every accumulator takes the same steps in the
+// same order as without it.
+template <int PREC, bool SPLIT = false, typename UnitFn, typename StageHook = NoStageHook>
 __device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const GemmOps<PREC> &ops, int nk,
                                            UnitFn unit, int wr, int wc, int lane,
                                            f32x16 (&acc)[2][2], StageHook after = StageHook()) {
+  static_assert(!SPLIT || PREC == DSPS_FP32, "split stages are float32 only");
   StageRegs<PREC> regs;
   const float *pending = nullptr;   // B factors of the stage held in regs
   auto load = [&](int s) {
@@ -302,14 +333,35 @@ __device__ __forceinline__ void gemm_kloop(GemmSmem<PREC> *sm, const GemmOps<PRE
     if (nk > 1) load(1);
   }
   __syncthreads();
-  for (int ks = 0; ks < nk; ++ks) {
-    mma_stage(sm[ks & 1], wr, wc, lane, acc);
-    after(ks);
-    if (ks + 1 < nk) {
-      store(sm[(ks + 1) & 1]);
-      if (ks + 2 < nk) load(ks + 2);
+  if constexpr (SPLIT) {
+    HalfStage f0, f1;
+    if (nk > 0) read_half(sm[0], 0, wr, wc, lane, f0);
+    for (int ks = 0; ks < nk; ++ks) {
+      read_half(sm[ks & 1], 1, wr, wc, lane, f1);
+      mma_half(f0, acc);
+      if (ks + 1 < nk) {
+        // the other buffer's last reads (stage ks - 1) ended before the
+        // previous barrier
+        store(sm[(ks + 1) & 1]);
+        if (ks + 2 < nk) load(ks + 2);
+      }
+      __syncthreads();
+      if (ks + 1 < nk) read_half(sm[(ks + 1) & 1], 0, wr, wc, lane, f0);
+      mma_half(f1, acc);
+      after(ks);
     }
-    __syncthreads();
+    // every read of sm, the last stage's second half included, ended before
+    // the last iteration's barrier
+  } else {
+    for (int ks = 0; ks < nk; ++ks) {
+      mma_stage(sm[ks & 1], wr, wc, lane, acc);
+      after(ks);
+      if (ks + 1 < nk) {
+        store(sm[(ks + 1) & 1]);
+        if (ks + 2 < nk) load(ks + 2);
+      }
+      __syncthreads();
+    }
   }
 }
 

@@ -348,7 +348,7 @@ __global__ __launch_bounds__(GEMM_THREADS, (MOM || VAR == MAGS_AGED) ? 2 : 3) vo
                        },
                        wr, wc, lane, acc);
     } else {
-      gemm_kloop<PREC>(sm, ops, nk, unit, wr, wc, lane, acc);
+      gemm_kloop<PREC, PREC == DSPS_FP32>(sm, ops, nk, unit, wr, wc, lane, acc);
     }
     // (the loop's closing barrier makes s_lc, s_q and the filter tables visible)
 

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_sed_gemm(SedLaunch a) {
       for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = sed[mb][nb];
   } else {
     __syncthreads();
-    gemm_kloop<PREC>(sm, ops, nk, unit, wr, wc, lane, acc);
+    gemm_kloop<PREC, PREC == DSPS_FP32>(sm, ops, nk, unit, wr, wc, lane, acc);
   }
 
 #pragma unroll

@@ -332,7 +332,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar(VjpLaunch a) {
         gemm_ops<DSPS_FP32>(P.sk32, (size_t)P.n_u * slab, nwp, linear_rows<DSPS_FP32>(k0),
                             a.lbar + (size_t)g0 * nwp, nvalid, nwp);
     const int ucol = stage_col();
-    gemm_kloop<DSPS_FP32>(sm, ops, nk * n_uu,
+    gemm_kloop<DSPS_FP32, true>(sm, ops, nk * n_uu,
                           [&](int s) {
                             const int uu = s / nk;
                             const int l = contiguous_piece<DSPS_FP32>(l_begin, s - uu * nk, ucol);
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(GEMM_THREADS, 2) void k_vjp_wbar_rows(VjpLaunch a) 
       gemm_ops<DSPS_FP32>(P.sk32, (size_t)2 * P.sk_rows * nwp, nwp, ar, a.lbar + (size_t)g0 * nwp,
                           nvalid, nwp);
   const int ucol = stage_col();
-  gemm_kloop<DSPS_FP32>(sm, ops, nk,
+  gemm_kloop<DSPS_FP32, true>(sm, ops, nk,
                         [=](int ks) {
                           const int l = contiguous_piece<DSPS_FP32>(l_begin, ks, ucol);
                           return UnitSrc{l * 4, l * 4, nullptr};
